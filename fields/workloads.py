@@ -1,0 +1,47 @@
+"""Named synthetic workloads, shaped like the lattices of the paper's Section 4.
+
+Each entry fixes lattice extents, boundary condition, gauge roughness eps,
+anisotropy xi, quark mass, aggregate block shape, test-vector count, stream
+batch, truncation rank per chirality and the inner precision of the solve.
+A mass of None means "tuned so that the smallest |eigenvalue| of D is about
+1e-3"; the tuned value is read from tests/golden/tuned_masses.json.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+WORKLOADS = {
+    # 4^4, antiperiodic t, FP64 everywhere, GCR outer to 1e-10
+    "wilson4x4_fp64": dict(dims=(4, 4, 4, 4), bc_t=-1, eps=0.3, xi=1.0, mass=0.05,
+                           block=(2, 2, 2, 2), n_test=16, batch=4, rank=8,
+                           inner="f64", seed=14399, tag=1),
+    # 16^3x32 anisotropic, FP32 inner with FP64 refinement
+    "aniso16x32_fp32": dict(dims=(16, 16, 16, 32), bc_t=-1, eps=0.6, xi=3.5, mass=None,
+                            block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
+                            inner="f32", seed=14399, tag=2),
+    # 24^3x64 isotropic, BF16 storage with FP32 accumulation
+    "iso24x64_bf16": dict(dims=(24, 24, 24, 64), bc_t=-1, eps=0.7, xi=1.0, mass=None,
+                          block=(4, 4, 4, 4), n_test=96, batch=16, rank=24,
+                          inner="bf16", seed=14399, tag=3),
+    # 32^3x64 with 12 point sources
+    "batched32x64": dict(dims=(32, 32, 32, 64), bc_t=-1, eps=0.6, xi=1.0, mass=0.05,
+                         block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
+                         inner="f32", seed=14399, tag=4),
+    # differentiation workload
+    "grad16x32": dict(dims=(16, 16, 16, 32), bc_t=-1, eps=0.5, xi=1.0, mass=0.03,
+                      block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
+                      inner="f32", seed=14399, tag=5),
+}
+
+_TUNED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "tests", "golden", "tuned_masses.json")
+
+
+def get(name: str) -> dict:
+    w = dict(WORKLOADS[name])
+    w["name"] = name
+    if w["mass"] is None:
+        with open(_TUNED) as f:
+            w["mass"] = float(json.load(f)[name]["mass"])
+    return w
