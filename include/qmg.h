@@ -1,0 +1,193 @@
+/* qmg.h -- C ABI of libqmg: Wilson-Dirac stencil, streaming chiral-SVD multigrid setup,
+ * transfer operators, coarse operator and the multigrid-preconditioned solve on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is the adaptive multigrid setup with a streaming SVD of the chirally split
+ * test vectors of Whyte, Stathopoulos and Romero, "Accelerating multigrid with streaming
+ * chiral SVD for Wilson fermions in lattice QCD" (arXiv 2505.14399): Eq. (1) (D x = b),
+ * Eq. (2) (test vectors), Eq. (3) (chiral split), Eq. (5) (Galerkin coarse operator),
+ * Eq. (6) (chiral-SVD prolongator), Eqs. (7)-(8) and Algorithms 3-4 (streaming update).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns qmg_status; 0 is success, a negative value an error.
+ *   Inputs are validated before any launch; on error nothing has been written unless the
+ *   description says otherwise, and qmg_last_error() holds a message (per thread).
+ * Memory: every pointer argument named "device" is caller-owned device memory of the
+ *   current HIP device (for example a torch CUDA tensor's data_ptr()).  The library never
+ *   retains or frees a caller pointer after returning.  Handles (qmg_mg) are library-owned
+ *   until qmg_mg_destroy; one handle must not be used by two calls at the same time.
+ * Streams: all work is enqueued on the given stream.  Apply, transfer and force calls are
+ *   asynchronous.  Setup and solve make host decisions and synchronize the stream before
+ *   returning.
+ * Complex numbers are interleaved (re, im) in the given precision.
+ * Canonical layouts (row-major, lexicographic site = x + Lx*(y + Ly*(z + Lz*t))):
+ *   gauge   [4 mu][V][3][3]        U_mu(x), the physical link from x to x+mu
+ *   spinor  [nrhs][V][4 spin][3 colour] in the chiral basis, gamma_5 = diag(1,1,-1,-1)
+ *   coarse  [nrhs][d][2 chirality][k]   aggregates d in coarse lexicographic order,
+ *                                        rank index by descending singular value
+ * Native layouts (QMG_NATIVE) are the structure-of-arrays forms the kernels stream:
+ *   spinor  [nrhs][12 = 3*spin + colour][V]
+ *   gauge   [4 mu][9 = 3*row + col][V]
+ */
+#ifndef QMG_H
+#define QMG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qmg_status;
+enum {
+  QMG_OK = 0,
+  QMG_EINVAL = -1,      /* null pointer, bad enum, non-positive count              */
+  QMG_ESHAPE = -2,      /* lattice / block / rank / batch sizes inconsistent       */
+  QMG_EDTYPE = -3,      /* precision not supported by this entry point             */
+  QMG_ENOMEM = -4,      /* device allocation failed                                */
+  QMG_EHIP = -5,        /* a HIP runtime call or launch failed                     */
+  QMG_ENOCONV = -6,     /* solve stopped at max iterations; x holds the best iterate */
+  QMG_EBREAKDOWN = -7,  /* Krylov breakdown (zero or non-finite norm)              */
+  QMG_ENONFINITE = -8,  /* NaN or Inf in an input or a residual                    */
+  QMG_ENOTIMPL = -9
+};
+
+typedef enum { QMG_F64 = 0, QMG_F32 = 1, QMG_BF16 = 2, QMG_F16 = 3 } qmg_prec;
+typedef enum { QMG_CANONICAL = 0, QMG_NATIVE = 1 } qmg_layout;
+
+/* The lattice problem of Eq. (1): extents, time boundary condition, quark mass, anisotropy.
+ * D is the Wilson-Dirac operator
+ *   (D psi)(x) = (m + 1 + 3/xi) psi(x)
+ *     - 1/2 sum_mu c_mu [ s_mu(x) (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                       + s_mu(x-mu) (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ * with c_t = 1, c_x = c_y = c_z = 1/xi and s_mu(y) = bc_t for mu = t, y_t = Lt-1, else 1.
+ * Extents must be >= 1 and V = Lx Ly Lz Lt < 2^31. */
+typedef struct {
+  int32_t dims[4]; /* Lx, Ly, Lz, Lt */
+  int32_t bc_t;    /* +1 periodic, -1 antiperiodic in t (x, y, z periodic) */
+  double mass;     /* m */
+  double xi;       /* anisotropy a_s / a_t, > 0 */
+} qmg_lattice;
+
+/* out = D in (Eq. (1)'s operator), for nrhs spinors at once.
+ * U, in, out: device buffers in precision `prec` and layout `layout` (gauge and spinor
+ *   forms above); out must not alias in.  F64 computes in double, F32/BF16/F16 store in
+ *   that precision and accumulate in float.
+ * Errors: EINVAL (null, nrhs < 1, bad enum), ESHAPE (bad extents), EHIP. */
+qmg_status qmg_wilson_apply(const qmg_lattice* lat, const void* U, const void* in, void* out,
+                            int32_t nrhs, qmg_prec prec, qmg_layout layout, hipStream_t stream);
+/* out = D^dagger in = gamma_5 D gamma_5 in; arguments as qmg_wilson_apply. */
+qmg_status qmg_wilson_apply_adj(const qmg_lattice* lat, const void* U, const void* in, void* out,
+                                int32_t nrhs, qmg_prec prec, qmg_layout layout, hipStream_t stream);
+
+/* Layout/precision conversion: canonical FP64 <-> native `prec` (device buffers, no aliasing). */
+qmg_status qmg_pack_spinor(const qmg_lattice* lat, const void* canon_f64, void* native, int32_t nrhs,
+                           qmg_prec prec, hipStream_t stream);
+qmg_status qmg_unpack_spinor(const qmg_lattice* lat, const void* native, void* canon_f64, int32_t nrhs,
+                             qmg_prec prec, hipStream_t stream);
+qmg_status qmg_pack_gauge(const qmg_lattice* lat, const void* canon_f64, void* native, qmg_prec prec,
+                          hipStream_t stream);
+
+/* Parameters of the setup, Algorithms 3 and 4: block shape of the aggregates Lambda_j,
+ * the number of test vectors sampled (n_s streams of r = batch vectors each), the rank k
+ * kept per chirality, the smoother and the K-cycle. */
+typedef struct {
+  int32_t block[4];      /* aggregate extents; each must divide the lattice extent            */
+  int32_t n_test;        /* total test vectors sampled, n_s * batch                           */
+  int32_t batch;         /* r, test vectors per stream                                        */
+  int32_t rank;          /* k per chirality: 1 <= k <= 6*prod(block), k <= n_test, k+r <= 64  */
+  int32_t n_setup_iter;  /* GMRES(8) iterations smoothing each test vector (0: psi = phi)     */
+  int32_t n_post_smooth; /* GMRES post-smoothing iterations in the K-cycle (Section 4: 8)     */
+  double coarse_tol;     /* coarse solve to ||r_c|| <= coarse_tol ||b_c|| (Section 4: 0.03)   */
+  int32_t coarse_max_iter; /* cap on coarse GMRES iterations per cycle (e.g. 500)             */
+  qmg_prec inner_prec;   /* storage precision of D, P, D_c and vectors inside the K-cycle    */
+  uint64_t seed;         /* Philox4x32-10 key for the random initial guesses phi             */
+  const void* test_vectors; /* optional device buffer, canonical FP64 [n_test][V][4][3]: the
+                               initial guesses phi (NULL: internal counter RNG)               */
+} qmg_mg_params;
+
+typedef struct qmg_mg qmg_mg; /* opaque two-level hierarchy: P (FP64 and inner copy), D_c */
+
+/* Multigrid setup with the streaming chiral SVD (Algorithm 4 with Algorithm 3).  For every
+ * stream s: r initial guesses phi are smoothed on D psi ~ 0 (Eq. (2)), normalised, split by
+ * chirality and blocked (Eq. (3)), and every (aggregate, chirality) block updates its rank-k
+ * SVD of [Phi_{s-1}, Psi_s] (Eq. (8)); the last stream gives P = U_k (Eq. (6)), R = P^dag and
+ * D_c = R D P (Eq. (5)).
+ * U: device, canonical FP64 gauge field; it is copied into the handle.
+ * Errors: EINVAL, ESHAPE (block does not divide, k or r out of range, n_test % batch,
+ *   n_test < k), ENOMEM, EHIP, ENONFINITE (non-finite links). On error *out is NULL. */
+qmg_status qmg_mg_setup_stream_chiral_svd(const qmg_lattice* lat, const void* U, const qmg_mg_params* params,
+                                          qmg_mg** out, hipStream_t stream);
+
+/* fine_out = P coarse_in (Eq. (6)), canonical layouts, prec F64 or F32. */
+qmg_status qmg_prolong(const qmg_mg* mg, const void* coarse_in, void* fine_out, int32_t nrhs, qmg_prec prec,
+                       hipStream_t stream);
+/* coarse_out = R fine_in = P^dag fine_in, canonical layouts, prec F64 or F32. */
+qmg_status qmg_restrict(const qmg_mg* mg, const void* fine_in, void* coarse_out, int32_t nrhs, qmg_prec prec,
+                        hipStream_t stream);
+/* out = D_c in (Eq. (5)) as the nine-block coarse stencil, canonical coarse layout,
+ * prec F64 (the FP64 operator) or F32 (the inner copy when inner_prec is F32). */
+qmg_status qmg_coarse_apply(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
+                            hipStream_t stream);
+
+typedef struct {
+  int32_t outer_iters;      /* outer flexible-GCR iterations, summed over refinements        */
+  int32_t refinements;      /* FP64 defect-correction steps                                  */
+  int32_t coarse_iters;     /* coarse GMRES iterations, summed                               */
+  int32_t smoother_iters;   /* fine GMRES post-smoothing iterations, summed                  */
+  int32_t precision_escalations;
+  double true_rel_res;      /* ||b - D x|| / ||b|| recomputed in FP64 at the end              */
+  double seconds;
+} qmg_solve_info;
+
+/* Solve D x = b (or D^dag x = b when adjoint != 0, as gamma5 D^-1 gamma5) to a true FP64
+ * relative residual <= tol with flexible GCR preconditioned by the two-level K-cycle
+ * (Section 2.1: restrict, coarse GMRES to coarse_tol, prolong, post-smooth).  With an inner
+ * precision below F64 the K-cycle and the inner GCR run in that precision inside an FP64
+ * defect-correction loop.
+ * b, x: device, canonical FP64 [nrhs][V][4][3]; x is the initial guess on entry (zeros
+ *   allowed) and the solution on return.  info: host array of nrhs entries (may be NULL).
+ * Errors: ENOCONV (x holds the best iterate, info filled), ENONFINITE, EBREAKDOWN, EHIP. */
+qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, double tol, int32_t max_outer,
+                        int32_t adjoint, qmg_solve_info* info, hipStream_t stream);
+
+/* Gradient of L = sum_rhs Re <eta, D^-1 b> with respect to the gauge links, from the
+ * solution x = D^-1 b and the adjoint solution lambda = D^-dag eta:
+ *   dL/dU_mu(x) = 1/2 c_mu s_mu(x) G^dag,
+ *   G = tr_spin[(1-gamma_mu) x(x+mu) lambda(x)^dag] + tr_spin[(1+gamma_mu) lambda(x+mu) x(x)^dag]
+ * (gradient convention dL/dRe + i dL/dIm).  x, lambda: device canonical FP64 spinors;
+ * dU: device canonical FP64 gauge field, overwritten. */
+qmg_status qmg_link_force(const qmg_lattice* lat, const void* x, const void* lambda, void* dU, int32_t nrhs,
+                          hipStream_t stream);
+
+/* Test-vector initial guesses phi_v, v = v0 .. v0+n-1, from Philox4x32-10 keyed by seed
+ * (counter (site, g, v, 0), Box-Muller), canonical FP64 [n][V][4][3] into device `out`. */
+qmg_status qmg_random_test_vectors(const qmg_lattice* lat, uint64_t seed, int32_t v0, int32_t n, void* out,
+                                   hipStream_t stream);
+
+/* Smooth test vectors (Eq. (2)): psi = phi + psi', psi' from n_iter GMRES(8) iterations on
+ * D psi' = -D phi from zero, then psi /= ||psi||.  U, phi, psi: device canonical FP64;
+ * computed in `prec` (F64 or F32). */
+qmg_status qmg_smooth(const qmg_lattice* lat, const void* U, const void* phi, void* psi, int32_t nrhs,
+                      int32_t n_iter, qmg_prec prec, hipStream_t stream);
+
+/* Read the hierarchy: coarse extents [4], d and k; P as canonical FP64 blocks
+ * [d][2][N][k] (device, may be NULL), singular values [d][2][k] (host, may be NULL),
+ * Galerkin blocks [d][9][2k][2k] FP64 (device, may be NULL; slot 0 self, 1+dir hops). */
+qmg_status qmg_mg_query(const qmg_mg* mg, int32_t* coarse_dims, int32_t* n_agg, int32_t* rank);
+qmg_status qmg_mg_get_prolongator(const qmg_mg* mg, void* P, double* sigma, hipStream_t stream);
+qmg_status qmg_mg_get_coarse(const qmg_mg* mg, void* Y, hipStream_t stream);
+
+/* Setup timings in seconds: smoother, streaming SVD, coarse build, total (host array [4]). */
+qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);
+
+void qmg_mg_destroy(qmg_mg* mg);
+const char* qmg_last_error(void);
+const char* qmg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QMG_H */

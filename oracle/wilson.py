@@ -119,3 +119,25 @@ def free_field_eigenvalues(mass, xi, bc_t, dims):
     im = np.sqrt(sum((c[mu] * np.sin(P[mu])) ** 2 for mu in range(4)))
     lam = np.concatenate([(re + 1j * im).ravel(), (re - 1j * im).ravel()])
     return np.repeat(lam, 6)
+
+
+def apply_wilson_sites(U, psi, sites, mass, xi, bc_t, dims, dagger=False):
+    """(D psi)(x) for the listed sites only, hop by hop from the formula above (plain loops).
+
+    Used to check full-size lattices at sampled sites.  psi: [V][4][3]; returns [len(sites)][4][3].
+    """
+    nb = neighbor_table(dims)
+    sg = hop_sign(dims, bc_t)
+    c = hop_weights(xi)
+    a = diag_term(mass, xi)
+    s = -1.0 if dagger else 1.0
+    out = np.empty((len(sites), 4, 3), dtype=np.complex128)
+    for n, x in enumerate(sites):
+        acc = a * psi[x]
+        for mu in range(4):
+            y = nb[x, mu]
+            acc = acc - 0.5 * c[mu] * sg[x, mu] * ((ID4 - s * GAMMA[mu]) @ (psi[y] @ U[mu, x].T))
+            z = nb[x, 4 + mu]
+            acc = acc - 0.5 * c[mu] * sg[x, 4 + mu] * ((ID4 + s * GAMMA[mu]) @ (psi[z] @ np.conj(U[mu, z])))
+        out[n] = acc
+    return out

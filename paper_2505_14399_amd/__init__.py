@@ -1,0 +1,375 @@
+"""Python binding of libqmg: streaming chiral-SVD multigrid for Wilson fermions on MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of
+libqmg.so (include/qmg.h).  Device memory and streams come from PyTorch; the library must
+be built (``python -m paper_2505_14399_amd.build``) and fails loudly if it is missing.
+
+Names follow the C ABI without the ``qmg_`` prefix.  Tensors are CUDA (HIP) tensors in the
+canonical layouts of qmg.h: gauge [4][V][3][3], spinor [nrhs][V][4][3] (chiral basis),
+coarse [nrhs][d][2][k]; complex128 is QMG_F64 and complex64 QMG_F32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqmg.so")
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+CANONICAL, NATIVE = 0, 1
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EDTYPE", -4: "ENOMEM", -5: "EHIP",
+          -6: "ENOCONV", -7: "EBREAKDOWN", -8: "ENONFINITE", -9: "ENOTIMPL"}
+
+
+class QmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qmg {STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class qmg_lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("bc_t", ctypes.c_int32),
+                ("mass", ctypes.c_double), ("xi", ctypes.c_double)]
+
+
+class qmg_mg_params(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32 * 4), ("n_test", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("rank", ctypes.c_int32), ("n_setup_iter", ctypes.c_int32), ("n_post_smooth", ctypes.c_int32),
+                ("coarse_tol", ctypes.c_double), ("coarse_max_iter", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int32), ("seed", ctypes.c_uint64), ("test_vectors", ctypes.c_void_p)]
+
+
+class qmg_solve_info(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("coarse_iters", ctypes.c_int32), ("smoother_iters", ctypes.c_int32),
+                ("precision_escalations", ctypes.c_int32), ("true_rel_res", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+# exported symbols and their argument types (void* = device or host pointer, see qmg.h)
+_P, _I, _D, _U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64
+SIGNATURES = {
+    "qmg_wilson_apply": [_P, _P, _P, _P, _I, _I, _I, _P],
+    "qmg_wilson_apply_adj": [_P, _P, _P, _P, _I, _I, _I, _P],
+    "qmg_pack_spinor": [_P, _P, _P, _I, _I, _P],
+    "qmg_unpack_spinor": [_P, _P, _P, _I, _I, _P],
+    "qmg_pack_gauge": [_P, _P, _P, _I, _P],
+    "qmg_mg_setup_stream_chiral_svd": [_P, _P, _P, _P, _P],
+    "qmg_prolong": [_P, _P, _P, _I, _I, _P],
+    "qmg_restrict": [_P, _P, _P, _I, _I, _P],
+    "qmg_coarse_apply": [_P, _P, _P, _I, _I, _P],
+    "qmg_mg_solve": [_P, _P, _P, _I, _D, _I, _I, _P, _P],
+    "qmg_link_force": [_P, _P, _P, _P, _I, _P],
+    "qmg_random_test_vectors": [_P, _U64, _I, _I, _P, _P],
+    "qmg_smooth": [_P, _P, _P, _P, _I, _I, _I, _P],
+    "qmg_mg_query": [_P, _P, _P, _P],
+    "qmg_mg_get_prolongator": [_P, _P, _P, _P],
+    "qmg_mg_get_coarse": [_P, _P, _P],
+    "qmg_mg_setup_times": [_P, _P],
+    "qmg_mg_destroy": [_P],
+    "qmg_last_error": [],
+    "qmg_version": [],
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libqmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libqmg.so not found at {path}: build it with "
+                           "`python -m paper_2505_14399_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    for name, args in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int32
+    lib.qmg_last_error.restype = ctypes.c_char_p
+    lib.qmg_version.restype = ctypes.c_char_p
+    lib.qmg_mg_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise QmgError(rc, _lib.qmg_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec_of(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex128:
+        return F64
+    if t.dtype == torch.complex64:
+        return F32
+    if t.dtype == torch.bfloat16 and t.shape[-1] == 2:
+        return BF16
+    if t.dtype == torch.float16 and t.shape[-1] == 2:
+        return F16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+@dataclass
+class Lattice:
+    """Eq. (1)'s lattice problem: extents (Lx, Ly, Lz, Lt), time BC, mass, anisotropy."""
+    dims: Sequence[int]
+    mass: float
+    xi: float = 1.0
+    bc_t: int = -1
+
+    @property
+    def volume(self):
+        v = 1
+        for L in self.dims:
+            v *= int(L)
+        return v
+
+    def c(self):
+        s = qmg_lattice()
+        for i in range(4):
+            s.dims[i] = int(self.dims[i])
+        s.bc_t = int(self.bc_t)
+        s.mass = float(self.mass)
+        s.xi = float(self.xi)
+        return s
+
+
+def _apply(fn, lat, U, psi, layout, out):
+    lib = load_library()
+    prec = _prec_of(psi)
+    if _prec_of(U) != prec:
+        raise TypeError("U and psi must have the same precision")
+    nrhs = psi.shape[0]
+    out = torch.empty_like(psi) if out is None else out
+    s = lat.c()
+    _check(getattr(lib, fn)(ctypes.byref(s), _ptr(U), _ptr(psi), _ptr(out), nrhs, prec,
+                            CANONICAL if layout == "canonical" else NATIVE, _stream()))
+    return out
+
+
+def wilson_apply(lat: Lattice, U, psi, layout="canonical", out=None):
+    """out = D psi.  Canonical: U [4,V,3,3], psi [nrhs,V,4,3]; native: [4,9,V], [nrhs,12,V]."""
+    return _apply("qmg_wilson_apply", lat, U, psi, layout, out)
+
+
+def wilson_apply_adj(lat: Lattice, U, psi, layout="canonical", out=None):
+    """out = D^dagger psi."""
+    return _apply("qmg_wilson_apply_adj", lat, U, psi, layout, out)
+
+
+def _native_spinor_shape(nrhs, V, prec):
+    if prec in (BF16, F16):
+        return (nrhs, 12, V, 2)
+    return (nrhs, 12, V)
+
+
+def _dtype_of(prec):
+    return {F64: torch.complex128, F32: torch.complex64, BF16: torch.bfloat16, F16: torch.float16}[prec]
+
+
+def pack_spinor(lat: Lattice, psi64, prec="f64"):
+    """canonical complex128 [nrhs,V,4,3] -> native [nrhs,12,V] in `prec`."""
+    lib = load_library()
+    p = _PREC[prec]
+    nrhs = psi64.shape[0]
+    out = torch.empty(_native_spinor_shape(nrhs, lat.volume, p), dtype=_dtype_of(p), device=psi64.device)
+    s = lat.c()
+    _check(lib.qmg_pack_spinor(ctypes.byref(s), _ptr(psi64), _ptr(out), nrhs, p, _stream()))
+    return out
+
+
+def unpack_spinor(lat: Lattice, native, prec="f64"):
+    lib = load_library()
+    p = _PREC[prec]
+    nrhs = native.shape[0]
+    out = torch.empty((nrhs, lat.volume, 4, 3), dtype=torch.complex128, device=native.device)
+    s = lat.c()
+    _check(lib.qmg_unpack_spinor(ctypes.byref(s), _ptr(native), _ptr(out), nrhs, p, _stream()))
+    return out
+
+
+def pack_gauge(lat: Lattice, U64, prec="f64"):
+    """canonical complex128 [4,V,3,3] -> native [4,9,V] in `prec`."""
+    lib = load_library()
+    p = _PREC[prec]
+    shape = (4, 9, lat.volume, 2) if p in (BF16, F16) else (4, 9, lat.volume)
+    out = torch.empty(shape, dtype=_dtype_of(p), device=U64.device)
+    s = lat.c()
+    _check(lib.qmg_pack_gauge(ctypes.byref(s), _ptr(U64), _ptr(out), p, _stream()))
+    return out
+
+
+class MG:
+    """A two-level hierarchy built by mg_setup_stream_chiral_svd (owns the C handle)."""
+
+    def __init__(self, handle, lat, params):
+        self._h = handle
+        self.lat = lat
+        self.params = params
+        cd = (ctypes.c_int32 * 4)()
+        d = ctypes.c_int32()
+        k = ctypes.c_int32()
+        _check(load_library().qmg_mg_query(self._h, cd, ctypes.byref(d), ctypes.byref(k)))
+        self.coarse_dims = tuple(cd)
+        self.n_agg = d.value
+        self.rank = k.value
+        self.inner = {v: n for n, v in _PREC.items()}[params.inner_prec]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().qmg_mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prolongator(self):
+        """(P [d,2,N,k] complex128 on the GPU, canonical row order 6*site+3*spin+colour; sigma [d,2,k])."""
+        import numpy as np
+        N = 6 * int(torch.tensor(self.params.block[:]).prod())
+        P = torch.empty((self.n_agg, 2, N, self.rank), dtype=torch.complex128, device="cuda")
+        sig = np.empty((self.n_agg, 2, self.rank))
+        _check(load_library().qmg_mg_get_prolongator(self._h, _ptr(P), sig.ctypes.data_as(ctypes.c_void_p),
+                                                     _stream()))
+        return P, sig
+
+    def coarse_blocks(self):
+        m = 2 * self.rank
+        Y = torch.empty((self.n_agg, 9, m, m), dtype=torch.complex128, device="cuda")
+        _check(load_library().qmg_mg_get_coarse(self._h, _ptr(Y), _stream()))
+        return Y
+
+    def setup_times(self):
+        t = (ctypes.c_double * 4)()
+        _check(load_library().qmg_mg_setup_times(self._h, t))
+        return {"smooth": t[0], "svd": t[1], "coarse": t[2], "total": t[3]}
+
+
+def mg_setup_stream_chiral_svd(lat: Lattice, U, block, n_test, batch, rank, n_setup_iter=16, n_post_smooth=8,
+                               coarse_tol=0.03, coarse_max_iter=500, inner="f64", seed=0, test_vectors=None) -> MG:
+    """Algorithm 4 with Algorithm 3 (see qmg.h).  U: complex128 [4,V,3,3] on the GPU."""
+    lib = load_library()
+    if U.dtype != torch.complex128:
+        raise TypeError("setup takes the FP64 canonical gauge field")
+    p = qmg_mg_params()
+    for i in range(4):
+        p.block[i] = int(block[i])
+    p.n_test, p.batch, p.rank = int(n_test), int(batch), int(rank)
+    p.n_setup_iter, p.n_post_smooth = int(n_setup_iter), int(n_post_smooth)
+    p.coarse_tol, p.coarse_max_iter = float(coarse_tol), int(coarse_max_iter)
+    p.inner_prec = _PREC[inner]
+    p.seed = int(seed)
+    p.test_vectors = None if test_vectors is None else _ptr(test_vectors).value
+    h = ctypes.c_void_p()
+    s = lat.c()
+    _check(lib.qmg_mg_setup_stream_chiral_svd(ctypes.byref(s), _ptr(U), ctypes.byref(p), ctypes.byref(h), _stream()))
+    return MG(h, lat, p)
+
+
+def _coarse_prec(t):
+    return _prec_of(t)
+
+
+def prolong(mg: MG, vc, out=None):
+    """fine = P vc; vc [nrhs,d,2,k] complex128 (FP64 P) or complex64 (inner FP32 P)."""
+    p = _prec_of(vc)
+    nrhs = vc.shape[0]
+    out = torch.empty((nrhs, mg.lat.volume, 4, 3), dtype=vc.dtype, device=vc.device) if out is None else out
+    _check(load_library().qmg_prolong(mg.handle, _ptr(vc), _ptr(out), nrhs, p, _stream()))
+    return out
+
+
+def restrict(mg: MG, psi, out=None):
+    """coarse = P^dagger psi; psi [nrhs,V,4,3]."""
+    p = _prec_of(psi)
+    nrhs = psi.shape[0]
+    out = torch.empty((nrhs, mg.n_agg, 2, mg.rank), dtype=psi.dtype, device=psi.device) if out is None else out
+    _check(load_library().qmg_restrict(mg.handle, _ptr(psi), _ptr(out), nrhs, p, _stream()))
+    return out
+
+
+def coarse_apply(mg: MG, v, out=None):
+    """out = D_c v; v [nrhs,d,2,k]."""
+    p = _prec_of(v)
+    out = torch.empty_like(v) if out is None else out
+    _check(load_library().qmg_coarse_apply(mg.handle, _ptr(v), _ptr(out), v.shape[0], p, _stream()))
+    return out
+
+
+def mg_solve(mg: MG, b, x0=None, tol=1e-10, max_outer=1000, adjoint=False, check=True):
+    """Solve D x = b (D^dagger x = b if adjoint) to true FP64 relative residual tol.
+
+    Returns (x, info) with info a list of dicts per right-hand side.  With check=False a
+    non-convergence status is returned in info instead of raised.
+    """
+    nrhs = b.shape[0]
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    infos = (qmg_solve_info * nrhs)()
+    rc = load_library().qmg_mg_solve(mg.handle, _ptr(b), _ptr(x), nrhs, float(tol), int(max_outer),
+                                     1 if adjoint else 0, infos, _stream())
+    out = [{f: getattr(i, f) for f, _ in qmg_solve_info._fields_} for i in infos]
+    for o in out:
+        o["status"] = STATUS.get(rc, str(rc))
+    if check:
+        _check(rc)
+    return x, out
+
+
+def link_force(lat: Lattice, x, lam, out=None):
+    """Gradient of sum Re<eta, D^-1 b> w.r.t. the links from x = D^-1 b, lam = D^-dag eta."""
+    out = torch.empty((4, lat.volume, 3, 3), dtype=torch.complex128, device=x.device) if out is None else out
+    s = lat.c()
+    _check(load_library().qmg_link_force(ctypes.byref(s), _ptr(x), _ptr(lam), _ptr(out), x.shape[0], _stream()))
+    return out
+
+
+def random_test_vectors(lat: Lattice, seed, v0, n):
+    out = torch.empty((n, lat.volume, 4, 3), dtype=torch.complex128, device="cuda")
+    s = lat.c()
+    _check(load_library().qmg_random_test_vectors(ctypes.byref(s), int(seed), int(v0), int(n), _ptr(out),
+                                                  _stream()))
+    return out
+
+
+def smooth(lat: Lattice, U, phi, n_iter, prec="f64"):
+    """Eq. (2) smoothing of test vectors phi (canonical complex128), computed in `prec`."""
+    out = torch.empty_like(phi)
+    s = lat.c()
+    _check(load_library().qmg_smooth(ctypes.byref(s), _ptr(U), _ptr(phi), _ptr(out), phi.shape[0], int(n_iter),
+                                     _PREC[prec], _stream()))
+    return out
+
+
+def version():
+    return load_library().qmg_version().decode()

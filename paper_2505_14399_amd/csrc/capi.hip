@@ -1,0 +1,720 @@
+// C ABI of libqmg (qmg.h): validation, the multigrid setup driver (Algorithm 4 with
+// Algorithm 3), the K-cycle preconditioner and the mixed-precision MG solve.
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <memory>
+#include <new>
+
+#include "mg.hpp"
+
+struct qmg_mg {
+  qmg::HierarchyDev h;
+  qmg::DevBuf sigma_dev;
+};
+
+namespace qmg {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+const char* last_error_ptr() { return g_err; }
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+Geom make_geom(const qmg_lattice* lat) {
+  Geom g{};
+  int64_t V = 1;
+  for (int m = 0; m < 4; ++m) {
+    QMG_CHECK(lat->dims[m] >= 1, QMG_ESHAPE, "lattice extent %d is %d (must be >= 1)", m, lat->dims[m]);
+    g.L[m] = lat->dims[m];
+    V *= lat->dims[m];
+  }
+  QMG_CHECK(V < (int64_t(1) << 31), QMG_ESHAPE, "lattice volume %lld too large", (long long)V);
+  QMG_CHECK(lat->bc_t == 1 || lat->bc_t == -1, QMG_EINVAL, "bc_t must be +1 or -1");
+  QMG_CHECK(std::isfinite(lat->mass) && std::isfinite(lat->xi) && lat->xi > 0, QMG_EINVAL,
+            "mass must be finite and xi positive");
+  g.V = int(V);
+  g.bc_t = lat->bc_t;
+  g.mass = lat->mass;
+  g.xi = lat->xi;
+  return g;
+}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double secs(Clock::time_point a, Clock::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+void check_prec(qmg_prec p) {
+  QMG_CHECK(p == QMG_F64 || p == QMG_F32 || p == QMG_BF16 || p == QMG_F16, QMG_EINVAL, "bad precision %d", int(p));
+}
+
+// ---------------------------------------------------------------------------------------
+// operators
+struct WilsonOp : LinOp {
+  Geom g;
+  qmg_prec p;
+  const void* U;
+  WilsonOp(const Geom& g_, qmg_prec p_, const void* U_) : g(g_), p(p_), U(U_) {}
+  void apply(const void* in, void* out, int nrhs, hipStream_t st) override {
+    DslashArgs a = make_dslash_args(g, nrhs, false, false);
+    launch_dslash(p, U, in, out, a, st);
+  }
+  size_t len() const override { return size_t(12) * g.V; }
+  qmg_prec prec() const override { return p; }
+};
+
+struct CoarseOp : LinOp {
+  const HierarchyDev& h;
+  qmg_prec p;
+  const void* Y;
+  CoarseOp(const HierarchyDev& h_, qmg_prec p_, const void* Y_) : h(h_), p(p_), Y(Y_) {}
+  void apply(const void* in, void* out, int nrhs, hipStream_t st) override {
+    launch_coarse_apply(p, h, Y, in, out, nrhs, st);
+  }
+  size_t len() const override { return size_t(2) * h.k * h.blk.d; }
+  qmg_prec prec() const override { return p; }
+};
+
+template <class S>
+struct KCycle : Precond {
+  const HierarchyDev& h;
+  WilsonOp& D;
+  CoarseOp& Dc;
+  const void* P;
+  Gmres<S> gc, gf;
+  DevBuf rc, ec;
+  long coarse_iters = 0, smooth_iters = 0, cycles = 0;
+  KCycle(const HierarchyDev& h_, WilsonOp& D_, CoarseOp& Dc_, const void* P_) : h(h_), D(D_), Dc(Dc_), P(P_) {}
+  void apply(const void* r, void* z, int nrhs, hipStream_t st) override {
+    const size_t nc = size_t(nrhs) * 2 * h.k * h.blk.d;
+    rc.ensure(nc * sizeof(S));
+    ec.ensure(nc * sizeof(S));
+    const qmg_prec p = StoreTraits<S>::prec;
+    launch_restrict(p, h, P, r, rc.p, nrhs, st);
+    auto rcs = gc.solve(Dc, rc.p, ec.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st);
+    launch_prolong(p, h, P, ec.p, z, nrhs, st);
+    auto rfs = gf.solve(D, r, z, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    coarse_iters += rcs.iters;
+    smooth_iters += rfs.iters;
+    ++cycles;
+  }
+};
+
+// gamma_5 on native spinors: negate spins 2, 3
+template <class S>
+__global__ void k_gamma5(S* x, int V, int nrhs) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  const size_t n = size_t(nrhs) * 6 * V;
+  if (g >= n) return;
+  const size_t rhs = g / (size_t(6) * V), rem = g - rhs * 6 * V;
+  const size_t idx = (rhs * 12 + 6) * V + rem;
+  auto v = StoreTraits<S>::ld(x[idx]);
+  x[idx] = StoreTraits<S>::st(-v);
+}
+void gamma5_f64(void* x, int V, int nrhs, hipStream_t st) {
+  const size_t n = size_t(nrhs) * 6 * V;
+  k_gamma5<double2><<<unsigned((n + 255) / 256), 256, 0, st>>>((double2*)x, V, nrhs);
+  QMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------------------
+// tables
+void build_tables(HierarchyDev& h) {
+  const Geom& g = h.g;
+  const Blocking& b = h.blk;
+  std::vector<int> bsite(size_t(b.d) * b.nd), cnb(size_t(b.d) * 8);
+  for (int t = 0; t < g.L[3]; ++t)
+    for (int z = 0; z < g.L[2]; ++z)
+      for (int y = 0; y < g.L[1]; ++y)
+        for (int x = 0; x < g.L[0]; ++x) {
+          const int c[4] = {x, y, z, t};
+          int cj[4], ci[4];
+          for (int q = 0; q < 4; ++q) {
+            cj[q] = c[q] / b.b[q];
+            ci[q] = c[q] % b.b[q];
+          }
+          const int j = cj[0] + b.cL[0] * (cj[1] + b.cL[1] * (cj[2] + b.cL[2] * cj[3]));
+          const int ib = ci[0] + b.b[0] * (ci[1] + b.b[1] * (ci[2] + b.b[2] * ci[3]));
+          const int site = x + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
+          bsite[size_t(j) * b.nd + ib] = site;
+        }
+  for (int j = 0; j < b.d; ++j) {
+    int c[4], rem = j;
+    for (int q = 0; q < 4; ++q) {
+      c[q] = rem % b.cL[q];
+      rem /= b.cL[q];
+    }
+    for (int dir = 0; dir < 8; ++dir) {
+      const int mu = dir & 3, step = dir < 4 ? 1 : -1;
+      int cc[4] = {c[0], c[1], c[2], c[3]};
+      cc[mu] = (cc[mu] + step + b.cL[mu]) % b.cL[mu];
+      cnb[size_t(j) * 8 + dir] = cc[0] + b.cL[0] * (cc[1] + b.cL[1] * (cc[2] + b.cL[2] * cc[3]));
+    }
+  }
+  h.bsite.alloc(bsite.size() * sizeof(int));
+  h.cnb.alloc(cnb.size() * sizeof(int));
+  QMG_HIP(hipMemcpy(h.bsite.p, bsite.data(), bsite.size() * sizeof(int), hipMemcpyHostToDevice));
+  QMG_HIP(hipMemcpy(h.cnb.p, cnb.data(), cnb.size() * sizeof(int), hipMemcpyHostToDevice));
+}
+
+double host_norm2(const void* dev, size_t n_complex, hipStream_t st) {
+  RedWork rw;
+  DevBuf out(sizeof(double));
+  Blas<double2>::norm2(dev, n_complex, 1, out.as<double>(), rw, st);
+  double v = 0;
+  QMG_HIP(hipMemcpyAsync(&v, out.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  QMG_HIP(hipStreamSynchronize(st));
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Eq. (2) smoothing of r test vectors held in native FP64 `phi` (in place: phi <- psi/|psi|),
+// computed in storage precision S.
+template <class S>
+void smooth_native(const Geom& g, const void* Uin, void* phi, int r, int n_iter, hipStream_t st, Gmres<S>& gm,
+                   DevBuf& b_in, DevBuf& x_in, DevBuf& tmp64) {
+  const size_t n = size_t(r) * 12 * g.V;
+  constexpr qmg_prec P = StoreTraits<S>::prec;
+  if (n_iter > 0) {
+    b_in.ensure(n * sizeof(S));
+    x_in.ensure(n * sizeof(S));
+    tmp64.ensure(n * sizeof(double2));
+    WilsonOp D(g, P, Uin);
+    const void* phi_in = phi;
+    if (P != QMG_F64) {
+      launch_convert(phi, QMG_F64, x_in.p, P, n, st);
+      phi_in = x_in.p;
+    }
+    D.apply(phi_in, b_in.p, r, st);                         // b = D phi
+    Blas<S>::axpby(0.0, b_in.p, -1.0, b_in.p, n, st);      // b = -D phi
+    gm.solve(D, b_in.p, x_in.p, true, r, 8, n_iter, 0.0, st);  // D psi' = -D phi
+    if (P != QMG_F64) {
+      launch_convert(x_in.p, P, tmp64.p, QMG_F64, n, st);
+      Blas<double2>::axpby(1.0, tmp64.p, 1.0, phi, n, st);
+    } else {
+      Blas<double2>::axpby(1.0, x_in.p, 1.0, phi, n, st);
+    }
+  }
+  RedWork rw;
+  DevBuf nrm(size_t(r) * sizeof(double));
+  Blas<double2>::norm2(phi, size_t(12) * g.V, r, nrm.as<double>(), rw, st);
+  Blas<double2>::scale_dev(phi, nrm.as<double>(), 0, size_t(12) * g.V, r, st);
+  QMG_HIP(hipStreamSynchronize(st));
+}
+
+template <class S>
+void run_setup(qmg_mg* mg, const qmg_mg_params* p, hipStream_t st) {
+  HierarchyDev& h = mg->h;
+  const Geom& g = h.g;
+  const int r = p->batch, ns = p->n_test / p->batch;
+  constexpr qmg_prec P = StoreTraits<S>::prec;
+  const auto t0 = Clock::now();
+  const void* Uin = (P == QMG_F64) ? h.U64.p : h.Uin.p;
+  DevBuf phi(size_t(r) * 12 * g.V * sizeof(double2));
+  DevBuf blocks(size_t(2) * h.blk.d * r * h.blk.N * sizeof(double2));
+  DevBuf b_in, x_in, tmp64;
+  Gmres<S> gm;
+  h.P64.alloc(size_t(2) * h.blk.d * h.k * h.blk.N * sizeof(double2));
+  mg->sigma_dev.alloc(size_t(2) * h.blk.d * h.k * sizeof(double));
+  int kp = 0;
+  double ts = 0, tv = 0;
+  for (int s = 0; s < ns; ++s) {
+    const auto a0 = Clock::now();
+    if (p->test_vectors) {
+      const double2* tv0 = static_cast<const double2*>(p->test_vectors) + size_t(s) * r * 12 * g.V;
+      launch_pack_spinor(tv0, QMG_F64, phi.p, QMG_F64, g.V, r, st);
+    } else {
+      launch_philox_native(g, p->seed, s * r, r, phi.p, st);
+    }
+    smooth_native<S>(g, Uin, phi.p, r, p->n_setup_iter, st, gm, b_in, x_in, tmp64);
+    const auto a1 = Clock::now();
+    launch_chiral_gather(h, phi.p, blocks.p, r, st);
+    kp = isvd_stream(h, blocks.p, r, kp, mg->sigma_dev, st);
+    QMG_HIP(hipStreamSynchronize(st));
+    const auto a2 = Clock::now();
+    ts += secs(a0, a1);
+    tv += secs(a1, a2);
+  }
+  QMG_CHECK(kp == h.k, QMG_ESHAPE, "streaming SVD ended with %d < k columns", kp);
+  const auto c0 = Clock::now();
+  const int m = 2 * h.k;
+  h.Y64.alloc(size_t(h.blk.d) * 9 * m * m * sizeof(double2));
+  build_coarse(h, st);
+  if (h.inner != QMG_F64) {
+    const size_t np = size_t(2) * h.blk.d * h.k * h.blk.N, ny = size_t(h.blk.d) * 9 * m * m;
+    h.Pin.alloc(np * prec_bytes(h.inner));
+    h.Yin.alloc(ny * prec_bytes(h.inner));
+    launch_convert(h.P64.p, QMG_F64, h.Pin.p, h.inner, np, st);
+    launch_convert(h.Y64.p, QMG_F64, h.Yin.p, h.inner, ny, st);
+  }
+  h.sigma.resize(size_t(2) * h.blk.d * h.k);
+  QMG_HIP(hipMemcpyAsync(h.sigma.data(), mg->sigma_dev.p, h.sigma.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         st));
+  QMG_HIP(hipStreamSynchronize(st));
+  const auto c1 = Clock::now();
+  h.t_smooth = ts;
+  h.t_svd = tv;
+  h.t_coarse = secs(c0, c1);
+  h.t_total = secs(t0, c1);
+}
+
+// ---------------------------------------------------------------------------------------
+// solve
+struct SolveStats {
+  long outer = 0, refinements = 0, coarse = 0, smooth = 0, escalations = 0;
+};
+
+// FP64 flexible GCR with the FP64 K-cycle, in place on native x64
+void solve_f64(const HierarchyDev& h, const void* b64, void* x64, int nrhs, double tol, int max_iter, bool x_zero,
+               hipStream_t st, SolveStats& ss, bool& converged) {
+  WilsonOp D(h.g, QMG_F64, h.U64.p);
+  CoarseOp Dc(h, QMG_F64, h.Y64.p);
+  KCycle<double2> K(h, D, Dc, h.P64.p);
+  Fgcr<double2> f;
+  auto res = f.solve(D, K, b64, x64, x_zero, nrhs, 16, max_iter, tol, st);
+  ss.outer += res.iters;
+  ss.coarse += K.coarse_iters;
+  ss.smooth += K.smooth_iters;
+  ss.refinements += 1;
+  converged = res.converged;
+}
+
+// FP64 defect correction around an inner solve in precision S
+template <class S>
+void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, double tol, int max_outer,
+                 hipStream_t st, SolveStats& ss, bool& converged) {
+  constexpr qmg_prec P = StoreTraits<S>::prec;
+  const size_t len = size_t(12) * h.g.V, n = len * nrhs;
+  WilsonOp D64(h.g, QMG_F64, h.U64.p);
+  WilsonOp Din(h.g, P, h.Uin.p);
+  CoarseOp Dc(h, P, h.Yin.p);
+  KCycle<S> K(h, Din, Dc, h.Pin.p);
+  Fgcr<S> f;
+  DevBuf r64(n * sizeof(double2)), rin(n * sizeof(S)), ein(n * sizeof(S)), nrm(nrhs * sizeof(double)),
+      bn(nrhs * sizeof(double));
+  RedWork rw;
+  std::vector<double> hb(nrhs), hr(nrhs);
+  Blas<double2>::norm2(b64, len, nrhs, bn.as<double>(), rw, st);
+  QMG_HIP(hipMemcpyAsync(hb.data(), bn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  QMG_HIP(hipStreamSynchronize(st));
+  const double inner_tol = (P == QMG_F32) ? 1e-5 : 1e-2;
+  std::vector<double> hist;
+  converged = false;
+  struct Acc {
+    SolveStats& ss;
+    KCycle<S>& K;
+    ~Acc() {
+      ss.coarse += K.coarse_iters;
+      ss.smooth += K.smooth_iters;
+    }
+  } acc{ss, K};
+  for (int ref = 0; ref < 40 && ss.outer < max_outer; ++ref) {
+    D64.apply(x64, r64.p, nrhs, st);
+    Blas<double2>::axpby(1.0, b64, -1.0, r64.p, n, st);  // r = b - D x in FP64
+    Blas<double2>::norm2(r64.p, len, nrhs, nrm.as<double>(), rw, st);
+    QMG_HIP(hipMemcpyAsync(hr.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    QMG_HIP(hipStreamSynchronize(st));
+    double worst = 0;
+    for (int i = 0; i < nrhs; ++i) {
+      QMG_CHECK(std::isfinite(hr[i]), QMG_ENONFINITE, "non-finite residual in defect correction");
+      worst = std::max(worst, hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0);
+    }
+    hist.push_back(worst);
+    if (worst <= tol) {
+      converged = true;
+      return;
+    }
+    // stagnation: two refinements each reducing less than 2x -> finish in FP64
+    const size_t H = hist.size();
+    if (H >= 3 && hist[H - 1] > 0.5 * hist[H - 2] && hist[H - 2] > 0.5 * hist[H - 3]) {
+      ss.escalations += 1;
+      bool c = false;
+      solve_f64(h, b64, x64, nrhs, tol, std::max(1, int(max_outer - ss.outer)), false, st, ss, c);
+      converged = c;
+      return;
+    }
+    // r / |r| in the inner precision
+    Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 0, len, nrhs, st);
+    launch_convert(r64.p, QMG_F64, rin.p, P, n, st);
+    auto res = f.solve(Din, K, rin.p, ein.p, true, nrhs, 16, int(max_outer - ss.outer), inner_tol, st);
+    ss.outer += res.iters;
+    ss.refinements += 1;
+    // x += |r| e
+    launch_convert(ein.p, P, r64.p, QMG_F64, n, st);
+    Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 1, len, nrhs, st);
+    Blas<double2>::axpby(1.0, r64.p, 1.0, x64, n, st);
+  }
+}
+
+template <class F>
+qmg_status guard(F&& f) {
+  try {
+    f();
+    return QMG_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return QMG_ENOMEM;
+  } catch (...) {
+    set_error("unexpected exception");
+    return QMG_EINVAL;
+  }
+}
+
+void check_ptr(const void* p, const char* name) { QMG_CHECK(p != nullptr, QMG_EINVAL, "%s is NULL", name); }
+
+qmg_status wilson_common(const qmg_lattice* lat, const void* U, const void* in, void* out, int32_t nrhs,
+                         qmg_prec prec, qmg_layout layout, hipStream_t st, bool dag) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(U, "U");
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(in != out, QMG_EINVAL, "in and out must not alias");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    check_prec(prec);
+    QMG_CHECK(layout == QMG_CANONICAL || layout == QMG_NATIVE, QMG_EINVAL, "bad layout");
+    Geom g = make_geom(lat);
+    DslashArgs a = make_dslash_args(g, nrhs, dag, layout == QMG_CANONICAL);
+    launch_dslash(prec, U, in, out, a, st);
+  });
+}
+
+}  // namespace
+}  // namespace qmg
+
+using namespace qmg;
+
+extern "C" {
+
+qmg_status qmg_wilson_apply(const qmg_lattice* lat, const void* U, const void* in, void* out, int32_t nrhs,
+                            qmg_prec prec, qmg_layout layout, hipStream_t stream) {
+  return wilson_common(lat, U, in, out, nrhs, prec, layout, stream, false);
+}
+
+qmg_status qmg_wilson_apply_adj(const qmg_lattice* lat, const void* U, const void* in, void* out, int32_t nrhs,
+                                qmg_prec prec, qmg_layout layout, hipStream_t stream) {
+  return wilson_common(lat, U, in, out, nrhs, prec, layout, stream, true);
+}
+
+qmg_status qmg_pack_spinor(const qmg_lattice* lat, const void* canon, void* native, int32_t nrhs, qmg_prec prec,
+                           hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(canon, "canon");
+    check_ptr(native, "native");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    check_prec(prec);
+    Geom g = make_geom(lat);
+    launch_pack_spinor(canon, QMG_F64, native, prec, g.V, nrhs, stream);
+  });
+}
+
+qmg_status qmg_unpack_spinor(const qmg_lattice* lat, const void* native, void* canon, int32_t nrhs, qmg_prec prec,
+                             hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(canon, "canon");
+    check_ptr(native, "native");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    check_prec(prec);
+    Geom g = make_geom(lat);
+    launch_unpack_spinor(native, prec, canon, QMG_F64, g.V, nrhs, stream);
+  });
+}
+
+qmg_status qmg_pack_gauge(const qmg_lattice* lat, const void* canon, void* native, qmg_prec prec,
+                          hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(canon, "canon");
+    check_ptr(native, "native");
+    check_prec(prec);
+    Geom g = make_geom(lat);
+    launch_pack_gauge(canon, native, prec, g.V, stream);
+  });
+}
+
+qmg_status qmg_mg_setup_stream_chiral_svd(const qmg_lattice* lat, const void* U, const qmg_mg_params* p,
+                                          qmg_mg** out, hipStream_t stream) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(U, "U");
+    check_ptr(p, "params");
+    check_ptr(out, "out");
+    Geom g = make_geom(lat);
+    Blocking b{};
+    b.nd = 1;
+    b.d = 1;
+    for (int q = 0; q < 4; ++q) {
+      QMG_CHECK(p->block[q] >= 1 && g.L[q] % p->block[q] == 0, QMG_ESHAPE,
+                "block extent %d (%d) does not divide lattice extent %d", q, p->block[q], g.L[q]);
+      b.b[q] = p->block[q];
+      b.cL[q] = g.L[q] / p->block[q];
+      b.nd *= b.b[q];
+      b.d *= b.cL[q];
+    }
+    b.N = 6 * b.nd;
+    QMG_CHECK(p->batch >= 1 && p->batch <= 48, QMG_ESHAPE, "batch r must be in [1, 48]");
+    QMG_CHECK(p->n_test >= p->batch && p->n_test % p->batch == 0, QMG_ESHAPE,
+              "n_test must be a positive multiple of batch");
+    QMG_CHECK(p->rank >= 1 && p->rank <= b.N && p->rank <= p->n_test && p->rank <= 32, QMG_ESHAPE,
+              "rank k must satisfy 1 <= k <= min(6*prod(block), n_test, 32)");
+    QMG_CHECK(p->n_setup_iter >= 0 && p->n_post_smooth >= 0 && p->coarse_max_iter >= 1, QMG_EINVAL,
+              "iteration counts must be non-negative");
+    QMG_CHECK(p->coarse_tol > 0 && p->coarse_tol < 1, QMG_EINVAL, "coarse_tol must be in (0, 1)");
+    check_prec(p->inner_prec);
+    QMG_CHECK(p->inner_prec == QMG_F64 || p->inner_prec == QMG_F32, QMG_EDTYPE,
+              "inner precision must be F64 or F32");
+    std::unique_ptr<qmg_mg> mg(new qmg_mg());
+    HierarchyDev& h = mg->h;
+    h.g = g;
+    h.blk = b;
+    h.k = p->rank;
+    h.inner = p->inner_prec;
+    h.n_post = p->n_post_smooth;
+    h.coarse_tol = p->coarse_tol;
+    h.coarse_max = p->coarse_max_iter;
+    build_tables(h);
+    h.U64.alloc(size_t(36) * g.V * sizeof(double2));
+    launch_pack_gauge(U, h.U64.p, QMG_F64, g.V, stream);
+    const double un = host_norm2(h.U64.p, size_t(36) * g.V, stream);
+    QMG_CHECK(std::isfinite(un), QMG_ENONFINITE, "gauge field has non-finite entries");
+    if (h.inner != QMG_F64) {
+      h.Uin.alloc(size_t(36) * g.V * prec_bytes(h.inner));
+      launch_pack_gauge(U, h.Uin.p, h.inner, g.V, stream);
+    }
+    if (h.inner == QMG_F64) run_setup<double2>(mg.get(), p, stream);
+    else run_setup<float2>(mg.get(), p, stream);
+    *out = mg.release();
+  });
+}
+
+qmg_status qmg_prolong(const qmg_mg* mg, const void* coarse_in, void* fine_out, int32_t nrhs, qmg_prec prec,
+                       hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(coarse_in, "coarse_in");
+    check_ptr(fine_out, "fine_out");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    const HierarchyDev& h = mg->h;
+    QMG_CHECK(prec == QMG_F64 || (prec == h.inner && prec == QMG_F32), QMG_EDTYPE,
+              "prolong: precision must be F64 or the F32 inner precision");
+    const void* P = prec == QMG_F64 ? h.P64.p : h.Pin.p;
+    const size_t n = size_t(nrhs) * 12 * h.g.V;
+    DevBuf nat(n * prec_bytes(prec));
+    launch_prolong(prec, h, P, coarse_in, nat.p, nrhs, stream);
+    launch_unpack_spinor(nat.p, prec, fine_out, prec, h.g.V, nrhs, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+qmg_status qmg_restrict(const qmg_mg* mg, const void* fine_in, void* coarse_out, int32_t nrhs, qmg_prec prec,
+                        hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(fine_in, "fine_in");
+    check_ptr(coarse_out, "coarse_out");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    const HierarchyDev& h = mg->h;
+    QMG_CHECK(prec == QMG_F64 || (prec == h.inner && prec == QMG_F32), QMG_EDTYPE,
+              "restrict: precision must be F64 or the F32 inner precision");
+    const void* P = prec == QMG_F64 ? h.P64.p : h.Pin.p;
+    const size_t n = size_t(nrhs) * 12 * h.g.V;
+    DevBuf nat(n * prec_bytes(prec));
+    launch_pack_spinor(fine_in, prec, nat.p, prec, h.g.V, nrhs, stream);
+    launch_restrict(prec, h, P, nat.p, coarse_out, nrhs, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+qmg_status qmg_coarse_apply(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
+                            hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(in != out, QMG_EINVAL, "in and out must not alias");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    const HierarchyDev& h = mg->h;
+    QMG_CHECK(prec == QMG_F64 || (prec == h.inner && prec == QMG_F32), QMG_EDTYPE,
+              "coarse_apply: precision must be F64 or the F32 inner precision");
+    launch_coarse_apply(prec, h, prec == QMG_F64 ? h.Y64.p : h.Yin.p, in, out, nrhs, stream);
+  });
+}
+
+qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, double tol, int32_t max_outer,
+                        int32_t adjoint, qmg_solve_info* info, hipStream_t stream) {
+  bool converged = false;
+  SolveStats ss;
+  double tr = 0, el = 0;
+  std::vector<double> rel;
+  qmg_status rc = guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(b, "b");
+    check_ptr(x, "x");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    QMG_CHECK(tol > 0 && tol < 1, QMG_EINVAL, "tol must be in (0, 1)");
+    QMG_CHECK(max_outer >= 1, QMG_EINVAL, "max_outer must be >= 1");
+    const HierarchyDev& h = mg->h;
+    const auto t0 = Clock::now();
+    const size_t len = size_t(12) * h.g.V, n = len * nrhs;
+    DevBuf b64(n * sizeof(double2)), x64(n * sizeof(double2)), r64(n * sizeof(double2));
+    launch_pack_spinor(b, QMG_F64, b64.p, QMG_F64, h.g.V, nrhs, stream);
+    launch_pack_spinor(x, QMG_F64, x64.p, QMG_F64, h.g.V, nrhs, stream);
+    if (adjoint) {
+      gamma5_f64(b64.p, h.g.V, nrhs, stream);
+      gamma5_f64(x64.p, h.g.V, nrhs, stream);
+    }
+    {
+      const double bn = host_norm2(b64.p, n, stream);
+      QMG_CHECK(std::isfinite(bn), QMG_ENONFINITE, "right-hand side has non-finite entries");
+    }
+    if (h.inner == QMG_F64) solve_f64(h, b64.p, x64.p, nrhs, tol, max_outer, false, stream, ss, converged);
+    else solve_mixed<float2>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
+    // true residual in FP64
+    WilsonOp D(h.g, QMG_F64, h.U64.p);
+    D.apply(x64.p, r64.p, nrhs, stream);
+    Blas<double2>::axpby(1.0, b64.p, -1.0, r64.p, n, stream);
+    RedWork rw;
+    DevBuf nr(2 * nrhs * sizeof(double));
+    Blas<double2>::norm2(r64.p, len, nrhs, nr.as<double>(), rw, stream);
+    Blas<double2>::norm2(b64.p, len, nrhs, nr.as<double>() + nrhs, rw, stream);
+    std::vector<double> hn(2 * nrhs);
+    QMG_HIP(hipMemcpyAsync(hn.data(), nr.p, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, stream));
+    QMG_HIP(hipStreamSynchronize(stream));
+    rel.resize(nrhs);
+    for (int i = 0; i < nrhs; ++i) {
+      rel[i] = hn[nrhs + i] > 0 ? std::sqrt(hn[i] / hn[nrhs + i]) : 0.0;
+      tr = std::max(tr, rel[i]);
+    }
+    QMG_CHECK(std::isfinite(tr), QMG_ENONFINITE, "non-finite final residual");
+    if (adjoint) gamma5_f64(x64.p, h.g.V, nrhs, stream);
+    launch_unpack_spinor(x64.p, QMG_F64, x, QMG_F64, h.g.V, nrhs, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+    el = secs(t0, Clock::now());
+    QMG_CHECK(tr <= tol, QMG_ENOCONV, "solve stopped at relative residual %.3e > tol %.3e", tr, tol);
+  });
+  if (info) {
+    for (int i = 0; i < nrhs; ++i) {
+      info[i].outer_iters = int(ss.outer);
+      info[i].refinements = int(ss.refinements);
+      info[i].coarse_iters = int(ss.coarse);
+      info[i].smoother_iters = int(ss.smooth);
+      info[i].precision_escalations = int(ss.escalations);
+      info[i].true_rel_res = i < int(rel.size()) ? rel[i] : tr;
+      info[i].seconds = el;
+    }
+  }
+  return rc;
+}
+
+qmg_status qmg_link_force(const qmg_lattice* lat, const void* xv, const void* lam, void* dU, int32_t nrhs,
+                          hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(xv, "x");
+    check_ptr(lam, "lambda");
+    check_ptr(dU, "dU");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    Geom g = make_geom(lat);
+    launch_link_force(g, xv, lam, dU, nrhs, stream);
+  });
+}
+
+qmg_status qmg_random_test_vectors(const qmg_lattice* lat, uint64_t seed, int32_t v0, int32_t n, void* out,
+                                   hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(out, "out");
+    QMG_CHECK(n >= 1 && v0 >= 0, QMG_EINVAL, "need n >= 1 and v0 >= 0");
+    Geom g = make_geom(lat);
+    DevBuf nat(size_t(n) * 12 * g.V * sizeof(double2));
+    launch_philox_native(g, seed, v0, n, nat.p, stream);
+    launch_unpack_spinor(nat.p, QMG_F64, out, QMG_F64, g.V, n, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+qmg_status qmg_smooth(const qmg_lattice* lat, const void* U, const void* phi, void* psi, int32_t nrhs,
+                      int32_t n_iter, qmg_prec prec, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(U, "U");
+    check_ptr(phi, "phi");
+    check_ptr(psi, "psi");
+    QMG_CHECK(nrhs >= 1 && n_iter >= 0, QMG_EINVAL, "need nrhs >= 1, n_iter >= 0");
+    QMG_CHECK(prec == QMG_F64 || prec == QMG_F32, QMG_EDTYPE, "smooth: precision must be F64 or F32");
+    Geom g = make_geom(lat);
+    DevBuf Un(size_t(36) * g.V * prec_bytes(prec)), ph(size_t(nrhs) * 12 * g.V * sizeof(double2));
+    launch_pack_gauge(U, Un.p, prec, g.V, stream);
+    launch_pack_spinor(phi, QMG_F64, ph.p, QMG_F64, g.V, nrhs, stream);
+    DevBuf b_in, x_in, tmp64;
+    if (prec == QMG_F64) {
+      Gmres<double2> gm;
+      smooth_native<double2>(g, Un.p, ph.p, nrhs, n_iter, stream, gm, b_in, x_in, tmp64);
+    } else {
+      Gmres<float2> gm;
+      smooth_native<float2>(g, Un.p, ph.p, nrhs, n_iter, stream, gm, b_in, x_in, tmp64);
+    }
+    launch_unpack_spinor(ph.p, QMG_F64, psi, QMG_F64, g.V, nrhs, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+qmg_status qmg_mg_query(const qmg_mg* mg, int32_t* coarse_dims, int32_t* n_agg, int32_t* rank) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    if (coarse_dims)
+      for (int q = 0; q < 4; ++q) coarse_dims[q] = mg->h.blk.cL[q];
+    if (n_agg) *n_agg = mg->h.blk.d;
+    if (rank) *rank = mg->h.k;
+  });
+}
+
+qmg_status qmg_mg_get_prolongator(const qmg_mg* mg, void* P, double* sigma, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    if (P) launch_export_P(mg->h, P, stream);
+    if (sigma) std::memcpy(sigma, mg->h.sigma.data(), mg->h.sigma.size() * sizeof(double));
+    QMG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+qmg_status qmg_mg_get_coarse(const qmg_mg* mg, void* Y, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(Y, "Y");
+    launch_export_Y(mg->h, Y, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(t, "t");
+    t[0] = mg->h.t_smooth;
+    t[1] = mg->h.t_svd;
+    t[2] = mg->h.t_coarse;
+    t[3] = mg->h.t_total;
+  });
+}
+
+void qmg_mg_destroy(qmg_mg* mg) { delete mg; }
+
+const char* qmg_last_error(void) { return last_error_ptr(); }
+
+const char* qmg_version(void) { return "qmg 0.1 (gfx950)"; }
+
+}  // extern "C"

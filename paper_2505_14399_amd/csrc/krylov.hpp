@@ -1,0 +1,106 @@
+// Vector kernels and Krylov solvers over native complex arrays [nrhs][len].
+//
+// Reductions accumulate in double and are deterministic: each workgroup reduces a fixed
+// slice (wavefront shuffles, then LDS), partial sums are combined in fixed order by a
+// second pass.  Coefficients produced by one kernel (inner products, norms) stay on the
+// device and are consumed by the next, so a Krylov iteration needs no host round trip
+// except the one that reads the small Hessenberg column for the convergence test.
+#pragma once
+
+#include "qmg_internal.hpp"
+
+namespace qmg {
+
+struct LinOp {
+  virtual ~LinOp() = default;
+  // out = A in, nrhs vectors of len() complex numbers each, storage prec()
+  virtual void apply(const void* in, void* out, int nrhs, hipStream_t st) = 0;
+  virtual size_t len() const = 0;
+  virtual qmg_prec prec() const = 0;
+};
+
+struct Precond {
+  virtual ~Precond() = default;
+  // z ~ A^-1 r (may vary between calls: flexible outer solver required)
+  virtual void apply(const void* r, void* z, int nrhs, hipStream_t st) = 0;
+};
+
+// scratch for two-pass reductions
+struct RedWork {
+  DevBuf partial;  // double2 partial sums
+  DevBuf result;   // double2 results
+  void ensure(size_t npart, size_t nres) {
+    partial.ensure(npart * sizeof(double2));
+    result.ensure(nres * sizeof(double2));
+  }
+};
+
+template <class S>
+struct Blas {
+  static void zero(void* x, size_t n, hipStream_t st);
+  static void copy(const void* x, void* y, size_t n, hipStream_t st);
+  // y = a x + b y (real scalars)
+  static void axpby(double a, const void* x, double b, void* y, size_t n, hipStream_t st);
+  // out[i * nrhs + r] = <X_i[r], w[r]>, X_i = X + i * xstride complex entries, i < m
+  static void dot_multi(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs,
+                        double2* out, RedWork& rw, hipStream_t st);
+  // out[r] = ||w[r]||^2
+  static void norm2(const void* w, size_t len, int nrhs, double* out, RedWork& rw, hipStream_t st);
+  // w[r] += sgn * sum_i c[i * nrhs + r] X_i[r]
+  static void axpy_multi(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w,
+                         size_t len, int nrhs, hipStream_t st);
+  // w[r] *= f(n2[r]) with f = 1/sqrt (mode 0) or sqrt (mode 1) or a direct factor (mode 2,
+  // n2 then holds the factor); a zero norm gives a zero vector in mode 0
+  static void scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st);
+  // w[r] *= c[r] (complex, device)
+  static void scale_cdev(void* w, const double2* c, double sgn, size_t len, int nrhs, hipStream_t st);
+  // x[r] += sgn * c[r] * y[r]  (complex scalar per rhs, on device)
+  static void caxpy_dev(const double2* c, double sgn, const void* y, void* x, size_t len, int nrhs,
+                        hipStream_t st);
+};
+
+// Restarted GMRES(m), multi right-hand side, Arnoldi with classical Gram-Schmidt done twice
+// (CGS2) on the device and Givens rotations on the host.
+template <class S>
+class Gmres {
+ public:
+  struct Result {
+    int iters = 0;           // Arnoldi steps taken (max over rhs)
+    bool converged = true;
+    std::vector<double> rel_est;  // final residual estimate / ||b|| per rhs
+  };
+  // x: initial guess if !x_zero, solution on return.  tol <= 0: exactly max_iter steps.
+  Result solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int restart, int max_iter, double tol,
+               hipStream_t st);
+
+ private:
+  void ensure(size_t len, int nrhs, int restart);
+  DevBuf V_, H_, h1_, h2_, nrm_, y_, r_;
+  PinnedBuf hb_;
+  RedWork rw_;
+  size_t len_ = 0;
+  int nrhs_ = 0, restart_ = 0;
+};
+
+// Flexible GCR(restart) with a (possibly nonlinear) preconditioner, multi right-hand side.
+template <class S>
+class Fgcr {
+ public:
+  struct Result {
+    int iters = 0;
+    bool converged = false;
+    std::vector<double> rel_res;  // true residual / ||b|| per rhs at exit (in precision S)
+  };
+  Result solve(LinOp& A, Precond& M, const void* b, void* x, bool x_zero, int nrhs, int restart, int max_iter,
+               double tol, hipStream_t st);
+
+ private:
+  void ensure(size_t len, int nrhs, int restart);
+  DevBuf Z_, W_, r_, beta_, tmp_, nrm_, bn_;
+  PinnedBuf hb_;
+  RedWork rw_;
+  size_t len_ = 0;
+  int nrhs_ = 0, restart_ = 0;
+};
+
+}  // namespace qmg

@@ -1,0 +1,54 @@
+// The two-level hierarchy owned by a qmg_mg handle, and the kernels that act on it.
+#pragma once
+
+#include "krylov.hpp"
+
+namespace qmg {
+
+// Aggregate-local tables (device, int32):
+//   bsite [d][nd]   fine site of (aggregate j, in-block index ib), ib lexicographic in the block
+//   cnb   [d][8]    coarse neighbour of aggregate j in direction dir
+// P row order inside (j, alpha): row = s6 * nd + ib with s6 = 3 * spin_in_chirality + colour;
+// this component-major order lets consecutive threads read consecutive P entries.
+struct HierarchyDev {
+  Geom g;
+  Blocking blk;
+  int k = 0;                 // rank per chirality
+  qmg_prec inner = QMG_F64;  // inner storage precision
+
+  DevBuf U64, Uin;           // native gauge, FP64 and inner precision
+  DevBuf bsite, cnb;         // tables
+  DevBuf P64, Pin;           // [d][2][k][N]
+  DevBuf Y64, Yin;           // [d][9][2k][2k] column-major blocks
+  std::vector<double> sigma; // [d][2][k]
+  double t_smooth = 0, t_svd = 0, t_coarse = 0, t_total = 0;
+  int n_post = 8, coarse_max = 500;
+  double coarse_tol = 0.03;
+};
+
+// prolong: fine[rhs] (native, storage S) = P coarse[rhs]
+void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const void* coarse, void* fine, int nrhs,
+                    hipStream_t st);
+// restrict: coarse[rhs] = P^dag fine[rhs]
+void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const void* fine, void* coarse, int nrhs,
+                     hipStream_t st);
+// out = D_c in, coarse vectors [nrhs][d][2k]
+void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, const void* in, void* out, int nrhs,
+                         hipStream_t st);
+// Galerkin build in FP64 from U64 and P64 into Y64 (needs a workspace of 8 * d * (2k)^2 double2)
+void build_coarse(HierarchyDev& h, hipStream_t st);
+// chiral split + block gather: fine FP64 native [r][12][V] -> blocks [2d][r][N] FP64
+void launch_chiral_gather(const HierarchyDev& h, const void* fine, void* blocks, int r, hipStream_t st);
+// one streaming-SVD stream for all (aggregate, chirality) problems, in place on P64 / sigma
+// kp: current columns (0 on the first stream), returns the new column count
+int isvd_stream(HierarchyDev& h, const void* blocks, int r, int kp, DevBuf& sigma_dev, hipStream_t st);
+// canonical P export [d][2][N][k] with canonical row order 6*ib + 3*sp + c
+void launch_export_P(const HierarchyDev& h, void* out, hipStream_t st);
+// canonical Y export [d][9][2k row][2k col]
+void launch_export_Y(const HierarchyDev& h, void* out, hipStream_t st);
+// Philox4x32-10 Gaussian test vectors into native FP64 [n][12][V]
+void launch_philox_native(const Geom& g, uint64_t seed, int v0, int n, void* out, hipStream_t st);
+// link force: canonical FP64 x, lambda -> canonical FP64 dU
+void launch_link_force(const Geom& g, const void* x, const void* lam, void* dU, int nrhs, hipStream_t st);
+
+}  // namespace qmg

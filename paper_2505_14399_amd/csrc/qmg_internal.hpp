@@ -1,0 +1,266 @@
+// Internal definitions shared by the HIP translation units of libqmg.
+//
+// Native layouts (structure of arrays, one complex plane per component, so that a
+// wavefront reading one component of 64 consecutive sites issues one coalesced load):
+//   spinor  [nrhs][12 = 3*spin + colour][V]   complex
+//   gauge   [4 mu][9 = 3*row + col][V]        complex (physical links, no boundary sign)
+//   coarse  [nrhs][d][2k]                     complex (dof order chirality, then rank index)
+//   P       [d][2][k][N]                      complex, N = 6 n_d rows per (aggregate, chirality)
+//                                             row = s6 * n_d + site_in_block, s6 = 3*spin_in_chirality + colour
+//   Y       [d][9][2k col][2k row]            complex (slot 0 self, 1+d the hop direction d)
+// Site index is lexicographic, x fastest; direction d < 4 is +mu, d >= 4 is -mu.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qmg.h"
+
+namespace qmg {
+
+// ----------------------------------------------------------------------------------------
+// errors
+
+void set_error(const char* fmt, ...);
+const char* last_error_ptr();
+
+struct Error {
+  qmg_status code;
+};
+
+#define QMG_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      ::qmg::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call, hipGetErrorString(e_));  \
+      throw ::qmg::Error{QMG_EHIP};                                                         \
+    }                                                                                       \
+  } while (0)
+
+#define QMG_CHECK(cond, code, ...)      \
+  do {                                  \
+    if (!(cond)) {                      \
+      ::qmg::set_error(__VA_ARGS__);    \
+      throw ::qmg::Error{code};         \
+    }                                   \
+  } while (0)
+
+#define QMG_LAUNCH_CHECK() QMG_HIP(hipGetLastError())
+
+// ----------------------------------------------------------------------------------------
+// complex arithmetic (compute types: float, double)
+
+template <class T>
+struct cplx {
+  T re, im;
+};
+
+template <class T> __host__ __device__ inline cplx<T> mk(T r, T i) { return {r, i}; }
+template <class T> __host__ __device__ inline cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __host__ __device__ inline cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __host__ __device__ inline cplx<T> operator-(cplx<T> a) { return {-a.re, -a.im}; }
+template <class T> __host__ __device__ inline cplx<T> operator*(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T> __host__ __device__ inline cplx<T> operator*(T s, cplx<T> a) { return {s * a.re, s * a.im}; }
+template <class T> __host__ __device__ inline cplx<T>& operator+=(cplx<T>& a, cplx<T> b) { a.re += b.re; a.im += b.im; return a; }
+template <class T> __host__ __device__ inline cplx<T>& operator-=(cplx<T>& a, cplx<T> b) { a.re -= b.re; a.im -= b.im; return a; }
+template <class T> __host__ __device__ inline cplx<T> conj(cplx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <class T> __host__ __device__ inline cplx<T> cmul_conj(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <class T> __host__ __device__ inline T norm2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
+// i * a, -i * a
+template <class T> __host__ __device__ inline cplx<T> times_i(cplx<T> a) { return {-a.im, a.re}; }
+template <class T> __host__ __device__ inline cplx<T> times_mi(cplx<T> a) { return {a.im, -a.re}; }
+
+// ----------------------------------------------------------------------------------------
+// storage types: complex numbers as stored in memory
+
+struct cbf16 {  // two bfloat16 (upper halves of IEEE binary32), round to nearest even
+  uint16_t re, im;
+};
+struct chalf {
+  _Float16 re, im;
+};
+
+__host__ __device__ inline float bf16_to_f(uint16_t h) {
+  uint32_t u = uint32_t(h) << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+__host__ __device__ inline uint16_t f_to_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf/nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+template <class S> struct StoreTraits;
+template <> struct StoreTraits<double2> {
+  using C = double;
+  static constexpr qmg_prec prec = QMG_F64;
+  __host__ __device__ static cplx<double> ld(double2 v) { return {v.x, v.y}; }
+  __host__ __device__ static double2 st(cplx<double> v) { return make_double2(v.re, v.im); }
+};
+template <> struct StoreTraits<float2> {
+  using C = float;
+  static constexpr qmg_prec prec = QMG_F32;
+  __host__ __device__ static cplx<float> ld(float2 v) { return {v.x, v.y}; }
+  __host__ __device__ static float2 st(cplx<float> v) { return make_float2(v.re, v.im); }
+};
+template <> struct StoreTraits<cbf16> {
+  using C = float;
+  static constexpr qmg_prec prec = QMG_BF16;
+  __host__ __device__ static cplx<float> ld(cbf16 v) { return {bf16_to_f(v.re), bf16_to_f(v.im)}; }
+  __host__ __device__ static cbf16 st(cplx<float> v) { return {f_to_bf16(v.re), f_to_bf16(v.im)}; }
+};
+template <> struct StoreTraits<chalf> {
+  using C = float;
+  static constexpr qmg_prec prec = QMG_F16;
+  __host__ __device__ static cplx<float> ld(chalf v) { return {float(v.re), float(v.im)}; }
+  __host__ __device__ static chalf st(cplx<float> v) { return {_Float16(v.re), _Float16(v.im)}; }
+};
+
+template <class S> using ctype = typename StoreTraits<S>::C;
+
+template <class S, class T>
+__device__ inline cplx<ctype<S>> ldc(const S* p, T i) {
+  return StoreTraits<S>::ld(p[i]);
+}
+template <class S, class T, class U>
+__device__ inline void stc(S* p, T i, cplx<U> v) {
+  using C = ctype<S>;
+  p[i] = StoreTraits<S>::st(cplx<C>{C(v.re), C(v.im)});
+}
+
+inline size_t prec_bytes(qmg_prec p) {  // bytes per complex number
+  switch (p) {
+    case QMG_F64: return 16;
+    case QMG_F32: return 8;
+    case QMG_BF16: return 4;
+    case QMG_F16: return 4;
+  }
+  return 0;
+}
+
+// ----------------------------------------------------------------------------------------
+// geometry
+
+struct Geom {
+  int L[4];      // extents x, y, z, t
+  int V;         // volume
+  int bc_t;      // +1 periodic, -1 antiperiodic in t
+  double mass, xi;
+  double diag() const { return mass + 1.0 + 3.0 / xi; }
+  double cw(int mu) const { return mu == 3 ? 1.0 : 1.0 / xi; }
+};
+
+Geom make_geom(const qmg_lattice* lat);
+
+struct Blocking {
+  int b[4];     // block extents
+  int cL[4];    // coarse extents
+  int nd;       // sites per block
+  int d;        // number of aggregates
+  int N;        // rows per (aggregate, chirality) = 6 nd
+};
+
+// ----------------------------------------------------------------------------------------
+// device memory owned by the library
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      set_error("hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+      throw Error{QMG_ENOMEM};
+    }
+    bytes = n;
+  }
+  void ensure(size_t n) { if (n > bytes) alloc(n); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// pinned host staging memory (for asynchronous device-to-host reads of small scalars)
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  void ensure(size_t n) {
+    if (n <= bytes) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(&p, n, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      set_error("hipHostMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+      throw Error{QMG_ENOMEM};
+    }
+    bytes = n;
+  }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  template <class T> T* as() { return static_cast<T*>(p); }
+};
+
+// ----------------------------------------------------------------------------------------
+// kernels exposed across translation units (host launchers)
+
+struct DslashArgs {
+  int L[4];
+  int V;
+  int bc_t;
+  float  diag_f, cw_f[4];
+  double diag_d, cw_d[4];
+  int nrhs;
+  int dagger;
+  int canonical;  // 1: AoS canonical layouts, 0: native SoA
+};
+DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical);
+
+// out = D in (or D^dag) ; U in the same storage type and layout as the spinors
+void launch_dslash(qmg_prec prec, const void* U, const void* in, void* out, const DslashArgs& a,
+                   hipStream_t st);
+
+// layout conversion (canonical FP64 <-> native storage), spinors and gauge
+// canonical [nrhs][V][12] in precision pc <-> native [nrhs][12][V] in precision pn
+void launch_pack_spinor(const void* canon, qmg_prec pc, void* native, qmg_prec pn, int V, int nrhs, hipStream_t st);
+void launch_unpack_spinor(const void* native, qmg_prec pn, void* canon, qmg_prec pc, int V, int nrhs, hipStream_t st);
+void launch_pack_gauge(const void* canon_f64, void* native, qmg_prec prec, int V, hipStream_t st);
+// precision conversion between native buffers of n complex numbers
+void launch_convert(const void* in, qmg_prec pin, void* out, qmg_prec pout, size_t n, hipStream_t st);
+
+}  // namespace qmg

@@ -1,0 +1,569 @@
+// Transfer operators P and R = P^dagger (Eq. (6)), the Galerkin coarse operator D_c = R D P
+// (Eq. (5)) and its application, plus the layout kernels of the hierarchy.
+#include <cmath>
+
+#include "mg.hpp"
+
+namespace qmg {
+
+namespace {
+
+inline unsigned cdiv(size_t a, size_t b) { return unsigned((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------------------
+// prolong: one thread per (row of a (j, alpha) block), all k columns of P
+template <class S>
+__global__ __launch_bounds__(256) void k_prolong(const S* __restrict__ P, const S* __restrict__ vc,
+                                                 S* __restrict__ fine, const int* __restrict__ bsite, int nd, int N,
+                                                 int k, int d, int V) {
+  using C = ctype<S>;
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int ja = blockIdx.y;  // j * 2 + alpha
+  const int rhs = blockIdx.z;
+  if (row >= N) return;
+  const int j = ja >> 1, a = ja & 1;
+  const int s6 = row / nd, ib = row - s6 * nd;
+  const S* Pc = P + size_t(ja) * k * N + row;
+  const S* v = vc + (size_t(rhs) * d + j) * 2 * k + a * k;
+  cplx<C> acc = {C(0), C(0)};
+  for (int i = 0; i < k; ++i) acc += ldc(Pc, size_t(i) * N) * ldc(v, i);
+  const int site = bsite[size_t(j) * nd + ib];
+  const int comp = 6 * a + s6;
+  stc(fine, (size_t(rhs) * 12 + comp) * V + site, acc);
+}
+
+// restrict: one workgroup per (j, alpha, rhs); the block of the fine vector is staged in LDS,
+// wavefront w reduces columns i = w, w+4, ... with lanes striding over rows
+template <class S>
+__global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const S* __restrict__ fine,
+                                                  S* __restrict__ vc, const int* __restrict__ bsite, int nd, int N,
+                                                  int k, int d, int V) {
+  using C = ctype<S>;
+  extern __shared__ unsigned char smem[];
+  cplx<C>* psi = reinterpret_cast<cplx<C>*>(smem);
+  const int ja = blockIdx.x, rhs = blockIdx.y;
+  const int j = ja >> 1, a = ja & 1;
+  for (int row = threadIdx.x; row < N; row += 256) {
+    const int s6 = row / nd, ib = row - s6 * nd;
+    const int site = bsite[size_t(j) * nd + ib];
+    psi[row] = ldc(fine, (size_t(rhs) * 12 + 6 * a + s6) * V + site);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = w; i < k; i += 4) {
+    const S* Pc = P + (size_t(ja) * k + i) * N;
+    cplx<C> acc = {C(0), C(0)};
+    for (int row = lane; row < N; row += 64) acc += cmul_conj(ldc(Pc, row), psi[row]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.re += __shfl_down(acc.re, off, 64);
+      acc.im += __shfl_down(acc.im, off, 64);
+    }
+    if (lane == 0) stc(vc, (size_t(rhs) * d + j) * 2 * k + a * k + i, acc);
+  }
+}
+
+// coarse apply: one thread per (aggregate, row); Y blocks column-major so that the threads of
+// one aggregate read consecutive entries
+template <class S>
+__global__ __launch_bounds__(256) void k_coarse_apply(const S* __restrict__ Y, const S* __restrict__ in,
+                                                      S* __restrict__ out, const int* __restrict__ cnb, int d, int m) {
+  using C = ctype<S>;
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (g >= size_t(d) * m) return;
+  const int j = int(g / m), row = int(g - size_t(j) * m);
+  const S* vin = in + size_t(rhs) * d * m;
+  cplx<C> acc = {C(0), C(0)};
+  for (int slot = 0; slot < 9; ++slot) {
+    const int nbj = slot == 0 ? j : cnb[j * 8 + slot - 1];
+    const S* Yb = Y + (size_t(j) * 9 + slot) * m * m + row;
+    const S* v = vin + size_t(nbj) * m;
+    for (int col = 0; col < m; ++col) acc += ldc(Yb, size_t(col) * m) * ldc(v, col);
+  }
+  stc(out, size_t(rhs) * d * m + g, acc);
+}
+
+// ---------------------------------------------------------------------------------------
+// Galerkin build (FP64).  One workgroup per aggregate j.  For every site x of the block and
+// every hop direction, the hop term H(x, dir) is applied to the 2k columns of P at the
+// neighbour y and contracted with P(x)^dag; hops leaving the block through its face go to
+// Y_{1+dir}(j), the others (and the diagonal term) to Y_0(j).
+struct BuildArgs {
+  int L[4], b[4], cL[4];
+  int V, nd, N, k, d, bc_t;
+  double diag, cw[4];
+};
+
+__device__ inline int lex4(const int* c, const int* L) { return c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3])); }
+
+// chi (12 comps, chirality beta only) -> H chi  for direction dir with link u (already U or U^dag)
+template <int MU>
+__device__ inline void hop_col(const cplx<double>* q, int beta, double sg, const cplx<double>* u, double coef,
+                               cplx<double>* out) {
+  // h = chi_up + sg A chi_dn
+  cplx<double> h[6];
+  for (int c = 0; c < 3; ++c) {
+    cplx<double> u0, u1, d0, d1;
+    if (beta == 0) {
+      u0 = q[c]; u1 = q[3 + c]; d0 = {0, 0}; d1 = {0, 0};
+    } else {
+      u0 = {0, 0}; u1 = {0, 0}; d0 = q[c]; d1 = q[3 + c];
+    }
+    if (MU == 0) { h[c] = u0 + sg * times_mi(d1); h[3 + c] = u1 + sg * times_mi(d0); }
+    else if (MU == 1) { h[c] = u0 - sg * d1; h[3 + c] = u1 + sg * d0; }
+    else if (MU == 2) { h[c] = u0 + sg * times_mi(d0); h[3 + c] = u1 + sg * times_i(d1); }
+    else { h[c] = u0 + sg * d0; h[3 + c] = u1 + sg * d1; }
+  }
+  cplx<double> w[6];
+  for (int sp = 0; sp < 2; ++sp)
+    for (int a = 0; a < 3; ++a) {
+      cplx<double> t = {0, 0};
+      for (int bb = 0; bb < 3; ++bb) t += u[3 * a + bb] * h[3 * sp + bb];
+      w[3 * sp + a] = t;
+    }
+  for (int c = 0; c < 3; ++c) {
+    cplx<double> w0 = w[c], w1 = w[3 + c];
+    out[c] = coef * w0;
+    out[3 + c] = coef * w1;
+    cplx<double> l0, l1;
+    if (MU == 0) { l0 = times_i(w1); l1 = times_i(w0); }
+    else if (MU == 1) { l0 = w1; l1 = -w0; }
+    else if (MU == 2) { l0 = times_i(w0); l1 = times_mi(w1); }
+    else { l0 = w0; l1 = w1; }
+    out[6 + c] = (coef * sg) * l0;
+    out[9 + c] = (coef * sg) * l1;
+  }
+}
+
+constexpr int kMaxM = 64;        // 2k <= 64
+constexpr int kMaxPerThread = (kMaxM * kMaxM + 255) / 256;
+
+__global__ __launch_bounds__(256) void k_build_coarse(const double2* __restrict__ U, const double2* __restrict__ P,
+                                                      const int* __restrict__ bsite, double2* __restrict__ Y,
+                                                      BuildArgs a) {
+  __shared__ cplx<double> Px[2 * 6 * 32];        // [alpha][s6][i]
+  __shared__ cplx<double> HP[12 * kMaxM];        // [comp][col]
+  __shared__ cplx<double> link[9];
+  const int j = blockIdx.x;
+  const int k = a.k, m = 2 * k, N = a.N, nd = a.nd, V = a.V;
+  const int tid = threadIdx.x;
+  const int nent = m * m;
+  cplx<double> face[kMaxPerThread], intra[kMaxPerThread];
+  for (int e = 0; e < kMaxPerThread; ++e) intra[e] = {0, 0};
+
+  for (int dir = 0; dir < 8; ++dir) {
+    const int mu = dir & 3;
+    const bool fwd = dir < 4;
+    for (int e = 0; e < kMaxPerThread; ++e) face[e] = {0, 0};
+    for (int ib = 0; ib < nd; ++ib) {
+      const int x = bsite[size_t(j) * nd + ib];
+      int c[4];
+      {
+        int rem = x;
+        for (int q = 0; q < 4; ++q) { c[q] = rem % a.L[q]; rem /= a.L[q]; }
+      }
+      int cy[4] = {c[0], c[1], c[2], c[3]};
+      cy[mu] = fwd ? (c[mu] + 1) % a.L[mu] : (c[mu] + a.L[mu] - 1) % a.L[mu];
+      const int y = lex4(cy, a.L);
+      int cj[4], ci[4];
+      for (int q = 0; q < 4; ++q) { cj[q] = cy[q] / a.b[q]; ci[q] = cy[q] % a.b[q]; }
+      const int jy = lex4(cj, a.cL), iby = lex4(ci, a.b);
+      const bool is_face = fwd ? (c[mu] % a.b[mu] == a.b[mu] - 1) : (c[mu] % a.b[mu] == 0);
+      double sgnbc = 1.0;
+      if (mu == 3 && a.bc_t < 0) {
+        if (fwd && c[3] == a.L[3] - 1) sgnbc = -1.0;
+        if (!fwd && c[3] == 0) sgnbc = -1.0;
+      }
+      const double coef = -0.5 * a.cw[mu] * sgnbc;
+      // stage P(x) rows and the link
+      for (int t = tid; t < 2 * 6 * k; t += 256) {
+        const int al = t / (6 * k), rem = t - al * 6 * k, s6 = rem / k, i = rem - s6 * k;
+        double2 v = P[((size_t(j) * 2 + al) * k + i) * N + size_t(s6) * nd + ib];
+        Px[(al * 6 + s6) * k + i] = {v.x, v.y};
+      }
+      if (tid < 9) {
+        // forward: U_mu(x); backward: U_mu(y)^dag
+        if (fwd) {
+          double2 v = U[(size_t(mu) * 9 + tid) * V + x];
+          link[tid] = {v.x, v.y};
+        } else {
+          const int r = tid / 3, cc = tid % 3;
+          double2 v = U[(size_t(mu) * 9 + cc * 3 + r) * V + y];
+          link[tid] = {v.x, -v.y};
+        }
+      }
+      __syncthreads();
+      if (tid < m) {
+        const int beta = tid / k, l = tid - beta * k;
+        cplx<double> q[6];
+        for (int s6 = 0; s6 < 6; ++s6) {
+          double2 v = P[((size_t(jy) * 2 + beta) * k + l) * N + size_t(s6) * nd + iby];
+          q[s6] = {v.x, v.y};
+        }
+        cplx<double> out[12];
+        const double sg = fwd ? -1.0 : 1.0;
+        switch (mu) {
+          case 0: hop_col<0>(q, beta, sg, link, coef, out); break;
+          case 1: hop_col<1>(q, beta, sg, link, coef, out); break;
+          case 2: hop_col<2>(q, beta, sg, link, coef, out); break;
+          default: hop_col<3>(q, beta, sg, link, coef, out); break;
+        }
+        for (int cc = 0; cc < 12; ++cc) HP[cc * m + tid] = out[cc];
+      }
+      __syncthreads();
+      for (int e = 0; e < kMaxPerThread; ++e) {
+        const int idx = tid + e * 256;
+        if (idx >= nent) break;
+        const int col = idx / m, row = idx - col * m;
+        const int al = row / k, i = row - al * k;
+        cplx<double> s = {0, 0};
+        for (int s6 = 0; s6 < 6; ++s6) s += cmul_conj(Px[(al * 6 + s6) * k + i], HP[(6 * al + s6) * m + col]);
+        if (is_face) face[e] += s;
+        else intra[e] += s;
+        if (dir == 0) {  // diagonal term once per site
+          const int be = col / k, l = col - be * k;
+          if (be == al) {
+            cplx<double> dsum = {0, 0};
+            for (int s6 = 0; s6 < 6; ++s6) dsum += cmul_conj(Px[(al * 6 + s6) * k + i], Px[(al * 6 + s6) * k + l]);
+            intra[e] += a.diag * dsum;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = 0; e < kMaxPerThread; ++e) {
+      const int idx = tid + e * 256;
+      if (idx >= nent) break;
+      Y[(size_t(j) * 9 + 1 + dir) * nent + idx] = make_double2(face[e].re, face[e].im);
+    }
+  }
+  for (int e = 0; e < kMaxPerThread; ++e) {
+    const int idx = tid + e * 256;
+    if (idx >= nent) break;
+    Y[(size_t(j) * 9) * nent + idx] = make_double2(intra[e].re, intra[e].im);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+__global__ void k_chiral_gather(const double2* __restrict__ fine, double2* __restrict__ blocks,
+                                const int* __restrict__ bsite, int nd, int N, int r, int V) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int v = blockIdx.y, ja = blockIdx.z;
+  if (row >= N) return;
+  const int j = ja >> 1, a = ja & 1;
+  const int s6 = row / nd, ib = row - s6 * nd;
+  const int site = bsite[size_t(j) * nd + ib];
+  blocks[(size_t(ja) * r + v) * N + row] = fine[(size_t(v) * 12 + 6 * a + s6) * V + site];
+}
+
+__global__ void k_export_P(const double2* __restrict__ P, double2* __restrict__ out, int nd, int N, int k, size_t n) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= n) return;
+  // out [ja][row_c][i], row_c = 6 ib + s6
+  const int i = int(g % k);
+  const size_t t = g / k;
+  const int rowc = int(t % N);
+  const size_t ja = t / N;
+  const int ib = rowc / 6, s6 = rowc - 6 * ib;
+  out[g] = P[(ja * k + i) * N + size_t(s6) * nd + ib];
+}
+
+__global__ void k_export_Y(const double2* __restrict__ Y, double2* __restrict__ out, int m, size_t n) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= n) return;
+  const int col = int(g % m);
+  const size_t t = g / m;
+  const int row = int(t % m);
+  const size_t blk = t / m;
+  out[g] = Y[(blk * m + col) * m + row];
+}
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = uint64_t(M0) * c[0], p1 = uint64_t(M1) * c[2];
+    const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0), hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__global__ void k_philox(double2* __restrict__ out, uint64_t seed, int v0, int V) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int vi = blockIdx.y;
+  if (site >= V) return;
+  const uint32_t k0 = uint32_t(seed & 0xffffffffu), k1 = uint32_t(seed >> 32);
+  const double twopi = 2.0 * M_PI;
+  for (int g = 0; g < 6; ++g) {
+    uint32_t c[4] = {uint32_t(site), uint32_t(g), uint32_t(v0 + vi), 0u};
+    philox4x32_10(c, k0, k1);
+    double u[4];
+    for (int q = 0; q < 4; ++q) u[q] = (double(c[q]) + 0.5) * 0x1p-32;
+    const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    const double t0 = twopi * u[1], t1 = twopi * u[3];
+    out[(size_t(vi) * 12 + 2 * g) * V + site] = make_double2(r0 * cos(t0), r0 * sin(t0));
+    out[(size_t(vi) * 12 + 2 * g + 1) * V + site] = make_double2(r1 * cos(t1), r1 * sin(t1));
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// link force, canonical FP64
+__constant__ double2 c_gamma[4][16];  // gamma_mu, row-major 4x4
+
+__global__ void k_link_force(const double2* __restrict__ x, const double2* __restrict__ lam, double2* __restrict__ dU,
+                             int L0, int L1, int L2, int L3, int bc_t, double cws, double cwt, int nrhs, int V) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int mu = blockIdx.y;
+  if (site >= V) return;
+  const int Ls[4] = {L0, L1, L2, L3};
+  int c[4];
+  {
+    int rem = site;
+    for (int q = 0; q < 4; ++q) { c[q] = rem % Ls[q]; rem /= Ls[q]; }
+  }
+  int cy[4] = {c[0], c[1], c[2], c[3]};
+  cy[mu] = (c[mu] + 1) % Ls[mu];
+  const int y = cy[0] + L0 * (cy[1] + L1 * (cy[2] + L2 * cy[3]));
+  cplx<double> G[9];
+  for (int e = 0; e < 9; ++e) G[e] = {0, 0};
+  for (int r = 0; r < nrhs; ++r) {
+    const double2* xx = x + (size_t(r) * V + site) * 12;
+    const double2* xy = x + (size_t(r) * V + y) * 12;
+    const double2* lx = lam + (size_t(r) * V + site) * 12;
+    const double2* ly = lam + (size_t(r) * V + y) * 12;
+    for (int s = 0; s < 4; ++s)
+      for (int t = 0; t < 4; ++t) {
+        const double2 gm = c_gamma[mu][s * 4 + t];
+        const cplx<double> pm = {(s == t ? 1.0 : 0.0) - gm.x, -gm.y};  // (1 - gamma)_{st}
+        const cplx<double> pp = {(s == t ? 1.0 : 0.0) + gm.x, gm.y};   // (1 + gamma)_{st}
+        if (pm.re == 0 && pm.im == 0 && pp.re == 0 && pp.im == 0) continue;
+        for (int aa = 0; aa < 3; ++aa)
+          for (int bb = 0; bb < 3; ++bb) {
+            const double2 x1 = xy[3 * t + aa], l1 = lx[3 * s + bb];
+            const double2 l2 = ly[3 * t + aa], x2 = xx[3 * s + bb];
+            G[3 * aa + bb] += pm * cmul_conj(cplx<double>{l1.x, l1.y}, cplx<double>{x1.x, x1.y});
+            G[3 * aa + bb] += pp * cmul_conj(cplx<double>{x2.x, x2.y}, cplx<double>{l2.x, l2.y});
+          }
+      }
+  }
+  double sg = 1.0;
+  if (mu == 3 && bc_t < 0 && c[3] == L3 - 1) sg = -1.0;
+  const double f = 0.5 * (mu == 3 ? cwt : cws) * sg;
+  for (int aa = 0; aa < 3; ++aa)
+    for (int bb = 0; bb < 3; ++bb) {
+      const cplx<double> gba = G[3 * bb + aa];  // (G^dag)_{ab} = conj(G_{ba})
+      dU[(size_t(mu) * V + site) * 9 + 3 * aa + bb] = make_double2(f * gba.re, -f * gba.im);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// layout conversion
+template <class Sc, class Sn>
+__global__ void k_pack_spinor(const Sc* __restrict__ in, Sn* __restrict__ out, int V, size_t n) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;  // canonical index
+  if (g >= n) return;
+  const int comp = int(g % 12);
+  const size_t t = g / 12;
+  const int site = int(t % V);
+  const size_t rhs = t / V;
+  stc(out, (rhs * 12 + comp) * V + site, ldc(in, g));
+}
+template <class Sn, class Sc>
+__global__ void k_unpack_spinor(const Sn* __restrict__ in, Sc* __restrict__ out, int V, size_t n) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= n) return;
+  const int comp = int(g % 12);
+  const size_t t = g / 12;
+  const int site = int(t % V);
+  const size_t rhs = t / V;
+  stc(out, g, ldc(in, (rhs * 12 + comp) * V + site));
+}
+template <class S>
+__global__ void k_pack_gauge(const double2* __restrict__ in, S* __restrict__ out, int V, size_t n) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= n) return;
+  const int e = int(g % 9);
+  const size_t t = g / 9;
+  const int site = int(t % V);
+  const size_t mu = t / V;
+  const double2 v = in[g];
+  stc(out, (mu * 9 + e) * V + site, cplx<double>{v.x, v.y});
+}
+template <class Si, class So>
+__global__ void k_convert(const Si* __restrict__ in, So* __restrict__ out, size_t n) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= n) return;
+  auto v = ldc(in, g);
+  stc(out, g, v);
+}
+
+template <class F>
+void dispatch_prec(qmg_prec p, F&& f) {
+  switch (p) {
+    case QMG_F64: f(double2{}); break;
+    case QMG_F32: f(float2{}); break;
+    case QMG_BF16: f(cbf16{}); break;
+    case QMG_F16: f(chalf{}); break;
+  }
+}
+
+}  // namespace
+
+void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const void* coarse, void* fine, int nrhs,
+                    hipStream_t st) {
+  dispatch_prec(prec, [&](auto tag) {
+    using S = decltype(tag);
+    dim3 grid(cdiv(h.blk.N, 256), 2 * h.blk.d, nrhs);
+    k_prolong<S><<<grid, 256, 0, st>>>((const S*)P, (const S*)coarse, (S*)fine, h.bsite.as<int>(), h.blk.nd,
+                                       h.blk.N, h.k, h.blk.d, h.g.V);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const void* fine, void* coarse, int nrhs,
+                     hipStream_t st) {
+  dispatch_prec(prec, [&](auto tag) {
+    using S = decltype(tag);
+    const size_t lds = size_t(h.blk.N) * sizeof(cplx<ctype<S>>);
+    k_restrict<S><<<dim3(2 * h.blk.d, nrhs), 256, lds, st>>>((const S*)P, (const S*)fine, (S*)coarse,
+                                                              h.bsite.as<int>(), h.blk.nd, h.blk.N, h.k, h.blk.d,
+                                                              h.g.V);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, const void* in, void* out, int nrhs,
+                         hipStream_t st) {
+  const int m = 2 * h.k;
+  dispatch_prec(prec, [&](auto tag) {
+    using S = decltype(tag);
+    dim3 grid(cdiv(size_t(h.blk.d) * m, 256), nrhs);
+    k_coarse_apply<S><<<grid, 256, 0, st>>>((const S*)Y, (const S*)in, (S*)out, h.cnb.as<int>(), h.blk.d, m);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void build_coarse(HierarchyDev& h, hipStream_t st) {
+  QMG_CHECK(2 * h.k <= kMaxM && h.k <= 32, QMG_ESHAPE, "coarse build supports k <= 32");
+  BuildArgs a{};
+  for (int q = 0; q < 4; ++q) {
+    a.L[q] = h.g.L[q];
+    a.b[q] = h.blk.b[q];
+    a.cL[q] = h.blk.cL[q];
+    a.cw[q] = h.g.cw(q);
+  }
+  a.V = h.g.V;
+  a.nd = h.blk.nd;
+  a.N = h.blk.N;
+  a.k = h.k;
+  a.d = h.blk.d;
+  a.bc_t = h.g.bc_t;
+  a.diag = h.g.diag();
+  k_build_coarse<<<h.blk.d, 256, 0, st>>>(h.U64.as<double2>(), h.P64.as<double2>(), h.bsite.as<int>(),
+                                          h.Y64.as<double2>(), a);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_chiral_gather(const HierarchyDev& h, const void* fine, void* blocks, int r, hipStream_t st) {
+  dim3 grid(cdiv(h.blk.N, 256), r, 2 * h.blk.d);
+  k_chiral_gather<<<grid, 256, 0, st>>>((const double2*)fine, (double2*)blocks, h.bsite.as<int>(), h.blk.nd,
+                                        h.blk.N, r, h.g.V);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_export_P(const HierarchyDev& h, void* out, hipStream_t st) {
+  const size_t n = size_t(h.blk.d) * 2 * h.blk.N * h.k;
+  k_export_P<<<cdiv(n, 256), 256, 0, st>>>(h.P64.as<double2>(), (double2*)out, h.blk.nd, h.blk.N, h.k, n);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_export_Y(const HierarchyDev& h, void* out, hipStream_t st) {
+  const int m = 2 * h.k;
+  const size_t n = size_t(h.blk.d) * 9 * m * m;
+  k_export_Y<<<cdiv(n, 256), 256, 0, st>>>(h.Y64.as<double2>(), (double2*)out, m, n);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_philox_native(const Geom& g, uint64_t seed, int v0, int n, void* out, hipStream_t st) {
+  k_philox<<<dim3(cdiv(g.V, 256), n), 256, 0, st>>>((double2*)out, seed, v0, g.V);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_link_force(const Geom& g, const void* x, const void* lam, void* dU, int nrhs, hipStream_t st) {
+  static bool init = false;
+  if (!init) {
+    // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]
+    double2 gm[4][16] = {};
+    auto set = [&](int mu, int r, int c, double re, double im) { gm[mu][r * 4 + c] = make_double2(re, im); };
+    // -i sigma_1 = [[0,-i],[-i,0]] ; i sigma_1 = [[0,i],[i,0]]
+    set(0, 0, 3, 0, -1); set(0, 1, 2, 0, -1); set(0, 2, 1, 0, 1); set(0, 3, 0, 0, 1);
+    // -i sigma_2 = [[0,-1],[1,0]] ; i sigma_2 = [[0,1],[-1,0]]
+    set(1, 0, 3, -1, 0); set(1, 1, 2, 1, 0); set(1, 2, 1, 1, 0); set(1, 3, 0, -1, 0);
+    // -i sigma_3 = [[-i,0],[0,i]] ; i sigma_3 = [[i,0],[0,-i]]
+    set(2, 0, 2, 0, -1); set(2, 1, 3, 0, 1); set(2, 2, 0, 0, 1); set(2, 3, 1, 0, -1);
+    // gamma_t
+    set(3, 0, 2, 1, 0); set(3, 1, 3, 1, 0); set(3, 2, 0, 1, 0); set(3, 3, 1, 1, 0);
+    QMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gamma), gm, sizeof(gm)));
+    init = true;
+  }
+  k_link_force<<<dim3(cdiv(g.V, 256), 4), 256, 0, st>>>((const double2*)x, (const double2*)lam, (double2*)dU,
+                                                         g.L[0], g.L[1], g.L[2], g.L[3], g.bc_t, g.cw(0), g.cw(3),
+                                                         nrhs, g.V);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_pack_spinor(const void* canon, qmg_prec pc, void* native, qmg_prec pn, int V, int nrhs,
+                        hipStream_t st) {
+  const size_t n = size_t(nrhs) * V * 12;
+  dispatch_prec(pc, [&](auto tc) {
+    using Sc = decltype(tc);
+    dispatch_prec(pn, [&](auto tn) {
+      using Sn = decltype(tn);
+      k_pack_spinor<Sc, Sn><<<cdiv(n, 256), 256, 0, st>>>((const Sc*)canon, (Sn*)native, V, n);
+    });
+  });
+  QMG_LAUNCH_CHECK();
+}
+void launch_unpack_spinor(const void* native, qmg_prec pn, void* canon, qmg_prec pc, int V, int nrhs,
+                          hipStream_t st) {
+  const size_t n = size_t(nrhs) * V * 12;
+  dispatch_prec(pn, [&](auto tn) {
+    using Sn = decltype(tn);
+    dispatch_prec(pc, [&](auto tc) {
+      using Sc = decltype(tc);
+      k_unpack_spinor<Sn, Sc><<<cdiv(n, 256), 256, 0, st>>>((const Sn*)native, (Sc*)canon, V, n);
+    });
+  });
+  QMG_LAUNCH_CHECK();
+}
+void launch_pack_gauge(const void* canon, void* native, qmg_prec prec, int V, hipStream_t st) {
+  const size_t n = size_t(4) * V * 9;
+  dispatch_prec(prec, [&](auto tag) {
+    using S = decltype(tag);
+    k_pack_gauge<S><<<cdiv(n, 256), 256, 0, st>>>((const double2*)canon, (S*)native, V, n);
+  });
+  QMG_LAUNCH_CHECK();
+}
+void launch_convert(const void* in, qmg_prec pin, void* out, qmg_prec pout, size_t n, hipStream_t st) {
+  if (!n) return;
+  dispatch_prec(pin, [&](auto ti) {
+    using Si = decltype(ti);
+    dispatch_prec(pout, [&](auto to) {
+      using So = decltype(to);
+      k_convert<Si, So><<<cdiv(n, 256), 256, 0, st>>>((const Si*)in, (So*)out, n);
+    });
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+}  // namespace qmg

@@ -1,0 +1,88 @@
+"""GPU parity of the Wilson-Dirac stencil (qmg_wilson_apply / _adj) against the oracle."""
+import numpy as np
+import pytest
+
+import fields
+from oracle import wilson
+from tests._util import to_gpu, to_np, rel, banner
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # dims, xi, bc_t, mass, nrhs
+    ((4, 4, 4, 4), 1.0, -1, 0.05, 1),
+    ((6, 6, 4, 10), 3.5, -1, -0.3, 3),     # 1440 sites: several 256-site tiles + ragged tail
+    ((2, 4, 6, 8), 1.7, 1, 0.2, 4),        # periodic t, extent 2, 4 rhs per thread
+    ((5, 3, 2, 7), 2.0, -1, 0.0, 2),       # odd extents
+    ((1, 1, 1, 4), 1.0, -1, 0.1, 1),       # degenerate extents (self-neighbours)
+]
+
+
+@pytest.mark.parametrize("dims,xi,bc,m,nrhs", CASES)
+@pytest.mark.parametrize("dag", [False, True])
+def test_dslash_f64_canonical(qmg, dims, xi, bc, m, nrhs, dag):
+    banner(f"dslash f64 canonical {dims} nrhs={nrhs} dag={dag}")
+    U = fields.random_gauge(dims, 0.6, 1)
+    psi = fields.gaussian_spinor(dims, nrhs, 2)
+    lat = qmg.Lattice(dims, m, xi, bc)
+    f = qmg.wilson_apply_adj if dag else qmg.wilson_apply
+    got = to_np(f(lat, to_gpu(U), to_gpu(psi)))
+    ref = wilson.apply_wilson(U, psi, m, xi, bc, dims, dagger=dag)
+    assert rel(got, ref) < 1e-14
+
+
+@pytest.mark.parametrize("dims,xi,bc,m,nrhs", CASES)
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 1e-6)])
+def test_dslash_native(qmg, dims, xi, bc, m, nrhs, prec, tol):
+    banner(f"dslash native {prec} {dims} nrhs={nrhs}")
+    U = fields.random_gauge(dims, 0.6, 3)
+    psi = fields.gaussian_spinor(dims, nrhs, 4)
+    lat = qmg.Lattice(dims, m, xi, bc)
+    Un = qmg.pack_gauge(lat, to_gpu(U), prec)
+    pn = qmg.pack_spinor(lat, to_gpu(psi), prec)
+    for dag in (False, True):
+        f = qmg.wilson_apply_adj if dag else qmg.wilson_apply
+        got = to_np(qmg.unpack_spinor(lat, f(lat, Un, pn, layout="native"), prec))
+        ref = wilson.apply_wilson(U, psi, m, xi, bc, dims, dagger=dag)
+        assert rel(got, ref) < tol
+
+
+def test_dslash_f32_canonical_and_bf16(qmg):
+    dims = (6, 6, 4, 10)
+    banner(f"dslash f32 canonical + bf16/f16 native {dims}")
+    U = fields.random_gauge(dims, 0.6, 5)
+    psi = fields.gaussian_spinor(dims, 2, 6)
+    lat = qmg.Lattice(dims, 0.05, 3.5, -1)
+    ref = wilson.apply_wilson(U, psi, 0.05, 3.5, -1, dims)
+    got = to_np(qmg.wilson_apply(lat, to_gpu(U.astype(np.complex64)), to_gpu(psi.astype(np.complex64))))
+    assert rel(got, ref) < 1e-6
+    for prec, tol in (("bf16", 1e-2), ("f16", 2e-3)):
+        Un = qmg.pack_gauge(lat, to_gpu(U), prec)
+        pn = qmg.pack_spinor(lat, to_gpu(psi), prec)
+        got = to_np(qmg.unpack_spinor(lat, qmg.wilson_apply(lat, Un, pn, layout="native"), prec))
+        err = rel(got, ref)
+        print(f"[precision] dslash {prec} storage, fp32 accumulate: rel err {err:.3e}")
+        assert err < tol
+
+
+@pytest.mark.parametrize("dims,nrhs", [((16, 16, 16, 32), 1), ((24, 24, 24, 64), 1), ((32, 32, 32, 64), 12)])
+def test_dslash_full_size_sampled(qmg, dims, nrhs):
+    """Full-size lattices in the benchmark's native FP32 launch: sampled sites vs the oracle."""
+    banner(f"dslash full size {dims} nrhs={nrhs}")
+    xi = 3.5 if dims[0] == 16 else 1.0
+    U = fields.random_gauge(dims, 0.6, 7)
+    lat = qmg.Lattice(dims, -0.2, xi, -1)
+    V = lat.volume
+    rng = np.random.default_rng(0)
+    sites = np.unique(np.concatenate([rng.integers(0, V, 48), [0, V - 1, dims[0] - 1, V - dims[0] * dims[1]]]))
+    Un = qmg.pack_gauge(lat, to_gpu(U), "f32")
+    del U
+    psi = fields.gaussian_spinor(dims, nrhs, 8)
+    pn = qmg.pack_spinor(lat, to_gpu(psi), "f32")
+    out = qmg.unpack_spinor(lat, qmg.wilson_apply(lat, Un, pn, layout="native"), "f32")
+    got = to_np(out[:, sites])
+    del out, pn, Un
+    U = fields.random_gauge(dims, 0.6, 7)
+    for r in (0, nrhs - 1):
+        ref = wilson.apply_wilson_sites(U, psi[r], sites, -0.2, xi, -1, dims)
+        assert rel(got[r], ref) < 1e-6
