@@ -183,6 +183,15 @@ qmg_status qmg_mg_get_coarse(const qmg_mg* mg, void* Y, hipStream_t stream);
 /* Setup timings in seconds: smoother, streaming SVD, coarse build, total (host array [4]). */
 qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);
 
+/* Measurement hooks.  qmg_timing_enable(1) clears the record and brackets every later launch
+ * of the instrumented kernel families ("dslash", "isvd", "coarse_apply", "prolong",
+ * "restrict", "coarse_build") with HIP events on its stream; 0 stops recording.
+ * qmg_timing_query returns, for one family, the launches recorded, their summed duration
+ * (ms, it synchronizes on the events) and the summed algorithmic bytes and flops. */
+qmg_status qmg_timing_enable(int32_t on);
+qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total_ms, double* algo_bytes,
+                            double* algo_flops);
+
 void qmg_mg_destroy(qmg_mg* mg);
 const char* qmg_last_error(void);
 const char* qmg_version(void);

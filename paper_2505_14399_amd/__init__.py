@@ -74,6 +74,8 @@ SIGNATURES = {
     "qmg_mg_get_prolongator": [_P, _P, _P, _P],
     "qmg_mg_get_coarse": [_P, _P, _P],
     "qmg_mg_setup_times": [_P, _P],
+    "qmg_timing_enable": [_I],
+    "qmg_timing_query": [ctypes.c_char_p, _P, _P, _P, _P],
     "qmg_mg_destroy": [_P],
     "qmg_last_error": [],
     "qmg_version": [],
@@ -369,6 +371,20 @@ def smooth(lat: Lattice, U, phi, n_iter, prec="f64"):
     _check(load_library().qmg_smooth(ctypes.byref(s), _ptr(U), _ptr(phi), _ptr(out), phi.shape[0], int(n_iter),
                                      _PREC[prec], _stream()))
     return out
+
+
+def timing_enable(on=True):
+    """Start (clearing the record) or stop per-launch HIP-event timing of the kernel families."""
+    _check(load_library().qmg_timing_enable(1 if on else 0))
+
+
+def timing_query(family):
+    """{'launches', 'ms', 'bytes', 'flops'} summed over the recorded launches of `family`."""
+    n = ctypes.c_int64()
+    ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().qmg_timing_query(family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                           ctypes.byref(fl)))
+    return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
 
 
 def version():

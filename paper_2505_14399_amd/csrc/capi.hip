@@ -7,6 +7,7 @@
 #include <new>
 
 #include "mg.hpp"
+#include "timing.hpp"
 
 struct qmg_mg {
   qmg::HierarchyDev h;
@@ -159,6 +160,23 @@ void build_tables(HierarchyDev& h) {
       cnb[size_t(j) * 8 + dir] = cc[0] + b.cL[0] * (cc[1] + b.cL[1] * (cc[2] + b.cL[2] * cc[3]));
     }
   }
+  // for each hop direction, the in-block indices whose hop stays inside the block, then those
+  // whose hop crosses the block face (x_mu mod b_mu = b_mu - 1 forward, = 0 backward)
+  std::vector<int> lists(size_t(8) * b.nd);
+  const int stride[4] = {1, b.b[0], b.b[0] * b.b[1], b.b[0] * b.b[1] * b.b[2]};
+  for (int dir = 0; dir < 8; ++dir) {
+    const int mu = dir & 3;
+    const bool fwd = dir < 4;
+    int n = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int ib = 0; ib < b.nd; ++ib) {
+        const int c = (ib / stride[mu]) % b.b[mu];
+        const bool face = fwd ? (c == b.b[mu] - 1) : (c == 0);
+        if (face == (pass == 1)) lists[size_t(dir) * b.nd + n++] = ib;
+      }
+  }
+  h.blists.alloc(lists.size() * sizeof(int));
+  QMG_HIP(hipMemcpy(h.blists.p, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice));
   h.bsite.alloc(bsite.size() * sizeof(int));
   h.cnb.alloc(cnb.size() * sizeof(int));
   QMG_HIP(hipMemcpy(h.bsite.p, bsite.data(), bsite.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -708,6 +726,23 @@ qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t) {
     t[1] = mg->h.t_svd;
     t[2] = mg->h.t_coarse;
     t[3] = mg->h.t_total;
+  });
+}
+
+qmg_status qmg_timing_enable(int32_t on) {
+  return guard([&] { timing_enable(on != 0); });
+}
+
+qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total_ms, double* algo_bytes,
+                            double* algo_flops) {
+  return guard([&] {
+    check_ptr(family, "family");
+    check_ptr(launches, "launches");
+    check_ptr(total_ms, "total_ms");
+    double b = 0, f = 0;
+    timing_query(family, launches, total_ms, &b, &f);
+    if (algo_bytes) *algo_bytes = b;
+    if (algo_flops) *algo_flops = f;
   });
 }
 

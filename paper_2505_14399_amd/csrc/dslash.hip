@@ -12,7 +12,7 @@
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; the tile index is
 // remapped so that each XCD walks a contiguous range of sites, keeping the +-t neighbour
 // slices of a tile inside that XCD's L2.
-#include "qmg_internal.hpp"
+#include "timing.hpp"
 
 namespace qmg {
 
@@ -140,10 +140,14 @@ template <class S, bool CANON, int NR, bool DAG>
 __global__ __launch_bounds__(kBlock) void k_dslash(const S* __restrict__ U, const S* __restrict__ in,
                                                    S* __restrict__ out, DslashArgs a) {
   using C = ctype<S>;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  // flattened grid over (tile, rhs group) with the rhs groups of a tile adjacent in the
+  // XCD-local order, so that they share the tile's links in L2
+  const int ng = a.nrhs / NR;
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = wg / ng;
   const int site = tile * kBlock + threadIdx.x;
   if (site >= a.V) return;
-  const int rhs0 = blockIdx.y * NR;
+  const int rhs0 = (wg - tile * ng) * NR;
   const int V = a.V;
   const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
   int rem = site;
@@ -199,13 +203,124 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const S* __restrict__ U, cons
   }
 }
 
+
+// Native-layout kernel that walks along t.  Thread (spatial site, t-chunk) computes the TCH
+// sites t0 .. t0+TCH-1 of its column.  The spinor of the next slice, loaded for the forward
+// t-hop, becomes the own spinor of the next step, and the backward t-hop
+// U_t(x, t-1)^dag (1 + gamma_t) psi(x, t-1) is formed from the own spinor and forward t-link
+// of the previous step, so t-neighbours and t-links are read once.  Workgroups are 256
+// consecutive spatial sites of one (t-chunk, right-hand side); the right-hand sides of a tile
+// are adjacent in the XCD-local schedule so that they share its links in L2.
+template <class S, int TCH, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, const S* __restrict__ in,
+                                                     S* __restrict__ out, DslashArgs a, int ntile_s) {
+  using C = ctype<S>;
+  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
+  const int Vs = L0 * L1 * L2, V = a.V;
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  const int rhs = wg % a.nrhs;
+  const int tile = wg / a.nrhs;                 // (t-chunk, spatial tile)
+  const int chunk = tile / ntile_s, ts = tile - chunk * ntile_s;
+  const int xs = ts * kBlock + threadIdx.x;     // spatial site
+  if (xs >= Vs) return;
+  const int t0 = chunk * TCH;
+  int rem = xs;
+  const int x = rem % L0; rem /= L0;
+  const int y = rem % L1;
+  const int z = rem / L1;
+  const int s1 = L0, s2 = L0 * L1;
+  const int dxp = (x + 1 == L0) ? -(L0 - 1) : 1, dxm = (x == 0) ? (L0 - 1) : -1;
+  const int dyp = (y + 1 == L1) ? -(L1 - 1) * s1 : s1, dym = (y == 0) ? (L1 - 1) * s1 : -s1;
+  const int dzp = (z + 1 == L2) ? -(L2 - 1) * s2 : s2, dzm = (z == 0) ? (L2 - 1) * s2 : -s2;
+  C cw[4], diag;
+  if constexpr (sizeof(C) == 8) {
+    for (int m = 0; m < 4; ++m) cw[m] = a.cw_d[m];
+    diag = a.diag_d;
+  } else {
+    for (int m = 0; m < 4; ++m) cw[m] = a.cw_f[m];
+    diag = a.diag_f;
+  }
+  const C mh = C(-0.5);
+  const C sf = DAG ? C(1) : C(-1);  // forward projector sign: (1 + sf gamma)
+  const C sb = -sf;                  // backward projector sign
+  const S* inr = in + size_t(rhs) * 12 * V;
+  S* outr = out + size_t(rhs) * 12 * V;
+
+  // own spinor of the first site and the backward t-hop carried into it
+  cplx<C> psi[12], hb[6];
+  {
+    const int tm = (t0 == 0) ? L3 - 1 : t0 - 1;
+    const int sm = xs + tm * Vs;
+    cplx<C> chi[12], h[6], u[9];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) chi[k] = ldc(inr, size_t(k) * V + sm);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = ldc(U, size_t(3 * 9 + e) * V + sm);
+    project<3>(chi, sb, h);
+    su3_mul<C, true>(u, h, hb);
+    const int s0 = xs + t0 * Vs;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = ldc(inr, size_t(k) * V + s0);
+  }
+#pragma unroll 1
+  for (int dt = 0; dt < TCH; ++dt) {
+    const int t = t0 + dt;
+    const int site = xs + t * Vs;
+    const int tp = (t + 1 == L3) ? 0 : t + 1;
+    const int sp = xs + tp * Vs;
+    cplx<C> acc[1][12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[0][k] = {C(0), C(0)};
+    do_hop<S, false, 1, 0, true, DAG>(U, inr, acc, site, site + dxp, 0, V, mh * cw[0]);
+    do_hop<S, false, 1, 0, false, DAG>(U, inr, acc, site + dxm, site + dxm, 0, V, mh * cw[0]);
+    do_hop<S, false, 1, 1, true, DAG>(U, inr, acc, site, site + dyp, 0, V, mh * cw[1]);
+    do_hop<S, false, 1, 1, false, DAG>(U, inr, acc, site + dym, site + dym, 0, V, mh * cw[1]);
+    do_hop<S, false, 1, 2, true, DAG>(U, inr, acc, site, site + dzp, 0, V, mh * cw[2]);
+    do_hop<S, false, 1, 2, false, DAG>(U, inr, acc, site + dzm, site + dzm, 0, V, mh * cw[2]);
+    // backward t-hop (carried), boundary sign at t = 0
+    const C bt_b = (a.bc_t < 0 && t == 0) ? C(-1) : C(1);
+    reconstruct<3>(acc[0], hb, sb, mh * cw[3] * bt_b);
+    // forward t-hop: load the next spinor and this site's t-link
+    cplx<C> nxt[12], u[9], h[6], w[6];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) nxt[k] = ldc(inr, size_t(k) * V + sp);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = ldc(U, size_t(3 * 9 + e) * V + site);
+    const C bt_f = (a.bc_t < 0 && t == L3 - 1) ? C(-1) : C(1);
+    project<3>(nxt, sf, h);
+    su3_mul<C, false>(u, h, w);
+    reconstruct<3>(acc[0], w, sf, mh * cw[3] * bt_f);
+    // backward t-hop of the next site from this site's spinor and t-link
+    project<3>(psi, sb, h);
+    su3_mul<C, true>(u, h, hb);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      stc(outr, size_t(k) * V + site, diag * psi[k] + acc[0][k]);
+      psi[k] = nxt[k];
+    }
+  }
+}
+
 template <class S, bool CANON, int NR>
 void launch_t(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
-  dim3 grid((a.V + kBlock - 1) / kBlock, a.nrhs / NR);
+  dim3 grid(unsigned((a.V + kBlock - 1) / kBlock) * unsigned(a.nrhs / NR));
   if (a.dagger)
     k_dslash<S, CANON, NR, true><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a);
   else
     k_dslash<S, CANON, NR, false><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a);
+  QMG_LAUNCH_CHECK();
+}
+
+template <class S, int TCH>
+void launch_tw(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
+  const int Vs = a.L[0] * a.L[1] * a.L[2];
+  const int ntile_s = (Vs + kBlock - 1) / kBlock;
+  const int nchunk = a.L[3] / TCH;
+  dim3 grid(unsigned(ntile_s * nchunk * a.nrhs));
+  if (a.dagger)
+    k_dslash_t<S, TCH, true><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a, ntile_s);
+  else
+    k_dslash_t<S, TCH, false><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a, ntile_s);
   QMG_LAUNCH_CHECK();
 }
 
@@ -215,15 +330,33 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     launch_t<S, true, 1>(U, in, out, a, st);
     return;
   }
-  if (a.nrhs % 4 == 0) launch_t<S, false, 4>(U, in, out, a, st);
-  else if (a.nrhs % 2 == 0) launch_t<S, false, 2>(U, in, out, a, st);
-  else launch_t<S, false, 1>(U, in, out, a, st);
+  // t-walking kernel: chunk length chosen so that the grid still has >= 4 workgroups per CU
+  const int Vs = a.L[0] * a.L[1] * a.L[2];
+  const long wg1 = long((Vs + kBlock - 1) / kBlock) * a.nrhs;  // workgroups per t-slice
+  const int Lt = a.L[3];
+  auto fits = [&](int tch) { return Lt % tch == 0 && wg1 * (Lt / tch) >= 1024; };
+  if (a.tchunk > 0 && Lt % a.tchunk == 0) {
+    switch (a.tchunk) {
+      case 1: launch_t<S, false, 1>(U, in, out, a, st); return;
+      case 2: launch_tw<S, 2>(U, in, out, a, st); return;
+      case 4: launch_tw<S, 4>(U, in, out, a, st); return;
+      case 8: launch_tw<S, 8>(U, in, out, a, st); return;
+      default: break;
+    }
+  }
+  if (fits(8)) launch_tw<S, 8>(U, in, out, a, st);
+  else if (fits(4)) launch_tw<S, 4>(U, in, out, a, st);
+  else if (fits(2)) launch_tw<S, 2>(U, in, out, a, st);
+  else launch_t<S, false, 1>(U, in, out, a, st);  // small lattices: one site per thread
 }
 
 }  // namespace
 
 void launch_dslash(qmg_prec prec, const void* U, const void* in, void* out, const DslashArgs& a,
                    hipStream_t st) {
+  // algorithmic traffic: spinor in + out (2 x 12 complex per site and rhs) + 4 links per site
+  const double cb = double(prec_bytes(prec));
+  TimedLaunch tl("dslash", st, double(a.V) * (24.0 * a.nrhs + 36.0) * cb, 1368.0 * a.V * a.nrhs);
   switch (prec) {
     case QMG_F64: launch_s<double2>(U, in, out, a, st); break;
     case QMG_F32: launch_s<float2>(U, in, out, a, st); break;

@@ -3,30 +3,37 @@
 //
 // For each problem the state is Phi_{s-1} = U Sigma (U: N x kp orthonormal) and the new block
 // Psi (N x r).  The rank-k SVD of [U Sigma, Psi] is obtained without forming it:
-//   X  = U^dag Psi,  R = Psi - U X,  X2 = U^dag R,  G = R^dag R        (row passes 1 and 2;
-//        projection done twice, classical Gram-Schmidt)
+//   X  = U^dag Psi,  R = Psi - U X,  X2 = U^dag R,  G = R^dag R        (Gram kernel: two row
+//        passes, the projection done twice, i.e. classical Gram-Schmidt with one re-projection)
 //   G2 = G - X2^dag X2 = T^dag T        (Cholesky; a column whose remaining norm falls below
 //        1e-12 of its original norm is dropped: its row of T is zero)
 //   [U Sigma, Psi] = [U, Q] K,  K = [[Sigma, X + X2], [0, T]],  Q = (Psi - U (X + X2)) T^-1
 //   K = Y S Z^dag by one-sided Jacobi on the columns of K^dag with the rotations accumulated,
-//        so Y (the left singular vectors of K) is unitary even where S is zero
-//   U_new = [U, Q] Y_k = U A + Psi B,   B = T^-1 Y_bot,   A = Y_top - (X + X2) B   (pass 3)
+//        so Y (the left singular vectors of K) is unitary even where S is zero   (small kernel,
+//        one wavefront per problem)
+//   U_new = [U, Q] Y_k = U A + Psi B,   B = T^-1 Y_bot,   A = Y_top - (X + X2) B  (rotation
+//        kernel, in place, row-local)
 // Singular values are sorted descending with ties broken by the lower index.
 //
-// Launch: persistent grid, one 256-thread workgroup per problem at a time; rows are streamed
-// through LDS in chunks, the small dense matrices (at most (k+r)^2) live in LDS.
+// The row passes stream N rows through LDS in chunks of CH rows; the next chunk is prefetched
+// into registers while the current one is used.  Each thread owns a 2 x 2 tile of the small
+// output and a subset of the rows (split-K), the partial tiles are summed once per pass.
 #include <cmath>
 
 #include "mg.hpp"
+#include "timing.hpp"
 
 namespace qmg {
 
 namespace {
 
 using cd = cplx<double>;
-constexpr int T = 256;
-constexpr int CH = 32;       // rows per chunk
-constexpr int CHP = CH + 1;  // padded LDS stride
+constexpr int T = 256;                 // threads of the row-pass kernels
+constexpr int CH = 64;                 // rows per chunk
+constexpr int CHP = CH + 1;            // padded LDS column stride
+constexpr int MAXW = 64;               // k + r <= MAXW
+constexpr int PF = (MAXW * CH) / T;    // prefetch registers per thread (complex), upper bound
+constexpr double kJacobiTol = 1e-14;   // |<m_p, m_q>| <= tol |m_p| |m_q| counts as orthogonal
 
 struct IsvdArgs {
   int nprob, N, k, r, kp, w, kn;
@@ -38,152 +45,176 @@ __device__ inline cd ld2(const double2* p, size_t i) {
 }
 __device__ inline void st2(double2* p, size_t i, cd v) { p[i] = make_double2(v.re, v.im); }
 
+// scratch per problem: X [kp][r], X2 [kp][r], G [r][r], pn [r]   (complex)
+__host__ __device__ inline size_t small_stride(int kp, int r) { return size_t(2) * kp * r + size_t(r) * r + r; }
+
+// Load chunk rows [r0, r0+CH) of the w columns (U then Psi) into registers (NPF per thread).
+template <int NPF>
+__device__ inline void prefetch(cd* reg, const double2* U, const double2* Psi, int kp, int w, int N, int r0,
+                                int tid) {
+#pragma unroll
+  for (int q = 0; q < NPF; ++q) {
+    const int t = tid + q * T;
+    const int col = t / CH, row = t - col * CH;
+    const int gr = r0 + row;
+    cd v = {0, 0};
+    if (col < w && gr < N) v = col < kp ? ld2(U, size_t(col) * N + gr) : ld2(Psi, size_t(col - kp) * N + gr);
+    reg[q] = v;
+  }
+}
+template <int NPF>
+__device__ inline void stage(cd* chunk, const cd* reg, int w, int tid) {
+#pragma unroll
+  for (int q = 0; q < NPF; ++q) {
+    const int t = tid + q * T;
+    const int col = t / CH, row = t - col * CH;
+    if (col < w) chunk[col * CHP + row] = reg[q];
+  }
+}
+
+// Gram kernel: rows of the result are the w columns [U, Psi or R], columns the r columns of
+// Psi (pass 1) or R (pass 2).  2x2 tiles over (a, b), row groups over the chunk rows.
+template <int NPF>
+__global__ __launch_bounds__(T) void k_isvd_gram(const double2* __restrict__ Ug, const double2* __restrict__ Psig,
+                                                 double2* __restrict__ small, IsvdArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = a.N, kp = a.kp, r = a.r, w = a.w, k = a.k;
+  const int tid = threadIdx.x;
+  cd* chunk = reinterpret_cast<cd*>(smem_raw);   // [w][CHP]
+  cd* Xs = chunk + size_t(w) * CHP;              // [kp][r]  X of pass 1
+  cd* red = Xs + size_t(kp) * r;                 // reduction buffer [nrg][w][r]
+  const int ta = (w + 1) / 2, tb = (r + 1) / 2, ntile = ta * tb;
+  const int nrg = max(1, T / ntile);
+  const int tile = tid % ntile, rg = tid / ntile;
+  const bool active = rg < nrg && tid < ntile * nrg;
+  const int a0 = 2 * (tile / tb), b0 = 2 * (tile % tb);
+  const size_t sstride = small_stride(kp, r);
+
+  for (int p = blockIdx.x; p < a.nprob; p += gridDim.x) {
+    const double2* U = Ug + size_t(p) * k * N;
+    const double2* Psi = Psig + size_t(p) * r * N;
+    double2* sm = small + size_t(p) * sstride;
+    for (int pass = 0; pass < 2; ++pass) {
+      cd acc[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+      cd reg[NPF];
+      prefetch<NPF>(reg, U, Psi, kp, w, N, 0, tid);
+      for (int r0 = 0; r0 < N; r0 += CH) {
+        stage<NPF>(chunk, reg, w, tid);
+        __syncthreads();
+        if (r0 + CH < N) prefetch<NPF>(reg, U, Psi, kp, w, N, r0 + CH, tid);
+        if (pass == 1 && kp > 0) {
+          // residual R = Psi - U X in place over the Psi columns of the chunk
+          for (int t = tid; t < r * CH; t += T) {
+            const int b = t / CH, row = t - b * CH;
+            cd v = chunk[(kp + b) * CHP + row];
+#pragma unroll 4
+            for (int aa = 0; aa < kp; ++aa) v -= chunk[aa * CHP + row] * Xs[aa * r + b];
+            chunk[(kp + b) * CHP + row] = v;
+          }
+          __syncthreads();
+        }
+        if (active) {
+          const int a1 = min(a0 + 1, w - 1), b1 = min(b0 + 1, r - 1);
+          const cd* A0 = chunk + a0 * CHP;
+          const cd* A1 = chunk + a1 * CHP;
+          const cd* B0 = chunk + (kp + b0) * CHP;
+          const cd* B1 = chunk + (kp + b1) * CHP;
+#pragma unroll 4
+          for (int row = rg; row < CH; row += nrg) {
+            const cd x0 = A0[row], x1 = A1[row], y0 = B0[row], y1 = B1[row];
+            acc[0][0] += cmul_conj(x0, y0);
+            acc[0][1] += cmul_conj(x0, y1);
+            acc[1][0] += cmul_conj(x1, y0);
+            acc[1][1] += cmul_conj(x1, y1);
+          }
+        }
+        __syncthreads();
+      }
+      // sum the partial tiles over the row groups
+      if (active) {
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) {
+            const int aa = a0 + i, bb = b0 + j;
+            if (aa < w && bb < r) red[(size_t(rg) * w + aa) * r + bb] = acc[i][j];
+          }
+      }
+      __syncthreads();
+      for (int e = tid; e < w * r; e += T) {
+        cd s = {0, 0};
+        for (int g = 0; g < nrg; ++g) s += red[size_t(g) * w * r + e];
+        const int aa = e / r, bb = e - aa * r;
+        if (pass == 0) {
+          if (aa < kp) {
+            Xs[e] = s;
+            st2(sm, e, s);                                          // X
+          } else if (aa - kp == bb) {
+            st2(sm, size_t(2) * kp * r + size_t(r) * r + bb, s);    // pn = |Psi_b|^2
+          }
+        } else {
+          if (aa < kp) st2(sm, size_t(kp) * r + e, s);              // X2
+          else st2(sm, size_t(2) * kp * r + size_t(aa - kp) * r + bb, s);  // G
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// small dense part: one wavefront per problem
+constexpr int TW = 64;
+
 __device__ inline int rr_pos(int i, int t, int w) {  // round-robin tournament position
   return i == 0 ? 0 : 1 + (i - 1 + t) % (w - 1);
 }
 
-__global__ __launch_bounds__(T) void k_isvd(double2* __restrict__ Ug, double* __restrict__ sig,
-                                            const double2* __restrict__ Psig, IsvdArgs a) {
+__global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ small, double* __restrict__ sig,
+                                                   double2* __restrict__ AB, IsvdArgs a) {
   extern __shared__ unsigned char smem_raw[];
-  const int N = a.N, kp = a.kp, r = a.r, w = a.w, kn = a.kn, k = a.k;
-  const int tid = threadIdx.x;
-  // LDS regions
-  cd* chunk = reinterpret_cast<cd*>(smem_raw);      // [w][CHP]: U columns then Psi columns
-  cd* X = chunk + size_t(w) * CHP;                  // [kp][r]
-  cd* X2 = X + size_t(kp) * r;                      // [kp][r]
-  cd* G = X2 + size_t(kp) * r;                      // [r][r]
-  cd* Tm = G + size_t(r) * r;                       // [r][r] upper triangular, row-major
-  cd* Ti = Tm + size_t(r) * r;                      // [r][r]
-  const int we = w + (w & 1);                       // even size for the tournament
-  cd* M = Ti + size_t(r) * r;                       // [we][we] column-major: column p at M + p*we
-  cd* J = M + size_t(we) * we;                      // [we][we]
+  const int kp = a.kp, r = a.r, w = a.w, kn = a.kn, k = a.k;
+  const int we = w + (w & 1);
+  const int lane = threadIdx.x;
+  cd* X = reinterpret_cast<cd*>(smem_raw);  // [kp][r]  (X + X2 after the first step)
+  cd* X2 = X + size_t(kp) * r;              // [kp][r]
+  cd* G = X2 + size_t(kp) * r;              // [r][r]
+  cd* Tm = G + size_t(r) * r;               // [r][r] upper, row-major
+  cd* Ti = Tm + size_t(r) * r;              // [r][r]
+  cd* M = Ti + size_t(r) * r;               // [we][we] column-major
+  cd* J = M + size_t(we) * we;              // [we][we]
   double* s = reinterpret_cast<double*>(J + size_t(we) * we);  // [we]
-  double* pn = s + we;                              // [r]
-  double* offg = pn + r;                            // [32]
-  int* keep = reinterpret_cast<int*>(offg + 32);    // [r]
-  int* perm = keep + r;                             // [we]
-  __shared__ int s_flag;
-
-  const int nown1 = kp * r + r;       // pass-1 outputs: X entries then |Psi_b|^2
-  const int nown2 = kp * r + r * r;   // pass-2 outputs: X2 entries then G entries
-  constexpr int MAXO = 4;             // outputs per thread (kp*r + r*r <= 4 * 256)
+  double* pn = s + we;                      // [r]
+  int* keep = reinterpret_cast<int*>(pn + r);  // [r]
+  int* perm = keep + r;                     // [we]
+  const size_t sstride = small_stride(kp, r);
+  const int npairs = we / 2;
+  int lpp = 1;  // lanes per pair (power of two)
+  while (lpp * 2 * npairs <= TW) lpp *= 2;
+  const int grp = lane / lpp, gl = lane % lpp;
 
   for (int p = blockIdx.x; p < a.nprob; p += gridDim.x) {
-    double2* U = Ug + size_t(p) * k * N;
-    const double2* Psi = Psig + size_t(p) * r * N;
+    const double2* sm = small + size_t(p) * sstride;
     double* sg = sig + size_t(p) * k;
-
-    // ---------------- pass 1: X = U^dag Psi, pn = |Psi_b|^2
-    cd acc[MAXO];
-    for (int q = 0; q < MAXO; ++q) acc[q] = {0, 0};
-    for (int r0 = 0; r0 < N; r0 += CH) {
-      for (int t = tid; t < w * CH; t += T) {
-        const int col = t / CH, row = t - col * CH;
-        const int gr = r0 + row;
-        cd v = {0, 0};
-        if (gr < N) v = col < kp ? ld2(U, size_t(col) * N + gr) : ld2(Psi, size_t(col - kp) * N + gr);
-        chunk[col * CHP + row] = v;
-      }
-      __syncthreads();
-      for (int q = 0; q < MAXO; ++q) {
-        const int e = tid + q * T;
-        if (e >= nown1) break;
-        const cd* x;
-        const cd* y;
-        if (e < kp * r) {
-          x = chunk + (e / r) * CHP;
-          y = chunk + (kp + e % r) * CHP;
-        } else {
-          x = y = chunk + (kp + e - kp * r) * CHP;
-        }
-        cd sum = {0, 0};
-        for (int row = 0; row < CH; ++row) sum += cmul_conj(x[row], y[row]);
-        acc[q] += sum;
-      }
-      __syncthreads();
+    double2* ab = AB + size_t(p) * w * kn;
+    for (int e = lane; e < 2 * kp * r + r * r; e += TW) {
+      const double2 v = sm[e];
+      X[e] = {v.x, v.y};  // X, X2, G are contiguous in both layouts
     }
-    for (int q = 0; q < MAXO; ++q) {
-      const int e = tid + q * T;
-      if (e >= nown1) break;
-      if (e < kp * r) X[e] = acc[q];
-      else pn[e - kp * r] = acc[q].re;
-    }
+    for (int b = lane; b < r; b += TW) pn[b] = sm[size_t(2) * kp * r + size_t(r) * r + b].x;
     __syncthreads();
-
-    // ---------------- pass 2: R = Psi - U X ; X2 = U^dag R ; G = R^dag R
-    for (int q = 0; q < MAXO; ++q) acc[q] = {0, 0};
-    for (int r0 = 0; r0 < N; r0 += CH) {
-      for (int t = tid; t < w * CH; t += T) {
-        const int col = t / CH, row = t - col * CH;
-        const int gr = r0 + row;
-        cd v = {0, 0};
-        if (gr < N) v = col < kp ? ld2(U, size_t(col) * N + gr) : ld2(Psi, size_t(col - kp) * N + gr);
-        chunk[col * CHP + row] = v;
-      }
-      __syncthreads();
-      if (kp > 0) {
-        // residual in registers, then written over the Psi part of the chunk
-        cd res[(CH * 48 + T - 1) / T];
-        int nres = 0;
-        for (int t = tid; t < r * CH; t += T, ++nres) {
-          const int b = t / CH, row = t - b * CH;
-          cd v = chunk[(kp + b) * CHP + row];
-          for (int aa = 0; aa < kp; ++aa) v -= chunk[aa * CHP + row] * X[aa * r + b];
-          res[nres] = v;
-        }
-        __syncthreads();
-        nres = 0;
-        for (int t = tid; t < r * CH; t += T, ++nres) {
-          const int b = t / CH, row = t - b * CH;
-          chunk[(kp + b) * CHP + row] = res[nres];
-        }
-        __syncthreads();
-      }
-      for (int q = 0; q < MAXO; ++q) {
-        const int e = tid + q * T;
-        if (e >= nown2) break;
-        const cd* x;
-        const cd* y;
-        if (e < kp * r) {
-          x = chunk + (e / r) * CHP;
-          y = chunk + (kp + e % r) * CHP;
-        } else {
-          const int f = e - kp * r;
-          x = chunk + (kp + f / r) * CHP;
-          y = chunk + (kp + f % r) * CHP;
-        }
-        cd sum = {0, 0};
-        for (int row = 0; row < CH; ++row) sum += cmul_conj(x[row], y[row]);
-        acc[q] += sum;
-      }
-      __syncthreads();
-    }
-    for (int q = 0; q < MAXO; ++q) {
-      const int e = tid + q * T;
-      if (e >= nown2) break;
-      if (e < kp * r) X2[e] = acc[q];
-      else G[e - kp * r] = acc[q];
-    }
-    __syncthreads();
-
-    // ---------------- small dense part
-    // G2 = G - X2^dag X2 (in G), X += X2
-    for (int e = tid; e < r * r; e += T) {
+    // G2 = G - X2^dag X2 ; X <- X + X2
+    for (int e = lane; e < r * r; e += TW) {
       const int i = e / r, l = e - i * r;
       cd v = G[e];
       for (int aa = 0; aa < kp; ++aa) v -= cmul_conj(X2[aa * r + i], X2[aa * r + l]);
       G[e] = v;
-    }
-    __syncthreads();
-    for (int e = tid; e < kp * r; e += T) X[e] += X2[e];
-    for (int e = tid; e < r * r; e += T) {
       Tm[e] = {0, 0};
       Ti[e] = {0, 0};
     }
     __syncthreads();
-    // Cholesky with dropping: G2 = T^dag T, T upper, row-major Tm[i*r + l]
+    for (int e = lane; e < kp * r; e += TW) X[e] += X2[e];
+    // Cholesky with dropping: G2 = T^dag T
     for (int jj = 0; jj < r; ++jj) {
-      if (tid == 0) {
+      if (lane == 0) {
         double dj = G[jj * r + jj].re;
         for (int i = 0; i < jj; ++i) dj -= norm2(Tm[i * r + jj]);
         const bool ok = dj > 1e-24 * pn[jj] && dj > 0.0;
@@ -192,172 +223,204 @@ __global__ __launch_bounds__(T) void k_isvd(double2* __restrict__ Ug, double* __
       }
       __syncthreads();
       if (keep[jj]) {
-        const double djj = Tm[jj * r + jj].re;
-        for (int l = jj + 1 + tid; l < r; l += T) {
+        const double inv = 1.0 / Tm[jj * r + jj].re;
+        for (int l = jj + 1 + lane; l < r; l += TW) {
           cd v = G[jj * r + l];
           for (int i = 0; i < jj; ++i) v -= cmul_conj(Tm[i * r + jj], Tm[i * r + l]);
-          Tm[jj * r + l] = (1.0 / djj) * v;
+          Tm[jj * r + l] = inv * v;
         }
       }
       __syncthreads();
     }
-    // Ti = T^-1 on the kept rows/columns (zero elsewhere): column l solved by thread l
-    if (tid < r) {
-      const int l = tid;
-      if (keep[l]) {
-        for (int i = l; i >= 0; --i) {
-          if (!keep[i]) continue;
-          cd v = (i == l) ? cd{1.0, 0.0} : cd{0.0, 0.0};
-          for (int q = i + 1; q <= l; ++q)
-            if (keep[q]) v -= Tm[i * r + q] * Ti[q * r + l];
-          Ti[i * r + l] = (1.0 / Tm[i * r + i].re) * v;
-        }
+    // Ti = T^-1 on the kept rows/columns: column l by lane l
+    for (int l = lane; l < r; l += TW) {
+      if (!keep[l]) continue;
+      for (int i = l; i >= 0; --i) {
+        if (!keep[i]) continue;
+        cd v = (i == l) ? cd{1.0, 0.0} : cd{0.0, 0.0};
+        for (int q = i + 1; q <= l; ++q)
+          if (keep[q]) v -= Tm[i * r + q] * Ti[q * r + l];
+        Ti[i * r + l] = (1.0 / Tm[i * r + i].re) * v;
       }
     }
-    // M = K^dag (column-major, M[c*we + row] = conj(K[row][c])), J = I
-    for (int e = tid; e < we * we; e += T) {
+    // M = K^dag: M(row, c) = conj(K(c, row)), column-major; J = I
+    for (int e = lane; e < we * we; e += TW) {
       const int c = e / we, row = e - c * we;
-      cd kv = {0, 0};  // K[row][c]... M column c = conj of K row c
-      // M[c][row] (column c, entry row) = conj(K[c][row])
-      const int kr = c, kc = row;
-      if (kr < w && kc < w) {
-        if (kr < kp) {
-          if (kc < kp) kv = (kr == kc) ? cd{sg[kr], 0.0} : cd{0, 0};
-          else kv = X[kr * r + (kc - kp)];
-        } else if (kc >= kp) {
-          kv = Tm[(kr - kp) * r + (kc - kp)];
+      cd kv = {0, 0};
+      if (c < w && row < w) {
+        if (c < kp) {
+          if (row < kp) kv = (c == row) ? cd{sg[c], 0.0} : cd{0, 0};
+          else kv = X[c * r + (row - kp)];
+        } else if (row >= kp) {
+          kv = Tm[(c - kp) * r + (row - kp)];
         }
       }
       M[e] = conj(kv);
       J[e] = (c == row) ? cd{1.0, 0.0} : cd{0.0, 0.0};
     }
     __syncthreads();
-
     // one-sided Jacobi on the columns of M, rotations accumulated in J
-    const int npairs = we / 2;
-    const int grp = tid >> 3, gl = tid & 7;
     for (int sweep = 0; sweep < 40; ++sweep) {
       double offmax = 0.0;
       for (int t = 0; t < we - 1; ++t) {
         if (grp < npairs) {
           int pp = rr_pos(grp, t, we), qq = rr_pos(we - 1 - grp, t, we);
-          if (pp > qq) { const int tmp = pp; pp = qq; qq = tmp; }
+          if (pp > qq) {
+            const int tmp = pp;
+            pp = qq;
+            qq = tmp;
+          }
           cd* Mp = M + size_t(pp) * we;
           cd* Mq = M + size_t(qq) * we;
           double al = 0, be = 0;
           cd ga = {0, 0};
-          for (int row = gl; row < we; row += 8) {
-            al += norm2(Mp[row]);
-            be += norm2(Mq[row]);
-            ga += cmul_conj(Mp[row], Mq[row]);
+          for (int row = gl; row < we; row += lpp) {
+            const cd u = Mp[row], v = Mq[row];
+            al += norm2(u);
+            be += norm2(v);
+            ga += cmul_conj(u, v);
           }
-#pragma unroll
-          for (int off = 1; off < 8; off <<= 1) {
-            al += __shfl_xor(al, off, 64);
-            be += __shfl_xor(be, off, 64);
-            ga.re += __shfl_xor(ga.re, off, 64);
-            ga.im += __shfl_xor(ga.im, off, 64);
+          for (int off = 1; off < lpp; off <<= 1) {
+            al += __shfl_xor(al, off, TW);
+            be += __shfl_xor(be, off, TW);
+            ga.re += __shfl_xor(ga.re, off, TW);
+            ga.im += __shfl_xor(ga.im, off, TW);
           }
           const double g = sqrt(norm2(ga));
           if (al > 0.0 && be > 0.0 && g > 1e-300) {
             const double rel = g / sqrt(al * be);
             offmax = fmax(offmax, rel);
-            if (rel > 1e-16) {
+            if (rel > kJacobiTol) {
               const double zeta = (be - al) / (2.0 * g);
               const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
               const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
               const cd e = {ga.re / g, -ga.im / g};  // exp(-i theta)
-              for (int row = gl; row < we; row += 8) {
+              cd* Jp = J + size_t(pp) * we;
+              cd* Jq = J + size_t(qq) * we;
+              for (int row = gl; row < we; row += lpp) {
                 const cd u = Mp[row], v = e * Mq[row];
                 Mp[row] = cs * u - sn * v;
                 Mq[row] = sn * u + cs * v;
-              }
-              cd* Jp = J + size_t(pp) * we;
-              cd* Jq = J + size_t(qq) * we;
-              for (int row = gl; row < we; row += 8) {
-                const cd u = Jp[row], v = e * Jq[row];
-                Jp[row] = cs * u - sn * v;
-                Jq[row] = sn * u + cs * v;
+                const cd u2 = Jp[row], v2 = e * Jq[row];
+                Jp[row] = cs * u2 - sn * v2;
+                Jq[row] = sn * u2 + cs * v2;
               }
             }
           }
         }
         __syncthreads();
       }
-      if (gl == 0 && grp < 32) offg[grp] = (grp < npairs) ? offmax : 0.0;
-      __syncthreads();
-      if (tid == 0) {
-        double mx = 0.0;
-        for (int q = 0; q < npairs && q < 32; ++q) mx = fmax(mx, offg[q]);
-        s_flag = (mx < 1e-15) ? 1 : 0;
-      }
-      __syncthreads();
-      if (s_flag) break;
+      for (int off = 1; off < TW; off <<= 1) offmax = fmax(offmax, __shfl_xor(offmax, off, TW));
+      if (offmax <= kJacobiTol) break;
     }
     // singular values = column norms of M, sorted descending (stable)
-    for (int c = tid; c < we; c += T) {
+    for (int c = lane; c < we; c += TW) {
       double v = 0;
       for (int row = 0; row < we; ++row) v += norm2(M[size_t(c) * we + row]);
       s[c] = (c < w) ? sqrt(v) : -1.0;
     }
     __syncthreads();
-    for (int c = tid; c < we; c += T) {
+    for (int c = lane; c < we; c += TW) {
       int rank = 0;
       for (int q = 0; q < we; ++q) rank += (s[q] > s[c] || (s[q] == s[c] && q < c)) ? 1 : 0;
       perm[rank] = c;
     }
     __syncthreads();
-    // B = Ti Y_bot (r x kn), A = Y_top - X B (kp x kn); Y = J[:, perm], stored over M:
-    // M[0 .. kp*kn) = A (row-major [a][i]), then B ([b][i])
-    cd* Am = M;
-    cd* Bm = M + size_t(kp) * kn;
-    // M is no longer needed; write B first from J (J untouched)
-    for (int e = tid; e < r * kn; e += T) {
+    // AB = [A; B] (w x kn, row-major): B = Ti Y_bot, A = Y_top - X B with Y = J[:, perm]
+    for (int e = lane; e < r * kn; e += TW) {
       const int b = e / kn, i = e - b * kn;
       const cd* Yc = J + size_t(perm[i]) * we;
       cd v = {0, 0};
       for (int q = 0; q < r; ++q) v += Ti[b * r + q] * Yc[kp + q];
-      Bm[e] = v;
+      M[e] = v;  // M is free now: B staged at M[0 .. r*kn)
+      st2(ab, size_t(kp + b) * kn + i, v);
     }
     __syncthreads();
-    for (int e = tid; e < kp * kn; e += T) {
+    for (int e = lane; e < kp * kn; e += TW) {
       const int aa = e / kn, i = e - aa * kn;
       const cd* Yc = J + size_t(perm[i]) * we;
       cd v = Yc[aa];
-      for (int b = 0; b < r; ++b) v -= X[aa * r + b] * Bm[b * kn + i];
-      Am[e] = v;
+      for (int b = 0; b < r; ++b) v -= X[aa * r + b] * M[b * kn + i];
+      st2(ab, size_t(aa) * kn + i, v);
     }
-    for (int i = tid; i < kn; i += T) sg[i] = s[perm[i]];
+    for (int i = lane; i < kn; i += TW) sg[i] = s[perm[i]];
     __syncthreads();
+  }
+}
 
-    // ---------------- pass 3: U_new = U A + Psi B (row-local, in place)
+// ---------------------------------------------------------------------------------------
+// rotation: U_new = [U, Psi] AB, in place.  Thread owns 2 rows x (kn / 8) columns.
+template <int NPF>
+__global__ __launch_bounds__(T) void k_isvd_rotate(double2* __restrict__ Ug, const double2* __restrict__ Psig,
+                                                   const double2* __restrict__ AB, IsvdArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = a.N, kp = a.kp, r = a.r, w = a.w, kn = a.kn, k = a.k;
+  const int tid = threadIdx.x;
+  cd* chunk = reinterpret_cast<cd*>(smem_raw);  // [w][CHP]
+  cd* Ms = chunk + size_t(w) * CHP;             // [w][kn]
+  constexpr int NG = T / (CH / 2);              // column groups
+  const int rp = tid % (CH / 2), ig = tid / (CH / 2);
+  for (int p = blockIdx.x; p < a.nprob; p += gridDim.x) {
+    double2* U = Ug + size_t(p) * k * N;
+    const double2* Psi = Psig + size_t(p) * r * N;
+    const double2* ab = AB + size_t(p) * w * kn;
+    for (int e = tid; e < w * kn; e += T) Ms[e] = ld2(ab, e);
+    cd reg[NPF];
+    prefetch<NPF>(reg, U, Psi, kp, w, N, 0, tid);
     for (int r0 = 0; r0 < N; r0 += CH) {
-      for (int t = tid; t < w * CH; t += T) {
-        const int col = t / CH, row = t - col * CH;
-        const int gr = r0 + row;
-        cd v = {0, 0};
-        if (gr < N) v = col < kp ? ld2(U, size_t(col) * N + gr) : ld2(Psi, size_t(col - kp) * N + gr);
-        chunk[col * CHP + row] = v;
-      }
+      stage<NPF>(chunk, reg, w, tid);
       __syncthreads();
-      for (int t = tid; t < kn * CH; t += T) {
-        const int i = t / CH, row = t - i * CH;
-        const int gr = r0 + row;
-        if (gr >= N) continue;
-        cd v = {0, 0};
-        for (int aa = 0; aa < kp; ++aa) v += chunk[aa * CHP + row] * Am[aa * kn + i];
-        for (int b = 0; b < r; ++b) v += chunk[(kp + b) * CHP + row] * Bm[b * kn + i];
-        st2(U, size_t(i) * N + gr, v);
+      if (r0 + CH < N) prefetch<NPF>(reg, U, Psi, kp, w, N, r0 + CH, tid);
+      const int row0 = 2 * rp, row1 = 2 * rp + 1;
+      for (int i = ig; i < kn; i += NG) {
+        cd v0 = {0, 0}, v1 = {0, 0};
+#pragma unroll 4
+        for (int c = 0; c < w; ++c) {
+          const cd m = Ms[c * kn + i];
+          v0 += chunk[c * CHP + row0] * m;
+          v1 += chunk[c * CHP + row1] * m;
+        }
+        if (r0 + row0 < N) st2(U, size_t(i) * N + r0 + row0, v0);
+        if (r0 + row1 < N) st2(U, size_t(i) * N + r0 + row1, v1);
       }
       __syncthreads();
     }
   }
 }
 
-size_t isvd_lds_bytes(int kp, int r) {
+size_t gram_lds(int kp, int r) {
+  const int w = kp + r;
+  const int ta = (w + 1) / 2, tb = (r + 1) / 2, ntile = ta * tb;
+  const int nrg = std::max(1, T / ntile);
+  return (size_t(w) * CHP + size_t(kp) * r + size_t(nrg) * w * r) * sizeof(cd);
+}
+size_t small_lds(int kp, int r) {
   const int w = kp + r, we = w + (w & 1);
-  const size_t n = size_t(w) * CHP + 2 * size_t(kp) * r + 3 * size_t(r) * r + 2 * size_t(we) * we;
-  return n * sizeof(cd) + (we + r + 32) * sizeof(double) + (r + we) * sizeof(int);
+  const size_t n = 2 * size_t(kp) * r + 3 * size_t(r) * r + 2 * size_t(we) * we;
+  return n * sizeof(cd) + (we + r) * sizeof(double) + (r + we) * sizeof(int);
+}
+size_t rotate_lds(int kp, int r, int kn) {
+  const int w = kp + r;
+  return (size_t(w) * CHP + size_t(w) * kn) * sizeof(cd);
+}
+
+void set_lds(const void* f, size_t lds) {
+  if (lds > 64 * 1024) QMG_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+}
+
+template <int NPF>
+void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, HierarchyDev& h, const void* blocks,
+                 DevBuf& small, DevBuf& AB, DevBuf& sigma_dev, size_t ls, hipStream_t st) {
+  set_lds((const void*)k_isvd_gram<NPF>, lg);
+  set_lds((const void*)k_isvd_small, ls);
+  set_lds((const void*)k_isvd_rotate<NPF>, lr);
+  const int grid = std::min(a.nprob, 4 * ncu);
+  k_isvd_gram<NPF><<<grid, T, lg, st>>>(h.P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+  QMG_LAUNCH_CHECK();
+  k_isvd_small<<<a.nprob, TW, ls, st>>>(small.as<double2>(), sigma_dev.as<double>(), AB.as<double2>(), a);
+  QMG_LAUNCH_CHECK();
+  k_isvd_rotate<NPF><<<grid, T, lr, st>>>(h.P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+  QMG_LAUNCH_CHECK();
 }
 
 }  // namespace
@@ -365,18 +428,30 @@ size_t isvd_lds_bytes(int kp, int r) {
 int isvd_stream(HierarchyDev& h, const void* blocks, int r, int kp, DevBuf& sigma_dev, hipStream_t st) {
   const int w = kp + r;
   const int kn = std::min(h.k, w);
-  QMG_CHECK(kp * r + r * r <= 4 * T && kp * r + r <= 4 * T, QMG_ESHAPE, "streaming SVD: k*r + r*r too large");
-  QMG_CHECK(r >= 1 && r <= 48, QMG_ESHAPE, "streaming SVD: batch r must be in [1, 48]");
-  const size_t lds = isvd_lds_bytes(kp, r);
-  QMG_CHECK(lds <= 160 * 1024, QMG_ESHAPE, "streaming SVD: k + r = %d needs %zu bytes of LDS (> 160 KiB)", w, lds);
+  QMG_CHECK(r >= 1 && w <= MAXW, QMG_ESHAPE, "streaming SVD: k + r = %d exceeds %d", w, MAXW);
+  QMG_CHECK(((w + 1) / 2) * ((r + 1) / 2) <= T, QMG_ESHAPE,
+            "streaming SVD: ceil((k+r)/2) * ceil(r/2) = %d exceeds %d", ((w + 1) / 2) * ((r + 1) / 2), T);
+  const size_t lg = gram_lds(kp, r), ls = small_lds(kp, r), lr = rotate_lds(kp, r, kn);
+  QMG_CHECK(lg <= 160 * 1024 && ls <= 160 * 1024 && lr <= 160 * 1024, QMG_ESHAPE,
+            "streaming SVD: k + r = %d needs more than 160 KiB of LDS", w);
   IsvdArgs a{2 * h.blk.d, h.blk.N, h.k, r, kp, w, kn};
   int dev = 0, ncu = 256;
   QMG_HIP(hipGetDevice(&dev));
   QMG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int grid = std::min(a.nprob, ncu * 2);
-  if (lds > 64 * 1024) QMG_HIP(hipFuncSetAttribute((const void*)k_isvd, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  k_isvd<<<grid, T, lds, st>>>(h.P64.as<double2>(), sigma_dev.as<double>(), (const double2*)blocks, a);
-  QMG_LAUNCH_CHECK();
+  DevBuf small(size_t(a.nprob) * small_stride(kp, r) * sizeof(double2));
+  DevBuf AB(size_t(a.nprob) * w * kn * sizeof(double2));
+  // algorithmic: read U (kp cols) and Psi (r cols) in the two Gram passes and the rotation,
+  // write U (kn cols); flops of the Gram passes, the residual and the rotation
+  const double Nn = double(a.N) * a.nprob;
+  {
+    TimedLaunch tl("isvd", st, Nn * 16.0 * (3.0 * (kp + r) + kn),
+                   Nn * 8.0 * (2.0 * double(w) * r + double(kp) * r + double(w) * kn));
+    const int need = (w * CH + T - 1) / T;  // prefetch registers needed
+    if (need <= 4) launch_rows<4>(a, ncu, lg, lr, h, blocks, small, AB, sigma_dev, ls, st);
+    else if (need <= 8) launch_rows<8>(a, ncu, lg, lr, h, blocks, small, AB, sigma_dev, ls, st);
+    else launch_rows<PF>(a, ncu, lg, lr, h, blocks, small, AB, sigma_dev, ls, st);
+  }
+  QMG_HIP(hipStreamSynchronize(st));  // scratch buffers are released on return
   return kn;
 }
 

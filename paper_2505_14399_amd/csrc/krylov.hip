@@ -2,6 +2,8 @@
 // solvers used by the smoother, the coarse solve and the outer solve.
 #include <cmath>
 #include <complex>
+#include <cstring>
+#include <type_traits>
 
 #include "krylov.hpp"
 
@@ -180,6 +182,163 @@ __global__ void k_caxpy_dev(const double2* __restrict__ c, double sgn, const S* 
 
 inline unsigned nb256(size_t n) { return unsigned((n + 255) / 256); }
 
+// ---------------------------------------------------------------------------------------
+// Fused multi-vector kernels for the Arnoldi/GCR orthogonalisation: each reads the target
+// vector w once for up to MG basis vectors (grid.z = group of MG vectors).
+constexpr int MG = 8;
+
+template <class S>
+__device__ inline void store_partials(double2 (&acc)[MG], int mi, double2* partial, int i0, int nrhs, int r, int b,
+                                      int nblk) {
+  __shared__ double2 red[MG][RB / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < MG; ++i) {
+    const double2 v = warp_sum(acc[i]);
+    if (lane == 0) red[i][wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < mi) {
+    const int i = threadIdx.x;
+    double2 sacc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < RB / 64; ++q) {
+      sacc.x += red[i][q].x;
+      sacc.y += red[i][q].y;
+    }
+    partial[(size_t(i0 + i) * nrhs + r) * nblk + b] = sacc;
+  }
+}
+
+// partial <X_i, w> for i in [i0, i0 + MG) of this z-group
+template <class S>
+__global__ __launch_bounds__(RB) void k_mdot(const S* __restrict__ X, size_t xstride, int m, const S* __restrict__ w,
+                                             size_t len, int nrhs, int nblk, double2* __restrict__ partial) {
+  const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
+  const int mi = min(MG, m - i0);
+  const S* wr = w + size_t(r) * len;
+  double2 acc[MG];
+#pragma unroll
+  for (int i = 0; i < MG; ++i) acc[i] = make_double2(0.0, 0.0);
+  for (size_t e = size_t(b) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
+    const auto c = StoreTraits<S>::ld(wr[e]);
+    const double cr = c.re, ci = c.im;
+#pragma unroll
+    for (int i = 0; i < MG; ++i) {
+      if (i < mi) {
+        const auto a = StoreTraits<S>::ld(X[(i0 + i) * xstride + size_t(r) * len + e]);
+        const double ar = a.re, ai = a.im;
+        acc[i].x += ar * cr + ai * ci;
+        acc[i].y += ar * ci - ai * cr;
+      }
+    }
+  }
+  store_partials<S>(acc, mi, partial, i0, nrhs, r, b, nblk);
+}
+
+// w <- w + sgn * sum_i c_i X_i (all m vectors), then partial <X_i, w> (grid.z groups) or
+// partial |w|^2 (mode 1, grid.z = 1).  Each z-group recomputes the same w update; only z = 0
+// stores it.
+template <class S, int MODE>
+__global__ __launch_bounds__(RB) void k_axpy_then(const S* __restrict__ X, size_t xstride, int m,
+                                                  const double2* __restrict__ c, double sgn, S* __restrict__ w,
+                                                  size_t len, int nrhs, int nblk, double2* __restrict__ partial) {
+  using C = ctype<S>;
+  const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
+  const int mi = MODE == 0 ? min(MG, m - i0) : 1;
+  S* wr = w + size_t(r) * len;
+  double2 acc[MG];
+#pragma unroll
+  for (int i = 0; i < MG; ++i) acc[i] = make_double2(0.0, 0.0);
+  for (size_t e = size_t(b) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
+    auto v = StoreTraits<S>::ld(wr[e]);
+    for (int i = 0; i < m; ++i) {
+      const double2 ci = c[size_t(i) * nrhs + r];
+      const cplx<C> cc = {C(sgn * ci.x), C(sgn * ci.y)};
+      v += cc * StoreTraits<S>::ld(X[i * xstride + size_t(r) * len + e]);
+    }
+    const S vs = StoreTraits<S>::st(v);
+    if (blockIdx.z == 0) wr[e] = vs;
+    const auto vv = StoreTraits<S>::ld(vs);  // the stored (rounded) value
+    const double cr = vv.re, cim = vv.im;
+    if (MODE == 0) {
+#pragma unroll
+      for (int i = 0; i < MG; ++i) {
+        if (i < mi) {
+          const auto a = StoreTraits<S>::ld(X[(i0 + i) * xstride + size_t(r) * len + e]);
+          const double ar = a.re, ai = a.im;
+          acc[i].x += ar * cr + ai * cim;
+          acc[i].y += ar * cim - ai * cr;
+        }
+      }
+    } else {
+      acc[0].x += cr * cr + cim * cim;
+    }
+  }
+  store_partials<S>(acc, mi, partial, i0, nrhs, r, b, nblk);
+}
+
+// partial <X_i, w> (grid.z groups of MG) and, in group 0, partial |w|^2 stored at slot m
+template <class S>
+__global__ __launch_bounds__(RB) void k_mdot_norm(const S* __restrict__ X, size_t xstride, int m,
+                                                  const S* __restrict__ w, size_t len, int nrhs, int nblk,
+                                                  double2* __restrict__ partial) {
+  const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
+  const int mi = min(MG, m - i0);
+  const S* wr = w + size_t(r) * len;
+  double2 acc[MG];
+  double nn = 0.0;
+#pragma unroll
+  for (int i = 0; i < MG; ++i) acc[i] = make_double2(0.0, 0.0);
+  for (size_t e = size_t(b) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
+    const auto c = StoreTraits<S>::ld(wr[e]);
+    const double cr = c.re, ci = c.im;
+    nn += cr * cr + ci * ci;
+#pragma unroll
+    for (int i = 0; i < MG; ++i) {
+      if (i < mi) {
+        const auto a = StoreTraits<S>::ld(X[(i0 + i) * xstride + size_t(r) * len + e]);
+        const double ar = a.re, ai = a.im;
+        acc[i].x += ar * cr + ai * ci;
+        acc[i].y += ar * ci - ai * cr;
+      }
+    }
+  }
+  store_partials<S>(acc, mi, partial, i0, nrhs, r, b, nblk);
+  if (blockIdx.z == 0) {
+    double2 t = block_sum(make_double2(nn, 0.0));
+    if (threadIdx.x == 0) partial[(size_t(m) * nrhs + r) * nblk + b] = t;
+  }
+}
+
+// w <- (w - sum_i c_i X_i) / beta with beta^2 = |w|^2 - sum_i |c_i|^2 (Pythagoras, c = X^dag w
+// for orthonormal X); beta^2 is also written to out_n2 (block 0).  n2 = |w|^2 before the update.
+template <class S>
+__global__ __launch_bounds__(RB) void k_axpy_scale(const S* __restrict__ X, size_t xstride, int m,
+                                                   const double2* __restrict__ c, const double2* __restrict__ n2,
+                                                   S* __restrict__ w, size_t len, int nrhs, double* __restrict__ out_n2) {
+  using C = ctype<S>;
+  const int r = blockIdx.y;
+  double b2 = n2[r].x;
+  for (int i = 0; i < m; ++i) {
+    const double2 ci = c[size_t(i) * nrhs + r];
+    b2 -= ci.x * ci.x + ci.y * ci.y;
+  }
+  b2 = fmax(b2, 0.0);
+  const double inv = b2 > 0.0 ? 1.0 / sqrt(b2) : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) out_n2[r] = b2;
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  S* wr = w + size_t(r) * len;
+  auto v = StoreTraits<S>::ld(wr[e]);
+  for (int i = 0; i < m; ++i) {
+    const double2 ci = c[size_t(i) * nrhs + r];
+    const cplx<C> cc = {C(-ci.x), C(-ci.y)};
+    v += cc * StoreTraits<S>::ld(X[i * xstride + size_t(r) * len + e]);
+  }
+  wr[e] = StoreTraits<S>::st(C(inv) * v);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
@@ -243,6 +402,67 @@ template <class S>
 void Blas<S>::caxpy_dev(const double2* c, double sgn, const void* y, void* x, size_t len, int nrhs,
                         hipStream_t st) {
   k_caxpy_dev<S><<<dim3(nb256(len), nrhs), 256, 0, st>>>(c, sgn, (const S*)y, (S*)x, len);
+  QMG_LAUNCH_CHECK();
+}
+
+template <class S>
+void Blas<S>::mdot(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
+                   RedWork& rw, hipStream_t st) {
+  if (m <= 0) return;
+  const int ng = (m + MG - 1) / MG;
+  const int nblk = pick_nblk(len, ng * nrhs);
+  rw.ensure(size_t(nblk) * m * nrhs, 0);
+  k_mdot<S><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride, m, (const S*)w, len, nrhs, nblk,
+                                                 rw.partial.as<double2>());
+  QMG_LAUNCH_CHECK();
+  k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+  QMG_LAUNCH_CHECK();
+}
+template <class S>
+void Blas<S>::axpy_mdot(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
+                        int nrhs, double2* out, RedWork& rw, hipStream_t st) {
+  if (m <= 0) return;
+  // the update must be complete before other z-groups read w: one group only when m > MG
+  if (m > MG) {
+    axpy_multi(X, xstride, m, c, sgn, w, len, nrhs, st);
+    mdot(X, xstride, m, w, len, nrhs, out, rw, st);
+    return;
+  }
+  const int nblk = pick_nblk(len, nrhs);
+  rw.ensure(size_t(nblk) * m * nrhs, 0);
+  k_axpy_then<S, 0><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride, m, c, sgn, (S*)w, len, nrhs, nblk,
+                                                         rw.partial.as<double2>());
+  QMG_LAUNCH_CHECK();
+  k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+  QMG_LAUNCH_CHECK();
+}
+template <class S>
+void Blas<S>::axpy_norm(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
+                        int nrhs, double* out, RedWork& rw, hipStream_t st) {
+  const int nblk = pick_nblk(len, nrhs);
+  rw.ensure(size_t(nblk) * nrhs, 0);
+  k_axpy_then<S, 1><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride, m, c, sgn, (S*)w, len, nrhs, nblk,
+                                                         rw.partial.as<double2>());
+  QMG_LAUNCH_CHECK();
+  k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+  QMG_LAUNCH_CHECK();
+}
+
+template <class S>
+void Blas<S>::cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
+                        RedWork& rw, hipStream_t st) {
+  const int ng = (m + MG - 1) / MG;
+  const int nblk = pick_nblk(len, ng * nrhs);
+  rw.ensure(size_t(nblk) * (m + 1) * nrhs, size_t(nrhs));
+  k_mdot_norm<S><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride, m, (const S*)w, len, nrhs, nblk,
+                                                      rw.partial.as<double2>());
+  QMG_LAUNCH_CHECK();
+  k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, h);
+  QMG_LAUNCH_CHECK();
+  double2* wn = rw.result.as<double2>();
+  k_finalize2<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>() + size_t(m) * nrhs * nblk, nblk, wn);
+  QMG_LAUNCH_CHECK();
+  k_axpy_scale<S><<<dim3(nb256(len), nrhs), 256, 0, st>>>((const S*)X, xstride, m, h, wn, (S*)w, len, nrhs, n2);
   QMG_LAUNCH_CHECK();
 }
 
@@ -330,6 +550,9 @@ struct GivensState {
 template <class S>
 typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int m,
                                           int max_iter, double tol, hipStream_t st) {
+  // FP64 keeps two Gram-Schmidt passes (parity with the FP64 reference to ~1e-12); lower
+  // storage precisions use one pass with the Pythagorean norm, which halves the basis traffic
+  constexpr bool kCgs2 = std::is_same<S, double2>::value;
   const size_t len = A.len();
   ensure(len, nrhs, m);
   S* V = V_.as<S>();
@@ -385,16 +608,23 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
       S* vj = V + size_t(j) * vs;
       S* vn = V + size_t(j + 1) * vs;
       A.apply(vj, vn, nrhs, st);
-      Blas<S>::dot_multi(V, vs, j + 1, vn, len, nrhs, h1, rw_, st);
-      Blas<S>::axpy_multi(V, vs, j + 1, h1, -1.0, vn, len, nrhs, st);
-      Blas<S>::dot_multi(V, vs, j + 1, vn, len, nrhs, h2, rw_, st);
-      Blas<S>::axpy_multi(V, vs, j + 1, h2, -1.0, vn, len, nrhs, st);
-      Blas<S>::norm2(vn, len, nrhs, nrm, rw_, st);
-      Blas<S>::scale_dev(vn, nrm, 0, len, nrhs, st);
+      if (kCgs2) {
+        // CGS2: h1 = V^dag w ; w -= V h1 and h2 = V^dag w ; w -= V h2 and |w|^2 ; w /= |w|
+        Blas<S>::mdot(V, vs, j + 1, vn, len, nrhs, h1, rw_, st);
+        Blas<S>::axpy_mdot(V, vs, j + 1, h1, -1.0, vn, len, nrhs, h2, rw_, st);
+        Blas<S>::axpy_norm(V, vs, j + 1, h2, -1.0, vn, len, nrhs, nrm, rw_, st);
+        Blas<S>::scale_dev(vn, nrm, 0, len, nrhs, st);
+      } else {
+        // one classical Gram-Schmidt pass with the norm from Pythagoras, scaling fused
+        Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, nrm, rw_, st);
+      }
       double2* snap = hcols + size_t(j) * per_col;
       QMG_HIP(hipMemcpyAsync(snap, h1, size_t(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
-      QMG_HIP(hipMemcpyAsync(snap + size_t(m + 1) * nrhs, h2, size_t(j + 1) * nrhs * sizeof(double2),
-                             hipMemcpyDeviceToHost, st));
+      if (kCgs2)
+        QMG_HIP(hipMemcpyAsync(snap + size_t(m + 1) * nrhs, h2, size_t(j + 1) * nrhs * sizeof(double2),
+                               hipMemcpyDeviceToHost, st));
+      else
+        std::memset(snap + size_t(m + 1) * nrhs, 0, size_t(j + 1) * nrhs * sizeof(double2));
       QMG_HIP(hipMemcpyAsync(snap + size_t(2 * (m + 1)) * nrhs, nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost,
                              st));
       ++it;
@@ -523,7 +753,7 @@ typename Fgcr<S>::Result Fgcr<S>::solve(LinOp& A, Precond& M, const void* b, voi
       M.apply(r, zk, nrhs, st);
       A.apply(zk, wk, nrhs, st);
       for (int pass = 0; pass < 2 && k > 0; ++pass) {
-        Blas<S>::dot_multi(W, vs, k, wk, len, nrhs, beta, rw_, st);
+        Blas<S>::mdot(W, vs, k, wk, len, nrhs, beta, rw_, st);
         Blas<S>::axpy_multi(W, vs, k, beta, -1.0, wk, len, nrhs, st);
         Blas<S>::axpy_multi(Z, vs, k, beta, -1.0, zk, len, nrhs, st);
       }

@@ -44,6 +44,19 @@ struct Blas {
   // out[i * nrhs + r] = <X_i[r], w[r]>, X_i = X + i * xstride complex entries, i < m
   static void dot_multi(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs,
                         double2* out, RedWork& rw, hipStream_t st);
+  // as dot_multi, reading w once per group of up to 8 vectors
+  static void mdot(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
+                   RedWork& rw, hipStream_t st);
+  // w[r] += sgn * sum_i c[i * nrhs + r] X_i[r], then out = <X_i[r], w[r]> (fused)
+  static void axpy_mdot(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
+                        int nrhs, double2* out, RedWork& rw, hipStream_t st);
+  // w[r] += sgn * sum_i c[i * nrhs + r] X_i[r], then out[r] = ||w[r]||^2 (fused)
+  static void axpy_norm(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
+                        int nrhs, double* out, RedWork& rw, hipStream_t st);
+  // one Gram-Schmidt step: h = X^dag w (m vectors), w <- (w - X h) / beta with
+  // beta^2 = |w|^2 - |h|^2, n2[r] = beta^2 (device)
+  static void cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
+                        RedWork& rw, hipStream_t st);
   // out[r] = ||w[r]||^2
   static void norm2(const void* w, size_t len, int nrhs, double* out, RedWork& rw, hipStream_t st);
   // w[r] += sgn * sum_i c[i * nrhs + r] X_i[r]

@@ -18,6 +18,7 @@ struct HierarchyDev {
 
   DevBuf U64, Uin;           // native gauge, FP64 and inner precision
   DevBuf bsite, cnb;         // tables
+  DevBuf blists;             // [8][nd]: in-block sites per hop direction, intra-block hops first
   DevBuf P64, Pin;           // [d][2][k][N]
   DevBuf Y64, Yin;           // [d][9][2k][2k] column-major blocks
   std::vector<double> sigma; // [d][2][k]

@@ -248,6 +248,7 @@ struct DslashArgs {
   int nrhs;
   int dagger;
   int canonical;  // 1: AoS canonical layouts, 0: native SoA
+  int tchunk;     // native kernel: sites per thread along t (0: chosen by the launcher)
 };
 DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical);
 

@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "mg.hpp"
+#include "timing.hpp"
 
 namespace qmg {
 
@@ -137,112 +138,174 @@ __device__ inline void hop_col(const cplx<double>* q, int beta, double sg, const
 }
 
 constexpr int kMaxM = 64;        // 2k <= 64
-constexpr int kMaxPerThread = (kMaxM * kMaxM + 255) / 256;
 
+// grid (d, 8): workgroup (j, dir) forms, for the hops of direction dir leaving the sites of
+// aggregate j, the sum over sites of P_j(x)^dag H(x, dir) P_{j'}(x + dir) as a small GEMM:
+// rows (alpha, i) of P_j(x)^dag, columns (beta, l) of H P at the neighbour, reduction over
+// the sites and the 6 spin-colour components of chirality alpha.  The sites of the block are
+// visited by class from a host-built list: hops that stay inside the block (accumulated into
+// the partial W[dir][j] of Y_0), then, for dir 0 only, the diagonal term (m+1+3/xi) P^dag P
+// (also into W), then the hops through the face (written to Y_{1+dir}(j)).  NS sites are
+// staged per phase; each thread owns a TS x TS tile of the (2k) x (2k) block.
+template <int TS>
 __global__ __launch_bounds__(256) void k_build_coarse(const double2* __restrict__ U, const double2* __restrict__ P,
-                                                      const int* __restrict__ bsite, double2* __restrict__ Y,
-                                                      BuildArgs a) {
-  __shared__ cplx<double> Px[2 * 6 * 32];        // [alpha][s6][i]
-  __shared__ cplx<double> HP[12 * kMaxM];        // [comp][col]
-  __shared__ cplx<double> link[9];
-  const int j = blockIdx.x;
+                                                      const int* __restrict__ bsite, const int* __restrict__ lists,
+                                                      double2* __restrict__ Y, double2* __restrict__ W, BuildArgs a,
+                                                      int NS) {
+  extern __shared__ unsigned char smem_raw[];
   const int k = a.k, m = 2 * k, N = a.N, nd = a.nd, V = a.V;
+  cplx<double>* Px = reinterpret_cast<cplx<double>*>(smem_raw);  // [NS][12][k]
+  cplx<double>* HP = Px + size_t(NS) * 12 * k;                    // [NS][12][m]
+  cplx<double>* lnk = HP + size_t(NS) * 12 * m;                   // [NS][9]
+  double* scoef = reinterpret_cast<double*>(lnk + size_t(NS) * 9); // [NS]
+  int* sinfo = reinterpret_cast<int*>(scoef + NS);                // [NS][5]: ib, x, y, jy, iby
+  const int j = blockIdx.x, dir = blockIdx.y;
+  const int mu = dir & 3;
+  const bool fwd = dir < 4;
+  const double sg = fwd ? -1.0 : 1.0;
   const int tid = threadIdx.x;
+  const int nrk = (k + TS - 1) / TS;        // row tiles per chirality
+  const int nct = (m + TS - 1) / TS;        // column tiles
+  const bool active = tid < 2 * nrk * nct;
+  const int rt = tid / nct, ct = tid - (tid / nct) * nct;
+  const int al = rt / nrk, i0 = (rt - al * nrk) * TS, c0 = ct * TS;
+  const int nface = nd / a.b[mu];
+  const int* list = lists + size_t(dir) * nd;  // intra sites, then face sites
   const int nent = m * m;
-  cplx<double> face[kMaxPerThread], intra[kMaxPerThread];
-  for (int e = 0; e < kMaxPerThread; ++e) intra[e] = {0, 0};
+  cplx<double> acc[TS][TS];
 
-  for (int dir = 0; dir < 8; ++dir) {
-    const int mu = dir & 3;
-    const bool fwd = dir < 4;
-    for (int e = 0; e < kMaxPerThread; ++e) face[e] = {0, 0};
-    for (int ib = 0; ib < nd; ++ib) {
-      const int x = bsite[size_t(j) * nd + ib];
-      int c[4];
-      {
+  for (int cls = 0; cls < 3; ++cls) {
+    // cls 0: intra hops, cls 1: diagonal term (dir 0 only), cls 2: face hops
+    if (cls == 1 && dir != 0) continue;
+    const int count = cls == 0 ? nd - nface : (cls == 1 ? nd : nface);
+    const int base = cls == 2 ? nd - nface : 0;
+    if (cls != 1) {
+#pragma unroll
+      for (int t = 0; t < TS; ++t)
+#pragma unroll
+        for (int u = 0; u < TS; ++u) acc[t][u] = {0, 0};
+    }
+    for (int n0 = 0; n0 < count; n0 += NS) {
+      const int ns = min(NS, count - n0);
+      if (tid < ns) {
+        const int ib = cls == 1 ? n0 + tid : list[base + n0 + tid];
+        const int x = bsite[size_t(j) * nd + ib];
+        int c[4];
         int rem = x;
         for (int q = 0; q < 4; ++q) { c[q] = rem % a.L[q]; rem /= a.L[q]; }
+        int cy[4] = {c[0], c[1], c[2], c[3]};
+        if (cls != 1) cy[mu] = fwd ? (c[mu] + 1) % a.L[mu] : (c[mu] + a.L[mu] - 1) % a.L[mu];
+        int cj[4], ci[4];
+        for (int q = 0; q < 4; ++q) { cj[q] = cy[q] / a.b[q]; ci[q] = cy[q] % a.b[q]; }
+        int* si = sinfo + tid * 5;
+        si[0] = ib;
+        si[1] = x;
+        si[2] = lex4(cy, a.L);
+        si[3] = lex4(cj, a.cL);
+        si[4] = lex4(ci, a.b);
+        double sgnbc = 1.0;
+        if (mu == 3 && a.bc_t < 0) {
+          if (fwd && c[3] == a.L[3] - 1) sgnbc = -1.0;
+          if (!fwd && c[3] == 0) sgnbc = -1.0;
+        }
+        scoef[tid] = -0.5 * a.cw[mu] * sgnbc;
       }
-      int cy[4] = {c[0], c[1], c[2], c[3]};
-      cy[mu] = fwd ? (c[mu] + 1) % a.L[mu] : (c[mu] + a.L[mu] - 1) % a.L[mu];
-      const int y = lex4(cy, a.L);
-      int cj[4], ci[4];
-      for (int q = 0; q < 4; ++q) { cj[q] = cy[q] / a.b[q]; ci[q] = cy[q] % a.b[q]; }
-      const int jy = lex4(cj, a.cL), iby = lex4(ci, a.b);
-      const bool is_face = fwd ? (c[mu] % a.b[mu] == a.b[mu] - 1) : (c[mu] % a.b[mu] == 0);
-      double sgnbc = 1.0;
-      if (mu == 3 && a.bc_t < 0) {
-        if (fwd && c[3] == a.L[3] - 1) sgnbc = -1.0;
-        if (!fwd && c[3] == 0) sgnbc = -1.0;
-      }
-      const double coef = -0.5 * a.cw[mu] * sgnbc;
-      // stage P(x) rows and the link
-      for (int t = tid; t < 2 * 6 * k; t += 256) {
-        const int al = t / (6 * k), rem = t - al * 6 * k, s6 = rem / k, i = rem - s6 * k;
-        double2 v = P[((size_t(j) * 2 + al) * k + i) * N + size_t(s6) * nd + ib];
-        Px[(al * 6 + s6) * k + i] = {v.x, v.y};
-      }
-      if (tid < 9) {
-        // forward: U_mu(x); backward: U_mu(y)^dag
+      __syncthreads();
+      // links and the rows of P at the staged sites
+      for (int t = tid; t < ns * 9; t += 256) {
+        const int q = t / 9, e = t - q * 9;
+        const int* si = sinfo + q * 5;
         if (fwd) {
-          double2 v = U[(size_t(mu) * 9 + tid) * V + x];
-          link[tid] = {v.x, v.y};
+          const double2 v = U[(size_t(mu) * 9 + e) * V + si[1]];
+          lnk[q * 9 + e] = {v.x, v.y};
         } else {
-          const int r = tid / 3, cc = tid % 3;
-          double2 v = U[(size_t(mu) * 9 + cc * 3 + r) * V + y];
-          link[tid] = {v.x, -v.y};
+          const int rr = e / 3, cc = e - rr * 3;
+          const double2 v = U[(size_t(mu) * 9 + cc * 3 + rr) * V + si[2]];
+          lnk[q * 9 + e] = {v.x, -v.y};
+        }
+      }
+      for (int t = tid; t < ns * 12 * k; t += 256) {
+        const int q = t % ns, rem = t / ns;
+        const int comp = rem / k, i = rem - comp * k;
+        const int alc = comp / 6, s6 = comp - alc * 6;
+        const double2 v = P[((size_t(j) * 2 + alc) * k + i) * N + size_t(s6) * nd + sinfo[q * 5]];
+        Px[(size_t(q) * 12 + comp) * k + i] = {v.x, v.y};
+      }
+      __syncthreads();
+      // H P at the neighbour (cls 1: the diagonal term times P at the site itself)
+      for (int t = tid; t < ns * m; t += 256) {
+        const int q = t / m, col = t - q * m;
+        const int beta = col / k, l = col - beta * k;
+        cplx<double>* hp = HP + size_t(q) * 12 * m + col;
+        if (cls == 1) {
+          for (int comp = 0; comp < 12; ++comp)
+            hp[comp * m] = (comp / 6 == beta) ? a.diag * Px[(size_t(q) * 12 + comp) * k + l] : cplx<double>{0, 0};
+        } else {
+          const int* si = sinfo + q * 5;
+          cplx<double> qv[6];
+          for (int s6 = 0; s6 < 6; ++s6) {
+            const double2 v = P[((size_t(si[3]) * 2 + beta) * k + l) * N + size_t(s6) * nd + si[4]];
+            qv[s6] = {v.x, v.y};
+          }
+          cplx<double> out[12];
+          switch (mu) {
+            case 0: hop_col<0>(qv, beta, sg, lnk + q * 9, scoef[q], out); break;
+            case 1: hop_col<1>(qv, beta, sg, lnk + q * 9, scoef[q], out); break;
+            case 2: hop_col<2>(qv, beta, sg, lnk + q * 9, scoef[q], out); break;
+            default: hop_col<3>(qv, beta, sg, lnk + q * 9, scoef[q], out); break;
+          }
+          for (int comp = 0; comp < 12; ++comp) hp[comp * m] = out[comp];
         }
       }
       __syncthreads();
-      if (tid < m) {
-        const int beta = tid / k, l = tid - beta * k;
-        cplx<double> q[6];
-        for (int s6 = 0; s6 < 6; ++s6) {
-          double2 v = P[((size_t(jy) * 2 + beta) * k + l) * N + size_t(s6) * nd + iby];
-          q[s6] = {v.x, v.y};
-        }
-        cplx<double> out[12];
-        const double sg = fwd ? -1.0 : 1.0;
-        switch (mu) {
-          case 0: hop_col<0>(q, beta, sg, link, coef, out); break;
-          case 1: hop_col<1>(q, beta, sg, link, coef, out); break;
-          case 2: hop_col<2>(q, beta, sg, link, coef, out); break;
-          default: hop_col<3>(q, beta, sg, link, coef, out); break;
-        }
-        for (int cc = 0; cc < 12; ++cc) HP[cc * m + tid] = out[cc];
-      }
-      __syncthreads();
-      for (int e = 0; e < kMaxPerThread; ++e) {
-        const int idx = tid + e * 256;
-        if (idx >= nent) break;
-        const int col = idx / m, row = idx - col * m;
-        const int al = row / k, i = row - al * k;
-        cplx<double> s = {0, 0};
-        for (int s6 = 0; s6 < 6; ++s6) s += cmul_conj(Px[(al * 6 + s6) * k + i], HP[(6 * al + s6) * m + col]);
-        if (is_face) face[e] += s;
-        else intra[e] += s;
-        if (dir == 0) {  // diagonal term once per site
-          const int be = col / k, l = col - be * k;
-          if (be == al) {
-            cplx<double> dsum = {0, 0};
-            for (int s6 = 0; s6 < 6; ++s6) dsum += cmul_conj(Px[(al * 6 + s6) * k + i], Px[(al * 6 + s6) * k + l]);
-            intra[e] += a.diag * dsum;
+      if (active) {
+        for (int q = 0; q < ns; ++q) {
+#pragma unroll 2
+          for (int s6 = 0; s6 < 6; ++s6) {
+            const int comp = 6 * al + s6;
+            const cplx<double>* pr = Px + (size_t(q) * 12 + comp) * k;
+            const cplx<double>* hr = HP + (size_t(q) * 12 + comp) * m;
+            cplx<double> pa[TS], hb[TS];
+#pragma unroll
+            for (int t = 0; t < TS; ++t) pa[t] = (i0 + t < k) ? pr[i0 + t] : cplx<double>{0, 0};
+#pragma unroll
+            for (int u = 0; u < TS; ++u) hb[u] = (c0 + u < m) ? hr[c0 + u] : cplx<double>{0, 0};
+#pragma unroll
+            for (int t = 0; t < TS; ++t)
+#pragma unroll
+              for (int u = 0; u < TS; ++u) acc[t][u] += cmul_conj(pa[t], hb[u]);
           }
         }
       }
       __syncthreads();
     }
-    for (int e = 0; e < kMaxPerThread; ++e) {
-      const int idx = tid + e * 256;
-      if (idx >= nent) break;
-      Y[(size_t(j) * 9 + 1 + dir) * nent + idx] = make_double2(face[e].re, face[e].im);
+    // write: intra (after the diagonal term for dir 0) to W, face to Y_{1+dir}
+    const bool write_w = (cls == 0 && dir != 0) || cls == 1;
+    if (active && (write_w || cls == 2)) {
+      for (int t = 0; t < TS; ++t)
+        for (int u = 0; u < TS; ++u) {
+          const int i = i0 + t, col = c0 + u;
+          if (i >= k || col >= m) continue;
+          const int idx = col * m + al * k + i;
+          const double2 v = make_double2(acc[t][u].re, acc[t][u].im);
+          if (cls == 2) Y[(size_t(j) * 9 + 1 + dir) * nent + idx] = v;
+          else W[(size_t(dir) * a.d + j) * nent + idx] = v;
+        }
     }
   }
-  for (int e = 0; e < kMaxPerThread; ++e) {
-    const int idx = tid + e * 256;
-    if (idx >= nent) break;
-    Y[(size_t(j) * 9) * nent + idx] = make_double2(intra[e].re, intra[e].im);
+}
+
+__global__ void k_sum_self(const double2* __restrict__ W, double2* __restrict__ Y, int d, int nent) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= size_t(d) * nent) return;
+  const size_t j = g / nent, idx = g - j * nent;
+  double2 s = make_double2(0.0, 0.0);
+  for (int dir = 0; dir < 8; ++dir) {
+    const double2 v = W[(size_t(dir) * d + j) * nent + idx];
+    s.x += v.x;
+    s.y += v.y;
   }
+  Y[(j * 9) * nent + idx] = s;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -421,6 +484,8 @@ void dispatch_prec(qmg_prec p, F&& f) {
 
 void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const void* coarse, void* fine, int nrhs,
                     hipStream_t st) {
+  TimedLaunch tl("prolong", st, double(h.g.V) * (12.0 * h.k + 12.0 * nrhs) * prec_bytes(prec),
+                 8.0 * 12.0 * h.k * h.g.V * nrhs);
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
     dim3 grid(cdiv(h.blk.N, 256), 2 * h.blk.d, nrhs);
@@ -432,6 +497,8 @@ void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const v
 
 void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const void* fine, void* coarse, int nrhs,
                      hipStream_t st) {
+  TimedLaunch tl("restrict", st, double(h.g.V) * (12.0 * h.k + 12.0 * nrhs) * prec_bytes(prec),
+                 8.0 * 12.0 * h.k * h.g.V * nrhs);
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
     const size_t lds = size_t(h.blk.N) * sizeof(cplx<ctype<S>>);
@@ -445,6 +512,8 @@ void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const 
 void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, const void* in, void* out, int nrhs,
                          hipStream_t st) {
   const int m = 2 * h.k;
+  TimedLaunch tl("coarse_apply", st, double(h.blk.d) * (9.0 * m * m + 2.0 * m * nrhs) * prec_bytes(prec),
+                 8.0 * 9.0 * m * m * h.blk.d * nrhs);
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
     dim3 grid(cdiv(size_t(h.blk.d) * m, 256), nrhs);
@@ -469,9 +538,26 @@ void build_coarse(HierarchyDev& h, hipStream_t st) {
   a.d = h.blk.d;
   a.bc_t = h.g.bc_t;
   a.diag = h.g.diag();
-  k_build_coarse<<<h.blk.d, 256, 0, st>>>(h.U64.as<double2>(), h.P64.as<double2>(), h.bsite.as<int>(),
-                                          h.Y64.as<double2>(), a);
+  TimedLaunch tl("coarse_build", st, double(h.g.V) * 12.0 * h.k * 16.0 + 9.0 * h.blk.d * 4.0 * h.k * h.k * 16.0,
+                 double(h.g.V) * 8.0 * (2.0 * h.k) * (2.0 * h.k) * 6.0 * 8.0);
+  const int nent = 4 * h.k * h.k;
+  DevBuf W(size_t(8) * h.blk.d * nent * sizeof(double2));
+  // per site: Px (12 k) + HP (24 k) + link (9) complex, + coefficient and 5 ints
+  const size_t per_site = size_t(12 * h.k + 24 * h.k + 9) * sizeof(cplx<double>) + sizeof(double) + 5 * sizeof(int);
+  const int NS = int(std::max<size_t>(1, std::min<size_t>(16, (110 * 1024) / per_site)));
+  const size_t lds = per_site * NS;
+  auto go = [&](auto kern) {
+    if (lds > 64 * 1024) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     int(lds)));
+    kern<<<dim3(h.blk.d, 8), 256, lds, st>>>(h.U64.as<double2>(), h.P64.as<double2>(), h.bsite.as<int>(),
+                                             h.blists.as<int>(), h.Y64.as<double2>(), W.as<double2>(), a, NS);
+  };
+  if (h.k <= 24) go(k_build_coarse<3>);
+  else go(k_build_coarse<4>);
   QMG_LAUNCH_CHECK();
+  k_sum_self<<<cdiv(size_t(h.blk.d) * nent, 256), 256, 0, st>>>(W.as<double2>(), h.Y64.as<double2>(), h.blk.d, nent);
+  QMG_LAUNCH_CHECK();
+  QMG_HIP(hipStreamSynchronize(st));  // W is released on return
 }
 
 void launch_chiral_gather(const HierarchyDev& h, const void* fine, void* blocks, int r, hipStream_t st) {

@@ -1,0 +1,97 @@
+"""Write tests/golden/tuned_masses.json: the quark masses of the near-critical workloads.
+
+Reading of "mass tuned so that |lambda_min| ~ 1e-3": since D(m) = D(0) + m, find the
+eigenvalue lambda* of D(0) with the smallest real part (ARPACK, which='SR', on the oracle's
+stencil) and set m = -Re(lambda*) + 1e-3.  For the 24^3 x 64 lattice ("m near critical") the
+same search runs on a 12^3 x 16 lattice with the same roughness and seed (the critical mass is
+intensive).  ARPACK runs on a sparse matrix assembled from the oracle's hop definition and the margin is 2e-2, so that D(m) on the large lattice keeps its spectrum in the
+right half plane.  Uses only oracle/ and fields/.  Run: python tests/golden/make_tuned_masses.py
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+from scipy.sparse.linalg import LinearOperator, eigs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+import fields  # noqa: E402
+from fields.workloads import WORKLOADS  # noqa: E402
+from oracle import wilson, geometry as geo  # noqa: E402
+from oracle.gamma import GAMMA, ID4  # noqa: E402
+import scipy.sparse as sp  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_masses.json")
+
+
+def sparse_wilson(U, mass, xi, bc_t, dims):
+    """D as a scipy CSR matrix assembled hop by hop from the oracle's geometry, gamma matrices
+    and weights (same definition as oracle.wilson); checked against apply_wilson before use."""
+    V = geo.volume(dims)
+    nb = geo.neighbor_table(dims)
+    sg = geo.hop_sign(dims, bc_t)
+    c = wilson.hop_weights(xi)
+    rows, cols, vals = [], [], []
+    base = 12 * np.arange(V)
+    for mu in range(4):
+        for fwd in (True, False):
+            d = mu if fwd else 4 + mu
+            y = nb[:, d]
+            proj = (ID4 - GAMMA[mu]) if fwd else (ID4 + GAMMA[mu])
+            link = U[mu] if fwd else np.conj(np.swapaxes(U[mu][y], -1, -2))
+            blk = np.einsum("st,xab->xsatb", proj, link).reshape(V, 12, 12)
+            blk = blk * (-0.5 * c[mu] * sg[:, d])[:, None, None]
+            r = (base[:, None, None] + np.arange(12)[None, :, None]) + 0 * np.arange(12)[None, None, :]
+            cc = (12 * y[:, None, None] + np.arange(12)[None, None, :]) + 0 * np.arange(12)[None, :, None]
+            keep = blk != 0
+            rows.append(r[keep]); cols.append(cc[keep]); vals.append(blk[keep])
+    n = 12 * V
+    rows.append(np.arange(n)); cols.append(np.arange(n)); vals.append(np.full(n, wilson.diag_term(mass, xi), complex))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+def leftmost(dims, eps, xi, bc_t, seed, tag):
+    U = fields.random_gauge(dims, eps, seed, tag)
+    n = 12 * int(np.prod(dims))
+    A = sparse_wilson(U, 0.0, xi, bc_t, dims)
+    v = fields.gaussian_spinor(dims, 1, 99)[0]
+    err = np.abs(A @ v.ravel() - wilson.apply_wilson(U, v, 0.0, xi, bc_t, dims).ravel()).max()
+    assert err < 1e-12, err
+    cnt = [0]
+
+    def mv(x):
+        cnt[0] += 1
+        if cnt[0] % 500 == 0:
+            print(f"  {dims}: {cnt[0]} matvecs", flush=True)
+        return A @ x
+
+    Op = LinearOperator((n, n), matvec=mv, dtype=np.complex128)
+    t0 = time.time()
+    vals = eigs(Op, k=6, which="SR", ncv=80, tol=1e-5, maxiter=100000, return_eigenvectors=False,
+                v0=np.ones(n, dtype=np.complex128))
+    vals = vals[np.argsort(vals.real)]
+    print(f"  {dims}: {cnt[0]} matvecs, {time.time() - t0:.0f} s, leftmost {vals[:3]}", flush=True)
+    return vals
+
+
+def main():
+    out = {}
+    if os.path.exists(OUT):
+        out = json.load(open(OUT))
+    for name, small, margin in (("aniso16x32_fp32", None, 1e-3), ("iso24x64_bf16", (12, 12, 12, 16), 2e-2)):
+        w = WORKLOADS[name]
+        dims = small or w["dims"]
+        vals = leftmost(dims, w["eps"], w["xi"], w["bc_t"], w["seed"], w["tag"])
+        lam = vals[0]
+        m = float(-lam.real + margin)
+        out[name] = {"mass": m, "leftmost_eigenvalue_of_D0": [float(lam.real), float(lam.imag)],
+                     "min_abs_eig_at_mass": float(np.min(np.abs(vals + m))),
+                     "searched_on": list(dims), "margin": margin}
+        json.dump(out, open(OUT, "w"), indent=1)
+        print(name, out[name], flush=True)
+
+
+if __name__ == "__main__":
+    main()

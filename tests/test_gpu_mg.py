@@ -200,3 +200,22 @@ def test_error_statuses(qmg):
     with pytest.raises(qmg.QmgError) as e:
         qmg.mg_solve(mg, bn, tol=1e-10)
     assert e.value.status == "ENONFINITE"
+
+
+@pytest.mark.parametrize("dims,block,k,r,ns", [((8, 4, 4, 8), (4, 4, 4, 4), 24, 8, 3),
+                                               ((4, 4, 4, 4), (4, 2, 2, 2), 32, 16, 2),
+                                               ((6, 4, 2, 6), (2, 2, 1, 3), 5, 3, 2),
+                                               ((4, 4, 4, 4), (1, 1, 1, 1), 6, 4, 2)])
+def test_coarse_operator_shapes(qmg, dims, block, k, r, ns):
+    """Galerkin blocks against the oracle for tile shapes 3x3/4x4, odd k, unit blocks."""
+    banner(f"coarse build {dims} block={block} k={k}")
+    U = fields.random_gauge(dims, 0.5, 41)
+    phi = fields.gaussian_test_vectors(dims, ns * r, 41)
+    lat = qmg.Lattice(dims, -0.1, 2.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, ns * r, r, k, n_setup_iter=0, inner="f64",
+                                        test_vectors=to_gpu(phi))
+    P = to_np(mg.prolongator()[0])
+    Y = to_np(mg.coarse_blocks())
+    Yo = coarse.build_coarse(U, P, -0.1, 2.0, -1, dims, block)
+    assert rel(Y, Yo) < 1e-13
+    mg.close()
