@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <memory>
 #include <new>
+#include <type_traits>
 
 #include "mg.hpp"
 #include "timing.hpp"
@@ -84,25 +85,39 @@ struct CoarseOp : LinOp {
   qmg_prec prec() const override { return p; }
 };
 
-template <class S>
+// Two-level K-cycle with storage precision S; r and z are in the outer solver's type F.
+template <class F, class S>
 struct KCycle : Precond {
   const HierarchyDev& h;
   WilsonOp& D;
   CoarseOp& Dc;
   const void* P;
   Gmres<S> gc, gf;
-  DevBuf rc, ec;
+  DevBuf rc, ec, rS, zS;
   long coarse_iters = 0, smooth_iters = 0, cycles = 0;
   KCycle(const HierarchyDev& h_, WilsonOp& D_, CoarseOp& Dc_, const void* P_) : h(h_), D(D_), Dc(Dc_), P(P_) {}
   void apply(const void* r, void* z, int nrhs, hipStream_t st) override {
     const size_t nc = size_t(nrhs) * 2 * h.k * h.blk.d;
+    const size_t nf = size_t(nrhs) * 12 * h.g.V;
     rc.ensure(nc * sizeof(S));
     ec.ensure(nc * sizeof(S));
-    const qmg_prec p = StoreTraits<S>::prec;
-    launch_restrict(p, h, P, r, rc.p, nrhs, st);
+    constexpr qmg_prec p = StoreTraits<S>::prec;
+    constexpr qmg_prec pf = StoreTraits<F>::prec;
+    constexpr bool same = std::is_same<F, S>::value;
+    const void* r_s = r;
+    void* z_s = z;
+    if (!same) {
+      rS.ensure(nf * sizeof(S));
+      zS.ensure(nf * sizeof(S));
+      launch_convert(r, pf, rS.p, p, nf, st);
+      r_s = rS.p;
+      z_s = zS.p;
+    }
+    launch_restrict(p, h, P, r_s, rc.p, nrhs, st);
     auto rcs = gc.solve(Dc, rc.p, ec.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st);
-    launch_prolong(p, h, P, ec.p, z, nrhs, st);
-    auto rfs = gf.solve(D, r, z, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    launch_prolong(p, h, P, ec.p, z_s, nrhs, st);
+    auto rfs = gf.solve(D, r_s, z_s, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    if (!same) launch_convert(z_s, p, z, pf, nf, st);
     coarse_iters += rcs.iters;
     smooth_iters += rfs.iters;
     ++cycles;
@@ -235,7 +250,7 @@ void run_setup(qmg_mg* mg, const qmg_mg_params* p, hipStream_t st) {
   const int r = p->batch, ns = p->n_test / p->batch;
   constexpr qmg_prec P = StoreTraits<S>::prec;
   const auto t0 = Clock::now();
-  const void* Uin = (P == QMG_F64) ? h.U64.p : h.Uin.p;
+  const void* Uin = (P == QMG_F64) ? h.U64.p : (h.inner == QMG_F32 ? h.Uin.p : h.U32.p);
   DevBuf phi(size_t(r) * 12 * g.V * sizeof(double2));
   DevBuf blocks(size_t(2) * h.blk.d * r * h.blk.N * sizeof(double2));
   DevBuf b_in, x_in, tmp64;
@@ -295,7 +310,7 @@ void solve_f64(const HierarchyDev& h, const void* b64, void* x64, int nrhs, doub
                hipStream_t st, SolveStats& ss, bool& converged) {
   WilsonOp D(h.g, QMG_F64, h.U64.p);
   CoarseOp Dc(h, QMG_F64, h.Y64.p);
-  KCycle<double2> K(h, D, Dc, h.P64.p);
+  KCycle<double2, double2> K(h, D, Dc, h.P64.p);
   Fgcr<double2> f;
   auto res = f.solve(D, K, b64, x64, x_zero, nrhs, 16, max_iter, tol, st);
   ss.outer += res.iters;
@@ -305,30 +320,32 @@ void solve_f64(const HierarchyDev& h, const void* b64, void* x64, int nrhs, doub
   converged = res.converged;
 }
 
-// FP64 defect correction around an inner solve in precision S
+// FP64 defect correction around an FP32 flexible GCR whose K-cycle stores in precision S
 template <class S>
 void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, double tol, int max_outer,
                  hipStream_t st, SolveStats& ss, bool& converged) {
   constexpr qmg_prec P = StoreTraits<S>::prec;
+  using F = float2;
   const size_t len = size_t(12) * h.g.V, n = len * nrhs;
   WilsonOp D64(h.g, QMG_F64, h.U64.p);
+  WilsonOp D32(h.g, QMG_F32, P == QMG_F32 ? h.Uin.p : h.U32.p);
   WilsonOp Din(h.g, P, h.Uin.p);
   CoarseOp Dc(h, P, h.Yin.p);
-  KCycle<S> K(h, Din, Dc, h.Pin.p);
-  Fgcr<S> f;
-  DevBuf r64(n * sizeof(double2)), rin(n * sizeof(S)), ein(n * sizeof(S)), nrm(nrhs * sizeof(double)),
+  KCycle<F, S> K(h, Din, Dc, h.Pin.p);
+  Fgcr<F> f;
+  DevBuf r64(n * sizeof(double2)), rin(n * sizeof(F)), ein(n * sizeof(F)), nrm(nrhs * sizeof(double)),
       bn(nrhs * sizeof(double));
   RedWork rw;
   std::vector<double> hb(nrhs), hr(nrhs);
   Blas<double2>::norm2(b64, len, nrhs, bn.as<double>(), rw, st);
   QMG_HIP(hipMemcpyAsync(hb.data(), bn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
   QMG_HIP(hipStreamSynchronize(st));
-  const double inner_tol = (P == QMG_F32) ? 1e-5 : 1e-2;
+  const double inner_tol = (P == QMG_F32) ? 1e-5 : 1e-2;  // BF16/FP16 K-cycle limits the inner solve
   std::vector<double> hist;
   converged = false;
   struct Acc {
     SolveStats& ss;
-    KCycle<S>& K;
+    KCycle<F, S>& K;
     ~Acc() {
       ss.coarse += K.coarse_iters;
       ss.smooth += K.smooth_iters;
@@ -361,12 +378,12 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
     }
     // r / |r| in the inner precision
     Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 0, len, nrhs, st);
-    launch_convert(r64.p, QMG_F64, rin.p, P, n, st);
-    auto res = f.solve(Din, K, rin.p, ein.p, true, nrhs, 16, int(max_outer - ss.outer), inner_tol, st);
+    launch_convert(r64.p, QMG_F64, rin.p, QMG_F32, n, st);
+    auto res = f.solve(D32, K, rin.p, ein.p, true, nrhs, 16, int(max_outer - ss.outer), inner_tol, st);
     ss.outer += res.iters;
     ss.refinements += 1;
     // x += |r| e
-    launch_convert(ein.p, P, r64.p, QMG_F64, n, st);
+    launch_convert(ein.p, QMG_F32, r64.p, QMG_F64, n, st);
     Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 1, len, nrhs, st);
     Blas<double2>::axpby(1.0, r64.p, 1.0, x64, n, st);
   }
@@ -492,8 +509,7 @@ qmg_status qmg_mg_setup_stream_chiral_svd(const qmg_lattice* lat, const void* U,
               "iteration counts must be non-negative");
     QMG_CHECK(p->coarse_tol > 0 && p->coarse_tol < 1, QMG_EINVAL, "coarse_tol must be in (0, 1)");
     check_prec(p->inner_prec);
-    QMG_CHECK(p->inner_prec == QMG_F64 || p->inner_prec == QMG_F32, QMG_EDTYPE,
-              "inner precision must be F64 or F32");
+
     std::unique_ptr<qmg_mg> mg(new qmg_mg());
     HierarchyDev& h = mg->h;
     h.g = g;
@@ -512,6 +528,11 @@ qmg_status qmg_mg_setup_stream_chiral_svd(const qmg_lattice* lat, const void* U,
       h.Uin.alloc(size_t(36) * g.V * prec_bytes(h.inner));
       launch_pack_gauge(U, h.Uin.p, h.inner, g.V, stream);
     }
+    if (h.inner == QMG_BF16 || h.inner == QMG_F16) {
+      h.U32.alloc(size_t(36) * g.V * sizeof(float2));
+      launch_pack_gauge(U, h.U32.p, QMG_F32, g.V, stream);
+    }
+    // test-vector smoothing in FP64 for an FP64 hierarchy, else in FP32
     if (h.inner == QMG_F64) run_setup<double2>(mg.get(), p, stream);
     else run_setup<float2>(mg.get(), p, stream);
     *out = mg.release();
@@ -599,7 +620,9 @@ qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, 
       QMG_CHECK(std::isfinite(bn), QMG_ENONFINITE, "right-hand side has non-finite entries");
     }
     if (h.inner == QMG_F64) solve_f64(h, b64.p, x64.p, nrhs, tol, max_outer, false, stream, ss, converged);
-    else solve_mixed<float2>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
+    else if (h.inner == QMG_F32) solve_mixed<float2>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
+    else if (h.inner == QMG_BF16) solve_mixed<cbf16>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
+    else solve_mixed<chalf>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
     // true residual in FP64
     WilsonOp D(h.g, QMG_F64, h.U64.p);
     D.apply(x64.p, r64.p, nrhs, stream);

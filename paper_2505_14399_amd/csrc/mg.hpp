@@ -17,6 +17,7 @@ struct HierarchyDev {
   qmg_prec inner = QMG_F64;  // inner storage precision
 
   DevBuf U64, Uin;           // native gauge, FP64 and inner precision
+  DevBuf U32;                // FP32 gauge when the inner precision is below FP32 (outer GCR, setup)
   DevBuf bsite, cnb;         // tables
   DevBuf blists;             // [8][nd]: in-block sites per hop direction, intra-block hops first
   DevBuf P64, Pin;           // [d][2][k][N]

@@ -1,0 +1,80 @@
+"""Gradients of Re<eta, D^-1 b> through the MG solve: adjoint + force kernel vs the oracle and
+vs central finite differences of GPU solves."""
+import numpy as np
+import pytest
+import torch
+
+import fields
+from oracle import wilson, force
+from tests._util import to_gpu, to_np, rel, banner
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(qmg, dims, mass, xi, seed, block=(2, 2, 2, 2), k=8):
+    U = fields.random_gauge(dims, 0.5, seed)
+    lat = qmg.Lattice(dims, mass, xi, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 2 * k, k // 2 if k >= 4 else k, k,
+                                        n_setup_iter=8, inner="f64", seed=seed)
+    return U, lat, mg
+
+
+def test_gradients_vs_oracle(qmg):
+    from paper_2505_14399_amd.autograd import solve
+    dims, mass, xi = (4, 4, 4, 4), 0.03, 1.0
+    banner("autograd gradients vs oracle")
+    U, lat, mg = _setup(qmg, dims, mass, xi, 51)
+    b = fields.gaussian_spinor(dims, 1, 51)
+    eta = fields.gaussian_spinor(dims, 1, 51, stream=fields.ETA_STREAM)
+    Ug = to_gpu(U).requires_grad_(True)
+    bg = to_gpu(b).requires_grad_(True)
+    x = solve(Ug, bg, mg, 1e-13)
+    L = torch.real(torch.sum(torch.conj(to_gpu(eta)) * x))
+    L.backward()
+    Dm = wilson.dense_wilson(U, mass, xi, -1, dims)
+    xo = np.linalg.solve(Dm, b[0].ravel()).reshape(b[0].shape)
+    lo = np.linalg.solve(np.conj(Dm.T), eta[0].ravel()).reshape(b[0].shape)
+    assert rel(to_np(bg.grad)[0], lo) < 1e-9
+    go = force.link_force(xo, lo, xi, -1, dims)
+    err = rel(to_np(Ug.grad), go)
+    print(f"[grad] link gradient vs oracle: {err:.2e}")
+    assert err < 1e-9
+
+
+def test_gradients_finite_differences(qmg):
+    """Directional derivative along a random perturbation supported on a 4^4 sublattice that
+    straddles the antiperiodic time boundary, central differences of GPU solves."""
+    from paper_2505_14399_amd.autograd import solve
+    dims, mass, xi = (8, 8, 4, 8), 0.03, 1.0
+    banner("autograd gradients vs central differences")
+    U = fields.random_gauge(dims, 0.5, 61)
+    lat = qmg.Lattice(dims, mass, xi, -1)
+    b = fields.gaussian_spinor(dims, 1, 61)
+    eta = fields.gaussian_spinor(dims, 1, 61, stream=fields.ETA_STREAM)
+    kw = dict(block=(4, 4, 4, 4), n_test=16, batch=8, rank=8, n_setup_iter=8, inner="f64", seed=61)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), **kw)
+    Ug = to_gpu(U).requires_grad_(True)
+    x = solve(Ug, to_gpu(b), mg, 1e-13)
+    L = torch.real(torch.sum(torch.conj(to_gpu(eta)) * x))
+    L.backward()
+    g = to_np(Ug.grad)
+    # perturbation on x,y,z in [0,4), t in {Lt-2, Lt-1, 0, 1}
+    from oracle import geometry as geo
+    c = geo.coords(dims)
+    mask = (c[:, 0] < 4) & (c[:, 1] < 4) & (c[:, 2] < 4) & np.isin(c[:, 3], [dims[3] - 2, dims[3] - 1, 0, 1])
+    rng = np.random.default_rng(0)
+    for trial in range(3):
+        Dl = np.zeros_like(U)
+        Dl[:, mask] = rng.standard_normal((4, mask.sum(), 3, 3)) + 1j * rng.standard_normal((4, mask.sum(), 3, 3))
+        h = 1e-4
+        Ls = []
+        for sgn in (1, -1):
+            Up = U + sgn * h * Dl
+            mgp = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(Up), **kw)
+            xp, _ = qmg.mg_solve(mgp, to_gpu(b), tol=1e-13)
+            Ls.append(float(np.real(np.vdot(eta.ravel(), to_np(xp).ravel()))))
+            mgp.close()
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+        an = float(np.real(np.vdot(g.ravel(), Dl.ravel())))
+        print(f"[grad] FD {fd:.10e} analytic {an:.10e} rel {abs(fd - an) / abs(an):.2e}")
+        assert abs(fd - an) <= 1e-6 * abs(an)

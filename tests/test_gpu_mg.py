@@ -219,3 +219,30 @@ def test_coarse_operator_shapes(qmg, dims, block, k, r, ns):
     Yo = coarse.build_coarse(U, P, -0.1, 2.0, -1, dims, block)
     assert rel(Y, Yo) < 1e-13
     mg.close()
+
+
+@pytest.mark.parametrize("inner", ["bf16", "f16"])
+def test_solve_half_storage(qmg, inner):
+    """K-cycle stored in BF16/FP16 (FP32 arithmetic) inside FP32 GCR and FP64 refinement."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    banner(f"solve {inner} inner {dims}")
+    U = fields.random_gauge(dims, 0.4, 23)
+    lat = qmg.Lattice(dims, 0.02, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 24, 8, 12, n_setup_iter=16, inner=inner, seed=3)
+    b = fields.gaussian_spinor(dims, 1, 24)
+    x, info = qmg.mg_solve(mg, to_gpu(b), tol=1e-10)
+    print(f"[solve] {inner} info {info}")
+    r = b - wilson.apply_wilson(U, to_np(x), 0.02, 1.0, -1, dims)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 2e-10
+
+
+def test_solve_point_sources_multi_rhs(qmg, c1):
+    """12 spin-colour point sources solved together; each against the dense solve."""
+    w, U, lat, mg, olat, oh = c1
+    banner("solve 12 point sources")
+    b = fields.point_sources(w["dims"])
+    x, info = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+    Dm = wilson.dense_wilson(U, w["mass"], w["xi"], w["bc_t"], w["dims"])
+    X = np.linalg.solve(Dm, b.reshape(12, -1).T).T.reshape(b.shape)
+    assert max(i["true_rel_res"] for i in info) <= 1e-12
+    assert rel(to_np(x), X) < 1e-8
