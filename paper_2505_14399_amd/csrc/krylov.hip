@@ -553,15 +553,19 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
   // FP64 keeps two Gram-Schmidt passes (parity with the FP64 reference to ~1e-12); lower
   // storage precisions use one pass with the Pythagorean norm, which halves the basis traffic
   constexpr bool kCgs2 = std::is_same<S, double2>::value;
+  // with a tolerance, Arnoldi steps are issued in batches of kBatch before the host reads the
+  // Hessenberg columns; steps past the converged one are discarded
+  constexpr int kBatch = 4;
   const size_t len = A.len();
   ensure(len, nrhs, m);
   S* V = V_.as<S>();
   const size_t vs = size_t(nrhs) * len;  // stride between basis vectors
+  // per-column device staging: h1 [(m+1) nrhs], h2 [(m+1) nrhs], nrm [nrhs] (as double2 slots)
+  const size_t per_col = size_t(2 * (m + 1) + 1) * nrhs;
+  cols_.ensure(size_t(m) * per_col * sizeof(double2));
+  double2* colsd = cols_.as<double2>();
   double* nrm = nrm_.as<double>();
-  double2* h1 = h1_.as<double2>();
-  double2* h2 = h2_.as<double2>();
   PinnedBuf& hb = hb_;
-  const size_t per_col = size_t(2 * (m + 1) + 1) * nrhs;  // doubles2 per column snapshot
   hb.ensure((size_t(m) * per_col + 2 * nrhs + size_t(m + 1) * nrhs) * sizeof(double2));
   double2* hcols = hb.as<double2>();
   double* hnrm0 = reinterpret_cast<double*>(hcols + size_t(m) * per_col);
@@ -581,6 +585,24 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
   std::vector<zc> y, hcol(m + 2);
   std::vector<double2> yh(size_t(m) * nrhs);
   bool all_conv = false;
+  auto process = [&](int j) {  // host Givens step on column j; true if every rhs converged
+    const double2* snap = hcols + size_t(j) * per_col;
+    bool conv = true;
+    for (int r = 0; r < nrhs; ++r) {
+      for (int i = 0; i <= j; ++i) {
+        const double2 a = snap[size_t(i) * nrhs + r];
+        double2 c = make_double2(0.0, 0.0);
+        if (kCgs2) c = snap[size_t(m + 1 + i) * nrhs + r];
+        hcol[i] = zc(a.x + c.x, a.y + c.y);
+      }
+      hcol[j + 1] = std::sqrt(reinterpret_cast<const double*>(snap + size_t(2 * (m + 1)) * nrhs)[r]);
+      const double est = gs[r].step(j, hcol.data());
+      QMG_CHECK(std::isfinite(est), QMG_ENONFINITE, "GMRES: non-finite Hessenberg entry");
+      res.rel_est[r] = bn[r] > 0 ? est / bn[r] : 0.0;
+      if (!(tol > 0 && est <= tol * bn[r])) conv = false;
+    }
+    return conv;
+  };
   while (it < max_iter) {
     if (first && x_zero) {
       Blas<S>::copy(b, V, vs, st);
@@ -603,68 +625,45 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
     Blas<S>::scale_dev(V, nrm, 0, len, nrhs, st);
     const int mc = std::min(m, max_iter - it);
     for (int r = 0; r < nrhs; ++r) gs[r].init(mc, std::sqrt(hnrm0[r]));
-    int jdone = 0;
+    int jdone = 0, processed = 0;
     for (int j = 0; j < mc; ++j) {
       S* vj = V + size_t(j) * vs;
       S* vn = V + size_t(j + 1) * vs;
+      double2* col = colsd + size_t(j) * per_col;
+      double2* h1 = col;
+      double2* h2 = col + size_t(m + 1) * nrhs;
+      double* cn = reinterpret_cast<double*>(col + size_t(2 * (m + 1)) * nrhs);
       A.apply(vj, vn, nrhs, st);
       if (kCgs2) {
         // CGS2: h1 = V^dag w ; w -= V h1 and h2 = V^dag w ; w -= V h2 and |w|^2 ; w /= |w|
         Blas<S>::mdot(V, vs, j + 1, vn, len, nrhs, h1, rw_, st);
         Blas<S>::axpy_mdot(V, vs, j + 1, h1, -1.0, vn, len, nrhs, h2, rw_, st);
-        Blas<S>::axpy_norm(V, vs, j + 1, h2, -1.0, vn, len, nrhs, nrm, rw_, st);
-        Blas<S>::scale_dev(vn, nrm, 0, len, nrhs, st);
+        Blas<S>::axpy_norm(V, vs, j + 1, h2, -1.0, vn, len, nrhs, cn, rw_, st);
+        Blas<S>::scale_dev(vn, cn, 0, len, nrhs, st);
       } else {
         // one classical Gram-Schmidt pass with the norm from Pythagoras, scaling fused
-        Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, nrm, rw_, st);
+        Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, cn, rw_, st);
       }
-      double2* snap = hcols + size_t(j) * per_col;
-      QMG_HIP(hipMemcpyAsync(snap, h1, size_t(j + 1) * nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
-      if (kCgs2)
-        QMG_HIP(hipMemcpyAsync(snap + size_t(m + 1) * nrhs, h2, size_t(j + 1) * nrhs * sizeof(double2),
-                               hipMemcpyDeviceToHost, st));
-      else
-        std::memset(snap + size_t(m + 1) * nrhs, 0, size_t(j + 1) * nrhs * sizeof(double2));
-      QMG_HIP(hipMemcpyAsync(snap + size_t(2 * (m + 1)) * nrhs, nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost,
+      QMG_HIP(hipMemcpyAsync(hcols + size_t(j) * per_col, col, per_col * sizeof(double2), hipMemcpyDeviceToHost,
                              st));
-      ++it;
       jdone = j + 1;
-      if (tol > 0) {
+      if (tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) {
         QMG_HIP(hipStreamSynchronize(st));
-        bool conv = true;
-        for (int r = 0; r < nrhs; ++r) {
-          for (int i = 0; i <= j; ++i) {
-            const double2 a = snap[size_t(i) * nrhs + r], c = snap[size_t(m + 1 + i) * nrhs + r];
-            hcol[i] = zc(a.x + c.x, a.y + c.y);
+        for (; processed <= j; ++processed) {
+          if (process(processed)) {
+            jdone = processed + 1;
+            all_conv = true;
+            break;
           }
-          hcol[j + 1] = std::sqrt(reinterpret_cast<const double*>(snap + size_t(2 * (m + 1)) * nrhs)[r]);
-          const double est = gs[r].step(j, hcol.data());
-          QMG_CHECK(std::isfinite(est), QMG_ENONFINITE, "GMRES: non-finite Hessenberg entry");
-          res.rel_est[r] = bn[r] > 0 ? est / bn[r] : 0.0;
-          if (est > tol * bn[r]) conv = false;
         }
-        if (conv) {
-          all_conv = true;
-          break;
-        }
+        if (all_conv) break;
       }
     }
     if (tol <= 0) {
       QMG_HIP(hipStreamSynchronize(st));
-      for (int j = 0; j < jdone; ++j) {
-        const double2* snap = hcols + size_t(j) * per_col;
-        for (int r = 0; r < nrhs; ++r) {
-          for (int i = 0; i <= j; ++i) {
-            const double2 a = snap[size_t(i) * nrhs + r], c = snap[size_t(m + 1 + i) * nrhs + r];
-            hcol[i] = zc(a.x + c.x, a.y + c.y);
-          }
-          hcol[j + 1] = std::sqrt(reinterpret_cast<const double*>(snap + size_t(2 * (m + 1)) * nrhs)[r]);
-          const double est = gs[r].step(j, hcol.data());
-          QMG_CHECK(std::isfinite(est), QMG_ENONFINITE, "GMRES: non-finite Hessenberg entry");
-          res.rel_est[r] = bn[r] > 0 ? est / bn[r] : 0.0;
-        }
-      }
+      for (int j = 0; j < jdone; ++j) process(j);
     }
+    it += jdone;
     // x += sum_i y_i V_i
     for (int r = 0; r < nrhs; ++r) {
       gs[r].solve(y);

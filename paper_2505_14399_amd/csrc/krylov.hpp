@@ -88,7 +88,7 @@ class Gmres {
 
  private:
   void ensure(size_t len, int nrhs, int restart);
-  DevBuf V_, H_, h1_, h2_, nrm_, y_, r_;
+  DevBuf V_, H_, h1_, h2_, nrm_, y_, r_, cols_;
   PinnedBuf hb_;
   RedWork rw_;
   size_t len_ = 0;

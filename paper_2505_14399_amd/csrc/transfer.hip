@@ -64,25 +64,49 @@ __global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const
   }
 }
 
-// coarse apply: one thread per (aggregate, row); Y blocks column-major so that the threads of
-// one aggregate read consecutive entries
-template <class S>
-__global__ __launch_bounds__(256) void k_coarse_apply(const S* __restrict__ Y, const S* __restrict__ in,
-                                                      S* __restrict__ out, const int* __restrict__ cnb, int d, int m) {
+// coarse apply: one workgroup per (aggregate, group of NR right-hand sides).  The nine input
+// vectors v(j + dir) are staged in LDS; thread (slot, row) forms the row of Y_slot(j) times
+// v(j + slot) for NR right-hand sides (each Y entry read once, coalesced over rows because
+// the blocks are stored column-major); the nine partial rows are summed in LDS.
+template <class S, int NR>
+__global__ __launch_bounds__(1024) void k_coarse_apply(const S* __restrict__ Y, const S* __restrict__ in,
+                                                       S* __restrict__ out, const int* __restrict__ cnb, int d, int m,
+                                                       int nrhs) {
   using C = ctype<S>;
-  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
-  const int rhs = blockIdx.y;
-  if (g >= size_t(d) * m) return;
-  const int j = int(g / m), row = int(g - size_t(j) * m);
-  const S* vin = in + size_t(rhs) * d * m;
-  cplx<C> acc = {C(0), C(0)};
-  for (int slot = 0; slot < 9; ++slot) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<C>* vin = reinterpret_cast<cplx<C>*>(smem_raw);  // [NR][9][m]
+  cplx<C>* part = vin + size_t(NR) * 9 * m;              // [NR][9][m]
+  const int j = blockIdx.x, rhs0 = blockIdx.y * NR;
+  const int nr = min(NR, nrhs - rhs0);
+  for (int t = threadIdx.x; t < NR * 9 * m; t += blockDim.x) {
+    const int r = t / (9 * m), rem = t - r * 9 * m, slot = rem / m, col = rem - slot * m;
     const int nbj = slot == 0 ? j : cnb[j * 8 + slot - 1];
-    const S* Yb = Y + (size_t(j) * 9 + slot) * m * m + row;
-    const S* v = vin + size_t(nbj) * m;
-    for (int col = 0; col < m; ++col) acc += ldc(Yb, size_t(col) * m) * ldc(v, col);
+    vin[t] = r < nr ? ldc(in, (size_t(rhs0 + r) * d + nbj) * m + col) : cplx<C>{C(0), C(0)};
   }
-  stc(out, size_t(rhs) * d * m + g, acc);
+  __syncthreads();
+  for (int t = threadIdx.x; t < 9 * m; t += blockDim.x) {
+    const int slot = t / m, row = t - slot * m;
+    const S* Yb = Y + (size_t(j) * 9 + slot) * m * m + row;
+    cplx<C> acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = {C(0), C(0)};
+#pragma unroll 4
+    for (int col = 0; col < m; ++col) {
+      const cplx<C> y = ldc(Yb, size_t(col) * m);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] += y * vin[(r * 9 + slot) * m + col];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) part[(r * 9 + slot) * m + row] = acc[r];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nr * m; t += blockDim.x) {
+    const int r = t / m, row = t - r * m;
+    cplx<C> s = {C(0), C(0)};
+#pragma unroll
+    for (int slot = 0; slot < 9; ++slot) s += part[(r * 9 + slot) * m + row];
+    stc(out, (size_t(rhs0 + r) * d + j) * m + row, s);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -516,8 +540,15 @@ void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, co
                  8.0 * 9.0 * m * m * h.blk.d * nrhs);
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
-    dim3 grid(cdiv(size_t(h.blk.d) * m, 256), nrhs);
-    k_coarse_apply<S><<<grid, 256, 0, st>>>((const S*)Y, (const S*)in, (S*)out, h.cnb.as<int>(), h.blk.d, m);
+    const int threads = int(std::min<size_t>(1024, ((size_t(9) * m + 63) / 64) * 64));
+    auto go = [&](auto kern, int NR) {
+      const size_t lds = size_t(2) * NR * 9 * m * sizeof(cplx<ctype<S>>);
+      kern<<<dim3(h.blk.d, (nrhs + NR - 1) / NR), threads, lds, st>>>((const S*)Y, (const S*)in, (S*)out,
+                                                                       h.cnb.as<int>(), h.blk.d, m, nrhs);
+    };
+    if (nrhs >= 4) go(k_coarse_apply<S, 4>, 4);
+    else if (nrhs == 2) go(k_coarse_apply<S, 2>, 2);
+    else go(k_coarse_apply<S, 1>, 1);
   });
   QMG_LAUNCH_CHECK();
 }
