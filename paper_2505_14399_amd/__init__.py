@@ -76,6 +76,10 @@ SIGNATURES = {
     "qmg_mg_setup_times": [_P, _P],
     "qmg_timing_enable": [_I],
     "qmg_timing_query": [ctypes.c_char_p, _P, _P, _P, _P],
+    "qmg_autotune": [_I],
+    "qmg_set_dslash_variant": [_I],
+    "qmg_tune_save": [ctypes.c_char_p],
+    "qmg_tune_load": [ctypes.c_char_p],
     "qmg_mg_destroy": [_P],
     "qmg_last_error": [],
     "qmg_version": [],
@@ -385,6 +389,24 @@ def timing_query(family):
     _check(load_library().qmg_timing_query(family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
                                            ctypes.byref(fl)))
     return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+
+
+def autotune(on=True):
+    """Enable (or disable) per-shape timing of kernel launch variants on first use."""
+    _check(load_library().qmg_autotune(1 if on else 0))
+
+
+def set_dslash_variant(v=0):
+    """Force a native dslash launch variant (1, 2, 4, 8) or restore the automatic choice (0)."""
+    _check(load_library().qmg_set_dslash_variant(int(v)))
+
+
+def tune_save(path):
+    _check(load_library().qmg_tune_save(os.fspath(path).encode()))
+
+
+def tune_load(path):
+    _check(load_library().qmg_tune_load(os.fspath(path).encode()))
 
 
 def version():

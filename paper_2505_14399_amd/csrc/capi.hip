@@ -9,6 +9,7 @@
 
 #include "mg.hpp"
 #include "timing.hpp"
+#include "tune.hpp"
 
 struct qmg_mg {
   qmg::HierarchyDev h;
@@ -766,6 +767,31 @@ qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total
     timing_query(family, launches, total_ms, &b, &f);
     if (algo_bytes) *algo_bytes = b;
     if (algo_flops) *algo_flops = f;
+  });
+}
+
+qmg_status qmg_autotune(int32_t on) {
+  return guard([&] { tune_enable(on != 0); });
+}
+
+qmg_status qmg_set_dslash_variant(int32_t v) {
+  return guard([&] {
+    QMG_CHECK(v == 0 || v == 1 || v == 2 || v == 4 || v == 8, QMG_EINVAL, "dslash variant must be 0, 1, 2, 4 or 8");
+    set_dslash_variant(v);
+  });
+}
+
+qmg_status qmg_tune_save(const char* path) {
+  return guard([&] {
+    check_ptr(path, "path");
+    QMG_CHECK(tune_save(path) == 0, QMG_EINVAL, "cannot write tuning cache %s", path);
+  });
+}
+
+qmg_status qmg_tune_load(const char* path) {
+  return guard([&] {
+    check_ptr(path, "path");
+    QMG_CHECK(tune_load(path) >= 0, QMG_EINVAL, "cannot read tuning cache %s", path);
   });
 }
 

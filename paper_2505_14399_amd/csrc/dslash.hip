@@ -12,12 +12,22 @@
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; the tile index is
 // remapped so that each XCD walks a contiguous range of sites, keeping the +-t neighbour
 // slices of a tile inside that XCD's L2.
+#include <string>
+
 #include "timing.hpp"
+#include "tune.hpp"
 
 namespace qmg {
 
+namespace {
+int g_variant = 0;  // forced native-layout launch variant (0: heuristic or tuned)
+}
+
+void set_dslash_variant(int v) { g_variant = v; }
+
 DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical) {
   DslashArgs a{};
+  a.tchunk = g_variant;
   for (int m = 0; m < 4; ++m) a.L[m] = g.L[m];
   a.V = g.V;
   a.bc_t = g.bc_t;
@@ -330,24 +340,43 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     launch_t<S, true, 1>(U, in, out, a, st);
     return;
   }
-  // t-walking kernel: chunk length chosen so that the grid still has >= 4 workgroups per CU
+  // Launch variants for the native layout: 1 = one site per thread, 2/4/8 = t-walking with
+  // that many sites per thread along t.  Default heuristic: the longest t-chunk that still
+  // gives >= 1024 workgroups.  With the autotuner enabled every valid variant is timed on first
+  // use of (precision, extents, nrhs, adjoint) and the fastest is kept.
   const int Vs = a.L[0] * a.L[1] * a.L[2];
   const long wg1 = long((Vs + kBlock - 1) / kBlock) * a.nrhs;  // workgroups per t-slice
   const int Lt = a.L[3];
+  auto run = [&](int v) {
+    switch (v) {
+      case 8: launch_tw<S, 8>(U, in, out, a, st); break;
+      case 4: launch_tw<S, 4>(U, in, out, a, st); break;
+      case 2: launch_tw<S, 2>(U, in, out, a, st); break;
+      default: launch_t<S, false, 1>(U, in, out, a, st); break;
+    }
+  };
+  if (a.tchunk > 0 && (a.tchunk == 1 || Lt % a.tchunk == 0)) {
+    run(a.tchunk);
+    return;
+  }
   auto fits = [&](int tch) { return Lt % tch == 0 && wg1 * (Lt / tch) >= 1024; };
-  if (a.tchunk > 0 && Lt % a.tchunk == 0) {
-    switch (a.tchunk) {
-      case 1: launch_t<S, false, 1>(U, in, out, a, st); return;
-      case 2: launch_tw<S, 2>(U, in, out, a, st); return;
-      case 4: launch_tw<S, 4>(U, in, out, a, st); return;
-      case 8: launch_tw<S, 8>(U, in, out, a, st); return;
-      default: break;
+  int choice = fits(8) ? 8 : fits(4) ? 4 : fits(2) ? 2 : 1;
+  if (tune_enabled()) {
+    const std::string key = "dslash/" + std::to_string(int(StoreTraits<S>::prec)) + "/" + std::to_string(a.L[0]) +
+                            "x" + std::to_string(a.L[1]) + "x" + std::to_string(a.L[2]) + "x" +
+                            std::to_string(a.L[3]) + "/" + std::to_string(a.nrhs) + "/" + std::to_string(a.dagger);
+    const int cached = tune_lookup(key);
+    if (cached > 0) {
+      choice = cached;
+    } else {
+      int cand[4], n = 0;
+      cand[n++] = 1;
+      for (int tch : {2, 4, 8})
+        if (Lt % tch == 0) cand[n++] = tch;
+      choice = tune_measure(key, cand, n, st, run);
     }
   }
-  if (fits(8)) launch_tw<S, 8>(U, in, out, a, st);
-  else if (fits(4)) launch_tw<S, 4>(U, in, out, a, st);
-  else if (fits(2)) launch_tw<S, 2>(U, in, out, a, st);
-  else launch_t<S, false, 1>(U, in, out, a, st);  // small lattices: one site per thread
+  run(choice);
 }
 
 }  // namespace

@@ -251,6 +251,7 @@ struct DslashArgs {
   int tchunk;     // native kernel: sites per thread along t (0: chosen by the launcher)
 };
 DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical);
+void set_dslash_variant(int v);
 
 // out = D in (or D^dag) ; U in the same storage type and layout as the spinors
 void launch_dslash(qmg_prec prec, const void* U, const void* in, void* out, const DslashArgs& a,

@@ -86,3 +86,46 @@ def test_dslash_full_size_sampled(qmg, dims, nrhs):
     for r in (0, nrhs - 1):
         ref = wilson.apply_wilson_sites(U, psi[r], sites, -0.2, xi, -1, dims)
         assert rel(got[r], ref) < 1e-6
+
+
+@pytest.mark.parametrize("variant", [1, 2, 4, 8])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 1e-6), ("bf16", 1e-2)])
+def test_dslash_every_launch_variant(qmg, variant, prec, tol):
+    """Each native launch form (site-parallel, t-walking with 2/4/8 sites per thread)."""
+    dims, nrhs = (6, 4, 4, 16), 3
+    banner(f"dslash variant {variant} {prec}")
+    U = fields.random_gauge(dims, 0.6, 9)
+    psi = fields.gaussian_spinor(dims, nrhs, 10)
+    lat = qmg.Lattice(dims, -0.1, 2.5, -1)
+    Un = qmg.pack_gauge(lat, to_gpu(U), prec)
+    pn = qmg.pack_spinor(lat, to_gpu(psi), prec)
+    try:
+        qmg.set_dslash_variant(variant)
+        for dag in (False, True):
+            f = qmg.wilson_apply_adj if dag else qmg.wilson_apply
+            got = to_np(qmg.unpack_spinor(lat, f(lat, Un, pn, layout="native"), prec))
+            ref = wilson.apply_wilson(U, psi, -0.1, 2.5, -1, dims, dagger=dag)
+            assert rel(got, ref) < tol
+    finally:
+        qmg.set_dslash_variant(0)
+
+
+def test_autotuner_cache_roundtrip(qmg, tmp_path):
+    dims = (8, 8, 8, 16)
+    banner("autotuner")
+    U = fields.random_gauge(dims, 0.6, 11)
+    psi = fields.gaussian_spinor(dims, 2, 12)
+    lat = qmg.Lattice(dims, -0.1, 1.0, -1)
+    Un = qmg.pack_gauge(lat, to_gpu(U), "f32")
+    pn = qmg.pack_spinor(lat, to_gpu(psi), "f32")
+    try:
+        qmg.autotune(True)
+        got = to_np(qmg.unpack_spinor(lat, qmg.wilson_apply(lat, Un, pn, layout="native"), "f32"))
+        assert rel(got, wilson.apply_wilson(U, psi, -0.1, 1.0, -1, dims)) < 1e-6
+        path = tmp_path / "tune.json"
+        qmg.tune_save(path)
+        text = path.read_text()
+        assert "dslash/1/8x8x8x16/2/0" in text
+        qmg.tune_load(path)
+    finally:
+        qmg.autotune(False)
