@@ -193,14 +193,15 @@ qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total
                             double* algo_flops);
 
 /* Autotuner.  qmg_autotune(1) (or QMG_TUNE=1 in the environment) makes every kernel with
- * launch variants (the native-layout dslash: one site per thread or 2/4/8 sites per thread
- * along t) time each variant with HIP events on its first call for a given (precision,
+ * launch variants (the native-layout dslash: one site per thread, 2/4/8 sites per thread
+ * along t, or four threads per site) time each variant with HIP events on its first call for a given (precision,
  * extents, right-hand sides, adjoint) and keep the fastest; 0 returns to the built-in
  * heuristic.  Tuning never runs while the stream is being captured into a graph.
  * qmg_tune_save / qmg_tune_load write / read the choices as JSON {"key": variant}. */
 qmg_status qmg_autotune(int32_t on);
 /* Force one native-layout dslash variant for every later call (1: one site per thread; 2, 4, 8:
- * sites per thread along t, used when Lt is a multiple); 0 restores the automatic choice.
+ * sites per thread along t, used when Lt is a multiple; 16: four threads per site, one per
+ * direction); 0 restores the automatic choice.
  * For tests and tuning studies. */
 qmg_status qmg_set_dslash_variant(int32_t variant);
 qmg_status qmg_tune_save(const char* path);

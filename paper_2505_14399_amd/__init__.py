@@ -397,7 +397,7 @@ def autotune(on=True):
 
 
 def set_dslash_variant(v=0):
-    """Force a native dslash launch variant (1, 2, 4, 8) or restore the automatic choice (0)."""
+    """Force a native dslash launch variant (1, 2, 4, 8, 16) or restore the automatic choice (0)."""
     _check(load_library().qmg_set_dslash_variant(int(v)))
 
 

@@ -776,7 +776,8 @@ qmg_status qmg_autotune(int32_t on) {
 
 qmg_status qmg_set_dslash_variant(int32_t v) {
   return guard([&] {
-    QMG_CHECK(v == 0 || v == 1 || v == 2 || v == 4 || v == 8, QMG_EINVAL, "dslash variant must be 0, 1, 2, 4 or 8");
+    QMG_CHECK(v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16, QMG_EINVAL,
+              "dslash variant must be 0, 1, 2, 4, 8 or 16");
     set_dslash_variant(v);
   });
 }

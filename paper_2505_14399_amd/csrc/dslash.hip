@@ -311,6 +311,102 @@ __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, co
   }
 }
 
+// Direction-split native kernel: a workgroup covers 64 consecutive sites, wavefront mu forms
+// the forward and backward hops along mu for those sites (mu is uniform in the wavefront, so
+// there is no divergence), the four partial sums meet in LDS, and wavefront w then writes
+// spinor components 3w .. 3w+2 of the 64 sites.  Four times as many threads as the site
+// kernel, each with two hops in flight: for lattices too small to fill the GPU with one
+// thread per site.
+template <class S, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_dslash_dir(const S* __restrict__ U, const S* __restrict__ in,
+                                                       S* __restrict__ out, DslashArgs a) {
+  using C = ctype<S>;
+  constexpr int TS = kBlock / 4;  // sites per workgroup
+  __shared__ cplx<C> part[4][12][TS];
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  const int ntile = (a.V + TS - 1) / TS;
+  const int tile = wg % ntile, rhs = wg / ntile;
+  const int lane = threadIdx.x & (TS - 1), mu = threadIdx.x / TS;
+  const int site = tile * TS + lane;
+  const bool live = site < a.V;
+  const int V = a.V;
+  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
+  const S* inr = in + size_t(rhs) * 12 * V;
+  S* outr = out + size_t(rhs) * 12 * V;
+  C cw, diag;
+  if constexpr (sizeof(C) == 8) {
+    cw = a.cw_d[mu];
+    diag = a.diag_d;
+  } else {
+    cw = a.cw_f[mu];
+    diag = a.diag_f;
+  }
+  const C mh = C(-0.5);
+  cplx<C> acc[1][12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[0][k] = {C(0), C(0)};
+  if (live) {
+    int rem = site;
+    const int x = rem % L0; rem /= L0;
+    const int y = rem % L1; rem /= L1;
+    const int z = rem % L2;
+    const int t = rem / L2;
+    int c, L, st;
+    if (mu == 0) { c = x; L = L0; st = 1; }
+    else if (mu == 1) { c = y; L = L1; st = L0; }
+    else if (mu == 2) { c = z; L = L2; st = L0 * L1; }
+    else { c = t; L = L3; st = L0 * L1 * L2; }
+    const int fp = (c + 1 == L) ? site - (L - 1) * st : site + st;
+    const int bm = (c == 0) ? site + (L - 1) * st : site - st;
+    C cf = mh * cw, cb = mh * cw;
+    if (mu == 3 && a.bc_t < 0) {
+      if (t == L3 - 1) cf = -cf;
+      if (t == 0) cb = -cb;
+    }
+    switch (mu) {  // uniform within the wavefront
+      case 0:
+        do_hop<S, false, 1, 0, true, DAG>(U, inr, acc, site, fp, 0, V, cf);
+        do_hop<S, false, 1, 0, false, DAG>(U, inr, acc, bm, bm, 0, V, cb);
+        break;
+      case 1:
+        do_hop<S, false, 1, 1, true, DAG>(U, inr, acc, site, fp, 0, V, cf);
+        do_hop<S, false, 1, 1, false, DAG>(U, inr, acc, bm, bm, 0, V, cb);
+        break;
+      case 2:
+        do_hop<S, false, 1, 2, true, DAG>(U, inr, acc, site, fp, 0, V, cf);
+        do_hop<S, false, 1, 2, false, DAG>(U, inr, acc, bm, bm, 0, V, cb);
+        break;
+      default:
+        do_hop<S, false, 1, 3, true, DAG>(U, inr, acc, site, fp, 0, V, cf);
+        do_hop<S, false, 1, 3, false, DAG>(U, inr, acc, bm, bm, 0, V, cb);
+        break;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[0][k];
+  __syncthreads();
+  if (!live) return;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int k = 3 * mu + q;
+    const size_t i = size_t(k) * V + site;
+    cplx<C> v = diag * ldc(inr, i);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v += part[m][k][lane];
+    stc(outr, i, v);
+  }
+}
+
+template <class S>
+void launch_dir(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
+  dim3 grid(unsigned((a.V + kBlock / 4 - 1) / (kBlock / 4)) * unsigned(a.nrhs));
+  if (a.dagger)
+    k_dslash_dir<S, true><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a);
+  else
+    k_dslash_dir<S, false><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a);
+  QMG_LAUNCH_CHECK();
+}
+
 template <class S, bool CANON, int NR>
 void launch_t(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
   dim3 grid(unsigned((a.V + kBlock - 1) / kBlock) * unsigned(a.nrhs / NR));
@@ -341,8 +437,9 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     return;
   }
   // Launch variants for the native layout: 1 = one site per thread, 2/4/8 = t-walking with
-  // that many sites per thread along t.  Default heuristic: the longest t-chunk that still
-  // gives >= 1024 workgroups.  With the autotuner enabled every valid variant is timed on first
+  // that many sites per thread along t, 16 = direction-split (four threads per site).
+  // Default heuristic: the longest t-chunk that still gives >= 1024 workgroups, else the
+  // direction split when one thread per site would leave the GPU short of wavefronts.  With the autotuner enabled every valid variant is timed on first
   // use of (precision, extents, nrhs, adjoint) and the fastest is kept.
   const int Vs = a.L[0] * a.L[1] * a.L[2];
   const long wg1 = long((Vs + kBlock - 1) / kBlock) * a.nrhs;  // workgroups per t-slice
@@ -352,15 +449,18 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
       case 8: launch_tw<S, 8>(U, in, out, a, st); break;
       case 4: launch_tw<S, 4>(U, in, out, a, st); break;
       case 2: launch_tw<S, 2>(U, in, out, a, st); break;
+      case 16: launch_dir<S>(U, in, out, a, st); break;
       default: launch_t<S, false, 1>(U, in, out, a, st); break;
     }
   };
-  if (a.tchunk > 0 && (a.tchunk == 1 || Lt % a.tchunk == 0)) {
+  if (a.tchunk > 0 && (a.tchunk == 1 || a.tchunk == 16 || Lt % a.tchunk == 0)) {
     run(a.tchunk);
     return;
   }
   auto fits = [&](int tch) { return Lt % tch == 0 && wg1 * (Lt / tch) >= 1024; };
-  int choice = fits(8) ? 8 : fits(4) ? 4 : fits(2) ? 2 : 1;
+  // one thread per site fills 256 CUs x 32 wavefronts only from 2^18 sites x rhs on
+  const bool small = long(a.V) * a.nrhs < (1L << 19);
+  int choice = fits(8) ? 8 : fits(4) ? 4 : fits(2) ? 2 : small ? 16 : 1;
   if (tune_enabled()) {
     const std::string key = "dslash/" + std::to_string(int(StoreTraits<S>::prec)) + "/" + std::to_string(a.L[0]) +
                             "x" + std::to_string(a.L[1]) + "x" + std::to_string(a.L[2]) + "x" +
@@ -369,8 +469,9 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     if (cached > 0) {
       choice = cached;
     } else {
-      int cand[4], n = 0;
+      int cand[5], n = 0;
       cand[n++] = 1;
+      cand[n++] = 16;
       for (int tch : {2, 4, 8})
         if (Lt % tch == 0) cand[n++] = tch;
       choice = tune_measure(key, cand, n, st, run);

@@ -2,7 +2,9 @@
 // solvers used by the smoother, the coarse solve and the outer solve.
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <type_traits>
 
 #include "krylov.hpp"
@@ -12,7 +14,6 @@ namespace qmg {
 namespace {
 
 constexpr int RB = 256;  // threads per reduction workgroup (4 wavefronts)
-
 
 __device__ inline double2 warp_sum(double2 v) {
 #pragma unroll
@@ -40,38 +41,11 @@ __device__ inline double2 block_sum(double2 v) {
   return s;  // valid in thread 0
 }
 
-template <class S>
-__global__ __launch_bounds__(RB) void k_dot_partial(const S* __restrict__ X, size_t xstride, const S* __restrict__ w,
-                                                    size_t len, int nrhs, int nblk, double2* __restrict__ partial) {
-  const int b = blockIdx.x, r = blockIdx.y, i = blockIdx.z;
-  const S* xi = X + i * xstride + size_t(r) * len;
-  const S* wr = w + size_t(r) * len;
-  double2 acc = make_double2(0.0, 0.0);
-  for (size_t e = size_t(b) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
-    auto a = StoreTraits<S>::ld(xi[e]);
-    auto c = StoreTraits<S>::ld(wr[e]);
-    const double ar = a.re, ai = a.im, cr = c.re, ci = c.im;
-    acc.x += ar * cr + ai * ci;
-    acc.y += ar * ci - ai * cr;
-  }
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) partial[(size_t(i) * nrhs + r) * nblk + b] = acc;
-}
+// Vectors are read and written in packs of P consecutive complex numbers (16 bytes for every
+// storage type when the length and the pointers allow it, else P = 1).  Index arithmetic below
+// is in packs: a vector of len complex numbers holds np = len / P packs.
 
-template <class S>
-__global__ __launch_bounds__(RB) void k_norm_partial(const S* __restrict__ w, size_t len, int nblk,
-                                                     double2* __restrict__ partial) {
-  const int b = blockIdx.x, r = blockIdx.y;
-  const S* wr = w + size_t(r) * len;
-  double2 acc = make_double2(0.0, 0.0);
-  for (size_t e = size_t(b) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
-    auto a = StoreTraits<S>::ld(wr[e]);
-    const double ar = a.re, ai = a.im;
-    acc.x += ar * ar + ai * ai;
-  }
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) partial[size_t(r) * nblk + b] = acc;
-}
+}  // namespace
 
 // out[c] = sum over b < nblk of partial[c * nblk + b], fixed order per thread + tree
 __global__ __launch_bounds__(RB) void k_finalize2(const double2* __restrict__ partial, int nblk,
@@ -95,97 +69,188 @@ __global__ __launch_bounds__(RB) void k_finalize1(const double2* __restrict__ pa
   if (threadIdx.x == 0) out[c] = acc.x;
 }
 
-int pick_nblk(size_t len, int ncols) {
-  size_t nb = (len + RB * 4 - 1) / (RB * 4);
-  size_t cap = std::max<size_t>(1, 4096 / std::max(1, ncols));
+namespace {
+
+// workgroups for a reduction over np packs with ncols independent outputs: at most about one
+// resident wave of workgroups (256 CUs x 4 workgroups of the fused kernels), so that no
+// partial second round of workgroups trails the first
+int pick_nblk(size_t np, int ncols) {
+  size_t nb = (np + RB * 2 - 1) / (RB * 2);
+  size_t cap = std::max<size_t>(1, 1024 / std::max(1, ncols));
   nb = std::min(nb, cap);
   return int(std::max<size_t>(nb, 1));
 }
 
-template <class S>
-__global__ void k_zero(S* x, size_t n) {
-  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = StoreTraits<S>::st({ctype<S>(0), ctype<S>(0)});
+inline unsigned nb256(size_t n) { return unsigned((n + 255) / 256); }
+
+template <class S, int P>
+__global__ void k_zero(S* x, size_t np) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  Pk<S, P> z;
+#pragma unroll
+  for (int u = 0; u < P; ++u) z.v[u] = StoreTraits<S>::st({ctype<S>(0), ctype<S>(0)});
+  stp<S, P>(x, i, z);
 }
 
-template <class S>
-__global__ void k_copy(const S* __restrict__ x, S* __restrict__ y, size_t n) {
-  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = x[i];
+template <class S, int P>
+__global__ void k_copy(const S* __restrict__ x, S* __restrict__ y, size_t np) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < np) stp<S, P>(y, i, ldp<S, P>(x, i));
 }
 
-template <class S>
-__global__ void k_axpby(double a, const S* __restrict__ x, double b, S* __restrict__ y, size_t n) {
+template <class S, int P>
+__global__ void k_axpby(double a, const S* __restrict__ x, double b, S* __restrict__ y, size_t np) {
   using C = ctype<S>;
-  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) {
-    auto xv = StoreTraits<S>::ld(x[i]);
-    auto yv = StoreTraits<S>::ld(y[i]);
-    y[i] = StoreTraits<S>::st(C(a) * xv + C(b) * yv);
-  }
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const auto xv = ldp<S, P>(x, i);
+  auto yv = ldp<S, P>(y, i);
+#pragma unroll
+  for (int u = 0; u < P; ++u)
+    yv.v[u] = StoreTraits<S>::st(C(a) * StoreTraits<S>::ld(xv.v[u]) + C(b) * StoreTraits<S>::ld(yv.v[u]));
+  stp<S, P>(y, i, yv);
 }
 
-template <class S>
-__global__ void k_axpy_multi(const S* __restrict__ X, size_t xstride, int m, const double2* __restrict__ c,
-                             double sgn, S* __restrict__ w, size_t len, int nrhs) {
+// w[r] += sgn * sum_i c[i * nrhs + r] X_i[r], accumulated in order of i; the basis loads are
+// issued eight at a time so that their latencies overlap
+template <class S, int P>
+__global__ void k_axpy_multi(const S* __restrict__ X, size_t xstride_p, int m, const double2* __restrict__ c,
+                             double sgn, S* __restrict__ w, size_t np, int nrhs) {
   using C = ctype<S>;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (e >= len) return;
-  const size_t off = size_t(r) * len + e;
-  auto acc = StoreTraits<S>::ld(w[off]);
-  for (int i = 0; i < m; ++i) {
+  if (e >= np) return;
+  const size_t off = size_t(r) * np + e;
+  auto wv = ldp<S, P>(w, off);
+  cplx<C> acc[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) acc[u] = StoreTraits<S>::ld(wv.v[u]);
+  int i = 0;
+  for (; i + 8 <= m; i += 8) {
+    Pk<S, P> xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = ldp<S, P>(X, (i + q) * xstride_p + off);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double2 ci = c[size_t(i + q) * nrhs + r];
+      const cplx<C> cc = {C(sgn * ci.x), C(sgn * ci.y)};
+#pragma unroll
+      for (int u = 0; u < P; ++u) acc[u] += cc * StoreTraits<S>::ld(xv[q].v[u]);
+    }
+  }
+  for (; i < m; ++i) {
     const double2 ci = c[size_t(i) * nrhs + r];
     const cplx<C> cc = {C(sgn * ci.x), C(sgn * ci.y)};
-    acc += cc * StoreTraits<S>::ld(X[i * xstride + off]);
+    const auto xv = ldp<S, P>(X, i * xstride_p + off);
+#pragma unroll
+    for (int u = 0; u < P; ++u) acc[u] += cc * StoreTraits<S>::ld(xv.v[u]);
   }
-  w[off] = StoreTraits<S>::st(acc);
+#pragma unroll
+  for (int u = 0; u < P; ++u) wv.v[u] = StoreTraits<S>::st(acc[u]);
+  stp<S, P>(w, off, wv);
 }
 
-template <class S>
-__global__ void k_scale_dev(S* __restrict__ w, const double* __restrict__ n2, int mode, size_t len) {
+template <class S, int P>
+__global__ void k_scale_dev(S* __restrict__ w, const double* __restrict__ n2, int mode, size_t np) {
   using C = ctype<S>;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (e >= len) return;
+  if (e >= np) return;
   const double v = n2[r];
   double f;
   if (mode == 0) f = (v > 0.0) ? 1.0 / sqrt(v) : 0.0;
   else if (mode == 1) f = sqrt(v);
   else f = v;
-  const size_t off = size_t(r) * len + e;
-  w[off] = StoreTraits<S>::st(C(f) * StoreTraits<S>::ld(w[off]));
+  const size_t off = size_t(r) * np + e;
+  auto wv = ldp<S, P>(w, off);
+#pragma unroll
+  for (int u = 0; u < P; ++u) wv.v[u] = StoreTraits<S>::st(C(f) * StoreTraits<S>::ld(wv.v[u]));
+  stp<S, P>(w, off, wv);
 }
 
-template <class S>
-__global__ void k_scale_cdev(S* __restrict__ w, const double2* __restrict__ c, double sgn, size_t len) {
+template <class S, int P>
+__global__ void k_scale_cdev(S* __restrict__ w, const double2* __restrict__ c, double sgn, size_t np) {
   using C = ctype<S>;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (e >= len) return;
+  if (e >= np) return;
   const cplx<C> cc = {C(sgn * c[r].x), C(sgn * c[r].y)};
-  const size_t off = size_t(r) * len + e;
-  w[off] = StoreTraits<S>::st(cc * StoreTraits<S>::ld(w[off]));
+  const size_t off = size_t(r) * np + e;
+  auto wv = ldp<S, P>(w, off);
+#pragma unroll
+  for (int u = 0; u < P; ++u) wv.v[u] = StoreTraits<S>::st(cc * StoreTraits<S>::ld(wv.v[u]));
+  stp<S, P>(w, off, wv);
 }
 
-template <class S>
+template <class S, int P>
 __global__ void k_caxpy_dev(const double2* __restrict__ c, double sgn, const S* __restrict__ y, S* __restrict__ x,
-                            size_t len) {
+                            size_t np) {
   using C = ctype<S>;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (e >= len) return;
+  if (e >= np) return;
   const cplx<C> cc = {C(sgn * c[r].x), C(sgn * c[r].y)};
-  const size_t off = size_t(r) * len + e;
-  x[off] = StoreTraits<S>::st(StoreTraits<S>::ld(x[off]) + cc * StoreTraits<S>::ld(y[off]));
+  const size_t off = size_t(r) * np + e;
+  auto xv = ldp<S, P>(x, off);
+  const auto yv = ldp<S, P>(y, off);
+#pragma unroll
+  for (int u = 0; u < P; ++u)
+    xv.v[u] = StoreTraits<S>::st(StoreTraits<S>::ld(xv.v[u]) + cc * StoreTraits<S>::ld(yv.v[u]));
+  stp<S, P>(x, off, xv);
 }
-
-inline unsigned nb256(size_t n) { return unsigned((n + 255) / 256); }
 
 // ---------------------------------------------------------------------------------------
+// Reductions.  Workgroup b of rhs r covers packs b*RB + tid, stepping by nblk*RB, and writes
+// one partial sum per output column c at partial[c * nblk + b] (c = i * nrhs + r for basis
+// vector i); a finalise kernel or the consuming kernel sums the partials in fixed order.
+
+// partial <X_i, w> for the single basis vector i = blockIdx.z
+template <class S, int P>
+__global__ __launch_bounds__(RB) void k_dot_partial(const S* __restrict__ X, size_t xstride_p,
+                                                    const S* __restrict__ w, size_t np, int nrhs, int nblk,
+                                                    double2* __restrict__ partial) {
+  const int b = blockIdx.x, r = blockIdx.y, i = blockIdx.z;
+  const S* xi = X + i * xstride_p * P;
+  double2 acc = make_double2(0.0, 0.0);
+  for (size_t e = size_t(b) * RB + threadIdx.x; e < np; e += size_t(nblk) * RB) {
+    const auto a = ldp<S, P>(xi, size_t(r) * np + e);
+    const auto c = ldp<S, P>(w, size_t(r) * np + e);
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const auto av = StoreTraits<S>::ld(a.v[u]);
+      const auto cv = StoreTraits<S>::ld(c.v[u]);
+      const double ar = av.re, ai = av.im, cr = cv.re, ci = cv.im;
+      acc.x += ar * cr + ai * ci;
+      acc.y += ar * ci - ai * cr;
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[(size_t(i) * nrhs + r) * nblk + b] = acc;
+}
+
+template <class S, int P>
+__global__ __launch_bounds__(RB) void k_norm_partial(const S* __restrict__ w, size_t np, int nblk,
+                                                     double2* __restrict__ partial) {
+  const int b = blockIdx.x, r = blockIdx.y;
+  double2 acc = make_double2(0.0, 0.0);
+  for (size_t e = size_t(b) * RB + threadIdx.x; e < np; e += size_t(nblk) * RB) {
+    const auto a = ldp<S, P>(w, size_t(r) * np + e);
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const auto av = StoreTraits<S>::ld(a.v[u]);
+      const double ar = av.re, ai = av.im;
+      acc.x += ar * ar + ai * ai;
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[size_t(r) * nblk + b] = acc;
+}
+
 // Fused multi-vector kernels for the Arnoldi/GCR orthogonalisation: each reads the target
 // vector w once for up to MG basis vectors (grid.z = group of MG vectors).
 constexpr int MG = 8;
+constexpr int kMaxCoef = 72;  // coefficients per right-hand side a fused consumer stages in LDS
 
 template <class S>
 __device__ inline void store_partials(double2 (&acc)[MG], int mi, double2* partial, int i0, int nrhs, int r, int b,
@@ -210,99 +275,176 @@ __device__ inline void store_partials(double2 (&acc)[MG], int mi, double2* parti
   }
 }
 
+// Where a kernel finds its per-rhs coefficients c_i (i < n): finalised values fin[i * nrhs + r],
+// or, when partial is set, the per-workgroup partial sums partial[(i * nrhs + r) * nblk + q]
+// (q < nblk) of the previous kernel, which every consumer workgroup sums itself in the same
+// fixed order; workgroup (0, r) then stores the sums to fin_out[i * nrhs + r] (if set).
+struct CoefSrc {
+  const double2* fin;
+  const double2* partial;
+  int nblk;
+  double2* fin_out;
+};
+
+__device__ inline void load_coefs(double2* s_c, int n, int r, int nrhs, const CoefSrc& src) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (src.partial) {
+    for (int i = wid; i < n; i += nw) {
+      const double2* p = src.partial + (size_t(i) * nrhs + r) * src.nblk;
+      double2 a = make_double2(0.0, 0.0);
+      for (int q = lane; q < src.nblk; q += 64) {
+        a.x += p[q].x;
+        a.y += p[q].y;
+      }
+      a = warp_sum(a);
+      if (lane == 0) {
+        s_c[i] = a;
+        if (blockIdx.x == 0 && blockIdx.z == 0 && src.fin_out) src.fin_out[size_t(i) * nrhs + r] = a;
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s_c[i] = src.fin[size_t(i) * nrhs + r];
+  }
+  __syncthreads();
+}
+
+// v[u] += sgn * sum_{i < m} c_i X_i[off] for the P entries of one pack, accumulated in order
+// of i; loads are issued eight at a time so that their latencies overlap
+template <class S, int P>
+__device__ inline void acc_basis(cplx<ctype<S>> (&v)[P], const S* __restrict__ X, size_t xstride_p, size_t off,
+                                 const double2* c, int m, double sgn) {
+  using C = ctype<S>;
+  int i = 0;
+  for (; i + 8 <= m; i += 8) {
+    Pk<S, P> xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = ldp<S, P>(X, (i + q) * xstride_p + off);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const cplx<C> cc = {C(sgn * c[i + q].x), C(sgn * c[i + q].y)};
+#pragma unroll
+      for (int u = 0; u < P; ++u) v[u] += cc * StoreTraits<S>::ld(xv[q].v[u]);
+    }
+  }
+  for (; i < m; ++i) {
+    const cplx<C> cc = {C(sgn * c[i].x), C(sgn * c[i].y)};
+    const auto xv = ldp<S, P>(X, i * xstride_p + off);
+#pragma unroll
+    for (int u = 0; u < P; ++u) v[u] += cc * StoreTraits<S>::ld(xv.v[u]);
+  }
+}
+
+// acc[i] += <X_{i0+i}[off], w> over the P entries of one pack (cw: the entries of w)
+template <class S, int P>
+__device__ inline void acc_dots(double2 (&acc)[MG], const S* __restrict__ X, size_t xstride_p, size_t off, int i0,
+                                int mi, const double (&cr)[P], const double (&ci)[P]) {
+  Pk<S, P> xv[MG];
+#pragma unroll
+  for (int i = 0; i < MG; ++i)
+    if (i < mi) xv[i] = ldp<S, P>(X, (i0 + i) * xstride_p + off);
+#pragma unroll
+  for (int i = 0; i < MG; ++i) {
+    if (i < mi) {
+#pragma unroll
+      for (int u = 0; u < P; ++u) {
+        const auto a = StoreTraits<S>::ld(xv[i].v[u]);
+        const double ar = a.re, ai = a.im;
+        acc[i].x += ar * cr[u] + ai * ci[u];
+        acc[i].y += ar * ci[u] - ai * cr[u];
+      }
+    }
+  }
+}
+
 // partial <X_i, w> for i in [i0, i0 + MG) of this z-group
-template <class S>
-__global__ __launch_bounds__(RB) void k_mdot(const S* __restrict__ X, size_t xstride, int m, const S* __restrict__ w,
-                                             size_t len, int nrhs, int nblk, double2* __restrict__ partial) {
+template <class S, int P>
+__global__ __launch_bounds__(RB) void k_mdot(const S* __restrict__ X, size_t xstride_p, int m,
+                                             const S* __restrict__ w, size_t np, int nrhs, int nblk,
+                                             double2* __restrict__ partial) {
   const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
   const int mi = min(MG, m - i0);
-  const S* wr = w + size_t(r) * len;
   double2 acc[MG];
 #pragma unroll
   for (int i = 0; i < MG; ++i) acc[i] = make_double2(0.0, 0.0);
-  for (size_t e = size_t(b) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
-    const auto c = StoreTraits<S>::ld(wr[e]);
-    const double cr = c.re, ci = c.im;
+  for (size_t e = size_t(b) * RB + threadIdx.x; e < np; e += size_t(nblk) * RB) {
+    const size_t off = size_t(r) * np + e;
+    const auto c = ldp<S, P>(w, off);
+    double cr[P], ci[P];
 #pragma unroll
-    for (int i = 0; i < MG; ++i) {
-      if (i < mi) {
-        const auto a = StoreTraits<S>::ld(X[(i0 + i) * xstride + size_t(r) * len + e]);
-        const double ar = a.re, ai = a.im;
-        acc[i].x += ar * cr + ai * ci;
-        acc[i].y += ar * ci - ai * cr;
-      }
+    for (int u = 0; u < P; ++u) {
+      const auto cv = StoreTraits<S>::ld(c.v[u]);
+      cr[u] = cv.re;
+      ci[u] = cv.im;
     }
+    acc_dots<S, P>(acc, X, xstride_p, off, i0, mi, cr, ci);
   }
   store_partials<S>(acc, mi, partial, i0, nrhs, r, b, nblk);
 }
 
-// w <- w + sgn * sum_i c_i X_i (all m vectors), then partial <X_i, w> (grid.z groups) or
-// partial |w|^2 (mode 1, grid.z = 1).  Each z-group recomputes the same w update; only z = 0
-// stores it.
-template <class S, int MODE>
-__global__ __launch_bounds__(RB) void k_axpy_then(const S* __restrict__ X, size_t xstride, int m,
-                                                  const double2* __restrict__ c, double sgn, S* __restrict__ w,
-                                                  size_t len, int nrhs, int nblk, double2* __restrict__ partial) {
+// wout <- w + sgn * sum_i c_i X_i (all m vectors), then partial <X_i, wout> (grid.z groups) or
+// partial |wout|^2 (mode 1, grid.z = 1).  Each z-group recomputes the same update; only z = 0
+// stores it, so wout may alias w only with a single z-group.
+template <class S, int MODE, int P>
+__global__ __launch_bounds__(RB) void k_axpy_then(const S* __restrict__ X, size_t xstride_p, int m, CoefSrc csrc,
+                                                  double sgn, const S* w, S* wout, size_t np, int nrhs, int nblk,
+                                                  double2* __restrict__ partial) {
   using C = ctype<S>;
   const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
   const int mi = MODE == 0 ? min(MG, m - i0) : 1;
-  S* wr = w + size_t(r) * len;
+  __shared__ double2 s_c[kMaxCoef];
+  load_coefs(s_c, m, r, nrhs, csrc);
   double2 acc[MG];
 #pragma unroll
   for (int i = 0; i < MG; ++i) acc[i] = make_double2(0.0, 0.0);
-  for (size_t e = size_t(b) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
-    auto v = StoreTraits<S>::ld(wr[e]);
-    for (int i = 0; i < m; ++i) {
-      const double2 ci = c[size_t(i) * nrhs + r];
-      const cplx<C> cc = {C(sgn * ci.x), C(sgn * ci.y)};
-      v += cc * StoreTraits<S>::ld(X[i * xstride + size_t(r) * len + e]);
-    }
-    const S vs = StoreTraits<S>::st(v);
-    if (blockIdx.z == 0) wr[e] = vs;
-    const auto vv = StoreTraits<S>::ld(vs);  // the stored (rounded) value
-    const double cr = vv.re, cim = vv.im;
-    if (MODE == 0) {
+  for (size_t e = size_t(b) * RB + threadIdx.x; e < np; e += size_t(nblk) * RB) {
+    const size_t off = size_t(r) * np + e;
+    auto wv = ldp<S, P>(w, off);
+    cplx<C> v[P];
 #pragma unroll
-      for (int i = 0; i < MG; ++i) {
-        if (i < mi) {
-          const auto a = StoreTraits<S>::ld(X[(i0 + i) * xstride + size_t(r) * len + e]);
-          const double ar = a.re, ai = a.im;
-          acc[i].x += ar * cr + ai * cim;
-          acc[i].y += ar * cim - ai * cr;
-        }
-      }
+    for (int u = 0; u < P; ++u) v[u] = StoreTraits<S>::ld(wv.v[u]);
+    acc_basis<S, P>(v, X, xstride_p, off, s_c, m, sgn);
+    double cr[P], ci[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      wv.v[u] = StoreTraits<S>::st(v[u]);
+      const auto vv = StoreTraits<S>::ld(wv.v[u]);  // the stored (rounded) value
+      cr[u] = vv.re;
+      ci[u] = vv.im;
+    }
+    if (blockIdx.z == 0) stp<S, P>(wout, off, wv);
+    if (MODE == 0) {
+      acc_dots<S, P>(acc, X, xstride_p, off, i0, mi, cr, ci);
     } else {
-      acc[0].x += cr * cr + cim * cim;
+#pragma unroll
+      for (int u = 0; u < P; ++u) acc[0].x += cr[u] * cr[u] + ci[u] * ci[u];
     }
   }
   store_partials<S>(acc, mi, partial, i0, nrhs, r, b, nblk);
 }
 
 // partial <X_i, w> (grid.z groups of MG) and, in group 0, partial |w|^2 stored at slot m
-template <class S>
-__global__ __launch_bounds__(RB) void k_mdot_norm(const S* __restrict__ X, size_t xstride, int m,
-                                                  const S* __restrict__ w, size_t len, int nrhs, int nblk,
+template <class S, int P>
+__global__ __launch_bounds__(RB) void k_mdot_norm(const S* __restrict__ X, size_t xstride_p, int m,
+                                                  const S* __restrict__ w, size_t np, int nrhs, int nblk,
                                                   double2* __restrict__ partial) {
   const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
   const int mi = min(MG, m - i0);
-  const S* wr = w + size_t(r) * len;
   double2 acc[MG];
   double nn = 0.0;
 #pragma unroll
   for (int i = 0; i < MG; ++i) acc[i] = make_double2(0.0, 0.0);
-  for (size_t e = size_t(b) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
-    const auto c = StoreTraits<S>::ld(wr[e]);
-    const double cr = c.re, ci = c.im;
-    nn += cr * cr + ci * ci;
+  for (size_t e = size_t(b) * RB + threadIdx.x; e < np; e += size_t(nblk) * RB) {
+    const size_t off = size_t(r) * np + e;
+    const auto c = ldp<S, P>(w, off);
+    double cr[P], ci[P];
 #pragma unroll
-    for (int i = 0; i < MG; ++i) {
-      if (i < mi) {
-        const auto a = StoreTraits<S>::ld(X[(i0 + i) * xstride + size_t(r) * len + e]);
-        const double ar = a.re, ai = a.im;
-        acc[i].x += ar * cr + ai * ci;
-        acc[i].y += ar * ci - ai * cr;
-      }
+    for (int u = 0; u < P; ++u) {
+      const auto cv = StoreTraits<S>::ld(c.v[u]);
+      cr[u] = cv.re;
+      ci[u] = cv.im;
+      nn += cr[u] * cr[u] + ci[u] * ci[u];
     }
+    acc_dots<S, P>(acc, X, xstride_p, off, i0, mi, cr, ci);
   }
   store_partials<S>(acc, mi, partial, i0, nrhs, r, b, nblk);
   if (blockIdx.z == 0) {
@@ -312,111 +454,267 @@ __global__ __launch_bounds__(RB) void k_mdot_norm(const S* __restrict__ X, size_
 }
 
 // w <- (w - sum_i c_i X_i) / beta with beta^2 = |w|^2 - sum_i |c_i|^2 (Pythagoras, c = X^dag w
-// for orthonormal X); beta^2 is also written to out_n2 (block 0).  n2 = |w|^2 before the update.
-template <class S>
-__global__ __launch_bounds__(RB) void k_axpy_scale(const S* __restrict__ X, size_t xstride, int m,
-                                                   const double2* __restrict__ c, const double2* __restrict__ n2,
-                                                   S* __restrict__ w, size_t len, int nrhs, double* __restrict__ out_n2) {
+// for orthonormal X); coefficient slot m holds |w|^2 before the update; beta^2 is written to
+// out_n2 (workgroup 0).
+template <class S, int P>
+__global__ __launch_bounds__(256) void k_axpy_scale(const S* __restrict__ X, size_t xstride_p, int m, CoefSrc csrc,
+                                                    S* __restrict__ w, size_t np, int nrhs,
+                                                    double* __restrict__ out_n2) {
   using C = ctype<S>;
   const int r = blockIdx.y;
-  double b2 = n2[r].x;
-  for (int i = 0; i < m; ++i) {
-    const double2 ci = c[size_t(i) * nrhs + r];
-    b2 -= ci.x * ci.x + ci.y * ci.y;
-  }
+  __shared__ double2 s_c[kMaxCoef];
+  load_coefs(s_c, m + 1, r, nrhs, csrc);
+  double b2 = s_c[m].x;
+  for (int i = 0; i < m; ++i) b2 -= s_c[i].x * s_c[i].x + s_c[i].y * s_c[i].y;
   b2 = fmax(b2, 0.0);
   const double inv = b2 > 0.0 ? 1.0 / sqrt(b2) : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) out_n2[r] = b2;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= len) return;
-  S* wr = w + size_t(r) * len;
-  auto v = StoreTraits<S>::ld(wr[e]);
-  for (int i = 0; i < m; ++i) {
-    const double2 ci = c[size_t(i) * nrhs + r];
-    const cplx<C> cc = {C(-ci.x), C(-ci.y)};
-    v += cc * StoreTraits<S>::ld(X[i * xstride + size_t(r) * len + e]);
-  }
-  wr[e] = StoreTraits<S>::st(C(inv) * v);
+  if (e >= np) return;
+  const size_t off = size_t(r) * np + e;
+  auto wv = ldp<S, P>(w, off);
+  cplx<C> v[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) v[u] = StoreTraits<S>::ld(wv.v[u]);
+  acc_basis<S, P>(v, X, xstride_p, off, s_c, m, -1.0);
+#pragma unroll
+  for (int u = 0; u < P; ++u) wv.v[u] = StoreTraits<S>::st(C(inv) * v[u]);
+  stp<S, P>(w, off, wv);
 }
+
+// w[r] /= sqrt(n2) with n2 = the real part of the single coefficient of rhs r (zero norm gives
+// a zero vector); workgroup 0 stores n2 to out_n2[r]
+template <class S, int P>
+__global__ __launch_bounds__(256) void k_scale_norm(S* __restrict__ w, CoefSrc csrc, size_t np, int nrhs,
+                                                    double* __restrict__ out_n2) {
+  using C = ctype<S>;
+  const int r = blockIdx.y;
+  __shared__ double2 s_c[1];
+  load_coefs(s_c, 1, r, nrhs, csrc);
+  const double v = s_c[0].x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) out_n2[r] = v;
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= np) return;
+  const double f = (v > 0.0) ? 1.0 / sqrt(v) : 0.0;
+  const size_t off = size_t(r) * np + e;
+  auto wv = ldp<S, P>(w, off);
+#pragma unroll
+  for (int u = 0; u < P; ++u) wv.v[u] = StoreTraits<S>::st(C(f) * StoreTraits<S>::ld(wv.v[u]));
+  stp<S, P>(w, off, wv);
+}
+
+// Pack width usable for vectors of len complex numbers at the given pointers (and basis
+// stride): the full 16-byte pack when everything is a multiple of it, else 1.
+template <class S>
+bool packable(size_t len, size_t xstride, std::initializer_list<const void*> ptrs) {
+  constexpr int P = kPack<S>;
+  if (P == 1) return true;
+  if (len % P || xstride % P) return false;
+  for (const void* p : ptrs)
+    if (reinterpret_cast<uintptr_t>(p) % 16) return false;
+  return true;
+}
+
+// Short vectors (the coarse level) are latency bound: there the consumer of a reduction sums
+// the producer's partials itself instead of a separate finalise launch, with at most
+// kSmallBlk partials per coefficient.
+constexpr size_t kSmallLen = size_t(RB) * 128 * 8;
+constexpr int kSmallBlk = 128;
+inline int small_nblk(size_t np) { return int(std::min<size_t>(kSmallBlk, std::max<size_t>(1, (np + RB - 1) / RB))); }
+
+// Host side of every operation, for one pack width.
+template <class S, int P>
+struct BlasP {
+  static void zero(void* x, size_t n, hipStream_t st) {
+    k_zero<S, P><<<nb256(n / P), 256, 0, st>>>((S*)x, n / P);
+    QMG_LAUNCH_CHECK();
+  }
+  static void copy(const void* x, void* y, size_t n, hipStream_t st) {
+    k_copy<S, P><<<nb256(n / P), 256, 0, st>>>((const S*)x, (S*)y, n / P);
+    QMG_LAUNCH_CHECK();
+  }
+  static void axpby(double a, const void* x, double b, void* y, size_t n, hipStream_t st) {
+    k_axpby<S, P><<<nb256(n / P), 256, 0, st>>>(a, (const S*)x, b, (S*)y, n / P);
+    QMG_LAUNCH_CHECK();
+  }
+  static void dot_multi(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
+                        RedWork& rw, hipStream_t st) {
+    const size_t np = len / P;
+    const int nblk = pick_nblk(np, m * nrhs);
+    rw.ensure(size_t(nblk) * m * nrhs, 0);
+    k_dot_partial<S, P><<<dim3(nblk, nrhs, m), RB, 0, st>>>((const S*)X, xstride / P, (const S*)w, np, nrhs, nblk,
+                                                             rw.partial.as<double2>());
+    QMG_LAUNCH_CHECK();
+    k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+    QMG_LAUNCH_CHECK();
+  }
+  static void norm2(const void* w, size_t len, int nrhs, double* out, RedWork& rw, hipStream_t st) {
+    const size_t np = len / P;
+    const int nblk = pick_nblk(np, nrhs);
+    rw.ensure(size_t(nblk) * nrhs, 0);
+    k_norm_partial<S, P><<<dim3(nblk, nrhs), RB, 0, st>>>((const S*)w, np, nblk, rw.partial.as<double2>());
+    QMG_LAUNCH_CHECK();
+    k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+    QMG_LAUNCH_CHECK();
+  }
+  static void axpy_multi(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
+                         int nrhs, hipStream_t st) {
+    const size_t np = len / P;
+    k_axpy_multi<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, c, sgn, (S*)w, np, nrhs);
+    QMG_LAUNCH_CHECK();
+  }
+  static void scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st) {
+    k_scale_dev<S, P><<<dim3(nb256(len / P), nrhs), 256, 0, st>>>((S*)w, n2, mode, len / P);
+    QMG_LAUNCH_CHECK();
+  }
+  static void scale_cdev(void* w, const double2* c, double sgn, size_t len, int nrhs, hipStream_t st) {
+    k_scale_cdev<S, P><<<dim3(nb256(len / P), nrhs), 256, 0, st>>>((S*)w, c, sgn, len / P);
+    QMG_LAUNCH_CHECK();
+  }
+  static void caxpy_dev(const double2* c, double sgn, const void* y, void* x, size_t len, int nrhs,
+                        hipStream_t st) {
+    k_caxpy_dev<S, P><<<dim3(nb256(len / P), nrhs), 256, 0, st>>>(c, sgn, (const S*)y, (S*)x, len / P);
+    QMG_LAUNCH_CHECK();
+  }
+  static void mdot(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
+                   RedWork& rw, hipStream_t st) {
+    const size_t np = len / P;
+    const int ng = (m + MG - 1) / MG;
+    const int nblk = pick_nblk(np, ng * nrhs);
+    rw.ensure(size_t(nblk) * m * nrhs, 0);
+    k_mdot<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk,
+                                                       rw.partial.as<double2>());
+    QMG_LAUNCH_CHECK();
+    k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+    QMG_LAUNCH_CHECK();
+  }
+  static void axpy_then(int mode, const void* X, size_t xstride, int m, const double2* c, double sgn, void* w,
+                        size_t len, int nrhs, void* out, RedWork& rw, hipStream_t st) {
+    const size_t np = len / P;
+    const int nblk = pick_nblk(np, nrhs);
+    rw.ensure(size_t(nblk) * std::max(m, 1) * nrhs, 0);
+    const CoefSrc src{c, nullptr, 0, nullptr};
+    if (mode == 0) {
+      k_axpy_then<S, 0, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride / P, m, src, sgn, (const S*)w,
+                                                                (S*)w, np, nrhs, nblk, rw.partial.as<double2>());
+      QMG_LAUNCH_CHECK();
+      k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, (double2*)out);
+    } else {
+      k_axpy_then<S, 1, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride / P, m, src, sgn, (const S*)w,
+                                                                (S*)w, np, nrhs, nblk, rw.partial.as<double2>());
+      QMG_LAUNCH_CHECK();
+      k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, (double*)out);
+    }
+    QMG_LAUNCH_CHECK();
+  }
+  static void cgs1(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
+                   RedWork& rw, hipStream_t st) {
+    const size_t np = len / P;
+    const int ng = (m + MG - 1) / MG;
+    const bool small = len <= kSmallLen;
+    const int nblk = small ? small_nblk(np) : pick_nblk(np, ng * nrhs);
+    rw.ensure(size_t(nblk) * (m + 1) * nrhs, size_t(nrhs));
+    double2* part = rw.partial.as<double2>();
+    k_mdot_norm<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk,
+                                                            part);
+    QMG_LAUNCH_CHECK();
+    CoefSrc src{h, nullptr, 0, nullptr};
+    if (small) {
+      src = CoefSrc{nullptr, part, nblk, h};
+    } else {
+      k_finalize2<<<(m + 1) * nrhs, RB, 0, st>>>(part, nblk, h);
+      QMG_LAUNCH_CHECK();
+    }
+    k_axpy_scale<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, src, (S*)w, np, nrhs, n2);
+    QMG_LAUNCH_CHECK();
+  }
+  static void cgs2_small(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
+                         double2* h2, double* n2, RedWork& rw, hipStream_t st) {
+    const size_t np = len / P;
+    const int ng = (m + MG - 1) / MG;
+    const int nblk = small_nblk(np);
+    rw.ensure(size_t(nblk) * m * nrhs, 0);
+    // second buffer: partials, then w' (16-byte aligned after the partials)
+    rw.ensure2(size_t(nblk) * m * nrhs + (len * nrhs * sizeof(S) + sizeof(double2) - 1) / sizeof(double2));
+    double2* pa = rw.partial.as<double2>();
+    double2* pb = rw.partial2.as<double2>();
+    S* wtmp = reinterpret_cast<S*>(pb + size_t(nblk) * m * nrhs);
+    // pass 1: partials of X^dag w
+    k_mdot<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk, pa);
+    QMG_LAUNCH_CHECK();
+    // w' = w - X h1 (h1 summed from pa) into wtmp, partials of X^dag w' into pb
+    k_axpy_then<S, 0, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>(
+        (const S*)X, xstride / P, m, CoefSrc{nullptr, pa, nblk, h1}, -1.0, (const S*)w, wtmp, np, nrhs, nblk, pb);
+    QMG_LAUNCH_CHECK();
+    // w = w' - X h2 (h2 summed from pb), partial |w|^2 into pa
+    k_axpy_then<S, 1, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>(
+        (const S*)X, xstride / P, m, CoefSrc{nullptr, pb, nblk, h2}, -1.0, (const S*)wtmp, (S*)w, np, nrhs, nblk, pa);
+    QMG_LAUNCH_CHECK();
+    k_scale_norm<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((S*)w, CoefSrc{nullptr, pa, nblk, nullptr}, np, nrhs,
+                                                              n2);
+    QMG_LAUNCH_CHECK();
+  }
+};
 
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
+// Blas<S>: pick the pack width, then dispatch
+#define QMG_PACKED(cond, call)             \
+  do {                                     \
+    if (cond) BlasP<S, kPack<S>>::call;    \
+    else BlasP<S, 1>::call;                \
+  } while (0)
+
 template <class S>
 void Blas<S>::zero(void* x, size_t n, hipStream_t st) {
   if (!n) return;
-  k_zero<S><<<nb256(n), 256, 0, st>>>((S*)x, n);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(n, 0, {x}), zero(x, n, st));
 }
 template <class S>
 void Blas<S>::copy(const void* x, void* y, size_t n, hipStream_t st) {
   if (!n) return;
-  k_copy<S><<<nb256(n), 256, 0, st>>>((const S*)x, (S*)y, n);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(n, 0, {x, y}), copy(x, y, n, st));
 }
 template <class S>
 void Blas<S>::axpby(double a, const void* x, double b, void* y, size_t n, hipStream_t st) {
   if (!n) return;
-  k_axpby<S><<<nb256(n), 256, 0, st>>>(a, (const S*)x, b, (S*)y, n);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(n, 0, {x, y}), axpby(a, x, b, y, n, st));
 }
 template <class S>
 void Blas<S>::dot_multi(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
                         RedWork& rw, hipStream_t st) {
   if (m <= 0) return;
-  const int nblk = pick_nblk(len, m * nrhs);
-  rw.ensure(size_t(nblk) * m * nrhs, 0);
-  k_dot_partial<S><<<dim3(nblk, nrhs, m), RB, 0, st>>>((const S*)X, xstride, (const S*)w, len, nrhs, nblk,
-                                                        rw.partial.as<double2>());
-  QMG_LAUNCH_CHECK();
-  k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), dot_multi(X, xstride, m, w, len, nrhs, out, rw, st));
 }
 template <class S>
 void Blas<S>::norm2(const void* w, size_t len, int nrhs, double* out, RedWork& rw, hipStream_t st) {
-  const int nblk = pick_nblk(len, nrhs);
-  rw.ensure(size_t(nblk) * nrhs, 0);
-  k_norm_partial<S><<<dim3(nblk, nrhs), RB, 0, st>>>((const S*)w, len, nblk, rw.partial.as<double2>());
-  QMG_LAUNCH_CHECK();
-  k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(len, 0, {w}), norm2(w, len, nrhs, out, rw, st));
 }
 template <class S>
 void Blas<S>::axpy_multi(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
                          int nrhs, hipStream_t st) {
   if (m <= 0) return;
-  k_axpy_multi<S><<<dim3(nb256(len), nrhs), 256, 0, st>>>((const S*)X, xstride, m, c, sgn, (S*)w, len, nrhs);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_multi(X, xstride, m, c, sgn, w, len, nrhs, st));
 }
 template <class S>
 void Blas<S>::scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st) {
-  k_scale_dev<S><<<dim3(nb256(len), nrhs), 256, 0, st>>>((S*)w, n2, mode, len);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(len, 0, {w}), scale_dev(w, n2, mode, len, nrhs, st));
 }
 template <class S>
 void Blas<S>::scale_cdev(void* w, const double2* c, double sgn, size_t len, int nrhs, hipStream_t st) {
-  k_scale_cdev<S><<<dim3(nb256(len), nrhs), 256, 0, st>>>((S*)w, c, sgn, len);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(len, 0, {w}), scale_cdev(w, c, sgn, len, nrhs, st));
 }
 template <class S>
 void Blas<S>::caxpy_dev(const double2* c, double sgn, const void* y, void* x, size_t len, int nrhs,
                         hipStream_t st) {
-  k_caxpy_dev<S><<<dim3(nb256(len), nrhs), 256, 0, st>>>(c, sgn, (const S*)y, (S*)x, len);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(len, 0, {x, y}), caxpy_dev(c, sgn, y, x, len, nrhs, st));
 }
-
 template <class S>
 void Blas<S>::mdot(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
                    RedWork& rw, hipStream_t st) {
   if (m <= 0) return;
-  const int ng = (m + MG - 1) / MG;
-  const int nblk = pick_nblk(len, ng * nrhs);
-  rw.ensure(size_t(nblk) * m * nrhs, 0);
-  k_mdot<S><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride, m, (const S*)w, len, nrhs, nblk,
-                                                 rw.partial.as<double2>());
-  QMG_LAUNCH_CHECK();
-  k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), mdot(X, xstride, m, w, len, nrhs, out, rw, st));
 }
 template <class S>
 void Blas<S>::axpy_mdot(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
@@ -428,43 +726,45 @@ void Blas<S>::axpy_mdot(const void* X, size_t xstride, int m, const double2* c, 
     mdot(X, xstride, m, w, len, nrhs, out, rw, st);
     return;
   }
-  const int nblk = pick_nblk(len, nrhs);
-  rw.ensure(size_t(nblk) * m * nrhs, 0);
-  k_axpy_then<S, 0><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride, m, c, sgn, (S*)w, len, nrhs, nblk,
-                                                         rw.partial.as<double2>());
-  QMG_LAUNCH_CHECK();
-  k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
-  QMG_LAUNCH_CHECK();
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_then(0, X, xstride, m, c, sgn, w, len, nrhs, out, rw, st));
 }
 template <class S>
 void Blas<S>::axpy_norm(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
                         int nrhs, double* out, RedWork& rw, hipStream_t st) {
-  const int nblk = pick_nblk(len, nrhs);
-  rw.ensure(size_t(nblk) * nrhs, 0);
-  k_axpy_then<S, 1><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride, m, c, sgn, (S*)w, len, nrhs, nblk,
-                                                         rw.partial.as<double2>());
-  QMG_LAUNCH_CHECK();
-  k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
-  QMG_LAUNCH_CHECK();
+  if (m > kMaxCoef) {
+    axpy_multi(X, xstride, m, c, sgn, w, len, nrhs, st);
+    norm2(w, len, nrhs, out, rw, st);
+    return;
+  }
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_then(1, X, xstride, m, c, sgn, w, len, nrhs, out, rw, st));
 }
-
 template <class S>
 void Blas<S>::cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
                         RedWork& rw, hipStream_t st) {
-  const int ng = (m + MG - 1) / MG;
-  const int nblk = pick_nblk(len, ng * nrhs);
-  rw.ensure(size_t(nblk) * (m + 1) * nrhs, size_t(nrhs));
-  k_mdot_norm<S><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride, m, (const S*)w, len, nrhs, nblk,
-                                                      rw.partial.as<double2>());
-  QMG_LAUNCH_CHECK();
-  k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, h);
-  QMG_LAUNCH_CHECK();
-  double2* wn = rw.result.as<double2>();
-  k_finalize2<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>() + size_t(m) * nrhs * nblk, nblk, wn);
-  QMG_LAUNCH_CHECK();
-  k_axpy_scale<S><<<dim3(nb256(len), nrhs), 256, 0, st>>>((const S*)X, xstride, m, h, wn, (S*)w, len, nrhs, n2);
-  QMG_LAUNCH_CHECK();
+  QMG_CHECK(m >= 1, QMG_EINVAL, "Gram-Schmidt step: no basis vectors");
+  if (m + 1 > kMaxCoef) {  // long bases: explicit update and norm instead of Pythagoras
+    mdot(X, xstride, m, w, len, nrhs, h, rw, st);
+    axpy_multi(X, xstride, m, h, -1.0, w, len, nrhs, st);
+    norm2(w, len, nrhs, n2, rw, st);
+    scale_dev(w, n2, 0, len, nrhs, st);
+    return;
+  }
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), cgs1(X, xstride, m, w, len, nrhs, h, n2, rw, st));
 }
+template <class S>
+void Blas<S>::cgs2_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
+                        double2* h2, double* n2, RedWork& rw, hipStream_t st) {
+  QMG_CHECK(m >= 1, QMG_EINVAL, "Gram-Schmidt step: no basis vectors");
+  if (len > kSmallLen || m > kMaxCoef) {
+    mdot(X, xstride, m, w, len, nrhs, h1, rw, st);
+    axpy_mdot(X, xstride, m, h1, -1.0, w, len, nrhs, h2, rw, st);
+    axpy_norm(X, xstride, m, h2, -1.0, w, len, nrhs, n2, rw, st);
+    scale_dev(w, n2, 0, len, nrhs, st);
+    return;
+  }
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), cgs2_small(X, xstride, m, w, len, nrhs, h1, h2, n2, rw, st));
+}
+#undef QMG_PACKED
 
 template struct Blas<double2>;
 template struct Blas<float2>;
@@ -625,7 +925,7 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
     Blas<S>::scale_dev(V, nrm, 0, len, nrhs, st);
     const int mc = std::min(m, max_iter - it);
     for (int r = 0; r < nrhs; ++r) gs[r].init(mc, std::sqrt(hnrm0[r]));
-    int jdone = 0, processed = 0;
+    int jdone = 0, processed = 0, copied = 0;
     for (int j = 0; j < mc; ++j) {
       S* vj = V + size_t(j) * vs;
       S* vn = V + size_t(j + 1) * vs;
@@ -636,17 +936,18 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
       A.apply(vj, vn, nrhs, st);
       if (kCgs2) {
         // CGS2: h1 = V^dag w ; w -= V h1 and h2 = V^dag w ; w -= V h2 and |w|^2 ; w /= |w|
-        Blas<S>::mdot(V, vs, j + 1, vn, len, nrhs, h1, rw_, st);
-        Blas<S>::axpy_mdot(V, vs, j + 1, h1, -1.0, vn, len, nrhs, h2, rw_, st);
-        Blas<S>::axpy_norm(V, vs, j + 1, h2, -1.0, vn, len, nrhs, cn, rw_, st);
-        Blas<S>::scale_dev(vn, cn, 0, len, nrhs, st);
+        Blas<S>::cgs2_step(V, vs, j + 1, vn, len, nrhs, h1, h2, cn, rw_, st);
       } else {
         // one classical Gram-Schmidt pass with the norm from Pythagoras, scaling fused
         Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, cn, rw_, st);
       }
-      QMG_HIP(hipMemcpyAsync(hcols + size_t(j) * per_col, col, per_col * sizeof(double2), hipMemcpyDeviceToHost,
-                             st));
       jdone = j + 1;
+      // the columns since the last read travel to the host in one copy
+      if ((tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) || (tol <= 0 && j == mc - 1)) {
+        QMG_HIP(hipMemcpyAsync(hcols + size_t(copied) * per_col, colsd + size_t(copied) * per_col,
+                               size_t(j + 1 - copied) * per_col * sizeof(double2), hipMemcpyDeviceToHost, st));
+        copied = j + 1;
+      }
       if (tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) {
         QMG_HIP(hipStreamSynchronize(st));
         for (; processed <= j; ++processed) {

@@ -25,14 +25,17 @@ struct Precond {
   virtual void apply(const void* r, void* z, int nrhs, hipStream_t st) = 0;
 };
 
-// scratch for two-pass reductions
+// scratch for two-pass reductions; the second buffer lets a kernel that sums one set of
+// partials (from the previous kernel) write the next set in the same launch
 struct RedWork {
-  DevBuf partial;  // double2 partial sums
-  DevBuf result;   // double2 results
+  DevBuf partial;   // double2 partial sums
+  DevBuf partial2;  // second partial buffer
+  DevBuf result;    // double2 results
   void ensure(size_t npart, size_t nres) {
     partial.ensure(npart * sizeof(double2));
     result.ensure(nres * sizeof(double2));
   }
+  void ensure2(size_t npart) { partial2.ensure(npart * sizeof(double2)); }
 };
 
 template <class S>
@@ -54,9 +57,14 @@ struct Blas {
   static void axpy_norm(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
                         int nrhs, double* out, RedWork& rw, hipStream_t st);
   // one Gram-Schmidt step: h = X^dag w (m vectors), w <- (w - X h) / beta with
-  // beta^2 = |w|^2 - |h|^2, n2[r] = beta^2 (device)
+  // beta^2 = |w|^2 - |h|^2, n2[r] = beta^2 (device); h needs (m + 1) * nrhs slots, slot m
+  // receives |w|^2 before the update
   static void cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
                         RedWork& rw, hipStream_t st);
+  // two Gram-Schmidt passes: h1 = X^dag w ; w -= X h1 ; h2 = X^dag w ; w -= X h2 ;
+  // n2[r] = |w|^2 ; w /= |w| (h1, h2, n2 on the device)
+  static void cgs2_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
+                        double2* h2, double* n2, RedWork& rw, hipStream_t st);
   // out[r] = ||w[r]||^2
   static void norm2(const void* w, size_t len, int nrhs, double* out, RedWork& rw, hipStream_t st);
   // w[r] += sgn * sum_i c[i * nrhs + r] X_i[r]

@@ -142,6 +142,24 @@ __device__ inline void stc(S* p, T i, cplx<U> v) {
   p[i] = StoreTraits<S>::st(cplx<C>{C(v.re), C(v.im)});
 }
 
+// P consecutive complex numbers moved as one 16-byte (or, for FP64, one-number) access;
+// pointers are to elements, indices to packs
+template <class S, int P>
+struct alignas(sizeof(S) * P) Pk {
+  S v[P];
+};
+template <class S>
+constexpr int kPack = sizeof(S) >= 16 ? 1 : int(16 / sizeof(S));
+
+template <class S, int P>
+__device__ inline Pk<S, P> ldp(const S* p, size_t pe) {
+  return reinterpret_cast<const Pk<S, P>*>(p)[pe];
+}
+template <class S, int P>
+__device__ inline void stp(S* p, size_t pe, const Pk<S, P>& v) {
+  reinterpret_cast<Pk<S, P>*>(p)[pe] = v;
+}
+
 inline size_t prec_bytes(qmg_prec p) {  // bytes per complex number
   switch (p) {
     case QMG_F64: return 16;

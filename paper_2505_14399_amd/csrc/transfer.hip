@@ -1,6 +1,7 @@
 // Transfer operators P and R = P^dagger (Eq. (6)), the Galerkin coarse operator D_c = R D P
 // (Eq. (5)) and its application, plus the layout kernels of the hierarchy.
 #include <cmath>
+#include <type_traits>
 
 #include "mg.hpp"
 #include "timing.hpp"
@@ -12,55 +13,142 @@ namespace {
 inline unsigned cdiv(size_t a, size_t b) { return unsigned((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------------------
-// prolong: one thread per (row of a (j, alpha) block), all k columns of P
-template <class S>
+// prolong: one thread per pack of PR rows of a (j, alpha) block, for NR right-hand sides; the
+// k coarse coefficients of those right-hand sides are staged in LDS, so P is read once per
+// group of right-hand sides.  Rows are s6 * nd + ib; the fine site is bsite[j][ib].
+template <class S, int PR, int NR>
 __global__ __launch_bounds__(256) void k_prolong(const S* __restrict__ P, const S* __restrict__ vc,
                                                  S* __restrict__ fine, const int* __restrict__ bsite, int nd, int N,
-                                                 int k, int d, int V) {
+                                                 int k, int d, int V, int nrhs) {
   using C = ctype<S>;
-  const int row = blockIdx.x * 256 + threadIdx.x;
+  __shared__ cplx<C> cv[NR][64];
   const int ja = blockIdx.y;  // j * 2 + alpha
-  const int rhs = blockIdx.z;
-  if (row >= N) return;
+  const int rhs0 = blockIdx.z * NR;
+  const int nr = min(NR, nrhs - rhs0);
   const int j = ja >> 1, a = ja & 1;
-  const int s6 = row / nd, ib = row - s6 * nd;
-  const S* Pc = P + size_t(ja) * k * N + row;
-  const S* v = vc + (size_t(rhs) * d + j) * 2 * k + a * k;
-  cplx<C> acc = {C(0), C(0)};
-  for (int i = 0; i < k; ++i) acc += ldc(Pc, size_t(i) * N) * ldc(v, i);
-  const int site = bsite[size_t(j) * nd + ib];
-  const int comp = 6 * a + s6;
-  stc(fine, (size_t(rhs) * 12 + comp) * V + site, acc);
-}
-
-// restrict: one workgroup per (j, alpha, rhs); the block of the fine vector is staged in LDS,
-// wavefront w reduces columns i = w, w+4, ... with lanes striding over rows
-template <class S>
-__global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const S* __restrict__ fine,
-                                                  S* __restrict__ vc, const int* __restrict__ bsite, int nd, int N,
-                                                  int k, int d, int V) {
-  using C = ctype<S>;
-  extern __shared__ unsigned char smem[];
-  cplx<C>* psi = reinterpret_cast<cplx<C>*>(smem);
-  const int ja = blockIdx.x, rhs = blockIdx.y;
-  const int j = ja >> 1, a = ja & 1;
-  for (int row = threadIdx.x; row < N; row += 256) {
+  for (int t = threadIdx.x; t < NR * k; t += 256) {
+    const int r = t / k, i = t - r * k;
+    cv[r][i] = r < nr ? ldc(vc, (size_t(rhs0 + r) * d + j) * 2 * k + a * k + i) : cplx<C>{C(0), C(0)};
+  }
+  __syncthreads();
+  const int rp = blockIdx.x * 256 + threadIdx.x;  // row pack
+  if (rp * PR >= N) return;
+  const S* Pc = P + size_t(ja) * k * N;
+  const size_t np = N / PR;
+  cplx<C> acc[NR][PR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int u = 0; u < PR; ++u) acc[r][u] = {C(0), C(0)};
+  int i = 0;
+  for (; i + 4 <= k; i += 4) {
+    Pk<S, PR> pv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pv[q] = ldp<S, PR>(Pc, size_t(i + q) * np + rp);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < PR; ++u) {
+        const cplx<C> pe = StoreTraits<S>::ld(pv[q].v[u]);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r][u] += pe * cv[r][i + q];
+      }
+  }
+  for (; i < k; ++i) {
+    const Pk<S, PR> pv = ldp<S, PR>(Pc, size_t(i) * np + rp);
+#pragma unroll
+    for (int u = 0; u < PR; ++u) {
+      const cplx<C> pe = StoreTraits<S>::ld(pv.v[u]);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r][u] += pe * cv[r][i];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PR; ++u) {
+    const int row = rp * PR + u;
     const int s6 = row / nd, ib = row - s6 * nd;
     const int site = bsite[size_t(j) * nd + ib];
-    psi[row] = ldc(fine, (size_t(rhs) * 12 + 6 * a + s6) * V + site);
+    const int comp = 6 * a + s6;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nr) stc(fine, (size_t(rhs0 + r) * 12 + comp) * V + site, acc[r][u]);
+  }
+}
+
+// restrict: one workgroup per (j, alpha, group of NR right-hand sides).  The block of each fine
+// vector is gathered into LDS; thread t takes row packs t, t + 256, ... and accumulates
+// conj(P) psi for eight columns at a time, which are then summed over the workgroup (wavefront
+// shuffles, then LDS across the four wavefronts).  P is read once per group.
+template <class S, int PR, int NR>
+__global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const S* __restrict__ fine,
+                                                  S* __restrict__ vc, const int* __restrict__ bsite, int nd, int N,
+                                                  int k, int d, int V, int nrhs) {
+  using C = ctype<S>;
+  constexpr int KC = 8;
+  extern __shared__ unsigned char smem[];
+  cplx<C>* psi = reinterpret_cast<cplx<C>*>(smem);  // [NR][N]
+  __shared__ cplx<C> red[4][KC * NR];
+  const int ja = blockIdx.x, rhs0 = blockIdx.y * NR;
+  const int nr = min(NR, nrhs - rhs0);
+  const int j = ja >> 1, a = ja & 1;
+  for (int t = threadIdx.x; t < NR * N; t += 256) {
+    const int r = t / N, row = t - r * N;
+    const int s6 = row / nd, ib = row - s6 * nd;
+    const int site = bsite[size_t(j) * nd + ib];
+    psi[t] = r < nr ? ldc(fine, (size_t(rhs0 + r) * 12 + 6 * a + s6) * V + site) : cplx<C>{C(0), C(0)};
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int i = w; i < k; i += 4) {
-    const S* Pc = P + (size_t(ja) * k + i) * N;
-    cplx<C> acc = {C(0), C(0)};
-    for (int row = lane; row < N; row += 64) acc += cmul_conj(ldc(Pc, row), psi[row]);
+  const size_t np = N / PR;
+  const S* Pb = P + size_t(ja) * k * N;
+  for (int i0 = 0; i0 < k; i0 += KC) {
+    const int kc = min(KC, k - i0);
+    cplx<C> acc[KC][NR];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.re += __shfl_down(acc.re, off, 64);
-      acc.im += __shfl_down(acc.im, off, 64);
+    for (int q = 0; q < KC; ++q)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[q][r] = {C(0), C(0)};
+    for (size_t rp = threadIdx.x; rp < np; rp += 256) {
+      Pk<S, PR> pv[KC];
+#pragma unroll
+      for (int q = 0; q < KC; ++q)
+        if (q < kc) pv[q] = ldp<S, PR>(Pb, size_t(i0 + q) * np + rp);
+#pragma unroll
+      for (int u = 0; u < PR; ++u) {
+        cplx<C> ps[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) ps[r] = psi[size_t(r) * N + rp * PR + u];
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+          if (q < kc) {
+            const cplx<C> pe = StoreTraits<S>::ld(pv[q].v[u]);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[q][r] += cmul_conj(pe, ps[r]);
+          }
+        }
+      }
     }
-    if (lane == 0) stc(vc, (size_t(rhs) * d + j) * 2 * k + a * k + i, acc);
+#pragma unroll
+    for (int q = 0; q < KC; ++q)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        cplx<C> v = acc[q][r];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          v.re += __shfl_down(v.re, off, 64);
+          v.im += __shfl_down(v.im, off, 64);
+        }
+        if (lane == 0) red[w][q * NR + r] = v;
+      }
+    __syncthreads();
+    if (threadIdx.x < kc * NR) {
+      const int q = threadIdx.x / NR, r = threadIdx.x - q * NR;
+      cplx<C> s = red[0][threadIdx.x];
+#pragma unroll
+      for (int ww = 1; ww < 4; ++ww) s += red[ww][threadIdx.x];
+      if (r < nr) stc(vc, (size_t(rhs0 + r) * d + j) * 2 * k + a * k + i0 + q, s);
+    }
+    __syncthreads();
   }
 }
 
@@ -506,15 +594,37 @@ void dispatch_prec(qmg_prec p, F&& f) {
 
 }  // namespace
 
+// pack width over the rows of P (N rows per column; every column starts at a multiple of N)
+template <class S>
+static int row_pack(int N) {
+  return (N % kPack<S> == 0) ? kPack<S> : 1;
+}
+
 void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const void* coarse, void* fine, int nrhs,
                     hipStream_t st) {
   TimedLaunch tl("prolong", st, double(h.g.V) * (12.0 * h.k + 12.0 * nrhs) * prec_bytes(prec),
                  8.0 * 12.0 * h.k * h.g.V * nrhs);
+  QMG_CHECK(h.k <= 64, QMG_EINVAL, "prolong: rank above 64");
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
-    dim3 grid(cdiv(h.blk.N, 256), 2 * h.blk.d, nrhs);
-    k_prolong<S><<<grid, 256, 0, st>>>((const S*)P, (const S*)coarse, (S*)fine, h.bsite.as<int>(), h.blk.nd,
-                                       h.blk.N, h.k, h.blk.d, h.g.V);
+    constexpr int PK = kPack<S>;
+    const bool packed = row_pack<S>(h.blk.N) == PK;
+    auto go = [&](auto pr, auto nrt) {
+      constexpr int PR = decltype(pr)::value, NR = decltype(nrt)::value;
+      dim3 grid(cdiv(h.blk.N / PR, 256), 2 * h.blk.d, cdiv(nrhs, NR));
+      k_prolong<S, PR, NR><<<grid, 256, 0, st>>>((const S*)P, (const S*)coarse, (S*)fine, h.bsite.as<int>(),
+                                                 h.blk.nd, h.blk.N, h.k, h.blk.d, h.g.V, nrhs);
+    };
+    using one = std::integral_constant<int, 1>;
+    using four = std::integral_constant<int, 4>;
+    using pk = std::integral_constant<int, PK>;
+    if (packed) {
+      if (nrhs >= 4) go(pk{}, four{});
+      else go(pk{}, one{});
+    } else {
+      if (nrhs >= 4) go(one{}, four{});
+      else go(one{}, one{});
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -525,10 +635,26 @@ void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const 
                  8.0 * 12.0 * h.k * h.g.V * nrhs);
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
-    const size_t lds = size_t(h.blk.N) * sizeof(cplx<ctype<S>>);
-    k_restrict<S><<<dim3(2 * h.blk.d, nrhs), 256, lds, st>>>((const S*)P, (const S*)fine, (S*)coarse,
-                                                              h.bsite.as<int>(), h.blk.nd, h.blk.N, h.k, h.blk.d,
-                                                              h.g.V);
+    constexpr int PK = kPack<S>;
+    const bool packed = row_pack<S>(h.blk.N) == PK;
+    auto go = [&](auto pr, auto nrt) {
+      constexpr int PR = decltype(pr)::value, NR = decltype(nrt)::value;
+      const size_t lds = size_t(NR) * h.blk.N * sizeof(cplx<ctype<S>>);
+      QMG_CHECK(lds <= 96 * 1024, QMG_EINVAL, "restrict: aggregate too large for LDS staging");
+      k_restrict<S, PR, NR><<<dim3(2 * h.blk.d, cdiv(nrhs, NR)), 256, lds, st>>>(
+          (const S*)P, (const S*)fine, (S*)coarse, h.bsite.as<int>(), h.blk.nd, h.blk.N, h.k, h.blk.d, h.g.V, nrhs);
+    };
+    using one = std::integral_constant<int, 1>;
+    using four = std::integral_constant<int, 4>;
+    using pk = std::integral_constant<int, PK>;
+    const bool multi = nrhs >= 4 && size_t(4) * h.blk.N * sizeof(cplx<ctype<S>>) <= 96 * 1024;
+    if (packed) {
+      if (multi) go(pk{}, four{});
+      else go(pk{}, one{});
+    } else {
+      if (multi) go(one{}, four{});
+      else go(one{}, one{});
+    }
   });
   QMG_LAUNCH_CHECK();
 }

@@ -1,6 +1,7 @@
 """GPU parity of the setup (smoother, streaming SVD), transfer, coarse operator, solve and force."""
 import numpy as np
 import pytest
+import torch
 
 import fields
 from fields import workloads
@@ -246,3 +247,41 @@ def test_solve_point_sources_multi_rhs(qmg, c1):
     X = np.linalg.solve(Dm, b.reshape(12, -1).T).T.reshape(b.shape)
     assert max(i["true_rel_res"] for i in info) <= 1e-12
     assert rel(to_np(x), X) < 1e-8
+
+
+@pytest.mark.parametrize("dims,block,k,inner,nrhs", [((4, 4, 4, 4), (2, 2, 2, 2), 8, "f64", 6),
+                                                     ((6, 4, 2, 6), (1, 1, 1, 3), 5, "f64", 5),
+                                                     ((8, 4, 4, 8), (4, 4, 2, 2), 12, "f32", 1),
+                                                     ((8, 4, 4, 8), (4, 4, 2, 2), 12, "f32", 6),
+                                                     ((6, 4, 2, 6), (2, 2, 1, 3), 5, "f32", 7)])
+def test_transfer_multi_rhs(qmg, dims, block, k, inner, nrhs):
+    """P and P^dagger on several right-hand sides (groups of four plus a ragged rest), FP64 and
+    the FP32 copy of P, against the oracle applied with the exported FP64 P."""
+    banner(f"transfer {dims} block={block} k={k} {inner} nrhs={nrhs}")
+    U = fields.random_gauge(dims, 0.5, 43)
+    r = 4
+    n_test = r * -(-k // r)
+    phi = fields.gaussian_test_vectors(dims, n_test, 43)
+    lat = qmg.Lattice(dims, -0.1, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, n_test, r, k, n_setup_iter=0, inner=inner,
+                                        test_vectors=to_gpu(phi))
+    P = to_np(mg.prolongator()[0])
+    d = P.shape[0]
+    vc = fields.gaussian_coarse(d * 2 * k, nrhs, 5).reshape(nrhs, d, 2, k)
+    psi = fields.gaussian_spinor(dims, nrhs, 6)
+    want_f = transfer.prolong(P, vc, dims, block)
+    want_c = transfer.restrict(P, psi, dims, block)
+    if inner == "f64":
+        tol = 1e-14
+        got_f = to_np(qmg.prolong(mg, to_gpu(vc)))
+        got_c = to_np(qmg.restrict(mg, to_gpu(psi)))
+    else:
+        # FP32 P and vectors, FP32 accumulation over at most 6 * nd rows
+        tol = 2e-6
+        got_f = to_np(qmg.prolong(mg, to_gpu(vc).to(torch.complex64)))
+        got_c = to_np(qmg.restrict(mg, to_gpu(psi).to(torch.complex64)))
+    print(f"[parity] prolong {rel(got_f, want_f):.2e} restrict {rel(got_c, want_c):.2e}")
+    for q in range(nrhs):
+        assert rel(got_f[q], want_f[q]) < tol
+        assert rel(got_c[q], want_c[q]) < tol
+    mg.close()
