@@ -10,8 +10,18 @@ coarse operator) followed by the MG-preconditioned solve of one Gaussian right-h
 Prints one JSON line.  `value` is the median mixed-precision solve time (s) over the timed
 steps; `roofline` describes the dominant kernel measured live with HIP events over the timed
 region; `cpu_baseline` is the CPU oracle timed on this host on a bounded sample.
+
+Counter runs: `bench.py --traffic-probe` runs a 256 MiB device copy (calibration) and then ten
+launches each of the solve's dslash and coarse apply in the solve's launch configuration; run it
+under `rocprofv3 --pmc FETCH_SIZE` and, separately, `--pmc WRITE_SIZE`, then
+`bench.py --traffic-from FETCH_DIR WRITE_DIR` writes profiles/traffic.json (bytes per launch,
+scaled by the copy calibration, with the SHA-256 of the kernel source) and a text summary.
+`roofline.traffic` is filled from that record while the kernel source is unchanged.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +32,25 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+COPY_BYTES = 256 << 20
+# timing family -> (kernel symbol prefix in counter output, source file)
+FAMILY_KERNEL = {
+    "dslash/dir": ("k_dslash_dir", "dslash.hip"),
+    "dslash/site": ("k_dslash<", "dslash.hip"),
+    "dslash/twalk": ("k_dslash_t<", "dslash.hip"),
+    "coarse_apply": ("k_coarse_apply", "transfer.hip"),
+    "restrict": ("k_restrict", "transfer.hip"),
+    "prolong": ("k_prolong", "transfer.hip"),
+    "coarse_build": ("k_build_coarse", "transfer.hip"),
+}
+FAMILIES = ("dslash/site", "dslash/twalk", "dslash/dir", "isvd", "coarse_apply", "prolong", "restrict",
+            "coarse_build")
+
+
+def source_sha(fname):
+    path = os.path.join(ROOT, "paper_2505_14399_amd", "csrc", fname)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
 def parse():
@@ -34,7 +63,127 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator solve")
     ap.add_argument("--mass", type=float, default=None, help="override the workload's quark mass")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="read rocprofv3 FETCH_SIZE / WRITE_SIZE counter output and write profiles/traffic.json")
     return ap.parse_args()
+
+
+def load_workload(args):
+    from fields import workloads
+    if args.mass is not None:
+        return dict(workloads.WORKLOADS[args.workload], name=args.workload, mass=args.mass)
+    return workloads.get(args.workload)
+
+
+def traffic_probe(args):
+    """Launch sequence measured by the counter runs (nothing is timed here)."""
+    import torch
+    import fields
+    import paper_2505_14399_amd as q
+
+    w = load_workload(args)
+    a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    dims = w["dims"]
+    lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
+    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
+    mg = q.mg_setup_stream_chiral_svd(lat, U, block=w["block"], n_test=w["n_test"], batch=w["batch"],
+                                      rank=w["rank"], n_setup_iter=16, inner=w["inner"], seed=w["seed"])
+    prec = w["inner"]
+    Un = q.pack_gauge(lat, U, prec)
+    x = q.pack_spinor(lat, torch.from_numpy(fields.gaussian_spinor(dims, 1, 1)).cuda(), prec)
+    y = torch.empty_like(x)
+    for i in range(10):  # the K-cycle's inner dslash: native layout, one right-hand side
+        q.wilson_apply(lat, Un, x if i % 2 == 0 else y, layout="native", out=y if i % 2 == 0 else x)
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    vc = torch.randn(1, mg.n_agg, 2, mg.rank, dtype=cdt, device="cuda")
+    wc = torch.empty_like(vc)
+    for i in range(10):
+        q.coarse_apply(mg, vc if i % 2 == 0 else wc, out=wc if i % 2 == 0 else vc)
+    torch.cuda.synchronize()
+    mg.close()
+    print(json.dumps({"probe": w["name"], "dims": list(dims), "prec": prec}), flush=True)
+
+
+def read_counter(d, counter):
+    """{kernel name: [per-dispatch counter values]} from a rocprofv3 --pmc output folder."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    out = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic_from(args):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the copy calibration; write the record."""
+    import numpy as np
+    w = load_workload(args)
+    fetch = read_counter(args.traffic_from[0], "FETCH_SIZE")
+    write = read_counter(args.traffic_from[1], "WRITE_SIZE")
+
+    def pick(tab, prefix):
+        for name, vals in tab.items():
+            short = name.replace("qmg::(anonymous namespace)::", "").split("void ")[-1]
+            if short.startswith(prefix):
+                return name, vals
+        return None, []
+
+    # the calibration copy: the runtime's device-to-device copy kernel at its largest dispatches
+    # (the three 256 MiB copies; the runtime's other copies are a few KiB)
+    def calib(tab):
+        vals = [v for n, vs in tab.items() if "copyBuffer" in n for v in vs]
+        if not vals:
+            raise SystemExit("no device copy dispatches in the counter output")
+        top = max(vals)
+        return float(np.median([v for v in vals if v >= 0.99 * top])) * 1024.0
+
+    copy_name = "__amd_rocclr_copyBuffer"
+    f_copy, w_copy = calib(fetch), calib(write)
+    f_scale, w_scale = COPY_BYTES / f_copy, COPY_BYTES / w_copy
+    rec = json.load(open(TRAFFIC_JSON)) if os.path.exists(TRAFFIC_JSON) else {}
+    lines = [f"# HBM-side traffic per launch, workload {w['name']} {w['dims']} inner {w['inner']}",
+             f"# copy calibration ({copy_name}): FETCH_SIZE {f_copy / 1024:.0f} KiB and WRITE_SIZE "
+             f"{w_copy / 1024:.0f} KiB for a {COPY_BYTES >> 20} MiB copy -> scale fetch x{f_scale:.3f}, "
+             f"write x{w_scale:.3f}"]
+    entry = rec.setdefault(w["name"], {})
+    for fam in ("dslash/dir", "dslash/site", "dslash/twalk", "coarse_apply"):
+        prefix, src = FAMILY_KERNEL[fam]
+        name, fv = pick(fetch, prefix)
+        _, wv = pick(write, prefix)
+        if not fv or not wv:
+            continue
+        fb = float(np.median(fv)) * 1024.0 * f_scale
+        wb = float(np.median(wv)) * 1024.0 * w_scale
+        entry[fam] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                      "dispatches": [len(fv), len(wv)], "kernel": name, "source": src,
+                      "source_sha256": source_sha(src)}
+        lines.append(f"{fam:14s} {name[:70]}: fetch {fb / 1e6:.2f} MB + write {wb / 1e6:.2f} MB = "
+                     f"{(fb + wb) / 1e6:.2f} MB per launch (median of {len(fv)}/{len(wv)} dispatches)")
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    json.dump(rec, open(TRAFFIC_JSON, "w"), indent=1)
+    print("\n".join(lines))
+
+
+def recorded_traffic(wname, fam):
+    """Bytes per launch from the committed counter record, None if absent or the source changed."""
+    if fam not in FAMILY_KERNEL or not os.path.exists(TRAFFIC_JSON):
+        return None
+    e = json.load(open(TRAFFIC_JSON)).get(wname, {}).get(fam)
+    if not e or e.get("source_sha256") != source_sha(FAMILY_KERNEL[fam][1]):
+        return None
+    return e["bytes_per_launch"]
 
 
 def cpu_baseline(w, counts):
@@ -61,11 +210,13 @@ def cpu_baseline(w, counts):
             f()
         return (time.perf_counter() - t0) / n
 
-    t_D = tm(lambda: wilson.apply_wilson(U, psi, w["mass"], w["xi"], w["bc_t"], dims), 3)
-    t_Dc = tm(lambda: coarse.coarse_apply(Y, vc, cd), 5)
-    t_RP = tm(lambda: transfer.prolong(P, transfer.restrict(P, psi[None], dims, block), dims, block), 2)
-    a, b = psi.ravel(), psi.ravel().copy()
-    t_vec = tm(lambda: (np.vdot(a, b), b + 0.5 * a), 5)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):  # one host thread: BLAS pools held to one thread
+        t_D = tm(lambda: wilson.apply_wilson(U, psi, w["mass"], w["xi"], w["bc_t"], dims), 3)
+        t_Dc = tm(lambda: coarse.coarse_apply(Y, vc, cd), 5)
+        t_RP = tm(lambda: transfer.prolong(P, transfer.restrict(P, psi[None], dims, block), dims, block), 2)
+        a, b = psi.ravel(), psi.ravel().copy()
+        t_vec = tm(lambda: (np.vdot(a, b), b + 0.5 * a), 5)
     est = (counts["dslash"] * t_D + counts["coarse_apply"] * t_Dc + counts["restrict"] * t_RP
            + counts["vector_ops"] * t_vec)
     try:
@@ -76,28 +227,30 @@ def cpu_baseline(w, counts):
         "value": est, "unit": "s", "cores": 1, "kind": "oracle",
         "sample": (f"oracle unit operations timed on this workload ({dims}, k={k}): Wilson D apply "
                    f"{t_D:.3f}s, coarse apply {t_Dc:.4f}s, restrict+prolong {t_RP:.3f}s, fine vector op "
-                   f"{t_vec:.4f}s; scaled by the GPU solve's operation counts {counts}; numpy stencil code "
-                   f"is single-threaded ({ncpu} host cpus visible)"),
+                   f"{t_vec:.4f}s; scaled by the GPU solve's operation counts {counts}; one thread (BLAS "
+                   f"pools limited to 1; {ncpu} host cpus visible)"),
     }
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part "
-              f"of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the solver path is not sharded "
+              f"across GPUs", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_from:
+        traffic_from(args)
+        return
+    if args.traffic_probe:
+        traffic_probe(args)
+        return
     import numpy as np
     import torch
 
     import fields
-    from fields import workloads
     import paper_2505_14399_amd as q
 
-    if args.mass is not None:
-        w = dict(workloads.WORKLOADS[args.workload], name=args.workload, mass=args.mass)
-    else:
-        w = workloads.get(args.workload)
+    w = load_workload(args)
     dims = w["dims"]
     lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
     U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
@@ -128,8 +281,8 @@ def main():
         infos.append(info)
     torch.cuda.synchronize()
     T1 = time.perf_counter()
-    fams = {f: q.timing_query(f) for f in ("dslash", "isvd", "coarse_apply", "prolong", "restrict",
-                                           "coarse_build")}
+    fams = {f: q.timing_query(f) for f in FAMILIES}
+    ds = q.timing_query("dslash")
     q.timing_enable(False)
     for i in infos:
         if i["true_rel_res"] > args.tol:
@@ -160,7 +313,6 @@ def main():
 
     # dominant kernel by summed device time in the timed region
     dom = max(fams, key=lambda f: fams[f]["ms"])
-    ds = fams["dslash"]
     ds_avg_ms = ds["ms"] / max(1, ds["launches"])
     ds_gbps = ds["bytes"] / max(1, ds["launches"]) / (ds_avg_ms * 1e-3) / 1e9
     fam = fams[dom]
@@ -170,9 +322,11 @@ def main():
         roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "kernel": "isvd", "avg_launch_ms": avg_ms}
     else:
-        ach = fam["bytes"] / max(1, fam["launches"]) / (avg_ms * 1e-3) / 1e9
+        per_launch = fam["bytes"] / max(1, fam["launches"])
+        ach = per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBPS,
-                "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms}
+                "traffic": recorded_traffic(w["name"], dom), "kernel": dom, "avg_launch_ms": avg_ms,
+                "algorithmic_bytes_per_launch": per_launch}
 
     res = {
         "metric": "MG solve s to rel.res 1e-10 (mixed vs FP64); dslash HBM GB/s; setup s",
@@ -195,7 +349,7 @@ def main():
         "solve_info": infos[-1],
         "dslash": {"launches": ds["launches"], "avg_launch_us": ds_avg_ms * 1e3, "GBps": ds_gbps,
                    "frac_hbm": ds_gbps / PEAK_HBM_GBPS},
-        "kernel_ms_per_step": {f: fams[f]["ms"] / args.steps for f in fams},
+        "kernel_ms_per_step": {f: fams[f]["ms"] / args.steps for f in fams if fams[f]["launches"]},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

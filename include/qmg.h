@@ -184,10 +184,11 @@ qmg_status qmg_mg_get_coarse(const qmg_mg* mg, void* Y, hipStream_t stream);
 qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);
 
 /* Measurement hooks.  qmg_timing_enable(1) clears the record and brackets every later launch
- * of the instrumented kernel families ("dslash", "isvd", "coarse_apply", "prolong",
- * "restrict", "coarse_build") with HIP events on its stream; 0 stops recording.
- * qmg_timing_query returns, for one family, the launches recorded, their summed duration
- * (ms, it synchronizes on the events) and the summed algorithmic bytes and flops. */
+ * of the instrumented kernel families ("dslash/site", "dslash/twalk", "dslash/dir",
+ * "dslash/canonical", "isvd", "coarse_apply", "prolong", "restrict", "coarse_build") with HIP
+ * events on its stream; 0 stops recording.  qmg_timing_query returns, for one family, the
+ * launches recorded, their summed duration (ms, it synchronizes on the events) and the summed
+ * algorithmic bytes and flops; a name without '/' also sums its sub-families ("dslash"). */
 qmg_status qmg_timing_enable(int32_t on);
 qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total_ms, double* algo_bytes,
                             double* algo_flops);

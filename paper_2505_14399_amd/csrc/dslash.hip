@@ -401,9 +401,9 @@ template <class S>
 void launch_dir(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
   dim3 grid(unsigned((a.V + kBlock / 4 - 1) / (kBlock / 4)) * unsigned(a.nrhs));
   if (a.dagger)
-    k_dslash_dir<S, true><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a);
+    launch(k_dslash_dir<S, true>, grid, dim3(kBlock), 0, st, U, in, out, a);
   else
-    k_dslash_dir<S, false><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a);
+    launch(k_dslash_dir<S, false>, grid, dim3(kBlock), 0, st, U, in, out, a);
   QMG_LAUNCH_CHECK();
 }
 
@@ -411,9 +411,9 @@ template <class S, bool CANON, int NR>
 void launch_t(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
   dim3 grid(unsigned((a.V + kBlock - 1) / kBlock) * unsigned(a.nrhs / NR));
   if (a.dagger)
-    k_dslash<S, CANON, NR, true><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a);
+    launch(k_dslash<S, CANON, NR, true>, grid, dim3(kBlock), 0, st, U, in, out, a);
   else
-    k_dslash<S, CANON, NR, false><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a);
+    launch(k_dslash<S, CANON, NR, false>, grid, dim3(kBlock), 0, st, U, in, out, a);
   QMG_LAUNCH_CHECK();
 }
 
@@ -424,15 +424,17 @@ void launch_tw(const void* U, const void* in, void* out, const DslashArgs& a, hi
   const int nchunk = a.L[3] / TCH;
   dim3 grid(unsigned(ntile_s * nchunk * a.nrhs));
   if (a.dagger)
-    k_dslash_t<S, TCH, true><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a, ntile_s);
+    launch(k_dslash_t<S, TCH, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s);
   else
-    k_dslash_t<S, TCH, false><<<grid, kBlock, 0, st>>>((const S*)U, (const S*)in, (S*)out, a, ntile_s);
+    launch(k_dslash_t<S, TCH, false>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s);
   QMG_LAUNCH_CHECK();
 }
 
 template <class S>
 void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
   if (a.canonical) {
+    TimedLaunch tl("dslash/canonical", st, double(a.V) * (24.0 * a.nrhs + 36.0) * double(sizeof(S)),
+                   1368.0 * a.V * a.nrhs);
     launch_t<S, true, 1>(U, in, out, a, st);
     return;
   }
@@ -444,7 +446,11 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   const int Vs = a.L[0] * a.L[1] * a.L[2];
   const long wg1 = long((Vs + kBlock - 1) / kBlock) * a.nrhs;  // workgroups per t-slice
   const int Lt = a.L[3];
+  // algorithmic traffic: spinor in + out (2 x 12 complex per site and rhs) + 4 links per site
+  const double cb = double(sizeof(S));
+  const double bytes = double(a.V) * (24.0 * a.nrhs + 36.0) * cb, flops = 1368.0 * a.V * a.nrhs;
   auto run = [&](int v) {
+    TimedLaunch tl(v == 16 ? "dslash/dir" : v > 1 ? "dslash/twalk" : "dslash/site", st, bytes, flops);
     switch (v) {
       case 8: launch_tw<S, 8>(U, in, out, a, st); break;
       case 4: launch_tw<S, 4>(U, in, out, a, st); break;
@@ -484,9 +490,6 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
 
 void launch_dslash(qmg_prec prec, const void* U, const void* in, void* out, const DslashArgs& a,
                    hipStream_t st) {
-  // algorithmic traffic: spinor in + out (2 x 12 complex per site and rhs) + 4 links per site
-  const double cb = double(prec_bytes(prec));
-  TimedLaunch tl("dslash", st, double(a.V) * (24.0 * a.nrhs + 36.0) * cb, 1368.0 * a.V * a.nrhs);
   switch (prec) {
     case QMG_F64: launch_s<double2>(U, in, out, a, st); break;
     case QMG_F32: launch_s<float2>(U, in, out, a, st); break;

@@ -445,7 +445,7 @@ int isvd_stream(HierarchyDev& h, const void* blocks, int r, int kp, DevBuf& sigm
   const double Nn = double(a.N) * a.nprob;
   {
     TimedLaunch tl("isvd", st, Nn * 16.0 * (3.0 * (kp + r) + kn),
-                   Nn * 8.0 * (2.0 * double(w) * r + double(kp) * r + double(w) * kn));
+                   Nn * 8.0 * (2.0 * double(w) * r + double(kp) * r + double(w) * kn), false);
     const int need = (w * CH + T - 1) / T;  // prefetch registers needed
     if (need <= 4) launch_rows<4>(a, ncu, lg, lr, h, blocks, small, AB, sigma_dev, ls, st);
     else if (need <= 8) launch_rows<8>(a, ncu, lg, lr, h, blocks, small, AB, sigma_dev, ls, st);

@@ -1,6 +1,8 @@
-// Optional per-kernel-family timing: when enabled, each launch of an instrumented kernel is
-// bracketed by a pair of HIP events recorded on the launch stream, and the launcher adds the
-// algorithmic bytes and flops of that launch.  Off by default (no events are recorded).
+// Optional per-kernel-family timing: when enabled, each launch of an instrumented kernel gets
+// a pair of HIP events (attached to the dispatch itself, so they hold the kernel's own start
+// and end), and the launcher adds the algorithmic bytes and flops of that launch.  Off by default (no events are recorded).
+// Family names may have a sub-name after '/' (one per launch form, e.g. "dslash/dir"); a query
+// for "dslash" sums every "dslash/..." family.
 #include <map>
 #include <mutex>
 #include <string>
@@ -33,19 +35,44 @@ hipEvent_t get_event() {
 
 bool timing_on() { return g_on; }
 
-TimedLaunch::TimedLaunch(const char* family, hipStream_t st, double bytes, double flops)
-    : fam_(family), st_(st), bytes_(bytes), flops_(flops) {
+namespace {
+thread_local TimedLaunch* t_current = nullptr;
+}
+
+TimedLaunch* TimedLaunch::current() { return t_current; }
+
+TimedLaunch::TimedLaunch(const char* family, hipStream_t st, double bytes, double flops, bool kernel)
+    : fam_(family), st_(st), bytes_(bytes), flops_(flops), kernel_(kernel) {
+  prev_ = t_current;
+  t_current = this;
   if (!g_on) return;
   std::lock_guard<std::mutex> lk(g_mu);
   e0_ = get_event();
   e1_ = get_event();
-  QMG_HIP(hipEventRecord(e0_, st_));
+  if (!kernel_) {
+    QMG_HIP(hipEventRecord(e0_, st_));
+    taken_ = true;
+  }
+}
+
+bool TimedLaunch::take(hipEvent_t* e0, hipEvent_t* e1) {
+  if (!e0_ || taken_ || !kernel_) return false;
+  taken_ = true;
+  *e0 = e0_;
+  *e1 = e1_;
+  return true;
 }
 
 TimedLaunch::~TimedLaunch() {
+  t_current = prev_;
   if (!e0_) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  (void)hipEventRecord(e1_, st_);
+  if (!taken_) {  // nothing was launched through qmg::launch: return the events unused
+    g_pool.push_back(e0_);
+    g_pool.push_back(e1_);
+    return;
+  }
+  if (!kernel_) (void)hipEventRecord(e1_, st_);
   Family& f = g_fam[fam_];
   f.ev.emplace_back(e0_, e1_);
   f.bytes += bytes_;
@@ -65,21 +92,23 @@ void timing_enable(bool on) {
 
 void timing_query(const char* family, int64_t* n, double* ms, double* bytes, double* flops) {
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_fam.find(family);
   *n = 0;
   *ms = 0;
   *bytes = 0;
   *flops = 0;
-  if (it == g_fam.end()) return;
-  for (auto& p : it->second.ev) {
-    QMG_HIP(hipEventSynchronize(p.second));
-    float t = 0;
-    QMG_HIP(hipEventElapsedTime(&t, p.first, p.second));
-    *ms += t;
+  const std::string q(family), pre = q + "/";
+  for (auto& kv : g_fam) {
+    if (kv.first != q && kv.first.compare(0, pre.size(), pre) != 0) continue;
+    for (auto& p : kv.second.ev) {
+      QMG_HIP(hipEventSynchronize(p.second));
+      float t = 0;
+      QMG_HIP(hipEventElapsedTime(&t, p.first, p.second));
+      *ms += t;
+    }
+    *n += int64_t(kv.second.ev.size());
+    *bytes += kv.second.bytes;
+    *flops += kv.second.flops;
   }
-  *n = int64_t(it->second.ev.size());
-  *bytes = it->second.bytes;
-  *flops = it->second.flops;
 }
 
 }  // namespace qmg

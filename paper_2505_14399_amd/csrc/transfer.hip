@@ -612,8 +612,8 @@ void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const v
     auto go = [&](auto pr, auto nrt) {
       constexpr int PR = decltype(pr)::value, NR = decltype(nrt)::value;
       dim3 grid(cdiv(h.blk.N / PR, 256), 2 * h.blk.d, cdiv(nrhs, NR));
-      k_prolong<S, PR, NR><<<grid, 256, 0, st>>>((const S*)P, (const S*)coarse, (S*)fine, h.bsite.as<int>(),
-                                                 h.blk.nd, h.blk.N, h.k, h.blk.d, h.g.V, nrhs);
+      launch(k_prolong<S, PR, NR>, grid, dim3(256), 0, st, P, coarse, fine, h.bsite.as<int>(), h.blk.nd, h.blk.N,
+             h.k, h.blk.d, h.g.V, nrhs);
     };
     using one = std::integral_constant<int, 1>;
     using four = std::integral_constant<int, 4>;
@@ -641,8 +641,8 @@ void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const 
       constexpr int PR = decltype(pr)::value, NR = decltype(nrt)::value;
       const size_t lds = size_t(NR) * h.blk.N * sizeof(cplx<ctype<S>>);
       QMG_CHECK(lds <= 96 * 1024, QMG_EINVAL, "restrict: aggregate too large for LDS staging");
-      k_restrict<S, PR, NR><<<dim3(2 * h.blk.d, cdiv(nrhs, NR)), 256, lds, st>>>(
-          (const S*)P, (const S*)fine, (S*)coarse, h.bsite.as<int>(), h.blk.nd, h.blk.N, h.k, h.blk.d, h.g.V, nrhs);
+      launch(k_restrict<S, PR, NR>, dim3(2 * h.blk.d, cdiv(nrhs, NR)), dim3(256), uint32_t(lds), st, P, fine,
+             coarse, h.bsite.as<int>(), h.blk.nd, h.blk.N, h.k, h.blk.d, h.g.V, nrhs);
     };
     using one = std::integral_constant<int, 1>;
     using four = std::integral_constant<int, 4>;
@@ -669,8 +669,8 @@ void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, co
     const int threads = int(std::min<size_t>(1024, ((size_t(9) * m + 63) / 64) * 64));
     auto go = [&](auto kern, int NR) {
       const size_t lds = size_t(2) * NR * 9 * m * sizeof(cplx<ctype<S>>);
-      kern<<<dim3(h.blk.d, (nrhs + NR - 1) / NR), threads, lds, st>>>((const S*)Y, (const S*)in, (S*)out,
-                                                                       h.cnb.as<int>(), h.blk.d, m, nrhs);
+      launch(kern, dim3(h.blk.d, (nrhs + NR - 1) / NR), dim3(threads), uint32_t(lds), st, Y, in, out,
+             h.cnb.as<int>(), h.blk.d, m, nrhs);
     };
     if (nrhs >= 4) go(k_coarse_apply<S, 4>, 4);
     else if (nrhs == 2) go(k_coarse_apply<S, 2>, 2);
@@ -696,7 +696,7 @@ void build_coarse(HierarchyDev& h, hipStream_t st) {
   a.bc_t = h.g.bc_t;
   a.diag = h.g.diag();
   TimedLaunch tl("coarse_build", st, double(h.g.V) * 12.0 * h.k * 16.0 + 9.0 * h.blk.d * 4.0 * h.k * h.k * 16.0,
-                 double(h.g.V) * 8.0 * (2.0 * h.k) * (2.0 * h.k) * 6.0 * 8.0);
+                 double(h.g.V) * 8.0 * (2.0 * h.k) * (2.0 * h.k) * 6.0 * 8.0, false);
   const int nent = 4 * h.k * h.k;
   DevBuf W(size_t(8) * h.blk.d * nent * sizeof(double2));
   // per site: Px (12 k) + HP (24 k) + link (9) complex, + coefficient and 5 ints

@@ -1,11 +1,16 @@
 """Write tests/golden/tuned_masses.json: the quark masses of the near-critical workloads.
 
 Reading of "mass tuned so that |lambda_min| ~ 1e-3": since D(m) = D(0) + m, find the
-eigenvalue lambda* of D(0) with the smallest real part (ARPACK, which='SR', on the oracle's
-stencil) and set m = -Re(lambda*) + 1e-3.  For the 24^3 x 64 lattice ("m near critical") the
-same search runs on a 12^3 x 16 lattice with the same roughness and seed (the critical mass is
-intensive).  ARPACK runs on a sparse matrix assembled from the oracle's hop definition and the margin is 2e-2, so that D(m) on the large lattice keeps its spectrum in the
-right half plane.  Uses only oracle/ and fields/.  Run: python tests/golden/make_tuned_masses.py
+eigenvalue lambda* of D(0) with the smallest real part (ARPACK, which='SR', on a sparse matrix
+assembled from the oracle's hop definition) and set m = -Re(lambda*) + margin.  On these rough
+random gauge fields the leftmost eigenvalues come as a complex-conjugate pair with imaginary
+part ~0.1, so no real mass brings |lambda_min| to 1e-3; the margin instead puts the left edge
+of the spectrum just inside the right half plane.  The critical mass is intensive, and ARPACK's
+'SR' search does not finish in reasonable time on the full lattices, so the search runs on a
+smaller lattice with the same roughness, anisotropy and seed (8^3 x 16 for the anisotropic
+16^3 x 32 workload, 12^3 x 16 for the isotropic 24^3 x 64 one), with a margin that covers the
+finite-volume shift of the edge.  Uses only oracle/ and fields/.
+Run: python tests/golden/make_tuned_masses.py
 """
 import json
 import os
@@ -80,7 +85,7 @@ def main():
     out = {}
     if os.path.exists(OUT):
         out = json.load(open(OUT))
-    for name, small, margin in (("aniso16x32_fp32", None, 1e-3), ("iso24x64_bf16", (12, 12, 12, 16), 2e-2)):
+    for name, small, margin in (("aniso16x32_fp32", (8, 8, 8, 16), 1.5e-2), ("iso24x64_bf16", (12, 12, 12, 16), 2e-2)):
         w = WORKLOADS[name]
         dims = small or w["dims"]
         vals = leftmost(dims, w["eps"], w["xi"], w["bc_t"], w["seed"], w["tag"])
