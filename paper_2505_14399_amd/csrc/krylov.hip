@@ -275,6 +275,103 @@ __device__ inline void store_partials(double2 (&acc)[MG], int mi, double2* parti
   }
 }
 
+// Least-squares state of restarted GMRES, one thread per right-hand side, kept on the device
+// so that a fixed-length cycle needs no host round trip.  Per rhs (double2 slots):
+//   cs[m] (real in .x), sn[m], g[m+1], R[m*m] (upper triangle, column-major), {valid, stopped}
+//   and |b| (in .x).
+__host__ __device__ inline size_t gv_stride(int m) { return size_t(m) * m + 3 * size_t(m) + 3; }
+
+struct GvView {
+  double2* base;
+  int m;
+  __device__ double2* cs() const { return base; }
+  __device__ double2* sn() const { return base + m; }
+  __device__ double2* g() const { return base + 2 * m; }
+  __device__ double2* R() const { return base + 3 * m + 1; }
+  __device__ double2& flags() const { return base[size_t(m) * m + 3 * m + 1]; }
+  __device__ double2& bn() const { return base[size_t(m) * m + 3 * m + 2]; }
+};
+
+__device__ inline double cabs2(double2 a) { return sqrt(a.x * a.x + a.y * a.y); }
+__device__ inline double2 cmul2(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cconj2(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline double2 cscale2(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ inline double2 cadd2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 cdiv2(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+__device__ inline double2 shfl2(double2 v, int src) {
+  return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+// One Givens step of the GMRES least-squares problem, executed by one whole wavefront (lane
+// i holds entry i of Hessenberg column j in hl, i <= j; hsub = h[j+1]): applies the previous
+// rotations in order through lane broadcasts, forms rotation j, stores column j of R and
+// updates g; lane 0 writes (|g[j]|, |g[j+1]|) / |b| to *est.  m <= 64.
+__device__ inline void gv_apply(GvView v, double2 hl, double2 hsub, int j, int lane, double2* est) {
+  double2* g = v.g();
+  const double2 fl = v.flags();
+  const int valid = int(fl.x);
+  const double bn = v.bn().x;
+  const double inv_bn = bn > 0.0 ? 1.0 / bn : 0.0;
+  const double before = cabs2(g[valid]) * inv_bn;
+  if (fl.y != 0.0) {  // stopped earlier in this cycle
+    if (lane == 0) *est = make_double2(before, before);
+    return;
+  }
+  double2 csl = make_double2(0.0, 0.0), snl = make_double2(0.0, 0.0);
+  if (lane < j) {
+    csl = v.cs()[lane];
+    snl = v.sn()[lane];
+  }
+  double2* R = v.R();
+  const int m = v.m;
+  // cur = h[i] after rotations 0..i-1; rotation i mixes it with h[i+1]
+  double2 cur = shfl2(hl, 0);
+  for (int i = 0; i < j; ++i) {
+    const double2 nxt = shfl2(hl, i + 1);
+    const double ci = __shfl(csl.x, i, 64);
+    const double2 si = shfl2(snl, i);
+    const double2 t = cadd2(cscale2(ci, cur), cmul2(si, nxt));
+    cur = cadd2(cscale2(-1.0, cmul2(cconj2(si), cur)), cscale2(ci, nxt));
+    if (lane == 0) R[size_t(j) * m + i] = t;
+  }
+  if (lane != 0) return;
+  const double2 a = cur, b = hsub;
+  const double aa = cabs2(a), bb = cabs2(b);
+  const double den = sqrt(aa * aa + bb * bb);
+  if (den == 0.0 || !isfinite(den)) {  // singular column: the cycle stops before it
+    v.flags() = make_double2(double(valid), 1.0);
+    *est = make_double2(before, isfinite(den) ? before : den);
+    return;
+  }
+  double2 c, sn;
+  if (aa == 0.0) {
+    c = make_double2(0.0, 0.0);
+    sn = cscale2(1.0 / bb, cconj2(b));
+  } else {
+    c = make_double2(aa / den, 0.0);
+    sn = cscale2(1.0 / den, cmul2(cscale2(1.0 / aa, a), cconj2(b)));
+  }
+  v.cs()[j] = c;
+  v.sn()[j] = sn;
+  R[size_t(j) * m + j] = cadd2(cscale2(c.x, a), cmul2(sn, b));
+  const double2 gj = g[j];
+  g[j + 1] = cscale2(-1.0, cmul2(cconj2(sn), gj));
+  g[j] = cscale2(c.x, gj);
+  v.flags() = make_double2(double(j + 1), bb == 0.0 ? 1.0 : 0.0);  // exact breakdown stops
+  *est = make_double2(before, cabs2(g[j + 1]) * inv_bn);
+}
+
+// Givens step fused into the last kernel of an Arnoldi step (gst == nullptr: none)
+struct GvFuse {
+  double2* gst;
+  int m, j;
+  double2* est;
+};
+
 // Where a kernel finds its per-rhs coefficients c_i (i < n): finalised values fin[i * nrhs + r],
 // or, when partial is set, the per-workgroup partial sums partial[(i * nrhs + r) * nblk + q]
 // (q < nblk) of the previous kernel, which every consumer workgroup sums itself in the same
@@ -459,7 +556,7 @@ __global__ __launch_bounds__(RB) void k_mdot_norm(const S* __restrict__ X, size_
 template <class S, int P>
 __global__ __launch_bounds__(256) void k_axpy_scale(const S* __restrict__ X, size_t xstride_p, int m, CoefSrc csrc,
                                                     S* __restrict__ w, size_t np, int nrhs,
-                                                    double* __restrict__ out_n2) {
+                                                    double* __restrict__ out_n2, GvFuse gf) {
   using C = ctype<S>;
   const int r = blockIdx.y;
   __shared__ double2 s_c[kMaxCoef];
@@ -469,6 +566,12 @@ __global__ __launch_bounds__(256) void k_axpy_scale(const S* __restrict__ X, siz
   b2 = fmax(b2, 0.0);
   const double inv = b2 > 0.0 ? 1.0 / sqrt(b2) : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) out_n2[r] = b2;
+  if (gf.gst && blockIdx.x == 0 && threadIdx.x < 64) {  // Hessenberg column j = (h, beta)
+    const int lane = threadIdx.x;
+    const double2 hl = lane <= gf.j ? s_c[lane] : make_double2(0.0, 0.0);
+    gv_apply(GvView{gf.gst + r * gv_stride(gf.m), gf.m}, hl, make_double2(sqrt(b2), 0.0), gf.j, lane,
+             gf.est + r);
+  }
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= np) return;
   const size_t off = size_t(r) * np + e;
@@ -513,6 +616,11 @@ bool packable(size_t len, size_t xstride, std::initializer_list<const void*> ptr
   for (const void* p : ptrs)
     if (reinterpret_cast<uintptr_t>(p) % 16) return false;
   return true;
+}
+
+template <class S>
+bool packable_vec(size_t len, const void* p) {
+  return packable<S>(len, 0, {p});
 }
 
 // Short vectors (the coarse level) are latency bound: there the consumer of a reduction sums
@@ -608,7 +716,7 @@ struct BlasP {
     QMG_LAUNCH_CHECK();
   }
   static void cgs1(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
-                   RedWork& rw, hipStream_t st) {
+                   RedWork& rw, hipStream_t st, GvFuse gf) {
     const size_t np = len / P;
     const int ng = (m + MG - 1) / MG;
     const bool small = len <= kSmallLen;
@@ -625,7 +733,8 @@ struct BlasP {
       k_finalize2<<<(m + 1) * nrhs, RB, 0, st>>>(part, nblk, h);
       QMG_LAUNCH_CHECK();
     }
-    k_axpy_scale<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, src, (S*)w, np, nrhs, n2);
+    k_axpy_scale<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, src, (S*)w, np, nrhs, n2,
+                                                               gf);
     QMG_LAUNCH_CHECK();
   }
   static void cgs2_small(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
@@ -739,17 +848,19 @@ void Blas<S>::axpy_norm(const void* X, size_t xstride, int m, const double2* c, 
   QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_then(1, X, xstride, m, c, sgn, w, len, nrhs, out, rw, st));
 }
 template <class S>
-void Blas<S>::cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
-                        RedWork& rw, hipStream_t st) {
+bool Blas<S>::cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
+                        RedWork& rw, hipStream_t st, double2* gst, int gm, double2* est) {
   QMG_CHECK(m >= 1, QMG_EINVAL, "Gram-Schmidt step: no basis vectors");
-  if (m + 1 > kMaxCoef) {  // long bases: explicit update and norm instead of Pythagoras
+  if (m + 1 > kMaxCoef || m > 64) {  // long bases: explicit update and norm instead of Pythagoras
     mdot(X, xstride, m, w, len, nrhs, h, rw, st);
     axpy_multi(X, xstride, m, h, -1.0, w, len, nrhs, st);
     norm2(w, len, nrhs, n2, rw, st);
     scale_dev(w, n2, 0, len, nrhs, st);
-    return;
+    return false;
   }
-  QMG_PACKED(packable<S>(len, xstride, {X, w}), cgs1(X, xstride, m, w, len, nrhs, h, n2, rw, st));
+  const GvFuse gf{gst, gm, m - 1, est};
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), cgs1(X, xstride, m, w, len, nrhs, h, n2, rw, st, gf));
+  return gst != nullptr;
 }
 template <class S>
 void Blas<S>::cgs2_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
@@ -785,66 +896,86 @@ void Gmres<S>::ensure(size_t len, int nrhs, int restart) {
   V_.ensure(size_t(restart_ + 1) * nrhs_ * len_ * sizeof(S));
   h1_.ensure(size_t(restart_ + 1) * nrhs_ * sizeof(double2));
   h2_.ensure(size_t(restart_ + 1) * nrhs_ * sizeof(double2));
-  nrm_.ensure(size_t(nrhs_) * sizeof(double));
+  nrm_.ensure(size_t(2 * nrhs_) * sizeof(double));
   y_.ensure(size_t(restart_ + 1) * nrhs_ * sizeof(double2));
   r_.ensure(size_t(nrhs_) * len_ * sizeof(S));
 }
 
 namespace {
-// one Givens step on column j of a Hessenberg matrix (column-major h[0..j+1])
-struct GivensState {
-  std::vector<double> cs;
-  std::vector<zc> sn, g, R;  // R: upper triangle, column-major (m x m)
-  int m = 0, valid = 0;
-  bool stopped = false;
-  void init(int m_, double beta) {
-    m = m_;
-    cs.assign(m, 0.0);
-    sn.assign(m, 0.0);
-    g.assign(m + 1, 0.0);
-    R.assign(size_t(m) * m, 0.0);
-    g[0] = beta;
-    valid = 0;
-    stopped = (beta == 0.0);
-  }
-  // h has j+2 entries; returns |g[j+1]|
-  double step(int j, zc* h) {
-    if (stopped) return std::abs(g[valid]);
-    for (int i = 0; i < j; ++i) {
-      zc t = cs[i] * h[i] + sn[i] * h[i + 1];
-      h[i + 1] = -std::conj(sn[i]) * h[i] + cs[i] * h[i + 1];
-      h[i] = t;
-    }
-    const zc a = h[j], b = h[j + 1];
-    const double den = std::sqrt(std::norm(a) + std::norm(b));
-    if (den == 0.0 || !std::isfinite(den)) {  // singular column: stop this cycle before it
-      stopped = true;
-      return std::abs(g[valid]);
-    }
-    if (std::abs(a) == 0.0) {
-      cs[j] = 0.0;
-      sn[j] = std::conj(b) / std::abs(b);
-    } else {
-      cs[j] = std::abs(a) / den;
-      sn[j] = (a / std::abs(a)) * std::conj(b) / den;
-    }
-    h[j] = cs[j] * a + sn[j] * b;
-    for (int i = 0; i <= j; ++i) R[size_t(j) * m + i] = h[i];
-    g[j + 1] = -std::conj(sn[j]) * g[j];
-    g[j] = cs[j] * g[j];
-    valid = j + 1;
-    if (std::abs(b) == 0.0) stopped = true;  // exact (lucky) breakdown
-    return std::abs(g[j + 1]);
-  }
-  void solve(std::vector<zc>& y) const {
-    y.assign(m, 0.0);
-    for (int i = valid - 1; i >= 0; --i) {
-      zc s = g[i];
-      for (int l = i + 1; l < valid; ++l) s -= R[size_t(l) * m + i] * y[l];
-      y[i] = s / R[size_t(i) * m + i];
+// Start of a cycle, fused with the normalisation of the first basis vector:
+// w[r] /= beta_r with beta_r^2 = nr2[r]; workgroup (0, r) resets the rotations of rhs r with
+// g = (beta_r, 0, ...) and, when nb2 is given, stores |b_r| = sqrt(nb2[r]).
+template <class S, int P>
+__global__ void k_gv_start(S* __restrict__ w, const double* __restrict__ nr2, size_t np, double2* st, int m,
+                           const double* __restrict__ nb2) {
+  using C = ctype<S>;
+  const int r = blockIdx.y;
+  const double beta2 = nr2[r];
+  const double beta = sqrt(beta2);
+  if (blockIdx.x == 0) {
+    GvView v{st + r * gv_stride(m), m};
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) v.g()[i] = make_double2(i == 0 ? beta : 0.0, 0.0);
+    if (threadIdx.x == 0) {
+      v.flags() = make_double2(0.0, beta == 0.0 ? 1.0 : 0.0);
+      if (nb2) v.bn() = make_double2(sqrt(nb2[r]), 0.0);
     }
   }
-};
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= np) return;
+  const double f = beta2 > 0.0 ? 1.0 / beta : 0.0;
+  const size_t off = size_t(r) * np + e;
+  auto wv = ldp<S, P>(w, off);
+#pragma unroll
+  for (int u = 0; u < P; ++u) wv.v[u] = StoreTraits<S>::st(C(f) * StoreTraits<S>::ld(wv.v[u]));
+  stp<S, P>(w, off, wv);
+}
+
+// Arnoldi column j of rhs r, staged in a separate buffer (h1 [(m+1) nrhs], h2 [(m+1) nrhs] if
+// two passes, |w|^2 [nrhs] as doubles) -> rotations; one wavefront per rhs.
+__global__ __launch_bounds__(64) void k_gv_step(double2* st, int m, int nrhs, int j, const double2* col,
+                                                int two_pass, double2* est) {
+  const int r = blockIdx.x, lane = threadIdx.x;
+  const double2* h1 = col;
+  const double2* h2 = col + size_t(m + 1) * nrhs;
+  const double* cn = reinterpret_cast<const double*>(col + size_t(2 * (m + 1)) * nrhs);
+  double2 hl = make_double2(0.0, 0.0);
+  if (lane <= j) {
+    hl = h1[size_t(lane) * nrhs + r];
+    if (two_pass) hl = cadd2(hl, h2[size_t(lane) * nrhs + r]);
+  }
+  gv_apply(GvView{st + r * gv_stride(m), m}, hl, make_double2(sqrt(cn[r]), 0.0), j, lane, est + r);
+}
+
+// y = R^-1 g over the first min(n, valid) columns, zero beyond; y[i * nrhs + r].  One
+// wavefront per rhs: R is staged in LDS, lane l holds y[l], each row is a wavefront sum.
+__global__ __launch_bounds__(64) void k_gv_solve(const double2* st, int m, int nrhs, int n, double2* y) {
+  __shared__ double2 Rs[64 * 64];
+  const int r = blockIdx.x, lane = threadIdx.x;
+  GvView v{const_cast<double2*>(st) + r * gv_stride(m), m};
+  const int nv = min(n, int(v.flags().x));
+  const double2* R = v.R();
+  for (int t = lane; t < nv * nv; t += 64) {
+    const int col = t / nv, row = t - col * nv;
+    Rs[col * 64 + row] = R[size_t(col) * m + row];
+  }
+  const double2 gl = lane < nv ? v.g()[lane] : make_double2(0.0, 0.0);
+  __syncthreads();
+  double2 yl = make_double2(0.0, 0.0);
+  for (int i = nv - 1; i >= 0; --i) {
+    // s = g[i] - sum_{l > i} R[i][l] y[l]
+    double2 p = lane > i && lane < nv ? cmul2(Rs[lane * 64 + i], yl) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      p.x += __shfl_xor(p.x, off, 64);
+      p.y += __shfl_xor(p.y, off, 64);
+    }
+    const double2 gi = shfl2(gl, i);
+    const double2 yi = cdiv2(cadd2(gi, cscale2(-1.0, p)), Rs[i * 64 + i]);
+    if (lane == i) yl = yi;
+  }
+  if (lane < m) y[size_t(lane) * nrhs + r] = lane < nv ? yl : make_double2(0.0, 0.0);  // m <= 64
+}
+
 }  // namespace
 
 template <class S>
@@ -853,56 +984,47 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
   // FP64 keeps two Gram-Schmidt passes (parity with the FP64 reference to ~1e-12); lower
   // storage precisions use one pass with the Pythagorean norm, which halves the basis traffic
   constexpr bool kCgs2 = std::is_same<S, double2>::value;
-  // with a tolerance, Arnoldi steps are issued in batches of kBatch before the host reads the
-  // Hessenberg columns; steps past the converged one are discarded
+  // with a tolerance the host reads the convergence estimates once per kBatch Arnoldi steps
+  // (steps past the converged one are discarded); without one (fixed step count) the cycle
+  // runs without any host round trip: rotations and the small triangular solve are on the device
   constexpr int kBatch = 4;
+  QMG_CHECK(m >= 1 && m <= 64, QMG_EINVAL, "GMRES restart length must be in [1, 64]");
   const size_t len = A.len();
   ensure(len, nrhs, m);
   S* V = V_.as<S>();
   const size_t vs = size_t(nrhs) * len;  // stride between basis vectors
-  // per-column device staging: h1 [(m+1) nrhs], h2 [(m+1) nrhs], nrm [nrhs] (as double2 slots)
-  const size_t per_col = size_t(2 * (m + 1) + 1) * nrhs;
+  // per-column device staging: h1 [(m+1) nrhs], h2 [(m+1) nrhs], |w|^2 [nrhs], estimates [nrhs]
+  const size_t per_col = size_t(2 * (m + 1) + 2) * nrhs;
+  const size_t est_off = size_t(2 * (m + 1) + 1) * nrhs;
   cols_.ensure(size_t(m) * per_col * sizeof(double2));
+  gst_.ensure(size_t(nrhs) * gv_stride(m) * sizeof(double2));
   double2* colsd = cols_.as<double2>();
+  double2* gst = gst_.as<double2>();
   double* nrm = nrm_.as<double>();
+  double2* yd = y_.as<double2>();
   PinnedBuf& hb = hb_;
-  hb.ensure((size_t(m) * per_col + 2 * nrhs + size_t(m + 1) * nrhs) * sizeof(double2));
+  hb.ensure(size_t(m) * per_col * sizeof(double2));
   double2* hcols = hb.as<double2>();
-  double* hnrm0 = reinterpret_cast<double*>(hcols + size_t(m) * per_col);
 
   Result res;
-  res.rel_est.assign(nrhs, 0.0);
-  std::vector<double> bn(nrhs, 0.0);
-  Blas<S>::norm2(b, len, nrhs, nrm, rw_, st);
-  QMG_HIP(hipMemcpyAsync(hnrm0, nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-  QMG_HIP(hipStreamSynchronize(st));
-  for (int r = 0; r < nrhs; ++r) bn[r] = std::sqrt(hnrm0[r]);
+  res.rel_est.assign(nrhs, -1.0);  // unknown without a tolerance
+  double* nb = nrm + nrhs;  // |b|^2 (only needed apart from |r0|^2 when x is not zero)
+  if (!x_zero) Blas<S>::norm2(b, len, nrhs, nb, rw_, st);
   if (x_zero) Blas<S>::zero(x, vs, st);
+  auto start = [&](bool first_cycle) {  // normalise V_0, reset the rotations (and |b|)
+    const double* nb2 = first_cycle ? (x_zero ? nrm : nb) : nullptr;
+    if (packable_vec<S>(len, V)) {
+      constexpr int P = kPack<S>;
+      k_gv_start<S, P><<<dim3(unsigned((len / P + 255) / 256), nrhs), 256, 0, st>>>(V, nrm, len / P, gst, m, nb2);
+    } else {
+      k_gv_start<S, 1><<<dim3(unsigned((len + 255) / 256), nrhs), 256, 0, st>>>(V, nrm, len, gst, m, nb2);
+    }
+    QMG_LAUNCH_CHECK();
+  };
 
   int it = 0;
   bool first = true;
-  std::vector<GivensState> gs(nrhs);
-  std::vector<zc> y, hcol(m + 2);
-  std::vector<double2> yh(size_t(m) * nrhs);
   bool all_conv = false;
-  auto process = [&](int j) {  // host Givens step on column j; true if every rhs converged
-    const double2* snap = hcols + size_t(j) * per_col;
-    bool conv = true;
-    for (int r = 0; r < nrhs; ++r) {
-      for (int i = 0; i <= j; ++i) {
-        const double2 a = snap[size_t(i) * nrhs + r];
-        double2 c = make_double2(0.0, 0.0);
-        if (kCgs2) c = snap[size_t(m + 1 + i) * nrhs + r];
-        hcol[i] = zc(a.x + c.x, a.y + c.y);
-      }
-      hcol[j + 1] = std::sqrt(reinterpret_cast<const double*>(snap + size_t(2 * (m + 1)) * nrhs)[r]);
-      const double est = gs[r].step(j, hcol.data());
-      QMG_CHECK(std::isfinite(est), QMG_ENONFINITE, "GMRES: non-finite Hessenberg entry");
-      res.rel_est[r] = bn[r] > 0 ? est / bn[r] : 0.0;
-      if (!(tol > 0 && est <= tol * bn[r])) conv = false;
-    }
-    return conv;
-  };
   while (it < max_iter) {
     if (first && x_zero) {
       Blas<S>::copy(b, V, vs, st);
@@ -910,21 +1032,10 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
       A.apply(x, V, nrhs, st);
       Blas<S>::axpby(1.0, b, -1.0, V, vs, st);
     }
-    first = false;
     Blas<S>::norm2(V, len, nrhs, nrm, rw_, st);
-    QMG_HIP(hipMemcpyAsync(hnrm0, nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-    QMG_HIP(hipStreamSynchronize(st));
-    all_conv = true;
-    for (int r = 0; r < nrhs; ++r) {
-      const double beta = std::sqrt(hnrm0[r]);
-      QMG_CHECK(std::isfinite(beta), QMG_ENONFINITE, "GMRES: non-finite residual norm");
-      res.rel_est[r] = bn[r] > 0 ? beta / bn[r] : 0.0;
-      if (!(tol > 0 && beta <= tol * bn[r]) && beta > 0) all_conv = false;
-    }
-    if (all_conv) break;
-    Blas<S>::scale_dev(V, nrm, 0, len, nrhs, st);
+    start(first);
+    first = false;
     const int mc = std::min(m, max_iter - it);
-    for (int r = 0; r < nrhs; ++r) gs[r].init(mc, std::sqrt(hnrm0[r]));
     int jdone = 0, processed = 0, copied = 0;
     for (int j = 0; j < mc; ++j) {
       S* vj = V + size_t(j) * vs;
@@ -934,24 +1045,42 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
       double2* h2 = col + size_t(m + 1) * nrhs;
       double* cn = reinterpret_cast<double*>(col + size_t(2 * (m + 1)) * nrhs);
       A.apply(vj, vn, nrhs, st);
+      bool fused = false;
       if (kCgs2) {
         // CGS2: h1 = V^dag w ; w -= V h1 and h2 = V^dag w ; w -= V h2 and |w|^2 ; w /= |w|
         Blas<S>::cgs2_step(V, vs, j + 1, vn, len, nrhs, h1, h2, cn, rw_, st);
       } else {
-        // one classical Gram-Schmidt pass with the norm from Pythagoras, scaling fused
-        Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, cn, rw_, st);
+        // one classical Gram-Schmidt pass with the norm from Pythagoras; scaling and the
+        // Givens step fused into its last kernel
+        fused = Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, cn, rw_, st, gst, m, col + est_off);
+      }
+      if (!fused) {
+        k_gv_step<<<nrhs, 64, 0, st>>>(gst, m, nrhs, j, col, kCgs2 ? 1 : 0, col + est_off);
+        QMG_LAUNCH_CHECK();
       }
       jdone = j + 1;
-      // the columns since the last read travel to the host in one copy
-      if ((tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) || (tol <= 0 && j == mc - 1)) {
+      if (tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) {
+        // the columns since the last read travel to the host in one copy
         QMG_HIP(hipMemcpyAsync(hcols + size_t(copied) * per_col, colsd + size_t(copied) * per_col,
                                size_t(j + 1 - copied) * per_col * sizeof(double2), hipMemcpyDeviceToHost, st));
         copied = j + 1;
-      }
-      if (tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) {
         QMG_HIP(hipStreamSynchronize(st));
         for (; processed <= j; ++processed) {
-          if (process(processed)) {
+          const double2* e = hcols + size_t(processed) * per_col + est_off;
+          bool before = true, after = true;
+          for (int r = 0; r < nrhs; ++r) {
+            QMG_CHECK(std::isfinite(e[r].x) && std::isfinite(e[r].y), QMG_ENONFINITE,
+                      "GMRES: non-finite Hessenberg entry");
+            res.rel_est[r] = e[r].y;
+            if (!(e[r].x <= tol)) before = false;
+            if (!(e[r].y <= tol)) after = false;
+          }
+          if (processed == 0 && before) {  // already converged at the start of the cycle
+            jdone = 0;
+            all_conv = true;
+            break;
+          }
+          if (after) {
             jdone = processed + 1;
             all_conv = true;
             break;
@@ -960,22 +1089,14 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
         if (all_conv) break;
       }
     }
-    if (tol <= 0) {
-      QMG_HIP(hipStreamSynchronize(st));
-      for (int j = 0; j < jdone; ++j) process(j);
-    }
     it += jdone;
-    // x += sum_i y_i V_i
-    for (int r = 0; r < nrhs; ++r) {
-      gs[r].solve(y);
-      for (int i = 0; i < jdone; ++i) yh[size_t(i) * nrhs + r] = make_double2(y[i].real(), y[i].imag());
+    if (jdone > 0) {
+      // x += V y with y = R^-1 g over the accepted columns
+      k_gv_solve<<<nrhs, 64, 0, st>>>(gst, m, nrhs, jdone, yd);
+      QMG_LAUNCH_CHECK();
+      Blas<S>::axpy_multi(V, vs, jdone, yd, 1.0, x, len, nrhs, st);
     }
-    double2* yd = y_.as<double2>();
-    QMG_HIP(hipMemcpyAsync(yd, yh.data(), size_t(jdone) * nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
-    Blas<S>::axpy_multi(V, vs, jdone, yd, 1.0, x, len, nrhs, st);
-    // the host vector yh must outlive the async copy
-    QMG_HIP(hipStreamSynchronize(st));
-    if (all_conv) break;
+    if (all_conv || jdone == 0) break;
   }
   res.iters = it;
   res.converged = (tol <= 0) || all_conv;

@@ -58,9 +58,11 @@ struct Blas {
                         int nrhs, double* out, RedWork& rw, hipStream_t st);
   // one Gram-Schmidt step: h = X^dag w (m vectors), w <- (w - X h) / beta with
   // beta^2 = |w|^2 - |h|^2, n2[r] = beta^2 (device); h needs (m + 1) * nrhs slots, slot m
-  // receives |w|^2 before the update
-  static void cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
-                        RedWork& rw, hipStream_t st);
+  // receives |w|^2 before the update.  With gst, the GMRES Givens step for Hessenberg column
+  // m - 1 (restart length gm) runs in the same launch and writes its estimates to est; returns
+  // whether it did.
+  static bool cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
+                        RedWork& rw, hipStream_t st, double2* gst = nullptr, int gm = 0, double2* est = nullptr);
   // two Gram-Schmidt passes: h1 = X^dag w ; w -= X h1 ; h2 = X^dag w ; w -= X h2 ;
   // n2[r] = |w|^2 ; w /= |w| (h1, h2, n2 on the device)
   static void cgs2_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
@@ -80,8 +82,9 @@ struct Blas {
                         hipStream_t st);
 };
 
-// Restarted GMRES(m), multi right-hand side, Arnoldi with classical Gram-Schmidt done twice
-// (CGS2) on the device and Givens rotations on the host.
+// Restarted GMRES(m), multi right-hand side: Arnoldi with classical Gram-Schmidt (twice in
+// FP64) and the Givens least-squares update on the device; with a tolerance the host reads
+// the residual estimates once per few steps, without one a cycle has no host round trip.
 template <class S>
 class Gmres {
  public:
@@ -96,7 +99,7 @@ class Gmres {
 
  private:
   void ensure(size_t len, int nrhs, int restart);
-  DevBuf V_, H_, h1_, h2_, nrm_, y_, r_, cols_;
+  DevBuf V_, H_, h1_, h2_, nrm_, y_, r_, cols_, gst_;
   PinnedBuf hb_;
   RedWork rw_;
   size_t len_ = 0;
