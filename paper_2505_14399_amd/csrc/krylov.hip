@@ -15,13 +15,8 @@ namespace {
 
 constexpr int RB = 256;  // threads per reduction workgroup (4 wavefronts)
 
-__device__ inline double2 warp_sum(double2 v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    v.x += __shfl_down(v.x, off, 64);
-    v.y += __shfl_down(v.y, off, 64);
-  }
-  return v;
+__device__ inline double2 warp_sum(double2 v) {  // total in every lane
+  return make_double2(wave_sum(v.x), wave_sum(v.y));
 }
 
 __device__ inline double2 block_sum(double2 v) {
@@ -259,8 +254,10 @@ __device__ inline void store_partials(double2 (&acc)[MG], int mi, double2* parti
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < MG; ++i) {
-    const double2 v = warp_sum(acc[i]);
-    if (lane == 0) red[i][wid] = v;
+    if (i < mi) {  // uniform: only the live accumulators
+      const double2 v = warp_sum(acc[i]);
+      if (lane == 0) red[i][wid] = v;
+    }
   }
   __syncthreads();
   if (threadIdx.x < mi) {
@@ -964,11 +961,7 @@ __global__ __launch_bounds__(64) void k_gv_solve(const double2* st, int m, int n
   for (int i = nv - 1; i >= 0; --i) {
     // s = g[i] - sum_{l > i} R[i][l] y[l]
     double2 p = lane > i && lane < nv ? cmul2(Rs[lane * 64 + i], yl) : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      p.x += __shfl_xor(p.x, off, 64);
-      p.y += __shfl_xor(p.y, off, 64);
-    }
+    p = warp_sum(p);
     const double2 gi = shfl2(gl, i);
     const double2 yi = cdiv2(cadd2(gi, cscale2(-1.0, p)), Rs[i * 64 + i]);
     if (lane == i) yl = yi;

@@ -142,6 +142,36 @@ __device__ inline void stc(S* p, T i, cplx<U> v) {
   p[i] = StoreTraits<S>::st(cplx<C>{C(v.re), C(v.im)});
 }
 
+// Wavefront sums through DPP row operations (gfx9 family: quad permutations and row rotations
+// within each 16-lane row, then the row broadcasts of lanes 15 and 31), a few cycles per step
+// instead of an LDS-crossbar shuffle.  The additions happen in a fixed order, so every call
+// gives the same bits.  All 64 lanes must be active; wave_sum returns the total in every lane.
+template <int CTRL, int ROWMASK>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+__device__ inline double lane63(double v) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+template <class T>
+__device__ inline T wave_sum(T v) {
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124, 0xF>(v);  // row_ror:4
+  v += dpp_move<0x128, 0xF>(v);  // row_ror:8  (every lane: its 16-lane row)
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3 (lane 63: all 64)
+  return lane63(v);
+}
+
 // P consecutive complex numbers moved as one 16-byte (or, for FP64, one-number) access;
 // pointers are to elements, indices to packs
 template <class S, int P>

@@ -132,12 +132,7 @@ __global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const
     for (int q = 0; q < KC; ++q)
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        cplx<C> v = acc[q][r];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          v.re += __shfl_down(v.re, off, 64);
-          v.im += __shfl_down(v.im, off, 64);
-        }
+        const cplx<C> v = {wave_sum(acc[q][r].re), wave_sum(acc[q][r].im)};
         if (lane == 0) red[w][q * NR + r] = v;
       }
     __syncthreads();
