@@ -148,17 +148,19 @@ __global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const
 }
 
 // coarse apply: one workgroup per (aggregate, group of NR right-hand sides).  The nine input
-// vectors v(j + dir) are staged in LDS; thread (slot, row) forms the row of Y_slot(j) times
-// v(j + slot) for NR right-hand sides (each Y entry read once, coalesced over rows because
-// the blocks are stored column-major); the nine partial rows are summed in LDS.
-template <class S, int NR>
+// vectors v(j + slot) are staged in LDS.  Thread (h, slot, row pack) forms PR rows of
+// Y_slot(j) times v(j + slot) over column chunk h of H (each Y entry read once per group of
+// right-hand sides; PR consecutive rows of a column-major block are one 16-byte load); the
+// 9 H partial rows are summed in LDS.  H splits the columns so that a workgroup has enough
+// wavefronts to keep the Y stream in flight.
+template <class S, int NR, int PR>
 __global__ __launch_bounds__(1024) void k_coarse_apply(const S* __restrict__ Y, const S* __restrict__ in,
                                                        S* __restrict__ out, const int* __restrict__ cnb, int d, int m,
-                                                       int nrhs) {
+                                                       int nrhs, int H) {
   using C = ctype<S>;
   extern __shared__ unsigned char smem_raw[];
   cplx<C>* vin = reinterpret_cast<cplx<C>*>(smem_raw);  // [NR][9][m]
-  cplx<C>* part = vin + size_t(NR) * 9 * m;              // [NR][9][m]
+  cplx<C>* part = vin + size_t(NR) * 9 * m;              // [NR][9 H][m]
   const int j = blockIdx.x, rhs0 = blockIdx.y * NR;
   const int nr = min(NR, nrhs - rhs0);
   for (int t = threadIdx.x; t < NR * 9 * m; t += blockDim.x) {
@@ -167,27 +169,38 @@ __global__ __launch_bounds__(1024) void k_coarse_apply(const S* __restrict__ Y, 
     vin[t] = r < nr ? ldc(in, (size_t(rhs0 + r) * d + nbj) * m + col) : cplx<C>{C(0), C(0)};
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < 9 * m; t += blockDim.x) {
-    const int slot = t / m, row = t - slot * m;
-    const S* Yb = Y + (size_t(j) * 9 + slot) * m * m + row;
-    cplx<C> acc[NR];
+  const int mp = m / PR;           // row packs per column
+  const int cc = (m + H - 1) / H;  // columns per chunk
+  for (int t = threadIdx.x; t < H * 9 * mp; t += blockDim.x) {
+    const int hs = t / mp, rp = t - hs * mp;  // hs = h * 9 + slot
+    const int h = hs / 9, slot = hs - h * 9;
+    const int c0 = h * cc, c1 = min(m, c0 + cc);
+    const S* Yb = Y + (size_t(j) * 9 + slot) * m * m;
+    cplx<C> acc[NR][PR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = {C(0), C(0)};
-#pragma unroll 4
-    for (int col = 0; col < m; ++col) {
-      const cplx<C> y = ldc(Yb, size_t(col) * m);
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] += y * vin[(r * 9 + slot) * m + col];
+      for (int u = 0; u < PR; ++u) acc[r][u] = {C(0), C(0)};
+#pragma unroll 6
+    for (int col = c0; col < c1; ++col) {
+      const Pk<S, PR> y = ldp<S, PR>(Yb, size_t(col) * mp + rp);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const cplx<C> v = vin[(r * 9 + slot) * m + col];
+#pragma unroll
+        for (int u = 0; u < PR; ++u) acc[r][u] += StoreTraits<S>::ld(y.v[u]) * v;
+      }
     }
 #pragma unroll
-    for (int r = 0; r < NR; ++r) part[(r * 9 + slot) * m + row] = acc[r];
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int u = 0; u < PR; ++u) part[(size_t(r) * 9 * H + hs) * m + rp * PR + u] = acc[r][u];
   }
   __syncthreads();
   for (int t = threadIdx.x; t < nr * m; t += blockDim.x) {
     const int r = t / m, row = t - r * m;
     cplx<C> s = {C(0), C(0)};
-#pragma unroll
-    for (int slot = 0; slot < 9; ++slot) s += part[(r * 9 + slot) * m + row];
+    for (int q = 0; q < 9 * H; ++q) s += part[(size_t(r) * 9 * H + q) * m + row];
     stc(out, (size_t(rhs0 + r) * d + j) * m + row, s);
   }
 }
@@ -661,15 +674,28 @@ void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, co
                  8.0 * 9.0 * m * m * h.blk.d * nrhs);
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
-    const int threads = int(std::min<size_t>(1024, ((size_t(9) * m + 63) / 64) * 64));
-    auto go = [&](auto kern, int NR) {
-      const size_t lds = size_t(2) * NR * 9 * m * sizeof(cplx<ctype<S>>);
+    constexpr int PK = kPack<S>;
+    auto go = [&](auto kern, int NR, int PR) {
+      const int mp = m / PR;
+      const int H = std::max(1, std::min(8, 1024 / (9 * mp)));
+      const int threads = int(std::min<size_t>(1024, ((size_t(9) * mp * H + 63) / 64) * 64));
+      const size_t lds = size_t(NR) * 9 * m * (1 + H) * sizeof(cplx<ctype<S>>);
+      QMG_CHECK(lds <= 160 * 1024, QMG_EINVAL, "coarse apply: block too large for LDS staging");
+      if (lds > 64 * 1024)
+        QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
       launch(kern, dim3(h.blk.d, (nrhs + NR - 1) / NR), dim3(threads), uint32_t(lds), st, Y, in, out,
-             h.cnb.as<int>(), h.blk.d, m, nrhs);
+             h.cnb.as<int>(), h.blk.d, m, nrhs, H);
     };
-    if (nrhs >= 4) go(k_coarse_apply<S, 4>, 4);
-    else if (nrhs == 2) go(k_coarse_apply<S, 2>, 2);
-    else go(k_coarse_apply<S, 1>, 1);
+    const bool packed = m % PK == 0;
+    if (packed) {
+      if (nrhs >= 4) go(k_coarse_apply<S, 4, PK>, 4, PK);
+      else if (nrhs == 2) go(k_coarse_apply<S, 2, PK>, 2, PK);
+      else go(k_coarse_apply<S, 1, PK>, 1, PK);
+    } else {
+      if (nrhs >= 4) go(k_coarse_apply<S, 4, 1>, 4, 1);
+      else if (nrhs == 2) go(k_coarse_apply<S, 2, 1>, 2, 1);
+      else go(k_coarse_apply<S, 1, 1>, 1, 1);
+    }
   });
   QMG_LAUNCH_CHECK();
 }

@@ -255,8 +255,8 @@ def test_solve_point_sources_multi_rhs(qmg, c1):
                                                      ((8, 4, 4, 8), (4, 4, 2, 2), 12, "f32", 6),
                                                      ((6, 4, 2, 6), (2, 2, 1, 3), 5, "f32", 7)])
 def test_transfer_multi_rhs(qmg, dims, block, k, inner, nrhs):
-    """P and P^dagger on several right-hand sides (groups of four plus a ragged rest), FP64 and
-    the FP32 copy of P, against the oracle applied with the exported FP64 P."""
+    """P, P^dagger and D_c on several right-hand sides (groups of four plus a ragged rest), FP64
+    and the FP32 copies of P and Y, against the oracle applied with the exported FP64 P and Y."""
     banner(f"transfer {dims} block={block} k={k} {inner} nrhs={nrhs}")
     U = fields.random_gauge(dims, 0.5, 43)
     r = 4
@@ -280,8 +280,16 @@ def test_transfer_multi_rhs(qmg, dims, block, k, inner, nrhs):
         tol = 2e-6
         got_f = to_np(qmg.prolong(mg, to_gpu(vc).to(torch.complex64)))
         got_c = to_np(qmg.restrict(mg, to_gpu(psi).to(torch.complex64)))
-    print(f"[parity] prolong {rel(got_f, want_f):.2e} restrict {rel(got_c, want_c):.2e}")
+    Y = to_np(mg.coarse_blocks())
+    want_a = coarse.coarse_apply(Y, vc, geo.coarse_dims(dims, block))
+    if inner == "f64":
+        got_a = to_np(qmg.coarse_apply(mg, to_gpu(vc)))
+    else:
+        got_a = to_np(qmg.coarse_apply(mg, to_gpu(vc).to(torch.complex64)))
+    print(f"[parity] prolong {rel(got_f, want_f):.2e} restrict {rel(got_c, want_c):.2e} "
+          f"coarse apply {rel(got_a, want_a):.2e}")
     for q in range(nrhs):
         assert rel(got_f[q], want_f[q]) < tol
         assert rel(got_c[q], want_c[q]) < tol
+        assert rel(got_a[q], want_a[q]) < (1e-13 if inner == "f64" else 5e-6)
     mg.close()
