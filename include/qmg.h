@@ -82,6 +82,22 @@ qmg_status qmg_wilson_apply(const qmg_lattice* lat, const void* U, const void* i
 qmg_status qmg_wilson_apply_adj(const qmg_lattice* lat, const void* U, const void* in, void* out,
                                 int32_t nrhs, qmg_prec prec, qmg_layout layout, hipStream_t stream);
 
+/* Many independent lattices in one launch (for example 64 small lattices of 4,096 to 20,736
+ * sites with different extents): out_i = D_i in_i (D_i^dagger if dagger = 1) for i < n_lat,
+ * each lattice with its own extents, boundary, mass, anisotropy, gauge field and nrhs spinors,
+ * the operator of qmg_wilson_apply in the native layout.  Workgroups are assigned to lattices
+ * by a prefix sum of their site tiles, so uneven lattices share one launch.
+ * lats: host array of n_lat descriptors.  U, in, out: DEVICE arrays of n_lat device pointers
+ *   (native gauge [4][9][V_i], native spinors [nrhs][12][V_i] in precision prec); out_i must
+ *   not alias in_i.
+ * The descriptor table is uploaded on the first call for a given set of lattices (after the
+ * stream has drained) and reused while the set is unchanged; calls with different sets on
+ * several streams at once are not supported.
+ * Errors: EINVAL (null, n_lat outside [1, 65536], nrhs < 1, bad enum), ESHAPE (extents), EHIP. */
+qmg_status qmg_wilson_apply_batched(int32_t n_lat, const qmg_lattice* lats, const void* const* U,
+                                    const void* const* in, void* const* out, int32_t nrhs, qmg_prec prec,
+                                    int32_t dagger, hipStream_t stream);
+
 /* Layout/precision conversion: canonical FP64 <-> native `prec` (device buffers, no aliasing). */
 qmg_status qmg_pack_spinor(const qmg_lattice* lat, const void* canon_f64, void* native, int32_t nrhs,
                            qmg_prec prec, hipStream_t stream);

@@ -59,6 +59,7 @@ _P, _I, _D, _U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_ui
 SIGNATURES = {
     "qmg_wilson_apply": [_P, _P, _P, _P, _I, _I, _I, _P],
     "qmg_wilson_apply_adj": [_P, _P, _P, _P, _I, _I, _I, _P],
+    "qmg_wilson_apply_batched": [_I, _P, _P, _P, _P, _I, _I, _I, _P],
     "qmg_pack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_unpack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_pack_gauge": [_P, _P, _P, _I, _P],
@@ -185,6 +186,32 @@ def wilson_apply(lat: Lattice, U, psi, layout="canonical", out=None):
 def wilson_apply_adj(lat: Lattice, U, psi, layout="canonical", out=None):
     """out = D^dagger psi."""
     return _apply("qmg_wilson_apply_adj", lat, U, psi, layout, out)
+
+
+def wilson_apply_batched(lats: Sequence[Lattice], Us, psis, outs=None, dagger=False):
+    """out_i = D_i psi_i (D_i^dagger if dagger) for many lattices in one launch.
+
+    Native layout only: Us[i] [4,9,V_i], psis[i] [nrhs,12,V_i] (same precision and nrhs for all).
+    """
+    lib = load_library()
+    n = len(lats)
+    if not (len(Us) == len(psis) == n) or n == 0:
+        raise ValueError("need one gauge field and one spinor block per lattice")
+    prec = _prec_of(psis[0])
+    nrhs = psis[0].shape[0]
+    for U, p in zip(Us, psis):
+        if _prec_of(U) != prec or _prec_of(p) != prec or p.shape[0] != nrhs:
+            raise TypeError("all lattices need the same precision and number of right-hand sides")
+    outs = [torch.empty_like(p) for p in psis] if outs is None else list(outs)
+    arr = (qmg_lattice * n)(*[l.c() for l in lats])
+    ptrs = torch.tensor([[_ptr(t).value for t in grp] for grp in (Us, psis, outs)], dtype=torch.int64,
+                        device=psis[0].device)
+    _check(lib.qmg_wilson_apply_batched(n, arr, ctypes.c_void_p(ptrs[0].data_ptr()),
+                                        ctypes.c_void_p(ptrs[1].data_ptr()), ctypes.c_void_p(ptrs[2].data_ptr()),
+                                        nrhs, prec, 1 if dagger else 0, _stream()))
+    # the pointer table must outlive the launch: keep it until the stream has passed it
+    torch.cuda.current_stream().synchronize()
+    return outs
 
 
 def _native_spinor_shape(nrhs, V, prec):

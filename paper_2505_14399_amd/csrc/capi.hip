@@ -2,6 +2,7 @@
 // Algorithm 3), the K-cycle preconditioner and the mixed-precision MG solve.
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <cstdarg>
 #include <memory>
 #include <new>
@@ -425,6 +426,17 @@ qmg_status wilson_common(const qmg_lattice* lat, const void* U, const void* in, 
   });
 }
 
+// Device copy of the descriptor table of the last batched call (uploaded again, after the
+// stream has drained, when the lattice set changes)
+struct BatchCache {
+  std::vector<BatchLattice> host;
+  DevBuf dev;
+};
+BatchCache& batch_cache() {
+  static BatchCache c;
+  return c;
+}
+
 }  // namespace
 }  // namespace qmg
 
@@ -440,6 +452,44 @@ qmg_status qmg_wilson_apply(const qmg_lattice* lat, const void* U, const void* i
 qmg_status qmg_wilson_apply_adj(const qmg_lattice* lat, const void* U, const void* in, void* out, int32_t nrhs,
                                 qmg_prec prec, qmg_layout layout, hipStream_t stream) {
   return wilson_common(lat, U, in, out, nrhs, prec, layout, stream, true);
+}
+
+qmg_status qmg_wilson_apply_batched(int32_t n_lat, const qmg_lattice* lats, const void* const* U,
+                                    const void* const* in, void* const* out, int32_t nrhs, qmg_prec prec,
+                                    int32_t dagger, hipStream_t stream) {
+  return guard([&] {
+    QMG_CHECK(n_lat >= 1 && n_lat <= 65536, QMG_EINVAL, "n_lat must be in [1, 65536]");
+    check_ptr(lats, "lats");
+    check_ptr(U, "U");
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    QMG_CHECK(dagger == 0 || dagger == 1, QMG_EINVAL, "dagger must be 0 or 1");
+    check_prec(prec);
+    std::vector<BatchLattice> tab(n_lat);
+    long tiles = 0;
+    double sites = 0;
+    for (int i = 0; i < n_lat; ++i) {
+      Geom g = make_geom(&lats[i]);
+      tab[i].a = make_dslash_args(g, nrhs, dagger != 0, false);
+      tab[i].tile0 = int(tiles);
+      tiles += long((g.V + 255) / 256) * nrhs;
+      sites += double(g.V);
+      QMG_CHECK(tiles < (1L << 31), QMG_ESHAPE, "batched dslash: too many workgroups");
+    }
+    BatchCache& c = batch_cache();
+    const size_t bytes = tab.size() * sizeof(BatchLattice);
+    if (c.host.size() != tab.size() || std::memcmp(c.host.data(), tab.data(), bytes) != 0) {
+      QMG_HIP(hipStreamSynchronize(stream));  // the previous table may still be in use
+      QMG_HIP(hipDeviceSynchronize());
+      c.dev.ensure(bytes);
+      QMG_HIP(hipMemcpy(c.dev.p, tab.data(), bytes, hipMemcpyHostToDevice));
+      c.host = tab;
+    }
+    const double cb = double(prec_bytes(prec));
+    launch_dslash_batched(prec, c.dev.as<BatchLattice>(), n_lat, int(tiles), U, in, out, dagger != 0,
+                          sites * (24.0 * nrhs + 36.0) * cb, 1368.0 * sites * nrhs, stream);
+  });
 }
 
 qmg_status qmg_pack_spinor(const qmg_lattice* lat, const void* canon, void* native, int32_t nrhs, qmg_prec prec,

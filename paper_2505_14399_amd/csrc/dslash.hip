@@ -146,18 +146,11 @@ __device__ inline void do_hop(const S* __restrict__ U, const S* __restrict__ in,
   }
 }
 
+// D (or D^dag) at one site for NR right-hand sides starting at rhs0
 template <class S, bool CANON, int NR, bool DAG>
-__global__ __launch_bounds__(kBlock) void k_dslash(const S* __restrict__ U, const S* __restrict__ in,
-                                                   S* __restrict__ out, DslashArgs a) {
+__device__ inline void site_dslash(const S* __restrict__ U, const S* __restrict__ in, S* __restrict__ out,
+                                   const DslashArgs& a, int site, int rhs0) {
   using C = ctype<S>;
-  // flattened grid over (tile, rhs group) with the rhs groups of a tile adjacent in the
-  // XCD-local order, so that they share the tile's links in L2
-  const int ng = a.nrhs / NR;
-  const int wg = xcd_tile(blockIdx.x, gridDim.x);
-  const int tile = wg / ng;
-  const int site = tile * kBlock + threadIdx.x;
-  if (site >= a.V) return;
-  const int rhs0 = (wg - tile * ng) * NR;
   const int V = a.V;
   const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
   int rem = site;
@@ -213,6 +206,42 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const S* __restrict__ U, cons
   }
 }
 
+template <class S, bool CANON, int NR, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_dslash(const S* __restrict__ U, const S* __restrict__ in,
+                                                   S* __restrict__ out, DslashArgs a) {
+  // flattened grid over (tile, rhs group) with the rhs groups of a tile adjacent in the
+  // XCD-local order, so that they share the tile's links in L2
+  const int ng = a.nrhs / NR;
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = wg / ng;
+  const int site = tile * kBlock + threadIdx.x;
+  if (site >= a.V) return;
+  site_dslash<S, CANON, NR, DAG>(U, in, out, a, site, (wg - tile * ng) * NR);
+}
+
+// Many lattices in one launch: workgroup (after the XCD remap) w belongs to the lattice whose
+// tile range [tile0, tile0 + ntiles * nrhs) holds it; every lattice has its own extents,
+// coefficients, gauge field and spinors (native layout).
+template <class S, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_dslash_batched(const BatchLattice* __restrict__ lat, int n_lat,
+                                                           const S* const* __restrict__ U,
+                                                           const S* const* __restrict__ in,
+                                                           S* const* __restrict__ out) {
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  int lo = 0, hi = n_lat - 1;  // last lattice with tile0 <= wg
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (lat[mid].tile0 <= wg) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchLattice& b = lat[lo];
+  const int local = wg - b.tile0;
+  const int ntile = (b.a.V + kBlock - 1) / kBlock;
+  const int rhs = local / ntile, tile = local - rhs * ntile;
+  const int site = tile * kBlock + threadIdx.x;
+  if (site >= b.a.V) return;
+  site_dslash<S, false, 1, DAG>(U[lo], in[lo], out[lo], b.a, site, rhs);
+}
 
 // Native-layout kernel that walks along t.  Thread (spatial site, t-chunk) computes the TCH
 // sites t0 .. t0+TCH-1 of its column.  The spinor of the next slice, loaded for the forward
@@ -487,6 +516,26 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
 }
 
 }  // namespace
+
+void launch_dslash_batched(qmg_prec prec, const BatchLattice* lat_dev, int n_lat, int total_tiles,
+                           const void* const* U, const void* const* in, void* const* out, bool dagger,
+                           double bytes, double flops, hipStream_t st) {
+  TimedLaunch tl("dslash/batched", st, bytes, flops);
+  auto go = [&](auto tag) {
+    using S = decltype(tag);
+    if (dagger)
+      launch(k_dslash_batched<S, true>, dim3(total_tiles), dim3(kBlock), 0, st, lat_dev, n_lat, U, in, out);
+    else
+      launch(k_dslash_batched<S, false>, dim3(total_tiles), dim3(kBlock), 0, st, lat_dev, n_lat, U, in, out);
+  };
+  switch (prec) {
+    case QMG_F64: go(double2{}); break;
+    case QMG_F32: go(float2{}); break;
+    case QMG_BF16: go(cbf16{}); break;
+    case QMG_F16: go(chalf{}); break;
+  }
+  QMG_LAUNCH_CHECK();
+}
 
 void launch_dslash(qmg_prec prec, const void* U, const void* in, void* out, const DslashArgs& a,
                    hipStream_t st) {

@@ -299,6 +299,17 @@ struct DslashArgs {
   int tchunk;     // native kernel: sites per thread along t (0: chosen by the launcher)
 };
 DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical);
+
+// one lattice of a batched launch: its operator arguments and its first workgroup
+struct BatchLattice {
+  DslashArgs a;
+  int tile0;
+};
+// out[i] = D_i in[i] for n_lat lattices in one launch (native layout; U, in, out: device arrays
+// of device pointers; lat_dev: device array of descriptors with prefix-summed tile0)
+void launch_dslash_batched(qmg_prec prec, const BatchLattice* lat_dev, int n_lat, int total_tiles,
+                           const void* const* U, const void* const* in, void* const* out, bool dagger,
+                           double bytes, double flops, hipStream_t st);
 void set_dslash_variant(int v);
 
 // out = D in (or D^dag) ; U in the same storage type and layout as the spinors
