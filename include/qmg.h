@@ -199,6 +199,19 @@ qmg_status qmg_mg_get_coarse(const qmg_mg* mg, void* Y, hipStream_t stream);
 /* Setup timings in seconds: smoother, streaming SVD, coarse build, total (host array [4]). */
 qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);
 
+/* Form of the K-cycle used by later qmg_mg_solve calls on this hierarchy.
+ * coarse_steps = 0 (default): the coarse GMRES(32) runs to its tolerance with the host reading
+ *   its convergence estimates every few steps (restarted up to coarse_max_iter steps).
+ * coarse_steps in [1, 63]: the coarse solve is one GMRES cycle of at most coarse_steps steps
+ *   whose convergence test is made on the device: once every right-hand side is below the
+ *   tolerance the remaining launches of the cycle return at once, and the whole K-cycle needs
+ *   no host round trip (a weaker coarse solve if the budget is short: the outer solver is
+ *   flexible, so the solve still converges, possibly in more iterations).
+ * graph = 1 (needs coarse_steps > 0): the K-cycle is captured into a hipGraph on a private
+ *   stream at its first application in each solve and replayed for every later one.
+ * Errors: EINVAL (null, coarse_steps outside [0, 63], graph not 0/1, graph without steps). */
+qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
+
 /* Measurement hooks.  qmg_timing_enable(1) clears the record and brackets every later launch
  * of the instrumented kernel families ("dslash/site", "dslash/twalk", "dslash/dir",
  * "dslash/canonical", "isvd", "coarse_apply", "prolong", "restrict", "coarse_build") with HIP

@@ -77,6 +77,7 @@ SIGNATURES = {
     "qmg_mg_setup_times": [_P, _P],
     "qmg_timing_enable": [_I],
     "qmg_timing_query": [ctypes.c_char_p, _P, _P, _P, _P],
+    "qmg_mg_set_cycle": [_P, _I, _I],
     "qmg_autotune": [_I],
     "qmg_set_dslash_variant": [_I],
     "qmg_tune_save": [ctypes.c_char_p],
@@ -302,6 +303,11 @@ class MG:
         Y = torch.empty((self.n_agg, 9, m, m), dtype=torch.complex128, device="cuda")
         _check(load_library().qmg_mg_get_coarse(self._h, _ptr(Y), _stream()))
         return Y
+
+    def set_cycle(self, coarse_steps=0, graph=False):
+        """K-cycle form: coarse_steps > 0 gives a device-exit coarse solve with that step budget;
+        graph=True captures the cycle into a hipGraph replayed at every application."""
+        _check(load_library().qmg_mg_set_cycle(self._h, int(coarse_steps), 1 if graph else 0))
 
     def setup_times(self):
         t = (ctypes.c_double * 4)()

@@ -67,7 +67,7 @@ struct WilsonOp : LinOp {
   qmg_prec p;
   const void* U;
   WilsonOp(const Geom& g_, qmg_prec p_, const void* U_) : g(g_), p(p_), U(U_) {}
-  void apply(const void* in, void* out, int nrhs, hipStream_t st) override {
+  void apply(const void* in, void* out, int nrhs, hipStream_t st, const int* = nullptr) override {
     DslashArgs a = make_dslash_args(g, nrhs, false, false);
     launch_dslash(p, U, in, out, a, st);
   }
@@ -80,14 +80,19 @@ struct CoarseOp : LinOp {
   qmg_prec p;
   const void* Y;
   CoarseOp(const HierarchyDev& h_, qmg_prec p_, const void* Y_) : h(h_), p(p_), Y(Y_) {}
-  void apply(const void* in, void* out, int nrhs, hipStream_t st) override {
-    launch_coarse_apply(p, h, Y, in, out, nrhs, st);
+  void apply(const void* in, void* out, int nrhs, hipStream_t st, const int* skip = nullptr) override {
+    launch_coarse_apply(p, h, Y, in, out, nrhs, st, skip);
   }
   size_t len() const override { return size_t(2) * h.k * h.blk.d; }
   qmg_prec prec() const override { return p; }
 };
 
 // Two-level K-cycle with storage precision S; r and z are in the outer solver's type F.
+// Eager form: restrict, coarse GMRES to the tolerance (the host reads its convergence
+// estimates every few steps), prolong, fixed-length GMRES post-smoothing.  With a coarse step
+// budget (h.cycle_steps > 0) the coarse solve is one device-exit cycle (convergence tested and
+// acted on by the kernels themselves), so the whole cycle has no host round trip; with
+// h.cycle_graph it is then captured once into a hipGraph on a private stream and replayed.
 template <class F, class S>
 struct KCycle : Precond {
   const HierarchyDev& h;
@@ -95,34 +100,110 @@ struct KCycle : Precond {
   CoarseOp& Dc;
   const void* P;
   Gmres<S> gc, gf;
-  DevBuf rc, ec, rS, zS;
+  DevBuf rc, ec, rS, zS, conv;
   long coarse_iters = 0, smooth_iters = 0, cycles = 0;
+  hipStream_t gs = nullptr;        // private stream of the captured cycle
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_nrhs = 0;
   KCycle(const HierarchyDev& h_, WilsonOp& D_, CoarseOp& Dc_, const void* P_) : h(h_), D(D_), Dc(Dc_), P(P_) {}
+  ~KCycle() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gs) (void)hipStreamDestroy(gs);
+  }
+  // restrict -> coarse solve -> prolong -> post-smoothing, on storage-precision buffers
+  void body(const void* r_s, void* z_s, int nrhs, hipStream_t st) {
+    constexpr qmg_prec p = StoreTraits<S>::prec;
+    launch_restrict(p, h, P, r_s, rc.p, nrhs, st);
+    if (h.cycle_steps > 0) {
+      gc.solve(Dc, rc.p, ec.p, true, nrhs, h.cycle_steps, h.cycle_steps, h.coarse_tol, st, conv.as<int>());
+    } else {
+      auto rcs = gc.solve(Dc, rc.p, ec.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st);
+      coarse_iters += rcs.iters;
+    }
+    launch_prolong(p, h, P, ec.p, z_s, nrhs, st);
+    gf.solve(D, r_s, z_s, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    smooth_iters += h.n_post;
+  }
   void apply(const void* r, void* z, int nrhs, hipStream_t st) override {
     const size_t nc = size_t(nrhs) * 2 * h.k * h.blk.d;
     const size_t nf = size_t(nrhs) * 12 * h.g.V;
     rc.ensure(nc * sizeof(S));
     ec.ensure(nc * sizeof(S));
+    if (!conv.p) {
+      conv.alloc(4 * sizeof(int));
+      QMG_HIP(hipMemsetAsync(conv.p, 0, 4 * sizeof(int), st));  // outside any capture
+    }
     constexpr qmg_prec p = StoreTraits<S>::prec;
     constexpr qmg_prec pf = StoreTraits<F>::prec;
     constexpr bool same = std::is_same<F, S>::value;
-    const void* r_s = r;
-    void* z_s = z;
-    if (!same) {
-      rS.ensure(nf * sizeof(S));
-      zS.ensure(nf * sizeof(S));
-      launch_convert(r, pf, rS.p, p, nf, st);
-      r_s = rS.p;
-      z_s = zS.p;
-    }
-    launch_restrict(p, h, P, r_s, rc.p, nrhs, st);
-    auto rcs = gc.solve(Dc, rc.p, ec.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st);
-    launch_prolong(p, h, P, ec.p, z_s, nrhs, st);
-    auto rfs = gf.solve(D, r_s, z_s, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
-    if (!same) launch_convert(z_s, p, z, pf, nf, st);
-    coarse_iters += rcs.iters;
-    smooth_iters += rfs.iters;
     ++cycles;
+    if (!h.cycle_graph) {
+      const void* r_s = r;
+      void* z_s = z;
+      if (!same) {
+        rS.ensure(nf * sizeof(S));
+        zS.ensure(nf * sizeof(S));
+        launch_convert(r, pf, rS.p, p, nf, st);
+        r_s = rS.p;
+        z_s = zS.p;
+      }
+      body(r_s, z_s, nrhs, st);
+      if (!same) launch_convert(z_s, p, z, pf, nf, st);
+      return;
+    }
+    // captured form: fixed buffers rS / zS, private stream ordered after and before st
+    QMG_CHECK(h.cycle_steps > 0, QMG_EINVAL, "a captured K-cycle needs a coarse step budget");
+    rS.ensure(nf * sizeof(S));
+    zS.ensure(nf * sizeof(S));
+    if (!gs) {
+      QMG_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+      QMG_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+      QMG_HIP(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+    }
+    launch_convert(r, pf, rS.p, p, nf, st);  // a copy when F == S
+    QMG_HIP(hipEventRecord(ev_in, st));
+    QMG_HIP(hipStreamWaitEvent(gs, ev_in, 0));
+    if (!exec || graph_nrhs != nrhs) {
+      if (exec) {
+        QMG_HIP(hipGraphExecDestroy(exec));
+        exec = nullptr;
+      }
+      // this cycle runs eagerly (sizing every work buffer), then the same launches are captured
+      body(rS.p, zS.p, nrhs, gs);
+      hipGraph_t g = nullptr;
+      QMG_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+      try {
+        body(rS.p, zS.p, nrhs, gs);
+      } catch (...) {
+        (void)hipStreamEndCapture(gs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      smooth_iters -= h.n_post;  // the captured launches did not run
+      QMG_HIP(hipStreamEndCapture(gs, &g));
+      const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      QMG_HIP(e);
+      graph_nrhs = nrhs;
+    } else {
+      QMG_HIP(hipGraphLaunch(exec, gs));
+      smooth_iters += h.n_post;
+    }
+    QMG_HIP(hipEventRecord(ev_out, gs));
+    QMG_HIP(hipStreamWaitEvent(st, ev_out, 0));
+    launch_convert(zS.p, p, z, pf, nf, st);
+  }
+  // coarse steps taken in device-exit mode (read once, after the solve)
+  void finish(hipStream_t st) {
+    if (h.cycle_steps <= 0 || !conv.p) return;
+    int c[4];
+    QMG_HIP(hipStreamSynchronize(st));
+    if (gs) QMG_HIP(hipStreamSynchronize(gs));
+    QMG_HIP(hipMemcpy(c, conv.p, sizeof(c), hipMemcpyDeviceToHost));
+    coarse_iters += c[2];
   }
 };
 
@@ -315,6 +396,7 @@ void solve_f64(const HierarchyDev& h, const void* b64, void* x64, int nrhs, doub
   KCycle<double2, double2> K(h, D, Dc, h.P64.p);
   Fgcr<double2> f;
   auto res = f.solve(D, K, b64, x64, x_zero, nrhs, 16, max_iter, tol, st);
+  K.finish(st);
   ss.outer += res.iters;
   ss.coarse += K.coarse_iters;
   ss.smooth += K.smooth_iters;
@@ -348,11 +430,16 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
   struct Acc {
     SolveStats& ss;
     KCycle<F, S>& K;
+    hipStream_t st;
     ~Acc() {
+      try {
+        K.finish(st);
+      } catch (...) {
+      }
       ss.coarse += K.coarse_iters;
       ss.smooth += K.smooth_iters;
     }
-  } acc{ss, K};
+  } acc{ss, K, st};
   for (int ref = 0; ref < 40 && ss.outer < max_outer; ++ref) {
     D64.apply(x64, r64.p, nrhs, st);
     Blas<double2>::axpby(1.0, b64, -1.0, r64.p, n, st);  // r = b - D x in FP64
@@ -817,6 +904,17 @@ qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total
     timing_query(family, launches, total_ms, &b, &f);
     if (algo_bytes) *algo_bytes = b;
     if (algo_flops) *algo_flops = f;
+  });
+}
+
+qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    QMG_CHECK(coarse_steps >= 0 && coarse_steps <= 63, QMG_EINVAL, "coarse_steps must be in [0, 63]");
+    QMG_CHECK(graph == 0 || graph == 1, QMG_EINVAL, "graph must be 0 or 1");
+    QMG_CHECK(!graph || coarse_steps > 0, QMG_EINVAL, "a captured K-cycle needs coarse_steps > 0");
+    mg->h.cycle_steps = coarse_steps;
+    mg->h.cycle_graph = graph != 0;
   });
 }
 

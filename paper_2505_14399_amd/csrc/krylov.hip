@@ -44,7 +44,8 @@ __device__ inline double2 block_sum(double2 v) {
 
 // out[c] = sum over b < nblk of partial[c * nblk + b], fixed order per thread + tree
 __global__ __launch_bounds__(RB) void k_finalize2(const double2* __restrict__ partial, int nblk,
-                                                  double2* __restrict__ out) {
+                                                  double2* __restrict__ out, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   const int c = blockIdx.x;
   double2 acc = make_double2(0.0, 0.0);
   for (int b = threadIdx.x; b < nblk; b += RB) {
@@ -56,7 +57,8 @@ __global__ __launch_bounds__(RB) void k_finalize2(const double2* __restrict__ pa
 }
 
 __global__ __launch_bounds__(RB) void k_finalize1(const double2* __restrict__ partial, int nblk,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   const int c = blockIdx.x;
   double2 acc = make_double2(0.0, 0.0);
   for (int b = threadIdx.x; b < nblk; b += RB) acc.x += partial[size_t(c) * nblk + b].x;
@@ -111,11 +113,14 @@ __global__ void k_axpby(double a, const S* __restrict__ x, double b, S* __restri
 // issued eight at a time so that their latencies overlap
 template <class S, int P>
 __global__ void k_axpy_multi(const S* __restrict__ X, size_t xstride_p, int m, const double2* __restrict__ c,
-                             double sgn, S* __restrict__ w, size_t np, int nrhs) {
+                             double sgn, S* __restrict__ w, size_t np, int nrhs, const int* __restrict__ skip,
+                             const int* __restrict__ mcount) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   using C = ctype<S>;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (e >= np) return;
+  if (mcount) m = min(m, mcount[r]);  // only the vectors this rhs actually built
   const size_t off = size_t(r) * np + e;
   auto wv = ldp<S, P>(w, off);
   cplx<C> acc[P];
@@ -147,7 +152,8 @@ __global__ void k_axpy_multi(const S* __restrict__ X, size_t xstride_p, int m, c
 }
 
 template <class S, int P>
-__global__ void k_scale_dev(S* __restrict__ w, const double* __restrict__ n2, int mode, size_t np) {
+__global__ void k_scale_dev(S* __restrict__ w, const double* __restrict__ n2, int mode, size_t np, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   using C = ctype<S>;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
@@ -307,7 +313,8 @@ __device__ inline double2 shfl2(double2 v, int src) {
 // i holds entry i of Hessenberg column j in hl, i <= j; hsub = h[j+1]): applies the previous
 // rotations in order through lane broadcasts, forms rotation j, stores column j of R and
 // updates g; lane 0 writes (|g[j]|, |g[j+1]|) / |b| to *est.  m <= 64.
-__device__ inline void gv_apply(GvView v, double2 hl, double2 hsub, int j, int lane, double2* est) {
+__device__ inline void gv_apply(GvView v, double2 hl, double2 hsub, int j, int lane, double2* est, double tol = 0.0,
+                                int* conv = nullptr, int nrhs = 1, int r = 0) {
   double2* g = v.g();
   const double2 fl = v.flags();
   const int valid = int(fl.x);
@@ -358,8 +365,17 @@ __device__ inline void gv_apply(GvView v, double2 hl, double2 hsub, int j, int l
   const double2 gj = g[j];
   g[j + 1] = cscale2(-1.0, cmul2(cconj2(sn), gj));
   g[j] = cscale2(c.x, gj);
-  v.flags() = make_double2(double(j + 1), bb == 0.0 ? 1.0 : 0.0);  // exact breakdown stops
-  *est = make_double2(before, cabs2(g[j + 1]) * inv_bn);
+  const double after = cabs2(g[j + 1]) * inv_bn;
+  bool stop = bb == 0.0;  // exact breakdown
+  if (conv) {
+    if (r == 0) atomicAdd(conv + 2, 1);
+    if (after <= tol) {  // converged: this rhs stops; the last one to converge raises the skip flag
+      stop = true;
+      if (atomicAdd(conv, 1) == nrhs - 1) atomicExch(conv + 1, 1);
+    }
+  }
+  v.flags() = make_double2(double(j + 1), stop ? 1.0 : 0.0);
+  *est = make_double2(before, after);
 }
 
 // Givens step fused into the last kernel of an Arnoldi step (gst == nullptr: none)
@@ -367,6 +383,9 @@ struct GvFuse {
   double2* gst;
   int m, j;
   double2* est;
+  double tol;  // with conv: device-side convergence test est <= tol
+  int* conv;   // {rhs converged, all converged (the skip flag), steps of rhs 0}, or nullptr
+  int nrhs;
 };
 
 // Where a kernel finds its per-rhs coefficients c_i (i < n): finalised values fin[i * nrhs + r],
@@ -454,7 +473,8 @@ __device__ inline void acc_dots(double2 (&acc)[MG], const S* __restrict__ X, siz
 template <class S, int P>
 __global__ __launch_bounds__(RB) void k_mdot(const S* __restrict__ X, size_t xstride_p, int m,
                                              const S* __restrict__ w, size_t np, int nrhs, int nblk,
-                                             double2* __restrict__ partial) {
+                                             double2* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
   const int mi = min(MG, m - i0);
   double2 acc[MG];
@@ -481,7 +501,8 @@ __global__ __launch_bounds__(RB) void k_mdot(const S* __restrict__ X, size_t xst
 template <class S, int MODE, int P>
 __global__ __launch_bounds__(RB) void k_axpy_then(const S* __restrict__ X, size_t xstride_p, int m, CoefSrc csrc,
                                                   double sgn, const S* w, S* wout, size_t np, int nrhs, int nblk,
-                                                  double2* __restrict__ partial) {
+                                                  double2* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   using C = ctype<S>;
   const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
   const int mi = MODE == 0 ? min(MG, m - i0) : 1;
@@ -520,7 +541,8 @@ __global__ __launch_bounds__(RB) void k_axpy_then(const S* __restrict__ X, size_
 template <class S, int P>
 __global__ __launch_bounds__(RB) void k_mdot_norm(const S* __restrict__ X, size_t xstride_p, int m,
                                                   const S* __restrict__ w, size_t np, int nrhs, int nblk,
-                                                  double2* __restrict__ partial) {
+                                                  double2* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   const int b = blockIdx.x, r = blockIdx.y, i0 = blockIdx.z * MG;
   const int mi = min(MG, m - i0);
   double2 acc[MG];
@@ -553,7 +575,8 @@ __global__ __launch_bounds__(RB) void k_mdot_norm(const S* __restrict__ X, size_
 template <class S, int P>
 __global__ __launch_bounds__(256) void k_axpy_scale(const S* __restrict__ X, size_t xstride_p, int m, CoefSrc csrc,
                                                     S* __restrict__ w, size_t np, int nrhs,
-                                                    double* __restrict__ out_n2, GvFuse gf) {
+                                                    double* __restrict__ out_n2, GvFuse gf, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   using C = ctype<S>;
   const int r = blockIdx.y;
   __shared__ double2 s_c[kMaxCoef];
@@ -567,7 +590,7 @@ __global__ __launch_bounds__(256) void k_axpy_scale(const S* __restrict__ X, siz
     const int lane = threadIdx.x;
     const double2 hl = lane <= gf.j ? s_c[lane] : make_double2(0.0, 0.0);
     gv_apply(GvView{gf.gst + r * gv_stride(gf.m), gf.m}, hl, make_double2(sqrt(b2), 0.0), gf.j, lane,
-             gf.est + r);
+             gf.est + r, gf.tol, gf.conv, gf.nrhs, r);
   }
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= np) return;
@@ -586,7 +609,8 @@ __global__ __launch_bounds__(256) void k_axpy_scale(const S* __restrict__ X, siz
 // a zero vector); workgroup 0 stores n2 to out_n2[r]
 template <class S, int P>
 __global__ __launch_bounds__(256) void k_scale_norm(S* __restrict__ w, CoefSrc csrc, size_t np, int nrhs,
-                                                    double* __restrict__ out_n2) {
+                                                    double* __restrict__ out_n2, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a device-side early exit (converged)
   using C = ctype<S>;
   const int r = blockIdx.y;
   __shared__ double2 s_c[1];
@@ -644,13 +668,14 @@ struct BlasP {
   }
   static void dot_multi(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
                         RedWork& rw, hipStream_t st) {
+    const int* skip = nullptr;
     const size_t np = len / P;
     const int nblk = pick_nblk(np, m * nrhs);
     rw.ensure(size_t(nblk) * m * nrhs, 0);
     k_dot_partial<S, P><<<dim3(nblk, nrhs, m), RB, 0, st>>>((const S*)X, xstride / P, (const S*)w, np, nrhs, nblk,
                                                              rw.partial.as<double2>());
     QMG_LAUNCH_CHECK();
-    k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+    k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out, skip);
     QMG_LAUNCH_CHECK();
   }
   static void norm2(const void* w, size_t len, int nrhs, double* out, RedWork& rw, hipStream_t st) {
@@ -659,17 +684,19 @@ struct BlasP {
     rw.ensure(size_t(nblk) * nrhs, 0);
     k_norm_partial<S, P><<<dim3(nblk, nrhs), RB, 0, st>>>((const S*)w, np, nblk, rw.partial.as<double2>());
     QMG_LAUNCH_CHECK();
-    k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+    k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out, nullptr);
     QMG_LAUNCH_CHECK();
   }
   static void axpy_multi(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
-                         int nrhs, hipStream_t st) {
+                         int nrhs, hipStream_t st, const int* skip, const int* mcount) {
     const size_t np = len / P;
-    k_axpy_multi<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, c, sgn, (S*)w, np, nrhs);
+    k_axpy_multi<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, c, sgn, (S*)w, np, nrhs,
+                                                               skip, mcount);
     QMG_LAUNCH_CHECK();
   }
-  static void scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st) {
-    k_scale_dev<S, P><<<dim3(nb256(len / P), nrhs), 256, 0, st>>>((S*)w, n2, mode, len / P);
+  static void scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st,
+                        const int* skip) {
+    k_scale_dev<S, P><<<dim3(nb256(len / P), nrhs), 256, 0, st>>>((S*)w, n2, mode, len / P, skip);
     QMG_LAUNCH_CHECK();
   }
   static void scale_cdev(void* w, const double2* c, double sgn, size_t len, int nrhs, hipStream_t st) {
@@ -682,38 +709,38 @@ struct BlasP {
     QMG_LAUNCH_CHECK();
   }
   static void mdot(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
-                   RedWork& rw, hipStream_t st) {
+                   RedWork& rw, hipStream_t st, const int* skip) {
     const size_t np = len / P;
     const int ng = (m + MG - 1) / MG;
     const int nblk = pick_nblk(np, ng * nrhs);
     rw.ensure(size_t(nblk) * m * nrhs, 0);
     k_mdot<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk,
-                                                       rw.partial.as<double2>());
+                                                       rw.partial.as<double2>(), skip);
     QMG_LAUNCH_CHECK();
-    k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out);
+    k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out, skip);
     QMG_LAUNCH_CHECK();
   }
   static void axpy_then(int mode, const void* X, size_t xstride, int m, const double2* c, double sgn, void* w,
-                        size_t len, int nrhs, void* out, RedWork& rw, hipStream_t st) {
+                        size_t len, int nrhs, void* out, RedWork& rw, hipStream_t st, const int* skip) {
     const size_t np = len / P;
     const int nblk = pick_nblk(np, nrhs);
     rw.ensure(size_t(nblk) * std::max(m, 1) * nrhs, 0);
     const CoefSrc src{c, nullptr, 0, nullptr};
     if (mode == 0) {
       k_axpy_then<S, 0, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride / P, m, src, sgn, (const S*)w,
-                                                                (S*)w, np, nrhs, nblk, rw.partial.as<double2>());
+                                                                (S*)w, np, nrhs, nblk, rw.partial.as<double2>(), skip);
       QMG_LAUNCH_CHECK();
-      k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, (double2*)out);
+      k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, (double2*)out, skip);
     } else {
       k_axpy_then<S, 1, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride / P, m, src, sgn, (const S*)w,
-                                                                (S*)w, np, nrhs, nblk, rw.partial.as<double2>());
+                                                                (S*)w, np, nrhs, nblk, rw.partial.as<double2>(), skip);
       QMG_LAUNCH_CHECK();
-      k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, (double*)out);
+      k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, (double*)out, skip);
     }
     QMG_LAUNCH_CHECK();
   }
   static void cgs1(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
-                   RedWork& rw, hipStream_t st, GvFuse gf) {
+                   RedWork& rw, hipStream_t st, GvFuse gf, const int* skip) {
     const size_t np = len / P;
     const int ng = (m + MG - 1) / MG;
     const bool small = len <= kSmallLen;
@@ -721,21 +748,21 @@ struct BlasP {
     rw.ensure(size_t(nblk) * (m + 1) * nrhs, size_t(nrhs));
     double2* part = rw.partial.as<double2>();
     k_mdot_norm<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk,
-                                                            part);
+                                                            part, skip);
     QMG_LAUNCH_CHECK();
     CoefSrc src{h, nullptr, 0, nullptr};
     if (small) {
       src = CoefSrc{nullptr, part, nblk, h};
     } else {
-      k_finalize2<<<(m + 1) * nrhs, RB, 0, st>>>(part, nblk, h);
+      k_finalize2<<<(m + 1) * nrhs, RB, 0, st>>>(part, nblk, h, skip);
       QMG_LAUNCH_CHECK();
     }
     k_axpy_scale<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, src, (S*)w, np, nrhs, n2,
-                                                               gf);
+                                                               gf, skip);
     QMG_LAUNCH_CHECK();
   }
   static void cgs2_small(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
-                         double2* h2, double* n2, RedWork& rw, hipStream_t st) {
+                         double2* h2, double* n2, RedWork& rw, hipStream_t st, const int* skip) {
     const size_t np = len / P;
     const int ng = (m + MG - 1) / MG;
     const int nblk = small_nblk(np);
@@ -746,18 +773,19 @@ struct BlasP {
     double2* pb = rw.partial2.as<double2>();
     S* wtmp = reinterpret_cast<S*>(pb + size_t(nblk) * m * nrhs);
     // pass 1: partials of X^dag w
-    k_mdot<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk, pa);
+    k_mdot<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk, pa,
+                                                       skip);
     QMG_LAUNCH_CHECK();
     // w' = w - X h1 (h1 summed from pa) into wtmp, partials of X^dag w' into pb
     k_axpy_then<S, 0, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>(
-        (const S*)X, xstride / P, m, CoefSrc{nullptr, pa, nblk, h1}, -1.0, (const S*)w, wtmp, np, nrhs, nblk, pb);
+        (const S*)X, xstride / P, m, CoefSrc{nullptr, pa, nblk, h1}, -1.0, (const S*)w, wtmp, np, nrhs, nblk, pb, skip);
     QMG_LAUNCH_CHECK();
     // w = w' - X h2 (h2 summed from pb), partial |w|^2 into pa
     k_axpy_then<S, 1, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>(
-        (const S*)X, xstride / P, m, CoefSrc{nullptr, pb, nblk, h2}, -1.0, (const S*)wtmp, (S*)w, np, nrhs, nblk, pa);
+        (const S*)X, xstride / P, m, CoefSrc{nullptr, pb, nblk, h2}, -1.0, (const S*)wtmp, (S*)w, np, nrhs, nblk, pa, skip);
     QMG_LAUNCH_CHECK();
     k_scale_norm<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((S*)w, CoefSrc{nullptr, pa, nblk, nullptr}, np, nrhs,
-                                                              n2);
+                                                              n2, skip);
     QMG_LAUNCH_CHECK();
   }
 };
@@ -799,13 +827,14 @@ void Blas<S>::norm2(const void* w, size_t len, int nrhs, double* out, RedWork& r
 }
 template <class S>
 void Blas<S>::axpy_multi(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
-                         int nrhs, hipStream_t st) {
+                         int nrhs, hipStream_t st, const int* skip, const int* mcount) {
   if (m <= 0) return;
-  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_multi(X, xstride, m, c, sgn, w, len, nrhs, st));
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_multi(X, xstride, m, c, sgn, w, len, nrhs, st, skip, mcount));
 }
 template <class S>
-void Blas<S>::scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st) {
-  QMG_PACKED(packable<S>(len, 0, {w}), scale_dev(w, n2, mode, len, nrhs, st));
+void Blas<S>::scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st,
+                        const int* skip) {
+  QMG_PACKED(packable<S>(len, 0, {w}), scale_dev(w, n2, mode, len, nrhs, st, skip));
 }
 template <class S>
 void Blas<S>::scale_cdev(void* w, const double2* c, double sgn, size_t len, int nrhs, hipStream_t st) {
@@ -818,59 +847,62 @@ void Blas<S>::caxpy_dev(const double2* c, double sgn, const void* y, void* x, si
 }
 template <class S>
 void Blas<S>::mdot(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
-                   RedWork& rw, hipStream_t st) {
+                   RedWork& rw, hipStream_t st, const int* skip) {
   if (m <= 0) return;
-  QMG_PACKED(packable<S>(len, xstride, {X, w}), mdot(X, xstride, m, w, len, nrhs, out, rw, st));
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), mdot(X, xstride, m, w, len, nrhs, out, rw, st, skip));
 }
 template <class S>
 void Blas<S>::axpy_mdot(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
-                        int nrhs, double2* out, RedWork& rw, hipStream_t st) {
+                        int nrhs, double2* out, RedWork& rw, hipStream_t st, const int* skip) {
   if (m <= 0) return;
   // the update must be complete before other z-groups read w: one group only when m > MG
   if (m > MG) {
-    axpy_multi(X, xstride, m, c, sgn, w, len, nrhs, st);
-    mdot(X, xstride, m, w, len, nrhs, out, rw, st);
+    axpy_multi(X, xstride, m, c, sgn, w, len, nrhs, st, skip);
+    mdot(X, xstride, m, w, len, nrhs, out, rw, st, skip);
     return;
   }
-  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_then(0, X, xstride, m, c, sgn, w, len, nrhs, out, rw, st));
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_then(0, X, xstride, m, c, sgn, w, len, nrhs, out, rw, st, skip));
 }
 template <class S>
 void Blas<S>::axpy_norm(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
-                        int nrhs, double* out, RedWork& rw, hipStream_t st) {
+                        int nrhs, double* out, RedWork& rw, hipStream_t st, const int* skip) {
   if (m > kMaxCoef) {
+    QMG_CHECK(!skip, QMG_EINVAL, "device early exit needs at most 72 basis vectors");
     axpy_multi(X, xstride, m, c, sgn, w, len, nrhs, st);
     norm2(w, len, nrhs, out, rw, st);
     return;
   }
-  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_then(1, X, xstride, m, c, sgn, w, len, nrhs, out, rw, st));
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), axpy_then(1, X, xstride, m, c, sgn, w, len, nrhs, out, rw, st, skip));
 }
 template <class S>
 bool Blas<S>::cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
-                        RedWork& rw, hipStream_t st, double2* gst, int gm, double2* est) {
+                        RedWork& rw, hipStream_t st, double2* gst, int gm, double2* est, double tol, int* conv) {
   QMG_CHECK(m >= 1, QMG_EINVAL, "Gram-Schmidt step: no basis vectors");
+  const int* skip = conv ? conv + 1 : nullptr;
   if (m + 1 > kMaxCoef || m > 64) {  // long bases: explicit update and norm instead of Pythagoras
+    QMG_CHECK(!conv, QMG_EINVAL, "device early exit needs at most 63 basis vectors");
     mdot(X, xstride, m, w, len, nrhs, h, rw, st);
     axpy_multi(X, xstride, m, h, -1.0, w, len, nrhs, st);
     norm2(w, len, nrhs, n2, rw, st);
     scale_dev(w, n2, 0, len, nrhs, st);
     return false;
   }
-  const GvFuse gf{gst, gm, m - 1, est};
-  QMG_PACKED(packable<S>(len, xstride, {X, w}), cgs1(X, xstride, m, w, len, nrhs, h, n2, rw, st, gf));
+  const GvFuse gf{gst, gm, m - 1, est, tol, conv, nrhs};
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), cgs1(X, xstride, m, w, len, nrhs, h, n2, rw, st, gf, skip));
   return gst != nullptr;
 }
 template <class S>
 void Blas<S>::cgs2_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
-                        double2* h2, double* n2, RedWork& rw, hipStream_t st) {
+                        double2* h2, double* n2, RedWork& rw, hipStream_t st, const int* skip) {
   QMG_CHECK(m >= 1, QMG_EINVAL, "Gram-Schmidt step: no basis vectors");
   if (len > kSmallLen || m > kMaxCoef) {
-    mdot(X, xstride, m, w, len, nrhs, h1, rw, st);
-    axpy_mdot(X, xstride, m, h1, -1.0, w, len, nrhs, h2, rw, st);
-    axpy_norm(X, xstride, m, h2, -1.0, w, len, nrhs, n2, rw, st);
-    scale_dev(w, n2, 0, len, nrhs, st);
+    mdot(X, xstride, m, w, len, nrhs, h1, rw, st, skip);
+    axpy_mdot(X, xstride, m, h1, -1.0, w, len, nrhs, h2, rw, st, skip);
+    axpy_norm(X, xstride, m, h2, -1.0, w, len, nrhs, n2, rw, st, skip);
+    scale_dev(w, n2, 0, len, nrhs, st, skip);
     return;
   }
-  QMG_PACKED(packable<S>(len, xstride, {X, w}), cgs2_small(X, xstride, m, w, len, nrhs, h1, h2, n2, rw, st));
+  QMG_PACKED(packable<S>(len, xstride, {X, w}), cgs2_small(X, xstride, m, w, len, nrhs, h1, h2, n2, rw, st, skip));
 }
 #undef QMG_PACKED
 
@@ -894,7 +926,7 @@ void Gmres<S>::ensure(size_t len, int nrhs, int restart) {
   h1_.ensure(size_t(restart_ + 1) * nrhs_ * sizeof(double2));
   h2_.ensure(size_t(restart_ + 1) * nrhs_ * sizeof(double2));
   nrm_.ensure(size_t(2 * nrhs_) * sizeof(double));
-  y_.ensure(size_t(restart_ + 1) * nrhs_ * sizeof(double2));
+  y_.ensure(size_t(restart_ + 1) * nrhs_ * sizeof(double2) + size_t(nrhs_) * sizeof(int));  // y, then valid counts
   r_.ensure(size_t(nrhs_) * len_ * sizeof(S));
 }
 
@@ -904,11 +936,15 @@ namespace {
 // g = (beta_r, 0, ...) and, when nb2 is given, stores |b_r| = sqrt(nb2[r]).
 template <class S, int P>
 __global__ void k_gv_start(S* __restrict__ w, const double* __restrict__ nr2, size_t np, double2* st, int m,
-                           const double* __restrict__ nb2) {
+                           const double* __restrict__ nb2, int* conv) {
   using C = ctype<S>;
   const int r = blockIdx.y;
   const double beta2 = nr2[r];
   const double beta = sqrt(beta2);
+  if (conv && blockIdx.x == 0 && r == 0 && threadIdx.x == 0) {  // device-exit counters of this cycle
+    conv[0] = 0;
+    conv[1] = 0;
+  }
   if (blockIdx.x == 0) {
     GvView v{st + r * gv_stride(m), m};
     for (int i = threadIdx.x; i <= m; i += blockDim.x) v.g()[i] = make_double2(i == 0 ? beta : 0.0, 0.0);
@@ -930,7 +966,8 @@ __global__ void k_gv_start(S* __restrict__ w, const double* __restrict__ nr2, si
 // Arnoldi column j of rhs r, staged in a separate buffer (h1 [(m+1) nrhs], h2 [(m+1) nrhs] if
 // two passes, |w|^2 [nrhs] as doubles) -> rotations; one wavefront per rhs.
 __global__ __launch_bounds__(64) void k_gv_step(double2* st, int m, int nrhs, int j, const double2* col,
-                                                int two_pass, double2* est) {
+                                                int two_pass, double2* est, double tol, int* conv) {
+  if (conv && conv[1]) return;  // every rhs converged
   const int r = blockIdx.x, lane = threadIdx.x;
   const double2* h1 = col;
   const double2* h2 = col + size_t(m + 1) * nrhs;
@@ -940,12 +977,14 @@ __global__ __launch_bounds__(64) void k_gv_step(double2* st, int m, int nrhs, in
     hl = h1[size_t(lane) * nrhs + r];
     if (two_pass) hl = cadd2(hl, h2[size_t(lane) * nrhs + r]);
   }
-  gv_apply(GvView{st + r * gv_stride(m), m}, hl, make_double2(sqrt(cn[r]), 0.0), j, lane, est + r);
+  gv_apply(GvView{st + r * gv_stride(m), m}, hl, make_double2(sqrt(cn[r]), 0.0), j, lane, est + r, tol, conv, nrhs,
+           r);
 }
 
 // y = R^-1 g over the first min(n, valid) columns, zero beyond; y[i * nrhs + r].  One
 // wavefront per rhs: R is staged in LDS, lane l holds y[l], each row is a wavefront sum.
-__global__ __launch_bounds__(64) void k_gv_solve(const double2* st, int m, int nrhs, int n, double2* y) {
+__global__ __launch_bounds__(64) void k_gv_solve(const double2* st, int m, int nrhs, int n, double2* y,
+                                                 int* nvalid) {
   __shared__ double2 Rs[64 * 64];
   const int r = blockIdx.x, lane = threadIdx.x;
   GvView v{const_cast<double2*>(st) + r * gv_stride(m), m};
@@ -967,13 +1006,14 @@ __global__ __launch_bounds__(64) void k_gv_solve(const double2* st, int m, int n
     if (lane == i) yl = yi;
   }
   if (lane < m) y[size_t(lane) * nrhs + r] = lane < nv ? yl : make_double2(0.0, 0.0);  // m <= 64
+  if (lane == 0) nvalid[r] = nv;  // basis vectors beyond nv were never built for this rhs
 }
 
 }  // namespace
 
 template <class S>
 typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int m,
-                                          int max_iter, double tol, hipStream_t st) {
+                                          int max_iter, double tol, hipStream_t st, int* conv) {
   // FP64 keeps two Gram-Schmidt passes (parity with the FP64 reference to ~1e-12); lower
   // storage precisions use one pass with the Pythagorean norm, which halves the basis traffic
   constexpr bool kCgs2 = std::is_same<S, double2>::value;
@@ -982,6 +1022,12 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
   // runs without any host round trip: rotations and the small triangular solve are on the device
   constexpr int kBatch = 4;
   QMG_CHECK(m >= 1 && m <= 64, QMG_EINVAL, "GMRES restart length must be in [1, 64]");
+  // device-side exit (conv given): one cycle of at most m steps, convergence tested by the
+  // Givens kernels, every later kernel of the cycle returns at once; no host round trip
+  const bool dev_exit = conv != nullptr;
+  QMG_CHECK(!dev_exit || (x_zero && tol > 0 && max_iter <= m && m + 1 <= kMaxCoef), QMG_EINVAL,
+            "device-exit GMRES needs a zero guess, a tolerance and one cycle of at most 63 steps");
+  const int* skip = dev_exit ? conv + 1 : nullptr;
   const size_t len = A.len();
   ensure(len, nrhs, m);
   S* V = V_.as<S>();
@@ -1008,9 +1054,10 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
     const double* nb2 = first_cycle ? (x_zero ? nrm : nb) : nullptr;
     if (packable_vec<S>(len, V)) {
       constexpr int P = kPack<S>;
-      k_gv_start<S, P><<<dim3(unsigned((len / P + 255) / 256), nrhs), 256, 0, st>>>(V, nrm, len / P, gst, m, nb2);
+      k_gv_start<S, P><<<dim3(unsigned((len / P + 255) / 256), nrhs), 256, 0, st>>>(V, nrm, len / P, gst, m, nb2,
+                                                                                     conv);
     } else {
-      k_gv_start<S, 1><<<dim3(unsigned((len + 255) / 256), nrhs), 256, 0, st>>>(V, nrm, len, gst, m, nb2);
+      k_gv_start<S, 1><<<dim3(unsigned((len + 255) / 256), nrhs), 256, 0, st>>>(V, nrm, len, gst, m, nb2, conv);
     }
     QMG_LAUNCH_CHECK();
   };
@@ -1037,22 +1084,22 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
       double2* h1 = col;
       double2* h2 = col + size_t(m + 1) * nrhs;
       double* cn = reinterpret_cast<double*>(col + size_t(2 * (m + 1)) * nrhs);
-      A.apply(vj, vn, nrhs, st);
+      A.apply(vj, vn, nrhs, st, skip);
       bool fused = false;
       if (kCgs2) {
         // CGS2: h1 = V^dag w ; w -= V h1 and h2 = V^dag w ; w -= V h2 and |w|^2 ; w /= |w|
-        Blas<S>::cgs2_step(V, vs, j + 1, vn, len, nrhs, h1, h2, cn, rw_, st);
+        Blas<S>::cgs2_step(V, vs, j + 1, vn, len, nrhs, h1, h2, cn, rw_, st, skip);
       } else {
         // one classical Gram-Schmidt pass with the norm from Pythagoras; scaling and the
         // Givens step fused into its last kernel
-        fused = Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, cn, rw_, st, gst, m, col + est_off);
+        fused = Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, cn, rw_, st, gst, m, col + est_off, tol, conv);
       }
       if (!fused) {
-        k_gv_step<<<nrhs, 64, 0, st>>>(gst, m, nrhs, j, col, kCgs2 ? 1 : 0, col + est_off);
+        k_gv_step<<<nrhs, 64, 0, st>>>(gst, m, nrhs, j, col, kCgs2 ? 1 : 0, col + est_off, tol, conv);
         QMG_LAUNCH_CHECK();
       }
       jdone = j + 1;
-      if (tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) {
+      if (!dev_exit && tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) {
         // the columns since the last read travel to the host in one copy
         QMG_HIP(hipMemcpyAsync(hcols + size_t(copied) * per_col, colsd + size_t(copied) * per_col,
                                size_t(j + 1 - copied) * per_col * sizeof(double2), hipMemcpyDeviceToHost, st));
@@ -1084,15 +1131,16 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
     }
     it += jdone;
     if (jdone > 0) {
-      // x += V y with y = R^-1 g over the accepted columns
-      k_gv_solve<<<nrhs, 64, 0, st>>>(gst, m, nrhs, jdone, yd);
+      // x += V y with y = R^-1 g over the accepted columns (zero beyond each rhs's last valid one)
+      int* nvd = reinterpret_cast<int*>(yd + size_t(m + 1) * nrhs);
+      k_gv_solve<<<nrhs, 64, 0, st>>>(gst, m, nrhs, jdone, yd, nvd);
       QMG_LAUNCH_CHECK();
-      Blas<S>::axpy_multi(V, vs, jdone, yd, 1.0, x, len, nrhs, st);
+      Blas<S>::axpy_multi(V, vs, jdone, yd, 1.0, x, len, nrhs, st, nullptr, nvd);
     }
-    if (all_conv || jdone == 0) break;
+    if (dev_exit || all_conv || jdone == 0) break;
   }
-  res.iters = it;
-  res.converged = (tol <= 0) || all_conv;
+  res.iters = dev_exit ? -1 : it;  // device-exit steps are counted in conv[2]
+  res.converged = (tol <= 0) || all_conv || dev_exit;
   return res;
 }
 

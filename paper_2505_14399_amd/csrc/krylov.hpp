@@ -13,8 +13,9 @@ namespace qmg {
 
 struct LinOp {
   virtual ~LinOp() = default;
-  // out = A in, nrhs vectors of len() complex numbers each, storage prec()
-  virtual void apply(const void* in, void* out, int nrhs, hipStream_t st) = 0;
+  // out = A in, nrhs vectors of len() complex numbers each, storage prec().  skip: a device
+  // flag; an operator may return at once when it is set (device-side early exit), or ignore it
+  virtual void apply(const void* in, void* out, int nrhs, hipStream_t st, const int* skip = nullptr) = 0;
   virtual size_t len() const = 0;
   virtual qmg_prec prec() const = 0;
 };
@@ -49,32 +50,37 @@ struct Blas {
                         double2* out, RedWork& rw, hipStream_t st);
   // as dot_multi, reading w once per group of up to 8 vectors
   static void mdot(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
-                   RedWork& rw, hipStream_t st);
+                   RedWork& rw, hipStream_t st, const int* skip = nullptr);
   // w[r] += sgn * sum_i c[i * nrhs + r] X_i[r], then out = <X_i[r], w[r]> (fused)
   static void axpy_mdot(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
-                        int nrhs, double2* out, RedWork& rw, hipStream_t st);
+                        int nrhs, double2* out, RedWork& rw, hipStream_t st, const int* skip = nullptr);
   // w[r] += sgn * sum_i c[i * nrhs + r] X_i[r], then out[r] = ||w[r]||^2 (fused)
   static void axpy_norm(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
-                        int nrhs, double* out, RedWork& rw, hipStream_t st);
+                        int nrhs, double* out, RedWork& rw, hipStream_t st, const int* skip = nullptr);
   // one Gram-Schmidt step: h = X^dag w (m vectors), w <- (w - X h) / beta with
   // beta^2 = |w|^2 - |h|^2, n2[r] = beta^2 (device); h needs (m + 1) * nrhs slots, slot m
   // receives |w|^2 before the update.  With gst, the GMRES Givens step for Hessenberg column
   // m - 1 (restart length gm) runs in the same launch and writes its estimates to est; returns
   // whether it did.
+  // With conv (device counters, see Gmres::solve) the Givens step also tests est <= tol and the
+  // kernels return at once once every rhs has converged.
   static bool cgs1_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h, double* n2,
-                        RedWork& rw, hipStream_t st, double2* gst = nullptr, int gm = 0, double2* est = nullptr);
+                        RedWork& rw, hipStream_t st, double2* gst = nullptr, int gm = 0, double2* est = nullptr,
+                        double tol = 0.0, int* conv = nullptr);
   // two Gram-Schmidt passes: h1 = X^dag w ; w -= X h1 ; h2 = X^dag w ; w -= X h2 ;
   // n2[r] = |w|^2 ; w /= |w| (h1, h2, n2 on the device)
   static void cgs2_step(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
-                        double2* h2, double* n2, RedWork& rw, hipStream_t st);
+                        double2* h2, double* n2, RedWork& rw, hipStream_t st, const int* skip = nullptr);
   // out[r] = ||w[r]||^2
   static void norm2(const void* w, size_t len, int nrhs, double* out, RedWork& rw, hipStream_t st);
   // w[r] += sgn * sum_i c[i * nrhs + r] X_i[r]
+  // (mcount: optional device int per rhs capping m for that rhs)
   static void axpy_multi(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w,
-                         size_t len, int nrhs, hipStream_t st);
+                         size_t len, int nrhs, hipStream_t st, const int* skip = nullptr, const int* mcount = nullptr);
   // w[r] *= f(n2[r]) with f = 1/sqrt (mode 0) or sqrt (mode 1) or a direct factor (mode 2,
   // n2 then holds the factor); a zero norm gives a zero vector in mode 0
-  static void scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st);
+  static void scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st,
+                        const int* skip = nullptr);
   // w[r] *= c[r] (complex, device)
   static void scale_cdev(void* w, const double2* c, double sgn, size_t len, int nrhs, hipStream_t st);
   // x[r] += sgn * c[r] * y[r]  (complex scalar per rhs, on device)
@@ -94,8 +100,12 @@ class Gmres {
     std::vector<double> rel_est;  // final residual estimate / ||b|| per rhs
   };
   // x: initial guess if !x_zero, solution on return.  tol <= 0: exactly max_iter steps.
+  // conv (device int[3], optional): device-side exit for graph capture: one cycle of max_iter
+  // <= restart steps from a zero guess; conv[0] counts converged rhs, conv[1] is raised when
+  // all have converged (later kernels of the cycle return at once), conv[2] accumulates the
+  // steps of rhs 0.  No host round trip; iters is then -1.
   Result solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int restart, int max_iter, double tol,
-               hipStream_t st);
+               hipStream_t st, int* conv = nullptr);
 
  private:
   void ensure(size_t len, int nrhs, int restart);

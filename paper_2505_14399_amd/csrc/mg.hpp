@@ -26,6 +26,8 @@ struct HierarchyDev {
   double t_smooth = 0, t_svd = 0, t_coarse = 0, t_total = 0;
   int n_post = 8, coarse_max = 500;
   double coarse_tol = 0.03;
+  int cycle_steps = 0;       // > 0: device-exit coarse solve with this step budget
+  bool cycle_graph = false;  // capture the K-cycle into a hipGraph (needs cycle_steps > 0)
 };
 
 // prolong: fine[rhs] (native, storage S) = P coarse[rhs]
@@ -36,7 +38,7 @@ void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const 
                      hipStream_t st);
 // out = D_c in, coarse vectors [nrhs][d][2k]
 void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, const void* in, void* out, int nrhs,
-                         hipStream_t st);
+                         hipStream_t st, const int* skip = nullptr);  // skip: device early-exit flag
 // Galerkin build in FP64 from U64 and P64 into Y64 (needs a workspace of 8 * d * (2k)^2 double2)
 void build_coarse(HierarchyDev& h, hipStream_t st);
 // chiral split + block gather: fine FP64 native [r][12][V] -> blocks [2d][r][N] FP64

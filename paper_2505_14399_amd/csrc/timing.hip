@@ -46,6 +46,8 @@ TimedLaunch::TimedLaunch(const char* family, hipStream_t st, double bytes, doubl
   prev_ = t_current;
   t_current = this;
   if (!g_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st_, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;  // no events in graphs
   std::lock_guard<std::mutex> lk(g_mu);
   e0_ = get_event();
   e1_ = get_event();

@@ -156,8 +156,9 @@ __global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const
 template <class S, int NR, int PR>
 __global__ __launch_bounds__(1024) void k_coarse_apply(const S* __restrict__ Y, const S* __restrict__ in,
                                                        S* __restrict__ out, const int* __restrict__ cnb, int d, int m,
-                                                       int nrhs, int H) {
+                                                       int nrhs, int H, const int* __restrict__ skip) {
   using C = ctype<S>;
+  if (skip && *skip) return;  // device-side early exit of a converged coarse solve
   extern __shared__ unsigned char smem_raw[];
   cplx<C>* vin = reinterpret_cast<cplx<C>*>(smem_raw);  // [NR][9][m]
   cplx<C>* part = vin + size_t(NR) * 9 * m;              // [NR][9 H][m]
@@ -668,7 +669,7 @@ void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const 
 }
 
 void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, const void* in, void* out, int nrhs,
-                         hipStream_t st) {
+                         hipStream_t st, const int* skip) {
   const int m = 2 * h.k;
   TimedLaunch tl("coarse_apply", st, double(h.blk.d) * (9.0 * m * m + 2.0 * m * nrhs) * prec_bytes(prec),
                  8.0 * 9.0 * m * m * h.blk.d * nrhs);
@@ -684,7 +685,7 @@ void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, co
       if (lds > 64 * 1024)
         QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
       launch(kern, dim3(h.blk.d, (nrhs + NR - 1) / NR), dim3(threads), uint32_t(lds), st, Y, in, out,
-             h.cnb.as<int>(), h.blk.d, m, nrhs, H);
+             h.cnb.as<int>(), h.blk.d, m, nrhs, H, skip);
     };
     const bool packed = m % PK == 0;
     if (packed) {

@@ -293,3 +293,49 @@ def test_transfer_multi_rhs(qmg, dims, block, k, inner, nrhs):
         assert rel(got_c[q], want_c[q]) < tol
         assert rel(got_a[q], want_a[q]) < (1e-13 if inner == "f64" else 5e-6)
     mg.close()
+
+
+def test_graph_captured_kcycle_c1(qmg, c1):
+    """Device-exit coarse solve, eager and captured into a hipGraph: both reach the tolerance,
+    and every replay of the graph (interleaved with the solver's eager launches) reproduces the
+    eager device-exit cycle bit for bit, so the two solutions are identical."""
+    w, U, lat, mg, olat, oh = c1
+    banner("graph-captured K-cycle c1")
+    b = fields.gaussian_spinor(w["dims"], 1, w["seed"], tag=w["tag"])
+    Dm = wilson.dense_wilson(U, w["mass"], w["xi"], w["bc_t"], w["dims"])
+    X = np.linalg.solve(Dm, b.reshape(1, -1).T).T.reshape(b.shape)
+    try:
+        mg.set_cycle(12, graph=False)
+        x_e, info_e = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+        mg.set_cycle(12, graph=True)
+        x_g, info_g = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+        x_g2, _ = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)  # a second solve captures again
+    finally:
+        mg.set_cycle(0, graph=False)
+    print(f"[solve] eager {info_e[0]} graph {info_g[0]}")
+    assert info_e[0]["true_rel_res"] <= 1e-12 and info_g[0]["true_rel_res"] <= 1e-12
+    assert info_e[0]["outer_iters"] == info_g[0]["outer_iters"]
+    assert info_e[0]["coarse_iters"] == info_g[0]["coarse_iters"]
+    assert torch.equal(x_e, x_g) and torch.equal(x_g, x_g2)
+    assert rel(to_np(x_g), X) < 1e-8
+    with pytest.raises(qmg.QmgError):
+        mg.set_cycle(0, graph=True)
+
+
+def test_graph_captured_kcycle_mixed(qmg):
+    """Captured K-cycle inside the FP32 GCR / FP64 refinement on 8^4 (k = 12): reaches 1e-10."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    banner("graph-captured K-cycle, FP32 inner")
+    U = fields.random_gauge(dims, 0.4, 27)
+    lat = qmg.Lattice(dims, 0.02, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 24, 8, 12, n_setup_iter=16, inner="f32", seed=5)
+    b = fields.gaussian_spinor(dims, 2, 28)
+    x0, i0 = qmg.mg_solve(mg, to_gpu(b), tol=1e-10)
+    mg.set_cycle(16, graph=True)
+    x1, i1 = qmg.mg_solve(mg, to_gpu(b), tol=1e-10)
+    print(f"[solve] host-checked {i0} captured {i1}")
+    for x, info in ((x0, i0), (x1, i1)):
+        r = b - wilson.apply_wilson(U, to_np(x), 0.02, 1.0, -1, dims)
+        for q in range(2):
+            assert np.linalg.norm(r[q]) / np.linalg.norm(b[q]) < 2e-10
+    mg.close()
