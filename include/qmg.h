@@ -212,12 +212,13 @@ qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);
  * Errors: EINVAL (null, coarse_steps outside [0, 63], graph not 0/1, graph without steps). */
 qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
 
-/* Measurement hooks.  qmg_timing_enable(1) clears the record and brackets every later launch
- * of the instrumented kernel families ("dslash/site", "dslash/twalk", "dslash/dir",
- * "dslash/canonical", "isvd", "coarse_apply", "prolong", "restrict", "coarse_build") with HIP
- * events on its stream; 0 stops recording.  qmg_timing_query returns, for one family, the
- * launches recorded, their summed duration (ms, it synchronizes on the events) and the summed
- * algorithmic bytes and flops; a name without '/' also sums its sub-families ("dslash"). */
+/* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times every n-th
+ * later launch of each instrumented kernel family ("dslash/site", "dslash/twalk", "dslash/dir",
+ * "dslash/canonical", "dslash/batched", "isvd", "coarse_apply", "prolong", "restrict",
+ * "coarse_build") with a pair of HIP events attached to the dispatch (its own start and end);
+ * 0 stops recording.  qmg_timing_query returns, for one family, the launches timed, their
+ * summed duration (ms, it synchronizes on the events) and their summed algorithmic bytes and
+ * flops; a name without '/' also sums its sub-families ("dslash").  Errors: EINVAL (n < 0). */
 qmg_status qmg_timing_enable(int32_t on);
 qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total_ms, double* algo_bytes,
                             double* algo_flops);
@@ -231,7 +232,8 @@ qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total
 qmg_status qmg_autotune(int32_t on);
 /* Force one native-layout dslash variant for every later call (1: one site per thread; 2, 4, 8:
  * sites per thread along t, used when Lt is a multiple; 16: four threads per site, one per
- * direction); 0 restores the automatic choice.
+ * direction; 32, 64: one site per thread for 2 or 4 right-hand sides at once, used when nrhs is
+ * a multiple); 0 restores the automatic choice.
  * For tests and tuning studies. */
 qmg_status qmg_set_dslash_variant(int32_t variant);
 qmg_status qmg_tune_save(const char* path);

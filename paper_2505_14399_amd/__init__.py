@@ -410,9 +410,10 @@ def smooth(lat: Lattice, U, phi, n_iter, prec="f64"):
     return out
 
 
-def timing_enable(on=True):
-    """Start (clearing the record) or stop per-launch HIP-event timing of the kernel families."""
-    _check(load_library().qmg_timing_enable(1 if on else 0))
+def timing_enable(on=True, every=1):
+    """Start (clearing the record; every `every`-th launch of each family is timed) or stop
+    per-launch HIP-event timing of the kernel families."""
+    _check(load_library().qmg_timing_enable(int(every) if on else 0))
 
 
 def timing_query(family):

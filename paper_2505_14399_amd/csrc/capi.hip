@@ -891,7 +891,10 @@ qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t) {
 }
 
 qmg_status qmg_timing_enable(int32_t on) {
-  return guard([&] { timing_enable(on != 0); });
+  return guard([&] {
+    QMG_CHECK(on >= 0, QMG_EINVAL, "timing_enable: on must be >= 0");
+    timing_enable(on);
+  });
 }
 
 qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total_ms, double* algo_bytes,
@@ -924,8 +927,8 @@ qmg_status qmg_autotune(int32_t on) {
 
 qmg_status qmg_set_dslash_variant(int32_t v) {
   return guard([&] {
-    QMG_CHECK(v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16, QMG_EINVAL,
-              "dslash variant must be 0, 1, 2, 4, 8 or 16");
+    QMG_CHECK(v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64, QMG_EINVAL,
+              "dslash variant must be 0, 1, 2, 4, 8, 16, 32 or 64");
     set_dslash_variant(v);
   });
 }

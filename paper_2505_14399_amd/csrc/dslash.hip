@@ -468,7 +468,8 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     return;
   }
   // Launch variants for the native layout: 1 = one site per thread, 2/4/8 = t-walking with
-  // that many sites per thread along t, 16 = direction-split (four threads per site).
+  // that many sites per thread along t, 16 = direction-split (four threads per site), 32/64 =
+  // one site per thread for 2/4 right-hand sides at once (links loaded once for all of them).
   // Default heuristic: the longest t-chunk that still gives >= 1024 workgroups, else the
   // direction split when one thread per site would leave the GPU short of wavefronts.  With the autotuner enabled every valid variant is timed on first
   // use of (precision, extents, nrhs, adjoint) and the fastest is kept.
@@ -479,16 +480,24 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   const double cb = double(sizeof(S));
   const double bytes = double(a.V) * (24.0 * a.nrhs + 36.0) * cb, flops = 1368.0 * a.V * a.nrhs;
   auto run = [&](int v) {
-    TimedLaunch tl(v == 16 ? "dslash/dir" : v > 1 ? "dslash/twalk" : "dslash/site", st, bytes, flops);
+    TimedLaunch tl(v == 16 ? "dslash/dir" : (v == 1 || v >= 32) ? "dslash/site" : "dslash/twalk", st, bytes, flops);
     switch (v) {
       case 8: launch_tw<S, 8>(U, in, out, a, st); break;
       case 4: launch_tw<S, 4>(U, in, out, a, st); break;
       case 2: launch_tw<S, 2>(U, in, out, a, st); break;
       case 16: launch_dir<S>(U, in, out, a, st); break;
+      case 32: launch_t<S, false, 2>(U, in, out, a, st); break;
+      case 64: launch_t<S, false, 4>(U, in, out, a, st); break;
       default: launch_t<S, false, 1>(U, in, out, a, st); break;
     }
   };
-  if (a.tchunk > 0 && (a.tchunk == 1 || a.tchunk == 16 || Lt % a.tchunk == 0)) {
+  auto valid = [&](int v) {
+    if (v == 1 || v == 16) return true;
+    if (v == 32) return a.nrhs % 2 == 0;
+    if (v == 64) return a.nrhs % 4 == 0;
+    return (v == 2 || v == 4 || v == 8) && Lt % v == 0;
+  };
+  if (a.tchunk > 0 && valid(a.tchunk)) {
     run(a.tchunk);
     return;
   }
@@ -496,6 +505,9 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   // one thread per site fills 256 CUs x 32 wavefronts only from 2^18 sites x rhs on
   const bool small = long(a.V) * a.nrhs < (1L << 19);
   int choice = fits(8) ? 8 : fits(4) ? 4 : fits(2) ? 2 : small ? 16 : 1;
+  // 4-byte storage (BF16/FP16): the one-thread-per-site forms hold every hop's loads in
+  // registers (up to 256 VGPRs, one wavefront per SIMD); the direction split needs 64-70
+  if (sizeof(S) == 4) choice = 16;
   if (tune_enabled()) {
     const std::string key = "dslash/" + std::to_string(int(StoreTraits<S>::prec)) + "/" + std::to_string(a.L[0]) +
                             "x" + std::to_string(a.L[1]) + "x" + std::to_string(a.L[2]) + "x" +
@@ -504,11 +516,9 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     if (cached > 0) {
       choice = cached;
     } else {
-      int cand[5], n = 0;
-      cand[n++] = 1;
-      cand[n++] = 16;
-      for (int tch : {2, 4, 8})
-        if (Lt % tch == 0) cand[n++] = tch;
+      int cand[8], n = 0;
+      for (int v : {1, 16, 2, 4, 8, 32, 64})
+        if (valid(v)) cand[n++] = v;
       choice = tune_measure(key, cand, n, st, run);
     }
   }

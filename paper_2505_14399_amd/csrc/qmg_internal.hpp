@@ -83,10 +83,11 @@ template <class T> __host__ __device__ inline cplx<T> times_mi(cplx<T> a) { retu
 // ----------------------------------------------------------------------------------------
 // storage types: complex numbers as stored in memory
 
-struct cbf16 {  // two bfloat16 (upper halves of IEEE binary32), round to nearest even
+// 4-byte aligned, so that one complex number is one 32-bit access
+struct alignas(4) cbf16 {  // two bfloat16 (upper halves of IEEE binary32), round to nearest even
   uint16_t re, im;
 };
-struct chalf {
+struct alignas(4) chalf {
   _Float16 re, im;
 };
 

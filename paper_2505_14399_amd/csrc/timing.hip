@@ -1,6 +1,9 @@
 // Optional per-kernel-family timing: when enabled, each launch of an instrumented kernel gets
 // a pair of HIP events (attached to the dispatch itself, so they hold the kernel's own start
-// and end), and the launcher adds the algorithmic bytes and flops of that launch.  Off by default (no events are recorded).
+// and end), and the launcher adds the algorithmic bytes and flops of that launch.  Off by
+// default (no events are recorded).  With sampling n > 1 only every n-th launch of each family
+// is timed (and its bytes and flops added), which keeps the event traffic out of the
+// measured region.
 // Family names may have a sub-name after '/' (one per launch form, e.g. "dslash/dir"); a query
 // for "dslash" sums every "dslash/..." family.
 #include <map>
@@ -15,9 +18,11 @@ namespace {
 struct Family {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   double bytes = 0, flops = 0;
+  long calls = 0;
 };
 std::mutex g_mu;
 bool g_on = false;
+int g_every = 1;
 std::map<std::string, Family> g_fam;
 std::vector<hipEvent_t> g_pool;
 
@@ -49,6 +54,7 @@ TimedLaunch::TimedLaunch(const char* family, hipStream_t st, double bytes, doubl
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st_, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;  // no events in graphs
   std::lock_guard<std::mutex> lk(g_mu);
+  if (g_fam[fam_].calls++ % g_every != 0) return;  // not sampled
   e0_ = get_event();
   e1_ = get_event();
   if (!kernel_) {
@@ -81,8 +87,10 @@ TimedLaunch::~TimedLaunch() {
   f.flops += flops_;
 }
 
-void timing_enable(bool on) {
+void timing_enable(int every) {
   std::lock_guard<std::mutex> lk(g_mu);
+  const bool on = every > 0;
+  g_every = on ? every : 1;
   for (auto& kv : g_fam)
     for (auto& p : kv.second.ev) {
       g_pool.push_back(p.first);

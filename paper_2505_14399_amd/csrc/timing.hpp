@@ -8,7 +8,7 @@
 namespace qmg {
 
 bool timing_on();
-void timing_enable(bool on);
+void timing_enable(int every);  // 0: off; n >= 1: time every n-th launch of each family
 void timing_query(const char* family, int64_t* n, double* ms, double* bytes, double* flops);
 
 // RAII scope around one instrumented launch; events exist only while timing is enabled.

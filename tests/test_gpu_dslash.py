@@ -88,12 +88,12 @@ def test_dslash_full_size_sampled(qmg, dims, nrhs):
         assert rel(got[r], ref) < 1e-6
 
 
-@pytest.mark.parametrize("variant", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("variant", [1, 2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 1e-6), ("bf16", 1e-2)])
 def test_dslash_every_launch_variant(qmg, variant, prec, tol):
     """Each native launch form (site-parallel, t-walking with 2/4/8 sites per thread, four
     threads per site)."""
-    dims, nrhs = (6, 4, 4, 16), 3
+    dims, nrhs = (6, 4, 4, 16), 4
     banner(f"dslash variant {variant} {prec}")
     U = fields.random_gauge(dims, 0.6, 9)
     psi = fields.gaussian_spinor(dims, nrhs, 10)
