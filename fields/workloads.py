@@ -3,8 +3,9 @@
 Each entry fixes lattice extents, boundary condition, gauge roughness eps,
 anisotropy xi, quark mass, aggregate block shape, test-vector count, stream
 batch, truncation rank per chirality and the inner precision of the solve.
-A mass of None means "tuned so that the smallest |eigenvalue| of D is about
-1e-3"; the tuned value is read from tests/golden/tuned_masses.json.
+A mass of None means "near critical": the left edge of the spectrum of D moved just inside
+the right half plane (tests/golden/make_tuned_masses.py explains the reading and writes
+tests/golden/tuned_masses.json, from which the value is read).
 """
 from __future__ import annotations
 
