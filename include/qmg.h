@@ -212,8 +212,9 @@ qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);
  * Errors: EINVAL (null, coarse_steps outside [0, 63], graph not 0/1, graph without steps). */
 qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
 
-/* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times every n-th
- * later launch of each instrumented kernel family ("dslash/site", "dslash/twalk", "dslash/dir",
+/* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times the first 64
+ * later launches of each instrumented kernel family and then about one in n (picked by a hash
+ * of the call index) ("dslash/site", "dslash/twalk", "dslash/dir",
  * "dslash/canonical", "dslash/batched", "isvd", "coarse_apply", "prolong", "restrict",
  * "coarse_build") with a pair of HIP events attached to the dispatch (its own start and end);
  * 0 stops recording.  qmg_timing_query returns, for one family, the launches timed, their
@@ -222,6 +223,8 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
 qmg_status qmg_timing_enable(int32_t on);
 qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total_ms, double* algo_bytes,
                             double* algo_flops);
+/* Every launch of the family (timed or not) since qmg_timing_enable.  Errors: EINVAL (null). */
+qmg_status qmg_timing_calls(const char* family, int64_t* calls);
 
 /* Autotuner.  qmg_autotune(1) (or QMG_TUNE=1 in the environment) makes every kernel with
  * launch variants (the native-layout dslash: one site per thread, 2/4/8 sites per thread

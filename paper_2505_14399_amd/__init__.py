@@ -77,6 +77,7 @@ SIGNATURES = {
     "qmg_mg_setup_times": [_P, _P],
     "qmg_timing_enable": [_I],
     "qmg_timing_query": [ctypes.c_char_p, _P, _P, _P, _P],
+    "qmg_timing_calls": [ctypes.c_char_p, _P],
     "qmg_mg_set_cycle": [_P, _I, _I],
     "qmg_autotune": [_I],
     "qmg_set_dslash_variant": [_I],
@@ -417,12 +418,15 @@ def timing_enable(on=True, every=1):
 
 
 def timing_query(family):
-    """{'launches', 'ms', 'bytes', 'flops'} summed over the recorded launches of `family`."""
+    """{'launches', 'ms', 'bytes', 'flops'} summed over the timed launches of `family`, and 'calls'
+    (every launch since timing was enabled)."""
     n = ctypes.c_int64()
     ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(load_library().qmg_timing_query(family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
                                            ctypes.byref(fl)))
-    return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+    calls = ctypes.c_int64()
+    _check(load_library().qmg_timing_calls(family.encode(), ctypes.byref(calls)))
+    return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value, "calls": calls.value}
 
 
 def autotune(on=True):

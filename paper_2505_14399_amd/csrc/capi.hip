@@ -921,6 +921,14 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph) {
   });
 }
 
+qmg_status qmg_timing_calls(const char* family, int64_t* calls) {
+  return guard([&] {
+    check_ptr(family, "family");
+    check_ptr(calls, "calls");
+    *calls = timing_calls(family);
+  });
+}
+
 qmg_status qmg_autotune(int32_t on) {
   return guard([&] { tune_enable(on != 0); });
 }

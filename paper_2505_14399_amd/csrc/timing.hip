@@ -1,9 +1,10 @@
 // Optional per-kernel-family timing: when enabled, each launch of an instrumented kernel gets
 // a pair of HIP events (attached to the dispatch itself, so they hold the kernel's own start
 // and end), and the launcher adds the algorithmic bytes and flops of that launch.  Off by
-// default (no events are recorded).  With sampling n > 1 only every n-th launch of each family
-// is timed (and its bytes and flops added), which keeps the event traffic out of the
-// measured region.
+// default (no events are recorded).  With sampling n > 1, after its first 64 launches about one
+// launch in n of each family, picked by a hash of its call index, is timed (and its bytes and
+// flops added), which keeps the event traffic out of the measured region; every call is
+// counted.
 // Family names may have a sub-name after '/' (one per launch form, e.g. "dslash/dir"); a query
 // for "dslash" sums every "dslash/..." family.
 #include <map>
@@ -23,6 +24,7 @@ struct Family {
 std::mutex g_mu;
 bool g_on = false;
 int g_every = 1;
+constexpr long kAlwaysTimed = 64;  // the first launches of a family are always timed
 std::map<std::string, Family> g_fam;
 std::vector<hipEvent_t> g_pool;
 
@@ -54,7 +56,14 @@ TimedLaunch::TimedLaunch(const char* family, hipStream_t st, double bytes, doubl
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st_, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;  // no events in graphs
   std::lock_guard<std::mutex> lk(g_mu);
-  if (g_fam[fam_].calls++ % g_every != 0) return;  // not sampled
+  const long call = g_fam[fam_].calls++;
+  if (g_every > 1 && call >= kAlwaysTimed) {  // sample a pseudo-random 1 / every of the launches
+    uint64_t x = uint64_t(call) + 0x9E3779B97F4A7C15ull;  // (no aliasing with periodic launch patterns)
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    if (x % uint64_t(g_every) != 0) return;
+  }
   e0_ = get_event();
   e1_ = get_event();
   if (!kernel_) {
@@ -98,6 +107,15 @@ void timing_enable(int every) {
     }
   g_fam.clear();
   g_on = on;
+}
+
+int64_t timing_calls(const char* family) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const std::string q(family), pre = q + "/";
+  int64_t n = 0;
+  for (auto& kv : g_fam)
+    if (kv.first == q || kv.first.compare(0, pre.size(), pre) == 0) n += kv.second.calls;
+  return n;
 }
 
 void timing_query(const char* family, int64_t* n, double* ms, double* bytes, double* flops) {

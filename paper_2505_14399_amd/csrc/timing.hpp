@@ -10,6 +10,7 @@ namespace qmg {
 bool timing_on();
 void timing_enable(int every);  // 0: off; n >= 1: time every n-th launch of each family
 void timing_query(const char* family, int64_t* n, double* ms, double* bytes, double* flops);
+int64_t timing_calls(const char* family);  // every launch since timing was enabled, timed or not
 
 // RAII scope around one instrumented launch; events exist only while timing is enabled.
 // With kernel = true (default) the pair is attached to the next kernel started through
