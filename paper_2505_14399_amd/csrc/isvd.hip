@@ -388,6 +388,47 @@ __global__ __launch_bounds__(T) void k_isvd_rotate(double2* __restrict__ Ug, con
   }
 }
 
+// Rotation, row-parallel form: U_new = [U, Psi] M (M = [A; B], w x kn) is independent per row,
+// so a workgroup takes 256 rows of one problem (one row per thread, its w inputs held in
+// registers before any output of that row is written, which makes the in-place update safe)
+// and M is staged in LDS.  Every input and output element moves once, and all rows of all
+// problems are in flight at once instead of one problem per workgroup.
+template <int WM>
+__global__ __launch_bounds__(T) void k_isvd_rotate_rows(double2* __restrict__ Ug, const double2* __restrict__ Psig,
+                                                        const double2* __restrict__ AB, IsvdArgs a) {
+  __shared__ cd Ms[WM * MAXW];
+  const int N = a.N, kp = a.kp, w = a.w, kn = a.kn, k = a.k, r = a.r;
+  const int p = blockIdx.y;
+  const double2* ab = AB + size_t(p) * w * kn;
+  for (int e = threadIdx.x; e < w * kn; e += T) Ms[e] = ld2(ab, e);
+  __syncthreads();
+  const int row = blockIdx.x * T + threadIdx.x;
+  if (row >= N) return;
+  double2* U = Ug + size_t(p) * k * N;
+  const double2* Psi = Psig + size_t(p) * r * N;
+  cd in[WM];
+#pragma unroll
+  for (int c = 0; c < WM; ++c) {
+    if (c < w) in[c] = c < kp ? ld2(U, size_t(c) * N + row) : ld2(Psi, size_t(c - kp) * N + row);
+  }
+  for (int i0 = 0; i0 < kn; i0 += 8) {
+    cd acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = {0, 0};
+#pragma unroll
+    for (int c = 0; c < WM; ++c) {
+      if (c < w) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (i0 + t < kn) acc[t] += in[c] * Ms[c * kn + i0 + t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (i0 + t < kn) st2(U, size_t(i0 + t) * N + row, acc[t]);
+  }
+}
+
 size_t gram_lds(int kp, int r) {
   const int w = kp + r;
   const int ta = (w + 1) / 2, tb = (r + 1) / 2, ntile = ta * tb;
@@ -419,7 +460,14 @@ void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, HierarchyDev&
   QMG_LAUNCH_CHECK();
   k_isvd_small<<<a.nprob, TW, ls, st>>>(small.as<double2>(), sigma_dev.as<double>(), AB.as<double2>(), a);
   QMG_LAUNCH_CHECK();
-  k_isvd_rotate<NPF><<<grid, T, lr, st>>>(h.P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+  const dim3 rgrid((a.N + T - 1) / T, a.nprob);
+  if (a.w <= 32) {
+    k_isvd_rotate_rows<32><<<rgrid, T, 0, st>>>(h.P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+  } else if (a.w <= 48) {
+    k_isvd_rotate_rows<48><<<rgrid, T, 0, st>>>(h.P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+  } else {
+    k_isvd_rotate<NPF><<<grid, T, lr, st>>>(h.P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+  }
   QMG_LAUNCH_CHECK();
 }
 
