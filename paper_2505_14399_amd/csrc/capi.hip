@@ -102,6 +102,7 @@ struct KCycle : Precond {
   Gmres<S> gc, gf;
   DevBuf rc, ec, rS, zS, conv;
   long coarse_iters = 0, smooth_iters = 0, cycles = 0;
+  int last_coarse = 0;             // coarse steps of the previous cycle (host-checked form)
   hipStream_t gs = nullptr;        // private stream of the captured cycle
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -120,8 +121,11 @@ struct KCycle : Precond {
     if (h.cycle_steps > 0) {
       gc.solve(Dc, rc.p, ec.p, true, nrhs, h.cycle_steps, h.cycle_steps, h.coarse_tol, st, conv.as<int>());
     } else {
-      auto rcs = gc.solve(Dc, rc.p, ec.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st);
+      // first read of the convergence estimates one step before the previous cycle's count
+      const int hint = last_coarse > 1 ? last_coarse - 1 : 0;
+      auto rcs = gc.solve(Dc, rc.p, ec.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st, nullptr, hint);
       coarse_iters += rcs.iters;
+      last_coarse = rcs.iters;
     }
     launch_prolong(p, h, P, ec.p, z_s, nrhs, st);
     gf.solve(D, r_s, z_s, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);

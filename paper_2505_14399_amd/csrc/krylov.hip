@@ -1013,7 +1013,7 @@ __global__ __launch_bounds__(64) void k_gv_solve(const double2* st, int m, int n
 
 template <class S>
 typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int m,
-                                          int max_iter, double tol, hipStream_t st, int* conv) {
+                                          int max_iter, double tol, hipStream_t st, int* conv, int first_check) {
   // FP64 keeps two Gram-Schmidt passes (parity with the FP64 reference to ~1e-12); lower
   // storage precisions use one pass with the Pythagorean norm, which halves the basis traffic
   constexpr bool kCgs2 = std::is_same<S, double2>::value;
@@ -1099,7 +1099,12 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
         QMG_LAUNCH_CHECK();
       }
       jdone = j + 1;
-      if (!dev_exit && tol > 0 && ((j + 1) % kBatch == 0 || j == mc - 1)) {
+      // read points: every kBatch steps, or (with a hint, in the first cycle) at first_check and
+      // every second step after it
+      const bool read_now = first_check > 0 && it == 0
+                                ? (j + 1 >= first_check && (j + 1 - first_check) % 2 == 0)
+                                : (j + 1) % kBatch == 0;
+      if (!dev_exit && tol > 0 && (read_now || j == mc - 1)) {
         // the columns since the last read travel to the host in one copy
         QMG_HIP(hipMemcpyAsync(hcols + size_t(copied) * per_col, colsd + size_t(copied) * per_col,
                                size_t(j + 1 - copied) * per_col * sizeof(double2), hipMemcpyDeviceToHost, st));

@@ -104,8 +104,11 @@ class Gmres {
   // <= restart steps from a zero guess; conv[0] counts converged rhs, conv[1] is raised when
   // all have converged (later kernels of the cycle return at once), conv[2] accumulates the
   // steps of rhs 0.  No host round trip; iters is then -1.
+  // first_check (host-checked mode): Arnoldi step after which the host first reads the
+  // estimates (later every two steps); 0 = every four steps.  A caller that knows the typical
+  // count (the previous solve's) saves host round trips without changing the result.
   Result solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int restart, int max_iter, double tol,
-               hipStream_t st, int* conv = nullptr);
+               hipStream_t st, int* conv = nullptr, int first_check = 0);
 
  private:
   void ensure(size_t len, int nrhs, int restart);
