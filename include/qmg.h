@@ -159,10 +159,10 @@ typedef struct {
 } qmg_solve_info;
 
 /* Solve D x = b (or D^dag x = b when adjoint != 0, as gamma5 D^-1 gamma5) to a true FP64
- * relative residual <= tol with flexible GCR preconditioned by the two-level K-cycle
- * (Section 2.1: restrict, coarse GMRES to coarse_tol, prolong, post-smooth).  With an inner
- * precision below F64 the K-cycle and the inner GCR run in that precision inside an FP64
- * defect-correction loop.
+ * relative residual <= tol with flexible GMRES(16) preconditioned by the two-level K-cycle
+ * (Section 2.1: restrict, coarse GMRES to coarse_tol, prolong, post-smooth; Section 4: FGMRES
+ * as the outer solver).  With an inner precision below F64 the K-cycle runs in that precision
+ * and the flexible GMRES in FP32, inside an FP64 defect-correction loop.
  * b, x: device, canonical FP64 [nrhs][V][4][3]; x is the initial guess on entry (zeros
  *   allowed) and the solution on return.  info: host array of nrhs entries (may be NULL).
  * Errors: ENOCONV (x holds the best iterate, info filled), ENONFINITE, EBREAKDOWN, EHIP. */

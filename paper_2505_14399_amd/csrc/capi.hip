@@ -392,14 +392,14 @@ struct SolveStats {
   long outer = 0, refinements = 0, coarse = 0, smooth = 0, escalations = 0;
 };
 
-// FP64 flexible GCR with the FP64 K-cycle, in place on native x64
+// FP64 flexible GMRES(16) with the FP64 K-cycle, in place on native x64
 void solve_f64(const HierarchyDev& h, const void* b64, void* x64, int nrhs, double tol, int max_iter, bool x_zero,
                hipStream_t st, SolveStats& ss, bool& converged) {
   WilsonOp D(h.g, QMG_F64, h.U64.p);
   CoarseOp Dc(h, QMG_F64, h.Y64.p);
   KCycle<double2, double2> K(h, D, Dc, h.P64.p);
-  Fgcr<double2> f;
-  auto res = f.solve(D, K, b64, x64, x_zero, nrhs, 16, max_iter, tol, st);
+  Gmres<double2> f;  // flexible GMRES(16) with the K-cycle
+  auto res = f.solve(D, b64, x64, x_zero, nrhs, 16, max_iter, tol, st, nullptr, 0, &K);
   K.finish(st);
   ss.outer += res.iters;
   ss.coarse += K.coarse_iters;
@@ -408,7 +408,7 @@ void solve_f64(const HierarchyDev& h, const void* b64, void* x64, int nrhs, doub
   converged = res.converged;
 }
 
-// FP64 defect correction around an FP32 flexible GCR whose K-cycle stores in precision S
+// FP64 defect correction around an FP32 flexible GMRES(16) whose K-cycle stores in precision S
 template <class S>
 void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, double tol, int max_outer,
                  hipStream_t st, SolveStats& ss, bool& converged) {
@@ -420,7 +420,7 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
   WilsonOp Din(h.g, P, h.Uin.p);
   CoarseOp Dc(h, P, h.Yin.p);
   KCycle<F, S> K(h, Din, Dc, h.Pin.p);
-  Fgcr<F> f;
+  Gmres<F> f;  // flexible GMRES(16) with the K-cycle
   DevBuf r64(n * sizeof(double2)), rin(n * sizeof(F)), ein(n * sizeof(F)), nrm(nrhs * sizeof(double)),
       bn(nrhs * sizeof(double));
   RedWork rw;
@@ -472,7 +472,7 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
     // r / |r| in the inner precision
     Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 0, len, nrhs, st);
     launch_convert(r64.p, QMG_F64, rin.p, QMG_F32, n, st);
-    auto res = f.solve(D32, K, rin.p, ein.p, true, nrhs, 16, int(max_outer - ss.outer), inner_tol, st);
+    auto res = f.solve(D32, rin.p, ein.p, true, nrhs, 16, int(max_outer - ss.outer), inner_tol, st, nullptr, 0, &K);
     ss.outer += res.iters;
     ss.refinements += 1;
     // x += |r| e

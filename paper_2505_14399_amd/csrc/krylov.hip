@@ -1013,7 +1013,8 @@ __global__ __launch_bounds__(64) void k_gv_solve(const double2* st, int m, int n
 
 template <class S>
 typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int m,
-                                          int max_iter, double tol, hipStream_t st, int* conv, int first_check) {
+                                          int max_iter, double tol, hipStream_t st, int* conv, int first_check,
+                                          Precond* M) {
   // FP64 keeps two Gram-Schmidt passes (parity with the FP64 reference to ~1e-12); lower
   // storage precisions use one pass with the Pythagorean norm, which halves the basis traffic
   constexpr bool kCgs2 = std::is_same<S, double2>::value;
@@ -1025,13 +1026,21 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
   // device-side exit (conv given): one cycle of at most m steps, convergence tested by the
   // Givens kernels, every later kernel of the cycle returns at once; no host round trip
   const bool dev_exit = conv != nullptr;
-  QMG_CHECK(!dev_exit || (x_zero && tol > 0 && max_iter <= m && m + 1 <= kMaxCoef), QMG_EINVAL,
-            "device-exit GMRES needs a zero guess, a tolerance and one cycle of at most 63 steps");
+  QMG_CHECK(!dev_exit || (x_zero && tol > 0 && max_iter <= m && m + 1 <= kMaxCoef && !M), QMG_EINVAL,
+            "device-exit GMRES needs a zero guess, a tolerance, no preconditioner and one cycle of at most 63 steps");
+  // flexible form: z_j = M v_j is kept (Z), the Arnoldi vector is A z_j and the solution is
+  // updated with Z instead of V; each step is a preconditioner application, so the estimates
+  // are read after every step
   const int* skip = dev_exit ? conv + 1 : nullptr;
   const size_t len = A.len();
   ensure(len, nrhs, m);
   S* V = V_.as<S>();
   const size_t vs = size_t(nrhs) * len;  // stride between basis vectors
+  S* Z = nullptr;
+  if (M) {
+    Z_.ensure(size_t(m) * vs * sizeof(S));
+    Z = Z_.as<S>();
+  }
   // per-column device staging: h1 [(m+1) nrhs], h2 [(m+1) nrhs], |w|^2 [nrhs], estimates [nrhs]
   const size_t per_col = size_t(2 * (m + 1) + 2) * nrhs;
   const size_t est_off = size_t(2 * (m + 1) + 1) * nrhs;
@@ -1084,7 +1093,13 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
       double2* h1 = col;
       double2* h2 = col + size_t(m + 1) * nrhs;
       double* cn = reinterpret_cast<double*>(col + size_t(2 * (m + 1)) * nrhs);
-      A.apply(vj, vn, nrhs, st, skip);
+      if (M) {
+        S* zj = Z + size_t(j) * vs;
+        M->apply(vj, zj, nrhs, st);
+        A.apply(zj, vn, nrhs, st, skip);
+      } else {
+        A.apply(vj, vn, nrhs, st, skip);
+      }
       bool fused = false;
       if (kCgs2) {
         // CGS2: h1 = V^dag w ; w -= V h1 and h2 = V^dag w ; w -= V h2 and |w|^2 ; w /= |w|
@@ -1101,9 +1116,10 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
       jdone = j + 1;
       // read points: every kBatch steps, or (with a hint, in the first cycle) at first_check and
       // every second step after it
-      const bool read_now = first_check > 0 && it == 0
-                                ? (j + 1 >= first_check && (j + 1 - first_check) % 2 == 0)
-                                : (j + 1) % kBatch == 0;
+      const bool read_now = M ? true
+                              : first_check > 0 && it == 0
+                                  ? (j + 1 >= first_check && (j + 1 - first_check) % 2 == 0)
+                                  : (j + 1) % kBatch == 0;
       if (!dev_exit && tol > 0 && (read_now || j == mc - 1)) {
         // the columns since the last read travel to the host in one copy
         QMG_HIP(hipMemcpyAsync(hcols + size_t(copied) * per_col, colsd + size_t(copied) * per_col,
@@ -1140,7 +1156,7 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
       int* nvd = reinterpret_cast<int*>(yd + size_t(m + 1) * nrhs);
       k_gv_solve<<<nrhs, 64, 0, st>>>(gst, m, nrhs, jdone, yd, nvd);
       QMG_LAUNCH_CHECK();
-      Blas<S>::axpy_multi(V, vs, jdone, yd, 1.0, x, len, nrhs, st, nullptr, nvd);
+      Blas<S>::axpy_multi(M ? Z : V, vs, jdone, yd, 1.0, x, len, nrhs, st, nullptr, nvd);
     }
     if (dev_exit || all_conv || jdone == 0) break;
   }
@@ -1149,117 +1165,9 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
   return res;
 }
 
-// ---------------------------------------------------------------------------------------
-// flexible GCR
-
-template <class S>
-void Fgcr<S>::ensure(size_t len, int nrhs, int restart) {
-  if (len == len_ && nrhs <= nrhs_ && restart <= restart_) return;
-  len_ = len;
-  nrhs_ = std::max(nrhs, nrhs_);
-  restart_ = std::max(restart, restart_);
-  Z_.ensure(size_t(restart_) * nrhs_ * len_ * sizeof(S));
-  W_.ensure(size_t(restart_) * nrhs_ * len_ * sizeof(S));
-  r_.ensure(size_t(nrhs_) * len_ * sizeof(S));
-  tmp_.ensure(size_t(nrhs_) * len_ * sizeof(S));
-  beta_.ensure(size_t(restart_ + 1) * nrhs_ * sizeof(double2));
-  nrm_.ensure(size_t(2 * nrhs_) * sizeof(double));
-}
-
-template <class S>
-typename Fgcr<S>::Result Fgcr<S>::solve(LinOp& A, Precond& M, const void* b, void* x, bool x_zero, int nrhs,
-                                        int restart, int max_iter, double tol, hipStream_t st) {
-  const size_t len = A.len();
-  ensure(len, nrhs, restart);
-  const size_t vs = size_t(nrhs) * len;
-  S* Z = Z_.as<S>();
-  S* W = W_.as<S>();
-  S* r = r_.as<S>();
-  double2* beta = beta_.as<double2>();
-  double* nrm = nrm_.as<double>();
-  PinnedBuf& hb = hb_;
-  hb.ensure(size_t(2 * nrhs) * sizeof(double));
-  double* hn = hb.as<double>();
-
-  Result res;
-  res.rel_res.assign(nrhs, 0.0);
-  std::vector<double> bn(nrhs);
-  Blas<S>::norm2(b, len, nrhs, nrm, rw_, st);
-  QMG_HIP(hipMemcpyAsync(hn, nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-  QMG_HIP(hipStreamSynchronize(st));
-  for (int i = 0; i < nrhs; ++i) {
-    bn[i] = std::sqrt(hn[i]);
-    QMG_CHECK(std::isfinite(bn[i]), QMG_ENONFINITE, "FGCR: non-finite right-hand side");
-  }
-  auto residual = [&]() {  // r = b - A x, returns true if all converged
-    if (x_zero && res.iters == 0) {
-      Blas<S>::copy(b, r, vs, st);
-    } else {
-      A.apply(x, r, nrhs, st);
-      Blas<S>::axpby(1.0, b, -1.0, r, vs, st);
-    }
-    Blas<S>::norm2(r, len, nrhs, nrm, rw_, st);
-    QMG_HIP(hipMemcpyAsync(hn, nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-    QMG_HIP(hipStreamSynchronize(st));
-    bool conv = true;
-    for (int i = 0; i < nrhs; ++i) {
-      const double rn = std::sqrt(hn[i]);
-      QMG_CHECK(std::isfinite(rn), QMG_ENONFINITE, "FGCR: non-finite residual");
-      res.rel_res[i] = bn[i] > 0 ? rn / bn[i] : 0.0;
-      if (res.rel_res[i] > tol) conv = false;
-    }
-    return conv;
-  };
-  if (x_zero) Blas<S>::zero(x, vs, st);
-  bool conv = residual();
-  while (!conv && res.iters < max_iter) {
-    int k = 0;
-    for (; k < restart && res.iters < max_iter; ++k) {
-      S* zk = Z + size_t(k) * vs;
-      S* wk = W + size_t(k) * vs;
-      M.apply(r, zk, nrhs, st);
-      A.apply(zk, wk, nrhs, st);
-      for (int pass = 0; pass < 2 && k > 0; ++pass) {
-        Blas<S>::mdot(W, vs, k, wk, len, nrhs, beta, rw_, st);
-        Blas<S>::axpy_multi(W, vs, k, beta, -1.0, wk, len, nrhs, st);
-        Blas<S>::axpy_multi(Z, vs, k, beta, -1.0, zk, len, nrhs, st);
-      }
-      Blas<S>::norm2(wk, len, nrhs, nrm, rw_, st);
-      Blas<S>::scale_dev(wk, nrm, 0, len, nrhs, st);
-      Blas<S>::scale_dev(zk, nrm, 0, len, nrhs, st);
-      Blas<S>::dot_multi(wk, 0, 1, r, len, nrhs, beta, rw_, st);  // alpha = <w_k, r>
-      Blas<S>::caxpy_dev(beta, 1.0, zk, x, len, nrhs, st);
-      Blas<S>::caxpy_dev(beta, -1.0, wk, r, len, nrhs, st);
-      Blas<S>::norm2(r, len, nrhs, nrm + nrhs, rw_, st);
-      QMG_HIP(hipMemcpyAsync(hn, nrm, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      QMG_HIP(hipStreamSynchronize(st));
-      ++res.iters;
-      bool c2 = true;
-      for (int i = 0; i < nrhs; ++i) {
-        const double rn = std::sqrt(hn[nrhs + i]);
-        QMG_CHECK(std::isfinite(rn) && std::isfinite(hn[i]), QMG_ENONFINITE, "FGCR: non-finite residual");
-        const double rel = bn[i] > 0 ? rn / bn[i] : 0.0;
-        if (rel > tol) {
-          c2 = false;
-          QMG_CHECK(hn[i] > 0.0, QMG_EBREAKDOWN, "FGCR: preconditioned direction has zero image");
-        }
-      }
-      if (c2) {
-        ++k;
-        break;
-      }
-    }
-    conv = residual();
-  }
-  res.converged = conv;
-  return res;
-}
-
 template class Gmres<double2>;
 template class Gmres<float2>;
 template class Gmres<cbf16>;
 template class Gmres<chalf>;
-template class Fgcr<double2>;
-template class Fgcr<float2>;
 
 }  // namespace qmg

@@ -88,9 +88,10 @@ struct Blas {
                         hipStream_t st);
 };
 
-// Restarted GMRES(m), multi right-hand side: Arnoldi with classical Gram-Schmidt (twice in
-// FP64) and the Givens least-squares update on the device; with a tolerance the host reads
-// the residual estimates once per few steps, without one a cycle has no host round trip.
+// Restarted GMRES(m) and flexible GMRES(m), multi right-hand side: Arnoldi with classical
+// Gram-Schmidt (twice in FP64) and the Givens least-squares update on the device; with a
+// tolerance the host reads the residual estimates once per few steps (after every step in the
+// flexible form), without one a cycle has no host round trip.
 template <class S>
 class Gmres {
  public:
@@ -107,33 +108,14 @@ class Gmres {
   // first_check (host-checked mode): Arnoldi step after which the host first reads the
   // estimates (later every two steps); 0 = every four steps.  A caller that knows the typical
   // count (the previous solve's) saves host round trips without changing the result.
+  // M (optional): flexible GMRES, z_j = M v_j with a preconditioner that may change between
+  // applications (the solution is updated with the z_j).
   Result solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int restart, int max_iter, double tol,
-               hipStream_t st, int* conv = nullptr, int first_check = 0);
+               hipStream_t st, int* conv = nullptr, int first_check = 0, Precond* M = nullptr);
 
  private:
   void ensure(size_t len, int nrhs, int restart);
-  DevBuf V_, H_, h1_, h2_, nrm_, y_, r_, cols_, gst_;
-  PinnedBuf hb_;
-  RedWork rw_;
-  size_t len_ = 0;
-  int nrhs_ = 0, restart_ = 0;
-};
-
-// Flexible GCR(restart) with a (possibly nonlinear) preconditioner, multi right-hand side.
-template <class S>
-class Fgcr {
- public:
-  struct Result {
-    int iters = 0;
-    bool converged = false;
-    std::vector<double> rel_res;  // true residual / ||b|| per rhs at exit (in precision S)
-  };
-  Result solve(LinOp& A, Precond& M, const void* b, void* x, bool x_zero, int nrhs, int restart, int max_iter,
-               double tol, hipStream_t st);
-
- private:
-  void ensure(size_t len, int nrhs, int restart);
-  DevBuf Z_, W_, r_, beta_, tmp_, nrm_, bn_;
+  DevBuf V_, Z_, H_, h1_, h2_, nrm_, y_, r_, cols_, gst_;
   PinnedBuf hb_;
   RedWork rw_;
   size_t len_ = 0;

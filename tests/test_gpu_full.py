@@ -27,7 +27,7 @@ def _sample_sites(dims, rng, n, extra=()):
 
 
 def test_solve_iso24x64_bf16(qmg):
-    """BF16-stored K-cycle in FP32 GCR and FP64 defect correction reaches 1e-10 on 24^3 x 64."""
+    """BF16-stored K-cycle in FP32 flexible GMRES and FP64 defect correction reaches 1e-10 on 24^3 x 64."""
     w = workloads.get("iso24x64_bf16")
     banner(f"solve {w['name']} {w['dims']} m={w['mass']:.4f}")
     U = fields.random_gauge(w["dims"], w["eps"], w["seed"], w["tag"])

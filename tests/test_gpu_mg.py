@@ -224,7 +224,7 @@ def test_coarse_operator_shapes(qmg, dims, block, k, r, ns):
 
 @pytest.mark.parametrize("inner", ["bf16", "f16"])
 def test_solve_half_storage(qmg, inner):
-    """K-cycle stored in BF16/FP16 (FP32 arithmetic) inside FP32 GCR and FP64 refinement."""
+    """K-cycle stored in BF16/FP16 (FP32 arithmetic) inside FP32 flexible GMRES and FP64 refinement."""
     dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
     banner(f"solve {inner} inner {dims}")
     U = fields.random_gauge(dims, 0.4, 23)
@@ -323,7 +323,7 @@ def test_graph_captured_kcycle_c1(qmg, c1):
 
 
 def test_graph_captured_kcycle_mixed(qmg):
-    """Captured K-cycle inside the FP32 GCR / FP64 refinement on 8^4 (k = 12): reaches 1e-10."""
+    """Captured K-cycle inside the FP32 flexible GMRES / FP64 refinement on 8^4 (k = 12): reaches 1e-10."""
     dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
     banner("graph-captured K-cycle, FP32 inner")
     U = fields.random_gauge(dims, 0.4, 27)
