@@ -207,10 +207,12 @@ __global__ __launch_bounds__(1024) void k_coarse_apply(const S* __restrict__ Y, 
 }
 
 // ---------------------------------------------------------------------------------------
-// Galerkin build (FP64).  One workgroup per aggregate j.  For every site x of the block and
-// every hop direction, the hop term H(x, dir) is applied to the 2k columns of P at the
-// neighbour y and contracted with P(x)^dag; hops leaving the block through its face go to
-// Y_{1+dir}(j), the others (and the diagonal term) to Y_0(j).
+// Galerkin build (FP64).  One workgroup per (aggregate j, forward direction mu).  For every
+// site x of the block the hop term H(x, mu) is applied to the 2k columns of P at the neighbour
+// y and contracted with P(x)^dag; hops leaving the block through its face go to Y_{1+mu}(j),
+// the others to the partial self block W_mu(j) (workgroup mu = 0 also forms the diagonal
+// term).  The backward directions follow from sigma3-hermiticity (k_sum_self,
+// k_fill_backward).
 struct BuildArgs {
   int L[4], b[4], cL[4];
   int V, nd, N, k, d, bc_t;
@@ -300,12 +302,10 @@ __global__ __launch_bounds__(256) void k_build_coarse(const double2* __restrict_
     if (cls == 1 && dir != 0) continue;
     const int count = cls == 0 ? nd - nface : (cls == 1 ? nd : nface);
     const int base = cls == 2 ? nd - nface : 0;
-    if (cls != 1) {
 #pragma unroll
-      for (int t = 0; t < TS; ++t)
+    for (int t = 0; t < TS; ++t)
 #pragma unroll
-        for (int u = 0; u < TS; ++u) acc[t][u] = {0, 0};
-    }
+      for (int u = 0; u < TS; ++u) acc[t][u] = {0, 0};
     for (int n0 = 0; n0 < count; n0 += NS) {
       const int ns = min(NS, count - n0);
       if (tid < ns) {
@@ -400,9 +400,8 @@ __global__ __launch_bounds__(256) void k_build_coarse(const double2* __restrict_
       }
       __syncthreads();
     }
-    // write: intra (after the diagonal term for dir 0) to W, face to Y_{1+dir}
-    const bool write_w = (cls == 0 && dir != 0) || cls == 1;
-    if (active && (write_w || cls == 2)) {
+    // write: intra hops to W[dir], the diagonal term to W[4], face hops to Y_{1+dir}
+    if (active) {
       for (int t = 0; t < TS; ++t)
         for (int u = 0; u < TS; ++u) {
           const int i = i0 + t, col = c0 + u;
@@ -410,23 +409,49 @@ __global__ __launch_bounds__(256) void k_build_coarse(const double2* __restrict_
           const int idx = col * m + al * k + i;
           const double2 v = make_double2(acc[t][u].re, acc[t][u].im);
           if (cls == 2) Y[(size_t(j) * 9 + 1 + dir) * nent + idx] = v;
-          else W[(size_t(dir) * a.d + j) * nent + idx] = v;
+          else W[(size_t(cls == 1 ? 4 : dir) * a.d + j) * nent + idx] = v;
         }
     }
   }
 }
 
-__global__ void k_sum_self(const double2* __restrict__ W, double2* __restrict__ Y, int d, int nent) {
+// D_c is sigma3-hermitian (gamma5 P = P sigma3 and gamma5 D gamma5 = D^dag), so the hops
+// along -mu are the sigma3-adjoints of those along +mu: inside a block, the -mu intra-block
+// part of Y_0 is sigma3 W_mu^dag sigma3, and across faces Y_{-mu}(j) = sigma3 Y_{+mu}(j-mu)^dag
+// sigma3.  Only the four forward directions are built; sigma3 = diag(+1 (alpha = 0), -1).
+__device__ inline double2 s3adj(const double2* B, int m, int k, int row, int col) {
+  const double2 v = B[size_t(row) * m + col];  // B(col, row), column-major
+  const double s = ((row < k) == (col < k)) ? 1.0 : -1.0;
+  return make_double2(s * v.x, -s * v.y);
+}
+
+// Y_0(j) = diagonal term + sum over the four forward directions of (W_mu + sigma3 W_mu^dag sigma3)
+__global__ void k_sum_self(const double2* __restrict__ W, double2* __restrict__ Y, int d, int m, int k) {
+  const int nent = m * m;
   const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
   if (g >= size_t(d) * nent) return;
   const size_t j = g / nent, idx = g - j * nent;
-  double2 s = make_double2(0.0, 0.0);
-  for (int dir = 0; dir < 8; ++dir) {
-    const double2 v = W[(size_t(dir) * d + j) * nent + idx];
-    s.x += v.x;
-    s.y += v.y;
+  const int col = int(idx / m), row = int(idx - size_t(col) * m);
+  double2 s = W[(size_t(4) * d + j) * nent + idx];
+  for (int dir = 0; dir < 4; ++dir) {
+    const double2* B = W + (size_t(dir) * d + j) * nent;
+    const double2 v = B[idx], a = s3adj(B, m, k, row, col);
+    s.x += v.x + a.x;
+    s.y += v.y + a.y;
   }
   Y[(j * 9) * nent + idx] = s;
+}
+
+// Y_{1+4+mu}(j) = sigma3 Y_{1+mu}(j - mu)^dag sigma3
+__global__ void k_fill_backward(double2* __restrict__ Y, const int* __restrict__ cnb, int d, int m, int k) {
+  const int nent = m * m;
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= size_t(d) * 4 * nent) return;
+  const size_t jm = g / nent, idx = g - jm * nent;
+  const int j = int(jm / 4), mu = int(jm - size_t(j) * 4);
+  const int col = int(idx / m), row = int(idx - size_t(col) * m);
+  const int jb = cnb[j * 8 + 4 + mu];
+  Y[(size_t(j) * 9 + 5 + mu) * nent + idx] = s3adj(Y + (size_t(jb) * 9 + 1 + mu) * nent, m, k, row, col);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -718,7 +743,7 @@ void build_coarse(HierarchyDev& h, hipStream_t st) {
   a.bc_t = h.g.bc_t;
   a.diag = h.g.diag();
   TimedLaunch tl("coarse_build", st, double(h.g.V) * 12.0 * h.k * 16.0 + 9.0 * h.blk.d * 4.0 * h.k * h.k * 16.0,
-                 double(h.g.V) * 8.0 * (2.0 * h.k) * (2.0 * h.k) * 6.0 * 8.0, false);
+                 double(h.g.V) * 4.0 * (2.0 * h.k) * (2.0 * h.k) * 6.0 * 8.0, false);
   const int nent = 4 * h.k * h.k;
   DevBuf W(size_t(8) * h.blk.d * nent * sizeof(double2));
   // per site: Px (12 k) + HP (24 k) + link (9) complex, + coefficient and 5 ints
@@ -728,13 +753,17 @@ void build_coarse(HierarchyDev& h, hipStream_t st) {
   auto go = [&](auto kern) {
     if (lds > 64 * 1024) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      int(lds)));
-    kern<<<dim3(h.blk.d, 8), 256, lds, st>>>(h.U64.as<double2>(), h.P64.as<double2>(), h.bsite.as<int>(),
+    kern<<<dim3(h.blk.d, 4), 256, lds, st>>>(h.U64.as<double2>(), h.P64.as<double2>(), h.bsite.as<int>(),
                                              h.blists.as<int>(), h.Y64.as<double2>(), W.as<double2>(), a, NS);
   };
   if (h.k <= 24) go(k_build_coarse<3>);
   else go(k_build_coarse<4>);
   QMG_LAUNCH_CHECK();
-  k_sum_self<<<cdiv(size_t(h.blk.d) * nent, 256), 256, 0, st>>>(W.as<double2>(), h.Y64.as<double2>(), h.blk.d, nent);
+  k_sum_self<<<cdiv(size_t(h.blk.d) * nent, 256), 256, 0, st>>>(W.as<double2>(), h.Y64.as<double2>(), h.blk.d,
+                                                                2 * h.k, h.k);
+  QMG_LAUNCH_CHECK();
+  k_fill_backward<<<cdiv(size_t(h.blk.d) * 4 * nent, 256), 256, 0, st>>>(h.Y64.as<double2>(), h.cnb.as<int>(),
+                                                                        h.blk.d, 2 * h.k, h.k);
   QMG_LAUNCH_CHECK();
   QMG_HIP(hipStreamSynchronize(st));  // W is released on return
 }
