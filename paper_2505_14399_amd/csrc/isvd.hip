@@ -162,7 +162,7 @@ __global__ __launch_bounds__(T) void k_isvd_gram(const double2* __restrict__ Ug,
 
 // ---------------------------------------------------------------------------------------
 // small dense part: one wavefront per problem
-constexpr int TW = 64;
+constexpr int TW = 128;  // two wavefronts per small problem
 
 __device__ inline int rr_pos(int i, int t, int w) {  // round-robin tournament position
   return i == 0 ? 0 : 1 + (i - 1 + t) % (w - 1);
@@ -186,6 +186,7 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
   int* keep = reinterpret_cast<int*>(pn + r);  // [r]
   int* perm = keep + r;                     // [we]
   const size_t sstride = small_stride(kp, r);
+  __shared__ double wmax[TW / 64];
   const int npairs = we / 2;
   int lpp = 1;  // lanes per pair (power of two)
   while (lpp * 2 * npairs <= TW) lpp *= 2;
@@ -281,10 +282,10 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
             ga += cmul_conj(u, v);
           }
           for (int off = 1; off < lpp; off <<= 1) {
-            al += __shfl_xor(al, off, TW);
-            be += __shfl_xor(be, off, TW);
-            ga.re += __shfl_xor(ga.re, off, TW);
-            ga.im += __shfl_xor(ga.im, off, TW);
+            al += __shfl_xor(al, off, 64);  // lpp divides 64
+            be += __shfl_xor(be, off, 64);  // lpp divides 64
+            ga.re += __shfl_xor(ga.re, off, 64);  // lpp divides 64
+            ga.im += __shfl_xor(ga.im, off, 64);  // lpp divides 64
           }
           const double g = sqrt(norm2(ga));
           if (al > 0.0 && be > 0.0 && g > 1e-300) {
@@ -310,7 +311,11 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
         }
         __syncthreads();
       }
-      for (int off = 1; off < TW; off <<= 1) offmax = fmax(offmax, __shfl_xor(offmax, off, TW));
+      for (int off = 1; off < 64; off <<= 1) offmax = fmax(offmax, __shfl_xor(offmax, off, 64));
+      if ((lane & 63) == 0) wmax[lane >> 6] = offmax;
+      __syncthreads();
+      for (int q = 0; q < TW / 64; ++q) offmax = fmax(offmax, wmax[q]);
+      __syncthreads();
       if (offmax <= kJacobiTol) break;
     }
     // singular values = column norms of M, sorted descending (stable)
