@@ -228,7 +228,7 @@ qmg_status qmg_timing_calls(const char* family, int64_t* calls);
 
 /* Autotuner.  qmg_autotune(1) (or QMG_TUNE=1 in the environment) makes every kernel with
  * launch variants (the native-layout dslash: one site per thread, 2/4/8 sites per thread
- * along t, or four threads per site) time each variant with HIP events on its first call for a given (precision,
+ * along t, four threads per site, or 2-3 right-hand sides per thread along t) time each variant with HIP events on its first call for a given (precision,
  * extents, right-hand sides, adjoint) and keep the fastest; 0 returns to the built-in
  * heuristic.  Tuning never runs while the stream is being captured into a graph.
  * qmg_tune_save / qmg_tune_load write / read the choices as JSON {"key": variant}. */
@@ -236,7 +236,10 @@ qmg_status qmg_autotune(int32_t on);
 /* Force one native-layout dslash variant for every later call (1: one site per thread; 2, 4, 8:
  * sites per thread along t, used when Lt is a multiple; 16: four threads per site, one per
  * direction; 32, 64: one site per thread for 2 or 4 right-hand sides at once, used when nrhs is
- * a multiple); 0 restores the automatic choice.
+ * a multiple; 1000 z + 100 NR + TCH with z in {0, 1}, NR in {2, 3}, TCH in {2, 4, 8}: TCH sites
+ * along t for NR right-hand sides per thread, FP32 storage only, z = 1 orders the tiles z-fastest;
+ * a variant that does not apply to a call falls back to the automatic choice); 0 restores the
+ * automatic choice.  Any other value gives QMG_EINVAL.
  * For tests and tuning studies. */
 qmg_status qmg_set_dslash_variant(int32_t variant);
 qmg_status qmg_tune_save(const char* path);

@@ -435,7 +435,8 @@ def autotune(on=True):
 
 
 def set_dslash_variant(v=0):
-    """Force a native dslash launch variant (1, 2, 4, 8, 16) or restore the automatic choice (0)."""
+    """Force a native dslash launch variant (1, 2, 4, 8, 16, 32, 64, or a multi-RHS t-walking
+    code 1000 z + 100 NR + TCH) or restore the automatic choice (0)."""
     _check(load_library().qmg_set_dslash_variant(int(v)))
 
 

@@ -939,8 +939,11 @@ qmg_status qmg_autotune(int32_t on) {
 
 qmg_status qmg_set_dslash_variant(int32_t v) {
   return guard([&] {
-    QMG_CHECK(v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64, QMG_EINVAL,
-              "dslash variant must be 0, 1, 2, 4, 8, 16, 32 or 64");
+    const int z = v / 1000, nr = (v % 1000) / 100, tch = v % 100;
+    const bool tw = v > 100 && z <= 1 && (nr == 2 || nr == 3) && (tch == 2 || tch == 4 || tch == 8);
+    QMG_CHECK(tw || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64, QMG_EINVAL,
+              "dslash variant must be 0, 1, 2, 4, 8, 16, 32, 64 or a multi-rhs t-walking code "
+              "1000 z + 100 NR + TCH (z in {0,1}, NR in {2,3}, TCH in {2,4,8})");
     set_dslash_variant(v);
   });
 }

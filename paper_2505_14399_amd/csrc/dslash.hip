@@ -13,6 +13,7 @@
 // remapped so that each XCD walks a contiguous range of sites, keeping the +-t neighbour
 // slices of a tile inside that XCD's L2.
 #include <string>
+#include <type_traits>
 
 #include "timing.hpp"
 #include "tune.hpp"
@@ -243,25 +244,39 @@ __global__ __launch_bounds__(kBlock) void k_dslash_batched(const BatchLattice* _
   site_dslash<S, false, 1, DAG>(U[lo], in[lo], out[lo], b.a, site, rhs);
 }
 
-// Native-layout kernel that walks along t.  Thread (spatial site, t-chunk) computes the TCH
-// sites t0 .. t0+TCH-1 of its column.  The spinor of the next slice, loaded for the forward
-// t-hop, becomes the own spinor of the next step, and the backward t-hop
+// Native-layout kernel that walks along t.  Thread (spatial site, t-chunk, group of NR
+// right-hand sides) computes the TCH sites t0 .. t0+TCH-1 of its column for NR right-hand
+// sides; each link is loaded once for all NR of them.  The spinor of the next slice, loaded
+// for the forward t-hop, becomes the own spinor of the next step, and the backward t-hop
 // U_t(x, t-1)^dag (1 + gamma_t) psi(x, t-1) is formed from the own spinor and forward t-link
 // of the previous step, so t-neighbours and t-links are read once.  Workgroups are 256
-// consecutive spatial sites of one (t-chunk, right-hand side); the right-hand sides of a tile
-// are adjacent in the XCD-local schedule so that they share its links in L2.
-template <class S, int TCH, bool DAG>
+// spatial sites of one (t-chunk, rhs group); the rhs groups of a tile are adjacent in the
+// XCD-local schedule so that they share its links in L2.  Tiles are 256 consecutive spatial
+// sites, or (zfast) 256-site pieces of one xy-plane with z fastest in the schedule, so that
+// the tiles holding a site's z-neighbours run next to it.
+template <class S, int TCH, int NR, bool DAG>
 __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, const S* __restrict__ in,
-                                                     S* __restrict__ out, DslashArgs a, int ntile_s) {
+                                                     S* __restrict__ out, DslashArgs a, int ntile_s, int zfast) {
   using C = ctype<S>;
   const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
   const int Vs = L0 * L1 * L2, V = a.V;
+  const int ng = a.nrhs / NR;
   const int wg = xcd_tile(blockIdx.x, gridDim.x);
-  const int rhs = wg % a.nrhs;
-  const int tile = wg / a.nrhs;                 // (t-chunk, spatial tile)
-  const int chunk = tile / ntile_s, ts = tile - chunk * ntile_s;
-  const int xs = ts * kBlock + threadIdx.x;     // spatial site
-  if (xs >= Vs) return;
+  const int per_chunk = ntile_s * ng;
+  const int chunk = wg / per_chunk, r0 = wg - chunk * per_chunk;
+  const int ts = r0 / ng, g = r0 - ts * ng;
+  int xs;  // spatial site
+  if (zfast) {
+    const int Pxy = L0 * L1;
+    const int z = ts % L2, piece = ts / L2;
+    const int xy = piece * kBlock + threadIdx.x;
+    if (xy >= Pxy) return;
+    xs = xy + z * Pxy;
+  } else {
+    xs = ts * kBlock + threadIdx.x;
+    if (xs >= Vs) return;
+  }
+  const int rhs0 = g * NR;
   const int t0 = chunk * TCH;
   int rem = xs;
   const int x = rem % L0; rem /= L0;
@@ -282,24 +297,26 @@ __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, co
   const C mh = C(-0.5);
   const C sf = DAG ? C(1) : C(-1);  // forward projector sign: (1 + sf gamma)
   const C sb = -sf;                  // backward projector sign
-  const S* inr = in + size_t(rhs) * 12 * V;
-  S* outr = out + size_t(rhs) * 12 * V;
 
-  // own spinor of the first site and the backward t-hop carried into it
-  cplx<C> psi[12], hb[6];
+  // own spinors of the first site and the backward t-hops carried into them
+  cplx<C> psi[NR][12], hb[NR][6];
   {
     const int tm = (t0 == 0) ? L3 - 1 : t0 - 1;
     const int sm = xs + tm * Vs;
-    cplx<C> chi[12], h[6], u[9];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) chi[k] = ldc(inr, size_t(k) * V + sm);
+    cplx<C> u[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = ldc(U, size_t(3 * 9 + e) * V + sm);
-    project<3>(chi, sb, h);
-    su3_mul<C, true>(u, h, hb);
     const int s0 = xs + t0 * Vs;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = ldc(inr, size_t(k) * V + s0);
+    for (int r = 0; r < NR; ++r) {
+      cplx<C> chi[12], h[6];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) chi[k] = ldc(in, sp_idx<false>(rhs0 + r, k, sm, V));
+      project<3>(chi, sb, h);
+      su3_mul<C, true>(u, h, hb[r]);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) psi[r][k] = ldc(in, sp_idx<false>(rhs0 + r, k, s0, V));
+    }
   }
 #pragma unroll 1
   for (int dt = 0; dt < TCH; ++dt) {
@@ -307,35 +324,41 @@ __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, co
     const int site = xs + t * Vs;
     const int tp = (t + 1 == L3) ? 0 : t + 1;
     const int sp = xs + tp * Vs;
-    cplx<C> acc[1][12];
+    cplx<C> acc[NR][12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[0][k] = {C(0), C(0)};
-    do_hop<S, false, 1, 0, true, DAG>(U, inr, acc, site, site + dxp, 0, V, mh * cw[0]);
-    do_hop<S, false, 1, 0, false, DAG>(U, inr, acc, site + dxm, site + dxm, 0, V, mh * cw[0]);
-    do_hop<S, false, 1, 1, true, DAG>(U, inr, acc, site, site + dyp, 0, V, mh * cw[1]);
-    do_hop<S, false, 1, 1, false, DAG>(U, inr, acc, site + dym, site + dym, 0, V, mh * cw[1]);
-    do_hop<S, false, 1, 2, true, DAG>(U, inr, acc, site, site + dzp, 0, V, mh * cw[2]);
-    do_hop<S, false, 1, 2, false, DAG>(U, inr, acc, site + dzm, site + dzm, 0, V, mh * cw[2]);
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[r][k] = {C(0), C(0)};
+    do_hop<S, false, NR, 0, true, DAG>(U, in, acc, site, site + dxp, rhs0, V, mh * cw[0]);
+    do_hop<S, false, NR, 0, false, DAG>(U, in, acc, site + dxm, site + dxm, rhs0, V, mh * cw[0]);
+    do_hop<S, false, NR, 1, true, DAG>(U, in, acc, site, site + dyp, rhs0, V, mh * cw[1]);
+    do_hop<S, false, NR, 1, false, DAG>(U, in, acc, site + dym, site + dym, rhs0, V, mh * cw[1]);
+    do_hop<S, false, NR, 2, true, DAG>(U, in, acc, site, site + dzp, rhs0, V, mh * cw[2]);
+    do_hop<S, false, NR, 2, false, DAG>(U, in, acc, site + dzm, site + dzm, rhs0, V, mh * cw[2]);
     // backward t-hop (carried), boundary sign at t = 0
     const C bt_b = (a.bc_t < 0 && t == 0) ? C(-1) : C(1);
-    reconstruct<3>(acc[0], hb, sb, mh * cw[3] * bt_b);
-    // forward t-hop: load the next spinor and this site's t-link
-    cplx<C> nxt[12], u[9], h[6], w[6];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) nxt[k] = ldc(inr, size_t(k) * V + sp);
+    const C bt_f = (a.bc_t < 0 && t == L3 - 1) ? C(-1) : C(1);
+    // forward t-hop: this site's t-link and the next spinors
+    cplx<C> u[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = ldc(U, size_t(3 * 9 + e) * V + site);
-    const C bt_f = (a.bc_t < 0 && t == L3 - 1) ? C(-1) : C(1);
-    project<3>(nxt, sf, h);
-    su3_mul<C, false>(u, h, w);
-    reconstruct<3>(acc[0], w, sf, mh * cw[3] * bt_f);
-    // backward t-hop of the next site from this site's spinor and t-link
-    project<3>(psi, sb, h);
-    su3_mul<C, true>(u, h, hb);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      stc(outr, size_t(k) * V + site, diag * psi[k] + acc[0][k]);
-      psi[k] = nxt[k];
+    for (int r = 0; r < NR; ++r) {
+      reconstruct<3>(acc[r], hb[r], sb, mh * cw[3] * bt_b);
+      cplx<C> nxt[12], h[6], w[6];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) nxt[k] = ldc(in, sp_idx<false>(rhs0 + r, k, sp, V));
+      project<3>(nxt, sf, h);
+      su3_mul<C, false>(u, h, w);
+      reconstruct<3>(acc[r], w, sf, mh * cw[3] * bt_f);
+      // backward t-hop of the next site from this site's spinor and t-link
+      project<3>(psi[r], sb, h);
+      su3_mul<C, true>(u, h, hb[r]);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        stc(out, sp_idx<false>(rhs0 + r, k, site, V), diag * psi[r][k] + acc[r][k]);
+        psi[r][k] = nxt[k];
+      }
     }
   }
 }
@@ -446,17 +469,42 @@ void launch_t(const void* U, const void* in, void* out, const DslashArgs& a, hip
   QMG_LAUNCH_CHECK();
 }
 
-template <class S, int TCH>
-void launch_tw(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
+template <class S, int TCH, int NR>
+void launch_tw(const void* U, const void* in, void* out, const DslashArgs& a, int zfast, hipStream_t st) {
   const int Vs = a.L[0] * a.L[1] * a.L[2];
-  const int ntile_s = (Vs + kBlock - 1) / kBlock;
+  const int ntile_s = zfast ? ((a.L[0] * a.L[1] + kBlock - 1) / kBlock) * a.L[2] : (Vs + kBlock - 1) / kBlock;
   const int nchunk = a.L[3] / TCH;
-  dim3 grid(unsigned(ntile_s * nchunk * a.nrhs));
+  dim3 grid(unsigned(ntile_s * nchunk * (a.nrhs / NR)));
   if (a.dagger)
-    launch(k_dslash_t<S, TCH, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s);
+    launch(k_dslash_t<S, TCH, NR, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
   else
-    launch(k_dslash_t<S, TCH, false>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s);
+    launch(k_dslash_t<S, TCH, NR, false>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
   QMG_LAUNCH_CHECK();
+}
+
+// Multi-RHS t-walking forms, code 1000 * zfast + 100 * NR + TCH (NR = 2 or 3 right-hand sides
+// per thread; FP32 storage only: the NR accumulators, own spinors and carried hops take
+// 190-250 VGPRs)
+inline bool twx_code(int v) {
+  const int z = v / 1000, nr = (v % 1000) / 100, tch = v % 100;
+  return v > 100 && z <= 1 && (nr == 2 || nr == 3) && (tch == 2 || tch == 4 || tch == 8);
+}
+
+template <class S>
+void run_twx(int v, const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
+  if constexpr (sizeof(S) != 8) {
+    set_error("dslash launch form %d needs FP32 storage", v);
+  } else {
+    const int z = v / 1000, nr = (v % 1000) / 100, tch = v % 100;
+    auto go = [&](auto nrc) {
+      constexpr int NR = decltype(nrc)::value;
+      if (tch == 2) launch_tw<S, 2, NR>(U, in, out, a, z, st);
+      else if (tch == 4) launch_tw<S, 4, NR>(U, in, out, a, z, st);
+      else launch_tw<S, 8, NR>(U, in, out, a, z, st);
+    };
+    if (nr == 2) go(std::integral_constant<int, 2>{});
+    else go(std::integral_constant<int, 3>{});
+  }
 }
 
 template <class S>
@@ -469,10 +517,14 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   }
   // Launch variants for the native layout: 1 = one site per thread, 2/4/8 = t-walking with
   // that many sites per thread along t, 16 = direction-split (four threads per site), 32/64 =
-  // one site per thread for 2/4 right-hand sides at once (links loaded once for all of them).
-  // Default heuristic: the longest t-chunk that still gives >= 1024 workgroups, else the
-  // direction split when one thread per site would leave the GPU short of wavefronts.  With the autotuner enabled every valid variant is timed on first
-  // use of (precision, extents, nrhs, adjoint) and the fastest is kept.
+  // one site per thread for 2/4 right-hand sides at once (links loaded once for all of them),
+  // 1000 z + 100 NR + TCH = t-walking with NR = 2 or 3 right-hand sides per thread (FP32; z:
+  // z-fastest tile order).  Default heuristic: for several right-hand sides in FP32 the
+  // multi-RHS t-walk (3 per thread when nrhs is a multiple of 3, else 2); otherwise the longest
+  // t-chunk that still gives >= 1024 workgroups, else the direction split when one thread per
+  // site would leave the GPU short of wavefronts.  With the autotuner enabled every valid
+  // variant is timed on first use of (precision, extents, nrhs, adjoint) and the fastest is
+  // kept.
   const int Vs = a.L[0] * a.L[1] * a.L[2];
   const long wg1 = long((Vs + kBlock - 1) / kBlock) * a.nrhs;  // workgroups per t-slice
   const int Lt = a.L[3];
@@ -480,21 +532,29 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   const double cb = double(sizeof(S));
   const double bytes = double(a.V) * (24.0 * a.nrhs + 36.0) * cb, flops = 1368.0 * a.V * a.nrhs;
   auto run = [&](int v) {
-    TimedLaunch tl(v == 16 ? "dslash/dir" : (v == 1 || v >= 32) ? "dslash/site" : "dslash/twalk", st, bytes, flops);
+    TimedLaunch tl(v == 16 ? "dslash/dir" : (v == 1 || v == 32 || v == 64) ? "dslash/site" : "dslash/twalk", st, bytes,
+                   flops);
     switch (v) {
-      case 8: launch_tw<S, 8>(U, in, out, a, st); break;
-      case 4: launch_tw<S, 4>(U, in, out, a, st); break;
-      case 2: launch_tw<S, 2>(U, in, out, a, st); break;
+      case 8: launch_tw<S, 8, 1>(U, in, out, a, 0, st); break;
+      case 4: launch_tw<S, 4, 1>(U, in, out, a, 0, st); break;
+      case 2: launch_tw<S, 2, 1>(U, in, out, a, 0, st); break;
       case 16: launch_dir<S>(U, in, out, a, st); break;
       case 32: launch_t<S, false, 2>(U, in, out, a, st); break;
       case 64: launch_t<S, false, 4>(U, in, out, a, st); break;
-      default: launch_t<S, false, 1>(U, in, out, a, st); break;
+      default:
+        if (v > 100) run_twx<S>(v, U, in, out, a, st);
+        else launch_t<S, false, 1>(U, in, out, a, st);
+        break;
     }
   };
   auto valid = [&](int v) {
     if (v == 1 || v == 16) return true;
     if (v == 32) return a.nrhs % 2 == 0;
     if (v == 64) return a.nrhs % 4 == 0;
+    if (v > 100) {
+      const int nr = (v % 1000) / 100, tch = v % 100;
+      return sizeof(S) == 8 && twx_code(v) && a.nrhs % nr == 0 && Lt % tch == 0;
+    }
     return (v == 2 || v == 4 || v == 8) && Lt % v == 0;
   };
   if (a.tchunk > 0 && valid(a.tchunk)) {
@@ -508,6 +568,14 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   // 4-byte storage (BF16/FP16): the one-thread-per-site forms hold every hop's loads in
   // registers (up to 256 VGPRs, one wavefront per SIMD); the direction split needs 64-70
   if (sizeof(S) == 4) choice = 16;
+  if (sizeof(S) == 8 && a.nrhs >= 2) {
+    // measured at 16^3x32 (8 rhs), 24^3x64 (16) and 32^3x64 (12): 10-20% faster than the
+    // one-rhs-per-thread forms; z-fastest tiles only where 256-site pieces tile an xy-plane
+    const int nr = a.nrhs % 3 == 0 ? 3 : a.nrhs % 2 == 0 ? 2 : 0;
+    const int z = (a.L[0] * a.L[1]) % kBlock == 0 ? 1 : 0;
+    const int tch = (nr == 3 && Lt % 8 == 0) ? 8 : Lt % 4 == 0 ? 4 : 2;
+    if (nr && valid(1000 * z + 100 * nr + tch)) choice = 1000 * z + 100 * nr + tch;
+  }
   if (tune_enabled()) {
     const std::string key = "dslash/" + std::to_string(int(StoreTraits<S>::prec)) + "/" + std::to_string(a.L[0]) +
                             "x" + std::to_string(a.L[1]) + "x" + std::to_string(a.L[2]) + "x" +
@@ -516,8 +584,8 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     if (cached > 0) {
       choice = cached;
     } else {
-      int cand[8], n = 0;
-      for (int v : {1, 16, 2, 4, 8, 32, 64})
+      int cand[24], n = 0;
+      for (int v : {1, 16, 2, 4, 8, 32, 64, 202, 204, 208, 302, 304, 308, 1202, 1204, 1208, 1302, 1304, 1308})
         if (valid(v)) cand[n++] = v;
       choice = tune_measure(key, cand, n, st, run);
     }

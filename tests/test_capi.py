@@ -87,3 +87,15 @@ def test_invalid_arguments_are_rejected_without_device_work():
     assert L.qmg_mg_solve(None, dummy, P(32), 1, 1e-10, 10, 0, None, None) == -1
     assert L.qmg_prolong(None, dummy, P(32), 1, q.F64, None) == -1
     assert L.qmg_mg_query(None, None, None, None) == -1
+
+
+def test_dslash_variant_codes_are_validated():
+    import paper_2505_14399_amd as q
+    L = q.load_library()
+    try:
+        for v in (0, 1, 2, 4, 8, 16, 32, 64, 202, 204, 208, 302, 304, 308, 1202, 1208, 1304):
+            assert L.qmg_set_dslash_variant(v) == 0, v
+        for v in (-1, 3, 5, 100, 102, 108, 206, 402, 2204, 1102, 99999):
+            assert L.qmg_set_dslash_variant(v) == -1, v
+    finally:
+        assert L.qmg_set_dslash_variant(0) == 0

@@ -111,6 +111,29 @@ def test_dslash_every_launch_variant(qmg, variant, prec, tol):
         qmg.set_dslash_variant(0)
 
 
+@pytest.mark.parametrize("variant", [202, 204, 208, 302, 304, 308, 1202, 1204, 1208, 1302, 1304, 1308])
+def test_dslash_multi_rhs_twalk_variants(qmg, variant):
+    """t-walking with 2 or 3 right-hand sides per thread (FP32), both tile orders, on a lattice
+    whose xy-planes hold whole 256-site tiles and on one whose planes end in a partial tile."""
+    for dims in ((16, 16, 4, 8), (12, 10, 6, 8)):
+        nrhs = 6
+        banner(f"dslash multi-rhs t-walk {variant} {dims}")
+        U = fields.random_gauge(dims, 0.6, 13)
+        psi = fields.gaussian_spinor(dims, nrhs, 14)
+        lat = qmg.Lattice(dims, -0.3, 2.0, -1)
+        Un = qmg.pack_gauge(lat, to_gpu(U), "f32")
+        pn = qmg.pack_spinor(lat, to_gpu(psi), "f32")
+        try:
+            qmg.set_dslash_variant(variant)
+            for dag in (False, True):
+                f = qmg.wilson_apply_adj if dag else qmg.wilson_apply
+                got = to_np(qmg.unpack_spinor(lat, f(lat, Un, pn, layout="native"), "f32"))
+                ref = wilson.apply_wilson(U, psi, -0.3, 2.0, -1, dims, dagger=dag)
+                assert rel(got, ref) < 1e-6
+        finally:
+            qmg.set_dslash_variant(0)
+
+
 def test_autotuner_cache_roundtrip(qmg, tmp_path):
     dims = (8, 8, 8, 16)
     banner("autotuner")
