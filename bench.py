@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--mass", type=float, default=None, help="override the workload's quark mass")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
+    ap.add_argument("--compare-setups", action="store_true",
+                    help="Regular / CSVD / streaming (iCSVD) setups on the workload: iterations per level, "
+                         "setup and solve seconds, leading singular values (prints a table and JSON lines)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="read rocprofv3 FETCH_SIZE / WRITE_SIZE counter output and write profiles/traffic.json")
     return ap.parse_args()
@@ -111,6 +114,71 @@ def traffic_probe(args):
     torch.cuda.synchronize()
     mg.close()
     print(json.dumps({"probe": w["name"], "dims": list(dims), "prec": prec}), flush=True)
+
+
+# setup methods compared by --compare-setups: (name, n_test m, batch r); rank k from the workload.
+# Regular = one batch of k test vectors (its span is that of the block-orthonormalised vectors of
+# the regular setup); CSVD = one batch of m vectors truncated to k; iCSVD = m vectors streamed in
+# m / r batches of r.  Test vector i is the same in every method (the counter of its random
+# initial guess is its global index), so the methods differ only in how the basis is formed.
+SETUP_METHODS = (("Regular", 24, 24), ("CSVD", 48, 48), ("iCSVD", 48, 24), ("iCSVD", 48, 16), ("iCSVD", 48, 12),
+                 ("iCSVD", 48, 8), ("iCSVD", 48, 6), ("iCSVD", 48, 4), ("iCSVD", 96, 24), ("iCSVD", 96, 16),
+                 ("iCSVD", 96, 8))
+
+
+def compare_setups(args):
+    """Setup methods on the workload's lattice: per method one untimed setup + solve (warm-up), then
+    a timed setup and the median of three solves.  Levels: l = 0 the outer (fine) iterations, l = 1
+    the coarse GMRES iterations summed over the solve; 'normalised' is l = 1 per l = 0 iteration."""
+    import numpy as np
+    import torch
+
+    import fields
+    import paper_2505_14399_amd as q
+
+    w = load_workload(args)
+    dims = w["dims"]
+    lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
+    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
+    b = torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda()
+    k = w["rank"]
+    rows = []
+    for name, m, r in SETUP_METHODS:
+        kw = dict(block=w["block"], n_test=m, batch=r, rank=k, n_setup_iter=16, n_post_smooth=8, coarse_tol=0.03,
+                  coarse_max_iter=500, inner=w["inner"], seed=w["seed"])
+        mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
+        q.mg_solve(mg, b, tol=args.tol)
+        mg.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
+        t_setup = time.perf_counter() - t0
+        ts, info = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, info = q.mg_solve(mg, b, tol=args.tol)
+            ts.append(time.perf_counter() - t0)
+        _, sig = mg.prolongator()
+        mg.close()
+        i0 = info[0]
+        if i0["true_rel_res"] > args.tol:
+            raise SystemExit(f"{name} m={m} r={r}: solve did not reach {args.tol}: {i0}")
+        row = {"method": name, "m": m, "r": r, "n_s": m // r, "k": k, "setup_s": t_setup,
+               "solve_s": float(np.median(ts)), "iters_l0": i0["outer_iters"], "iters_l1": i0["coarse_iters"],
+               "normalised_l1": i0["coarse_iters"] / max(1, i0["outer_iters"]),
+               "sigma_agg0": [[float(v) for v in sig[0, a]] for a in (0, 1)]}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    print(f"\n# setup methods on {w['name']} {dims}, k = {k}, n_setup = 16, inner {w['inner']}, tol {args.tol}")
+    print("| method | m | r | n_s | iterations l=0 | iterations l=1 | l=1 per l=0 | setup s | solve s |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|")
+    for x in rows:
+        print(f"| {x['method']} | {x['m']} | {x['r']} | {x['n_s']} | {x['iters_l0']} | {x['iters_l1']} | "
+              f"{x['normalised_l1']:.2f} | {x['setup_s']:.3f} | {x['solve_s']:.3f} |")
+    print("\nLeading singular values of aggregate 0 (chirality 0), sigma_1 .. sigma_k:")
+    for x in rows:
+        sv = x["sigma_agg0"][0]
+        print(f"{x['method']:8s} m={x['m']:3d} r={x['r']:2d}: " + " ".join(f"{v:.3g}" for v in sv))
 
 
 def read_counter(d, counter):
@@ -244,6 +312,9 @@ def main():
         return
     if args.traffic_probe:
         traffic_probe(args)
+        return
+    if args.compare_setups:
+        compare_setups(args)
         return
     import numpy as np
     import torch

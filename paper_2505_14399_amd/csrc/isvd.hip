@@ -17,7 +17,9 @@
 //
 // The row passes stream N rows through LDS in chunks of CH rows; the next chunk is prefetched
 // into registers while the current one is used.  Each thread owns a 2 x 2 tile of the small
-// output and a subset of the rows (split-K), the partial tiles are summed once per pass.
+// output (up to four tiles when there are more tiles than threads) and a subset of the rows
+// (split-K), the partial tiles are summed once per pass.
+#include <algorithm>
 #include <cmath>
 
 #include "mg.hpp"
@@ -74,7 +76,7 @@ __device__ inline void stage(cd* chunk, const cd* reg, int w, int tid) {
 
 // Gram kernel: rows of the result are the w columns [U, Psi or R], columns the r columns of
 // Psi (pass 1) or R (pass 2).  2x2 tiles over (a, b), row groups over the chunk rows.
-template <int NPF>
+template <int NPF, int TPT>
 __global__ __launch_bounds__(T) void k_isvd_gram(const double2* __restrict__ Ug, const double2* __restrict__ Psig,
                                                  double2* __restrict__ small, IsvdArgs a) {
   extern __shared__ unsigned char smem_raw[];
@@ -84,10 +86,19 @@ __global__ __launch_bounds__(T) void k_isvd_gram(const double2* __restrict__ Ug,
   cd* Xs = chunk + size_t(w) * CHP;              // [kp][r]  X of pass 1
   cd* red = Xs + size_t(kp) * r;                 // reduction buffer [nrg][w][r]
   const int ta = (w + 1) / 2, tb = (r + 1) / 2, ntile = ta * tb;
-  const int nrg = max(1, T / ntile);
-  const int tile = tid % ntile, rg = tid / ntile;
-  const bool active = rg < nrg && tid < ntile * nrg;
-  const int a0 = 2 * (tile / tb), b0 = 2 * (tile % tb);
+  // TPT == 1: one tile per thread and the chunk rows split over T / ntile row groups;
+  // TPT > 1 (more tiles than threads): tiles tid, tid + T, ... per thread, one row group
+  const int nrg = TPT == 1 ? max(1, T / ntile) : 1;
+  const int rg = TPT == 1 ? tid / ntile : 0;
+  int a0[TPT], b0[TPT];
+  bool active[TPT];
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int tile = TPT == 1 ? tid % ntile : tid + q * T;
+    active[q] = TPT == 1 ? (rg < nrg && tid < ntile * nrg) : tile < ntile;
+    a0[q] = 2 * (tile / tb);
+    b0[q] = 2 * (tile % tb);
+  }
   const size_t sstride = small_stride(kp, r);
 
   for (int p = blockIdx.x; p < a.nprob; p += gridDim.x) {
@@ -95,7 +106,9 @@ __global__ __launch_bounds__(T) void k_isvd_gram(const double2* __restrict__ Ug,
     const double2* Psi = Psig + size_t(p) * r * N;
     double2* sm = small + size_t(p) * sstride;
     for (int pass = 0; pass < 2; ++pass) {
-      cd acc[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+      cd acc[TPT][2][2];
+#pragma unroll
+      for (int q = 0; q < TPT; ++q) acc[q][0][0] = acc[q][0][1] = acc[q][1][0] = acc[q][1][1] = {0, 0};
       cd reg[NPF];
       prefetch<NPF>(reg, U, Psi, kp, w, N, 0, tid);
       for (int r0 = 0; r0 < N; r0 += CH) {
@@ -113,29 +126,33 @@ __global__ __launch_bounds__(T) void k_isvd_gram(const double2* __restrict__ Ug,
           }
           __syncthreads();
         }
-        if (active) {
-          const int a1 = min(a0 + 1, w - 1), b1 = min(b0 + 1, r - 1);
-          const cd* A0 = chunk + a0 * CHP;
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+          if (!active[q]) continue;
+          const int a1 = min(a0[q] + 1, w - 1), b1 = min(b0[q] + 1, r - 1);
+          const cd* A0 = chunk + a0[q] * CHP;
           const cd* A1 = chunk + a1 * CHP;
-          const cd* B0 = chunk + (kp + b0) * CHP;
+          const cd* B0 = chunk + (kp + b0[q]) * CHP;
           const cd* B1 = chunk + (kp + b1) * CHP;
 #pragma unroll 4
           for (int row = rg; row < CH; row += nrg) {
             const cd x0 = A0[row], x1 = A1[row], y0 = B0[row], y1 = B1[row];
-            acc[0][0] += cmul_conj(x0, y0);
-            acc[0][1] += cmul_conj(x0, y1);
-            acc[1][0] += cmul_conj(x1, y0);
-            acc[1][1] += cmul_conj(x1, y1);
+            acc[q][0][0] += cmul_conj(x0, y0);
+            acc[q][0][1] += cmul_conj(x0, y1);
+            acc[q][1][0] += cmul_conj(x1, y0);
+            acc[q][1][1] += cmul_conj(x1, y1);
           }
         }
         __syncthreads();
       }
       // sum the partial tiles over the row groups
-      if (active) {
+#pragma unroll
+      for (int q = 0; q < TPT; ++q) {
+        if (!active[q]) continue;
         for (int i = 0; i < 2; ++i)
           for (int j = 0; j < 2; ++j) {
-            const int aa = a0 + i, bb = b0 + j;
-            if (aa < w && bb < r) red[(size_t(rg) * w + aa) * r + bb] = acc[i][j];
+            const int aa = a0[q] + i, bb = b0[q] + j;
+            if (aa < w && bb < r) red[(size_t(rg) * w + aa) * r + bb] = acc[q][i][j];
           }
       }
       __syncthreads();
@@ -174,14 +191,17 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
   const int kp = a.kp, r = a.r, w = a.w, kn = a.kn, k = a.k;
   const int we = w + (w & 1);
   const int lane = threadIdx.x;
+  // J (the accumulated rotations) takes G's space: G is last read by the Cholesky step, J is
+  // first written after it
+  const int gj = max(r * r, we * we);
   cd* X = reinterpret_cast<cd*>(smem_raw);  // [kp][r]  (X + X2 after the first step)
   cd* X2 = X + size_t(kp) * r;              // [kp][r]
   cd* G = X2 + size_t(kp) * r;              // [r][r]
-  cd* Tm = G + size_t(r) * r;               // [r][r] upper, row-major
+  cd* J = G;                                // [we][we]
+  cd* Tm = G + size_t(gj);                  // [r][r] upper, row-major
   cd* Ti = Tm + size_t(r) * r;              // [r][r]
   cd* M = Ti + size_t(r) * r;               // [we][we] column-major
-  cd* J = M + size_t(we) * we;              // [we][we]
-  double* s = reinterpret_cast<double*>(J + size_t(we) * we);  // [we]
+  double* s = reinterpret_cast<double*>(M + size_t(we) * we);  // [we]
   double* pn = s + we;                      // [r]
   int* keep = reinterpret_cast<int*>(pn + r);  // [r]
   int* perm = keep + r;                     // [we]
@@ -442,7 +462,8 @@ size_t gram_lds(int kp, int r) {
 }
 size_t small_lds(int kp, int r) {
   const int w = kp + r, we = w + (w & 1);
-  const size_t n = 2 * size_t(kp) * r + 3 * size_t(r) * r + 2 * size_t(we) * we;
+  const size_t n = 2 * size_t(kp) * r + std::max(size_t(r) * r, size_t(we) * we) + 2 * size_t(r) * r +
+                   size_t(we) * we;
   return n * sizeof(cd) + (we + r) * sizeof(double) + (r + we) * sizeof(int);
 }
 size_t rotate_lds(int kp, int r, int kn) {
@@ -457,11 +478,17 @@ void set_lds(const void* f, size_t lds) {
 template <int NPF>
 void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, HierarchyDev& h, const void* blocks,
                  DevBuf& small, DevBuf& AB, DevBuf& sigma_dev, size_t ls, hipStream_t st) {
-  set_lds((const void*)k_isvd_gram<NPF>, lg);
   set_lds((const void*)k_isvd_small, ls);
   set_lds((const void*)k_isvd_rotate<NPF>, lr);
   const int grid = std::min(a.nprob, 4 * ncu);
-  k_isvd_gram<NPF><<<grid, T, lg, st>>>(h.P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+  const int ntile = ((a.w + 1) / 2) * ((a.r + 1) / 2);
+  if (ntile <= T) {
+    set_lds((const void*)k_isvd_gram<NPF, 1>, lg);
+    k_isvd_gram<NPF, 1><<<grid, T, lg, st>>>(h.P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+  } else {
+    set_lds((const void*)k_isvd_gram<NPF, 4>, lg);
+    k_isvd_gram<NPF, 4><<<grid, T, lg, st>>>(h.P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+  }
   QMG_LAUNCH_CHECK();
   k_isvd_small<<<a.nprob, TW, ls, st>>>(small.as<double2>(), sigma_dev.as<double>(), AB.as<double2>(), a);
   QMG_LAUNCH_CHECK();
@@ -482,8 +509,8 @@ int isvd_stream(HierarchyDev& h, const void* blocks, int r, int kp, DevBuf& sigm
   const int w = kp + r;
   const int kn = std::min(h.k, w);
   QMG_CHECK(r >= 1 && w <= MAXW, QMG_ESHAPE, "streaming SVD: k + r = %d exceeds %d", w, MAXW);
-  QMG_CHECK(((w + 1) / 2) * ((r + 1) / 2) <= T, QMG_ESHAPE,
-            "streaming SVD: ceil((k+r)/2) * ceil(r/2) = %d exceeds %d", ((w + 1) / 2) * ((r + 1) / 2), T);
+  QMG_CHECK(((w + 1) / 2) * ((r + 1) / 2) <= 4 * T, QMG_ESHAPE,
+            "streaming SVD: ceil((k+r)/2) * ceil(r/2) = %d exceeds %d", ((w + 1) / 2) * ((r + 1) / 2), 4 * T);
   const size_t lg = gram_lds(kp, r), ls = small_lds(kp, r), lr = rotate_lds(kp, r, kn);
   QMG_CHECK(lg <= 160 * 1024 && ls <= 160 * 1024 && lr <= 160 * 1024, QMG_ESHAPE,
             "streaming SVD: k + r = %d needs more than 160 KiB of LDS", w);

@@ -45,7 +45,9 @@ def _oracle_icsvd(psis, dims, block, k):
 @pytest.mark.parametrize("dims,block,k,r,ns", [((4, 4, 4, 4), (2, 2, 2, 2), 8, 4, 4),
                                                ((8, 4, 4, 8), (4, 4, 4, 4), 24, 8, 6),
                                                ((4, 4, 4, 4), (2, 2, 2, 2), 12, 4, 3),   # k >= n_s r: no truncation
-                                               ((4, 4, 2, 6), (2, 2, 2, 3), 10, 7, 3)])  # odd sizes
+                                               ((4, 4, 2, 6), (2, 2, 2, 3), 10, 7, 3),   # odd sizes
+                                               ((8, 4, 4, 8), (4, 4, 4, 4), 16, 32, 2),  # > 256 Gram tiles
+                                               ((8, 4, 4, 8), (4, 4, 4, 4), 24, 48, 1)])  # one batch of 48
 def test_streaming_svd_given_vectors(qmg, dims, block, k, r, ns):
     """n_setup_iter = 0 and explicit phi isolate Algorithm 3 (psi = phi / |phi|)."""
     banner(f"streaming svd {dims} block={block} k={k} r={r} ns={ns}")
@@ -97,6 +99,33 @@ def c1(qmg):
     olat = omg.Lattice(U, w["dims"], w["mass"], w["xi"], w["bc_t"])
     oh = omg.setup(olat, w["block"], w["n_test"], w["batch"], w["rank"], 16, seed=w["seed"])
     return w, U, lat, mg, olat, oh
+
+
+def test_setup_methods_singular_value_bounds(qmg):
+    """Regular (k vectors), CSVD (all m in one batch) and streaming (m in batches of r) on the same
+    smoothed test vectors: the streamed factor satisfies Phi Phi^dag <= A A^dag with A all m
+    vectors, so sigma_i(streaming) <= sigma_i(CSVD); the first k vectors are columns of A, so
+    sigma_i(Regular) <= sigma_i(CSVD) as well (interlacing).  Both hold per aggregate and chirality."""
+    dims, block, k, m = (4, 4, 4, 8), (2, 2, 2, 2), 8, 16
+    banner("setup methods: singular value bounds")
+    U = fields.random_gauge(dims, 0.3, 21)
+    lat = qmg.Lattice(dims, 0.05, 1.0, -1)
+    Ug = to_gpu(U)
+
+    def sigma(n_test, batch):
+        mg = qmg.mg_setup_stream_chiral_svd(lat, Ug, block, n_test, batch, k, n_setup_iter=4, inner="f64", seed=5)
+        _, sig = mg.prolongator()
+        mg.close()
+        return sig
+
+    full = sigma(m, m)
+    assert np.all(np.diff(full, axis=-1) <= 1e-12 * full[..., :1])  # descending
+    for batch in (8, 4, 2):
+        s = sigma(m, batch)
+        assert np.all(s <= full * (1 + 1e-10) + 1e-14), batch
+        assert np.all(s > 0)
+    reg = sigma(k, k)
+    assert np.all(reg <= full * (1 + 1e-10) + 1e-14)
 
 
 def test_setup_full_c1(c1):
