@@ -149,7 +149,7 @@ qmg_status qmg_coarse_apply(const qmg_mg* mg, const void* in, void* out, int32_t
                             hipStream_t stream);
 
 typedef struct {
-  int32_t outer_iters;      /* outer flexible-GCR iterations, summed over refinements        */
+  int32_t outer_iters;      /* outer flexible GMRES iterations, summed over refinements      */
   int32_t refinements;      /* FP64 defect-correction steps                                  */
   int32_t coarse_iters;     /* coarse GMRES iterations, summed                               */
   int32_t smoother_iters;   /* fine GMRES post-smoothing iterations, summed                  */
@@ -195,6 +195,30 @@ qmg_status qmg_smooth(const qmg_lattice* lat, const void* U, const void* phi, vo
 qmg_status qmg_mg_query(const qmg_mg* mg, int32_t* coarse_dims, int32_t* n_agg, int32_t* rank);
 qmg_status qmg_mg_get_prolongator(const qmg_mg* mg, void* P, double* sigma, hipStream_t stream);
 qmg_status qmg_mg_get_coarse(const qmg_mg* mg, void* Y, hipStream_t stream);
+
+/* The lattice and setup parameters of a hierarchy (either pointer may be NULL).  n_test is the
+ * number of test vectors folded in so far (streams done * batch); test_vectors is NULL. */
+qmg_status qmg_mg_get_params(const qmg_mg* mg, qmg_lattice* lat, qmg_mg_params* params);
+
+/* Resumable streams: Algorithm 3 continues from the current factor U_k Sigma_k with n_streams
+ * more streams of `batch` test vectors (the counter RNG with the setup's seed at the next global
+ * indices streams_done * batch, ..., smoothed as in the setup), then P, R and D_c are rebuilt.
+ * The result equals a setup with the larger n_test.  Errors: EINVAL (null, n_streams < 1),
+ * ENOMEM, EHIP. */
+qmg_status qmg_mg_stream_more(qmg_mg* mg, int32_t n_streams, hipStream_t stream);
+
+/* Hierarchy checkpoint.  qmg_mg_save writes the lattice, the setup parameters, the number of
+ * streams done, a 64-bit hash of the gauge field, the singular values and the factor U_k (= P)
+ * in FP64 to `path` (a little-endian binary file ending in a hash of its arrays).
+ * qmg_mg_load rebuilds the hierarchy from such a file for the gauge field U (device, canonical
+ * FP64): the Galerkin operator and the inner-precision copies are recomputed, so the loaded
+ * hierarchy solves exactly as the saved one, and qmg_mg_stream_more continues the streaming SVD
+ * from it.  The file does not hold U.
+ * Errors: EINVAL (null, unreadable / truncated / corrupted file, wrong magic or version,
+ *   inconsistent header, U differs from the field the file was built for), ESHAPE, ENOMEM, EHIP.
+ *   On error *out is NULL. */
+qmg_status qmg_mg_save(const qmg_mg* mg, const char* path, hipStream_t stream);
+qmg_status qmg_mg_load(const char* path, const void* U, qmg_mg** out, hipStream_t stream);
 
 /* Setup timings in seconds: smoother, streaming SVD, coarse build, total (host array [4]). */
 qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);

@@ -83,6 +83,10 @@ SIGNATURES = {
     "qmg_set_dslash_variant": [_I],
     "qmg_tune_save": [ctypes.c_char_p],
     "qmg_tune_load": [ctypes.c_char_p],
+    "qmg_mg_stream_more": [_P, _I, _P],
+    "qmg_mg_save": [_P, ctypes.c_char_p, _P],
+    "qmg_mg_load": [ctypes.c_char_p, _P, _P, _P],
+    "qmg_mg_get_params": [_P, _P, _P],
     "qmg_mg_destroy": [_P],
     "qmg_last_error": [],
     "qmg_version": [],
@@ -310,6 +314,25 @@ class MG:
         graph=True captures the cycle into a hipGraph replayed at every application."""
         _check(load_library().qmg_mg_set_cycle(self._h, int(coarse_steps), 1 if graph else 0))
 
+    def stream_more(self, n_streams):
+        """Resume the streaming SVD with n_streams more batches of test vectors (the counter RNG's
+        next global indices), then rebuild P, R and D_c."""
+        _check(load_library().qmg_mg_stream_more(self._h, int(n_streams), _stream()))
+        self._refresh()
+
+    def save(self, path):
+        """Write the hierarchy (parameters, singular values, P in FP64) to a file."""
+        _check(load_library().qmg_mg_save(self._h, os.fsencode(str(path)), _stream()))
+
+    def _refresh(self):
+        lat, p = qmg_lattice(), qmg_mg_params()
+        _check(load_library().qmg_mg_get_params(self._h, ctypes.byref(lat), ctypes.byref(p)))
+        self.params = p
+
+    @property
+    def streams_done(self):
+        return self.params.n_test // self.params.batch
+
     def setup_times(self):
         t = (ctypes.c_double * 4)()
         _check(load_library().qmg_mg_setup_times(self._h, t))
@@ -334,6 +357,20 @@ def mg_setup_stream_chiral_svd(lat: Lattice, U, block, n_test, batch, rank, n_se
     h = ctypes.c_void_p()
     s = lat.c()
     _check(lib.qmg_mg_setup_stream_chiral_svd(ctypes.byref(s), _ptr(U), ctypes.byref(p), ctypes.byref(h), _stream()))
+    return MG(h, lat, p)
+
+
+def mg_load(path, U) -> MG:
+    """Rebuild a hierarchy saved by MG.save for the gauge field U (complex128 [4,V,3,3] on the
+    GPU; it must be the field the hierarchy was built for)."""
+    lib = load_library()
+    if U.dtype != torch.complex128:
+        raise TypeError("load takes the FP64 canonical gauge field")
+    h = ctypes.c_void_p()
+    _check(lib.qmg_mg_load(os.fsencode(str(path)), _ptr(U), ctypes.byref(h), _stream()))
+    cl, p = qmg_lattice(), qmg_mg_params()
+    _check(lib.qmg_mg_get_params(h, ctypes.byref(cl), ctypes.byref(p)))
+    lat = Lattice(tuple(cl.dims), cl.mass, cl.xi, cl.bc_t)
     return MG(h, lat, p)
 
 

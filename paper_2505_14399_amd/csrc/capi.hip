@@ -1,11 +1,15 @@
 // C ABI of libqmg (qmg.h): validation, the multigrid setup driver (Algorithm 4 with
 // Algorithm 3), the K-cycle preconditioner and the mixed-precision MG solve.
 #include <chrono>
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <cstdarg>
 #include <memory>
 #include <new>
+#include <string>
+#include <vector>
 #include <type_traits>
 
 #include "mg.hpp"
@@ -15,6 +19,10 @@
 struct qmg_mg {
   qmg::HierarchyDev h;
   qmg::DevBuf sigma_dev;
+  qmg_lattice lat{};        // as given to the setup
+  qmg_mg_params params{};   // as given to the setup (test_vectors cleared after it)
+  int streams_done = 0;     // streams of the streaming SVD applied so far
+  int kp = 0;               // columns of the current factor U_k
 };
 
 namespace qmg {
@@ -330,26 +338,25 @@ void smooth_native(const Geom& g, const void* Uin, void* phi, int r, int n_iter,
   QMG_HIP(hipStreamSynchronize(st));
 }
 
+// Streams [s0, s1) of Algorithm 3 on the handle's state (U_k in P64, Sigma in sigma_dev): test
+// vectors s * r .. s * r + r - 1 (Philox by global index, or the caller's buffer), smoothed in
+// storage precision S, split by chirality and folded into every (aggregate, chirality) factor.
 template <class S>
-void run_setup(qmg_mg* mg, const qmg_mg_params* p, hipStream_t st) {
+void run_streams(qmg_mg* mg, int s0, int s1, const void* test_vectors, hipStream_t st) {
   HierarchyDev& h = mg->h;
   const Geom& g = h.g;
-  const int r = p->batch, ns = p->n_test / p->batch;
+  const qmg_mg_params* p = &mg->params;
+  const int r = p->batch;
   constexpr qmg_prec P = StoreTraits<S>::prec;
-  const auto t0 = Clock::now();
   const void* Uin = (P == QMG_F64) ? h.U64.p : (h.inner == QMG_F32 ? h.Uin.p : h.U32.p);
   DevBuf phi(size_t(r) * 12 * g.V * sizeof(double2));
   DevBuf blocks(size_t(2) * h.blk.d * r * h.blk.N * sizeof(double2));
   DevBuf b_in, x_in, tmp64;
   Gmres<S> gm;
-  h.P64.alloc(size_t(2) * h.blk.d * h.k * h.blk.N * sizeof(double2));
-  mg->sigma_dev.alloc(size_t(2) * h.blk.d * h.k * sizeof(double));
-  int kp = 0;
-  double ts = 0, tv = 0;
-  for (int s = 0; s < ns; ++s) {
+  for (int s = s0; s < s1; ++s) {
     const auto a0 = Clock::now();
-    if (p->test_vectors) {
-      const double2* tv0 = static_cast<const double2*>(p->test_vectors) + size_t(s) * r * 12 * g.V;
+    if (test_vectors) {
+      const double2* tv0 = static_cast<const double2*>(test_vectors) + size_t(s - s0) * r * 12 * g.V;
       launch_pack_spinor(tv0, QMG_F64, phi.p, QMG_F64, g.V, r, st);
     } else {
       launch_philox_native(g, p->seed, s * r, r, phi.p, st);
@@ -357,13 +364,20 @@ void run_setup(qmg_mg* mg, const qmg_mg_params* p, hipStream_t st) {
     smooth_native<S>(g, Uin, phi.p, r, p->n_setup_iter, st, gm, b_in, x_in, tmp64);
     const auto a1 = Clock::now();
     launch_chiral_gather(h, phi.p, blocks.p, r, st);
-    kp = isvd_stream(h, blocks.p, r, kp, mg->sigma_dev, st);
+    mg->kp = isvd_stream(h, blocks.p, r, mg->kp, mg->sigma_dev, st);
     QMG_HIP(hipStreamSynchronize(st));
     const auto a2 = Clock::now();
-    ts += secs(a0, a1);
-    tv += secs(a1, a2);
+    h.t_smooth += secs(a0, a1);
+    h.t_svd += secs(a1, a2);
+    mg->streams_done = s + 1;
   }
-  QMG_CHECK(kp == h.k, QMG_ESHAPE, "streaming SVD ended with %d < k columns", kp);
+}
+
+// P = U_k: the Galerkin coarse operator from P64, the inner-precision copies of P and D_c and
+// the host copy of Sigma (after the last stream, after a load or after more streams)
+void finish_setup(qmg_mg* mg, hipStream_t st) {
+  HierarchyDev& h = mg->h;
+  QMG_CHECK(mg->kp == h.k, QMG_ESHAPE, "streaming SVD ended with %d < k columns", mg->kp);
   const auto c0 = Clock::now();
   const int m = 2 * h.k;
   h.Y64.alloc(size_t(h.blk.d) * 9 * m * m * sizeof(double2));
@@ -379,11 +393,23 @@ void run_setup(qmg_mg* mg, const qmg_mg_params* p, hipStream_t st) {
   QMG_HIP(hipMemcpyAsync(h.sigma.data(), mg->sigma_dev.p, h.sigma.size() * sizeof(double), hipMemcpyDeviceToHost,
                          st));
   QMG_HIP(hipStreamSynchronize(st));
-  const auto c1 = Clock::now();
-  h.t_smooth = ts;
-  h.t_svd = tv;
-  h.t_coarse = secs(c0, c1);
-  h.t_total = secs(t0, c1);
+  h.t_coarse = secs(c0, Clock::now());
+}
+
+void run_setup(qmg_mg* mg, hipStream_t st) {
+  HierarchyDev& h = mg->h;
+  const auto t0 = Clock::now();
+  h.P64.alloc(size_t(2) * h.blk.d * h.k * h.blk.N * sizeof(double2));
+  mg->sigma_dev.alloc(size_t(2) * h.blk.d * h.k * sizeof(double));
+  mg->kp = 0;
+  mg->streams_done = 0;
+  h.t_smooth = h.t_svd = 0;
+  const int ns = mg->params.n_test / mg->params.batch;
+  // test-vector smoothing in FP64 for an FP64 hierarchy, else in FP32
+  if (h.inner == QMG_F64) run_streams<double2>(mg, 0, ns, mg->params.test_vectors, st);
+  else run_streams<float2>(mg, 0, ns, mg->params.test_vectors, st);
+  finish_setup(mg, st);
+  h.t_total = secs(t0, Clock::now());
 }
 
 // ---------------------------------------------------------------------------------------
@@ -621,6 +647,197 @@ qmg_status qmg_pack_gauge(const qmg_lattice* lat, const void* canon, void* nativ
   });
 }
 
+}  // extern "C"
+
+namespace qmg {
+namespace {
+
+// Validated blocking for a lattice and setup parameters (ESHAPE / EINVAL otherwise).
+Blocking check_params(const Geom& g, const qmg_mg_params* p) {
+  Blocking b{};
+  b.nd = 1;
+  b.d = 1;
+  for (int q = 0; q < 4; ++q) {
+    QMG_CHECK(p->block[q] >= 1 && g.L[q] % p->block[q] == 0, QMG_ESHAPE,
+              "block extent %d (%d) does not divide lattice extent %d", q, p->block[q], g.L[q]);
+    b.b[q] = p->block[q];
+    b.cL[q] = g.L[q] / p->block[q];
+    b.nd *= b.b[q];
+    b.d *= b.cL[q];
+  }
+  b.N = 6 * b.nd;
+  QMG_CHECK(p->batch >= 1 && p->batch <= 48, QMG_ESHAPE, "batch r must be in [1, 48]");
+  QMG_CHECK(p->n_test >= p->batch && p->n_test % p->batch == 0, QMG_ESHAPE,
+            "n_test must be a positive multiple of batch");
+  QMG_CHECK(p->rank >= 1 && p->rank <= b.N && p->rank <= p->n_test && p->rank <= 32, QMG_ESHAPE,
+            "rank k must satisfy 1 <= k <= min(6*prod(block), n_test, 32)");
+  QMG_CHECK(p->n_setup_iter >= 0 && p->n_post_smooth >= 0 && p->coarse_max_iter >= 1, QMG_EINVAL,
+            "iteration counts must be non-negative");
+  QMG_CHECK(p->coarse_tol > 0 && p->coarse_tol < 1, QMG_EINVAL, "coarse_tol must be in (0, 1)");
+  check_prec(p->inner_prec);
+  return b;
+}
+
+// A handle with the tables and the packed gauge copies, before any stream.
+std::unique_ptr<qmg_mg> new_hierarchy(const qmg_lattice* lat, const void* U, const qmg_mg_params* p,
+                                      hipStream_t stream) {
+  const Geom g = make_geom(lat);
+  const Blocking b = check_params(g, p);
+  std::unique_ptr<qmg_mg> mg(new qmg_mg());
+  HierarchyDev& h = mg->h;
+  h.g = g;
+  h.blk = b;
+  h.k = p->rank;
+  h.inner = p->inner_prec;
+  h.n_post = p->n_post_smooth;
+  h.coarse_tol = p->coarse_tol;
+  h.coarse_max = p->coarse_max_iter;
+  build_tables(h);
+  h.U64.alloc(size_t(36) * g.V * sizeof(double2));
+  launch_pack_gauge(U, h.U64.p, QMG_F64, g.V, stream);
+  const double un = host_norm2(h.U64.p, size_t(36) * g.V, stream);
+  QMG_CHECK(std::isfinite(un), QMG_ENONFINITE, "gauge field has non-finite entries");
+  if (h.inner != QMG_F64) {
+    h.Uin.alloc(size_t(36) * g.V * prec_bytes(h.inner));
+    launch_pack_gauge(U, h.Uin.p, h.inner, g.V, stream);
+  }
+  if (h.inner == QMG_BF16 || h.inner == QMG_F16) {
+    h.U32.alloc(size_t(36) * g.V * sizeof(float2));
+    launch_pack_gauge(U, h.U32.p, QMG_F32, g.V, stream);
+  }
+  mg->lat = *lat;
+  mg->params = *p;
+  mg->params.test_vectors = nullptr;  // caller memory is not retained
+  return mg;
+}
+
+// ---------------------------------------------------------------------------------------
+// checkpoint file: fixed little-endian fields, then Sigma and U_k (P in FP64), then a hash of
+// both arrays.  The gauge field is not stored: its hash ties the file to the field it was built
+// for, and the Galerkin operator is rebuilt from P and the field on load.
+constexpr char kMagic[8] = {'Q', 'M', 'G', 'H', 'I', 'E', 'R', '1'};
+constexpr int32_t kFileVersion = 1;
+
+uint64_t hash_words(uint64_t h, const void* data, size_t bytes) {
+  const unsigned char* c = static_cast<const unsigned char*>(data);
+  size_t i = 0;
+  for (; i + 8 <= bytes; i += 8) {
+    uint64_t w;
+    std::memcpy(&w, c + i, 8);
+    h = (h ^ w) * 0x100000001b3ull;
+    h ^= h >> 29;
+  }
+  for (; i < bytes; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+  return h;
+}
+constexpr uint64_t kHashSeed = 0xcbf29ce484222325ull;
+
+// hash of a device buffer, streamed through pinned host memory
+uint64_t device_hash(const void* dev, size_t bytes, hipStream_t st) {
+  const size_t chunk = size_t(64) << 20;
+  PinnedBuf host;
+  host.ensure(std::min(chunk, bytes));
+  uint64_t h = kHashSeed;
+  for (size_t off = 0; off < bytes; off += chunk) {
+    const size_t n = std::min(chunk, bytes - off);
+    QMG_HIP(hipMemcpyAsync(host.p, static_cast<const char*>(dev) + off, n, hipMemcpyDeviceToHost, st));
+    QMG_HIP(hipStreamSynchronize(st));
+    h = hash_words(h, host.p, n);
+  }
+  return h;
+}
+
+struct File {
+  std::FILE* f = nullptr;
+  std::string path;
+  File(const char* p, const char* mode) : f(std::fopen(p, mode)), path(p) {
+    QMG_CHECK(f, QMG_EINVAL, "cannot open %s", p);
+  }
+  ~File() {
+    if (f) std::fclose(f);
+  }
+  void put(const void* d, size_t n) { QMG_CHECK(std::fwrite(d, 1, n, f) == n, QMG_EINVAL, "write to %s failed", path.c_str()); }
+  void get(void* d, size_t n) {
+    QMG_CHECK(std::fread(d, 1, n, f) == n, QMG_EINVAL, "%s is truncated or unreadable", path.c_str());
+  }
+  template <class T> void put(const T& v) { put(&v, sizeof(T)); }
+  template <class T> T get() {
+    T v;
+    get(&v, sizeof(T));
+    return v;
+  }
+};
+
+struct FileHeader {
+  qmg_lattice lat{};
+  qmg_mg_params params{};
+  int32_t streams_done = 0, kp = 0;
+  uint64_t gauge_hash = 0;
+  uint64_t n_sigma = 0, n_p = 0;
+};
+
+void put_header(File& f, const FileHeader& hd) {
+  f.put(kMagic, sizeof(kMagic));
+  f.put<int32_t>(kFileVersion);
+  for (int q = 0; q < 4; ++q) f.put<int32_t>(hd.lat.dims[q]);
+  f.put<int32_t>(hd.lat.bc_t);
+  f.put<double>(hd.lat.mass);
+  f.put<double>(hd.lat.xi);
+  const qmg_mg_params& p = hd.params;
+  for (int q = 0; q < 4; ++q) f.put<int32_t>(p.block[q]);
+  f.put<int32_t>(p.n_test);
+  f.put<int32_t>(p.batch);
+  f.put<int32_t>(p.rank);
+  f.put<int32_t>(p.n_setup_iter);
+  f.put<int32_t>(p.n_post_smooth);
+  f.put<double>(p.coarse_tol);
+  f.put<int32_t>(p.coarse_max_iter);
+  f.put<int32_t>(int32_t(p.inner_prec));
+  f.put<uint64_t>(p.seed);
+  f.put<int32_t>(hd.streams_done);
+  f.put<int32_t>(hd.kp);
+  f.put<uint64_t>(hd.gauge_hash);
+  f.put<uint64_t>(hd.n_sigma);
+  f.put<uint64_t>(hd.n_p);
+}
+
+FileHeader get_header(File& f) {
+  char magic[8];
+  f.get(magic, sizeof(magic));
+  QMG_CHECK(std::memcmp(magic, kMagic, sizeof(kMagic)) == 0, QMG_EINVAL, "%s is not a hierarchy file",
+            f.path.c_str());
+  const int32_t ver = f.get<int32_t>();
+  QMG_CHECK(ver == kFileVersion, QMG_EINVAL, "%s: unsupported hierarchy file version %d", f.path.c_str(), ver);
+  FileHeader hd;
+  for (int q = 0; q < 4; ++q) hd.lat.dims[q] = f.get<int32_t>();
+  hd.lat.bc_t = f.get<int32_t>();
+  hd.lat.mass = f.get<double>();
+  hd.lat.xi = f.get<double>();
+  qmg_mg_params& p = hd.params;
+  for (int q = 0; q < 4; ++q) p.block[q] = f.get<int32_t>();
+  p.n_test = f.get<int32_t>();
+  p.batch = f.get<int32_t>();
+  p.rank = f.get<int32_t>();
+  p.n_setup_iter = f.get<int32_t>();
+  p.n_post_smooth = f.get<int32_t>();
+  p.coarse_tol = f.get<double>();
+  p.coarse_max_iter = f.get<int32_t>();
+  p.inner_prec = qmg_prec(f.get<int32_t>());
+  p.seed = f.get<uint64_t>();
+  p.test_vectors = nullptr;
+  hd.streams_done = f.get<int32_t>();
+  hd.kp = f.get<int32_t>();
+  hd.gauge_hash = f.get<uint64_t>();
+  hd.n_sigma = f.get<uint64_t>();
+  hd.n_p = f.get<uint64_t>();
+  return hd;
+}
+
+}  // namespace
+}  // namespace qmg
+
+extern "C" {
+
 qmg_status qmg_mg_setup_stream_chiral_svd(const qmg_lattice* lat, const void* U, const qmg_mg_params* p,
                                           qmg_mg** out, hipStream_t stream) {
   if (out) *out = nullptr;
@@ -629,55 +846,115 @@ qmg_status qmg_mg_setup_stream_chiral_svd(const qmg_lattice* lat, const void* U,
     check_ptr(U, "U");
     check_ptr(p, "params");
     check_ptr(out, "out");
-    Geom g = make_geom(lat);
-    Blocking b{};
-    b.nd = 1;
-    b.d = 1;
-    for (int q = 0; q < 4; ++q) {
-      QMG_CHECK(p->block[q] >= 1 && g.L[q] % p->block[q] == 0, QMG_ESHAPE,
-                "block extent %d (%d) does not divide lattice extent %d", q, p->block[q], g.L[q]);
-      b.b[q] = p->block[q];
-      b.cL[q] = g.L[q] / p->block[q];
-      b.nd *= b.b[q];
-      b.d *= b.cL[q];
-    }
-    b.N = 6 * b.nd;
-    QMG_CHECK(p->batch >= 1 && p->batch <= 48, QMG_ESHAPE, "batch r must be in [1, 48]");
-    QMG_CHECK(p->n_test >= p->batch && p->n_test % p->batch == 0, QMG_ESHAPE,
-              "n_test must be a positive multiple of batch");
-    QMG_CHECK(p->rank >= 1 && p->rank <= b.N && p->rank <= p->n_test && p->rank <= 32, QMG_ESHAPE,
-              "rank k must satisfy 1 <= k <= min(6*prod(block), n_test, 32)");
-    QMG_CHECK(p->n_setup_iter >= 0 && p->n_post_smooth >= 0 && p->coarse_max_iter >= 1, QMG_EINVAL,
-              "iteration counts must be non-negative");
-    QMG_CHECK(p->coarse_tol > 0 && p->coarse_tol < 1, QMG_EINVAL, "coarse_tol must be in (0, 1)");
-    check_prec(p->inner_prec);
-
-    std::unique_ptr<qmg_mg> mg(new qmg_mg());
-    HierarchyDev& h = mg->h;
-    h.g = g;
-    h.blk = b;
-    h.k = p->rank;
-    h.inner = p->inner_prec;
-    h.n_post = p->n_post_smooth;
-    h.coarse_tol = p->coarse_tol;
-    h.coarse_max = p->coarse_max_iter;
-    build_tables(h);
-    h.U64.alloc(size_t(36) * g.V * sizeof(double2));
-    launch_pack_gauge(U, h.U64.p, QMG_F64, g.V, stream);
-    const double un = host_norm2(h.U64.p, size_t(36) * g.V, stream);
-    QMG_CHECK(std::isfinite(un), QMG_ENONFINITE, "gauge field has non-finite entries");
-    if (h.inner != QMG_F64) {
-      h.Uin.alloc(size_t(36) * g.V * prec_bytes(h.inner));
-      launch_pack_gauge(U, h.Uin.p, h.inner, g.V, stream);
-    }
-    if (h.inner == QMG_BF16 || h.inner == QMG_F16) {
-      h.U32.alloc(size_t(36) * g.V * sizeof(float2));
-      launch_pack_gauge(U, h.U32.p, QMG_F32, g.V, stream);
-    }
-    // test-vector smoothing in FP64 for an FP64 hierarchy, else in FP32
-    if (h.inner == QMG_F64) run_setup<double2>(mg.get(), p, stream);
-    else run_setup<float2>(mg.get(), p, stream);
+    std::unique_ptr<qmg_mg> mg = new_hierarchy(lat, U, p, stream);
+    mg->params.test_vectors = p->test_vectors;
+    run_setup(mg.get(), stream);
+    mg->params.test_vectors = nullptr;  // caller memory is not retained
     *out = mg.release();
+  });
+}
+
+qmg_status qmg_mg_stream_more(qmg_mg* mg, int32_t n_streams, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    QMG_CHECK(n_streams >= 1, QMG_EINVAL, "n_streams must be >= 1");
+    HierarchyDev& h = mg->h;
+    const auto t0 = Clock::now();
+    const int s0 = mg->streams_done;
+    if (h.inner == QMG_F64) run_streams<double2>(mg, s0, s0 + n_streams, nullptr, stream);
+    else run_streams<float2>(mg, s0, s0 + n_streams, nullptr, stream);
+    mg->params.n_test = mg->streams_done * mg->params.batch;
+    finish_setup(mg, stream);
+    h.t_total += secs(t0, Clock::now());
+  });
+}
+
+qmg_status qmg_mg_save(const qmg_mg* mg, const char* path, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(path, "path");
+    const HierarchyDev& h = mg->h;
+    FileHeader hd;
+    hd.lat = mg->lat;
+    hd.params = mg->params;
+    hd.params.test_vectors = nullptr;
+    hd.streams_done = mg->streams_done;
+    hd.kp = mg->kp;
+    hd.gauge_hash = device_hash(h.U64.p, size_t(36) * h.g.V * sizeof(double2), stream);
+    hd.n_sigma = uint64_t(2) * h.blk.d * h.k;
+    hd.n_p = uint64_t(2) * h.blk.d * h.k * h.blk.N;
+    std::vector<double> sig(hd.n_sigma);
+    QMG_HIP(hipMemcpyAsync(sig.data(), mg->sigma_dev.p, sig.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    QMG_HIP(hipStreamSynchronize(stream));
+    File f(path, "wb");
+    put_header(f, hd);
+    f.put(sig.data(), sig.size() * sizeof(double));
+    uint64_t ph = hash_words(kHashSeed, sig.data(), sig.size() * sizeof(double));
+    // P in chunks through pinned memory
+    const size_t bytes = hd.n_p * sizeof(double2), chunk = size_t(64) << 20;
+    PinnedBuf host;
+    host.ensure(std::min(chunk, bytes));
+    for (size_t off = 0; off < bytes; off += chunk) {
+      const size_t n = std::min(chunk, bytes - off);
+      QMG_HIP(hipMemcpyAsync(host.p, static_cast<const char*>(h.P64.p) + off, n, hipMemcpyDeviceToHost, stream));
+      QMG_HIP(hipStreamSynchronize(stream));
+      f.put(host.p, n);
+      ph = hash_words(ph, host.p, n);
+    }
+    f.put<uint64_t>(ph);
+  });
+}
+
+qmg_status qmg_mg_load(const char* path, const void* U, qmg_mg** out, hipStream_t stream) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    check_ptr(path, "path");
+    check_ptr(U, "U");
+    check_ptr(out, "out");
+    File f(path, "rb");
+    const FileHeader hd = get_header(f);
+    const Geom g = make_geom(&hd.lat);
+    const Blocking b = check_params(g, &hd.params);
+    QMG_CHECK(hd.kp == hd.params.rank && hd.streams_done * hd.params.batch == hd.params.n_test &&
+                  hd.n_sigma == uint64_t(2) * b.d * hd.params.rank &&
+                  hd.n_p == uint64_t(2) * b.d * hd.params.rank * b.N,
+              QMG_EINVAL, "%s: inconsistent hierarchy header", path);
+    const auto t0 = Clock::now();
+    std::unique_ptr<qmg_mg> mg = new_hierarchy(&hd.lat, U, &hd.params, stream);
+    HierarchyDev& h = mg->h;
+    const uint64_t gh = device_hash(h.U64.p, size_t(36) * g.V * sizeof(double2), stream);
+    QMG_CHECK(gh == hd.gauge_hash, QMG_EINVAL, "%s was built for a different gauge field", path);
+    std::vector<double> sig(hd.n_sigma);
+    f.get(sig.data(), sig.size() * sizeof(double));
+    uint64_t ph = hash_words(kHashSeed, sig.data(), sig.size() * sizeof(double));
+    h.P64.alloc(hd.n_p * sizeof(double2));
+    mg->sigma_dev.alloc(sig.size() * sizeof(double));
+    QMG_HIP(hipMemcpyAsync(mg->sigma_dev.p, sig.data(), sig.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    const size_t bytes = hd.n_p * sizeof(double2), chunk = size_t(64) << 20;
+    PinnedBuf host;
+    host.ensure(std::min(chunk, bytes));
+    for (size_t off = 0; off < bytes; off += chunk) {
+      const size_t n = std::min(chunk, bytes - off);
+      QMG_HIP(hipStreamSynchronize(stream));  // the previous chunk has left the staging buffer
+      f.get(host.p, n);
+      ph = hash_words(ph, host.p, n);
+      QMG_HIP(hipMemcpyAsync(static_cast<char*>(h.P64.p) + off, host.p, n, hipMemcpyHostToDevice, stream));
+    }
+    QMG_HIP(hipStreamSynchronize(stream));
+    QMG_CHECK(f.get<uint64_t>() == ph, QMG_EINVAL, "%s: checksum mismatch (corrupted file)", path);
+    mg->kp = hd.kp;
+    mg->streams_done = hd.streams_done;
+    finish_setup(mg.get(), stream);
+    h.t_total = secs(t0, Clock::now());
+    *out = mg.release();
+  });
+}
+
+qmg_status qmg_mg_get_params(const qmg_mg* mg, qmg_lattice* lat, qmg_mg_params* params) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    if (lat) *lat = mg->lat;
+    if (params) *params = mg->params;
   });
 }
 

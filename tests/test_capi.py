@@ -99,3 +99,26 @@ def test_dslash_variant_codes_are_validated():
             assert L.qmg_set_dslash_variant(v) == -1, v
     finally:
         assert L.qmg_set_dslash_variant(0) == 0
+
+
+def test_hierarchy_file_errors_without_device_work(tmp_path):
+    import paper_2505_14399_amd as q
+    L = q.load_library()
+    P = ctypes.c_void_p
+    out = ctypes.c_void_p()
+    dummy = P(16)  # never dereferenced: the file is rejected first
+    missing = str(tmp_path / "missing.qmg").encode()
+    assert L.qmg_mg_load(missing, dummy, ctypes.byref(out), None) == -1
+    assert b"cannot open" in L.qmg_last_error()
+    assert out.value is None
+    bad = tmp_path / "bad.qmg"
+    bad.write_bytes(b"NOTAHIER" + bytes(64))
+    assert L.qmg_mg_load(str(bad).encode(), dummy, ctypes.byref(out), None) == -1
+    assert b"not a hierarchy file" in L.qmg_last_error()
+    short = tmp_path / "short.qmg"
+    short.write_bytes(b"QMGHIER1" + (1).to_bytes(4, "little") + bytes(10))
+    assert L.qmg_mg_load(str(short).encode(), dummy, ctypes.byref(out), None) == -1
+    assert b"truncated" in L.qmg_last_error()
+    assert L.qmg_mg_load(str(bad).encode(), None, ctypes.byref(out), None) == -1
+    assert L.qmg_mg_save(None, str(bad).encode(), None) == -1
+    assert L.qmg_mg_stream_more(None, 1, None) == -1

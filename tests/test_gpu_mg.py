@@ -128,6 +128,67 @@ def test_setup_methods_singular_value_bounds(qmg):
     assert np.all(reg <= full * (1 + 1e-10) + 1e-14)
 
 
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_stream_more_and_checkpoint(qmg, tmp_path, inner):
+    """Resumable streams and the hierarchy checkpoint are exact: a setup of 8 test vectors
+    continued by two more streams equals a setup of 16; a saved and reloaded hierarchy has the
+    same P, singular values and D_c and solves bit for bit like the original; a checkpoint taken
+    after 8 vectors and continued after the reload equals the 16-vector setup as well."""
+    dims, block, k, r = (4, 4, 4, 4), (2, 2, 2, 2), 8, 4
+    banner(f"stream_more and checkpoint {inner}")
+    U = to_gpu(fields.random_gauge(dims, 0.3, 31))
+    lat = qmg.Lattice(dims, 0.05, 1.0, -1)
+    kw = dict(n_setup_iter=4, inner=inner, seed=9)
+
+    def state(mg):
+        P, sig = mg.prolongator()
+        return to_np(P), sig, to_np(mg.coarse_blocks())
+
+    def same(a, b):
+        return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+    full = qmg.mg_setup_stream_chiral_svd(lat, U, block, 16, r, k, **kw)
+    ref = state(full)
+    part = qmg.mg_setup_stream_chiral_svd(lat, U, block, 8, r, k, **kw)
+    assert part.streams_done == 2
+    path8 = tmp_path / "h8.qmg"
+    part.save(path8)
+    part.stream_more(2)
+    assert part.streams_done == 4 and part.params.n_test == 16
+    assert same(state(part), ref)
+    part.close()
+    # checkpoint of the full setup: identical state and solve
+    path = tmp_path / "h16.qmg"
+    full.save(path)
+    loaded = qmg.mg_load(path, U)
+    assert loaded.streams_done == 4 and loaded.rank == k and loaded.inner == inner
+    assert same(state(loaded), ref)
+    b = to_gpu(fields.gaussian_spinor(dims, 1, 32))
+    x1, i1 = qmg.mg_solve(full, b, tol=1e-10)
+    x2, i2 = qmg.mg_solve(loaded, b, tol=1e-10)
+    assert torch.equal(x1, x2)
+    for key in ("outer_iters", "coarse_iters", "smoother_iters", "refinements"):
+        assert i1[0][key] == i2[0][key]
+    loaded.close()
+    full.close()
+    # resume from the 8-vector checkpoint
+    resumed = qmg.mg_load(path8, U)
+    assert resumed.streams_done == 2
+    resumed.stream_more(2)
+    assert same(state(resumed), ref)
+    resumed.close()
+    # a different gauge field, and a corrupted file, are rejected
+    U2 = to_gpu(fields.random_gauge(dims, 0.3, 33))
+    with pytest.raises(qmg.QmgError, match="different gauge field"):
+        qmg.mg_load(path, U2)
+    raw = bytearray(path.read_bytes())
+    raw[-100] ^= 0xFF
+    bad = tmp_path / "bad.qmg"
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(qmg.QmgError, match="checksum"):
+        qmg.mg_load(bad, U)
+
+
 def test_setup_full_c1(c1):
     w, U, lat, mg, olat, oh = c1
     banner("setup c1 (philox + smoother + streaming svd)")
