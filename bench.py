@@ -9,7 +9,9 @@ coarse operator) followed by the MG-preconditioned solve of one Gaussian right-h
 
 Prints one JSON line.  `value` is the median mixed-precision solve time (s) over the timed
 steps; `roofline` describes the dominant kernel measured live with HIP events over the timed
-region; `cpu_baseline` is the CPU oracle timed on this host on a bounded sample.
+region; `cpu_baseline` is the CPU oracle timed on this host on a bounded sample; `dslash_hbm` is
+the dslash's algorithmic bandwidth on a 32^3 x 64 lattice (fields larger than the 256 MB
+last-level cache) at 1 and 12 right-hand sides.
 
 Counter runs: `bench.py --traffic-probe` runs a 256 MiB device copy (calibration) and then ten
 launches each of the solve's dslash and coarse apply in the solve's launch configuration; run it
@@ -66,6 +68,8 @@ def parse():
     ap.add_argument("--mass", type=float, default=None, help="override the workload's quark mass")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
+    ap.add_argument("--no-dslash-hbm", action="store_true",
+                    help="skip the dslash bandwidth measurement on the 32^3x64 lattice")
     ap.add_argument("--compare-setups", action="store_true",
                     help="Regular / CSVD / streaming (iCSVD) setups on the workload: iterations per level, "
                          "setup and solve seconds, leading singular values (prints a table and JSON lines)")
@@ -114,6 +118,51 @@ def traffic_probe(args):
     torch.cuda.synchronize()
     mg.close()
     print(json.dumps({"probe": w["name"], "dims": list(dims), "prec": prec}), flush=True)
+
+
+# dslash bandwidth on a lattice whose fields do not fit the 256 MB MALL (the workload's own
+# 16^3 x 32 fields do): 32^3 x 64, FP32 storage, the default launch form, 1 and 12 right-hand
+# sides.  Algorithmic bytes per site: (24 nrhs + 36) complex numbers of 8 bytes (spinor in and
+# out per rhs, four links).
+DSLASH_HBM_DIMS = (32, 32, 32, 64)
+
+
+def dslash_hbm():
+    import numpy as np
+    import torch
+
+    import paper_2505_14399_amd as q
+
+    lat = q.Lattice(DSLASH_HBM_DIMS, -0.2, 1.0, -1)
+    V = lat.volume
+    g = torch.Generator(device="cuda").manual_seed(7)
+    U = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
+    Un = q.pack_gauge(lat, U, "f32")
+    del U
+    out = {"lattice": list(DSLASH_HBM_DIMS), "prec": "f32", "launch": "default form", "per_rhs": {}}
+    for nrhs in (1, 12):
+        x = q.pack_spinor(lat, torch.randn(nrhs, V, 4, 3, dtype=torch.complex128, device="cuda", generator=g), "f32")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            q.wilson_apply(lat, Un, x, layout="native", out=y)
+        n, reps = (20 if nrhs == 1 else 6), []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for i in range(n):  # alternate the buffers so no application reads its own output
+                q.wilson_apply(lat, Un, x if i % 2 == 0 else y, layout="native", out=y if i % 2 == 0 else x)
+            e1.record()
+            torch.cuda.synchronize()
+            reps.append(e0.elapsed_time(e1) / n * 1e-3)
+        t = float(np.median(reps))
+        byt = V * (24.0 * nrhs + 36.0) * 8.0
+        out["per_rhs"][str(nrhs)] = {"us": t * 1e6, "algorithmic_MB": byt / 1e6, "GBps": byt / t / 1e9,
+                                     "frac_hbm": byt / t / 1e9 / PEAK_HBM_GBPS}
+        del x, y
+    del Un
+    torch.cuda.empty_cache()
+    return out
 
 
 # setup methods compared by --compare-setups: (name, n_test m, batch r); rank k from the workload.
@@ -428,6 +477,8 @@ def main():
                                for f in fams if fams[f]["launches"]},
         "roofline": roof,
     }
+    if not args.no_dslash_hbm:
+        res["dslash_hbm"] = dslash_hbm()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, cnt)
     print(json.dumps(res), flush=True)
