@@ -22,6 +22,9 @@ Modules
   coarse     Galerkin coarse operator (Eq. 5) as a 9-block stencil, coarse apply
   mg         test-vector smoothing (Eq. 2), setup (Algorithm 4), K-cycle, MG solve
   force      gradient of Re<eta, D^-1 b> w.r.t. b and the gauge links
+  level      the next coarser level of a coarse stencil (a third level): coarse test
+             vectors, chiral split by sigma3, Algorithm 3, coarse-coarse Galerkin operator,
+             three-level K-cycle solve
 
 Parity status: every function is pinned by a CPU test against a closed form,
 an invariant, a special case or brute force, except the MG iteration counts
