@@ -51,7 +51,8 @@ class qmg_solve_info(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("refinements", ctypes.c_int32),
                 ("coarse_iters", ctypes.c_int32), ("smoother_iters", ctypes.c_int32),
                 ("precision_escalations", ctypes.c_int32), ("true_rel_res", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("coarse2_iters", ctypes.c_int32),
+                ("smoother1_iters", ctypes.c_int32)]
 
 
 # exported symbols and their argument types (void* = device or host pointer, see qmg.h)
@@ -84,6 +85,12 @@ SIGNATURES = {
     "qmg_tune_save": [ctypes.c_char_p],
     "qmg_tune_load": [ctypes.c_char_p],
     "qmg_mg_stream_more": [_P, _I, _P],
+    "qmg_mg_add_level": [_P, _P, _I, _I, _I, _I, ctypes.c_uint64, _P],
+    "qmg_mg_level_query": [_P, _P, _P, _P],
+    "qmg_mg_level_get": [_P, _P, _P, _P, _P],
+    "qmg_level_prolong": [_P, _P, _P, _I, _I, _P],
+    "qmg_level_restrict": [_P, _P, _P, _I, _I, _P],
+    "qmg_level_coarse_apply": [_P, _P, _P, _I, _I, _P],
     "qmg_mg_save": [_P, ctypes.c_char_p, _P],
     "qmg_mg_load": [ctypes.c_char_p, _P, _P, _P],
     "qmg_mg_get_params": [_P, _P, _P],
@@ -320,6 +327,35 @@ class MG:
         _check(load_library().qmg_mg_stream_more(self._h, int(n_streams), _stream()))
         self._refresh()
 
+    def add_level(self, block, n_test, batch, rank, n_setup_iter=16, seed=None):
+        """Third level on D_c (qmg_mg_add_level); the solve then uses three levels."""
+        blk = (ctypes.c_int32 * 4)(*[int(b) for b in block])
+        seed = self.params.seed if seed is None else int(seed)
+        _check(load_library().qmg_mg_add_level(self._h, blk, int(n_test), int(batch), int(rank), int(n_setup_iter),
+                                               ctypes.c_uint64(seed), _stream()))
+        cd = (ctypes.c_int32 * 4)()
+        d = ctypes.c_int32()
+        k = ctypes.c_int32()
+        _check(load_library().qmg_mg_level_query(self._h, cd, ctypes.byref(d), ctypes.byref(k)))
+        self.level_dims, self.level_n_agg, self.level_rank = tuple(cd), d.value, k.value
+        self.level_block = tuple(int(b) for b in block)
+
+    def level_prolongator(self):
+        """(P2 [d2,2,N2,k2] complex128 on the GPU, rows site-in-block * k + i; sigma2 [d2,2,k2])."""
+        import numpy as np
+        N2 = self.rank * int(np.prod(self.level_block))
+        P = torch.empty((self.level_n_agg, 2, N2, self.level_rank), dtype=torch.complex128, device="cuda")
+        sig = np.empty((self.level_n_agg, 2, self.level_rank))
+        _check(load_library().qmg_mg_level_get(self._h, _ptr(P), sig.ctypes.data_as(ctypes.c_void_p), None,
+                                               _stream()))
+        return P, sig
+
+    def level_coarse_blocks(self):
+        m = 2 * self.level_rank
+        Y = torch.empty((self.level_n_agg, 9, m, m), dtype=torch.complex128, device="cuda")
+        _check(load_library().qmg_mg_level_get(self._h, None, None, _ptr(Y), _stream()))
+        return Y
+
     def save(self, path):
         """Write the hierarchy (parameters, singular values, P in FP64) to a file."""
         _check(load_library().qmg_mg_save(self._h, os.fsencode(str(path)), _stream()))
@@ -372,6 +408,31 @@ def mg_load(path, U) -> MG:
     _check(lib.qmg_mg_get_params(h, ctypes.byref(cl), ctypes.byref(p)))
     lat = Lattice(tuple(cl.dims), cl.mass, cl.xi, cl.bc_t)
     return MG(h, lat, p)
+
+
+def level_prolong(mg: MG, v2, out=None):
+    """v1 = P2 v2: v2 [nrhs,d2,2,k2] -> [nrhs,d,2,k] (complex128, or complex64 with FP32 inner)."""
+    nrhs = v2.shape[0]
+    out = torch.empty((nrhs, mg.n_agg, 2, mg.rank), dtype=v2.dtype, device=v2.device) if out is None else out
+    _check(load_library().qmg_level_prolong(mg.handle, _ptr(v2), _ptr(out), nrhs, _prec_of(v2), _stream()))
+    return out
+
+
+def level_restrict(mg: MG, v1, out=None):
+    """v2 = P2^dag v1: v1 [nrhs,d,2,k] -> [nrhs,d2,2,k2]."""
+    nrhs = v1.shape[0]
+    out = (torch.empty((nrhs, mg.level_n_agg, 2, mg.level_rank), dtype=v1.dtype, device=v1.device)
+           if out is None else out)
+    _check(load_library().qmg_level_restrict(mg.handle, _ptr(v1), _ptr(out), nrhs, _prec_of(v1), _stream()))
+    return out
+
+
+def level_coarse_apply(mg: MG, v2, out=None):
+    """D_cc v2 on third-level vectors [nrhs,d2,2,k2]."""
+    nrhs = v2.shape[0]
+    out = torch.empty_like(v2) if out is None else out
+    _check(load_library().qmg_level_coarse_apply(mg.handle, _ptr(v2), _ptr(out), nrhs, _prec_of(v2), _stream()))
+    return out
 
 
 def _coarse_prec(t):

@@ -95,6 +95,55 @@ struct CoarseOp : LinOp {
   qmg_prec prec() const override { return p; }
 };
 
+// the nine-block stencil of a further level
+struct StencilOp : LinOp {
+  int d, k;
+  const int* cnb;
+  qmg_prec p;
+  const void* Y;
+  StencilOp(int d_, int k_, const int* cnb_, qmg_prec p_, const void* Y_) : d(d_), k(k_), cnb(cnb_), p(p_), Y(Y_) {}
+  void apply(const void* in, void* out, int nrhs, hipStream_t st, const int* skip = nullptr) override {
+    launch_stencil_apply(p, d, k, cnb, Y, in, out, nrhs, st, skip);
+  }
+  size_t len() const override { return size_t(2) * k * d; }
+  qmg_prec prec() const override { return p; }
+};
+
+// K-cycle of the first coarse level when a third level exists (storage precision S): restrict
+// to the third level, GMRES(32) there to the coarse tolerance, prolong, GMRES post-smoothing on
+// D_c from the prolonged correction.
+template <class S>
+struct KCycleC : Precond {
+  const HierarchyDev& h;
+  const CoarseLevel& L;
+  CoarseOp& Dc;
+  StencilOp Dcc;
+  const void* P2;
+  Gmres<S> g2, gs;
+  DevBuf r2, e2;
+  long coarse_iters = 0, smooth_iters = 0;
+  int last = 0;
+  KCycleC(const HierarchyDev& h_, CoarseOp& Dc_)
+      : h(h_), L(*h_.l2), Dc(Dc_),
+        Dcc(h_.l2->d, h_.l2->k, h_.l2->cnb.as<int>(), StoreTraits<S>::prec,
+            StoreTraits<S>::prec == QMG_F64 ? h_.l2->Y64.p : h_.l2->Yin.p),
+        P2(StoreTraits<S>::prec == QMG_F64 ? h_.l2->P64.p : h_.l2->Pin.p) {}
+  void apply(const void* r1, void* z1, int nrhs, hipStream_t st) override {
+    constexpr qmg_prec p = StoreTraits<S>::prec;
+    const size_t n2 = size_t(nrhs) * 2 * L.k * L.d;
+    r2.ensure(n2 * sizeof(S));
+    e2.ensure(n2 * sizeof(S));
+    launch_level_restrict(p, L, h.blk.d, P2, r1, r2.p, nrhs, st);
+    const int hint = last > 1 ? last - 1 : 0;
+    auto res = g2.solve(Dcc, r2.p, e2.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st, nullptr, hint);
+    coarse_iters += res.iters;
+    last = res.iters;
+    launch_level_prolong(p, L, h.blk.d, P2, e2.p, z1, nrhs, st);
+    gs.solve(Dc, r1, z1, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    smooth_iters += h.n_post;
+  }
+};
+
 // Two-level K-cycle with storage precision S; r and z are in the outer solver's type F.
 // Eager form: restrict, coarse GMRES to the tolerance (the host reads its convergence
 // estimates every few steps), prolong, fixed-length GMRES post-smoothing.  With a coarse step
@@ -109,6 +158,7 @@ struct KCycle : Precond {
   const void* P;
   Gmres<S> gc, gf;
   DevBuf rc, ec, rS, zS, conv;
+  std::unique_ptr<KCycleC<S>> Kc;  // level-one K-cycle when a third level exists
   long coarse_iters = 0, smooth_iters = 0, cycles = 0;
   int last_coarse = 0;             // coarse steps of the previous cycle (host-checked form)
   hipStream_t gs = nullptr;        // private stream of the captured cycle
@@ -126,7 +176,14 @@ struct KCycle : Precond {
   void body(const void* r_s, void* z_s, int nrhs, hipStream_t st) {
     constexpr qmg_prec p = StoreTraits<S>::prec;
     launch_restrict(p, h, P, r_s, rc.p, nrhs, st);
-    if (h.cycle_steps > 0) {
+    if (h.l2) {
+      // three levels: flexible GMRES(32) on D_c preconditioned by the level-one K-cycle
+      if (!Kc) Kc.reset(new KCycleC<S>(h, Dc));
+      const int hint = last_coarse > 1 ? last_coarse - 1 : 0;
+      auto rcs = gc.solve(Dc, rc.p, ec.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st, nullptr, hint, Kc.get());
+      coarse_iters += rcs.iters;
+      last_coarse = rcs.iters;
+    } else if (h.cycle_steps > 0) {
       gc.solve(Dc, rc.p, ec.p, true, nrhs, h.cycle_steps, h.cycle_steps, h.coarse_tol, st, conv.as<int>());
     } else {
       // first read of the convergence estimates one step before the previous cycle's count
@@ -415,7 +472,16 @@ void run_setup(qmg_mg* mg, hipStream_t st) {
 // ---------------------------------------------------------------------------------------
 // solve
 struct SolveStats {
-  long outer = 0, refinements = 0, coarse = 0, smooth = 0, escalations = 0;
+  long outer = 0, refinements = 0, coarse = 0, smooth = 0, escalations = 0, coarse2 = 0, smooth1 = 0;
+  template <class K>
+  void add_cycle(const K& k) {
+    coarse += k.coarse_iters;
+    smooth += k.smooth_iters;
+    if (k.Kc) {
+      coarse2 += k.Kc->coarse_iters;
+      smooth1 += k.Kc->smooth_iters;
+    }
+  }
 };
 
 // FP64 flexible GMRES(16) with the FP64 K-cycle, in place on native x64
@@ -428,8 +494,7 @@ void solve_f64(const HierarchyDev& h, const void* b64, void* x64, int nrhs, doub
   auto res = f.solve(D, b64, x64, x_zero, nrhs, 16, max_iter, tol, st, nullptr, 0, &K);
   K.finish(st);
   ss.outer += res.iters;
-  ss.coarse += K.coarse_iters;
-  ss.smooth += K.smooth_iters;
+  ss.add_cycle(K);
   ss.refinements += 1;
   converged = res.converged;
 }
@@ -466,8 +531,7 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
         K.finish(st);
       } catch (...) {
       }
-      ss.coarse += K.coarse_iters;
-      ss.smooth += K.smooth_iters;
+      ss.add_cycle(K);
     }
   } acc{ss, K, st};
   for (int ref = 0; ref < 40 && ss.outer < max_outer; ++ref) {
@@ -712,6 +776,107 @@ std::unique_ptr<qmg_mg> new_hierarchy(const qmg_lattice* lat, const void* U, con
 }
 
 // ---------------------------------------------------------------------------------------
+// Third level: Algorithm 4 with Algorithm 3 applied to D_c.  Tables on the coarse lattice,
+// streams of coarse test vectors (Philox, level word 1) smoothed in FP64 on D_c, the chiral
+// split by the coarse chirality (the alpha block of every coarse site), the streaming SVD per
+// (aggregate, chirality), the Galerkin stencil and the inner-precision copies.
+void build_level_tables(CoarseLevel& L, const HierarchyDev& h) {
+  const int* cL1 = h.blk.cL;
+  const int d1 = h.blk.d;
+  std::vector<int> bsite(size_t(L.d) * L.nd), cnb(size_t(L.d) * 8), agg(d1), pos(d1);
+  for (int j = 0; j < d1; ++j) {
+    int c[4], rem = j;
+    for (int q = 0; q < 4; ++q) {
+      c[q] = rem % cL1[q];
+      rem /= cL1[q];
+    }
+    int cj[4], ci[4];
+    for (int q = 0; q < 4; ++q) {
+      cj[q] = c[q] / L.b[q];
+      ci[q] = c[q] % L.b[q];
+    }
+    const int J = cj[0] + L.cL[0] * (cj[1] + L.cL[1] * (cj[2] + L.cL[2] * cj[3]));
+    const int jb = ci[0] + L.b[0] * (ci[1] + L.b[1] * (ci[2] + L.b[2] * ci[3]));
+    bsite[size_t(J) * L.nd + jb] = j;
+    agg[j] = J;
+    pos[j] = jb;
+  }
+  for (int J = 0; J < L.d; ++J) {
+    int c[4], rem = J;
+    for (int q = 0; q < 4; ++q) {
+      c[q] = rem % L.cL[q];
+      rem /= L.cL[q];
+    }
+    for (int dir = 0; dir < 8; ++dir) {
+      const int mu = dir & 3, step = dir < 4 ? 1 : -1;
+      int cc[4] = {c[0], c[1], c[2], c[3]};
+      cc[mu] = (cc[mu] + step + L.cL[mu]) % L.cL[mu];
+      cnb[size_t(J) * 8 + dir] = cc[0] + L.cL[0] * (cc[1] + L.cL[1] * (cc[2] + L.cL[2] * cc[3]));
+    }
+  }
+  auto up = [](DevBuf& b, const std::vector<int>& v) {
+    b.alloc(v.size() * sizeof(int));
+    QMG_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
+  };
+  up(L.bsite, bsite);
+  up(L.cnb, cnb);
+  up(L.agg, agg);
+  up(L.pos, pos);
+}
+
+void run_level_setup(HierarchyDev& h, hipStream_t st) {
+  CoarseLevel& L = *h.l2;
+  const auto t0 = Clock::now();
+  const int d1 = h.blk.d, m1 = 2 * h.k, r = L.batch, ns = L.n_test / L.batch;
+  const size_t len = size_t(d1) * m1, n = size_t(r) * len;
+  CoarseOp Dc(h, QMG_F64, h.Y64.p);
+  Gmres<double2> gm;
+  DevBuf phi(n * sizeof(double2)), b(n * sizeof(double2)), x(n * sizeof(double2)), nrm(r * sizeof(double));
+  DevBuf blocks(size_t(2) * L.d * r * L.N * sizeof(double2));
+  RedWork rw;
+  L.P64.alloc(size_t(2) * L.d * L.k * L.N * sizeof(double2));
+  L.sigma_dev.alloc(size_t(2) * L.d * L.k * sizeof(double));
+  L.kp = 0;
+  for (int s = 0; s < ns; ++s) {
+    launch_philox_coarse(L.seed, s * r, r, d1, m1, 1, phi.p, st);
+    if (L.n_setup_iter > 0) {  // psi = phi + psi', D_c psi' = -D_c phi by GMRES(8) from zero
+      Dc.apply(phi.p, b.p, r, st);
+      Blas<double2>::axpby(0.0, b.p, -1.0, b.p, n, st);
+      gm.solve(Dc, b.p, x.p, true, r, 8, L.n_setup_iter, 0.0, st);
+      Blas<double2>::axpby(1.0, x.p, 1.0, phi.p, n, st);
+    }
+    Blas<double2>::norm2(phi.p, len, r, nrm.as<double>(), rw, st);
+    Blas<double2>::scale_dev(phi.p, nrm.as<double>(), 0, len, r, st);
+    launch_level_gather(L, phi.p, blocks.p, r, st);
+    L.kp = isvd_stream(2 * L.d, L.N, L.k, L.P64, blocks.p, r, L.kp, L.sigma_dev, st);
+    L.streams_done = s + 1;
+  }
+  QMG_CHECK(L.kp == L.k, QMG_ESHAPE, "third level: streaming SVD ended with %d < k columns", L.kp);
+  build_level_coarse(L, h, st);
+  if (h.inner != QMG_F64) {
+    const int m2 = 2 * L.k;
+    const size_t np = size_t(2) * L.d * L.k * L.N, ny = size_t(L.d) * 9 * m2 * m2;
+    L.Pin.alloc(np * prec_bytes(h.inner));
+    L.Yin.alloc(ny * prec_bytes(h.inner));
+    launch_convert(L.P64.p, QMG_F64, L.Pin.p, h.inner, np, st);
+    launch_convert(L.Y64.p, QMG_F64, L.Yin.p, h.inner, ny, st);
+  }
+  L.sigma.resize(size_t(2) * L.d * L.k);
+  QMG_HIP(hipMemcpyAsync(L.sigma.data(), L.sigma_dev.p, L.sigma.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         st));
+  QMG_HIP(hipStreamSynchronize(st));
+  L.t_total = secs(t0, Clock::now());
+}
+
+const CoarseLevel& level_for(const qmg_mg* mg, qmg_prec prec) {
+  check_ptr(mg, "mg");
+  QMG_CHECK(mg->h.l2, QMG_EINVAL, "the hierarchy has no third level");
+  QMG_CHECK(prec == QMG_F64 || (prec == mg->h.inner && prec == QMG_F32), QMG_EDTYPE,
+            "precision must be F64 or the F32 inner precision");
+  return *mg->h.l2;
+}
+
+// ---------------------------------------------------------------------------------------
 // checkpoint file: fixed little-endian fields, then Sigma and U_k (P in FP64), then a hash of
 // both arrays.  The gauge field is not stored: its hash ties the file to the field it was built
 // for, and the Galerkin operator is rebuilt from P and the field on load.
@@ -866,6 +1031,108 @@ qmg_status qmg_mg_stream_more(qmg_mg* mg, int32_t n_streams, hipStream_t stream)
     mg->params.n_test = mg->streams_done * mg->params.batch;
     finish_setup(mg, stream);
     h.t_total += secs(t0, Clock::now());
+  });
+}
+
+qmg_status qmg_mg_add_level(qmg_mg* mg, const int32_t* block, int32_t n_test, int32_t batch, int32_t rank,
+                            int32_t n_setup_iter, uint64_t seed, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(block, "block");
+    HierarchyDev& h = mg->h;
+    QMG_CHECK(!h.l2, QMG_EINVAL, "the hierarchy already has a third level");
+    QMG_CHECK(h.cycle_steps == 0, QMG_EINVAL, "a third level needs the host-checked K-cycle (coarse_steps = 0)");
+    std::unique_ptr<CoarseLevel> L(new CoarseLevel());
+    L->nd = 1;
+    L->d = 1;
+    for (int q = 0; q < 4; ++q) {
+      QMG_CHECK(block[q] >= 1 && h.blk.cL[q] % block[q] == 0, QMG_ESHAPE,
+                "third-level block extent %d (%d) does not divide coarse extent %d", q, block[q], h.blk.cL[q]);
+      L->b[q] = block[q];
+      L->cL[q] = h.blk.cL[q] / block[q];
+      L->nd *= block[q];
+      L->d *= L->cL[q];
+    }
+    L->k1 = h.k;
+    L->N = L->nd * h.k;
+    QMG_CHECK(L->N <= 4096, QMG_ESHAPE, "third level: block of %d rows exceeds 4096", L->N);
+    QMG_CHECK(batch >= 1 && batch <= 48, QMG_ESHAPE, "batch r must be in [1, 48]");
+    QMG_CHECK(n_test >= batch && n_test % batch == 0, QMG_ESHAPE, "n_test must be a positive multiple of batch");
+    QMG_CHECK(rank >= 1 && rank <= L->N && rank <= n_test && rank <= 32, QMG_ESHAPE,
+              "rank k must satisfy 1 <= k <= min(k1 * prod(block), n_test, 32)");
+    QMG_CHECK(n_setup_iter >= 0, QMG_EINVAL, "n_setup_iter must be non-negative");
+    L->k = rank;
+    L->n_test = n_test;
+    L->batch = batch;
+    L->n_setup_iter = n_setup_iter;
+    L->seed = seed;
+    build_level_tables(*L, h);
+    h.l2 = std::move(L);
+    try {
+      run_level_setup(h, stream);
+    } catch (...) {
+      h.l2.reset();
+      throw;
+    }
+  });
+}
+
+qmg_status qmg_mg_level_query(const qmg_mg* mg, int32_t* coarse_dims, int32_t* n_agg, int32_t* rank) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    QMG_CHECK(mg->h.l2, QMG_EINVAL, "the hierarchy has no third level");
+    const CoarseLevel& L = *mg->h.l2;
+    if (coarse_dims)
+      for (int q = 0; q < 4; ++q) coarse_dims[q] = L.cL[q];
+    if (n_agg) *n_agg = L.d;
+    if (rank) *rank = L.k;
+  });
+}
+
+qmg_status qmg_mg_level_get(const qmg_mg* mg, void* P, double* sigma, void* Y, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    QMG_CHECK(mg->h.l2, QMG_EINVAL, "the hierarchy has no third level");
+    const CoarseLevel& L = *mg->h.l2;
+    if (P) launch_level_export_P(L, P, stream);
+    if (Y) launch_level_export_Y(L, Y, stream);
+    if (sigma) std::memcpy(sigma, L.sigma.data(), L.sigma.size() * sizeof(double));
+    QMG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+qmg_status qmg_level_prolong(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
+                             hipStream_t stream) {
+  return guard([&] {
+    const CoarseLevel& L = level_for(mg, prec);
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    launch_level_prolong(prec, L, mg->h.blk.d, prec == QMG_F64 ? L.P64.p : L.Pin.p, in, out, nrhs, stream);
+  });
+}
+
+qmg_status qmg_level_restrict(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
+                              hipStream_t stream) {
+  return guard([&] {
+    const CoarseLevel& L = level_for(mg, prec);
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    launch_level_restrict(prec, L, mg->h.blk.d, prec == QMG_F64 ? L.P64.p : L.Pin.p, in, out, nrhs, stream);
+  });
+}
+
+qmg_status qmg_level_coarse_apply(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
+                                  hipStream_t stream) {
+  return guard([&] {
+    const CoarseLevel& L = level_for(mg, prec);
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(in != out, QMG_EINVAL, "in and out must not alias");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    launch_stencil_apply(prec, L.d, L.k, L.cnb.as<int>(), prec == QMG_F64 ? L.Y64.p : L.Yin.p, in, out, nrhs,
+                         stream);
   });
 }
 
@@ -1074,6 +1341,8 @@ qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, 
       info[i].precision_escalations = int(ss.escalations);
       info[i].true_rel_res = i < int(rel.size()) ? rel[i] : tr;
       info[i].seconds = el;
+      info[i].coarse2_iters = int(ss.coarse2);
+      info[i].smoother1_iters = int(ss.smooth1);
     }
   }
   return rc;
@@ -1197,6 +1466,8 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph) {
     QMG_CHECK(coarse_steps >= 0 && coarse_steps <= 63, QMG_EINVAL, "coarse_steps must be in [0, 63]");
     QMG_CHECK(graph == 0 || graph == 1, QMG_EINVAL, "graph must be 0 or 1");
     QMG_CHECK(!graph || coarse_steps > 0, QMG_EINVAL, "a captured K-cycle needs coarse_steps > 0");
+    QMG_CHECK(coarse_steps == 0 || !mg->h.l2, QMG_EINVAL,
+              "with a third level the K-cycle is host-checked (coarse_steps must be 0)");
     mg->h.cycle_steps = coarse_steps;
     mg->h.cycle_graph = graph != 0;
   });

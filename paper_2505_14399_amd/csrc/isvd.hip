@@ -476,7 +476,7 @@ void set_lds(const void* f, size_t lds) {
 }
 
 template <int NPF>
-void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, HierarchyDev& h, const void* blocks,
+void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, DevBuf& P64, const void* blocks,
                  DevBuf& small, DevBuf& AB, DevBuf& sigma_dev, size_t ls, hipStream_t st) {
   set_lds((const void*)k_isvd_small, ls);
   set_lds((const void*)k_isvd_rotate<NPF>, lr);
@@ -484,21 +484,21 @@ void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, HierarchyDev&
   const int ntile = ((a.w + 1) / 2) * ((a.r + 1) / 2);
   if (ntile <= T) {
     set_lds((const void*)k_isvd_gram<NPF, 1>, lg);
-    k_isvd_gram<NPF, 1><<<grid, T, lg, st>>>(h.P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+    k_isvd_gram<NPF, 1><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
   } else {
     set_lds((const void*)k_isvd_gram<NPF, 4>, lg);
-    k_isvd_gram<NPF, 4><<<grid, T, lg, st>>>(h.P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+    k_isvd_gram<NPF, 4><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
   }
   QMG_LAUNCH_CHECK();
   k_isvd_small<<<a.nprob, TW, ls, st>>>(small.as<double2>(), sigma_dev.as<double>(), AB.as<double2>(), a);
   QMG_LAUNCH_CHECK();
   const dim3 rgrid((a.N + T - 1) / T, a.nprob);
   if (a.w <= 32) {
-    k_isvd_rotate_rows<32><<<rgrid, T, 0, st>>>(h.P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+    k_isvd_rotate_rows<32><<<rgrid, T, 0, st>>>(P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
   } else if (a.w <= 48) {
-    k_isvd_rotate_rows<48><<<rgrid, T, 0, st>>>(h.P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+    k_isvd_rotate_rows<48><<<rgrid, T, 0, st>>>(P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
   } else {
-    k_isvd_rotate<NPF><<<grid, T, lr, st>>>(h.P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+    k_isvd_rotate<NPF><<<grid, T, lr, st>>>(P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
   }
   QMG_LAUNCH_CHECK();
 }
@@ -506,15 +506,20 @@ void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, HierarchyDev&
 }  // namespace
 
 int isvd_stream(HierarchyDev& h, const void* blocks, int r, int kp, DevBuf& sigma_dev, hipStream_t st) {
+  return isvd_stream(2 * h.blk.d, h.blk.N, h.k, h.P64, blocks, r, kp, sigma_dev, st);
+}
+
+int isvd_stream(int nprob, int N, int k, DevBuf& P64, const void* blocks, int r, int kp, DevBuf& sigma_dev,
+                hipStream_t st) {
   const int w = kp + r;
-  const int kn = std::min(h.k, w);
+  const int kn = std::min(k, w);
   QMG_CHECK(r >= 1 && w <= MAXW, QMG_ESHAPE, "streaming SVD: k + r = %d exceeds %d", w, MAXW);
   QMG_CHECK(((w + 1) / 2) * ((r + 1) / 2) <= 4 * T, QMG_ESHAPE,
             "streaming SVD: ceil((k+r)/2) * ceil(r/2) = %d exceeds %d", ((w + 1) / 2) * ((r + 1) / 2), 4 * T);
   const size_t lg = gram_lds(kp, r), ls = small_lds(kp, r), lr = rotate_lds(kp, r, kn);
   QMG_CHECK(lg <= 160 * 1024 && ls <= 160 * 1024 && lr <= 160 * 1024, QMG_ESHAPE,
             "streaming SVD: k + r = %d needs more than 160 KiB of LDS", w);
-  IsvdArgs a{2 * h.blk.d, h.blk.N, h.k, r, kp, w, kn};
+  IsvdArgs a{nprob, N, k, r, kp, w, kn};
   int dev = 0, ncu = 256;
   QMG_HIP(hipGetDevice(&dev));
   QMG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -527,9 +532,9 @@ int isvd_stream(HierarchyDev& h, const void* blocks, int r, int kp, DevBuf& sigm
     TimedLaunch tl("isvd", st, Nn * 16.0 * (3.0 * (kp + r) + kn),
                    Nn * 8.0 * (2.0 * double(w) * r + double(kp) * r + double(w) * kn), false);
     const int need = (w * CH + T - 1) / T;  // prefetch registers needed
-    if (need <= 4) launch_rows<4>(a, ncu, lg, lr, h, blocks, small, AB, sigma_dev, ls, st);
-    else if (need <= 8) launch_rows<8>(a, ncu, lg, lr, h, blocks, small, AB, sigma_dev, ls, st);
-    else launch_rows<PF>(a, ncu, lg, lr, h, blocks, small, AB, sigma_dev, ls, st);
+    if (need <= 4) launch_rows<4>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
+    else if (need <= 8) launch_rows<8>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
+    else launch_rows<PF>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
   }
   QMG_HIP(hipStreamSynchronize(st));  // scratch buffers are released on return
   return kn;

@@ -1,6 +1,8 @@
 // The two-level hierarchy owned by a qmg_mg handle, and the kernels that act on it.
 #pragma once
 
+#include <memory>
+
 #include "krylov.hpp"
 
 namespace qmg {
@@ -10,6 +12,25 @@ namespace qmg {
 //   cnb   [d][8]    coarse neighbour of aggregate j in direction dir
 // P row order inside (j, alpha): row = s6 * nd + ib with s6 = 3 * spin_in_chirality + colour;
 // this component-major order lets consecutive threads read consecutive P entries.
+
+// A further level built on the coarse stencil of the level above (Algorithm 4 applied to D_c):
+// sites J of the lattice cL, each a block b of nd sites of the level above (k1 degrees of
+// freedom per chirality there).  Rows of a (J, alpha) block: row = i * nd + jb (i < k1 the dof
+// index inside chirality alpha, jb the site in the block), N = nd * k1.
+struct CoarseLevel {
+  int cL[4] = {1, 1, 1, 1}, b[4] = {1, 1, 1, 1};
+  int nd = 1, d = 1, N = 0, k = 0, k1 = 0;
+  DevBuf bsite, cnb;         // [d][nd] site of the level above; [d][8] neighbours on cL
+  DevBuf agg, pos;           // [d1] aggregate J and in-block index jb of every site above
+  DevBuf P64, Pin;           // [d][2][k][N]
+  DevBuf Y64, Yin;           // [d][9][2k][2k] column-major blocks
+  DevBuf sigma_dev;          // [d][2][k]
+  std::vector<double> sigma;
+  int n_test = 0, batch = 0, n_setup_iter = 0, streams_done = 0, kp = 0;
+  uint64_t seed = 0;
+  double t_total = 0;
+};
+
 struct HierarchyDev {
   Geom g;
   Blocking blk;
@@ -28,6 +49,7 @@ struct HierarchyDev {
   double coarse_tol = 0.03;
   int cycle_steps = 0;       // > 0: device-exit coarse solve with this step budget
   bool cycle_graph = false;  // capture the K-cycle into a hipGraph (needs cycle_steps > 0)
+  std::unique_ptr<CoarseLevel> l2;  // optional third level
 };
 
 // prolong: fine[rhs] (native, storage S) = P coarse[rhs]
@@ -39,6 +61,23 @@ void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const 
 // out = D_c in, coarse vectors [nrhs][d][2k]
 void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, const void* in, void* out, int nrhs,
                          hipStream_t st, const int* skip = nullptr);  // skip: device early-exit flag
+// the same for any nine-block stencil: d sites, 2k dof per site, neighbour table cnb [d][8]
+void launch_stencil_apply(qmg_prec prec, int d, int k, const int* cnb, const void* Y, const void* in, void* out,
+                          int nrhs, hipStream_t st, const int* skip = nullptr);
+// third level: Philox coarse test vectors [n][d][m] FP64 (counter (j, g, v0 + n, level))
+void launch_philox_coarse(uint64_t seed, int v0, int n, int d, int m, int level, void* out, hipStream_t st);
+// chiral split of r coarse vectors [r][d1][2k1] FP64 into blocks [2d][r][N] FP64
+void launch_level_gather(const CoarseLevel& L, const void* v, void* blocks, int r, hipStream_t st);
+// v1 [nrhs][d1][2k1] = P2 v2 [nrhs][d][2k]; v2 = P2^dag v1 (storage precision prec)
+void launch_level_prolong(qmg_prec prec, const CoarseLevel& L, int d1, const void* P, const void* v2, void* v1,
+                          int nrhs, hipStream_t st);
+void launch_level_restrict(qmg_prec prec, const CoarseLevel& L, int d1, const void* P, const void* v1, void* v2,
+                           int nrhs, hipStream_t st);
+// Y2 = P2^dag D_c P2 in FP64 from the level above (its Y64, cnb and coarse extents)
+void build_level_coarse(CoarseLevel& L, const HierarchyDev& h, hipStream_t st);
+// canonical exports of the third level: P [d][2][N][k] with rows (jb * k1 + i), Y [d][9][2k][2k]
+void launch_level_export_P(const CoarseLevel& L, void* out, hipStream_t st);
+void launch_level_export_Y(const CoarseLevel& L, void* out, hipStream_t st);
 // Galerkin build in FP64 from U64 and P64 into Y64 (needs a workspace of 8 * d * (2k)^2 double2)
 void build_coarse(HierarchyDev& h, hipStream_t st);
 // chiral split + block gather: fine FP64 native [r][12][V] -> blocks [2d][r][N] FP64
@@ -46,6 +85,9 @@ void launch_chiral_gather(const HierarchyDev& h, const void* fine, void* blocks,
 // one streaming-SVD stream for all (aggregate, chirality) problems, in place on P64 / sigma
 // kp: current columns (0 on the first stream), returns the new column count
 int isvd_stream(HierarchyDev& h, const void* blocks, int r, int kp, DevBuf& sigma_dev, hipStream_t st);
+// the same for nprob problems of N rows and rank k with the factor U in P64
+int isvd_stream(int nprob, int N, int k, DevBuf& P64, const void* blocks, int r, int kp, DevBuf& sigma_dev,
+                hipStream_t st);
 // canonical P export [d][2][N][k] with canonical row order 6*ib + 3*sp + c
 void launch_export_P(const HierarchyDev& h, void* out, hipStream_t st);
 // canonical Y export [d][9][2k row][2k col]

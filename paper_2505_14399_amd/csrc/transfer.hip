@@ -616,6 +616,199 @@ __global__ void k_convert(const Si* __restrict__ in, So* __restrict__ out, size_
   stc(out, g, v);
 }
 
+// ---------------------------------------------------------------------------------------
+// Third level (Algorithm 4 applied to the coarse stencil D_c)
+
+// coarse test vectors [n][d][m] FP64: Philox counter (j, g, v, level), components 2g, 2g + 1
+__global__ void k_philox_coarse(double2* __restrict__ out, uint64_t seed, int v0, int d, int m, int level) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int vi = blockIdx.y;
+  if (j >= d) return;
+  const uint32_t k0 = uint32_t(seed & 0xffffffffu), k1 = uint32_t(seed >> 32);
+  const double twopi = 2.0 * M_PI;
+  for (int g = 0; g < m / 2; ++g) {
+    uint32_t c[4] = {uint32_t(j), uint32_t(g), uint32_t(v0 + vi), uint32_t(level)};
+    philox4x32_10(c, k0, k1);
+    double u[4];
+    for (int q = 0; q < 4; ++q) u[q] = (double(c[q]) + 0.5) * 0x1p-32;
+    const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    const double t0 = twopi * u[1], t1 = twopi * u[3];
+    double2* o = out + (size_t(vi) * d + j) * m;
+    o[2 * g] = make_double2(r0 * cos(t0), r0 * sin(t0));
+    o[2 * g + 1] = make_double2(r1 * cos(t1), r1 * sin(t1));
+  }
+}
+
+// chiral split + block gather of coarse vectors: blocks[(2J + alpha) * r + v][row], row = i * nd + jb,
+// from v[v][j][alpha * k1 + i] with j = bsite[J][jb]
+__global__ void k_level_gather(const double2* __restrict__ v, double2* __restrict__ blocks,
+                               const int* __restrict__ bsite, int nd, int k1, int d1, int r) {
+  const int N = nd * k1;
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int vi = blockIdx.y, ja = blockIdx.z;  // ja = 2J + alpha
+  if (row >= N) return;
+  const int J = ja >> 1, a = ja & 1;
+  const int i = row / nd, jb = row - i * nd;
+  const int j = bsite[J * nd + jb];
+  blocks[(size_t(ja) * r + vi) * N + row] = v[(size_t(vi) * d1 + j) * (2 * k1) + a * k1 + i];
+}
+
+// v1[rhs][j][alpha k1 + i] = sum_l P[(2J + alpha) k + l][row] v2[rhs][J][alpha k + l]
+template <class S>
+__global__ __launch_bounds__(256) void k_level_prolong(const S* __restrict__ P, const S* __restrict__ v2,
+                                                       S* __restrict__ v1, const int* __restrict__ bsite, int nd,
+                                                       int k1, int k, int d1, int d) {
+  using C = ctype<S>;
+  const int N = nd * k1;
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int ja = blockIdx.y, rhs = blockIdx.z;
+  if (row >= N) return;
+  const int J = ja >> 1, a = ja & 1;
+  const S* Pc = P + size_t(ja) * k * N;
+  const S* c = v2 + (size_t(rhs) * d + J) * (2 * k) + a * k;
+  cplx<C> acc = {C(0), C(0)};
+  for (int l = 0; l < k; ++l) acc += ldc(Pc, size_t(l) * N + row) * ldc(c, l);
+  const int i = row / nd, jb = row - i * nd;
+  const int j = bsite[J * nd + jb];
+  stc(v1, (size_t(rhs) * d1 + j) * (2 * k1) + a * k1 + i, acc);
+}
+
+// v2[rhs][J][alpha k + l] = sum_row conj(P[(2J + alpha) k + l][row]) v1[rhs][j(row)][alpha k1 + i(row)]
+// one workgroup per (J, alpha, rhs): the block's N entries of v1 staged in LDS, one wavefront per l
+template <class S>
+__global__ __launch_bounds__(256) void k_level_restrict(const S* __restrict__ P, const S* __restrict__ v1,
+                                                        S* __restrict__ v2, const int* __restrict__ bsite, int nd,
+                                                        int k1, int k, int d1, int d) {
+  using C = ctype<S>;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<C>* vb = reinterpret_cast<cplx<C>*>(smem_raw);  // [N]
+  const int N = nd * k1;
+  const int ja = blockIdx.x, rhs = blockIdx.y;
+  const int J = ja >> 1, a = ja & 1;
+  for (int row = threadIdx.x; row < N; row += blockDim.x) {
+    const int i = row / nd, jb = row - i * nd;
+    const int j = bsite[J * nd + jb];
+    vb[row] = ldc(v1, (size_t(rhs) * d1 + j) * (2 * k1) + a * k1 + i);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const S* Pc = P + size_t(ja) * k * N;
+  for (int l = w; l < k; l += nw) {
+    double sr = 0.0, si = 0.0;
+    for (int row = lane; row < N; row += 64) {
+      const cplx<C> p = ldc(Pc, size_t(l) * N + row), x = vb[row];
+      sr += double(p.re) * double(x.re) + double(p.im) * double(x.im);
+      si += double(p.re) * double(x.im) - double(p.im) * double(x.re);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      sr += __shfl_xor(sr, off, 64);
+      si += __shfl_xor(si, off, 64);
+    }
+    if (lane == 0) stc(v2, (size_t(rhs) * d + J) * (2 * k) + a * k + l, cplx<double>{sr, si});
+  }
+}
+
+// Y2[J][slot] = sum over the (site jb, term dir1) pairs of this slot of R(j)^dag Y1_dir1(j) R(t),
+// R(x)[(alpha, i), (alpha, l)] = P[(2 J(x) + alpha) k + l][i nd + jb(x)] (block diagonal in alpha).
+// Workgroup (J, slot): slot 0 takes the self terms and the hops that stay inside the block, slot
+// 1 + dir the hops in direction dir that leave it through its face.  T = Y1 R(t) is staged in
+// LDS, then every thread adds its entries of R(j)^dag T.  FP64.
+struct LevelBuildArgs {
+  int cL1[4], b[4];
+  int nd, k1, k, d1, d;
+};
+
+__global__ __launch_bounds__(256) void k_level_build(const double2* __restrict__ Y1, const int* __restrict__ cnb1,
+                                                     const double2* __restrict__ P, const int* __restrict__ bsite,
+                                                     const int* __restrict__ agg, const int* __restrict__ pos,
+                                                     double2* __restrict__ Y2, LevelBuildArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  const int m1 = 2 * a.k1, m2 = 2 * a.k, N = a.nd * a.k1;
+  cplx<double>* T = reinterpret_cast<cplx<double>*>(smem_raw);  // [m1][m2] column-major (row (beta, i'))
+  cplx<double>* Rj = T + size_t(m1) * m2;                        // [2][k][k1]: conj P rows of site j
+  cplx<double>* Rt = Rj + size_t(2) * a.k * a.k1;                // [2][k][k1]: P rows of site t
+  const int J = blockIdx.x, slot = blockIdx.y;
+  constexpr int MAXE = 16;  // (2k)^2 / 256 entries per thread, 2k <= 64
+  cplx<double> acc[MAXE];
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) acc[q] = {0.0, 0.0};
+  const int ne = m2 * m2;
+  for (int jb = 0; jb < a.nd; ++jb) {
+    const int j = bsite[J * a.nd + jb];
+    int c[4], rem = j;
+    for (int q = 0; q < 4; ++q) {
+      c[q] = rem % a.cL1[q];
+      rem /= a.cL1[q];
+    }
+    for (int dir1 = 0; dir1 < 9; ++dir1) {
+      int target;  // slot this term belongs to
+      if (dir1 == 0) {
+        target = 0;
+      } else {
+        const int dd = dir1 - 1, mu = dd & 3;
+        const bool face = dd < 4 ? (c[mu] % a.b[mu] == a.b[mu] - 1) : (c[mu] % a.b[mu] == 0);
+        target = face ? dir1 : 0;
+      }
+      if (target != slot) continue;
+      const int t = dir1 == 0 ? j : cnb1[j * 8 + dir1 - 1];
+      const int Jt = agg[t], jbt = pos[t];
+      __syncthreads();  // the previous pair is done with T, Rj, Rt
+      for (int e = threadIdx.x; e < 2 * a.k * a.k1; e += blockDim.x) {
+        const int al = e / (a.k * a.k1), rem2 = e - al * a.k * a.k1, l = rem2 / a.k1, i = rem2 - l * a.k1;
+        const double2 pj = P[(size_t(2 * J + al) * a.k + l) * N + i * a.nd + jb];
+        const double2 pt = P[(size_t(2 * Jt + al) * a.k + l) * N + i * a.nd + jbt];
+        Rj[e] = {pj.x, -pj.y};
+        Rt[e] = {pt.x, pt.y};
+      }
+      __syncthreads();
+      // T[(beta, i'), (alpha, l)] = sum_i Y1[(beta, i'), (alpha, i)] Rt[alpha][l][i]
+      const double2* Yb = Y1 + (size_t(j) * 9 + dir1) * m1 * m1;  // column-major
+      for (int e = threadIdx.x; e < m1 * m2; e += blockDim.x) {
+        const int col = e / m1, row = e - col * m1;  // col = (alpha, l), row = (beta, i')
+        const int al = col / a.k, l = col - al * a.k;
+        cplx<double> v = {0.0, 0.0};
+        for (int i = 0; i < a.k1; ++i) {
+          const double2 y = Yb[size_t(al * a.k1 + i) * m1 + row];
+          v += cplx<double>{y.x, y.y} * Rt[(al * a.k + l) * a.k1 + i];
+        }
+        T[e] = v;
+      }
+      __syncthreads();
+      // acc[(beta, l'), (alpha, l)] += sum_i' Rj[beta][l'][i'] T[(beta, i'), (alpha, l)]
+#pragma unroll
+      for (int q = 0; q < MAXE; ++q) {
+        const int e = threadIdx.x + q * 256;
+        if (e < ne) {
+          const int col = e / m2, row = e - col * m2;  // row = (beta, l'), col = (alpha, l)
+          const int be = row / a.k, lp = row - be * a.k;
+          cplx<double> v = {0.0, 0.0};
+          for (int ip = 0; ip < a.k1; ++ip) v += Rj[(be * a.k + lp) * a.k1 + ip] * T[size_t(col) * m1 + be * a.k1 + ip];
+          acc[q] += v;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) {
+    const int e = threadIdx.x + q * 256;
+    if (e < ne) Y2[(size_t(J) * 9 + slot) * ne + e] = make_double2(acc[q].re, acc[q].im);  // column-major
+  }
+}
+
+// canonical export of the third level's P: [d][2][N][k] with rows (jb * k1 + i)
+__global__ void k_level_export_P(const double2* __restrict__ P, double2* __restrict__ out, int nd, int k1, int k,
+                                 size_t n) {
+  const size_t g = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= n) return;
+  const int N = nd * k1;
+  const int l = int(g % k);
+  const size_t t = g / k;
+  const int crow = int(t % N);            // canonical row jb * k1 + i
+  const size_t ja = t / N;
+  const int jb = crow / k1, i = crow - jb * k1;
+  out[g] = P[(ja * k + l) * N + size_t(i) * nd + jb];
+}
+
 template <class F>
 void dispatch_prec(qmg_prec p, F&& f) {
   switch (p) {
@@ -695,9 +888,14 @@ void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const 
 
 void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, const void* in, void* out, int nrhs,
                          hipStream_t st, const int* skip) {
-  const int m = 2 * h.k;
-  TimedLaunch tl("coarse_apply", st, double(h.blk.d) * (9.0 * m * m + 2.0 * m * nrhs) * prec_bytes(prec),
-                 8.0 * 9.0 * m * m * h.blk.d * nrhs);
+  TimedLaunch tl("coarse_apply", st, double(h.blk.d) * (9.0 * 4 * h.k * h.k + 4.0 * h.k * nrhs) * prec_bytes(prec),
+                 8.0 * 9.0 * 4 * h.k * h.k * h.blk.d * nrhs);
+  launch_stencil_apply(prec, h.blk.d, h.k, h.cnb.as<int>(), Y, in, out, nrhs, st, skip);
+}
+
+void launch_stencil_apply(qmg_prec prec, int d, int k, const int* cnb, const void* Y, const void* in, void* out,
+                          int nrhs, hipStream_t st, const int* skip) {
+  const int m = 2 * k;
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
     constexpr int PK = kPack<S>;
@@ -709,8 +907,8 @@ void launch_coarse_apply(qmg_prec prec, const HierarchyDev& h, const void* Y, co
       QMG_CHECK(lds <= 160 * 1024, QMG_EINVAL, "coarse apply: block too large for LDS staging");
       if (lds > 64 * 1024)
         QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-      launch(kern, dim3(h.blk.d, (nrhs + NR - 1) / NR), dim3(threads), uint32_t(lds), st, Y, in, out,
-             h.cnb.as<int>(), h.blk.d, m, nrhs, H, skip);
+      launch(kern, dim3(d, (nrhs + NR - 1) / NR), dim3(threads), uint32_t(lds), st, Y, in, out, cnb, d, m, nrhs, H,
+             skip);
     };
     const bool packed = m % PK == 0;
     if (packed) {
@@ -857,6 +1055,86 @@ void launch_convert(const void* in, qmg_prec pin, void* out, qmg_prec pout, size
       k_convert<Si, So><<<cdiv(n, 256), 256, 0, st>>>((const Si*)in, (So*)out, n);
     });
   });
+  QMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------------------
+// third level: launchers
+void launch_philox_coarse(uint64_t seed, int v0, int n, int d, int m, int level, void* out, hipStream_t st) {
+  k_philox_coarse<<<dim3(cdiv(d, 256), n), 256, 0, st>>>((double2*)out, seed, v0, d, m, level);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_level_gather(const CoarseLevel& L, const void* v, void* blocks, int r, hipStream_t st) {
+  const int d1 = L.d * L.nd;
+  k_level_gather<<<dim3(cdiv(L.N, 256), r, 2 * L.d), 256, 0, st>>>((const double2*)v, (double2*)blocks,
+                                                                    L.bsite.as<int>(), L.nd, L.k1, d1, r);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_level_prolong(qmg_prec prec, const CoarseLevel& L, int d1, const void* P, const void* v2, void* v1,
+                          int nrhs, hipStream_t st) {
+  TimedLaunch tl("level_prolong", st, (2.0 * L.d * L.k * L.N + double(nrhs) * (2.0 * L.d * L.k + 2.0 * d1 * L.k1)) *
+                                          prec_bytes(prec),
+                 8.0 * 2.0 * L.d * L.k * L.N * nrhs);
+  dispatch_prec(prec, [&](auto tag) {
+    using S = decltype(tag);
+    k_level_prolong<S><<<dim3(cdiv(L.N, 256), 2 * L.d, nrhs), 256, 0, st>>>(
+        (const S*)P, (const S*)v2, (S*)v1, L.bsite.as<int>(), L.nd, L.k1, L.k, d1, L.d);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_level_restrict(qmg_prec prec, const CoarseLevel& L, int d1, const void* P, const void* v1, void* v2,
+                           int nrhs, hipStream_t st) {
+  TimedLaunch tl("level_restrict", st, (2.0 * L.d * L.k * L.N + double(nrhs) * (2.0 * L.d * L.k + 2.0 * d1 * L.k1)) *
+                                           prec_bytes(prec),
+                 8.0 * 2.0 * L.d * L.k * L.N * nrhs);
+  dispatch_prec(prec, [&](auto tag) {
+    using S = decltype(tag);
+    const size_t lds = size_t(L.N) * sizeof(cplx<ctype<S>>);
+    QMG_CHECK(lds <= 64 * 1024, QMG_ESHAPE, "level restrict: block of %d rows too large", L.N);
+    k_level_restrict<S><<<dim3(2 * L.d, nrhs), 256, lds, st>>>((const S*)P, (const S*)v1, (S*)v2, L.bsite.as<int>(),
+                                                                 L.nd, L.k1, L.k, d1, L.d);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void build_level_coarse(CoarseLevel& L, const HierarchyDev& h, hipStream_t st) {
+  const int m2 = 2 * L.k, m1 = 2 * L.k1;
+  QMG_CHECK(m2 <= 64 && m1 <= 64, QMG_ESHAPE, "third level: 2k <= 64 on both levels");
+  LevelBuildArgs a{};
+  for (int q = 0; q < 4; ++q) {
+    a.cL1[q] = h.blk.cL[q];
+    a.b[q] = L.b[q];
+  }
+  a.nd = L.nd;
+  a.k1 = L.k1;
+  a.k = L.k;
+  a.d1 = h.blk.d;
+  a.d = L.d;
+  L.Y64.alloc(size_t(L.d) * 9 * m2 * m2 * sizeof(double2));
+  const size_t lds = (size_t(m1) * m2 + size_t(4) * L.k * L.k1) * sizeof(cplx<double>);
+  QMG_CHECK(lds <= 160 * 1024, QMG_ESHAPE, "third level: coarse build needs too much LDS");
+  if (lds > 64 * 1024)
+    QMG_HIP(hipFuncSetAttribute((const void*)k_level_build, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  TimedLaunch tl("level_build", st, 0.0, 8.0 * 2.0 * double(m1) * m2 * (m1 / 2 + m2 / 2) * h.blk.d * 9, false);
+  k_level_build<<<dim3(L.d, 9), 256, lds, st>>>(h.Y64.as<double2>(), h.cnb.as<int>(), L.P64.as<double2>(),
+                                                 L.bsite.as<int>(), L.agg.as<int>(), L.pos.as<int>(),
+                                                 L.Y64.as<double2>(), a);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_level_export_P(const CoarseLevel& L, void* out, hipStream_t st) {
+  const size_t n = size_t(2) * L.d * L.N * L.k;
+  k_level_export_P<<<cdiv(n, 256), 256, 0, st>>>(L.P64.as<double2>(), (double2*)out, L.nd, L.k1, L.k, n);
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_level_export_Y(const CoarseLevel& L, void* out, hipStream_t st) {
+  const int m = 2 * L.k;
+  const size_t n = size_t(L.d) * 9 * m * m;
+  k_export_Y<<<cdiv(n, 256), 256, 0, st>>>(L.Y64.as<double2>(), (double2*)out, m, n);
   QMG_LAUNCH_CHECK();
 }
 
