@@ -70,6 +70,9 @@ def parse():
                     help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
     ap.add_argument("--no-dslash-hbm", action="store_true",
                     help="skip the dslash bandwidth measurement on the 32^3x64 lattice")
+    ap.add_argument("--levels", action="store_true",
+                    help="two-level vs three-level solve on the workload (third level: 2^4 blocks of coarse "
+                         "sites, 48 coarse test vectors in batches of 8, rank 24)")
     ap.add_argument("--compare-setups", action="store_true",
                     help="Regular / CSVD / streaming (iCSVD) setups on the workload: iterations per level, "
                          "setup and solve seconds, leading singular values (prints a table and JSON lines)")
@@ -230,6 +233,60 @@ def compare_setups(args):
         print(f"{x['method']:8s} m={x['m']:3d} r={x['r']:2d}: " + " ".join(f"{v:.3g}" for v in sv))
 
 
+LEVEL2 = dict(block=(2, 2, 2, 2), n_test=48, batch=8, rank=24, n_setup_iter=16)
+
+
+def compare_levels(args):
+    """The workload's two-level hierarchy, then the same hierarchy with a third level: setup
+    seconds of the extra level, median of three solves, iterations per level (l = 0 outer,
+    l = 1 GMRES on D_c, l = 2 GMRES on the third level)."""
+    import numpy as np
+    import torch
+
+    import fields
+    import paper_2505_14399_amd as q
+
+    w = load_workload(args)
+    dims = w["dims"]
+    lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
+    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
+    b = torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda()
+    kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
+              inner=w["inner"], seed=w["seed"])
+    rows = []
+    for levels in (2, 3, 3):  # the first three-level pass is a warm-up of its kernels
+        mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
+        t_level = 0.0
+        if levels == 3:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mg.add_level(**LEVEL2)
+            torch.cuda.synchronize()
+            t_level = time.perf_counter() - t0
+        ts, info = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, info = q.mg_solve(mg, b, tol=args.tol)
+            ts.append(time.perf_counter() - t0)
+        dims3 = list(mg.level_dims) if levels == 3 else None
+        mg.close()
+        i0 = info[0]
+        rows.append({"levels": levels, "workload": w["name"], "coarse_dims_l2": dims3, "level_setup_s": t_level,
+                     "solve_s": float(np.median(ts)), "iters_l0": i0["outer_iters"], "iters_l1": i0["coarse_iters"],
+                     "iters_l2": i0["coarse2_iters"], "smoother_l1": i0["smoother1_iters"],
+                     "true_rel_res": i0["true_rel_res"]})
+    rows = [rows[0], rows[2]]
+    for x in rows:
+        print(json.dumps(x), flush=True)
+    print(f"\n# {w['name']} {dims}, inner {w['inner']}, tol {args.tol}; third level {LEVEL2}")
+    print("| levels | iterations l=0 | l=1 | l=2 | l=1 per l=0 | l=2 per l=1 | extra setup s | solve s |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|")
+    for x in rows:
+        n21 = f"{x['iters_l2'] / max(1, x['iters_l1']):.2f}" if x["levels"] == 3 else "-"
+        print(f"| {x['levels']} | {x['iters_l0']} | {x['iters_l1']} | {x['iters_l2'] if x['levels'] == 3 else '-'} | "
+              f"{x['iters_l1'] / max(1, x['iters_l0']):.2f} | {n21} | {x['level_setup_s']:.3f} | {x['solve_s']:.3f} |")
+
+
 def read_counter(d, counter):
     """{kernel name: [per-dispatch counter values]} from a rocprofv3 --pmc output folder."""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
@@ -364,6 +421,9 @@ def main():
         return
     if args.compare_setups:
         compare_setups(args)
+        return
+    if args.levels:
+        compare_levels(args)
         return
     import numpy as np
     import torch
