@@ -236,6 +236,14 @@ def compare_setups(args):
 LEVEL2 = dict(block=(2, 2, 2, 2), n_test=48, batch=8, rank=24, n_setup_iter=16)
 
 
+def isvd_rate(fam):
+    if not fam["launches"]:
+        return None
+    ms = fam["ms"] / fam["launches"]
+    tf = fam["flops"] / fam["launches"] / (ms * 1e-3) / 1e12
+    return {"timed_streams": fam["launches"], "avg_stream_ms": ms, "TFLOPs_fp64": tf, "frac_fp64": tf / PEAK_FP64_TFLOPS}
+
+
 def compare_levels(args):
     """The workload's two-level hierarchy, then the same hierarchy with a third level: setup
     seconds of the extra level, median of three solves, iterations per level (l = 0 outer,
@@ -532,6 +540,9 @@ def main():
         "timing_sample": TIMING_SAMPLE,
         "dslash": {"timed_launches": ds["launches"], "avg_launch_us": ds_avg_ms * 1e3, "GBps": ds_gbps,
                    "frac_hbm": ds_gbps / PEAK_HBM_GBPS},
+        # the streaming SVD of one stream (Gram, small SVD, rotation) in FP64: algorithmic flops
+        # of the Gram passes and the rotation over the timed stream updates
+        "isvd": isvd_rate(fams["isvd"]),
         # timed launches scaled to every call of the family
         "kernel_ms_per_step": {f: fams[f]["ms"] * fams[f]["calls"] / fams[f]["launches"] / args.steps
                                for f in fams if fams[f]["launches"]},
