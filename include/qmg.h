@@ -239,7 +239,8 @@ qmg_status qmg_mg_get_params(const qmg_mg* mg, qmg_lattice* lat, qmg_mg_params* 
 /* Resumable streams: Algorithm 3 continues from the current factor U_k Sigma_k with n_streams
  * more streams of `batch` test vectors (the counter RNG with the setup's seed at the next global
  * indices streams_done * batch, ..., smoothed as in the setup), then P, R and D_c are rebuilt.
- * The result equals a setup with the larger n_test.  Errors: EINVAL (null, n_streams < 1),
+ * The result equals a setup with the larger n_test.  A third level (qmg_mg_add_level) is
+ * rebuilt on the new D_c with its own parameters.  Errors: EINVAL (null, n_streams < 1),
  * ENOMEM, EHIP. */
 qmg_status qmg_mg_stream_more(qmg_mg* mg, int32_t n_streams, hipStream_t stream);
 

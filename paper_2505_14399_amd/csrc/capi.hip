@@ -1030,6 +1030,14 @@ qmg_status qmg_mg_stream_more(qmg_mg* mg, int32_t n_streams, hipStream_t stream)
     else run_streams<float2>(mg, s0, s0 + n_streams, nullptr, stream);
     mg->params.n_test = mg->streams_done * mg->params.batch;
     finish_setup(mg, stream);
+    if (h.l2) {  // the third level is built on D_c: rebuild it (dropped if that fails)
+      try {
+        run_level_setup(h, stream);
+      } catch (...) {
+        h.l2.reset();
+        throw;
+      }
+    }
     h.t_total += secs(t0, Clock::now());
   });
 }

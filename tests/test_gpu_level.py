@@ -105,3 +105,18 @@ def test_level_errors(qmg):
     with pytest.raises(qmg.QmgError, match="host-checked"):
         mg.set_cycle(coarse_steps=12)
     mg.close()
+
+
+def test_more_streams_rebuild_the_third_level(qmg):
+    """After qmg_mg_stream_more the third level is rebuilt on the new D_c: it equals a third level
+    added to a hierarchy set up with the larger n_test from the start."""
+    banner("third level after more streams")
+    a, U = _hier(qmg, (4, 4, 4, 8), (2, 2, 2, 2), 8, 4, 4, "f64", 56)
+    a.add_level((1, 1, 2, 2), 8, 4, 4, n_setup_iter=2, seed=3)
+    a.stream_more(1)
+    b, _ = _hier(qmg, (4, 4, 4, 8), (2, 2, 2, 2), 12, 4, 4, "f64", 56)
+    b.add_level((1, 1, 2, 2), 8, 4, 4, n_setup_iter=2, seed=3)
+    assert np.array_equal(to_np(a.level_coarse_blocks()), to_np(b.level_coarse_blocks()))
+    assert np.array_equal(a.level_prolongator()[1], b.level_prolongator()[1])
+    a.close()
+    b.close()
