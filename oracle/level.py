@@ -193,39 +193,58 @@ def setup(Y, cdims, block2, n_test, batch, rank, n_setup_iter=16, seed=0, level=
     return lv
 
 
-def solve3(h, lv, b, tol=1e-10, max_iter=1000, restart=16, coarse_tol=0.03, coarse_restart=32, coarse_max=500,
-           n_post=8):
-    """Three-level K-cycle preconditioned flexible GCR in FP64 (h: level-one hierarchy of
-    oracle.mg.setup, lv: its next level).  Returns (x, stats)."""
-    stats = {"coarse": 0, "coarse2": 0, "smoother": 0, "smoother1": 0}
+def solve_levels(h, lvs, b, tol=1e-10, max_iter=1000, restart=16, coarse_tol=0.03, coarse_restart=32,
+                 coarse_max=500, n_post=8):
+    """K-cycle preconditioned flexible GCR in FP64 over the fine level, the first coarse level
+    (h from oracle.mg.setup) and the further levels lvs (each from setup() on the stencil of the
+    level above).  Returns (x, stats) with stats["iters"][l] the Krylov iterations on level l
+    (l = 0 outer) and stats["smooth"][l] the post-smoothing iterations on level l."""
+    L = 2 + len(lvs)
+    stats = {"iters": [0] * L, "smooth": [0] * L}
+    ops = [None, (h.Y, h.cdims)] + [(lv.Y2, lv.cdims2) for lv in lvs]
 
-    def Dc(v):
-        return coarse.coarse_apply(h.Y, v[None], h.cdims)[0]
+    def A(l):
+        Y, cd = ops[l]
+        return lambda v: coarse.coarse_apply(Y, v[None], cd)[0]
 
-    def Dcc(v):
-        return coarse.coarse_apply(lv.Y2, v[None], lv.cdims2)[0]
-
-    d, m = h.Y.shape[0], h.Y.shape[-1]
-
-    def k1(r1):  # K-cycle of level one: level two solved by GMRES, 8 post-smoothing steps on D_c
-        r2 = restrict(lv.P, r1.reshape(1, d, m), h.cdims, lv.block2, lv.k)[0]
-        e2, it2, _ = krylov.gmres(Dcc, r2, None, restart=coarse_restart, max_iter=coarse_max, tol=coarse_tol)
-        e1 = prolong(lv.P, e2[None], h.cdims, lv.block2, lv.k)[0].reshape(r1.shape)
-        e1, its, _ = krylov.gmres(Dc, r1, e1, restart=n_post, max_iter=n_post, tol=0.0)
-        stats["coarse2"] += it2
-        stats["smoother1"] += its
-        return e1
-
-    def k0(r):  # K-cycle of level zero: level one solved by flexible GCR with k1
-        rc = mg.restrict(h, r[None])[0]
-        ec, it1, _ = krylov.fgcr(Dc, k1, rc, None, tol=coarse_tol, restart=coarse_restart, max_iter=coarse_max)
-        e = mg.prolong(h, ec[None])[0]
-        e, its, _ = krylov.gmres(h.lat.D, r, e, restart=n_post, max_iter=n_post, tol=0.0)
-        stats["coarse"] += it1
-        stats["smoother"] += its
+    def cycle(l, r):  # K-cycle of level l >= 1: solve level l + 1, prolong, post-smooth on level l
+        lv = lvs[l - 1]
+        d, m = ops[l][0].shape[0], ops[l][0].shape[-1]
+        r2 = restrict(lv.P, r.reshape(1, d, m), ops[l][1], lv.block2, lv.k)[0]
+        if l + 1 == L - 1:
+            e2, it, _ = krylov.gmres(A(l + 1), r2, None, restart=coarse_restart, max_iter=coarse_max, tol=coarse_tol)
+        else:
+            e2, it, _ = krylov.fgcr(A(l + 1), lambda q: cycle(l + 1, q), r2, None, tol=coarse_tol,
+                                    restart=coarse_restart, max_iter=coarse_max)
+        stats["iters"][l + 1] += it
+        e = prolong(lv.P, e2[None], ops[l][1], lv.block2, lv.k)[0].reshape(r.shape)
+        e, its, _ = krylov.gmres(A(l), r, e, restart=n_post, max_iter=n_post, tol=0.0)
+        stats["smooth"][l] += its
         return e
 
-    x, it, hist = krylov.fgcr(h.lat.D, k0, b, None, tol=tol, restart=restart, max_iter=max_iter)
-    stats["outer"] = it
+    def k0(r):  # K-cycle of the fine level
+        rc = mg.restrict(h, r[None])[0]
+        if L == 2:
+            ec, it, _ = krylov.gmres(A(1), rc, None, restart=coarse_restart, max_iter=coarse_max, tol=coarse_tol)
+        else:
+            ec, it, _ = krylov.fgcr(A(1), lambda q: cycle(1, q), rc, None, tol=coarse_tol, restart=coarse_restart,
+                                    max_iter=coarse_max)
+        stats["iters"][1] += it
+        e = mg.prolong(h, ec[None])[0]
+        e, its, _ = krylov.gmres(h.lat.D, r, e, restart=n_post, max_iter=n_post, tol=0.0)
+        stats["smooth"][0] += its
+        return e
+
+    x, it, _ = krylov.fgcr(h.lat.D, k0, b, None, tol=tol, restart=restart, max_iter=max_iter)
+    stats["iters"][0] = it
     stats["true_rel_res"] = float(np.linalg.norm((b - h.lat.D(x)).ravel()) / np.linalg.norm(b.ravel()))
     return x, stats
+
+
+def solve3(h, lv, b, tol=1e-10, **kw):
+    """Three levels: solve_levels with one further level.  Returns (x, stats) with stats["coarse"],
+    stats["coarse2"] (iterations on levels 1 and 2) and stats["smoother1"] (post-smoothing on D_c)."""
+    x, st = solve_levels(h, [lv], b, tol=tol, **kw)
+    st.update(outer=st["iters"][0], coarse=st["iters"][1], coarse2=st["iters"][2], smoother=st["smooth"][0],
+              smoother1=st["smooth"][1])
+    return x, st

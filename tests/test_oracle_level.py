@@ -144,3 +144,20 @@ def test_three_level_solve_matches_the_dense_solution():
     xd = np.linalg.solve(Dd, b.ravel())
     assert np.linalg.norm(x.ravel() - xd) < 1e-9 * np.linalg.norm(xd)
     assert st["coarse2"] > 0 and st["smoother1"] > 0
+
+
+def test_four_level_solve_matches_the_dense_solution():
+    """A fourth level set up on the third level's stencil (level word 2); the four-level solve at
+    1e-12 gives the dense LU solution."""
+    dims = (4, 4, 4, 8)
+    U = fields.random_gauge(dims, 0.3, 45)
+    lat = omg.Lattice(U, dims, 0.1, 1.0, -1)
+    h = omg.setup(lat, (2, 2, 2, 2), 12, 4, 6, n_setup_iter=8, seed=6)
+    lv2 = level.setup(h.Y, h.cdims, (2, 2, 1, 2), 12, 4, 4, n_setup_iter=8, seed=6, level=1)
+    lv3 = level.setup(lv2.Y2, lv2.cdims2, (1, 1, 2, 1), 8, 4, 3, n_setup_iter=8, seed=6, level=2)
+    assert lv3.cdims2 == (1, 1, 1, 2)
+    b = fields.gaussian_spinor(dims, 1, 46)[0]
+    x, st = level.solve_levels(h, [lv2, lv3], b, tol=1e-12)
+    assert st["true_rel_res"] < 1e-12 and st["iters"][3] > 0 and st["smooth"][2] > 0
+    xd = np.linalg.solve(wilson.dense_wilson(U, 0.1, 1.0, -1, dims), b.ravel())
+    assert np.linalg.norm(x.ravel() - xd) < 1e-9 * np.linalg.norm(xd)
