@@ -71,8 +71,8 @@ def parse():
     ap.add_argument("--no-dslash-hbm", action="store_true",
                     help="skip the dslash bandwidth measurement on the 32^3x64 lattice")
     ap.add_argument("--levels", action="store_true",
-                    help="two-level vs three-level solve on the workload (third level: 2^4 blocks of coarse "
-                         "sites, 48 coarse test vectors in batches of 8, rank 24)")
+                    help="two- vs three- vs four-level solve on the workload (further levels: 2^4 blocks of "
+                         "the level above, 48 test vectors in batches of 8, rank 24)")
     ap.add_argument("--compare-setups", action="store_true",
                     help="Regular / CSVD / streaming (iCSVD) setups on the workload: iterations per level, "
                          "setup and solve seconds, leading singular values (prints a table and JSON lines)")
@@ -234,6 +234,7 @@ def compare_setups(args):
 
 
 LEVEL2 = dict(block=(2, 2, 2, 2), n_test=48, batch=8, rank=24, n_setup_iter=16)
+LEVEL3 = dict(block=None, n_test=48, batch=8, rank=24, n_setup_iter=16)  # block from the extents of level 2
 
 
 def isvd_rate(fam):
@@ -245,9 +246,9 @@ def isvd_rate(fam):
 
 
 def compare_levels(args):
-    """The workload's two-level hierarchy, then the same hierarchy with a third level: setup
-    seconds of the extra level, median of three solves, iterations per level (l = 0 outer,
-    l = 1 GMRES on D_c, l = 2 GMRES on the third level)."""
+    """The workload's two-level hierarchy, then the same hierarchy with a third and with a third
+    and fourth level: setup seconds of the extra levels, median of three solves, iterations per
+    level (l = 0 outer, l = 1 on D_c, l = 2 and l = 3 on the further levels)."""
     import numpy as np
     import torch
 
@@ -262,13 +263,17 @@ def compare_levels(args):
     kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
               inner=w["inner"], seed=w["seed"])
     rows = []
-    for levels in (2, 3, 3):  # the first three-level pass is a warm-up of its kernels
+    for levels in (2, 3, 3, 4):  # the first three-level pass is a warm-up of its kernels
         mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
         t_level = 0.0
-        if levels == 3:
+        if levels >= 3:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             mg.add_level(**LEVEL2)
+            if levels == 4:  # block 2 along extents of level 2 that are even, 3 along multiples of 3, else 1
+                ext = mg.levels[2]["dims"]
+                blk = tuple(2 if e % 2 == 0 else 3 if e % 3 == 0 else 1 for e in ext)
+                mg.add_level(**dict(LEVEL3, block=blk))
             torch.cuda.synchronize()
             t_level = time.perf_counter() - t0
         ts, info = [], None
@@ -276,23 +281,28 @@ def compare_levels(args):
             t0 = time.perf_counter()
             _, info = q.mg_solve(mg, b, tol=args.tol)
             ts.append(time.perf_counter() - t0)
-        dims3 = list(mg.level_dims) if levels == 3 else None
+        dims_l = {lv: list(mg.levels[lv]["dims"]) for lv in mg.levels}
         mg.close()
         i0 = info[0]
-        rows.append({"levels": levels, "workload": w["name"], "coarse_dims_l2": dims3, "level_setup_s": t_level,
+        rows.append({"levels": levels, "workload": w["name"], "level_dims": dims_l, "level_setup_s": t_level,
                      "solve_s": float(np.median(ts)), "iters_l0": i0["outer_iters"], "iters_l1": i0["coarse_iters"],
-                     "iters_l2": i0["coarse2_iters"], "smoother_l1": i0["smoother1_iters"],
+                     "iters_l2": i0["coarse2_iters"], "iters_l3": i0["coarse3_iters"],
+                     "smoother_l1": i0["smoother1_iters"], "smoother_l2": i0["smoother2_iters"],
                      "true_rel_res": i0["true_rel_res"]})
-    rows = [rows[0], rows[2]]
+    rows = [rows[0], rows[2], rows[3]]
     for x in rows:
         print(json.dumps(x), flush=True)
-    print(f"\n# {w['name']} {dims}, inner {w['inner']}, tol {args.tol}; third level {LEVEL2}")
-    print("| levels | iterations l=0 | l=1 | l=2 | l=1 per l=0 | l=2 per l=1 | extra setup s | solve s |")
-    print("|---|---:|---:|---:|---:|---:|---:|---:|")
+    print(f"\n# {w['name']} {dims}, inner {w['inner']}, tol {args.tol}; level 2 {LEVEL2}; level 3 {LEVEL3}")
+    print("| levels | iterations l=0 | l=1 | l=2 | l=3 | l=1 per l=0 | l=2 per l=1 | l=3 per l=2 | extra setup s | "
+          "solve s |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|")
     for x in rows:
-        n21 = f"{x['iters_l2'] / max(1, x['iters_l1']):.2f}" if x["levels"] == 3 else "-"
-        print(f"| {x['levels']} | {x['iters_l0']} | {x['iters_l1']} | {x['iters_l2'] if x['levels'] == 3 else '-'} | "
-              f"{x['iters_l1'] / max(1, x['iters_l0']):.2f} | {n21} | {x['level_setup_s']:.3f} | {x['solve_s']:.3f} |")
+        lv = x["levels"]
+        c = lambda a, b: f"{a / max(1, b):.2f}"
+        print(f"| {lv} | {x['iters_l0']} | {x['iters_l1']} | {x['iters_l2'] if lv >= 3 else '-'} | "
+              f"{x['iters_l3'] if lv >= 4 else '-'} | {c(x['iters_l1'], x['iters_l0'])} | "
+              f"{c(x['iters_l2'], x['iters_l1']) if lv >= 3 else '-'} | {c(x['iters_l3'], x['iters_l2']) if lv >= 4 else '-'} | "
+              f"{x['level_setup_s']:.3f} | {x['solve_s']:.3f} |")
 
 
 def read_counter(d, counter):

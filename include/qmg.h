@@ -156,54 +156,59 @@ typedef struct {
   int32_t precision_escalations;
   double true_rel_res;      /* ||b - D x|| / ||b|| recomputed in FP64 at the end              */
   double seconds;
-  int32_t coarse2_iters;    /* third-level GMRES iterations, summed (0 without a third level) */
-  int32_t smoother1_iters;  /* GMRES post-smoothing iterations on D_c, summed (third level)   */
+  int32_t coarse2_iters;    /* Krylov iterations on level 2 (the third level), summed; 0 if none */
+  int32_t smoother1_iters;  /* GMRES post-smoothing iterations on D_c (level 1), summed        */
+  int32_t coarse3_iters;    /* Krylov iterations on level 3 (the fourth level), summed; 0 if none */
+  int32_t smoother2_iters;  /* GMRES post-smoothing iterations on level 2, summed              */
 } qmg_solve_info;
 
 /* Solve D x = b (or D^dag x = b when adjoint != 0, as gamma5 D^-1 gamma5) to a true FP64
  * relative residual <= tol with flexible GMRES(16) preconditioned by the two-level K-cycle
  * (Section 2.1: restrict, coarse GMRES to coarse_tol, prolong, post-smooth; Section 4: FGMRES
  * as the outer solver).  With an inner precision below F64 the K-cycle runs in that precision
- * and the flexible GMRES in FP32, inside an FP64 defect-correction loop.  When the hierarchy
- * has a third level (qmg_mg_add_level) the coarse solve is a flexible GMRES(32) on D_c to
- * coarse_tol preconditioned by the K-cycle of the first coarse level (restrict to the third
- * level, GMRES(32) there to coarse_tol, prolong, n_post_smooth GMRES steps on D_c).
+ * and the flexible GMRES in FP32, inside an FP64 defect-correction loop.  With further levels
+ * (qmg_mg_add_level) the coarse solve is a flexible GMRES(32) on D_c to coarse_tol
+ * preconditioned by the K-cycle of the first coarse level, recursively.
  * b, x: device, canonical FP64 [nrhs][V][4][3]; x is the initial guess on entry (zeros
  *   allowed) and the solution on return.  info: host array of nrhs entries (may be NULL).
  * Errors: ENOCONV (x holds the best iterate, info filled), ENONFINITE, EBREAKDOWN, EHIP. */
 qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, double tol, int32_t max_outer,
                         int32_t adjoint, qmg_solve_info* info, hipStream_t stream);
 
-/* Third level (the paper's hierarchies have three and four levels, Section 4): Algorithm 4
- * with Algorithm 3 applied to the coarse operator D_c of the hierarchy.  Coarse test vectors
- * phi_v (v < n_test) are complex Gaussian from Philox4x32-10 keyed by seed with counter
- * (coarse site, g, v, 1) (components 2g, 2g+1), smoothed by n_setup_iter GMRES(8) iterations
- * on D_c psi' = -D_c phi in FP64 and normalised; the coarse chirality is sigma3, so the chiral
- * split keeps the alpha block of every coarse site; blocks of `block` coarse sites (each extent
- * must divide the coarse extent) are folded into a rank-`rank` streaming SVD per (aggregate,
- * chirality) in batches of `batch`; P2 = U_k and D_cc = P2^dag D_c P2 as a nine-block stencil
- * (hops leaving an aggregate through its face kept in their directional block).  Afterwards
- * qmg_mg_solve uses three levels.  Limits: k1 * prod(block) <= 4096, 1 <= batch <= 48,
- * rank <= min(k1 * prod(block), n_test, 32).  Not combined with the device-exit / captured
- * K-cycle (qmg_mg_set_cycle with coarse_steps > 0: EINVAL either way), and not stored by
- * qmg_mg_save (a loaded hierarchy has two levels).
- * Errors: EINVAL (null, already three levels, device-exit cycle set), ESHAPE, ENOMEM, EHIP. */
+/* Further levels (the paper's hierarchies have three and four levels, Section 4): each call
+ * applies Algorithm 4 with Algorithm 3 to the operator of the current coarsest level (D_c of
+ * the hierarchy for level l = 2, then level 2's operator for l = 3; at most four levels).  Test
+ * vectors phi_v (v < n_test) on that level are complex Gaussian from Philox4x32-10 keyed by seed
+ * with counter (site, g, v, l - 1) (components 2g, 2g+1), smoothed by n_setup_iter GMRES(8)
+ * iterations on A psi' = -A phi in FP64 and normalised; the chirality is sigma3 (the alpha block
+ * of every site); blocks of `block` sites (each extent must divide the extent of the level
+ * above) are folded into a rank-`rank` streaming SVD per (aggregate, chirality) in batches of
+ * `batch`; P_l = U_k and A_l = P_l^dag A P_l as a nine-block stencil (hops leaving an aggregate
+ * through its face kept in their directional block).  qmg_mg_solve then recurses: level l - 1
+ * solves level l by flexible GMRES(32) to coarse_tol preconditioned by level l's K-cycle (plain
+ * GMRES(32) on the coarsest level), with n_post_smooth post-smoothing steps on level l - 1.
+ * Limits: k_above * prod(block) <= 4096, 1 <= batch <= 48, rank <= min(k_above * prod(block),
+ * n_test, 32).  Not combined with the device-exit / captured K-cycle (qmg_mg_set_cycle with
+ * coarse_steps > 0: EINVAL either way), not stored by qmg_mg_save (a loaded hierarchy has two
+ * levels); qmg_mg_stream_more rebuilds them.
+ * Errors: EINVAL (null, already four levels, device-exit cycle set), ESHAPE, ENOMEM, EHIP. */
 qmg_status qmg_mg_add_level(qmg_mg* mg, const int32_t* block, int32_t n_test, int32_t batch, int32_t rank,
                             int32_t n_setup_iter, uint64_t seed, hipStream_t stream);
-/* Third-level extents [4], aggregate count and rank (EINVAL without a third level). */
-qmg_status qmg_mg_level_query(const qmg_mg* mg, int32_t* coarse_dims, int32_t* n_agg, int32_t* rank);
-/* Third-level P2 as FP64 blocks [d2][2][N2][k2] with rows (site in block * k1 + i) (device, may be
- * NULL), singular values [d2][2][k2] (host, may be NULL), D_cc blocks [d2][9][2k2][2k2] FP64
- * (device, may be NULL; slot 0 self, 1 + dir hops, row-major blocks). */
-qmg_status qmg_mg_level_get(const qmg_mg* mg, void* P, double* sigma, void* Y, hipStream_t stream);
-/* Third-level transfer and operator on coarse vectors (device, [nrhs][d][2][k] layouts, prec F64
- * or the F32 inner precision): out = P2 in (d2 -> d1 sites), out = P2^dag in, out = D_cc in. */
-qmg_status qmg_level_prolong(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
-                             hipStream_t stream);
-qmg_status qmg_level_restrict(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
-                              hipStream_t stream);
-qmg_status qmg_level_coarse_apply(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
-                                  hipStream_t stream);
+/* Level l >= 2: extents [4], aggregate count and rank (EINVAL when the hierarchy has no level l). */
+qmg_status qmg_mg_level_query(const qmg_mg* mg, int32_t level, int32_t* coarse_dims, int32_t* n_agg,
+                              int32_t* rank);
+/* Level l >= 2: P_l as FP64 blocks [d_l][2][N_l][k_l] with rows (site in block * k_above + i)
+ * (device, may be NULL), singular values [d_l][2][k_l] (host, may be NULL), A_l blocks
+ * [d_l][9][2k_l][2k_l] FP64 (device, may be NULL; slot 0 self, 1 + dir hops, row-major blocks). */
+qmg_status qmg_mg_level_get(const qmg_mg* mg, int32_t level, void* P, double* sigma, void* Y, hipStream_t stream);
+/* Level l >= 2 transfer and operator on coarse vectors (device, [nrhs][d][2][k] layouts, prec F64
+ * or the F32 inner precision): out = P_l in (level l -> level l - 1), out = P_l^dag in, out = A_l in. */
+qmg_status qmg_level_prolong(const qmg_mg* mg, int32_t level, const void* in, void* out, int32_t nrhs,
+                             qmg_prec prec, hipStream_t stream);
+qmg_status qmg_level_restrict(const qmg_mg* mg, int32_t level, const void* in, void* out, int32_t nrhs,
+                              qmg_prec prec, hipStream_t stream);
+qmg_status qmg_level_coarse_apply(const qmg_mg* mg, int32_t level, const void* in, void* out, int32_t nrhs,
+                                  qmg_prec prec, hipStream_t stream);
 
 /* Gradient of L = sum_rhs Re <eta, D^-1 b> with respect to the gauge links, from the
  * solution x = D^-1 b and the adjoint solution lambda = D^-dag eta:

@@ -52,7 +52,8 @@ class qmg_solve_info(ctypes.Structure):
                 ("coarse_iters", ctypes.c_int32), ("smoother_iters", ctypes.c_int32),
                 ("precision_escalations", ctypes.c_int32), ("true_rel_res", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("coarse2_iters", ctypes.c_int32),
-                ("smoother1_iters", ctypes.c_int32)]
+                ("smoother1_iters", ctypes.c_int32), ("coarse3_iters", ctypes.c_int32),
+                ("smoother2_iters", ctypes.c_int32)]
 
 
 # exported symbols and their argument types (void* = device or host pointer, see qmg.h)
@@ -86,11 +87,11 @@ SIGNATURES = {
     "qmg_tune_load": [ctypes.c_char_p],
     "qmg_mg_stream_more": [_P, _I, _P],
     "qmg_mg_add_level": [_P, _P, _I, _I, _I, _I, ctypes.c_uint64, _P],
-    "qmg_mg_level_query": [_P, _P, _P, _P],
-    "qmg_mg_level_get": [_P, _P, _P, _P, _P],
-    "qmg_level_prolong": [_P, _P, _P, _I, _I, _P],
-    "qmg_level_restrict": [_P, _P, _P, _I, _I, _P],
-    "qmg_level_coarse_apply": [_P, _P, _P, _I, _I, _P],
+    "qmg_mg_level_query": [_P, _I, _P, _P, _P],
+    "qmg_mg_level_get": [_P, _I, _P, _P, _P, _P],
+    "qmg_level_prolong": [_P, _I, _P, _P, _I, _I, _P],
+    "qmg_level_restrict": [_P, _I, _P, _P, _I, _I, _P],
+    "qmg_level_coarse_apply": [_P, _I, _P, _P, _I, _I, _P],
     "qmg_mg_save": [_P, ctypes.c_char_p, _P],
     "qmg_mg_load": [ctypes.c_char_p, _P, _P, _P],
     "qmg_mg_get_params": [_P, _P, _P],
@@ -284,6 +285,7 @@ class MG:
         self.n_agg = d.value
         self.rank = k.value
         self.inner = {v: n for n, v in _PREC.items()}[params.inner_prec]
+        self.levels = {}  # further levels l >= 2: dims, n_agg, rank, block
 
     @property
     def handle(self):
@@ -328,32 +330,57 @@ class MG:
         self._refresh()
 
     def add_level(self, block, n_test, batch, rank, n_setup_iter=16, seed=None):
-        """Third level on D_c (qmg_mg_add_level); the solve then uses three levels."""
+        """One more level on the current coarsest operator (qmg_mg_add_level): level 2 on D_c,
+        then level 3; the solve then recurses over all levels.  Returns the new level's index."""
         blk = (ctypes.c_int32 * 4)(*[int(b) for b in block])
         seed = self.params.seed if seed is None else int(seed)
         _check(load_library().qmg_mg_add_level(self._h, blk, int(n_test), int(batch), int(rank), int(n_setup_iter),
                                                ctypes.c_uint64(seed), _stream()))
+        lvl = 2 + len(self.levels)
         cd = (ctypes.c_int32 * 4)()
         d = ctypes.c_int32()
         k = ctypes.c_int32()
-        _check(load_library().qmg_mg_level_query(self._h, cd, ctypes.byref(d), ctypes.byref(k)))
-        self.level_dims, self.level_n_agg, self.level_rank = tuple(cd), d.value, k.value
-        self.level_block = tuple(int(b) for b in block)
+        _check(load_library().qmg_mg_level_query(self._h, lvl, cd, ctypes.byref(d), ctypes.byref(k)))
+        self.levels[lvl] = {"dims": tuple(cd), "n_agg": d.value, "rank": k.value,
+                            "block": tuple(int(b) for b in block)}
+        return lvl
 
-    def level_prolongator(self):
-        """(P2 [d2,2,N2,k2] complex128 on the GPU, rows site-in-block * k + i; sigma2 [d2,2,k2])."""
+    def _above(self, level):
+        """(n_agg, rank) of the level above `level`."""
+        if level == 2:
+            return self.n_agg, self.rank
+        a = self.levels[level - 1]
+        return a["n_agg"], a["rank"]
+
+    # level 2 (the third level) shorthands
+    @property
+    def level_dims(self):
+        return self.levels[2]["dims"]
+
+    @property
+    def level_n_agg(self):
+        return self.levels[2]["n_agg"]
+
+    @property
+    def level_rank(self):
+        return self.levels[2]["rank"]
+
+    def level_prolongator(self, level=2):
+        """(P_l [d_l,2,N_l,k_l] complex128 on the GPU, rows site-in-block * k_above + i; sigma_l [d_l,2,k_l])."""
         import numpy as np
-        N2 = self.rank * int(np.prod(self.level_block))
-        P = torch.empty((self.level_n_agg, 2, N2, self.level_rank), dtype=torch.complex128, device="cuda")
-        sig = np.empty((self.level_n_agg, 2, self.level_rank))
-        _check(load_library().qmg_mg_level_get(self._h, _ptr(P), sig.ctypes.data_as(ctypes.c_void_p), None,
+        L = self.levels[level]
+        N = self._above(level)[1] * int(np.prod(L["block"]))
+        P = torch.empty((L["n_agg"], 2, N, L["rank"]), dtype=torch.complex128, device="cuda")
+        sig = np.empty((L["n_agg"], 2, L["rank"]))
+        _check(load_library().qmg_mg_level_get(self._h, level, _ptr(P), sig.ctypes.data_as(ctypes.c_void_p), None,
                                                _stream()))
         return P, sig
 
-    def level_coarse_blocks(self):
-        m = 2 * self.level_rank
-        Y = torch.empty((self.level_n_agg, 9, m, m), dtype=torch.complex128, device="cuda")
-        _check(load_library().qmg_mg_level_get(self._h, None, None, _ptr(Y), _stream()))
+    def level_coarse_blocks(self, level=2):
+        L = self.levels[level]
+        m = 2 * L["rank"]
+        Y = torch.empty((L["n_agg"], 9, m, m), dtype=torch.complex128, device="cuda")
+        _check(load_library().qmg_mg_level_get(self._h, level, None, None, _ptr(Y), _stream()))
         return Y
 
     def save(self, path):
@@ -410,28 +437,31 @@ def mg_load(path, U) -> MG:
     return MG(h, lat, p)
 
 
-def level_prolong(mg: MG, v2, out=None):
-    """v1 = P2 v2: v2 [nrhs,d2,2,k2] -> [nrhs,d,2,k] (complex128, or complex64 with FP32 inner)."""
+def level_prolong(mg: MG, v2, out=None, level=2):
+    """P_l v2: level-l vectors [nrhs,d_l,2,k_l] -> level-(l-1) vectors (complex128, or complex64 with FP32 inner)."""
     nrhs = v2.shape[0]
-    out = torch.empty((nrhs, mg.n_agg, 2, mg.rank), dtype=v2.dtype, device=v2.device) if out is None else out
-    _check(load_library().qmg_level_prolong(mg.handle, _ptr(v2), _ptr(out), nrhs, _prec_of(v2), _stream()))
+    d1, k1 = mg._above(level)
+    out = torch.empty((nrhs, d1, 2, k1), dtype=v2.dtype, device=v2.device) if out is None else out
+    _check(load_library().qmg_level_prolong(mg.handle, level, _ptr(v2), _ptr(out), nrhs, _prec_of(v2), _stream()))
     return out
 
 
-def level_restrict(mg: MG, v1, out=None):
-    """v2 = P2^dag v1: v1 [nrhs,d,2,k] -> [nrhs,d2,2,k2]."""
+def level_restrict(mg: MG, v1, out=None, level=2):
+    """P_l^dag v1: level-(l-1) vectors -> level-l vectors [nrhs,d_l,2,k_l]."""
     nrhs = v1.shape[0]
-    out = (torch.empty((nrhs, mg.level_n_agg, 2, mg.level_rank), dtype=v1.dtype, device=v1.device)
+    L = mg.levels[level]
+    out = (torch.empty((nrhs, L["n_agg"], 2, L["rank"]), dtype=v1.dtype, device=v1.device)
            if out is None else out)
-    _check(load_library().qmg_level_restrict(mg.handle, _ptr(v1), _ptr(out), nrhs, _prec_of(v1), _stream()))
+    _check(load_library().qmg_level_restrict(mg.handle, level, _ptr(v1), _ptr(out), nrhs, _prec_of(v1), _stream()))
     return out
 
 
-def level_coarse_apply(mg: MG, v2, out=None):
-    """D_cc v2 on third-level vectors [nrhs,d2,2,k2]."""
+def level_coarse_apply(mg: MG, v2, out=None, level=2):
+    """A_l v2 on level-l vectors [nrhs,d_l,2,k_l]."""
     nrhs = v2.shape[0]
     out = torch.empty_like(v2) if out is None else out
-    _check(load_library().qmg_level_coarse_apply(mg.handle, _ptr(v2), _ptr(out), nrhs, _prec_of(v2), _stream()))
+    _check(load_library().qmg_level_coarse_apply(mg.handle, level, _ptr(v2), _ptr(out), nrhs, _prec_of(v2),
+                                                 _stream()))
     return out
 
 

@@ -109,37 +109,41 @@ struct StencilOp : LinOp {
   qmg_prec prec() const override { return p; }
 };
 
-// K-cycle of the first coarse level when a third level exists (storage precision S): restrict
-// to the third level, GMRES(32) there to the coarse tolerance, prolong, GMRES post-smoothing on
-// D_c from the prolonged correction.
+// K-cycle of a coarse level l >= 1 when a further level exists (storage precision S): restrict
+// to level l + 1 (h.levels[i], i = l - 1), solve there to the coarse tolerance (GMRES(32) on the
+// coarsest level, else flexible GMRES(32) preconditioned by the K-cycle of level l + 1), prolong,
+// GMRES post-smoothing on level l (`above`) from the prolonged correction.
 template <class S>
 struct KCycleC : Precond {
   const HierarchyDev& h;
   const CoarseLevel& L;
-  CoarseOp& Dc;
-  StencilOp Dcc;
+  const int d1;
+  LinOp& above;
+  StencilOp own;
   const void* P2;
   Gmres<S> g2, gs;
   DevBuf r2, e2;
-  long coarse_iters = 0, smooth_iters = 0;
+  std::unique_ptr<KCycleC<S>> next;
+  long coarse_iters = 0, smooth_iters = 0;  // Krylov iterations on level l + 1, smoothing on level l
   int last = 0;
-  KCycleC(const HierarchyDev& h_, CoarseOp& Dc_)
-      : h(h_), L(*h_.l2), Dc(Dc_),
-        Dcc(h_.l2->d, h_.l2->k, h_.l2->cnb.as<int>(), StoreTraits<S>::prec,
-            StoreTraits<S>::prec == QMG_F64 ? h_.l2->Y64.p : h_.l2->Yin.p),
-        P2(StoreTraits<S>::prec == QMG_F64 ? h_.l2->P64.p : h_.l2->Pin.p) {}
+  KCycleC(const HierarchyDev& h_, size_t i, LinOp& above_)
+      : h(h_), L(*h_.levels[i]), d1(stencil_above(h_, i).d), above(above_),
+        own(L.d, L.k, L.cnb.as<int>(), StoreTraits<S>::prec, StoreTraits<S>::prec == QMG_F64 ? L.Y64.p : L.Yin.p),
+        P2(StoreTraits<S>::prec == QMG_F64 ? L.P64.p : L.Pin.p) {
+    if (i + 1 < h.levels.size()) next.reset(new KCycleC<S>(h, i + 1, own));
+  }
   void apply(const void* r1, void* z1, int nrhs, hipStream_t st) override {
     constexpr qmg_prec p = StoreTraits<S>::prec;
     const size_t n2 = size_t(nrhs) * 2 * L.k * L.d;
     r2.ensure(n2 * sizeof(S));
     e2.ensure(n2 * sizeof(S));
-    launch_level_restrict(p, L, h.blk.d, P2, r1, r2.p, nrhs, st);
+    launch_level_restrict(p, L, d1, P2, r1, r2.p, nrhs, st);
     const int hint = last > 1 ? last - 1 : 0;
-    auto res = g2.solve(Dcc, r2.p, e2.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st, nullptr, hint);
+    auto res = g2.solve(own, r2.p, e2.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st, nullptr, hint, next.get());
     coarse_iters += res.iters;
     last = res.iters;
-    launch_level_prolong(p, L, h.blk.d, P2, e2.p, z1, nrhs, st);
-    gs.solve(Dc, r1, z1, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    launch_level_prolong(p, L, d1, P2, e2.p, z1, nrhs, st);
+    gs.solve(above, r1, z1, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
     smooth_iters += h.n_post;
   }
 };
@@ -176,9 +180,9 @@ struct KCycle : Precond {
   void body(const void* r_s, void* z_s, int nrhs, hipStream_t st) {
     constexpr qmg_prec p = StoreTraits<S>::prec;
     launch_restrict(p, h, P, r_s, rc.p, nrhs, st);
-    if (h.l2) {
-      // three levels: flexible GMRES(32) on D_c preconditioned by the level-one K-cycle
-      if (!Kc) Kc.reset(new KCycleC<S>(h, Dc));
+    if (!h.levels.empty()) {
+      // further levels: flexible GMRES(32) on D_c preconditioned by the level-one K-cycle
+      if (!Kc) Kc.reset(new KCycleC<S>(h, 0, Dc));
       const int hint = last_coarse > 1 ? last_coarse - 1 : 0;
       auto rcs = gc.solve(Dc, rc.p, ec.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st, nullptr, hint, Kc.get());
       coarse_iters += rcs.iters;
@@ -472,14 +476,16 @@ void run_setup(qmg_mg* mg, hipStream_t st) {
 // ---------------------------------------------------------------------------------------
 // solve
 struct SolveStats {
-  long outer = 0, refinements = 0, coarse = 0, smooth = 0, escalations = 0, coarse2 = 0, smooth1 = 0;
+  long outer = 0, refinements = 0, coarse = 0, smooth = 0, escalations = 0;
+  long iters[4] = {0, 0, 0, 0}, smooths[4] = {0, 0, 0, 0};  // per level l = 2, 3 / l = 1, 2
   template <class K>
   void add_cycle(const K& k) {
     coarse += k.coarse_iters;
     smooth += k.smooth_iters;
-    if (k.Kc) {
-      coarse2 += k.Kc->coarse_iters;
-      smooth1 += k.Kc->smooth_iters;
+    int l = 2;
+    for (auto* c = k.Kc.get(); c && l < 4; c = c->next.get(), ++l) {
+      iters[l] += c->coarse_iters;
+      smooths[l - 1] += c->smooth_iters;
     }
   }
 };
@@ -780,9 +786,9 @@ std::unique_ptr<qmg_mg> new_hierarchy(const qmg_lattice* lat, const void* U, con
 // streams of coarse test vectors (Philox, level word 1) smoothed in FP64 on D_c, the chiral
 // split by the coarse chirality (the alpha block of every coarse site), the streaming SVD per
 // (aggregate, chirality), the Galerkin stencil and the inner-precision copies.
-void build_level_tables(CoarseLevel& L, const HierarchyDev& h) {
-  const int* cL1 = h.blk.cL;
-  const int d1 = h.blk.d;
+void build_level_tables(CoarseLevel& L, const StencilRef& above) {
+  const int* cL1 = above.cL;
+  const int d1 = above.d;
   std::vector<int> bsite(size_t(L.d) * L.nd), cnb(size_t(L.d) * 8), agg(d1), pos(d1);
   for (int j = 0; j < d1; ++j) {
     int c[4], rem = j;
@@ -824,12 +830,13 @@ void build_level_tables(CoarseLevel& L, const HierarchyDev& h) {
   up(L.pos, pos);
 }
 
-void run_level_setup(HierarchyDev& h, hipStream_t st) {
-  CoarseLevel& L = *h.l2;
+void run_level_setup(HierarchyDev& h, size_t i, hipStream_t st) {
+  CoarseLevel& L = *h.levels[i];
+  const StencilRef above = stencil_above(h, i);
   const auto t0 = Clock::now();
-  const int d1 = h.blk.d, m1 = 2 * h.k, r = L.batch, ns = L.n_test / L.batch;
+  const int d1 = above.d, m1 = 2 * above.k, r = L.batch, ns = L.n_test / L.batch;
   const size_t len = size_t(d1) * m1, n = size_t(r) * len;
-  CoarseOp Dc(h, QMG_F64, h.Y64.p);
+  StencilOp Dc(above.d, above.k, above.cnb, QMG_F64, above.Y64);  // the level above, FP64
   Gmres<double2> gm;
   DevBuf phi(n * sizeof(double2)), b(n * sizeof(double2)), x(n * sizeof(double2)), nrm(r * sizeof(double));
   DevBuf blocks(size_t(2) * L.d * r * L.N * sizeof(double2));
@@ -838,7 +845,7 @@ void run_level_setup(HierarchyDev& h, hipStream_t st) {
   L.sigma_dev.alloc(size_t(2) * L.d * L.k * sizeof(double));
   L.kp = 0;
   for (int s = 0; s < ns; ++s) {
-    launch_philox_coarse(L.seed, s * r, r, d1, m1, 1, phi.p, st);
+    launch_philox_coarse(L.seed, s * r, r, d1, m1, int(i) + 1, phi.p, st);  // level word l - 1
     if (L.n_setup_iter > 0) {  // psi = phi + psi', D_c psi' = -D_c phi by GMRES(8) from zero
       Dc.apply(phi.p, b.p, r, st);
       Blas<double2>::axpby(0.0, b.p, -1.0, b.p, n, st);
@@ -851,8 +858,8 @@ void run_level_setup(HierarchyDev& h, hipStream_t st) {
     L.kp = isvd_stream(2 * L.d, L.N, L.k, L.P64, blocks.p, r, L.kp, L.sigma_dev, st);
     L.streams_done = s + 1;
   }
-  QMG_CHECK(L.kp == L.k, QMG_ESHAPE, "third level: streaming SVD ended with %d < k columns", L.kp);
-  build_level_coarse(L, h, st);
+  QMG_CHECK(L.kp == L.k, QMG_ESHAPE, "further level: streaming SVD ended with %d < k columns", L.kp);
+  build_level_coarse(L, above, st);
   if (h.inner != QMG_F64) {
     const int m2 = 2 * L.k;
     const size_t np = size_t(2) * L.d * L.k * L.N, ny = size_t(L.d) * 9 * m2 * m2;
@@ -868,12 +875,17 @@ void run_level_setup(HierarchyDev& h, hipStream_t st) {
   L.t_total = secs(t0, Clock::now());
 }
 
-const CoarseLevel& level_for(const qmg_mg* mg, qmg_prec prec) {
+// level l >= 2 of the hierarchy (EINVAL when it has fewer levels)
+const CoarseLevel& level_at(const qmg_mg* mg, int l) {
   check_ptr(mg, "mg");
-  QMG_CHECK(mg->h.l2, QMG_EINVAL, "the hierarchy has no third level");
+  QMG_CHECK(l >= 2 && size_t(l - 2) < mg->h.levels.size(), QMG_EINVAL, "the hierarchy has no level %d", l);
+  return *mg->h.levels[l - 2];
+}
+const CoarseLevel& level_for(const qmg_mg* mg, int l, qmg_prec prec) {
+  const CoarseLevel& L = level_at(mg, l);
   QMG_CHECK(prec == QMG_F64 || (prec == mg->h.inner && prec == QMG_F32), QMG_EDTYPE,
             "precision must be F64 or the F32 inner precision");
-  return *mg->h.l2;
+  return L;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1030,11 +1042,12 @@ qmg_status qmg_mg_stream_more(qmg_mg* mg, int32_t n_streams, hipStream_t stream)
     else run_streams<float2>(mg, s0, s0 + n_streams, nullptr, stream);
     mg->params.n_test = mg->streams_done * mg->params.batch;
     finish_setup(mg, stream);
-    if (h.l2) {  // the third level is built on D_c: rebuild it (dropped if that fails)
+    // further levels are built on D_c and on each other: rebuild them in order (dropped if that fails)
+    for (size_t i = 0; i < h.levels.size(); ++i) {
       try {
-        run_level_setup(h, stream);
+        run_level_setup(h, i, stream);
       } catch (...) {
-        h.l2.reset();
+        h.levels.clear();
         throw;
       }
     }
@@ -1048,48 +1061,50 @@ qmg_status qmg_mg_add_level(qmg_mg* mg, const int32_t* block, int32_t n_test, in
     check_ptr(mg, "mg");
     check_ptr(block, "block");
     HierarchyDev& h = mg->h;
-    QMG_CHECK(!h.l2, QMG_EINVAL, "the hierarchy already has a third level");
-    QMG_CHECK(h.cycle_steps == 0, QMG_EINVAL, "a third level needs the host-checked K-cycle (coarse_steps = 0)");
+    QMG_CHECK(h.levels.size() < 2, QMG_EINVAL, "the hierarchy already has four levels");
+    QMG_CHECK(h.cycle_steps == 0, QMG_EINVAL, "further levels need the host-checked K-cycle (coarse_steps = 0)");
+    const size_t i = h.levels.size();
+    const StencilRef above = stencil_above(h, i);
     std::unique_ptr<CoarseLevel> L(new CoarseLevel());
     L->nd = 1;
     L->d = 1;
     for (int q = 0; q < 4; ++q) {
-      QMG_CHECK(block[q] >= 1 && h.blk.cL[q] % block[q] == 0, QMG_ESHAPE,
-                "third-level block extent %d (%d) does not divide coarse extent %d", q, block[q], h.blk.cL[q]);
+      QMG_CHECK(block[q] >= 1 && above.cL[q] % block[q] == 0, QMG_ESHAPE,
+                "level %d block extent %d (%d) does not divide extent %d of the level above", int(i) + 2, q,
+                block[q], above.cL[q]);
       L->b[q] = block[q];
-      L->cL[q] = h.blk.cL[q] / block[q];
+      L->cL[q] = above.cL[q] / block[q];
       L->nd *= block[q];
       L->d *= L->cL[q];
     }
-    L->k1 = h.k;
-    L->N = L->nd * h.k;
-    QMG_CHECK(L->N <= 4096, QMG_ESHAPE, "third level: block of %d rows exceeds 4096", L->N);
+    L->k1 = above.k;
+    L->N = L->nd * above.k;
+    QMG_CHECK(L->N <= 4096, QMG_ESHAPE, "further level: block of %d rows exceeds 4096", L->N);
     QMG_CHECK(batch >= 1 && batch <= 48, QMG_ESHAPE, "batch r must be in [1, 48]");
     QMG_CHECK(n_test >= batch && n_test % batch == 0, QMG_ESHAPE, "n_test must be a positive multiple of batch");
     QMG_CHECK(rank >= 1 && rank <= L->N && rank <= n_test && rank <= 32, QMG_ESHAPE,
-              "rank k must satisfy 1 <= k <= min(k1 * prod(block), n_test, 32)");
+              "rank k must satisfy 1 <= k <= min(k_above * prod(block), n_test, 32)");
     QMG_CHECK(n_setup_iter >= 0, QMG_EINVAL, "n_setup_iter must be non-negative");
     L->k = rank;
     L->n_test = n_test;
     L->batch = batch;
     L->n_setup_iter = n_setup_iter;
     L->seed = seed;
-    build_level_tables(*L, h);
-    h.l2 = std::move(L);
+    build_level_tables(*L, above);
+    h.levels.push_back(std::move(L));
     try {
-      run_level_setup(h, stream);
+      run_level_setup(h, i, stream);
     } catch (...) {
-      h.l2.reset();
+      h.levels.pop_back();
       throw;
     }
   });
 }
 
-qmg_status qmg_mg_level_query(const qmg_mg* mg, int32_t* coarse_dims, int32_t* n_agg, int32_t* rank) {
+qmg_status qmg_mg_level_query(const qmg_mg* mg, int32_t level, int32_t* coarse_dims, int32_t* n_agg,
+                              int32_t* rank) {
   return guard([&] {
-    check_ptr(mg, "mg");
-    QMG_CHECK(mg->h.l2, QMG_EINVAL, "the hierarchy has no third level");
-    const CoarseLevel& L = *mg->h.l2;
+    const CoarseLevel& L = level_at(mg, level);
     if (coarse_dims)
       for (int q = 0; q < 4; ++q) coarse_dims[q] = L.cL[q];
     if (n_agg) *n_agg = L.d;
@@ -1097,11 +1112,9 @@ qmg_status qmg_mg_level_query(const qmg_mg* mg, int32_t* coarse_dims, int32_t* n
   });
 }
 
-qmg_status qmg_mg_level_get(const qmg_mg* mg, void* P, double* sigma, void* Y, hipStream_t stream) {
+qmg_status qmg_mg_level_get(const qmg_mg* mg, int32_t level, void* P, double* sigma, void* Y, hipStream_t stream) {
   return guard([&] {
-    check_ptr(mg, "mg");
-    QMG_CHECK(mg->h.l2, QMG_EINVAL, "the hierarchy has no third level");
-    const CoarseLevel& L = *mg->h.l2;
+    const CoarseLevel& L = level_at(mg, level);
     if (P) launch_level_export_P(L, P, stream);
     if (Y) launch_level_export_Y(L, Y, stream);
     if (sigma) std::memcpy(sigma, L.sigma.data(), L.sigma.size() * sizeof(double));
@@ -1109,32 +1122,34 @@ qmg_status qmg_mg_level_get(const qmg_mg* mg, void* P, double* sigma, void* Y, h
   });
 }
 
-qmg_status qmg_level_prolong(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
-                             hipStream_t stream) {
+qmg_status qmg_level_prolong(const qmg_mg* mg, int32_t level, const void* in, void* out, int32_t nrhs,
+                             qmg_prec prec, hipStream_t stream) {
   return guard([&] {
-    const CoarseLevel& L = level_for(mg, prec);
+    const CoarseLevel& L = level_for(mg, level, prec);
     check_ptr(in, "in");
     check_ptr(out, "out");
     QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
-    launch_level_prolong(prec, L, mg->h.blk.d, prec == QMG_F64 ? L.P64.p : L.Pin.p, in, out, nrhs, stream);
+    const int d_above = stencil_above(mg->h, size_t(level) - 2).d;
+    launch_level_prolong(prec, L, d_above, prec == QMG_F64 ? L.P64.p : L.Pin.p, in, out, nrhs, stream);
   });
 }
 
-qmg_status qmg_level_restrict(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
-                              hipStream_t stream) {
+qmg_status qmg_level_restrict(const qmg_mg* mg, int32_t level, const void* in, void* out, int32_t nrhs,
+                              qmg_prec prec, hipStream_t stream) {
   return guard([&] {
-    const CoarseLevel& L = level_for(mg, prec);
+    const CoarseLevel& L = level_for(mg, level, prec);
     check_ptr(in, "in");
     check_ptr(out, "out");
     QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
-    launch_level_restrict(prec, L, mg->h.blk.d, prec == QMG_F64 ? L.P64.p : L.Pin.p, in, out, nrhs, stream);
+    const int d_above = stencil_above(mg->h, size_t(level) - 2).d;
+    launch_level_restrict(prec, L, d_above, prec == QMG_F64 ? L.P64.p : L.Pin.p, in, out, nrhs, stream);
   });
 }
 
-qmg_status qmg_level_coarse_apply(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
-                                  hipStream_t stream) {
+qmg_status qmg_level_coarse_apply(const qmg_mg* mg, int32_t level, const void* in, void* out, int32_t nrhs,
+                                  qmg_prec prec, hipStream_t stream) {
   return guard([&] {
-    const CoarseLevel& L = level_for(mg, prec);
+    const CoarseLevel& L = level_for(mg, level, prec);
     check_ptr(in, "in");
     check_ptr(out, "out");
     QMG_CHECK(in != out, QMG_EINVAL, "in and out must not alias");
@@ -1349,8 +1364,10 @@ qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, 
       info[i].precision_escalations = int(ss.escalations);
       info[i].true_rel_res = i < int(rel.size()) ? rel[i] : tr;
       info[i].seconds = el;
-      info[i].coarse2_iters = int(ss.coarse2);
-      info[i].smoother1_iters = int(ss.smooth1);
+      info[i].coarse2_iters = int(ss.iters[2]);
+      info[i].smoother1_iters = int(ss.smooths[1]);
+      info[i].coarse3_iters = int(ss.iters[3]);
+      info[i].smoother2_iters = int(ss.smooths[2]);
     }
   }
   return rc;
@@ -1474,8 +1491,8 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph) {
     QMG_CHECK(coarse_steps >= 0 && coarse_steps <= 63, QMG_EINVAL, "coarse_steps must be in [0, 63]");
     QMG_CHECK(graph == 0 || graph == 1, QMG_EINVAL, "graph must be 0 or 1");
     QMG_CHECK(!graph || coarse_steps > 0, QMG_EINVAL, "a captured K-cycle needs coarse_steps > 0");
-    QMG_CHECK(coarse_steps == 0 || !mg->h.l2, QMG_EINVAL,
-              "with a third level the K-cycle is host-checked (coarse_steps must be 0)");
+    QMG_CHECK(coarse_steps == 0 || mg->h.levels.empty(), QMG_EINVAL,
+              "with further levels the K-cycle is host-checked (coarse_steps must be 0)");
     mg->h.cycle_steps = coarse_steps;
     mg->h.cycle_graph = graph != 0;
   });

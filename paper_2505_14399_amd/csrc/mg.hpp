@@ -2,6 +2,7 @@
 #pragma once
 
 #include <memory>
+#include <vector>
 
 #include "krylov.hpp"
 
@@ -49,8 +50,35 @@ struct HierarchyDev {
   double coarse_tol = 0.03;
   int cycle_steps = 0;       // > 0: device-exit coarse solve with this step budget
   bool cycle_graph = false;  // capture the K-cycle into a hipGraph (needs cycle_steps > 0)
-  std::unique_ptr<CoarseLevel> l2;  // optional third level
+  std::vector<std::unique_ptr<CoarseLevel>> levels;  // further levels (l = 2, 3), each on the one above
 };
+
+// The nine-block stencil that a further level is built on: the first coarse level's D_c, or the
+// operator of the previous further level.
+struct StencilRef {
+  int cL[4];
+  int d, k;
+  const int* cnb;
+  const void* Y64;
+};
+inline StencilRef stencil_above(const HierarchyDev& h, size_t i) {
+  StencilRef s{};
+  if (i == 0) {
+    for (int q = 0; q < 4; ++q) s.cL[q] = h.blk.cL[q];
+    s.d = h.blk.d;
+    s.k = h.k;
+    s.cnb = h.cnb.as<int>();
+    s.Y64 = h.Y64.p;
+  } else {
+    const CoarseLevel& L = *h.levels[i - 1];
+    for (int q = 0; q < 4; ++q) s.cL[q] = L.cL[q];
+    s.d = L.d;
+    s.k = L.k;
+    s.cnb = L.cnb.as<int>();
+    s.Y64 = L.Y64.p;
+  }
+  return s;
+}
 
 // prolong: fine[rhs] (native, storage S) = P coarse[rhs]
 void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const void* coarse, void* fine, int nrhs,
@@ -73,8 +101,8 @@ void launch_level_prolong(qmg_prec prec, const CoarseLevel& L, int d1, const voi
                           int nrhs, hipStream_t st);
 void launch_level_restrict(qmg_prec prec, const CoarseLevel& L, int d1, const void* P, const void* v1, void* v2,
                            int nrhs, hipStream_t st);
-// Y2 = P2^dag D_c P2 in FP64 from the level above (its Y64, cnb and coarse extents)
-void build_level_coarse(CoarseLevel& L, const HierarchyDev& h, hipStream_t st);
+// Y2 = P2^dag A P2 in FP64 from the stencil A of the level above
+void build_level_coarse(CoarseLevel& L, const StencilRef& above, hipStream_t st);
 // canonical exports of the third level: P [d][2][N][k] with rows (jb * k1 + i), Y [d][9][2k][2k]
 void launch_level_export_P(const CoarseLevel& L, void* out, hipStream_t st);
 void launch_level_export_Y(const CoarseLevel& L, void* out, hipStream_t st);

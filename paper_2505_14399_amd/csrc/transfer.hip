@@ -1100,26 +1100,26 @@ void launch_level_restrict(qmg_prec prec, const CoarseLevel& L, int d1, const vo
   QMG_LAUNCH_CHECK();
 }
 
-void build_level_coarse(CoarseLevel& L, const HierarchyDev& h, hipStream_t st) {
+void build_level_coarse(CoarseLevel& L, const StencilRef& h, hipStream_t st) {
   const int m2 = 2 * L.k, m1 = 2 * L.k1;
   QMG_CHECK(m2 <= 64 && m1 <= 64, QMG_ESHAPE, "third level: 2k <= 64 on both levels");
   LevelBuildArgs a{};
   for (int q = 0; q < 4; ++q) {
-    a.cL1[q] = h.blk.cL[q];
+    a.cL1[q] = h.cL[q];
     a.b[q] = L.b[q];
   }
   a.nd = L.nd;
   a.k1 = L.k1;
   a.k = L.k;
-  a.d1 = h.blk.d;
+  a.d1 = h.d;
   a.d = L.d;
   L.Y64.alloc(size_t(L.d) * 9 * m2 * m2 * sizeof(double2));
   const size_t lds = (size_t(m1) * m2 + size_t(4) * L.k * L.k1) * sizeof(cplx<double>);
   QMG_CHECK(lds <= 160 * 1024, QMG_ESHAPE, "third level: coarse build needs too much LDS");
   if (lds > 64 * 1024)
     QMG_HIP(hipFuncSetAttribute((const void*)k_level_build, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  TimedLaunch tl("level_build", st, 0.0, 8.0 * 2.0 * double(m1) * m2 * (m1 / 2 + m2 / 2) * h.blk.d * 9, false);
-  k_level_build<<<dim3(L.d, 9), 256, lds, st>>>(h.Y64.as<double2>(), h.cnb.as<int>(), L.P64.as<double2>(),
+  TimedLaunch tl("level_build", st, 0.0, 8.0 * 2.0 * double(m1) * m2 * (m1 / 2 + m2 / 2) * h.d * 9, false);
+  k_level_build<<<dim3(L.d, 9), 256, lds, st>>>((const double2*)h.Y64, h.cnb, L.P64.as<double2>(),
                                                  L.bsite.as<int>(), L.agg.as<int>(), L.pos.as<int>(),
                                                  L.Y64.as<double2>(), a);
   QMG_LAUNCH_CHECK();

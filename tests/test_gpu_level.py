@@ -93,17 +93,21 @@ def test_three_level_solve(qmg, inner):
 def test_level_errors(qmg):
     banner("third level errors")
     mg, _ = _hier(qmg, (4, 4, 4, 8), (2, 2, 2, 2), 8, 4, 4, "f64", 55)
-    with pytest.raises(qmg.QmgError, match="no third level"):
+    with pytest.raises(qmg.QmgError, match="no level 2"):
         qmg.level_coarse_apply(mg, torch.zeros(1, 1, 2, 1, dtype=torch.complex128, device="cuda"))
     with pytest.raises(qmg.QmgError, match="does not divide"):
         mg.add_level((3, 1, 1, 1), 8, 4, 4)
     with pytest.raises(qmg.QmgError, match="rank"):
         mg.add_level((2, 2, 2, 2), 8, 4, 40)
     mg.add_level((2, 2, 2, 2), 8, 4, 4, n_setup_iter=2)
-    with pytest.raises(qmg.QmgError, match="already"):
-        mg.add_level((2, 2, 2, 2), 8, 4, 4)
     with pytest.raises(qmg.QmgError, match="host-checked"):
         mg.set_cycle(coarse_steps=12)
+    mg.level_coarse_blocks(level=2)  # level 2 exists, level 3 not yet
+    assert qmg.load_library().qmg_mg_level_query(mg.handle, 3, None, None, None) == -1
+    assert b"no level 3" in qmg.load_library().qmg_last_error()
+    mg.add_level((1, 1, 1, 2), 8, 4, 4, n_setup_iter=2)
+    with pytest.raises(qmg.QmgError, match="four levels"):
+        mg.add_level((1, 1, 1, 1), 8, 4, 4)
     mg.close()
 
 
@@ -120,3 +124,50 @@ def test_more_streams_rebuild_the_third_level(qmg):
     assert np.array_equal(a.level_prolongator()[1], b.level_prolongator()[1])
     a.close()
     b.close()
+
+
+def test_fourth_level_matches_oracle(qmg):
+    """A fourth level on the third level's operator (Philox level word 2): its setup against the
+    oracle run on the GPU's level-2 stencil, its Galerkin stencil, transfer and operator; and the
+    four-level solve gives the two-level solution."""
+    banner("fourth level parity and solve")
+    dims = (8, 8, 8, 8)
+    mg, U = _hier(qmg, dims, (2, 2, 2, 2), 12, 4, 6, "f64", 57, mass=-0.3, eps=0.4)
+    mg.add_level((2, 2, 2, 2), 12, 4, 6, n_setup_iter=4, seed=5)
+    block3 = (1, 2, 2, 2)
+    assert mg.add_level(block3, 8, 4, 5, n_setup_iter=4, seed=5) == 3
+    assert mg.levels[3]["dims"] == (2, 1, 1, 1)
+    Y2 = to_np(mg.level_coarse_blocks(2))
+    cd2 = mg.levels[2]["dims"]
+    lv = level.setup(Y2, cd2, block3, 8, 4, 5, n_setup_iter=4, seed=5, level=2)
+    P3, sig3 = mg.level_prolongator(3)
+    P3 = to_np(P3)
+    assert np.abs(sig3 - lv.sigma).max() < 1e-10 * lv.sigma.max()
+    for J in range(P3.shape[0]):
+        for a in range(2):
+            g, o = P3[J, a], lv.P[J, a]
+            assert np.abs(g @ np.conj(g).T - o @ np.conj(o).T).max() < 1e-9
+    Y3 = to_np(mg.level_coarse_blocks(3))
+    k2 = mg.levels[2]["rank"]
+    assert rel(Y3, level.galerkin(Y2, P3, cd2, block3, k2)) < 1e-12
+    rng = np.random.default_rng(4)
+    d2, d3, k3 = mg.levels[2]["n_agg"], mg.levels[3]["n_agg"], mg.levels[3]["rank"]
+    v3 = rng.normal(size=(2, d3, 2, k3)) + 1j * rng.normal(size=(2, d3, 2, k3))
+    v2 = rng.normal(size=(2, d2, 2, k2)) + 1j * rng.normal(size=(2, d2, 2, k2))
+    g = lambda a: torch.from_numpy(a).cuda()
+    got = to_np(qmg.level_prolong(mg, g(v3), level=3)).reshape(2, d2, 2 * k2)
+    assert rel(got, level.prolong(P3, v3, cd2, block3, k2)) < 1e-13
+    got = to_np(qmg.level_restrict(mg, g(v2), level=3))
+    assert rel(got, level.restrict(P3, v2.reshape(2, d2, 2 * k2), cd2, block3, k2)) < 1e-13
+    got = to_np(qmg.level_coarse_apply(mg, g(v3), level=3))
+    assert rel(got, coarse.coarse_apply(Y3, v3, mg.levels[3]["dims"])) < 1e-13
+    b = to_gpu(fields.gaussian_spinor(dims, 1, 58))
+    x4, i4 = qmg.mg_solve(mg, b, tol=1e-12)
+    assert i4[0]["true_rel_res"] < 1e-12 and i4[0]["coarse3_iters"] > 0 and i4[0]["smoother2_iters"] > 0
+    mg2, _ = _hier(qmg, dims, (2, 2, 2, 2), 12, 4, 6, "f64", 57, mass=-0.3, eps=0.4)
+    x2, _ = qmg.mg_solve(mg2, b, tol=1e-12)
+    assert rel(to_np(x4), to_np(x2)) < 1e-8
+    print(f"[levels] four levels: {i4[0]['outer_iters']} / {i4[0]['coarse_iters']} / {i4[0]['coarse2_iters']} / "
+          f"{i4[0]['coarse3_iters']}")
+    mg.close()
+    mg2.close()
