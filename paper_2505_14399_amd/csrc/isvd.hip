@@ -177,6 +177,100 @@ __global__ __launch_bounds__(T) void k_isvd_gram(const double2* __restrict__ Ug,
   }
 }
 
+// Gram kernel on the FP64 matrix cores: C = W^dag B with W the w columns [U, Psi or R] and B
+// the r columns of Psi or R, as real 16x16x4 products (Re C = Wr^T Br + Wi^T Bi, Im C =
+// Wr^T Bi - Wi^T Br); TM row tiles of 16 (w <= 16 TM) by one column tile (r <= 16).  Wavefront v
+// takes the 4-row steps v, v + 4, ... of every chunk (split-K); the four partial tiles are summed
+// in LDS as in the vector kernel.  Operand layout of the 16x16x4 FP64 instruction: lane l holds
+// A(l % 16, l / 16) and B(l / 16, l % 16); result register q of lane l is C(l / 16 + 4 q, l % 16).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int NPF, int TM>
+__global__ __launch_bounds__(T) void k_isvd_gram_mfma(const double2* __restrict__ Ug, const double2* __restrict__ Psig,
+                                                      double2* __restrict__ small, IsvdArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = a.N, kp = a.kp, r = a.r, w = a.w, k = a.k;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int NW = T / 64;                     // wavefronts (row groups of the reduction)
+  cd* chunk = reinterpret_cast<cd*>(smem_raw);   // [w][CHP]
+  cd* Xs = chunk + size_t(w) * CHP;              // [kp][r]  X of pass 1
+  cd* red = Xs + size_t(kp) * r;                 // reduction buffer [NW][w][r]
+  const size_t sstride = small_stride(kp, r);
+
+  for (int p = blockIdx.x; p < a.nprob; p += gridDim.x) {
+    const double2* U = Ug + size_t(p) * k * N;
+    const double2* Psi = Psig + size_t(p) * r * N;
+    double2* sm = small + size_t(p) * sstride;
+    for (int pass = 0; pass < 2; ++pass) {
+      v4d cr[TM], ci[TM];
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        cr[tm] = v4d{0.0, 0.0, 0.0, 0.0};
+        ci[tm] = v4d{0.0, 0.0, 0.0, 0.0};
+      }
+      cd reg[NPF];
+      prefetch<NPF>(reg, U, Psi, kp, w, N, 0, tid);
+      for (int r0 = 0; r0 < N; r0 += CH) {
+        stage<NPF>(chunk, reg, w, tid);
+        __syncthreads();
+        if (r0 + CH < N) prefetch<NPF>(reg, U, Psi, kp, w, N, r0 + CH, tid);
+        if (pass == 1 && kp > 0) {
+          // residual R = Psi - U X in place over the Psi columns of the chunk
+          for (int t = tid; t < r * CH; t += T) {
+            const int b = t / CH, row = t - b * CH;
+            cd v = chunk[(kp + b) * CHP + row];
+#pragma unroll 4
+            for (int aa = 0; aa < kp; ++aa) v -= chunk[aa * CHP + row] * Xs[aa * r + b];
+            chunk[(kp + b) * CHP + row] = v;
+          }
+          __syncthreads();
+        }
+        for (int ks = wv; ks < CH / 4; ks += NW) {
+          const int row = 4 * ks + lk;
+          const cd bv = li < r ? chunk[(kp + li) * CHP + row] : cd{0.0, 0.0};
+#pragma unroll
+          for (int tm = 0; tm < TM; ++tm) {
+            const int aa = tm * 16 + li;
+            const cd av = aa < w ? chunk[aa * CHP + row] : cd{0.0, 0.0};
+            cr[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.re, cr[tm], 0, 0, 0);
+            cr[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.im, bv.im, cr[tm], 0, 0, 0);
+            ci[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.im, ci[tm], 0, 0, 0);
+            ci[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.im, bv.re, ci[tm], 0, 0, 0);
+          }
+        }
+        __syncthreads();
+      }
+      // this wavefront's partial tiles -> red[wv]
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int aa = tm * 16 + lk + 4 * q, bb = li;
+          if (aa < w && bb < r) red[(size_t(wv) * w + aa) * r + bb] = cd{cr[tm][q], ci[tm][q]};
+        }
+      __syncthreads();
+      for (int e = tid; e < w * r; e += T) {
+        cd s = {0, 0};
+        for (int g = 0; g < NW; ++g) s += red[size_t(g) * w * r + e];
+        const int aa = e / r, bb = e - aa * r;
+        if (pass == 0) {
+          if (aa < kp) {
+            Xs[e] = s;
+            st2(sm, e, s);                                          // X
+          } else if (aa - kp == bb) {
+            st2(sm, size_t(2) * kp * r + size_t(r) * r + bb, s);    // pn = |Psi_b|^2
+          }
+        } else {
+          if (aa < kp) st2(sm, size_t(kp) * r + e, s);              // X2
+          else st2(sm, size_t(2) * kp * r + size_t(aa - kp) * r + bb, s);  // G
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // small dense part: one wavefront per problem
 constexpr int TW = 128;  // two wavefronts per small problem
@@ -454,10 +548,14 @@ __global__ __launch_bounds__(T) void k_isvd_rotate_rows(double2* __restrict__ Ug
   }
 }
 
+// the matrix-core Gram kernel takes one column tile (r <= 16) and 16 < w <= 64 (for w <= 16 a
+// 16 x 16 tile wastes most of its products and the vector kernel is faster)
+inline bool gram_on_mfma(int w, int r) { return r <= 16 && w > 16 && w <= 64; }
 size_t gram_lds(int kp, int r) {
   const int w = kp + r;
   const int ta = (w + 1) / 2, tb = (r + 1) / 2, ntile = ta * tb;
-  const int nrg = std::max(1, T / ntile);
+  // row groups of the reduction: the wavefronts (matrix-core kernel) or T / tiles (vector kernel)
+  const int nrg = gram_on_mfma(w, r) ? T / 64 : std::max(1, T / ntile);
   return (size_t(w) * CHP + size_t(kp) * r + size_t(nrg) * w * r) * sizeof(cd);
 }
 size_t small_lds(int kp, int r) {
@@ -482,7 +580,15 @@ void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, DevBuf& P64, 
   set_lds((const void*)k_isvd_rotate<NPF>, lr);
   const int grid = std::min(a.nprob, 4 * ncu);
   const int ntile = ((a.w + 1) / 2) * ((a.r + 1) / 2);
-  if (ntile <= T) {
+  if (gram_on_mfma(a.w, a.r)) {
+    if (a.w <= 32) {
+      set_lds((const void*)k_isvd_gram_mfma<NPF, 2>, lg);
+      k_isvd_gram_mfma<NPF, 2><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+    } else {
+      set_lds((const void*)k_isvd_gram_mfma<NPF, 4>, lg);
+      k_isvd_gram_mfma<NPF, 4><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+    }
+  } else if (ntile <= T) {
     set_lds((const void*)k_isvd_gram<NPF, 1>, lg);
     k_isvd_gram<NPF, 1><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
   } else {
