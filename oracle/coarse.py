@@ -33,8 +33,11 @@ def fine_rows(U, dims, block):
     return Pf
 
 
-def build_coarse(G, U, mass, xi, bc_t, dims, block, chunk=4096):
-    """Y [d][9][2k][2k] from gauge links G [4][V][3][3] and prolongator blocks U [d][2][N][k]."""
+def build_coarse(G, U, mass, xi, bc_t, dims, block, chunk=4096, T=None):
+    """Y [d][9][2k][2k] from gauge links G [4][V][3][3] and prolongator blocks U [d][2][N][k].
+
+    T: optional clover term [V][12][12] (clover.py), added to the diagonal term (it is site
+    local, so it only enters Y_0)."""
     agg, _ = aggregate_map(dims, block)
     cd = coarse_dims(dims, block)
     d = volume(cd)
@@ -48,6 +51,8 @@ def build_coarse(G, U, mass, xi, bc_t, dims, block, chunk=4096):
     V = volume(dims)
     # diagonal term
     diag = diag_term(mass, xi) * np.einsum("xsi,xsl->xil", np.conj(Pf), Pf)
+    if T is not None:
+        diag = diag + np.einsum("xsi,xst,xtl->xil", np.conj(Pf), T, Pf)
     np.add.at(Y, (agg, 0), diag)
     for dd in range(8):
         mu = dd % 4

@@ -17,18 +17,26 @@ iterations and coarse solves to 0.03 ||b||):
 """
 import numpy as np
 
-from . import wilson, krylov, icsvd as ic, transfer, coarse, philox
+from . import wilson, clover, krylov, icsvd as ic, transfer, coarse, philox
 from .geometry import volume, coarse_dims
 
 
 class Lattice:
-    def __init__(self, U, dims, mass, xi=1.0, bc_t=-1):
+    """The fine operator: Wilson, or Wilson-clover when the clover term T [V][12][12]
+    (clover.clover_term) is given."""
+
+    def __init__(self, U, dims, mass, xi=1.0, bc_t=-1, T=None):
         self.U, self.dims, self.mass, self.xi, self.bc_t = U, tuple(dims), mass, xi, bc_t
+        self.T = T
 
     def D(self, psi):
+        if self.T is not None:
+            return clover.apply_clover(self.U, self.T, psi, self.mass, self.xi, self.bc_t, self.dims)
         return wilson.apply_wilson(self.U, psi, self.mass, self.xi, self.bc_t, self.dims)
 
     def Ddag(self, psi):
+        if self.T is not None:
+            return clover.apply_clover(self.U, self.T, psi, self.mass, self.xi, self.bc_t, self.dims, dagger=True)
         return wilson.apply_wilson(self.U, psi, self.mass, self.xi, self.bc_t, self.dims, dagger=True)
 
 
@@ -70,7 +78,7 @@ def setup(lat, block, n_test, batch, rank, n_setup_iter=16, seed=0, test_vectors
     h.lat, h.block, h.k = lat, tuple(block), rank
     h.cdims = coarse_dims(lat.dims, block)
     h.P, h.sigma, h.sigma_hist = ic.icsvd(streams(), n_s, lat.dims, block, rank)
-    h.Y = coarse.build_coarse(lat.U, h.P, lat.mass, lat.xi, lat.bc_t, lat.dims, block)
+    h.Y = coarse.build_coarse(lat.U, h.P, lat.mass, lat.xi, lat.bc_t, lat.dims, block, T=lat.T)
     return h
 
 
