@@ -98,6 +98,35 @@ qmg_status qmg_wilson_apply_batched(int32_t n_lat, const qmg_lattice* lats, cons
                                     const void* const* in, void* const* out, int32_t nrhs, qmg_prec prec,
                                     int32_t dagger, hipStream_t stream);
 
+/* Wilson-clover operator D_sw = D + T, the operator of the paper's experiments (Section 4: Wilson
+ * fermions with the clover term), which the paper names but does not write out.  The reading
+ * implemented: the O(a)-improvement term of Luescher, Sint, Sommer and Weisz (1996) in the
+ * normalisation of D above,
+ *   T(x) = sum_{mu<nu} c_{mu nu} (i/2) sigma_{mu nu} (x) Fhat_{mu nu}(x),
+ *   sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu],  Fhat_{mu nu} = (Q_{mu nu} - Q_{mu nu}^dag)/8,
+ * Q_{mu nu}(x) the four plaquettes of the mu-nu plane with a corner at x, each walked
+ * counter-clockwise (a mu step before a nu step), no trace subtraction; c_{mu nu} = c_sw_t for
+ * the three planes containing t and c_sw_s for the spatial planes (c_sw_s = c_sw_t = c_sw: the
+ * isotropic term).  The gauge field is periodic in every direction, so T ignores bc_t.  T(x) is
+ * hermitian and commutes with gamma_5, so D_sw^dagger = gamma_5 D_sw gamma_5.
+ *
+ * qmg_clover_field: A = the site-local part (m + 1 + 3/xi) 1 + T(x) of D_sw, packed.
+ * U: device, canonical FP64 gauge field.  A: device, 36 V complex numbers in precision prec
+ *   (written): per chirality alpha (spins 0,1 for alpha = 0, spins 2,3 for alpha = 1) a
+ *   hermitian 6 x 6 block over (spin within the chirality, colour), stored site-fastest at
+ *   A[(alpha*18 + e)*V + x]; e = 0, 1, 2 hold the real diagonal entries (2e, 2e+1) as the (re, im)
+ *   pair of one complex number, e = 3 .. 17 the upper triangle (i < j) row by row.  The
+ *   computation is FP64 whatever prec is; it synchronizes the stream (it frees a temporary).
+ * Errors: EINVAL (null, bad enum, non-finite coefficient), ESHAPE (extents), ENOMEM, EHIP. */
+qmg_status qmg_clover_field(const qmg_lattice* lat, double c_sw_s, double c_sw_t, const void* U, void* A,
+                            qmg_prec prec, hipStream_t stream);
+/* out = D_sw in (dagger = 0) or D_sw^dagger in (dagger = 1): the stencil of qmg_wilson_apply with
+ * the packed site term A (from qmg_clover_field, device, precision prec) in place of its
+ * diagonal term, fused into the same kernels.  U, in, out as in qmg_wilson_apply; out must
+ * not alias in.  Errors: EINVAL (null, nrhs < 1, bad enum, aliasing), ESHAPE, EHIP. */
+qmg_status qmg_clover_apply(const qmg_lattice* lat, const void* U, const void* A, const void* in, void* out,
+                            int32_t nrhs, qmg_prec prec, qmg_layout layout, int32_t dagger, hipStream_t stream);
+
 /* Layout/precision conversion: canonical FP64 <-> native `prec` (device buffers, no aliasing). */
 qmg_status qmg_pack_spinor(const qmg_lattice* lat, const void* canon_f64, void* native, int32_t nrhs,
                            qmg_prec prec, hipStream_t stream);
@@ -122,6 +151,8 @@ typedef struct {
   uint64_t seed;         /* Philox4x32-10 key for the random initial guesses phi             */
   const void* test_vectors; /* optional device buffer, canonical FP64 [n_test][V][4][3]: the
                                initial guesses phi (NULL: internal counter RNG)               */
+  double c_sw_s;         /* clover coefficients of the fine operator (qmg_clover_field): spatial */
+  double c_sw_t;         /*   planes and planes containing t; both 0 (default): Wilson          */
 } qmg_mg_params;
 
 typedef struct qmg_mg qmg_mg; /* opaque two-level hierarchy: P (FP64 and inner copy), D_c */
@@ -131,7 +162,10 @@ typedef struct qmg_mg qmg_mg; /* opaque two-level hierarchy: P (FP64 and inner c
  * chirality and blocked (Eq. (3)), and every (aggregate, chirality) block updates its rank-k
  * SVD of [Phi_{s-1}, Psi_s] (Eq. (8)); the last stream gives P = U_k (Eq. (6)), R = P^dag and
  * D_c = R D P (Eq. (5)).
- * U: device, canonical FP64 gauge field; it is copied into the handle.
+ * U: device, canonical FP64 gauge field; it is copied into the handle.  With a non-zero clover
+ * coefficient in params the fine operator is D_sw (qmg_clover_field's site term is built from U
+ * and kept beside every gauge copy): smoothing, the Galerkin product (the site term enters
+ * Y_0), the smoother and the outer solve all use it.
  * Errors: EINVAL, ESHAPE (block does not divide, k or r out of range, n_test % batch,
  *   n_test < k), ENOMEM, EHIP, ENONFINITE (non-finite links). On error *out is NULL. */
 qmg_status qmg_mg_setup_stream_chiral_svd(const qmg_lattice* lat, const void* U, const qmg_mg_params* params,
@@ -249,7 +283,8 @@ qmg_status qmg_mg_get_params(const qmg_mg* mg, qmg_lattice* lat, qmg_mg_params* 
  * ENOMEM, EHIP. */
 qmg_status qmg_mg_stream_more(qmg_mg* mg, int32_t n_streams, hipStream_t stream);
 
-/* Hierarchy checkpoint.  qmg_mg_save writes the lattice, the setup parameters, the number of
+/* Hierarchy checkpoint.  qmg_mg_save writes the lattice, the setup parameters (with the clover
+ * coefficients), the number of
  * streams done, a 64-bit hash of the gauge field, the singular values and the factor U_k (= P)
  * in FP64 to `path` (a little-endian binary file ending in a hash of its arrays).
  * qmg_mg_load rebuilds the hierarchy from such a file for the gauge field U (device, canonical

@@ -44,7 +44,8 @@ class qmg_mg_params(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32 * 4), ("n_test", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("rank", ctypes.c_int32), ("n_setup_iter", ctypes.c_int32), ("n_post_smooth", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("coarse_max_iter", ctypes.c_int32),
-                ("inner_prec", ctypes.c_int32), ("seed", ctypes.c_uint64), ("test_vectors", ctypes.c_void_p)]
+                ("inner_prec", ctypes.c_int32), ("seed", ctypes.c_uint64), ("test_vectors", ctypes.c_void_p),
+                ("c_sw_s", ctypes.c_double), ("c_sw_t", ctypes.c_double)]
 
 
 class qmg_solve_info(ctypes.Structure):
@@ -62,6 +63,8 @@ SIGNATURES = {
     "qmg_wilson_apply": [_P, _P, _P, _P, _I, _I, _I, _P],
     "qmg_wilson_apply_adj": [_P, _P, _P, _P, _I, _I, _I, _P],
     "qmg_wilson_apply_batched": [_I, _P, _P, _P, _P, _I, _I, _I, _P],
+    "qmg_clover_field": [_P, _D, _D, _P, _P, _I, _P],
+    "qmg_clover_apply": [_P, _P, _P, _P, _P, _I, _I, _I, _I, _P],
     "qmg_pack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_unpack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_pack_gauge": [_P, _P, _P, _I, _P],
@@ -226,6 +229,37 @@ def wilson_apply_batched(lats: Sequence[Lattice], Us, psis, outs=None, dagger=Fa
     # the pointer table must outlive the launch: keep it until the stream has passed it
     torch.cuda.current_stream().synchronize()
     return outs
+
+
+def clover_field(lat: Lattice, U, c_sw_s, c_sw_t=None, prec="f64"):
+    """The packed site term (m + 1 + 3/xi) + T(x) of the Wilson-clover operator (see qmg.h:
+    qmg_clover_field) from the canonical complex128 gauge field U [4,V,3,3]: [2,18,V] in `prec`
+    (BF16/FP16: [2,18,V,2] real pairs).  c_sw_t defaults to c_sw_s (the isotropic term)."""
+    lib = load_library()
+    if U.dtype != torch.complex128:
+        raise TypeError("the clover field is built from the FP64 canonical gauge field")
+    p = _PREC[prec]
+    shape = (2, 18, lat.volume, 2) if p in (BF16, F16) else (2, 18, lat.volume)
+    out = torch.empty(shape, dtype=_dtype_of(p), device=U.device)
+    s = lat.c()
+    ct = c_sw_s if c_sw_t is None else c_sw_t
+    _check(lib.qmg_clover_field(ctypes.byref(s), float(c_sw_s), float(ct), _ptr(U), _ptr(out), p, _stream()))
+    return out
+
+
+def clover_apply(lat: Lattice, U, A, psi, layout="canonical", dagger=False, out=None):
+    """out = D_sw psi (D_sw^dagger psi if dagger): U and psi as in wilson_apply, A from
+    clover_field in the same precision."""
+    lib = load_library()
+    prec = _prec_of(psi)
+    if _prec_of(U) != prec or _prec_of(A) != prec:
+        raise TypeError("U, A and psi must have the same precision")
+    nrhs = psi.shape[0]
+    out = torch.empty_like(psi) if out is None else out
+    s = lat.c()
+    _check(lib.qmg_clover_apply(ctypes.byref(s), _ptr(U), _ptr(A), _ptr(psi), _ptr(out), nrhs, prec,
+                                CANONICAL if layout == "canonical" else NATIVE, 1 if dagger else 0, _stream()))
+    return out
 
 
 def _native_spinor_shape(nrhs, V, prec):
@@ -403,8 +437,10 @@ class MG:
 
 
 def mg_setup_stream_chiral_svd(lat: Lattice, U, block, n_test, batch, rank, n_setup_iter=16, n_post_smooth=8,
-                               coarse_tol=0.03, coarse_max_iter=500, inner="f64", seed=0, test_vectors=None) -> MG:
-    """Algorithm 4 with Algorithm 3 (see qmg.h).  U: complex128 [4,V,3,3] on the GPU."""
+                               coarse_tol=0.03, coarse_max_iter=500, inner="f64", seed=0, test_vectors=None,
+                               c_sw=None) -> MG:
+    """Algorithm 4 with Algorithm 3 (see qmg.h).  U: complex128 [4,V,3,3] on the GPU.
+    c_sw: None (Wilson), a number (isotropic clover term) or (c_sw_s, c_sw_t)."""
     lib = load_library()
     if U.dtype != torch.complex128:
         raise TypeError("setup takes the FP64 canonical gauge field")
@@ -417,6 +453,9 @@ def mg_setup_stream_chiral_svd(lat: Lattice, U, block, n_test, batch, rank, n_se
     p.inner_prec = _PREC[inner]
     p.seed = int(seed)
     p.test_vectors = None if test_vectors is None else _ptr(test_vectors).value
+    if c_sw is not None:
+        cs, ct = (c_sw, c_sw) if isinstance(c_sw, (int, float)) else c_sw
+        p.c_sw_s, p.c_sw_t = float(cs), float(ct)
     h = ctypes.c_void_p()
     s = lat.c()
     _check(lib.qmg_mg_setup_stream_chiral_svd(ctypes.byref(s), _ptr(U), ctypes.byref(p), ctypes.byref(h), _stream()))

@@ -70,13 +70,16 @@ void check_prec(qmg_prec p) {
 
 // ---------------------------------------------------------------------------------------
 // operators
+// the fine operator: Wilson, or Wilson-clover when A (the packed site term in precision p) is set
 struct WilsonOp : LinOp {
   Geom g;
   qmg_prec p;
   const void* U;
-  WilsonOp(const Geom& g_, qmg_prec p_, const void* U_) : g(g_), p(p_), U(U_) {}
+  const void* A;
+  WilsonOp(const Geom& g_, qmg_prec p_, const void* U_, const void* A_) : g(g_), p(p_), U(U_), A(A_) {}
   void apply(const void* in, void* out, int nrhs, hipStream_t st, const int* = nullptr) override {
     DslashArgs a = make_dslash_args(g, nrhs, false, false);
+    a.clov = A;
     launch_dslash(p, U, in, out, a, st);
   }
   size_t len() const override { return size_t(12) * g.V; }
@@ -368,15 +371,15 @@ double host_norm2(const void* dev, size_t n_complex, hipStream_t st) {
 // Eq. (2) smoothing of r test vectors held in native FP64 `phi` (in place: phi <- psi/|psi|),
 // computed in storage precision S.
 template <class S>
-void smooth_native(const Geom& g, const void* Uin, void* phi, int r, int n_iter, hipStream_t st, Gmres<S>& gm,
-                   DevBuf& b_in, DevBuf& x_in, DevBuf& tmp64) {
+void smooth_native(const Geom& g, const void* Uin, const void* Ain, void* phi, int r, int n_iter, hipStream_t st,
+                   Gmres<S>& gm, DevBuf& b_in, DevBuf& x_in, DevBuf& tmp64) {
   const size_t n = size_t(r) * 12 * g.V;
   constexpr qmg_prec P = StoreTraits<S>::prec;
   if (n_iter > 0) {
     b_in.ensure(n * sizeof(S));
     x_in.ensure(n * sizeof(S));
     tmp64.ensure(n * sizeof(double2));
-    WilsonOp D(g, P, Uin);
+    WilsonOp D(g, P, Uin, Ain);
     const void* phi_in = phi;
     if (P != QMG_F64) {
       launch_convert(phi, QMG_F64, x_in.p, P, n, st);
@@ -410,6 +413,7 @@ void run_streams(qmg_mg* mg, int s0, int s1, const void* test_vectors, hipStream
   const int r = p->batch;
   constexpr qmg_prec P = StoreTraits<S>::prec;
   const void* Uin = (P == QMG_F64) ? h.U64.p : (h.inner == QMG_F32 ? h.Uin.p : h.U32.p);
+  const void* Ain = (P == QMG_F64) ? h.A64.p : (h.inner == QMG_F32 ? h.Ain.p : h.A32.p);
   DevBuf phi(size_t(r) * 12 * g.V * sizeof(double2));
   DevBuf blocks(size_t(2) * h.blk.d * r * h.blk.N * sizeof(double2));
   DevBuf b_in, x_in, tmp64;
@@ -422,7 +426,7 @@ void run_streams(qmg_mg* mg, int s0, int s1, const void* test_vectors, hipStream
     } else {
       launch_philox_native(g, p->seed, s * r, r, phi.p, st);
     }
-    smooth_native<S>(g, Uin, phi.p, r, p->n_setup_iter, st, gm, b_in, x_in, tmp64);
+    smooth_native<S>(g, Uin, Ain, phi.p, r, p->n_setup_iter, st, gm, b_in, x_in, tmp64);
     const auto a1 = Clock::now();
     launch_chiral_gather(h, phi.p, blocks.p, r, st);
     mg->kp = isvd_stream(h, blocks.p, r, mg->kp, mg->sigma_dev, st);
@@ -493,7 +497,7 @@ struct SolveStats {
 // FP64 flexible GMRES(16) with the FP64 K-cycle, in place on native x64
 void solve_f64(const HierarchyDev& h, const void* b64, void* x64, int nrhs, double tol, int max_iter, bool x_zero,
                hipStream_t st, SolveStats& ss, bool& converged) {
-  WilsonOp D(h.g, QMG_F64, h.U64.p);
+  WilsonOp D(h.g, QMG_F64, h.U64.p, h.A64.p);
   CoarseOp Dc(h, QMG_F64, h.Y64.p);
   KCycle<double2, double2> K(h, D, Dc, h.P64.p);
   Gmres<double2> f;  // flexible GMRES(16) with the K-cycle
@@ -512,9 +516,9 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
   constexpr qmg_prec P = StoreTraits<S>::prec;
   using F = float2;
   const size_t len = size_t(12) * h.g.V, n = len * nrhs;
-  WilsonOp D64(h.g, QMG_F64, h.U64.p);
-  WilsonOp D32(h.g, QMG_F32, P == QMG_F32 ? h.Uin.p : h.U32.p);
-  WilsonOp Din(h.g, P, h.Uin.p);
+  WilsonOp D64(h.g, QMG_F64, h.U64.p, h.A64.p);
+  WilsonOp D32(h.g, QMG_F32, P == QMG_F32 ? h.Uin.p : h.U32.p, P == QMG_F32 ? h.Ain.p : h.A32.p);
+  WilsonOp Din(h.g, P, h.Uin.p, h.Ain.p);
   CoarseOp Dc(h, P, h.Yin.p);
   KCycle<F, S> K(h, Din, Dc, h.Pin.p);
   Gmres<F> f;  // flexible GMRES(16) with the K-cycle
@@ -641,6 +645,48 @@ qmg_status qmg_wilson_apply_adj(const qmg_lattice* lat, const void* U, const voi
   return wilson_common(lat, U, in, out, nrhs, prec, layout, stream, true);
 }
 
+qmg_status qmg_clover_field(const qmg_lattice* lat, double c_sw_s, double c_sw_t, const void* U, void* A,
+                            qmg_prec prec, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(U, "U");
+    check_ptr(A, "A");
+    check_prec(prec);
+    QMG_CHECK(std::isfinite(c_sw_s) && std::isfinite(c_sw_t), QMG_EINVAL, "clover coefficients must be finite");
+    Geom g = make_geom(lat);
+    const size_t na = size_t(36) * g.V;
+    DevBuf U64(na * sizeof(double2));
+    launch_pack_gauge(U, U64.p, QMG_F64, g.V, stream);
+    if (prec == QMG_F64) {
+      launch_clover_field(g, U64.p, c_sw_s, c_sw_t, A, stream);
+    } else {
+      DevBuf A64(na * sizeof(double2));
+      launch_clover_field(g, U64.p, c_sw_s, c_sw_t, A64.p, stream);
+      launch_convert(A64.p, QMG_F64, A, prec, na, stream);
+      QMG_HIP(hipStreamSynchronize(stream));  // A64 is released on return
+    }
+  });
+}
+
+qmg_status qmg_clover_apply(const qmg_lattice* lat, const void* U, const void* A, const void* in, void* out,
+                            int32_t nrhs, qmg_prec prec, qmg_layout layout, int32_t dagger, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    check_ptr(U, "U");
+    check_ptr(A, "A");
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(in != out, QMG_EINVAL, "in and out must not alias");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    check_prec(prec);
+    QMG_CHECK(layout == QMG_CANONICAL || layout == QMG_NATIVE, QMG_EINVAL, "bad layout");
+    Geom g = make_geom(lat);
+    DslashArgs a = make_dslash_args(g, nrhs, dagger != 0, layout == QMG_CANONICAL);
+    a.clov = A;
+    launch_dslash(prec, U, in, out, a, stream);
+  });
+}
+
 qmg_status qmg_wilson_apply_batched(int32_t n_lat, const qmg_lattice* lats, const void* const* U,
                                     const void* const* in, void* const* out, int32_t nrhs, qmg_prec prec,
                                     int32_t dagger, hipStream_t stream) {
@@ -744,6 +790,7 @@ Blocking check_params(const Geom& g, const qmg_mg_params* p) {
   QMG_CHECK(p->n_setup_iter >= 0 && p->n_post_smooth >= 0 && p->coarse_max_iter >= 1, QMG_EINVAL,
             "iteration counts must be non-negative");
   QMG_CHECK(p->coarse_tol > 0 && p->coarse_tol < 1, QMG_EINVAL, "coarse_tol must be in (0, 1)");
+  QMG_CHECK(std::isfinite(p->c_sw_s) && std::isfinite(p->c_sw_t), QMG_EINVAL, "clover coefficients must be finite");
   check_prec(p->inner_prec);
   return b;
 }
@@ -774,6 +821,19 @@ std::unique_ptr<qmg_mg> new_hierarchy(const qmg_lattice* lat, const void* U, con
   if (h.inner == QMG_BF16 || h.inner == QMG_F16) {
     h.U32.alloc(size_t(36) * g.V * sizeof(float2));
     launch_pack_gauge(U, h.U32.p, QMG_F32, g.V, stream);
+  }
+  if (p->c_sw_s != 0.0 || p->c_sw_t != 0.0) {  // Wilson-clover: the site term beside every gauge copy
+    const size_t na = size_t(36) * g.V;
+    h.A64.alloc(na * sizeof(double2));
+    launch_clover_field(g, h.U64.p, p->c_sw_s, p->c_sw_t, h.A64.p, stream);
+    if (h.inner != QMG_F64) {
+      h.Ain.alloc(na * prec_bytes(h.inner));
+      launch_convert(h.A64.p, QMG_F64, h.Ain.p, h.inner, na, stream);
+    }
+    if (h.inner == QMG_BF16 || h.inner == QMG_F16) {
+      h.A32.alloc(na * sizeof(float2));
+      launch_convert(h.A64.p, QMG_F64, h.A32.p, QMG_F32, na, stream);
+    }
   }
   mg->lat = *lat;
   mg->params = *p;
@@ -893,7 +953,7 @@ const CoarseLevel& level_for(const qmg_mg* mg, int l, qmg_prec prec) {
 // both arrays.  The gauge field is not stored: its hash ties the file to the field it was built
 // for, and the Galerkin operator is rebuilt from P and the field on load.
 constexpr char kMagic[8] = {'Q', 'M', 'G', 'H', 'I', 'E', 'R', '1'};
-constexpr int32_t kFileVersion = 1;
+constexpr int32_t kFileVersion = 2;
 
 uint64_t hash_words(uint64_t h, const void* data, size_t bytes) {
   const unsigned char* c = static_cast<const unsigned char*>(data);
@@ -971,6 +1031,8 @@ void put_header(File& f, const FileHeader& hd) {
   f.put<int32_t>(p.coarse_max_iter);
   f.put<int32_t>(int32_t(p.inner_prec));
   f.put<uint64_t>(p.seed);
+  f.put<double>(p.c_sw_s);
+  f.put<double>(p.c_sw_t);
   f.put<int32_t>(hd.streams_done);
   f.put<int32_t>(hd.kp);
   f.put<uint64_t>(hd.gauge_hash);
@@ -1001,6 +1063,8 @@ FileHeader get_header(File& f) {
   p.coarse_max_iter = f.get<int32_t>();
   p.inner_prec = qmg_prec(f.get<int32_t>());
   p.seed = f.get<uint64_t>();
+  p.c_sw_s = f.get<double>();
+  p.c_sw_t = f.get<double>();
   p.test_vectors = nullptr;
   hd.streams_done = f.get<int32_t>();
   hd.kp = f.get<int32_t>();
@@ -1333,7 +1397,7 @@ qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, 
     else if (h.inner == QMG_BF16) solve_mixed<cbf16>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
     else solve_mixed<chalf>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
     // true residual in FP64
-    WilsonOp D(h.g, QMG_F64, h.U64.p);
+    WilsonOp D(h.g, QMG_F64, h.U64.p, h.A64.p);
     D.apply(x64.p, r64.p, nrhs, stream);
     Blas<double2>::axpby(1.0, b64.p, -1.0, r64.p, n, stream);
     RedWork rw;
@@ -1416,10 +1480,10 @@ qmg_status qmg_smooth(const qmg_lattice* lat, const void* U, const void* phi, vo
     DevBuf b_in, x_in, tmp64;
     if (prec == QMG_F64) {
       Gmres<double2> gm;
-      smooth_native<double2>(g, Un.p, ph.p, nrhs, n_iter, stream, gm, b_in, x_in, tmp64);
+      smooth_native<double2>(g, Un.p, nullptr, ph.p, nrhs, n_iter, stream, gm, b_in, x_in, tmp64);
     } else {
       Gmres<float2> gm;
-      smooth_native<float2>(g, Un.p, ph.p, nrhs, n_iter, stream, gm, b_in, x_in, tmp64);
+      smooth_native<float2>(g, Un.p, nullptr, ph.p, nrhs, n_iter, stream, gm, b_in, x_in, tmp64);
     }
     launch_unpack_spinor(ph.p, QMG_F64, psi, QMG_F64, g.V, nrhs, stream);
     QMG_HIP(hipStreamSynchronize(stream));

@@ -8,6 +8,10 @@
 // per site and right-hand side the algorithm reads the spinor once (24 reals), the four
 // forward links once (72 reals, shared across right-hand sides) and writes 24 reals.
 //
+// With the clover term the site-local part of the operator, (m + 1 + 3/xi) + T(x), is two
+// hermitian 6 x 6 blocks per site (T commutes with gamma_5); every form then applies them in
+// its epilogue in place of the scalar diagonal term (kernels instantiated with CLOV = true).
+//
 // Launch: one thread per (site, group of NR right-hand sides), 256 threads per workgroup.
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; the tile index is
 // remapped so that each XCD walks a contiguous range of sites, keeping the +-t neighbour
@@ -41,6 +45,7 @@ DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical
   a.nrhs = nrhs;
   a.dagger = dagger ? 1 : 0;
   a.canonical = canonical ? 1 : 0;
+  a.clov = nullptr;
   return a;
 }
 
@@ -147,8 +152,43 @@ __device__ inline void do_hop(const S* __restrict__ U, const S* __restrict__ in,
   }
 }
 
+// acc[r] += A(x) v[r] for NR right-hand sides, A(x) the site's packed site term: per chirality
+// 18 complex entries at A[(alpha * 18 + e) * V + x], e = 0..2 the real diagonal in pairs
+// (re: entry 2e, im: entry 2e+1) and e = 3..17 the upper triangle row by row; the lower
+// triangle is its conjugate.  Each entry is loaded once for all NR right-hand sides.
+template <class S, int NR>
+__device__ inline void clover_acc(const S* __restrict__ A, int site, int V, const cplx<ctype<S>> (*v)[12],
+                                  cplx<ctype<S>> (*acc)[12]) {
+  using C = ctype<S>;
+#pragma unroll
+  for (int al = 0; al < 2; ++al) {
+    const S* b = A + size_t(al) * 18 * V + site;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const cplx<C> d = ldc(b, size_t(e) * V);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        acc[r][6 * al + 2 * e] += d.re * v[r][6 * al + 2 * e];
+        acc[r][6 * al + 2 * e + 1] += d.im * v[r][6 * al + 2 * e + 1];
+      }
+    }
+    int e = 3;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j, ++e) {
+        const cplx<C> o = ldc(b, size_t(e) * V);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          acc[r][6 * al + i] += o * v[r][6 * al + j];
+          acc[r][6 * al + j] += cmul_conj(o, v[r][6 * al + i]);
+        }
+      }
+  }
+}
+
 // D (or D^dag) at one site for NR right-hand sides starting at rhs0
-template <class S, bool CANON, int NR, bool DAG>
+template <class S, bool CANON, int NR, bool DAG, bool CLOV = false>
 __device__ inline void site_dslash(const S* __restrict__ U, const S* __restrict__ in, S* __restrict__ out,
                                    const DslashArgs& a, int site, int rhs0) {
   using C = ctype<S>;
@@ -196,18 +236,31 @@ __device__ inline void site_dslash(const S* __restrict__ U, const S* __restrict_
   do_hop<S, CANON, NR, 3, true, DAG>(U, in, acc, site, tp, rhs0, V, mh * cw[3] * bt_f);
   do_hop<S, CANON, NR, 3, false, DAG>(U, in, acc, tm, tm, rhs0, V, mh * cw[3] * bt_b);
 
+  if constexpr (CLOV) {
+    cplx<C> v[NR][12];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const size_t i = sp_idx<CANON>(rhs0 + r, k, site, V);
-      cplx<C> v = ldc(in, i);
-      stc(out, i, diag * v + acc[r][k]);
+      for (int k = 0; k < 12; ++k) v[r][k] = ldc(in, sp_idx<CANON>(rhs0 + r, k, site, V));
+    clover_acc<S, NR>(static_cast<const S*>(a.clov), site, V, v, acc);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) stc(out, sp_idx<CANON>(rhs0 + r, k, site, V), acc[r][k]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const size_t i = sp_idx<CANON>(rhs0 + r, k, site, V);
+        cplx<C> v = ldc(in, i);
+        stc(out, i, diag * v + acc[r][k]);
+      }
     }
   }
 }
 
-template <class S, bool CANON, int NR, bool DAG>
+template <class S, bool CANON, int NR, bool DAG, bool CLOV = false>
 __global__ __launch_bounds__(kBlock) void k_dslash(const S* __restrict__ U, const S* __restrict__ in,
                                                    S* __restrict__ out, DslashArgs a) {
   // flattened grid over (tile, rhs group) with the rhs groups of a tile adjacent in the
@@ -217,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const S* __restrict__ U, cons
   const int tile = wg / ng;
   const int site = tile * kBlock + threadIdx.x;
   if (site >= a.V) return;
-  site_dslash<S, CANON, NR, DAG>(U, in, out, a, site, (wg - tile * ng) * NR);
+  site_dslash<S, CANON, NR, DAG, CLOV>(U, in, out, a, site, (wg - tile * ng) * NR);
 }
 
 // Many lattices in one launch: workgroup (after the XCD remap) w belongs to the lattice whose
@@ -254,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_batched(const BatchLattice* _
 // XCD-local schedule so that they share its links in L2.  Tiles are 256 consecutive spatial
 // sites, or (zfast) 256-site pieces of one xy-plane with z fastest in the schedule, so that
 // the tiles holding a site's z-neighbours run next to it.
-template <class S, int TCH, int NR, bool DAG>
+template <class S, int TCH, int NR, bool DAG, bool CLOV = false>
 __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, const S* __restrict__ in,
                                                      S* __restrict__ out, DslashArgs a, int ntile_s, int zfast) {
   using C = ctype<S>;
@@ -354,12 +407,44 @@ __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, co
       // backward t-hop of the next site from this site's spinor and t-link
       project<3>(psi[r], sb, h);
       su3_mul<C, true>(u, h, hb[r]);
+      if constexpr (CLOV) {
+        // site term per right-hand side (its entries are cache hits after the first)
+        clover_acc<S, 1>(static_cast<const S*>(a.clov), site, V, &psi[r], &acc[r]);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        stc(out, sp_idx<false>(rhs0 + r, k, site, V), diag * psi[r][k] + acc[r][k]);
-        psi[r][k] = nxt[k];
+        for (int k = 0; k < 12; ++k) {
+          stc(out, sp_idx<false>(rhs0 + r, k, site, V), acc[r][k]);
+          psi[r][k] = nxt[k];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          stc(out, sp_idx<false>(rhs0 + r, k, site, V), diag * psi[r][k] + acc[r][k]);
+          psi[r][k] = nxt[k];
+        }
       }
     }
+  }
+}
+
+// Rows I0 .. I0+2 of one chirality block of the packed site term (layout of clover_acc)
+// applied to that chirality's six spinor components x; compile-time row indices.
+template <class S, int I0>
+__device__ inline void site_term_rows(const S* __restrict__ b, int V, const cplx<ctype<S>> (&x)[6],
+                                      cplx<ctype<S>> (&y)[3]) {
+  using C = ctype<S>;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = I0 + q;
+    const cplx<C> dd = ldc(b, size_t(i >> 1) * V);
+    cplx<C> v = ((i & 1) ? dd.im : dd.re) * x[i];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      if (j == i) continue;
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      const cplx<C> o = ldc(b, size_t(3 + lo * (11 - lo) / 2 + (hi - lo - 1)) * V);
+      v += (i < j) ? o * x[j] : cmul_conj(o, x[j]);
+    }
+    y[q] = v;
   }
 }
 
@@ -369,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, co
 // spinor components 3w .. 3w+2 of the 64 sites.  Four times as many threads as the site
 // kernel, each with two hops in flight: for lattices too small to fill the GPU with one
 // thread per site.
-template <class S, bool DAG>
+template <class S, bool DAG, bool CLOV = false>
 __global__ __launch_bounds__(kBlock) void k_dslash_dir(const S* __restrict__ U, const S* __restrict__ in,
                                                        S* __restrict__ out, DslashArgs a) {
   using C = ctype<S>;
@@ -438,30 +523,65 @@ __global__ __launch_bounds__(kBlock) void k_dslash_dir(const S* __restrict__ U, 
   for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[0][k];
   __syncthreads();
   if (!live) return;
+  if constexpr (CLOV) {
+    // wavefront mu writes rows 3 (mu & 1) .. +2 of chirality mu >> 1 (uniform in the wavefront)
+    const int al = mu >> 1;
+    cplx<C> x[6], y[3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int k = 3 * mu + q;
-    const size_t i = size_t(k) * V + site;
-    cplx<C> v = diag * ldc(inr, i);
+    for (int j = 0; j < 6; ++j) x[j] = ldc(inr, size_t(6 * al + j) * V + site);
+    const S* b = static_cast<const S*>(a.clov) + size_t(al) * 18 * V + site;
+    if (mu & 1) site_term_rows<S, 3>(b, V, x, y);
+    else site_term_rows<S, 0>(b, V, x, y);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v += part[m][k][lane];
-    stc(outr, i, v);
+    for (int q = 0; q < 3; ++q) {
+      const int k = 3 * mu + q;
+      cplx<C> v = y[q];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v += part[m][k][lane];
+      stc(outr, size_t(k) * V + site, v);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int k = 3 * mu + q;
+      const size_t i = size_t(k) * V + site;
+      cplx<C> v = diag * ldc(inr, i);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v += part[m][k][lane];
+      stc(outr, i, v);
+    }
   }
 }
 
 template <class S>
 void launch_dir(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
   dim3 grid(unsigned((a.V + kBlock / 4 - 1) / (kBlock / 4)) * unsigned(a.nrhs));
-  if (a.dagger)
+  if (a.clov) {
+    if (a.dagger)
+      launch(k_dslash_dir<S, true, true>, grid, dim3(kBlock), 0, st, U, in, out, a);
+    else
+      launch(k_dslash_dir<S, false, true>, grid, dim3(kBlock), 0, st, U, in, out, a);
+  } else if (a.dagger) {
     launch(k_dslash_dir<S, true>, grid, dim3(kBlock), 0, st, U, in, out, a);
-  else
+  } else {
     launch(k_dslash_dir<S, false>, grid, dim3(kBlock), 0, st, U, in, out, a);
+  }
   QMG_LAUNCH_CHECK();
 }
 
 template <class S, bool CANON, int NR>
 void launch_t(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
   dim3 grid(unsigned((a.V + kBlock - 1) / kBlock) * unsigned(a.nrhs / NR));
+  if constexpr (NR == 1) {
+    if (a.clov) {
+      if (a.dagger)
+        launch(k_dslash<S, CANON, 1, true, true>, grid, dim3(kBlock), 0, st, U, in, out, a);
+      else
+        launch(k_dslash<S, CANON, 1, false, true>, grid, dim3(kBlock), 0, st, U, in, out, a);
+      QMG_LAUNCH_CHECK();
+      return;
+    }
+  }
   if (a.dagger)
     launch(k_dslash<S, CANON, NR, true>, grid, dim3(kBlock), 0, st, U, in, out, a);
   else
@@ -475,6 +595,16 @@ void launch_tw(const void* U, const void* in, void* out, const DslashArgs& a, in
   const int ntile_s = zfast ? ((a.L[0] * a.L[1] + kBlock - 1) / kBlock) * a.L[2] : (Vs + kBlock - 1) / kBlock;
   const int nchunk = a.L[3] / TCH;
   dim3 grid(unsigned(ntile_s * nchunk * (a.nrhs / NR)));
+  if constexpr (sizeof(S) >= 8) {  // the site-term forms exist for FP32 and FP64 storage
+    if (a.clov) {
+      if (a.dagger)
+        launch(k_dslash_t<S, TCH, NR, true, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
+      else
+        launch(k_dslash_t<S, TCH, NR, false, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
+      QMG_LAUNCH_CHECK();
+      return;
+    }
+  }
   if (a.dagger)
     launch(k_dslash_t<S, TCH, NR, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
   else
@@ -509,9 +639,15 @@ void run_twx(int v, const void* U, const void* in, void* out, const DslashArgs& 
 
 template <class S>
 void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
+  const bool clov = a.clov != nullptr;
+  // algorithmic traffic: spinor in + out (2 x 12 complex per site and rhs) + 4 links per site
+  // (+ the site term's 2 x 18 complex entries with the clover term); flops: 1368 per site and
+  // rhs for the stencil, 504 more for the two 6 x 6 hermitian blocks
+  const double cb = double(sizeof(S));
+  const double bytes = double(a.V) * (24.0 * a.nrhs + 36.0 + (clov ? 36.0 : 0.0)) * cb;
+  const double flops = (clov ? 1872.0 : 1368.0) * a.V * a.nrhs;
   if (a.canonical) {
-    TimedLaunch tl("dslash/canonical", st, double(a.V) * (24.0 * a.nrhs + 36.0) * double(sizeof(S)),
-                   1368.0 * a.V * a.nrhs);
+    TimedLaunch tl(clov ? "clover/canonical" : "dslash/canonical", st, bytes, flops);
     launch_t<S, true, 1>(U, in, out, a, st);
     return;
   }
@@ -524,16 +660,16 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   // t-chunk that still gives >= 1024 workgroups, else the direction split when one thread per
   // site would leave the GPU short of wavefronts.  With the autotuner enabled every valid
   // variant is timed on first use of (precision, extents, nrhs, adjoint) and the fastest is
-  // kept.
+  // kept.  With the clover term: forms 1, 16, 2, 4, 8 and the multi-RHS t-walks (FP32 and FP64
+  // storage), the direction split alone for BF16/FP16 storage.
   const int Vs = a.L[0] * a.L[1] * a.L[2];
   const long wg1 = long((Vs + kBlock - 1) / kBlock) * a.nrhs;  // workgroups per t-slice
   const int Lt = a.L[3];
-  // algorithmic traffic: spinor in + out (2 x 12 complex per site and rhs) + 4 links per site
-  const double cb = double(sizeof(S));
-  const double bytes = double(a.V) * (24.0 * a.nrhs + 36.0) * cb, flops = 1368.0 * a.V * a.nrhs;
   auto run = [&](int v) {
-    TimedLaunch tl(v == 16 ? "dslash/dir" : (v == 1 || v == 32 || v == 64) ? "dslash/site" : "dslash/twalk", st, bytes,
-                   flops);
+    const int f = v == 16 ? 0 : (v == 1 || v == 32 || v == 64) ? 1 : 2;
+    static const char* const fams[2][3] = {{"dslash/dir", "dslash/site", "dslash/twalk"},
+                                           {"clover/dir", "clover/site", "clover/twalk"}};
+    TimedLaunch tl(fams[clov ? 1 : 0][f], st, bytes, flops);
     switch (v) {
       case 8: launch_tw<S, 8, 1>(U, in, out, a, 0, st); break;
       case 4: launch_tw<S, 4, 1>(U, in, out, a, 0, st); break;
@@ -548,7 +684,9 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     }
   };
   auto valid = [&](int v) {
-    if (v == 1 || v == 16) return true;
+    if (v == 16) return true;
+    if (clov && (sizeof(S) == 4 || v == 32 || v == 64)) return false;
+    if (v == 1) return true;
     if (v == 32) return a.nrhs % 2 == 0;
     if (v == 64) return a.nrhs % 4 == 0;
     if (v > 100) {
@@ -568,6 +706,7 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   // 4-byte storage (BF16/FP16): the one-thread-per-site forms hold every hop's loads in
   // registers (up to 256 VGPRs, one wavefront per SIMD); the direction split needs 64-70
   if (sizeof(S) == 4) choice = 16;
+  if (!valid(choice)) choice = 16;
   if (sizeof(S) == 8 && a.nrhs >= 2) {
     // measured at 16^3x32 (8 rhs), 24^3x64 (16) and 32^3x64 (12): 10-20% faster than the
     // one-rhs-per-thread forms; z-fastest tiles only where 256-site pieces tile an xy-plane
@@ -579,7 +718,8 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   if (tune_enabled()) {
     const std::string key = "dslash/" + std::to_string(int(StoreTraits<S>::prec)) + "/" + std::to_string(a.L[0]) +
                             "x" + std::to_string(a.L[1]) + "x" + std::to_string(a.L[2]) + "x" +
-                            std::to_string(a.L[3]) + "/" + std::to_string(a.nrhs) + "/" + std::to_string(a.dagger);
+                            std::to_string(a.L[3]) + "/" + std::to_string(a.nrhs) + "/" + std::to_string(a.dagger) +
+                            (clov ? "/clover" : "");
     const int cached = tune_lookup(key);
     if (cached > 0) {
       choice = cached;

@@ -40,6 +40,7 @@ struct HierarchyDev {
 
   DevBuf U64, Uin;           // native gauge, FP64 and inner precision
   DevBuf U32;                // FP32 gauge when the inner precision is below FP32 (outer GCR, setup)
+  DevBuf A64, Ain, A32;      // packed site term with the clover term, beside U64, Uin, U32 (empty: Wilson)
   DevBuf bsite, cnb;         // tables
   DevBuf blists;             // [8][nd]: in-block sites per hop direction, intra-block hops first
   DevBuf P64, Pin;           // [d][2][k][N]

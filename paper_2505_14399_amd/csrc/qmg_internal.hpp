@@ -298,6 +298,11 @@ struct DslashArgs {
   int dagger;
   int canonical;  // 1: AoS canonical layouts, 0: native SoA
   int tchunk;     // native kernel: sites per thread along t (0: chosen by the launcher)
+  // site term with the clover term, in the storage precision of U: per chirality alpha the 18
+  // complex entries of a hermitian 6 x 6 block at [(alpha * 18 + e) * V + site] (e = 0..2: the
+  // real diagonal in pairs, 3..17: the upper triangle row by row); nullptr: the scalar
+  // diagonal term of the Wilson operator
+  const void* clov;
 };
 DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical);
 
@@ -324,5 +329,9 @@ void launch_unpack_spinor(const void* native, qmg_prec pn, void* canon, qmg_prec
 void launch_pack_gauge(const void* canon_f64, void* native, qmg_prec prec, int V, hipStream_t st);
 // precision conversion between native buffers of n complex numbers
 void launch_convert(const void* in, qmg_prec pin, void* out, qmg_prec pout, size_t n, hipStream_t st);
+// A64 = the packed FP64 site term (layout of DslashArgs::clov) of the Wilson-clover operator with
+// clover coefficients cs (spatial planes) and ct (planes containing t), from the native FP64
+// gauge field U64; synchronises st before returning (it frees a temporary)
+void launch_clover_field(const Geom& g, const void* U64, double cs, double ct, void* A64, hipStream_t st);
 
 }  // namespace qmg

@@ -217,6 +217,7 @@ struct BuildArgs {
   int L[4], b[4], cL[4];
   int V, nd, N, k, d, bc_t;
   double diag, cw[4];
+  const double2* clov;  // packed FP64 site term with the clover term (nullptr: diag)
 };
 
 __device__ inline int lex4(const int* c, const int* L) { return c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3])); }
@@ -358,7 +359,28 @@ __global__ __launch_bounds__(256) void k_build_coarse(const double2* __restrict_
         const int q = t / m, col = t - q * m;
         const int beta = col / k, l = col - beta * k;
         cplx<double>* hp = HP + size_t(q) * 12 * m + col;
-        if (cls == 1) {
+        if (cls == 1 && a.clov) {
+          // the chirality-beta block of the site term at the staged site times P's column
+          const double2* blk = a.clov + size_t(beta) * 18 * V + sinfo[q * 5 + 1];
+          cplx<double> x[6];
+          for (int s6 = 0; s6 < 6; ++s6) x[s6] = Px[(size_t(q) * 12 + 6 * beta + s6) * k + l];
+          cplx<double> y[6];
+          for (int e = 0; e < 3; ++e) {
+            const double2 dd = blk[size_t(e) * V];
+            y[2 * e] = dd.x * x[2 * e];
+            y[2 * e + 1] = dd.y * x[2 * e + 1];
+          }
+          int e = 3;
+          for (int i = 0; i < 6; ++i)
+            for (int j = i + 1; j < 6; ++j, ++e) {
+              const double2 ov = blk[size_t(e) * V];
+              const cplx<double> o = {ov.x, ov.y};
+              y[i] += o * x[j];
+              y[j] += cmul_conj(o, x[i]);
+            }
+          for (int comp = 0; comp < 12; ++comp)
+            hp[comp * m] = (comp / 6 == beta) ? y[comp - 6 * beta] : cplx<double>{0, 0};
+        } else if (cls == 1) {
           for (int comp = 0; comp < 12; ++comp)
             hp[comp * m] = (comp / 6 == beta) ? a.diag * Px[(size_t(q) * 12 + comp) * k + l] : cplx<double>{0, 0};
         } else {
@@ -940,6 +962,7 @@ void build_coarse(HierarchyDev& h, hipStream_t st) {
   a.d = h.blk.d;
   a.bc_t = h.g.bc_t;
   a.diag = h.g.diag();
+  a.clov = static_cast<const double2*>(h.A64.p);
   TimedLaunch tl("coarse_build", st, double(h.g.V) * 12.0 * h.k * 16.0 + 9.0 * h.blk.d * 4.0 * h.k * h.k * 16.0,
                  double(h.g.V) * 4.0 * (2.0 * h.k) * (2.0 * h.k) * 6.0 * 8.0, false);
   const int nent = 4 * h.k * h.k;

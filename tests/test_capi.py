@@ -116,9 +116,45 @@ def test_hierarchy_file_errors_without_device_work(tmp_path):
     assert L.qmg_mg_load(str(bad).encode(), dummy, ctypes.byref(out), None) == -1
     assert b"not a hierarchy file" in L.qmg_last_error()
     short = tmp_path / "short.qmg"
-    short.write_bytes(b"QMGHIER1" + (1).to_bytes(4, "little") + bytes(10))
+    short.write_bytes(b"QMGHIER1" + (2).to_bytes(4, "little") + bytes(10))
     assert L.qmg_mg_load(str(short).encode(), dummy, ctypes.byref(out), None) == -1
     assert b"truncated" in L.qmg_last_error()
+    old = tmp_path / "old.qmg"  # the first format had no clover coefficients
+    old.write_bytes(b"QMGHIER1" + (1).to_bytes(4, "little") + bytes(200))
+    assert L.qmg_mg_load(str(old).encode(), dummy, ctypes.byref(out), None) == -1
+    assert b"unsupported hierarchy file version 1" in L.qmg_last_error()
     assert L.qmg_mg_load(str(bad).encode(), None, ctypes.byref(out), None) == -1
     assert L.qmg_mg_save(None, str(bad).encode(), None) == -1
     assert L.qmg_mg_stream_more(None, 1, None) == -1
+
+
+def test_clover_arguments_are_rejected_without_device_work():
+    import paper_2505_14399_amd as q
+    L = q.load_library()
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    dummy = P(16)  # never dereferenced: validation fails first
+    lat = _lat()
+    assert L.qmg_clover_field(ctypes.byref(lat), D(1.0), D(1.0), None, P(32), q.F64, None) == -1
+    assert L.qmg_clover_field(ctypes.byref(lat), D(1.0), D(1.0), dummy, None, q.F64, None) == -1
+    assert L.qmg_clover_field(ctypes.byref(lat), D(float("nan")), D(1.0), dummy, P(32), q.F64, None) == -1
+    assert b"clover coefficients" in L.qmg_last_error()
+    assert L.qmg_clover_field(ctypes.byref(lat), D(1.0), D(1.0), dummy, P(32), 9, None) == -1
+    bad = _lat(dims=(4, 4, 0, 4))
+    assert L.qmg_clover_field(ctypes.byref(bad), D(1.0), D(1.0), dummy, P(32), q.F64, None) == -2
+    # apply: null site term, aliasing, nrhs, layout
+    assert L.qmg_clover_apply(ctypes.byref(lat), dummy, None, P(32), P(48), 1, q.F64, q.CANONICAL, 0, None) == -1
+    assert L.qmg_clover_apply(ctypes.byref(lat), dummy, P(24), P(32), P(32), 1, q.F64, q.CANONICAL, 0, None) == -1
+    assert L.qmg_clover_apply(ctypes.byref(lat), dummy, P(24), P(32), P(48), 0, q.F64, q.CANONICAL, 0, None) == -1
+    assert L.qmg_clover_apply(ctypes.byref(lat), dummy, P(24), P(32), P(48), 1, q.F64, 3, 0, None) == -1
+    # setup with a non-finite clover coefficient
+    p = q.qmg_mg_params()
+    for i in range(4):
+        p.block[i] = 2
+    p.n_test, p.batch, p.rank = 8, 4, 4
+    p.n_setup_iter, p.n_post_smooth, p.coarse_tol, p.coarse_max_iter = 4, 8, 0.03, 100
+    p.inner_prec = q.F64
+    p.c_sw_s, p.c_sw_t = 1.0, float("inf")
+    out = ctypes.c_void_p()
+    assert L.qmg_mg_setup_stream_chiral_svd(ctypes.byref(lat), dummy, ctypes.byref(p), ctypes.byref(out), None) == -1
+    assert b"clover coefficients" in L.qmg_last_error() and out.value is None
