@@ -11,7 +11,10 @@ Prints one JSON line.  `value` is the median mixed-precision solve time (s) over
 steps; `roofline` describes the dominant kernel measured live with HIP events over the timed
 region; `cpu_baseline` is the CPU oracle timed on this host on a bounded sample; `dslash_hbm` is
 the dslash's algorithmic bandwidth on a 32^3 x 64 lattice (fields larger than the 256 MB
-last-level cache) at 1 and 12 right-hand sides.
+last-level cache) at 1 and 12 right-hand sides; `clover` is the same pair for the Wilson-clover
+operator (site term fused into the stencil) and the clover multigrid (setup and mixed-precision
+solve) on the same 16^3 x 32 anisotropic lattice with unit clover coefficients and a mass
+tuned for that operator.  `--workload aniso16x32_clover` makes the clover workload the main line.
 
 Counter runs: `bench.py --traffic-probe` runs a 256 MiB device copy (calibration) and then ten
 launches each of the solve's dslash and coarse apply in the solve's launch configuration; run it
@@ -49,6 +52,8 @@ FAMILY_KERNEL = {
 }
 FAMILIES = ("dslash/site", "dslash/twalk", "dslash/dir", "isvd", "coarse_apply", "prolong", "restrict",
             "coarse_build")
+CLOVER_FAMILIES = tuple(f.replace("dslash/", "clover/") for f in FAMILIES)
+CLOVER_WORKLOAD = "aniso16x32_clover"
 
 
 def source_sha(fname):
@@ -68,6 +73,7 @@ def parse():
     ap.add_argument("--mass", type=float, default=None, help="override the workload's quark mass")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
+    ap.add_argument("--no-clover", action="store_true", help="skip the clover operator and clover MG leg")
     ap.add_argument("--no-dslash-hbm", action="store_true",
                     help="skip the dslash bandwidth measurement on the 32^3x64 lattice")
     ap.add_argument("--levels", action="store_true",
@@ -130,7 +136,10 @@ def traffic_probe(args):
 DSLASH_HBM_DIMS = (32, 32, 32, 64)
 
 
-def dslash_hbm():
+def dslash_hbm(clover=False):
+    """Algorithmic bandwidth of the default launch form on 32^3 x 64 (FP32 storage): per site and
+    right-hand side the spinor in and out, per site the four links (and with the clover term the
+    two packed 6 x 6 hermitian blocks, 36 complex numbers)."""
     import numpy as np
     import torch
 
@@ -139,33 +148,97 @@ def dslash_hbm():
     lat = q.Lattice(DSLASH_HBM_DIMS, -0.2, 1.0, -1)
     V = lat.volume
     g = torch.Generator(device="cuda").manual_seed(7)
-    U = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
+    if clover:  # a near-unit field, so that the clover term is of natural size
+        H = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
+        U = torch.linalg.matrix_exp(0.3j * (H + H.conj().transpose(-1, -2)) / 2)
+        A = q.clover_field(lat, U, 1.0, 1.0, "f32")
+    else:
+        U = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
+        A = None
     Un = q.pack_gauge(lat, U, "f32")
     del U
     out = {"lattice": list(DSLASH_HBM_DIMS), "prec": "f32", "launch": "default form", "per_rhs": {}}
+
+    def apply(x, y):
+        if clover:
+            q.clover_apply(lat, Un, A, x, layout="native", out=y)
+        else:
+            q.wilson_apply(lat, Un, x, layout="native", out=y)
+
     for nrhs in (1, 12):
         x = q.pack_spinor(lat, torch.randn(nrhs, V, 4, 3, dtype=torch.complex128, device="cuda", generator=g), "f32")
         y = torch.empty_like(x)
         for _ in range(3):
-            q.wilson_apply(lat, Un, x, layout="native", out=y)
+            apply(x, y)
         n, reps = (20 if nrhs == 1 else 6), []
         for _ in range(3):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             e0.record()
             for i in range(n):  # alternate the buffers so no application reads its own output
-                q.wilson_apply(lat, Un, x if i % 2 == 0 else y, layout="native", out=y if i % 2 == 0 else x)
+                apply(x if i % 2 == 0 else y, y if i % 2 == 0 else x)
             e1.record()
             torch.cuda.synchronize()
             reps.append(e0.elapsed_time(e1) / n * 1e-3)
         t = float(np.median(reps))
-        byt = V * (24.0 * nrhs + 36.0) * 8.0
+        byt = V * (24.0 * nrhs + 36.0 + (36.0 if clover else 0.0)) * 8.0
         out["per_rhs"][str(nrhs)] = {"us": t * 1e6, "algorithmic_MB": byt / 1e6, "GBps": byt / t / 1e9,
                                      "frac_hbm": byt / t / 1e9 / PEAK_HBM_GBPS}
         del x, y
-    del Un
+    del Un, A
     torch.cuda.empty_cache()
     return out
+
+
+def clover_mg(args):
+    """The clover workload's setup and mixed-precision solve (one untimed warm-up setup + solve,
+    then three timed setups, each followed by one timed solve), with the operator's sampled
+    launch rate over the timed solves."""
+    import numpy as np
+    import torch
+
+    import fields
+    import paper_2505_14399_amd as q
+
+    w = workloads_get(CLOVER_WORKLOAD)
+    dims = w["dims"]
+    lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
+    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
+    b = torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda()
+    kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
+              n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"], c_sw=w["c_sw"])
+    mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
+    q.mg_solve(mg, b, tol=args.tol)
+    mg.close()
+    torch.cuda.synchronize()
+    setups, solves, info = [], [], None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
+        t1 = time.perf_counter()
+        q.timing_enable(True, every=TIMING_SAMPLE)
+        _, inf = q.mg_solve(mg, b, tol=args.tol)
+        t2 = time.perf_counter()
+        op = q.timing_query("clover")
+        q.timing_enable(False)
+        mg.close()
+        setups.append(t1 - t0)
+        solves.append(t2 - t1)
+        info = inf[0]
+    if info["true_rel_res"] > args.tol:
+        raise SystemExit(f"clover solve did not reach {args.tol}: {info}")
+    avg = op["ms"] / max(1, op["launches"])
+    gbps = op["bytes"] / max(1, op["launches"]) / (avg * 1e-3) / 1e9
+    return {"workload": w["name"], "c_sw": list(w["c_sw"]), "mass": w["mass"], "setup_s": float(np.median(setups)),
+            "solve_s": float(np.median(solves)), "outer_iters": info["outer_iters"],
+            "coarse_iters": info["coarse_iters"], "true_rel_res": info["true_rel_res"],
+            "operator": {"timed_launches": op["launches"], "avg_launch_us": avg * 1e3, "GBps": gbps,
+                         "frac_hbm": gbps / PEAK_HBM_GBPS}}
+
+
+def workloads_get(name):
+    from fields import workloads
+    return workloads.get(name)
 
 
 # setup methods compared by --compare-setups: (name, n_test m, batch r); rank k from the workload.
@@ -383,7 +456,7 @@ def cpu_baseline(w, counts):
     """Time the oracle's unit operations on this workload and scale by the solve's op counts."""
     import numpy as np
     import fields
-    from oracle import wilson, transfer, coarse, geometry as geo, krylov  # noqa: F401
+    from oracle import wilson, clover, transfer, coarse, geometry as geo, krylov  # noqa: F401
 
     dims, block, k = w["dims"], w["block"], w["rank"]
     V = geo.volume(dims)
@@ -404,8 +477,13 @@ def cpu_baseline(w, counts):
         return (time.perf_counter() - t0) / n
 
     from threadpoolctl import threadpool_limits
+    if w.get("c_sw"):  # the clover term is setup work, built once outside the timed calls
+        T = clover.clover_term(U, dims, *w["c_sw"])
+        apply_D = lambda: clover.apply_clover(U, T, psi, w["mass"], w["xi"], w["bc_t"], dims)  # noqa: E731
+    else:
+        apply_D = lambda: wilson.apply_wilson(U, psi, w["mass"], w["xi"], w["bc_t"], dims)  # noqa: E731
     with threadpool_limits(limits=1):  # one host thread: BLAS pools held to one thread
-        t_D = tm(lambda: wilson.apply_wilson(U, psi, w["mass"], w["xi"], w["bc_t"], dims), 3)
+        t_D = tm(apply_D, 3)
         t_Dc = tm(lambda: coarse.coarse_apply(Y, vc, cd), 5)
         t_RP = tm(lambda: transfer.prolong(P, transfer.restrict(P, psi[None], dims, block), dims, block), 2)
         a, b = psi.ravel(), psi.ravel().copy()
@@ -418,8 +496,8 @@ def cpu_baseline(w, counts):
         ncpu = os.cpu_count()
     return {
         "value": est, "unit": "s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle unit operations timed on this workload ({dims}, k={k}): Wilson D apply "
-                   f"{t_D:.3f}s, coarse apply {t_Dc:.4f}s, restrict+prolong {t_RP:.3f}s, fine vector op "
+        "sample": (f"oracle unit operations timed on this workload ({dims}, k={k}): fine D apply "
+                   f"{t_D:.3f}s{' (with the clover term)' if w.get('c_sw') else ''}, coarse apply {t_Dc:.4f}s, restrict+prolong {t_RP:.3f}s, fine vector op "
                    f"{t_vec:.4f}s; scaled by the GPU solve's operation counts {counts}; one thread (BLAS "
                    f"pools limited to 1; {ncpu} host cpus visible)"),
     }
@@ -455,7 +533,10 @@ def main():
     U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
     b = torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda()
     setup_kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
-                    n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"])
+                    n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"],
+                    c_sw=w.get("c_sw"))
+    op_name = "clover" if w.get("c_sw") else "dslash"  # timing families of the fine operator
+    families = CLOVER_FAMILIES if w.get("c_sw") else FAMILIES
 
     def step():
         t0 = time.perf_counter()
@@ -481,8 +562,8 @@ def main():
         infos.append(info)
     torch.cuda.synchronize()
     T1 = time.perf_counter()
-    fams = {f: q.timing_query(f) for f in FAMILIES}
-    ds = q.timing_query("dslash")
+    fams = {f: q.timing_query(f) for f in families}
+    ds = q.timing_query(op_name)
     q.timing_enable(False)
     for i in infos:
         if i["true_rel_res"] > args.tol:
@@ -492,7 +573,8 @@ def main():
     mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
     q.timing_enable(True)
     _, sinfo = q.mg_solve(mg, b, tol=args.tol)
-    cnt = {f: q.timing_query(f)["launches"] for f in ("dslash", "coarse_apply", "restrict")}
+    cnt = {f: q.timing_query(op_name if f == "dslash" else f)["launches"] for f in ("dslash", "coarse_apply",
+                                                                                      "restrict")}
     q.timing_enable(False)
     mg.close()
     cnt["vector_ops"] = 12 * (sinfo[0]["smoother_iters"] + sinfo[0]["outer_iters"])
@@ -543,7 +625,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "lattice": list(dims), "xi": w["xi"], "eps": w["eps"],
                    "mass": w["mass"], "bc_t": w["bc_t"], "block": list(w["block"]), "n_test": w["n_test"],
-                   "batch": w["batch"], "rank": w["rank"], "nrhs": 1, "tol": args.tol},
+                   "batch": w["batch"], "rank": w["rank"], "nrhs": 1, "tol": args.tol,
+                   **({"c_sw": list(w["c_sw"])} if w.get("c_sw") else {})},
         "setup_s": float(np.median(setups)),
         "solve_fp64": fp64_solve,
         "solve_info": infos[-1],
@@ -560,6 +643,10 @@ def main():
     }
     if not args.no_dslash_hbm:
         res["dslash_hbm"] = dslash_hbm()
+    if not args.no_clover and not w.get("c_sw"):
+        res["clover"] = {"mg": clover_mg(args)}
+        if not args.no_dslash_hbm:
+            res["clover"]["dslash_hbm"] = dslash_hbm(clover=True)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, cnt)
     print(json.dumps(res), flush=True)

@@ -21,6 +21,11 @@ WORKLOADS = {
     "aniso16x32_fp32": dict(dims=(16, 16, 16, 32), bc_t=-1, eps=0.6, xi=3.5, mass=None,
                             block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
                             inner="f32", seed=14399, tag=2),
+    # the 16^3x32 anisotropic lattice with the clover term (unit coefficients in both plane
+    # classes), mass tuned for D_sw
+    "aniso16x32_clover": dict(dims=(16, 16, 16, 32), bc_t=-1, eps=0.6, xi=3.5, mass=None, c_sw=(1.0, 1.0),
+                              block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
+                              inner="f32", seed=14399, tag=2),
     # 24^3x64 isotropic, BF16 storage with FP32 accumulation
     "iso24x64_bf16": dict(dims=(24, 24, 24, 64), bc_t=-1, eps=0.7, xi=1.0, mass=None,
                           block=(4, 4, 4, 4), n_test=96, batch=16, rank=24,

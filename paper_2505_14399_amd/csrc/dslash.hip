@@ -382,6 +382,9 @@ __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, co
     for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[r][k] = {C(0), C(0)};
+    // the site term first, from the own spinors that are live anyway: each of its entries is
+    // loaded once for all NR right-hand sides and nothing more stays live for the epilogue
+    if constexpr (CLOV) clover_acc<S, NR>(static_cast<const S*>(a.clov), site, V, psi, acc);
     do_hop<S, false, NR, 0, true, DAG>(U, in, acc, site, site + dxp, rhs0, V, mh * cw[0]);
     do_hop<S, false, NR, 0, false, DAG>(U, in, acc, site + dxm, site + dxm, rhs0, V, mh * cw[0]);
     do_hop<S, false, NR, 1, true, DAG>(U, in, acc, site, site + dyp, rhs0, V, mh * cw[1]);
@@ -408,8 +411,6 @@ __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, co
       project<3>(psi[r], sb, h);
       su3_mul<C, true>(u, h, hb[r]);
       if constexpr (CLOV) {
-        // site term per right-hand side (its entries are cache hits after the first)
-        clover_acc<S, 1>(static_cast<const S*>(a.clov), site, V, &psi[r], &acc[r]);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
           stc(out, sp_idx<false>(rhs0 + r, k, site, V), acc[r][k]);

@@ -9,8 +9,10 @@ of the spectrum just inside the right half plane.  The critical mass is intensiv
 'SR' search does not finish in reasonable time on the full lattices, so the search runs on a
 smaller lattice with the same roughness, anisotropy and seed (8^3 x 16 for the anisotropic
 16^3 x 32 workload, 12^3 x 16 for the isotropic 24^3 x 64 one), with a margin that covers the
-finite-volume shift of the edge.  Uses only oracle/ and fields/.
-Run: python tests/golden/make_tuned_masses.py
+finite-volume shift of the edge.  For a workload with clover coefficients the operator
+searched is D_sw(0) = D(0) + T (oracle.clover), whose left edge moves with the clover term.
+Uses only oracle/ and fields/.
+Run: python tests/golden/make_tuned_masses.py [workload ...]   (default: every tuned workload)
 """
 import json
 import os
@@ -24,7 +26,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 import fields  # noqa: E402
 from fields.workloads import WORKLOADS  # noqa: E402
-from oracle import wilson, geometry as geo  # noqa: E402
+from oracle import wilson, clover, geometry as geo  # noqa: E402
 from oracle.gamma import GAMMA, ID4  # noqa: E402
 import scipy.sparse as sp  # noqa: E402
 
@@ -57,12 +59,18 @@ def sparse_wilson(U, mass, xi, bc_t, dims):
     return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
 
 
-def leftmost(dims, eps, xi, bc_t, seed, tag):
+def leftmost(dims, eps, xi, bc_t, seed, tag, c_sw=None):
     U = fields.random_gauge(dims, eps, seed, tag)
     n = 12 * int(np.prod(dims))
     A = sparse_wilson(U, 0.0, xi, bc_t, dims)
     v = fields.gaussian_spinor(dims, 1, 99)[0]
-    err = np.abs(A @ v.ravel() - wilson.apply_wilson(U, v, 0.0, xi, bc_t, dims).ravel()).max()
+    if c_sw is None:
+        ref = wilson.apply_wilson(U, v, 0.0, xi, bc_t, dims)
+    else:
+        T = clover.clover_term(U, dims, c_sw[0], c_sw[1])
+        A = A + sp.block_diag(list(T), format="csr")
+        ref = clover.apply_clover(U, T, v, 0.0, xi, bc_t, dims)
+    err = np.abs(A @ v.ravel() - ref.ravel()).max()
     assert err < 1e-12, err
     cnt = [0]
 
@@ -85,10 +93,17 @@ def main():
     out = {}
     if os.path.exists(OUT):
         out = json.load(open(OUT))
-    for name, small, margin in (("aniso16x32_fp32", (8, 8, 8, 16), 1.5e-2), ("iso24x64_bf16", (12, 12, 12, 16), 2e-2)):
+    todo = (("aniso16x32_fp32", (8, 8, 8, 16), 1.5e-2), ("iso24x64_bf16", (12, 12, 12, 16), 2e-2),
+            # the clover term moves the left edge onto the real axis (0.255 here, against
+            # 0.694 +- 0.107i without it), so the margin alone sets |lambda_min|: 0.1 gives the
+            # clover workload about the |lambda_min| of the Wilson one (0.108)
+            ("aniso16x32_clover", (8, 8, 8, 16), 0.1))
+    for name, small, margin in todo:
+        if len(sys.argv) > 1 and name not in sys.argv[1:]:
+            continue
         w = WORKLOADS[name]
         dims = small or w["dims"]
-        vals = leftmost(dims, w["eps"], w["xi"], w["bc_t"], w["seed"], w["tag"])
+        vals = leftmost(dims, w["eps"], w["xi"], w["bc_t"], w["seed"], w["tag"], w.get("c_sw"))
         lam = vals[0]
         m = float(-lam.real + margin)
         out[name] = {"mass": m, "leftmost_eigenvalue_of_D0": [float(lam.real), float(lam.imag)],
