@@ -16,6 +16,7 @@ Modules
   gamma      chiral gamma basis, chirality projectors
   wilson     Wilson-Dirac D and D^dagger (stencil + dense builder)
   clover     clover leaves, field strength, the clover term and the Wilson-clover operator
+  evenodd    even-odd (Schur-complement) preconditioning of the fine operator
   philox     Philox4x32-10 counter RNG and Box-Muller (test-vector guesses)
   krylov     GMRES (smoother, coarse solver), flexible GCR
   icsvd      chiral split, Algorithm 3 (iCSVD) with LAPACK SVD, Algorithm 2, Algorithm 1
