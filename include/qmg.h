@@ -297,6 +297,50 @@ qmg_status qmg_mg_stream_more(qmg_mg* mg, int32_t n_streams, hipStream_t stream)
 qmg_status qmg_mg_save(const qmg_mg* mg, const char* path, hipStream_t stream);
 qmg_status qmg_mg_load(const char* path, const void* U, qmg_mg** out, hipStream_t stream);
 
+/* Even-odd (red-black) preconditioning of the fine operator, which the paper names among the
+ * standard accelerations of the solve (Section 1) without writing it out.  Reading: with every
+ * extent even, the hops of D (or D_sw) join sites of opposite parity p = (x+y+z+t) mod 2 and
+ * the site term A (the diagonal term, plus T with the clover term) is local, so D x = b is
+ * solved through the Schur complement on the even sites,
+ *   Dhat = A_ee - D_eo A_oo^-1 D_oe,   Dhat x_e = b_e - D_eo A_oo^-1 b_o,
+ *   x_o = A_oo^-1 (b_o - D_oe x_e);
+ * Dhat^dagger = gamma_5 Dhat gamma_5 is the Schur complement of D^dagger.
+ * Half-lattice layouts (device, precision F64 or F32 only): a site's half index is its
+ * lexicographic index / 2;
+ *   spinor      [nrhs][12 = 3*spin + colour][V/2] for one parity
+ *   gauge       [2 parity][4 mu][9][V/2]        U_mu(x) stored at the parity of x
+ *   site term   [2 parity][2 alpha][18][V/2]    the packed blocks of qmg_clover_field
+ * Errors of every entry below: EINVAL (null, bad count, aliasing), ESHAPE (an odd extent),
+ * EDTYPE (precision other than F64/F32), ENOMEM, EHIP. */
+qmg_status qmg_eo_pack_gauge(const qmg_lattice* lat, const void* U, void* U_eo, qmg_prec prec, hipStream_t stream);
+qmg_status qmg_eo_pack_spinor(const qmg_lattice* lat, const void* canon_f64, void* even, void* odd, int32_t nrhs,
+                              qmg_prec prec, hipStream_t stream);
+qmg_status qmg_eo_unpack_spinor(const qmg_lattice* lat, const void* even, const void* odd, void* canon_f64,
+                                int32_t nrhs, qmg_prec prec, hipStream_t stream);
+/* A_eo = the packed site term of D_sw with coefficients (c_sw_s, c_sw_t) (both 0: the Wilson
+ * diagonal term) in the half-lattice layout, and Ainv_eo its inverse (per site and chirality,
+ * Gauss-Jordan with partial pivoting in FP64).  U: device, canonical FP64 gauge field.
+ * Synchronizes the stream.  Extra error: EBREAKDOWN if a block is singular. */
+qmg_status qmg_eo_site_term(const qmg_lattice* lat, double c_sw_s, double c_sw_t, const void* U, void* A_eo,
+                            void* Ainv_eo, qmg_prec prec, hipStream_t stream);
+/* out_e = Dhat in_e (dagger = 0) or Dhat^dagger in_e (dagger = 1) on even half fields: two hop
+ * launches, A_oo^-1 D_oe in_e on the odd sites, then A_ee in_e - D_eo (...).  A_eo and Ainv_eo
+ * from qmg_eo_site_term, or both NULL for the Wilson operator (the scalar diagonal term).
+ * Synchronizes the stream (it frees the odd intermediate). */
+qmg_status qmg_schur_apply(const qmg_lattice* lat, const void* U_eo, const void* A_eo, const void* Ainv_eo,
+                           const void* in_e, void* out_e, int32_t nrhs, qmg_prec prec, int32_t dagger,
+                           hipStream_t stream);
+/* x = D^-1 b (D = D_sw when a clover coefficient is non-zero) by FP64 GMRES(32): with eo = 1 on
+ * the Schur complement (source preparation, Dhat solve to tol ||b|| / ||bhat_e||,
+ * reconstruction), with eo = 0 on the full-lattice operator (the same Krylov method, for
+ * comparison).  U: device canonical FP64 gauge field; b, x: device canonical FP64
+ * [nrhs][V][4][3].  info (host, optional): outer_iters = GMRES iterations, true_rel_res =
+ * ||b - D x|| / ||b|| in FP64 (worst over right-hand sides), seconds.  Extra errors: ENOCONV
+ * (not converged within max_iter; x holds the last iterate), ENONFINITE. */
+qmg_status qmg_eo_solve(const qmg_lattice* lat, const void* U, double c_sw_s, double c_sw_t, const void* b, void* x,
+                        int32_t nrhs, double tol, int32_t max_iter, int32_t eo, qmg_solve_info* info,
+                        hipStream_t stream);
+
 /* Setup timings in seconds: smoother, streaming SVD, coarse build, total (host array [4]). */
 qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);
 

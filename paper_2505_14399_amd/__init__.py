@@ -65,6 +65,12 @@ SIGNATURES = {
     "qmg_wilson_apply_batched": [_I, _P, _P, _P, _P, _I, _I, _I, _P],
     "qmg_clover_field": [_P, _D, _D, _P, _P, _I, _P],
     "qmg_clover_apply": [_P, _P, _P, _P, _P, _I, _I, _I, _I, _P],
+    "qmg_eo_pack_gauge": [_P, _P, _P, _I, _P],
+    "qmg_eo_pack_spinor": [_P, _P, _P, _P, _I, _I, _P],
+    "qmg_eo_unpack_spinor": [_P, _P, _P, _P, _I, _I, _P],
+    "qmg_eo_site_term": [_P, _D, _D, _P, _P, _P, _I, _P],
+    "qmg_schur_apply": [_P, _P, _P, _P, _P, _P, _I, _I, _I, _P],
+    "qmg_eo_solve": [_P, _P, _D, _D, _P, _P, _I, _D, _I, _I, _P, _P],
     "qmg_pack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_unpack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_pack_gauge": [_P, _P, _P, _I, _P],
@@ -260,6 +266,83 @@ def clover_apply(lat: Lattice, U, A, psi, layout="canonical", dagger=False, out=
     _check(lib.qmg_clover_apply(ctypes.byref(s), _ptr(U), _ptr(A), _ptr(psi), _ptr(out), nrhs, prec,
                                 CANONICAL if layout == "canonical" else NATIVE, 1 if dagger else 0, _stream()))
     return out
+
+
+def _eo_prec(prec):
+    p = _PREC[prec]
+    if p not in (F64, F32):
+        raise TypeError("even-odd fields are F64 or F32")
+    return p
+
+
+def eo_pack_gauge(lat: Lattice, U64, prec="f64"):
+    """canonical complex128 [4,V,3,3] -> half-lattice gauge [2,4,9,V/2] (parity, mu, entry, site)."""
+    p = _eo_prec(prec)
+    out = torch.empty((2, 4, 9, lat.volume // 2), dtype=_dtype_of(p), device=U64.device)
+    s = lat.c()
+    _check(load_library().qmg_eo_pack_gauge(ctypes.byref(s), _ptr(U64), _ptr(out), p, _stream()))
+    return out
+
+
+def eo_pack_spinor(lat: Lattice, psi64, prec="f64"):
+    """canonical complex128 [nrhs,V,4,3] -> (even, odd) half fields [nrhs,12,V/2]."""
+    p = _eo_prec(prec)
+    nrhs = psi64.shape[0]
+    even = torch.empty((nrhs, 12, lat.volume // 2), dtype=_dtype_of(p), device=psi64.device)
+    odd = torch.empty_like(even)
+    s = lat.c()
+    _check(load_library().qmg_eo_pack_spinor(ctypes.byref(s), _ptr(psi64), _ptr(even), _ptr(odd), nrhs, p,
+                                             _stream()))
+    return even, odd
+
+
+def eo_unpack_spinor(lat: Lattice, even, odd):
+    p = _prec_of(even)
+    nrhs = even.shape[0]
+    out = torch.empty((nrhs, lat.volume, 4, 3), dtype=torch.complex128, device=even.device)
+    s = lat.c()
+    _check(load_library().qmg_eo_unpack_spinor(ctypes.byref(s), _ptr(even), _ptr(odd), _ptr(out), nrhs, p,
+                                               _stream()))
+    return out
+
+
+def eo_site_term(lat: Lattice, U, c_sw_s=0.0, c_sw_t=None, prec="f64"):
+    """(A_eo, Ainv_eo) [2,2,18,V/2]: the packed site term of D_sw (Wilson for zero coefficients)
+    and its inverse in the half-lattice layout."""
+    p = _eo_prec(prec)
+    A = torch.empty((2, 2, 18, lat.volume // 2), dtype=_dtype_of(p), device=U.device)
+    Ai = torch.empty_like(A)
+    s = lat.c()
+    ct = c_sw_s if c_sw_t is None else c_sw_t
+    _check(load_library().qmg_eo_site_term(ctypes.byref(s), float(c_sw_s), float(ct), _ptr(U), _ptr(A), _ptr(Ai), p,
+                                           _stream()))
+    return A, Ai
+
+
+def schur_apply(lat: Lattice, U_eo, x_e, A_eo=None, Ainv_eo=None, dagger=False, out=None):
+    """out_e = Dhat x_e (Dhat^dagger with dagger) on even half fields [nrhs,12,V/2]."""
+    prec = _prec_of(x_e)
+    out = torch.empty_like(x_e) if out is None else out
+    s = lat.c()
+    _check(load_library().qmg_schur_apply(ctypes.byref(s), _ptr(U_eo), _ptr(A_eo), _ptr(Ainv_eo), _ptr(x_e),
+                                          _ptr(out), x_e.shape[0], prec, 1 if dagger else 0, _stream()))
+    return out
+
+
+def eo_solve(lat: Lattice, U, b, c_sw=None, tol=1e-10, max_iter=20000, eo=True, check=True):
+    """x = D^-1 b by FP64 GMRES(32), on the even-odd Schur complement (eo) or on the full
+    operator; c_sw: None (Wilson), a number or (c_sw_s, c_sw_t).  Returns (x, info)."""
+    cs, ct = (0.0, 0.0) if c_sw is None else ((c_sw, c_sw) if isinstance(c_sw, (int, float)) else c_sw)
+    x = torch.empty_like(b)
+    info = qmg_solve_info()
+    s = lat.c()
+    rc = load_library().qmg_eo_solve(ctypes.byref(s), _ptr(U), float(cs), float(ct), _ptr(b), _ptr(x), b.shape[0],
+                                     float(tol), int(max_iter), 1 if eo else 0, ctypes.byref(info), _stream())
+    out = {f: getattr(info, f) for f, _ in qmg_solve_info._fields_}
+    out["status"] = STATUS.get(rc, str(rc))
+    if check:
+        _check(rc)
+    return x, out
 
 
 def _native_spinor_shape(nrhs, V, prec):

@@ -86,6 +86,34 @@ struct WilsonOp : LinOp {
   qmg_prec prec() const override { return p; }
 };
 
+// the even-odd Schur complement Dhat = A_ee - D_eo A_oo^-1 D_oe (Dhat^dag with dag) on even
+// half fields; tmp holds the odd intermediate
+struct SchurOp : LinOp {
+  Geom g;
+  qmg_prec p;
+  const void *Ue, *Uo, *Ae, *Ao, *Aie, *Aio;
+  bool dag;
+  DevBuf tmp;
+  SchurOp(const Geom& g_, qmg_prec p_, const void* Ueo, const void* Aeo, const void* Ainv, bool dag_)
+      : g(g_), p(p_), dag(dag_) {
+    const size_t half = size_t(36) * (g.V / 2) * prec_bytes(p);  // one parity's gauge or packed block
+    Ue = Ueo;
+    Uo = static_cast<const char*>(Ueo) + half;
+    Ae = Aeo;
+    Ao = Aeo ? static_cast<const char*>(Aeo) + half : nullptr;
+    Aie = Ainv;
+    Aio = Ainv ? static_cast<const char*>(Ainv) + half : nullptr;
+  }
+  void apply(const void* in, void* out, int nrhs, hipStream_t st, const int* = nullptr) override {
+    tmp.ensure(size_t(nrhs) * len() * prec_bytes(p));
+    DslashArgs a = make_dslash_args(g, nrhs, dag, false);
+    launch_hop_eo(p, a, Ue, Uo, 1, in, nullptr, tmp.p, nullptr, Aio, 0, 1, 1.0, st);  // A_oo^-1 D_oe in
+    launch_hop_eo(p, a, Ue, Uo, 0, tmp.p, in, out, Ae, nullptr, 2, 0, -1.0, st);      // A_ee in - D_eo (...)
+  }
+  size_t len() const override { return size_t(12) * (g.V / 2); }
+  qmg_prec prec() const override { return p; }
+};
+
 struct CoarseOp : LinOp {
   const HierarchyDev& h;
   qmg_prec p;
@@ -617,6 +645,18 @@ qmg_status wilson_common(const qmg_lattice* lat, const void* U, const void* in, 
   });
 }
 
+Geom eo_geom_checked(const qmg_lattice* lat) {
+  check_ptr(lat, "lat");
+  Geom g = make_geom(lat);
+  QMG_CHECK(g.L[0] % 2 == 0 && g.L[1] % 2 == 0 && g.L[2] % 2 == 0 && g.L[3] % 2 == 0, QMG_ESHAPE,
+            "even-odd preconditioning needs every extent even");
+  return g;
+}
+
+void check_eo_prec(qmg_prec p) {
+  QMG_CHECK(p == QMG_F64 || p == QMG_F32, QMG_EDTYPE, "even-odd fields need F64 or F32 storage");
+}
+
 // Device copy of the descriptor table of the last batched call (uploaded again, after the
 // stream has drained, when the lattice set changes)
 struct BatchCache {
@@ -684,6 +724,163 @@ qmg_status qmg_clover_apply(const qmg_lattice* lat, const void* U, const void* A
     DslashArgs a = make_dslash_args(g, nrhs, dagger != 0, layout == QMG_CANONICAL);
     a.clov = A;
     launch_dslash(prec, U, in, out, a, stream);
+  });
+}
+
+qmg_status qmg_eo_pack_gauge(const qmg_lattice* lat, const void* U, void* U_eo, qmg_prec prec, hipStream_t stream) {
+  return guard([&] {
+    const Geom g = eo_geom_checked(lat);
+    check_ptr(U, "U");
+    check_ptr(U_eo, "U_eo");
+    check_eo_prec(prec);
+    launch_eo_pack_gauge(g, U, U_eo, prec, stream);
+  });
+}
+
+qmg_status qmg_eo_pack_spinor(const qmg_lattice* lat, const void* canon_f64, void* even, void* odd, int32_t nrhs,
+                              qmg_prec prec, hipStream_t stream) {
+  return guard([&] {
+    const Geom g = eo_geom_checked(lat);
+    check_ptr(canon_f64, "canon_f64");
+    check_ptr(even, "even");
+    check_ptr(odd, "odd");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    check_eo_prec(prec);
+    launch_eo_pack_spinor(g, canon_f64, even, odd, nrhs, prec, stream);
+  });
+}
+
+qmg_status qmg_eo_unpack_spinor(const qmg_lattice* lat, const void* even, const void* odd, void* canon_f64,
+                                int32_t nrhs, qmg_prec prec, hipStream_t stream) {
+  return guard([&] {
+    const Geom g = eo_geom_checked(lat);
+    check_ptr(canon_f64, "canon_f64");
+    check_ptr(even, "even");
+    check_ptr(odd, "odd");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    check_eo_prec(prec);
+    launch_eo_unpack_spinor(g, even, odd, canon_f64, nrhs, prec, stream);
+  });
+}
+
+qmg_status qmg_eo_site_term(const qmg_lattice* lat, double c_sw_s, double c_sw_t, const void* U, void* A_eo,
+                            void* Ainv_eo, qmg_prec prec, hipStream_t stream) {
+  return guard([&] {
+    const Geom g = eo_geom_checked(lat);
+    check_ptr(U, "U");
+    check_ptr(A_eo, "A_eo");
+    check_ptr(Ainv_eo, "Ainv_eo");
+    check_eo_prec(prec);
+    QMG_CHECK(std::isfinite(c_sw_s) && std::isfinite(c_sw_t), QMG_EINVAL, "clover coefficients must be finite");
+    const size_t na = size_t(36) * g.V;
+    DevBuf U64(na * sizeof(double2)), A64(na * sizeof(double2));
+    launch_pack_gauge(U, U64.p, QMG_F64, g.V, stream);
+    launch_clover_field(g, U64.p, c_sw_s, c_sw_t, A64.p, stream);
+    launch_eo_site_term(g, A64.p, A_eo, Ainv_eo, prec, stream);  // synchronises
+  });
+}
+
+qmg_status qmg_schur_apply(const qmg_lattice* lat, const void* U_eo, const void* A_eo, const void* Ainv_eo,
+                           const void* in_e, void* out_e, int32_t nrhs, qmg_prec prec, int32_t dagger,
+                           hipStream_t stream) {
+  return guard([&] {
+    const Geom g = eo_geom_checked(lat);
+    check_ptr(U_eo, "U_eo");
+    check_ptr(in_e, "in_e");
+    check_ptr(out_e, "out_e");
+    QMG_CHECK(in_e != out_e, QMG_EINVAL, "in_e and out_e must not alias");
+    QMG_CHECK((A_eo == nullptr) == (Ainv_eo == nullptr), QMG_EINVAL, "give both A_eo and Ainv_eo, or neither");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    check_eo_prec(prec);
+    SchurOp S(g, prec, U_eo, A_eo, Ainv_eo, dagger != 0);
+    S.apply(in_e, out_e, nrhs, stream);
+    QMG_HIP(hipStreamSynchronize(stream));  // the intermediate is released on return
+  });
+}
+
+qmg_status qmg_eo_solve(const qmg_lattice* lat, const void* U, double c_sw_s, double c_sw_t, const void* b, void* x,
+                        int32_t nrhs, double tol, int32_t max_iter, int32_t eo, qmg_solve_info* info,
+                        hipStream_t stream) {
+  return guard([&] {
+    check_ptr(lat, "lat");
+    const Geom g = eo ? eo_geom_checked(lat) : make_geom(lat);
+    check_ptr(U, "U");
+    check_ptr(b, "b");
+    check_ptr(x, "x");
+    QMG_CHECK(nrhs >= 1 && max_iter >= 1, QMG_EINVAL, "need nrhs >= 1, max_iter >= 1");
+    QMG_CHECK(tol > 0 && tol < 1, QMG_EINVAL, "tol must be in (0, 1)");
+    QMG_CHECK(std::isfinite(c_sw_s) && std::isfinite(c_sw_t), QMG_EINVAL, "clover coefficients must be finite");
+    const auto t0 = Clock::now();
+    const bool clov = c_sw_s != 0.0 || c_sw_t != 0.0;
+    const size_t V = size_t(g.V), Vh = V / 2, len = 12 * V, n = len * nrhs;
+    DevBuf U64(36 * V * sizeof(double2)), A64;
+    launch_pack_gauge(U, U64.p, QMG_F64, g.V, stream);
+    if (clov) {
+      A64.alloc(36 * V * sizeof(double2));
+      launch_clover_field(g, U64.p, c_sw_s, c_sw_t, A64.p, stream);
+    }
+    WilsonOp D(g, QMG_F64, U64.p, A64.p);
+    DevBuf b64(n * sizeof(double2)), x64(n * sizeof(double2)), r64(n * sizeof(double2));
+    launch_pack_spinor(b, QMG_F64, b64.p, QMG_F64, g.V, nrhs, stream);
+    RedWork rw;
+    DevBuf nb(nrhs * sizeof(double)), nr(nrhs * sizeof(double));
+    Blas<double2>::norm2(b64.p, len, nrhs, nb.as<double>(), rw, stream);
+    std::vector<double> hb(nrhs), hr(nrhs);
+    QMG_HIP(hipMemcpyAsync(hb.data(), nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, stream));
+    QMG_HIP(hipStreamSynchronize(stream));
+    Gmres<double2> gm;
+    Gmres<double2>::Result res;
+    if (eo) {
+      const size_t hl = 12 * Vh * nrhs;
+      DevBuf Ueo(36 * V * sizeof(double2)), Aeo, Ainv;
+      launch_eo_pack_gauge(g, U, Ueo.p, QMG_F64, stream);
+      if (clov) {
+        Aeo.alloc(36 * V * sizeof(double2));
+        Ainv.alloc(36 * V * sizeof(double2));
+        launch_eo_site_term(g, A64.p, Aeo.p, Ainv.p, QMG_F64, stream);
+      }
+      SchurOp S(g, QMG_F64, Ueo.p, Aeo.p, Ainv.p, false);
+      DevBuf be(hl * sizeof(double2)), bo(hl * sizeof(double2)), bh(hl * sizeof(double2)), xe(hl * sizeof(double2)),
+          xo(hl * sizeof(double2)), t(hl * sizeof(double2));
+      launch_eo_pack_spinor(g, b, be.p, bo.p, nrhs, QMG_F64, stream);
+      DslashArgs a = make_dslash_args(g, nrhs, false, false);
+      launch_site_eo(QMG_F64, a, S.Aio, true, bo.p, t.p, stream);                                 // A_oo^-1 b_o
+      launch_hop_eo(QMG_F64, a, S.Ue, S.Uo, 0, t.p, be.p, bh.p, nullptr, nullptr, 1, 0, -1.0, stream);  // bhat_e
+      // Dhat x_e = bhat_e to tol ||b|| / ||bhat_e||: the even residual of the reconstructed x is
+      // the Schur residual and its odd residual vanishes
+      DevBuf nh(nrhs * sizeof(double));
+      Blas<double2>::norm2(bh.p, 12 * Vh, nrhs, nh.as<double>(), rw, stream);
+      std::vector<double> hh(nrhs);
+      QMG_HIP(hipMemcpyAsync(hh.data(), nh.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, stream));
+      QMG_HIP(hipStreamSynchronize(stream));
+      double ratio = 1.0;
+      for (int i = 0; i < nrhs; ++i)
+        if (hh[i] > 0) ratio = std::min(ratio, std::sqrt(hb[i] / hh[i]));
+      res = gm.solve(S, bh.p, xe.p, true, nrhs, 32, max_iter, std::min(0.5, tol * ratio), stream);
+      launch_hop_eo(QMG_F64, a, S.Ue, S.Uo, 1, xe.p, bo.p, xo.p, nullptr, S.Aio, 1, 1, -1.0, stream);  // x_o
+      launch_eo_unpack_spinor(g, xe.p, xo.p, x, nrhs, QMG_F64, stream);
+      launch_pack_spinor(x, QMG_F64, x64.p, QMG_F64, g.V, nrhs, stream);
+    } else {
+      res = gm.solve(D, b64.p, x64.p, true, nrhs, 32, max_iter, tol, stream);
+      launch_unpack_spinor(x64.p, QMG_F64, x, QMG_F64, g.V, nrhs, stream);
+    }
+    D.apply(x64.p, r64.p, nrhs, stream);
+    Blas<double2>::axpby(1.0, b64.p, -1.0, r64.p, n, stream);
+    Blas<double2>::norm2(r64.p, len, nrhs, nr.as<double>(), rw, stream);
+    QMG_HIP(hipMemcpyAsync(hr.data(), nr.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, stream));
+    QMG_HIP(hipStreamSynchronize(stream));
+    double worst = 0;
+    for (int i = 0; i < nrhs; ++i) worst = std::max(worst, hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0);
+    if (info) {
+      *info = qmg_solve_info{};
+      info->outer_iters = res.iters;
+      info->refinements = 1;
+      info->true_rel_res = worst;
+      info->seconds = secs(t0, Clock::now());
+    }
+    QMG_CHECK(std::isfinite(worst), QMG_ENONFINITE, "non-finite residual");
+    QMG_CHECK(res.converged && worst <= 10 * tol, QMG_ENOCONV, "even-odd solve stopped at %d iterations, residual %.3g",
+              res.iters, worst);
   });
 }
 

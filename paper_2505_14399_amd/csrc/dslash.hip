@@ -734,6 +734,133 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   run(choice);
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Even-odd (Schur complement) forms on half-lattice fields.  Every extent is even; a site of
+// parity p = (x + y + z + t) mod 2 has the half-lattice index i = lex / 2, so within a row of
+// fixed (y, z, t) the sites of one parity are every other x.  Layouts: spinor [rhs][12][V/2]
+// per parity, gauge [parity][mu][9][V/2] (U_mu(x) stored at x's parity), site term and its
+// inverse [parity][alpha][18][V/2] in the packed form of clover_acc (nullptr: the scalar
+// diagonal term of the Wilson operator).
+
+// out (parity p) = POST( YM(y) + sgn * H in ), H the hopping part of D (of D^dag with DAG),
+// in on parity 1 - p.  YM: 0 nothing, 1 y, 2 A_p y.  POST: 0 nothing, 1 A_p^-1.
+template <class S, bool DAG, int YM, int POST>
+__global__ __launch_bounds__(kBlock) void k_hop_eo(const S* __restrict__ Ue, const S* __restrict__ Uo,
+                                                   const S* __restrict__ in, const S* __restrict__ y,
+                                                   S* __restrict__ out, const S* __restrict__ Ap,
+                                                   const S* __restrict__ Aip, DslashArgs a, int p, float sgn) {
+  using C = ctype<S>;
+  const int Vh = a.V >> 1;
+  const int ntile = (Vh + kBlock - 1) / kBlock;
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = wg % ntile, rhs = wg / ntile;
+  const int i = tile * kBlock + threadIdx.x;
+  if (i >= Vh) return;
+  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
+  const int Lxh = L0 >> 1;
+  const int xh = i % Lxh;
+  int row = i / Lxh;
+  const int yy = row % L1;
+  row /= L1;
+  const int z = row % L2;
+  const int t = row / L2;
+  const int x = 2 * xh + ((yy + z + t + p) & 1);
+  auto cb = [&](int cx, int cy, int cz, int ct) { return (cx + L0 * (cy + L1 * (cz + L2 * ct))) >> 1; };
+  const int xp = cb(x + 1 == L0 ? 0 : x + 1, yy, z, t), xm = cb(x == 0 ? L0 - 1 : x - 1, yy, z, t);
+  const int yp = cb(x, yy + 1 == L1 ? 0 : yy + 1, z, t), ym = cb(x, yy == 0 ? L1 - 1 : yy - 1, z, t);
+  const int zp = cb(x, yy, z + 1 == L2 ? 0 : z + 1, t), zm = cb(x, yy, z == 0 ? L2 - 1 : z - 1, t);
+  const int tp = cb(x, yy, z, t + 1 == L3 ? 0 : t + 1), tm = cb(x, yy, z, t == 0 ? L3 - 1 : t - 1);
+  const S* Uown = p ? Uo : Ue;  // links leaving this site
+  const S* Uoth = p ? Ue : Uo;  // links arriving from the backward neighbours
+  C cw[4], diag;
+  if constexpr (sizeof(C) == 8) {
+    for (int m = 0; m < 4; ++m) cw[m] = a.cw_d[m];
+    diag = a.diag_d;
+  } else {
+    for (int m = 0; m < 4; ++m) cw[m] = a.cw_f[m];
+    diag = a.diag_f;
+  }
+  const C bt_f = (a.bc_t < 0 && t == L3 - 1) ? C(-1) : C(1);
+  const C bt_b = (a.bc_t < 0 && t == 0) ? C(-1) : C(1);
+  cplx<C> acc[1][12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[0][k] = {C(0), C(0)};
+  const C mh = C(-0.5);
+  do_hop<S, false, 1, 0, true, DAG>(Uown, in, acc, i, xp, rhs, Vh, mh * cw[0]);
+  do_hop<S, false, 1, 0, false, DAG>(Uoth, in, acc, xm, xm, rhs, Vh, mh * cw[0]);
+  do_hop<S, false, 1, 1, true, DAG>(Uown, in, acc, i, yp, rhs, Vh, mh * cw[1]);
+  do_hop<S, false, 1, 1, false, DAG>(Uoth, in, acc, ym, ym, rhs, Vh, mh * cw[1]);
+  do_hop<S, false, 1, 2, true, DAG>(Uown, in, acc, i, zp, rhs, Vh, mh * cw[2]);
+  do_hop<S, false, 1, 2, false, DAG>(Uoth, in, acc, zm, zm, rhs, Vh, mh * cw[2]);
+  do_hop<S, false, 1, 3, true, DAG>(Uown, in, acc, i, tp, rhs, Vh, mh * cw[3] * bt_f);
+  do_hop<S, false, 1, 3, false, DAG>(Uoth, in, acc, tm, tm, rhs, Vh, mh * cw[3] * bt_b);
+  const C sg = C(sgn);
+  cplx<C> w[1][12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) w[0][k] = sg * acc[0][k];
+  if constexpr (YM == 1) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[0][k] += ldc(y, sp_idx<false>(rhs, k, i, Vh));
+  } else if constexpr (YM == 2) {
+    cplx<C> yv[1][12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) yv[0][k] = ldc(y, sp_idx<false>(rhs, k, i, Vh));
+    if (Ap) {
+      clover_acc<S, 1>(Ap, i, Vh, yv, w);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) w[0][k] += diag * yv[0][k];
+    }
+  }
+  if constexpr (POST == 1) {
+    if (Aip) {
+      cplx<C> r[1][12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) r[0][k] = {C(0), C(0)};
+      clover_acc<S, 1>(Aip, i, Vh, w, r);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) w[0][k] = r[0][k];
+    } else {
+      const C inv = C(1) / diag;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) w[0][k] = inv * w[0][k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) stc(out, sp_idx<false>(rhs, k, i, Vh), w[0][k]);
+}
+
+// out = M in on one parity's half field, M the packed site term (or its inverse) of that
+// parity, or the scalar diag (or 1 / diag) when M is nullptr
+template <class S, bool INV>
+__global__ __launch_bounds__(kBlock) void k_site_eo(const S* __restrict__ M, const S* __restrict__ in,
+                                                    S* __restrict__ out, DslashArgs a) {
+  using C = ctype<S>;
+  const int Vh = a.V >> 1;
+  const int ntile = (Vh + kBlock - 1) / kBlock;
+  const int wg = blockIdx.x;
+  const int tile = wg % ntile, rhs = wg / ntile;
+  const int i = tile * kBlock + threadIdx.x;
+  if (i >= Vh) return;
+  cplx<C> v[1][12], r[1][12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    v[0][k] = ldc(in, sp_idx<false>(rhs, k, i, Vh));
+    r[0][k] = {C(0), C(0)};
+  }
+  if (M) {
+    clover_acc<S, 1>(M, i, Vh, v, r);
+  } else {
+    const C d = sizeof(C) == 8 ? C(a.diag_d) : C(a.diag_f);
+    const C f = INV ? C(1) / d : d;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r[0][k] = f * v[0][k];
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) stc(out, sp_idx<false>(rhs, k, i, Vh), r[0][k]);
+}
+
 }  // namespace
 
 void launch_dslash_batched(qmg_prec prec, const BatchLattice* lat_dev, int n_lat, int total_tiles,
@@ -764,6 +891,64 @@ void launch_dslash(qmg_prec prec, const void* U, const void* in, void* out, cons
     case QMG_BF16: launch_s<cbf16>(U, in, out, a, st); break;
     case QMG_F16: launch_s<chalf>(U, in, out, a, st); break;
   }
+}
+
+void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const void* Uo, int p, const void* in,
+                   const void* y, void* out, const void* Ap, const void* Aip, int ym, int post, double sgn,
+                   hipStream_t st) {
+  const int Vh = a.V / 2;
+  const dim3 grid(unsigned((Vh + kBlock - 1) / kBlock) * unsigned(a.nrhs));
+  // algorithmic traffic: the other parity's spinors and both parities' links once per site of
+  // this parity, y when used, the output, and the packed blocks when used
+  const double cb = double(prec_bytes(prec));
+  const double bytes = double(Vh) * (a.nrhs * (12.0 + 12.0 + (ym ? 12.0 : 0.0)) + 72.0 +
+                                     ((ym == 2 && Ap) ? 36.0 : 0.0) + ((post && Aip) ? 36.0 : 0.0)) * cb;
+  TimedLaunch tl("evenodd/hop", st, bytes, 1320.0 * Vh * a.nrhs);
+  auto go = [&](auto tag) {
+    using S = decltype(tag);
+    auto run = [&](auto kern) {
+      launch(kern, grid, dim3(kBlock), 0, st, static_cast<const S*>(Ue), static_cast<const S*>(Uo),
+             static_cast<const S*>(in), static_cast<const S*>(y), static_cast<S*>(out), static_cast<const S*>(Ap),
+             static_cast<const S*>(Aip), a, p, float(sgn));
+    };
+    const int form = ym * 2 + post;  // forms used by the Schur operator, the source and the reconstruction
+    if (a.dagger) {
+      if (form == 1) run(k_hop_eo<S, true, 0, 1>);
+      else if (form == 4) run(k_hop_eo<S, true, 2, 0>);
+      else if (form == 2) run(k_hop_eo<S, true, 1, 0>);
+      else run(k_hop_eo<S, true, 1, 1>);
+    } else {
+      if (form == 1) run(k_hop_eo<S, false, 0, 1>);
+      else if (form == 4) run(k_hop_eo<S, false, 2, 0>);
+      else if (form == 2) run(k_hop_eo<S, false, 1, 0>);
+      else run(k_hop_eo<S, false, 1, 1>);
+    }
+  };
+  QMG_CHECK((ym == 0 && post == 1) || (ym == 2 && post == 0) || (ym == 1 && post == 0) || (ym == 1 && post == 1),
+            QMG_EINVAL, "even-odd hop form (%d, %d) is not built", ym, post);
+  QMG_CHECK(prec == QMG_F64 || prec == QMG_F32, QMG_EDTYPE, "even-odd forms need F64 or F32 storage");
+  if (prec == QMG_F64) go(double2{});
+  else go(float2{});
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_site_eo(qmg_prec prec, const DslashArgs& a, const void* M, bool inv, const void* in, void* out,
+                    hipStream_t st) {
+  const int Vh = a.V / 2;
+  const dim3 grid(unsigned((Vh + kBlock - 1) / kBlock) * unsigned(a.nrhs));
+  auto go = [&](auto tag) {
+    using S = decltype(tag);
+    if (inv)
+      launch(k_site_eo<S, true>, grid, dim3(kBlock), 0, st, static_cast<const S*>(M), static_cast<const S*>(in),
+             static_cast<S*>(out), a);
+    else
+      launch(k_site_eo<S, false>, grid, dim3(kBlock), 0, st, static_cast<const S*>(M), static_cast<const S*>(in),
+             static_cast<S*>(out), a);
+  };
+  QMG_CHECK(prec == QMG_F64 || prec == QMG_F32, QMG_EDTYPE, "even-odd forms need F64 or F32 storage");
+  if (prec == QMG_F64) go(double2{});
+  else go(float2{});
+  QMG_LAUNCH_CHECK();
 }
 
 }  // namespace qmg

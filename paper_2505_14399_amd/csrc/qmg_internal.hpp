@@ -333,5 +333,24 @@ void launch_convert(const void* in, qmg_prec pin, void* out, qmg_prec pout, size
 // clover coefficients cs (spatial planes) and ct (planes containing t), from the native FP64
 // gauge field U64; synchronises st before returning (it frees a temporary)
 void launch_clover_field(const Geom& g, const void* U64, double cs, double ct, void* A64, hipStream_t st);
+// Even-odd forms (every extent even; half-lattice index = lexicographic index / 2).  Layouts:
+// spinor [rhs][12][V/2] per parity, gauge [parity][mu][9][V/2], packed site term and inverse
+// [parity][alpha][18][V/2] (nullptr: the scalar diagonal term).  F64 and F32 storage.
+// out (parity p) = POST(YM(y) + sgn H in): ym 0 nothing, 1 y, 2 A_p y; post 0 nothing, 1 A_p^-1;
+// the forms (ym, post) = (0, 1), (2, 0), (1, 0), (1, 1) are built.  a.nrhs, a.dagger apply.
+void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const void* Uo, int p, const void* in,
+                   const void* y, void* out, const void* Ap, const void* Aip, int ym, int post, double sgn,
+                   hipStream_t st);
+// out = M in (M = A_p, or A_p^-1 with inv) on one parity's half fields
+void launch_site_eo(qmg_prec prec, const DslashArgs& a, const void* M, bool inv, const void* in, void* out,
+                    hipStream_t st);
+void launch_eo_pack_gauge(const Geom& g, const void* canon, void* out, qmg_prec prec, hipStream_t st);
+void launch_eo_pack_spinor(const Geom& g, const void* canon, void* even, void* odd, int nrhs, qmg_prec prec,
+                           hipStream_t st);
+void launch_eo_unpack_spinor(const Geom& g, const void* even, const void* odd, void* canon, int nrhs, qmg_prec prec,
+                             hipStream_t st);
+// the full-lattice packed FP64 site term -> its half-lattice copy and inverse in prec (synchronises;
+// EBREAKDOWN if a block is singular)
+void launch_eo_site_term(const Geom& g, const void* A64, void* Aeo, void* Ainv, qmg_prec prec, hipStream_t st);
 
 }  // namespace qmg

@@ -1,0 +1,134 @@
+"""GPU parity of the even-odd (Schur complement) forms against oracle/evenodd.py: half-lattice
+packing, the site term and its inverse, the Schur operator and its adjoint (Wilson and clover,
+FP64 and FP32), and the preconditioned solve."""
+import numpy as np
+import pytest
+import torch
+
+import fields
+from oracle import clover, evenodd, geometry as geo
+from tests._util import to_gpu, to_np, rel, banner
+
+pytestmark = pytest.mark.gpu
+
+
+def _full(lat, qmg, even, odd=None):
+    """Half fields -> canonical full-lattice array (decoding through the C ABI's unpack)."""
+    odd = torch.zeros_like(even) if odd is None else odd
+    return to_np(qmg.eo_unpack_spinor(lat, even, odd))
+
+
+def _unpack_blocks(Ah, dims):
+    """[2 parity][2 alpha][18][V/2] -> [V][2][6][6] (decoding only)."""
+    Ah = to_np(Ah)
+    V = int(np.prod(dims))
+    par = evenodd.parity(dims)
+    out = np.zeros((V, 2, 6, 6), dtype=np.complex128)
+    for s_ in range(V):
+        p, i = par[s_], s_ // 2
+        for al in range(2):
+            e18 = Ah[p, al, :, i]
+            for e in range(3):
+                out[s_, al, 2 * e, 2 * e] = e18[e].real
+                out[s_, al, 2 * e + 1, 2 * e + 1] = e18[e].imag
+            e = 3
+            for a in range(6):
+                for b in range(a + 1, 6):
+                    out[s_, al, a, b] = e18[e]
+                    out[s_, al, b, a] = np.conj(e18[e])
+                    e += 1
+    return out
+
+
+def test_eo_packing_roundtrip(qmg):
+    dims = (4, 6, 2, 8)
+    banner(f"even-odd packing {dims}")
+    lat = qmg.Lattice(dims, 0.1, 1.0, -1)
+    psi = fields.gaussian_spinor(dims, 3, 41)
+    e, o = qmg.eo_pack_spinor(lat, to_gpu(psi))
+    assert np.array_equal(_full(lat, qmg, e, o), psi)
+    par = evenodd.parity(dims)
+    assert np.array_equal(_full(lat, qmg, e), evenodd.restrict_parity(psi, par, 0))
+    U = fields.random_gauge(dims, 0.5, 42)
+    Ueo = to_np(qmg.eo_pack_gauge(lat, to_gpu(U)))
+    for s_ in (0, 1, 7, 100, geo.volume(dims) - 1):
+        for mu in range(4):
+            assert np.array_equal(Ueo[par[s_], mu, :, s_ // 2], U[mu, s_].ravel())
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-6)])
+def test_eo_site_term_and_inverse(qmg, prec, tol):
+    dims = (4, 4, 2, 6)
+    banner(f"even-odd site term {prec}")
+    U = fields.random_gauge(dims, 0.7, 43)
+    m, xi, cs, ct = -0.2, 2.0, 1.2, 0.8
+    lat = qmg.Lattice(dims, m, xi, -1)
+    A, Ai = qmg.eo_site_term(lat, to_gpu(U), cs, ct, prec)
+    T = clover.clover_term(U, dims, cs, ct)
+    ref = clover.chiral_blocks(clover.site_term(T, m, xi))
+    assert rel(_unpack_blocks(A, dims), ref) < tol
+    assert rel(_unpack_blocks(Ai, dims), np.linalg.inv(ref)) < tol * 10
+
+
+CASES = [((4, 4, 4, 4), False, 0.05, 1.0), ((6, 4, 2, 8), True, -0.2, 2.0), ((4, 2, 4, 6), True, 0.1, 3.5)]
+
+
+@pytest.mark.parametrize("dims,clov,m,xi", CASES)
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-6)])
+def test_schur_apply_matches_oracle(qmg, dims, clov, m, xi, prec, tol):
+    """Dhat and Dhat^dag on 1-3 right-hand sides against the oracle's Schur complement."""
+    U = fields.random_gauge(dims, 0.6, 44)
+    cs, ct = (1.1, 0.9) if clov else (0.0, 0.0)
+    T = clover.clover_term(U, dims, cs, ct) if clov else None
+    eo = evenodd.EvenOdd(U, dims, m, xi, -1, T)
+    lat = qmg.Lattice(dims, m, xi, -1)
+    Ueo = qmg.eo_pack_gauge(lat, to_gpu(U), prec)
+    A, Ai = qmg.eo_site_term(lat, to_gpu(U), cs, ct, prec) if clov else (None, None)
+    for nrhs in (1, 3):
+        x = fields.gaussian_spinor(dims, nrhs, 45 + nrhs)
+        x_e = evenodd.restrict_parity(x, eo.par, 0)
+        xe, _ = qmg.eo_pack_spinor(lat, to_gpu(x), prec)
+        for dag in (False, True):
+            banner(f"schur {dims} clover={clov} {prec} nrhs={nrhs} dag={dag}")
+            got = _full(lat, qmg, qmg.schur_apply(lat, Ueo, xe, A, Ai, dagger=dag))
+            ref = eo.schur(x_e, dagger=dag)
+            assert rel(got, ref) < tol
+    if not clov:  # the Wilson form without site-term fields equals the packed one
+        Aw, Aiw = qmg.eo_site_term(lat, to_gpu(U), 0.0, 0.0, prec)
+        a = qmg.schur_apply(lat, Ueo, xe, Aw, Aiw)
+        b = qmg.schur_apply(lat, Ueo, xe)
+        assert rel(to_np(a), to_np(b)) < tol
+
+
+@pytest.mark.parametrize("clov", [False, True])
+def test_eo_solve(qmg, clov):
+    """The preconditioned solve and the full-lattice GMRES reach 1e-10 in the oracle's residual,
+    give the same solution, and the Schur system needs fewer iterations."""
+    dims = (8, 8, 8, 8)
+    banner(f"even-odd solve clover={clov}")
+    U = fields.random_gauge(dims, 0.4, 47)
+    m = 0.1
+    c = (1.0, 1.0) if clov else None
+    lat = qmg.Lattice(dims, m, 1.0, -1)
+    b = fields.gaussian_spinor(dims, 2, 48)
+    xe, ie = qmg.eo_solve(lat, to_gpu(U), to_gpu(b), c_sw=c, tol=1e-10, eo=True)
+    xf, i_f = qmg.eo_solve(lat, to_gpu(U), to_gpu(b), c_sw=c, tol=1e-10, eo=False)
+    print(f"[evenodd] clover={clov}: Schur {ie['outer_iters']} iterations ({ie['seconds']:.3f} s), "
+          f"full {i_f['outer_iters']} ({i_f['seconds']:.3f} s)")
+    T = clover.clover_term(U, dims, *c) if clov else np.zeros((geo.volume(dims), 12, 12), complex)
+    for x in (xe, xf):
+        r = b - clover.apply_clover(U, T, to_np(x), m, 1.0, -1, dims)
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 2e-10
+    assert rel(to_np(xe), to_np(xf)) < 1e-8
+    assert ie["outer_iters"] < i_f["outer_iters"]
+
+
+def test_eo_errors(qmg):
+    dims = (4, 4, 4, 4)
+    lat = qmg.Lattice(dims, 0.1, 1.0, -1)
+    U = to_gpu(fields.random_gauge(dims, 0.5, 49))
+    with pytest.raises(TypeError):
+        qmg.eo_pack_gauge(lat, U, "bf16")
+    b = to_gpu(fields.gaussian_spinor(dims, 1, 50))
+    _, info = qmg.eo_solve(lat, U, b, tol=1e-12, max_iter=3, check=False)
+    assert info["status"] != "OK" and info["outer_iters"] <= 3
