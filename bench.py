@@ -14,7 +14,8 @@ the dslash's algorithmic bandwidth on a 32^3 x 64 lattice (fields larger than th
 last-level cache) at 1 and 12 right-hand sides; `clover` is the same pair for the Wilson-clover
 operator (site term fused into the stencil) and the clover multigrid (setup and mixed-precision
 solve) on the same 16^3 x 32 anisotropic lattice with unit clover coefficients and a mass
-tuned for that operator.  `--workload aniso16x32_clover` makes the clover workload the main line.
+tuned for that operator; `evenodd` is the even-odd Schur operator's bandwidth on 32^3 x 64 and
+its GMRES solve against GMRES on the full operator.  `--workload aniso16x32_clover` makes the clover workload the main line.
 
 Counter runs: `bench.py --traffic-probe` runs a 256 MiB device copy (calibration) and then ten
 launches each of the solve's dslash and coarse apply in the solve's launch configuration; run it
@@ -74,6 +75,7 @@ def parse():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover operator and clover MG leg")
+    ap.add_argument("--no-evenodd", action="store_true", help="skip the even-odd preconditioning leg")
     ap.add_argument("--no-dslash-hbm", action="store_true",
                     help="skip the dslash bandwidth measurement on the 32^3x64 lattice")
     ap.add_argument("--levels", action="store_true",
@@ -234,6 +236,66 @@ def clover_mg(args):
             "coarse_iters": info["coarse_iters"], "true_rel_res": info["true_rel_res"],
             "operator": {"timed_launches": op["launches"], "avg_launch_us": avg * 1e3, "GBps": gbps,
                          "frac_hbm": gbps / PEAK_HBM_GBPS}}
+
+
+def evenodd_leg(args):
+    """Even-odd preconditioning: the Schur operator Dhat = A_ee - D_eo A_oo^-1 D_oe on 32^3 x 64
+    (FP32 storage, one right-hand side, Wilson and clover), timed per hop launch with the
+    library's dispatch events, and FP64 GMRES(32) on the Schur complement against GMRES(32) on the
+    full operator on the benchmark lattice, each operator at a mass about 0.3 above the left edge
+    of its spectrum (Wilson -0.4, edge -0.694; clover 0.05, edge -0.255): unpreconditioned GMRES
+    does not finish near the critical mass."""
+    import numpy as np
+    import torch
+
+    import fields
+    import paper_2505_14399_amd as q
+
+    out = {"schur_apply": {}, "solve": {}}
+    lat = q.Lattice(DSLASH_HBM_DIMS, -0.2, 1.0, -1)
+    V = lat.volume
+    g = torch.Generator(device="cuda").manual_seed(9)
+    H = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
+    U = torch.linalg.matrix_exp(0.3j * (H + H.conj().transpose(-1, -2)) / 2)
+    del H
+    Ueo = q.eo_pack_gauge(lat, U, "f32")
+    x = torch.randn(1, V, 4, 3, dtype=torch.complex128, device="cuda", generator=g)
+    xe, _ = q.eo_pack_spinor(lat, x, "f32")
+    del x
+    for name, c in (("wilson", None), ("clover", 1.0)):
+        A, Ai = q.eo_site_term(lat, U, c, c, "f32") if c else (None, None)
+        y = torch.empty_like(xe)
+        for _ in range(3):
+            q.schur_apply(lat, Ueo, xe, A, Ai, out=y)
+        q.timing_enable(True)
+        for _ in range(10):
+            q.schur_apply(lat, Ueo, xe, A, Ai, out=y)
+        t = q.timing_query("evenodd")
+        q.timing_enable(False)
+        ms = t["ms"] / max(1, t["launches"])
+        gbps = t["bytes"] / max(1, t["launches"]) / (ms * 1e-3) / 1e9
+        out["schur_apply"][name] = {"lattice": list(DSLASH_HBM_DIMS), "prec": "f32", "hop_launch_us": ms * 1e3,
+                                    "apply_us": 2 * ms * 1e3, "GBps": gbps, "frac_hbm": gbps / PEAK_HBM_GBPS}
+        del A, Ai, y
+    del U, Ueo, xe
+    torch.cuda.empty_cache()
+    w = workloads_get(args.workload)
+    dims = w["dims"]
+    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
+    b = torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda()
+    for name, c, m in (("wilson", None, -0.4), ("clover", 1.0, 0.05)):
+        lat = q.Lattice(dims, m, w["xi"], w["bc_t"])
+        res = {}
+        for form, eo in (("schur", True), ("full", False)):
+            q.eo_solve(lat, U, b, c_sw=c, tol=args.tol, eo=eo, max_iter=6000, check=False)  # warm-up
+            ts, info = [], None
+            for _ in range(3):
+                _, info = q.eo_solve(lat, U, b, c_sw=c, tol=args.tol, eo=eo, max_iter=6000, check=False)
+                ts.append(info["seconds"])
+            res[form] = {"s": float(np.median(ts)), "gmres_iters": info["outer_iters"],
+                         "true_rel_res": info["true_rel_res"], "status": info["status"]}
+        out["solve"][name] = dict(res, mass=m, lattice=list(dims))
+    return out
 
 
 def workloads_get(name):
@@ -647,6 +709,8 @@ def main():
         res["clover"] = {"mg": clover_mg(args)}
         if not args.no_dslash_hbm:
             res["clover"]["dslash_hbm"] = dslash_hbm(clover=True)
+    if not args.no_evenodd and not w.get("c_sw"):
+        res["evenodd"] = evenodd_leg(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, cnt)
     print(json.dumps(res), flush=True)
