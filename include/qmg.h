@@ -357,6 +357,18 @@ qmg_status qmg_mg_setup_times(const qmg_mg* mg, double* t);
  * Errors: EINVAL (null, coarse_steps outside [0, 63], graph not 0/1, graph without steps). */
 qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
 
+/* Fine-level post-smoother of the K-cycle (later qmg_mg_solve calls on this hierarchy).
+ * eo = 0 (default): n_post_smooth GMRES steps on D e = r from the prolonged correction.
+ * eo = 1: even-odd smoothing: t = r - D z for the prolonged correction z, n_post_smooth GMRES
+ *   steps from zero on the Schur system of t (Dhat e_e = t_e - D_eo A_oo^-1 t_o, the operator
+ *   of qmg_schur_apply), e_o = A_oo^-1 (t_o - D_oe e_e), z += e.  The half-lattice gauge field,
+ *   site term and its inverse are built once (FP64, and FP32 for an F32 inner precision) from
+ *   the handle's fields; synchronizes the stream.  Works with every form of qmg_mg_set_cycle.
+ *   The choice is not stored by qmg_mg_save.
+ * Errors: EINVAL (null, eo not 0/1), ESHAPE (an odd extent), EDTYPE (BF16/FP16 inner
+ *   precision), EBREAKDOWN (a singular site block), ENOMEM, EHIP. */
+qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream);
+
 /* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times the first 64
  * later launches of each instrumented kernel family and then about one in n (picked by a hash
  * of the call index) ("dslash/site", "dslash/twalk", "dslash/dir",

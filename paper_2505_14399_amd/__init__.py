@@ -71,6 +71,7 @@ SIGNATURES = {
     "qmg_eo_site_term": [_P, _D, _D, _P, _P, _P, _I, _P],
     "qmg_schur_apply": [_P, _P, _P, _P, _P, _P, _I, _I, _I, _P],
     "qmg_eo_solve": [_P, _P, _D, _D, _P, _P, _I, _D, _I, _I, _P, _P],
+    "qmg_mg_set_smoother": [_P, _I, _P],
     "qmg_pack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_unpack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_pack_gauge": [_P, _P, _P, _I, _P],
@@ -439,6 +440,10 @@ class MG:
         """K-cycle form: coarse_steps > 0 gives a device-exit coarse solve with that step budget;
         graph=True captures the cycle into a hipGraph replayed at every application."""
         _check(load_library().qmg_mg_set_cycle(self._h, int(coarse_steps), 1 if graph else 0))
+
+    def set_smoother(self, eo=False):
+        """Even-odd (eo=True) or plain GMRES post-smoothing on the fine level (see qmg.h)."""
+        _check(load_library().qmg_mg_set_smoother(self._h, 1 if eo else 0, _stream()))
 
     def stream_more(self, n_streams):
         """Resume the streaming SVD with n_streams more batches of test vectors (the counter RNG's

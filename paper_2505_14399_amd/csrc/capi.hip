@@ -194,6 +194,8 @@ struct KCycle : Precond {
   Gmres<S> gc, gf;
   DevBuf rc, ec, rS, zS, conv;
   std::unique_ptr<KCycleC<S>> Kc;  // level-one K-cycle when a third level exists
+  std::unique_ptr<SchurOp> schur;  // even-odd post-smoother: the Schur complement and its buffers
+  DevBuf eo_t, eo_e, eo_o, eo_u, eo_b, eo_xe, eo_xo;
   long coarse_iters = 0, smooth_iters = 0, cycles = 0;
   int last_coarse = 0;             // coarse steps of the previous cycle (host-checked form)
   hipStream_t gs = nullptr;        // private stream of the captured cycle
@@ -228,8 +230,30 @@ struct KCycle : Precond {
       last_coarse = rcs.iters;
     }
     launch_prolong(p, h, P, ec.p, z_s, nrhs, st);
-    gf.solve(D, r_s, z_s, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    if (h.eo_smoother)
+      eo_smooth(r_s, z_s, nrhs, st);
+    else
+      gf.solve(D, r_s, z_s, false, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
     smooth_iters += h.n_post;
+  }
+  // even-odd post-smoothing: t = r - D z, then n_post GMRES steps from zero on the Schur system
+  // of t (Dhat e_e = t_e - D_eo A_oo^-1 t_o), e_o = A_oo^-1 (t_o - D_oe e_e), z += e
+  void eo_smooth(const void* r_s, void* z_s, int nrhs, hipStream_t st) {
+    constexpr qmg_prec p = StoreTraits<S>::prec;
+    const int w = p == QMG_F64 ? 0 : 1;
+    const size_t nf = size_t(nrhs) * 12 * h.g.V, nh = nf / 2;
+    eo_t.ensure(nf * sizeof(S));
+    for (DevBuf* b : {&eo_e, &eo_o, &eo_u, &eo_b, &eo_xe, &eo_xo}) b->ensure(nh * sizeof(S));
+    if (!schur) schur.reset(new SchurOp(h.g, p, h.Ueo[w].p, h.Aeo[w].p, h.Aieo[w].p, false));
+    D.apply(z_s, eo_t.p, nrhs, st);
+    Blas<S>::axpby(1.0, r_s, -1.0, eo_t.p, nf, st);
+    launch_eo_split(p, h.g, eo_t.p, eo_e.p, eo_o.p, nrhs, st);
+    const DslashArgs a = make_dslash_args(h.g, nrhs, false, false);
+    launch_site_eo(p, a, schur->Aio, true, eo_o.p, eo_u.p, st);
+    launch_hop_eo(p, a, schur->Ue, schur->Uo, 0, eo_u.p, eo_e.p, eo_b.p, nullptr, nullptr, 1, 0, -1.0, st);
+    gf.solve(*schur, eo_b.p, eo_xe.p, true, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    launch_hop_eo(p, a, schur->Ue, schur->Uo, 1, eo_xe.p, eo_o.p, eo_xo.p, nullptr, schur->Aio, 1, 1, -1.0, st);
+    launch_eo_merge_add(p, h.g, eo_xe.p, eo_xo.p, z_s, nrhs, st);
   }
   void apply(const void* r, void* z, int nrhs, hipStream_t st) override {
     const size_t nc = size_t(nrhs) * 2 * h.k * h.blk.d;
@@ -1756,6 +1780,38 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph) {
               "with further levels the K-cycle is host-checked (coarse_steps must be 0)");
     mg->h.cycle_steps = coarse_steps;
     mg->h.cycle_graph = graph != 0;
+  });
+}
+
+qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    QMG_CHECK(eo == 0 || eo == 1, QMG_EINVAL, "eo must be 0 or 1");
+    HierarchyDev& h = mg->h;
+    if (!eo) {
+      h.eo_smoother = false;
+      return;
+    }
+    const Geom& g = h.g;
+    QMG_CHECK(g.L[0] % 2 == 0 && g.L[1] % 2 == 0 && g.L[2] % 2 == 0 && g.L[3] % 2 == 0, QMG_ESHAPE,
+              "even-odd preconditioning needs every extent even");
+    QMG_CHECK(h.inner == QMG_F64 || h.inner == QMG_F32, QMG_EDTYPE,
+              "the even-odd smoother needs an F64 or F32 inner precision");
+    const size_t n = size_t(36) * g.V;
+    for (int w = 0; w < (h.inner == QMG_F32 ? 2 : 1); ++w) {
+      const qmg_prec p = w ? QMG_F32 : QMG_F64;
+      if (!h.Ueo[w].p) {
+        h.Ueo[w].alloc(n * prec_bytes(p));
+        launch_eo_gauge_from_native(g, h.U64.p, h.Ueo[w].p, p, stream);
+      }
+      if (h.A64.p && !h.Aeo[w].p) {
+        h.Aeo[w].alloc(n * prec_bytes(p));
+        h.Aieo[w].alloc(n * prec_bytes(p));
+        launch_eo_site_term(g, h.A64.p, h.Aeo[w].p, h.Aieo[w].p, p, stream);
+      }
+    }
+    QMG_HIP(hipStreamSynchronize(stream));
+    h.eo_smoother = true;
   });
 }
 

@@ -163,6 +163,46 @@ __global__ __launch_bounds__(128) void k_eo_site_term(const double2* __restrict_
     for (int j = i + 1; j < 6; ++j, ++e) stc(Ainv, dst0 + size_t(e) * Vh, R[i][j]);
 }
 
+// native FP64 gauge [mu][9][V] -> [parity][mu][9][V/2]
+template <class S>
+__global__ void k_eo_gauge_from_native(const double2* __restrict__ in, S* __restrict__ out, EoGeom g, size_t n) {
+  const size_t q = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int site = int(q % g.V);
+  const size_t me = q / g.V;  // mu * 9 + e
+  const int Vh = g.V >> 1;
+  const int p = site_parity(site, g);
+  const double2 v = in[q];
+  stc(out, (size_t(p) * 36 + me) * Vh + (site >> 1), cplx<double>{v.x, v.y});
+}
+
+// native spinors [rhs][12][V] (storage S) -> half fields of each parity, and back (added)
+template <class S>
+__global__ void k_eo_split(const S* __restrict__ full, S* __restrict__ even, S* __restrict__ odd, EoGeom g,
+                           size_t n) {
+  const size_t q = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int site = int(q % g.V);
+  const size_t rk = q / g.V;  // rhs * 12 + component
+  const int Vh = g.V >> 1;
+  S* dst = site_parity(site, g) ? odd : even;
+  dst[rk * Vh + (site >> 1)] = full[q];
+}
+
+template <class S>
+__global__ void k_eo_merge_add(const S* __restrict__ even, const S* __restrict__ odd, S* __restrict__ full, EoGeom g,
+                               size_t n) {
+  const size_t q = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int site = int(q % g.V);
+  const size_t rk = q / g.V;
+  const int Vh = g.V >> 1;
+  const S* src = site_parity(site, g) ? odd : even;
+  const auto a = ldc(full, q);
+  const auto b = ldc(src, rk * Vh + (site >> 1));
+  stc(full, q, a + b);
+}
+
 template <class F>
 void dispatch_eo(qmg_prec p, F&& f) {
   QMG_CHECK(p == QMG_F64 || p == QMG_F32, QMG_EDTYPE, "even-odd fields need F64 or F32 storage");
@@ -207,6 +247,37 @@ void launch_eo_unpack_spinor(const Geom& g, const void* even, const void* odd, v
     using S = decltype(tag);
     k_eo_unpack_spinor<S><<<nblk(n), 256, 0, st>>>(static_cast<const S*>(even), static_cast<const S*>(odd),
                                                    static_cast<double2*>(canon), eo_geom(g), n);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_prec prec, hipStream_t st) {
+  const size_t n = size_t(36) * g.V;
+  dispatch_eo(prec, [&](auto tag) {
+    using S = decltype(tag);
+    k_eo_gauge_from_native<S><<<nblk(n), 256, 0, st>>>(static_cast<const double2*>(U64), static_cast<S*>(out),
+                                                        eo_geom(g), n);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even, void* odd, int nrhs, hipStream_t st) {
+  const size_t n = size_t(12) * g.V * nrhs;
+  dispatch_eo(prec, [&](auto tag) {
+    using S = decltype(tag);
+    k_eo_split<S><<<nblk(n), 256, 0, st>>>(static_cast<const S*>(full), static_cast<S*>(even), static_cast<S*>(odd),
+                                           eo_geom(g), n);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const void* odd, void* full, int nrhs,
+                         hipStream_t st) {
+  const size_t n = size_t(12) * g.V * nrhs;
+  dispatch_eo(prec, [&](auto tag) {
+    using S = decltype(tag);
+    k_eo_merge_add<S><<<nblk(n), 256, 0, st>>>(static_cast<const S*>(even), static_cast<const S*>(odd),
+                                               static_cast<S*>(full), eo_geom(g), n);
   });
   QMG_LAUNCH_CHECK();
 }

@@ -349,6 +349,12 @@ void launch_eo_pack_spinor(const Geom& g, const void* canon, void* even, void* o
                            hipStream_t st);
 void launch_eo_unpack_spinor(const Geom& g, const void* even, const void* odd, void* canon, int nrhs, qmg_prec prec,
                              hipStream_t st);
+// native FP64 gauge [mu][9][V] -> [parity][mu][9][V/2] in prec
+void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_prec prec, hipStream_t st);
+// native spinors [rhs][12][V] in prec -> half fields of each parity; full += the two halves
+void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even, void* odd, int nrhs, hipStream_t st);
+void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const void* odd, void* full, int nrhs,
+                         hipStream_t st);
 // the full-lattice packed FP64 site term -> its half-lattice copy and inverse in prec (synchronises;
 // EBREAKDOWN if a block is singular)
 void launch_eo_site_term(const Geom& g, const void* A64, void* Aeo, void* Ainv, qmg_prec prec, hipStream_t st);

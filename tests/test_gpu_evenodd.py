@@ -132,3 +132,74 @@ def test_eo_errors(qmg):
     b = to_gpu(fields.gaussian_spinor(dims, 1, 50))
     _, info = qmg.eo_solve(lat, U, b, tol=1e-12, max_iter=3, check=False)
     assert info["status"] != "OK" and info["outer_iters"] <= 3
+
+
+@pytest.mark.parametrize("clov", [False, True])
+def test_mg_even_odd_smoother_f64(qmg, clov):
+    """FP64 K-cycle with the even-odd post-smoother: the solve to 1e-12 equals dense LU (D and
+    D^dag); the captured device-exit cycle reproduces the eager one bit for bit."""
+    dims, block = (4, 4, 4, 8), (2, 2, 2, 2)
+    banner(f"MG even-odd smoother f64 clover={clov}")
+    U = fields.random_gauge(dims, 0.3, 51)
+    m = 0.05
+    c = (1.0, 1.0) if clov else None
+    lat = qmg.Lattice(dims, m, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 12, 4, 6, n_setup_iter=8, inner="f64", seed=3,
+                                        c_sw=c)
+    T = clover.clover_term(U, dims, *c) if clov else np.zeros((geo.volume(dims), 12, 12), complex)
+    Dm = clover.dense_clover(U, T, m, 1.0, -1, dims)
+    b = fields.gaussian_spinor(dims, 1, 52)
+    _, i_plain = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+    mg.set_smoother(eo=True)
+    x, info = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+    print(f"[evenodd] MG f64 clover={clov}: even-odd smoother {info[0]['outer_iters']} outer, "
+          f"plain {i_plain[0]['outer_iters']}")
+    assert info[0]["true_rel_res"] <= 1e-12
+    assert rel(to_np(x)[0], np.linalg.solve(Dm, b[0].ravel()).reshape(b[0].shape)) < 1e-8
+    xa, _ = qmg.mg_solve(mg, to_gpu(b), tol=1e-12, adjoint=True)
+    assert rel(to_np(xa)[0], np.linalg.solve(np.conj(Dm.T), b[0].ravel()).reshape(b[0].shape)) < 1e-8
+    try:
+        mg.set_cycle(12, graph=False)
+        x_e, info_e = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+        mg.set_cycle(12, graph=True)
+        x_g, info_g = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+    finally:
+        mg.set_cycle(0, graph=False)
+    assert info_e[0]["outer_iters"] == info_g[0]["outer_iters"] and torch.equal(x_e, x_g)
+    mg.set_smoother(eo=False)
+    _, i_back = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+    assert i_back[0]["outer_iters"] == i_plain[0]["outer_iters"]
+    mg.close()
+
+
+def test_mg_even_odd_smoother_mixed(qmg):
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    banner("MG even-odd smoother mixed f32")
+    U = fields.random_gauge(dims, 0.4, 53)
+    lat = qmg.Lattice(dims, 0.02, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 24, 8, 12, n_setup_iter=16, inner="f32", seed=3)
+    b = fields.gaussian_spinor(dims, 2, 54)
+    _, i_plain = qmg.mg_solve(mg, to_gpu(b), tol=1e-10)
+    mg.set_smoother(eo=True)
+    x, info = qmg.mg_solve(mg, to_gpu(b), tol=1e-10)
+    print(f"[evenodd] MG mixed: even-odd smoother {info[0]['outer_iters']} outer, plain {i_plain[0]['outer_iters']}")
+    r = b - clover.apply_clover(U, np.zeros((geo.volume(dims), 12, 12), complex), to_np(x), 0.02, 1.0, -1, dims)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 2e-10
+    mg.close()
+
+
+def test_mg_even_odd_smoother_errors(qmg):
+    banner("MG even-odd smoother errors")
+    dims = (4, 4, 4, 3)
+    U = to_gpu(fields.random_gauge(dims, 0.3, 55))
+    mg = qmg.mg_setup_stream_chiral_svd(qmg.Lattice(dims, 0.1, 1.0, -1), U, (2, 2, 2, 3), 8, 4, 4, n_setup_iter=2)
+    with pytest.raises(qmg.QmgError, match="every extent even"):
+        mg.set_smoother(eo=True)
+    mg.close()
+    dims = (4, 4, 4, 4)
+    U = to_gpu(fields.random_gauge(dims, 0.3, 56))
+    mg = qmg.mg_setup_stream_chiral_svd(qmg.Lattice(dims, 0.1, 1.0, -1), U, (2, 2, 2, 2), 8, 4, 4, n_setup_iter=2,
+                                        inner="bf16")
+    with pytest.raises(qmg.QmgError, match="F64 or F32 inner"):
+        mg.set_smoother(eo=True)
+    mg.close()
