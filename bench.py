@@ -5,7 +5,10 @@ Metric: seconds of the multigrid solve to a true relative residual of 1e-10 (mix
 FP32-inner / FP64-outer, compared with the plain FP64 path), dslash bandwidth and setup
 seconds.  One step is one pass of the whole hot path on the workload: setup (Philox test
 vectors, GMRES smoothing, chiral split, streaming SVD over all streams, P and R, Galerkin
-coarse operator) followed by the MG-preconditioned solve of one Gaussian right-hand side.
+coarse operator, the half-lattice fields of the even-odd smoother) followed by the
+MG-preconditioned solve of one Gaussian right-hand side, whose fine-level post-smoother works on
+the even-odd Schur system (`--plain-smoother`: GMRES on D; the line reports the other smoother's
+solve on the same hierarchy beside it).
 
 Prints one JSON line.  `value` is the median mixed-precision solve time (s) over the timed
 steps; `roofline` describes the dominant kernel measured live with HIP events over the timed
@@ -50,9 +53,10 @@ FAMILY_KERNEL = {
     "restrict": ("k_restrict", "transfer.hip"),
     "prolong": ("k_prolong", "transfer.hip"),
     "coarse_build": ("k_build_coarse", "transfer.hip"),
+    "evenodd/hop": ("k_hop_eo", "dslash.hip"),
 }
 FAMILIES = ("dslash/site", "dslash/twalk", "dslash/dir", "isvd", "coarse_apply", "prolong", "restrict",
-            "coarse_build")
+            "coarse_build", "evenodd/hop")
 CLOVER_FAMILIES = tuple(f.replace("dslash/", "clover/") for f in FAMILIES)
 CLOVER_WORKLOAD = "aniso16x32_clover"
 
@@ -76,6 +80,8 @@ def parse():
                     help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover operator and clover MG leg")
     ap.add_argument("--no-evenodd", action="store_true", help="skip the even-odd preconditioning leg")
+    ap.add_argument("--plain-smoother", action="store_true",
+                    help="GMRES post-smoothing on D instead of the even-odd smoother in the main solve")
     ap.add_argument("--no-dslash-hbm", action="store_true",
                     help="skip the dslash bandwidth measurement on the 32^3x64 lattice")
     ap.add_argument("--levels", action="store_true",
@@ -126,6 +132,14 @@ def traffic_probe(args):
     wc = torch.empty_like(vc)
     for i in range(10):
         q.coarse_apply(mg, vc if i % 2 == 0 else wc, out=wc if i % 2 == 0 else vc)
+    # the even-odd smoother's Schur operator: two hop launches per application
+    Ueo = q.eo_pack_gauge(lat, U, prec)
+    xe, _ = q.eo_pack_spinor(lat, torch.from_numpy(fields.gaussian_spinor(dims, 1, 2)).cuda(), prec)
+    ye = torch.empty_like(xe)
+    c = w.get("c_sw")
+    A, Ai = q.eo_site_term(lat, U, c[0], c[1], prec) if c else (None, None)
+    for i in range(10):
+        q.schur_apply(lat, Ueo, xe if i % 2 == 0 else ye, A, Ai, out=ye if i % 2 == 0 else xe)
     torch.cuda.synchronize()
     mg.close()
     print(json.dumps({"probe": w["name"], "dims": list(dims), "prec": prec}), flush=True)
@@ -194,8 +208,7 @@ def dslash_hbm(clover=False):
 
 def clover_mg(args):
     """The clover workload's setup and mixed-precision solve (one untimed warm-up setup + solve,
-    then three timed setups, each followed by one timed solve), with the operator's sampled
-    launch rate over the timed solves."""
+    then three timed setups, each followed by one timed solve)."""
     import numpy as np
     import torch
 
@@ -209,7 +222,9 @@ def clover_mg(args):
     b = torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda()
     kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
               n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"], c_sw=w["c_sw"])
+    eo = not args.plain_smoother
     mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
+    mg.set_smoother(eo=eo)
     q.mg_solve(mg, b, tol=args.tol)
     mg.close()
     torch.cuda.synchronize()
@@ -217,25 +232,20 @@ def clover_mg(args):
     for _ in range(3):
         t0 = time.perf_counter()
         mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
+        mg.set_smoother(eo=eo)
         t1 = time.perf_counter()
-        q.timing_enable(True, every=TIMING_SAMPLE)
         _, inf = q.mg_solve(mg, b, tol=args.tol)
         t2 = time.perf_counter()
-        op = q.timing_query("clover")
-        q.timing_enable(False)
         mg.close()
         setups.append(t1 - t0)
         solves.append(t2 - t1)
         info = inf[0]
     if info["true_rel_res"] > args.tol:
         raise SystemExit(f"clover solve did not reach {args.tol}: {info}")
-    avg = op["ms"] / max(1, op["launches"])
-    gbps = op["bytes"] / max(1, op["launches"]) / (avg * 1e-3) / 1e9
-    return {"workload": w["name"], "c_sw": list(w["c_sw"]), "mass": w["mass"], "setup_s": float(np.median(setups)),
+    return {"workload": w["name"], "c_sw": list(w["c_sw"]), "mass": w["mass"],
+            "smoother": "even-odd GMRES(8)" if eo else "GMRES(8)", "setup_s": float(np.median(setups)),
             "solve_s": float(np.median(solves)), "outer_iters": info["outer_iters"],
-            "coarse_iters": info["coarse_iters"], "true_rel_res": info["true_rel_res"],
-            "operator": {"timed_launches": op["launches"], "avg_launch_us": avg * 1e3, "GBps": gbps,
-                         "frac_hbm": gbps / PEAK_HBM_GBPS}}
+            "coarse_iters": info["coarse_iters"], "true_rel_res": info["true_rel_res"]}
 
 
 def evenodd_leg(args):
@@ -461,12 +471,16 @@ def traffic_from(args):
     fetch = read_counter(args.traffic_from[0], "FETCH_SIZE")
     write = read_counter(args.traffic_from[1], "WRITE_SIZE")
 
-    def pick(tab, prefix):
+    def pick(tab, prefix, merge=False):
+        found, allv = None, []
         for name, vals in tab.items():
             short = name.replace("qmg::(anonymous namespace)::", "").split("void ")[-1]
             if short.startswith(prefix):
-                return name, vals
-        return None, []
+                if not merge:
+                    return name, vals
+                found = found or name
+                allv += list(vals)
+        return found, allv
 
     # the calibration copy: the runtime's device-to-device copy kernel at its largest dispatches
     # (the three 256 MiB copies; the runtime's other copies are a few KiB)
@@ -486,19 +500,23 @@ def traffic_from(args):
              f"{w_copy / 1024:.0f} KiB for a {COPY_BYTES >> 20} MiB copy -> scale fetch x{f_scale:.3f}, "
              f"write x{w_scale:.3f}"]
     entry = rec.setdefault(w["name"], {})
-    for fam in ("dslash/dir", "dslash/site", "dslash/twalk", "coarse_apply"):
+    for fam in ("dslash/dir", "dslash/site", "dslash/twalk", "coarse_apply", "evenodd/hop"):
         prefix, src = FAMILY_KERNEL[fam]
-        name, fv = pick(fetch, prefix)
-        _, wv = pick(write, prefix)
+        merge = fam == "evenodd/hop"
+        name, fv = pick(fetch, prefix, merge)
+        _, wv = pick(write, prefix, merge)
         if not fv or not wv:
             continue
-        fb = float(np.median(fv)) * 1024.0 * f_scale
-        wb = float(np.median(wv)) * 1024.0 * w_scale
+        # the two hop forms of the Schur operator alternate: their mean is the family's launch
+        avg = np.mean if fam == "evenodd/hop" else np.median
+        fb = float(avg(fv)) * 1024.0 * f_scale
+        wb = float(avg(wv)) * 1024.0 * w_scale
         entry[fam] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
                       "dispatches": [len(fv), len(wv)], "kernel": name, "source": src,
                       "source_sha256": source_sha(src)}
         lines.append(f"{fam:14s} {name[:70]}: fetch {fb / 1e6:.2f} MB + write {wb / 1e6:.2f} MB = "
-                     f"{(fb + wb) / 1e6:.2f} MB per launch (median of {len(fv)}/{len(wv)} dispatches)")
+                     f"{(fb + wb) / 1e6:.2f} MB per launch ({'mean' if merge else 'median'} of {len(fv)}/{len(wv)} "
+                     f"dispatches)")
     os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
     json.dump(rec, open(TRAFFIC_JSON, "w"), indent=1)
     print("\n".join(lines))
@@ -600,9 +618,12 @@ def main():
     op_name = "clover" if w.get("c_sw") else "dslash"  # timing families of the fine operator
     families = CLOVER_FAMILIES if w.get("c_sw") else FAMILIES
 
+    eo_smoother = not args.plain_smoother
+
     def step():
         t0 = time.perf_counter()
         mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
+        mg.set_smoother(eo=eo_smoother)  # builds the half-lattice fields: part of the setup
         t1 = time.perf_counter()
         x, info = q.mg_solve(mg, b, tol=args.tol)
         t2 = time.perf_counter()
@@ -633,11 +654,25 @@ def main():
 
     # operation counts of one mixed solve (for the CPU baseline), from an untimed solve
     mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
+    mg.set_smoother(eo=eo_smoother)
     q.timing_enable(True)
     _, sinfo = q.mg_solve(mg, b, tol=args.tol)
     cnt = {f: q.timing_query(op_name if f == "dslash" else f)["launches"] for f in ("dslash", "coarse_apply",
                                                                                       "restrict")}
+    # an even-odd hop does the work of half a fine operator application
+    cnt["dslash"] += q.timing_query("evenodd")["launches"] // 2
     q.timing_enable(False)
+    # the other smoother on the same hierarchy, for comparison (untimed region)
+    mg.set_smoother(eo=not eo_smoother)
+    q.mg_solve(mg, b, tol=args.tol)
+    ts_other, other = [], None
+    for _ in range(2):
+        t0 = time.perf_counter()
+        _, other = q.mg_solve(mg, b, tol=args.tol)
+        ts_other.append(time.perf_counter() - t0)
+    other_solve = {"smoother": "plain" if eo_smoother else "even-odd", "s": float(np.median(ts_other)),
+                   "outer_iters": other[0]["outer_iters"], "coarse_iters": other[0]["coarse_iters"],
+                   "true_rel_res": other[0]["true_rel_res"]}
     mg.close()
     cnt["vector_ops"] = 12 * (sinfo[0]["smoother_iters"] + sinfo[0]["outer_iters"])
 
@@ -646,6 +681,7 @@ def main():
     if not args.no_fp64 and w["inner"] != "f64":
         kw64 = dict(setup_kw, inner="f64")
         mg64 = q.mg_setup_stream_chiral_svd(lat, U, **kw64)
+        mg64.set_smoother(eo=eo_smoother)
         ts64 = []
         for _ in range(2):
             t0 = time.perf_counter()
@@ -688,9 +724,11 @@ def main():
         "config": {"workload": w["name"], "lattice": list(dims), "xi": w["xi"], "eps": w["eps"],
                    "mass": w["mass"], "bc_t": w["bc_t"], "block": list(w["block"]), "n_test": w["n_test"],
                    "batch": w["batch"], "rank": w["rank"], "nrhs": 1, "tol": args.tol,
+                   "smoother": "even-odd GMRES(8)" if eo_smoother else "GMRES(8)",
                    **({"c_sw": list(w["c_sw"])} if w.get("c_sw") else {})},
         "setup_s": float(np.median(setups)),
         "solve_fp64": fp64_solve,
+        "solve_other_smoother": other_solve,
         "solve_info": infos[-1],
         "timing_sample": TIMING_SAMPLE,
         "dslash": {"timed_launches": ds["launches"], "avg_launch_us": ds_avg_ms * 1e3, "GBps": ds_gbps,
