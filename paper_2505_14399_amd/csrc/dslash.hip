@@ -831,6 +831,138 @@ __global__ __launch_bounds__(kBlock) void k_hop_eo(const S* __restrict__ Ue, con
   for (int k = 0; k < 12; ++k) stc(out, sp_idx<false>(rhs, k, i, Vh), w[0][k]);
 }
 
+// Rows I0 .. I0+2 of one chirality of the even-odd epilogue: x holds sgn H in (+ y with YM = 1)
+// on the six components of the chirality; YM = 2 adds A_p y, POST = 1 applies A_p^-1
+template <class S, int YM, int POST, int I0>
+__device__ inline void eo_rows(const S* __restrict__ Ab, const S* __restrict__ Aib, const S* __restrict__ y,
+                               size_t ybase, int Vh, ctype<S> diag, cplx<ctype<S>> (&x)[6], cplx<ctype<S>> (&r)[3]) {
+  using C = ctype<S>;
+  if constexpr (YM == 2) {
+    cplx<C> yv[6], ay[3];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) yv[j] = ldc(y, ybase + size_t(j) * Vh);
+    if (Ab) {
+      site_term_rows<S, I0>(Ab, Vh, yv, ay);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) ay[q] = diag * yv[I0 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r[q] = x[I0 + q] + ay[q];
+  } else if constexpr (POST == 1) {
+    if (Aib) {
+      site_term_rows<S, I0>(Aib, Vh, x, r);
+    } else {
+      const C inv = C(1) / diag;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) r[q] = inv * x[I0 + q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r[q] = x[I0 + q];
+  }
+}
+
+// Direction-split form of k_hop_eo for half lattices too small to fill the GPU with one thread
+// per site: a workgroup covers 64 half-lattice sites, wavefront mu forms the two hops along mu,
+// the partial spinors meet in LDS, and wavefront w then finishes output components
+// 3w .. 3w+2 (rows 3 (w & 1) .. +2 of chirality w >> 1) with the epilogue of k_hop_eo.
+template <class S, bool DAG, int YM, int POST>
+__global__ __launch_bounds__(kBlock) void k_hop_eo_dir(const S* __restrict__ Ue, const S* __restrict__ Uo,
+                                                       const S* __restrict__ in, const S* __restrict__ y,
+                                                       S* __restrict__ out, const S* __restrict__ Ap,
+                                                       const S* __restrict__ Aip, DslashArgs a, int p, float sgn) {
+  using C = ctype<S>;
+  constexpr int TS = kBlock / 4;
+  __shared__ cplx<C> part[4][12][TS];
+  const int Vh = a.V >> 1;
+  const int ntile = (Vh + TS - 1) / TS;
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = wg % ntile, rhs = wg / ntile;
+  const int lane = threadIdx.x & (TS - 1), mu = threadIdx.x / TS;
+  const int i = tile * TS + lane;
+  const bool live = i < Vh;
+  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
+  C cw, diag;
+  if constexpr (sizeof(C) == 8) {
+    cw = a.cw_d[mu];
+    diag = a.diag_d;
+  } else {
+    cw = a.cw_f[mu];
+    diag = a.diag_f;
+  }
+  cplx<C> acc[1][12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[0][k] = {C(0), C(0)};
+  if (live) {
+    const int Lxh = L0 >> 1;
+    const int xh = i % Lxh;
+    int row = i / Lxh;
+    const int yy = row % L1;
+    row /= L1;
+    const int z = row % L2;
+    const int t = row / L2;
+    int c[4] = {2 * xh + ((yy + z + t + p) & 1), yy, z, t};
+    const int L = a.L[mu];
+    const int cmu = c[mu];
+    auto cb = [&](int v) {
+      int d[4] = {c[0], c[1], c[2], c[3]};
+      d[mu] = v;
+      return (d[0] + L0 * (d[1] + L1 * (d[2] + L2 * d[3]))) >> 1;
+    };
+    const int fp = cb(cmu + 1 == L ? 0 : cmu + 1), bm = cb(cmu == 0 ? L - 1 : cmu - 1);
+    const C mh = C(-0.5);
+    C cf = mh * cw, cbk = mh * cw;
+    if (mu == 3 && a.bc_t < 0) {
+      if (t == L3 - 1) cf = -cf;
+      if (t == 0) cbk = -cbk;
+    }
+    const S* Uown = p ? Uo : Ue;
+    const S* Uoth = p ? Ue : Uo;
+    switch (mu) {  // uniform within the wavefront
+      case 0:
+        do_hop<S, false, 1, 0, true, DAG>(Uown, in, acc, i, fp, rhs, Vh, cf);
+        do_hop<S, false, 1, 0, false, DAG>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
+        break;
+      case 1:
+        do_hop<S, false, 1, 1, true, DAG>(Uown, in, acc, i, fp, rhs, Vh, cf);
+        do_hop<S, false, 1, 1, false, DAG>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
+        break;
+      case 2:
+        do_hop<S, false, 1, 2, true, DAG>(Uown, in, acc, i, fp, rhs, Vh, cf);
+        do_hop<S, false, 1, 2, false, DAG>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
+        break;
+      default:
+        do_hop<S, false, 1, 3, true, DAG>(Uown, in, acc, i, fp, rhs, Vh, cf);
+        do_hop<S, false, 1, 3, false, DAG>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
+        break;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) part[mu][k][lane] = acc[0][k];
+  __syncthreads();
+  if (!live) return;
+  const int al = mu >> 1;
+  const C sg = C(sgn);
+  cplx<C> x6[6], r[3];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int k = 6 * al + j;
+    cplx<C> h = part[0][k][lane];
+#pragma unroll
+    for (int m = 1; m < 4; ++m) h += part[m][k][lane];
+    x6[j] = sg * h;
+    if constexpr (YM == 1) x6[j] += ldc(y, sp_idx<false>(rhs, k, i, Vh));
+  }
+  const size_t ybase = sp_idx<false>(rhs, 6 * al, i, Vh);
+  const S* Ab = Ap ? Ap + size_t(al) * 18 * Vh + i : nullptr;
+  const S* Aib = Aip ? Aip + size_t(al) * 18 * Vh + i : nullptr;
+  if (mu & 1) eo_rows<S, YM, POST, 3>(Ab, Aib, y, ybase, Vh, diag, x6, r);
+  else eo_rows<S, YM, POST, 0>(Ab, Aib, y, ybase, Vh, diag, x6, r);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) stc(out, sp_idx<false>(rhs, 3 * mu + q, i, Vh), r[q]);
+}
+
 // out = M in on one parity's half field, M the packed site term (or its inverse) of that
 // parity, or the scalar diag (or 1 / diag) when M is nullptr
 template <class S, bool INV>
@@ -897,7 +1029,16 @@ void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const voi
                    const void* y, void* out, const void* Ap, const void* Aip, int ym, int post, double sgn,
                    hipStream_t st) {
   const int Vh = a.V / 2;
-  const dim3 grid(unsigned((Vh + kBlock - 1) / kBlock) * unsigned(a.nrhs));
+  // direction split for the clover forms on half lattices too small to fill the GPU with one
+  // thread per site (measured FP32, one RHS: clover 23.1 against 25.1 us at 16^3 x 32 and 43.4
+  // against 48.7 us at 24^3 x 32; the Wilson forms are faster one site per thread at every size,
+  // 12.3 against 21.3 us at 16^3 x 32).  Forced with the launch-variant codes 1 = one site per
+  // thread, 16 = direction split.
+  const bool with_site_term = (ym == 2 && Ap) || (post == 1 && Aip);
+  const bool split =
+      a.tchunk == 16 || (a.tchunk != 1 && with_site_term && long(Vh) * a.nrhs < (1L << 19));
+  const int per_wg = split ? kBlock / 4 : kBlock;
+  const dim3 grid(unsigned((Vh + per_wg - 1) / per_wg) * unsigned(a.nrhs));
   // algorithmic traffic: the other parity's spinors and both parities' links once per site of
   // this parity, y when used, the output, and the packed blocks when used
   const double cb = double(prec_bytes(prec));
@@ -912,17 +1053,22 @@ void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const voi
              static_cast<const S*>(Aip), a, p, float(sgn));
     };
     const int form = ym * 2 + post;  // forms used by the Schur operator, the source and the reconstruction
-    if (a.dagger) {
-      if (form == 1) run(k_hop_eo<S, true, 0, 1>);
-      else if (form == 4) run(k_hop_eo<S, true, 2, 0>);
-      else if (form == 2) run(k_hop_eo<S, true, 1, 0>);
-      else run(k_hop_eo<S, true, 1, 1>);
-    } else {
-      if (form == 1) run(k_hop_eo<S, false, 0, 1>);
-      else if (form == 4) run(k_hop_eo<S, false, 2, 0>);
-      else if (form == 2) run(k_hop_eo<S, false, 1, 0>);
-      else run(k_hop_eo<S, false, 1, 1>);
-    }
+    auto pick = [&](auto dag) {
+      constexpr bool D = decltype(dag)::value;
+      if (split) {
+        if (form == 1) run(k_hop_eo_dir<S, D, 0, 1>);
+        else if (form == 4) run(k_hop_eo_dir<S, D, 2, 0>);
+        else if (form == 2) run(k_hop_eo_dir<S, D, 1, 0>);
+        else run(k_hop_eo_dir<S, D, 1, 1>);
+      } else {
+        if (form == 1) run(k_hop_eo<S, D, 0, 1>);
+        else if (form == 4) run(k_hop_eo<S, D, 2, 0>);
+        else if (form == 2) run(k_hop_eo<S, D, 1, 0>);
+        else run(k_hop_eo<S, D, 1, 1>);
+      }
+    };
+    if (a.dagger) pick(std::true_type{});
+    else pick(std::false_type{});
   };
   QMG_CHECK((ym == 0 && post == 1) || (ym == 2 && post == 0) || (ym == 1 && post == 0) || (ym == 1 && post == 1),
             QMG_EINVAL, "even-odd hop form (%d, %d) is not built", ym, post);

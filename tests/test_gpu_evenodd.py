@@ -84,15 +84,20 @@ def test_schur_apply_matches_oracle(qmg, dims, clov, m, xi, prec, tol):
     lat = qmg.Lattice(dims, m, xi, -1)
     Ueo = qmg.eo_pack_gauge(lat, to_gpu(U), prec)
     A, Ai = qmg.eo_site_term(lat, to_gpu(U), cs, ct, prec) if clov else (None, None)
-    for nrhs in (1, 3):
-        x = fields.gaussian_spinor(dims, nrhs, 45 + nrhs)
-        x_e = evenodd.restrict_parity(x, eo.par, 0)
-        xe, _ = qmg.eo_pack_spinor(lat, to_gpu(x), prec)
-        for dag in (False, True):
-            banner(f"schur {dims} clover={clov} {prec} nrhs={nrhs} dag={dag}")
-            got = _full(lat, qmg, qmg.schur_apply(lat, Ueo, xe, A, Ai, dagger=dag))
-            ref = eo.schur(x_e, dagger=dag)
-            assert rel(got, ref) < tol
+    try:
+        for form in (0, 1, 16):  # launcher's choice, one thread per site, direction split
+            qmg.set_dslash_variant(form)
+            for nrhs in (1, 3):
+                x = fields.gaussian_spinor(dims, nrhs, 45 + nrhs)
+                x_e = evenodd.restrict_parity(x, eo.par, 0)
+                xe, _ = qmg.eo_pack_spinor(lat, to_gpu(x), prec)
+                for dag in (False, True):
+                    banner(f"schur {dims} clover={clov} {prec} form={form} nrhs={nrhs} dag={dag}")
+                    got = _full(lat, qmg, qmg.schur_apply(lat, Ueo, xe, A, Ai, dagger=dag))
+                    ref = eo.schur(x_e, dagger=dag)
+                    assert rel(got, ref) < tol
+    finally:
+        qmg.set_dslash_variant(0)
     if not clov:  # the Wilson form without site-term fields equals the packed one
         Aw, Aiw = qmg.eo_site_term(lat, to_gpu(U), 0.0, 0.0, prec)
         a = qmg.schur_apply(lat, Ueo, xe, Aw, Aiw)
@@ -111,7 +116,13 @@ def test_eo_solve(qmg, clov):
     c = (1.0, 1.0) if clov else None
     lat = qmg.Lattice(dims, m, 1.0, -1)
     b = fields.gaussian_spinor(dims, 2, 48)
+    try:  # the one-site-per-thread form for the source and reconstruction forms too
+        qmg.set_dslash_variant(1)
+        x1, _ = qmg.eo_solve(lat, to_gpu(U), to_gpu(b), c_sw=c, tol=1e-10, eo=True)
+    finally:
+        qmg.set_dslash_variant(0)
     xe, ie = qmg.eo_solve(lat, to_gpu(U), to_gpu(b), c_sw=c, tol=1e-10, eo=True)
+    assert rel(to_np(x1), to_np(xe)) < 1e-8
     xf, i_f = qmg.eo_solve(lat, to_gpu(U), to_gpu(b), c_sw=c, tol=1e-10, eo=False)
     print(f"[evenodd] clover={clov}: Schur {ie['outer_iters']} iterations ({ie['seconds']:.3f} s), "
           f"full {i_f['outer_iters']} ({i_f['seconds']:.3f} s)")
