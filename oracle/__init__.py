@@ -9,7 +9,7 @@ Every function follows a passage of the paper (arXiv 2505.14399,
 "Accelerating multigrid with streaming chiral SVD for Wilson fermions in
 lattice QCD") cited in its docstring; where the paper is silent (the Wilson
 operator's formula, gamma basis, boundary conditions, smoother, cycle) the
-reading is stated beside the code and listed in the design doc.
+reading is stated beside the code.
 
 Modules
   geometry   lexicographic sites, neighbour/sign tables, aggregates, coarse neighbours
