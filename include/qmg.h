@@ -305,13 +305,13 @@ qmg_status qmg_mg_load(const char* path, const void* U, qmg_mg** out, hipStream_
  *   Dhat = A_ee - D_eo A_oo^-1 D_oe,   Dhat x_e = b_e - D_eo A_oo^-1 b_o,
  *   x_o = A_oo^-1 (b_o - D_oe x_e);
  * Dhat^dagger = gamma_5 Dhat gamma_5 is the Schur complement of D^dagger.
- * Half-lattice layouts (device, precision F64 or F32 only): a site's half index is its
- * lexicographic index / 2;
+ * Half-lattice layouts (device, any qmg_prec; BF16/FP16 store and FP32 accumulate): a site's
+ * half index is its lexicographic index / 2;
  *   spinor      [nrhs][12 = 3*spin + colour][V/2] for one parity
  *   gauge       [2 parity][4 mu][9][V/2]        U_mu(x) stored at the parity of x
  *   site term   [2 parity][2 alpha][18][V/2]    the packed blocks of qmg_clover_field
- * Errors of every entry below: EINVAL (null, bad count, aliasing), ESHAPE (an odd extent),
- * EDTYPE (precision other than F64/F32), ENOMEM, EHIP. */
+ * Errors of every entry below: EINVAL (null, bad count, aliasing, bad enum), ESHAPE (an odd
+ * extent), ENOMEM, EHIP. */
 qmg_status qmg_eo_pack_gauge(const qmg_lattice* lat, const void* U, void* U_eo, qmg_prec prec, hipStream_t stream);
 qmg_status qmg_eo_pack_spinor(const qmg_lattice* lat, const void* canon_f64, void* even, void* odd, int32_t nrhs,
                               qmg_prec prec, hipStream_t stream);
@@ -362,11 +362,11 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
  * eo = 1: even-odd smoothing: t = r - D z for the prolonged correction z, n_post_smooth GMRES
  *   steps from zero on the Schur system of t (Dhat e_e = t_e - D_eo A_oo^-1 t_o, the operator
  *   of qmg_schur_apply), e_o = A_oo^-1 (t_o - D_oe e_e), z += e.  The half-lattice gauge field,
- *   site term and its inverse are built once (FP64, and FP32 for an F32 inner precision) from
- *   the handle's fields; synchronizes the stream.  Works with every form of qmg_mg_set_cycle.
- *   The choice is not stored by qmg_mg_save.
- * Errors: EINVAL (null, eo not 0/1), ESHAPE (an odd extent), EDTYPE (BF16/FP16 inner
- *   precision), EBREAKDOWN (a singular site block), ENOMEM, EHIP. */
+ *   site term and its inverse are built once (FP64, and in the inner precision when that is
+ *   not FP64) from the handle's fields; synchronizes the stream.  Works with every form of
+ *   qmg_mg_set_cycle.  The choice is not stored by qmg_mg_save.
+ * Errors: EINVAL (null, eo not 0/1), ESHAPE (an odd extent), EBREAKDOWN (a singular site
+ *   block), ENOMEM, EHIP. */
 qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream);
 
 /* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times the first 64

@@ -270,16 +270,18 @@ def clover_apply(lat: Lattice, U, A, psi, layout="canonical", dagger=False, out=
 
 
 def _eo_prec(prec):
-    p = _PREC[prec]
-    if p not in (F64, F32):
-        raise TypeError("even-odd fields are F64 or F32")
-    return p
+    return _PREC[prec]
+
+
+def _eo_shape(shape, p):
+    """BF16/FP16 fields carry complex numbers as a trailing pair of reals."""
+    return tuple(shape) + ((2,) if p in (BF16, F16) else ())
 
 
 def eo_pack_gauge(lat: Lattice, U64, prec="f64"):
     """canonical complex128 [4,V,3,3] -> half-lattice gauge [2,4,9,V/2] (parity, mu, entry, site)."""
     p = _eo_prec(prec)
-    out = torch.empty((2, 4, 9, lat.volume // 2), dtype=_dtype_of(p), device=U64.device)
+    out = torch.empty(_eo_shape((2, 4, 9, lat.volume // 2), p), dtype=_dtype_of(p), device=U64.device)
     s = lat.c()
     _check(load_library().qmg_eo_pack_gauge(ctypes.byref(s), _ptr(U64), _ptr(out), p, _stream()))
     return out
@@ -289,7 +291,7 @@ def eo_pack_spinor(lat: Lattice, psi64, prec="f64"):
     """canonical complex128 [nrhs,V,4,3] -> (even, odd) half fields [nrhs,12,V/2]."""
     p = _eo_prec(prec)
     nrhs = psi64.shape[0]
-    even = torch.empty((nrhs, 12, lat.volume // 2), dtype=_dtype_of(p), device=psi64.device)
+    even = torch.empty(_eo_shape((nrhs, 12, lat.volume // 2), p), dtype=_dtype_of(p), device=psi64.device)
     odd = torch.empty_like(even)
     s = lat.c()
     _check(load_library().qmg_eo_pack_spinor(ctypes.byref(s), _ptr(psi64), _ptr(even), _ptr(odd), nrhs, p,
@@ -311,7 +313,7 @@ def eo_site_term(lat: Lattice, U, c_sw_s=0.0, c_sw_t=None, prec="f64"):
     """(A_eo, Ainv_eo) [2,2,18,V/2]: the packed site term of D_sw (Wilson for zero coefficients)
     and its inverse in the half-lattice layout."""
     p = _eo_prec(prec)
-    A = torch.empty((2, 2, 18, lat.volume // 2), dtype=_dtype_of(p), device=U.device)
+    A = torch.empty(_eo_shape((2, 2, 18, lat.volume // 2), p), dtype=_dtype_of(p), device=U.device)
     Ai = torch.empty_like(A)
     s = lat.c()
     ct = c_sw_s if c_sw_t is None else c_sw_t

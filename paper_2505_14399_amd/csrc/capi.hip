@@ -677,9 +677,7 @@ Geom eo_geom_checked(const qmg_lattice* lat) {
   return g;
 }
 
-void check_eo_prec(qmg_prec p) {
-  QMG_CHECK(p == QMG_F64 || p == QMG_F32, QMG_EDTYPE, "even-odd fields need F64 or F32 storage");
-}
+void check_eo_prec(qmg_prec p) { check_prec(p); }
 
 // Device copy of the descriptor table of the last batched call (uploaded again, after the
 // stream has drained, when the lattice set changes)
@@ -1795,11 +1793,9 @@ qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream) {
     const Geom& g = h.g;
     QMG_CHECK(g.L[0] % 2 == 0 && g.L[1] % 2 == 0 && g.L[2] % 2 == 0 && g.L[3] % 2 == 0, QMG_ESHAPE,
               "even-odd preconditioning needs every extent even");
-    QMG_CHECK(h.inner == QMG_F64 || h.inner == QMG_F32, QMG_EDTYPE,
-              "the even-odd smoother needs an F64 or F32 inner precision");
     const size_t n = size_t(36) * g.V;
-    for (int w = 0; w < (h.inner == QMG_F32 ? 2 : 1); ++w) {
-      const qmg_prec p = w ? QMG_F32 : QMG_F64;
+    for (int w = 0; w < (h.inner != QMG_F64 ? 2 : 1); ++w) {
+      const qmg_prec p = w ? h.inner : QMG_F64;
       if (!h.Ueo[w].p) {
         h.Ueo[w].alloc(n * prec_bytes(p));
         launch_eo_gauge_from_native(g, h.U64.p, h.Ueo[w].p, p, stream);

@@ -205,9 +205,12 @@ __global__ void k_eo_merge_add(const S* __restrict__ even, const S* __restrict__
 
 template <class F>
 void dispatch_eo(qmg_prec p, F&& f) {
-  QMG_CHECK(p == QMG_F64 || p == QMG_F32, QMG_EDTYPE, "even-odd fields need F64 or F32 storage");
-  if (p == QMG_F64) f(double2{});
-  else f(float2{});
+  switch (p) {
+    case QMG_F64: f(double2{}); break;
+    case QMG_F32: f(float2{}); break;
+    case QMG_BF16: f(cbf16{}); break;
+    case QMG_F16: f(chalf{}); break;
+  }
 }
 
 EoGeom eo_geom(const Geom& g) {

@@ -42,7 +42,7 @@ struct HierarchyDev {
   DevBuf U32;                // FP32 gauge when the inner precision is below FP32 (outer GCR, setup)
   DevBuf A64, Ain, A32;      // packed site term with the clover term, beside U64, Uin, U32 (empty: Wilson)
   // even-odd smoother (qmg_mg_set_smoother): half-lattice gauge, site term and its inverse in
-  // FP64 ([0]) and in the inner precision ([1], when it is F32); site terms empty for Wilson
+  // FP64 ([0]) and in the inner precision ([1], when it is not F64); site terms empty for Wilson
   bool eo_smoother = false;
   DevBuf Ueo[2], Aeo[2], Aieo[2];
   DevBuf bsite, cnb;         // tables

@@ -335,7 +335,7 @@ void launch_convert(const void* in, qmg_prec pin, void* out, qmg_prec pout, size
 void launch_clover_field(const Geom& g, const void* U64, double cs, double ct, void* A64, hipStream_t st);
 // Even-odd forms (every extent even; half-lattice index = lexicographic index / 2).  Layouts:
 // spinor [rhs][12][V/2] per parity, gauge [parity][mu][9][V/2], packed site term and inverse
-// [parity][alpha][18][V/2] (nullptr: the scalar diagonal term).  F64 and F32 storage.
+// [parity][alpha][18][V/2] (nullptr: the scalar diagonal term).  Every storage precision.
 // out (parity p) = POST(YM(y) + sgn H in): ym 0 nothing, 1 y, 2 A_p y; post 0 nothing, 1 A_p^-1;
 // the forms (ym, post) = (0, 1), (2, 0), (1, 0), (1, 1) are built.  a.nrhs, a.dagger apply.
 void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const void* Uo, int p, const void* in,

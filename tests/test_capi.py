@@ -170,14 +170,14 @@ def test_even_odd_arguments_are_rejected_without_device_work():
     odd = _lat(dims=(4, 4, 3, 4))
     assert L.qmg_eo_pack_gauge(ctypes.byref(odd), dummy, P(32), q.F64, None) == -2
     assert b"every extent even" in L.qmg_last_error()
-    assert L.qmg_eo_pack_gauge(ctypes.byref(lat), dummy, P(32), q.BF16, None) == -3
+    assert L.qmg_eo_pack_gauge(ctypes.byref(lat), dummy, P(32), 7, None) == -1
     assert L.qmg_eo_pack_spinor(ctypes.byref(lat), dummy, P(32), None, 1, q.F64, None) == -1
     assert L.qmg_eo_unpack_spinor(ctypes.byref(lat), dummy, P(32), P(48), 0, q.F64, None) == -1
     assert L.qmg_eo_site_term(ctypes.byref(lat), D(1.0), D(float("inf")), dummy, P(32), P(48), q.F64, None) == -1
     # the Schur apply: aliasing, one of the two site-term fields missing, bad precision
     assert L.qmg_schur_apply(ctypes.byref(lat), dummy, None, None, P(32), P(32), 1, q.F64, 0, None) == -1
     assert L.qmg_schur_apply(ctypes.byref(lat), dummy, P(24), None, P(32), P(48), 1, q.F64, 0, None) == -1
-    assert L.qmg_schur_apply(ctypes.byref(lat), dummy, None, None, P(32), P(48), 1, q.F16, 0, None) == -3
+    assert L.qmg_schur_apply(ctypes.byref(lat), dummy, None, None, P(32), P(48), 1, 9, 0, None) == -1
     # the solve: odd extent with eo, bad tolerance
     info = q.qmg_solve_info()
     assert L.qmg_eo_solve(ctypes.byref(odd), dummy, D(0.0), D(0.0), P(32), P(48), 1, D(1e-10), 100, 1,

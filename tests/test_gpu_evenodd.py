@@ -138,8 +138,8 @@ def test_eo_errors(qmg):
     dims = (4, 4, 4, 4)
     lat = qmg.Lattice(dims, 0.1, 1.0, -1)
     U = to_gpu(fields.random_gauge(dims, 0.5, 49))
-    with pytest.raises(TypeError):
-        qmg.eo_pack_gauge(lat, U, "bf16")
+    with pytest.raises(KeyError):
+        qmg.eo_pack_gauge(lat, U, "fp8")
     b = to_gpu(fields.gaussian_spinor(dims, 1, 50))
     _, info = qmg.eo_solve(lat, U, b, tol=1e-12, max_iter=3, check=False)
     assert info["status"] != "OK" and info["outer_iters"] <= 3
@@ -209,8 +209,52 @@ def test_mg_even_odd_smoother_errors(qmg):
     mg.close()
     dims = (4, 4, 4, 4)
     U = to_gpu(fields.random_gauge(dims, 0.3, 56))
-    mg = qmg.mg_setup_stream_chiral_svd(qmg.Lattice(dims, 0.1, 1.0, -1), U, (2, 2, 2, 2), 8, 4, 4, n_setup_iter=2,
-                                        inner="bf16")
-    with pytest.raises(qmg.QmgError, match="F64 or F32 inner"):
-        mg.set_smoother(eo=True)
+    mg = qmg.mg_setup_stream_chiral_svd(qmg.Lattice(dims, 0.1, 1.0, -1), U, (2, 2, 2, 2), 8, 4, 4, n_setup_iter=2)
+    with pytest.raises(qmg.QmgError, match="eo must be 0 or 1"):
+        qmg._check(qmg.load_library().qmg_mg_set_smoother(mg.handle, 2, None))
+    mg.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 1e-2), ("f16", 2e-3)])
+@pytest.mark.parametrize("clov", [False, True])
+def test_schur_apply_half_storage(qmg, prec, tol, clov):
+    """BF16/FP16 storage with FP32 accumulation, both launch forms, against the oracle."""
+    dims = (6, 4, 2, 8)
+    U = fields.random_gauge(dims, 0.6, 57)
+    m, xi = -0.2, 2.0
+    cs, ct = (1.1, 0.9) if clov else (0.0, 0.0)
+    T = clover.clover_term(U, dims, cs, ct) if clov else None
+    eo = evenodd.EvenOdd(U, dims, m, xi, -1, T)
+    lat = qmg.Lattice(dims, m, xi, -1)
+    Ueo = qmg.eo_pack_gauge(lat, to_gpu(U), prec)
+    A, Ai = qmg.eo_site_term(lat, to_gpu(U), cs, ct, prec) if clov else (None, None)
+    x = fields.gaussian_spinor(dims, 2, 58)
+    xe, _ = qmg.eo_pack_spinor(lat, to_gpu(x), prec)
+    try:
+        for form in (0, 1, 16):
+            qmg.set_dslash_variant(form)
+            for dag in (False, True):
+                banner(f"schur {prec} clover={clov} form={form} dag={dag}")
+                got = _full(lat, qmg, qmg.schur_apply(lat, Ueo, xe, A, Ai, dagger=dag))
+                assert rel(got, eo.schur(evenodd.restrict_parity(x, eo.par, 0), dagger=dag)) < tol
+    finally:
+        qmg.set_dslash_variant(0)
+
+
+@pytest.mark.parametrize("inner", ["bf16", "f16"])
+def test_mg_even_odd_smoother_half_storage(qmg, inner):
+    """Half-storage K-cycle with the even-odd smoother: the solve reaches 1e-10 in the oracle's
+    residual."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    banner(f"MG even-odd smoother {inner}")
+    U = fields.random_gauge(dims, 0.4, 59)
+    lat = qmg.Lattice(dims, 0.02, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 24, 8, 12, n_setup_iter=16, inner=inner, seed=3)
+    b = fields.gaussian_spinor(dims, 1, 60)
+    _, i_plain = qmg.mg_solve(mg, to_gpu(b), tol=1e-10)
+    mg.set_smoother(eo=True)
+    x, info = qmg.mg_solve(mg, to_gpu(b), tol=1e-10)
+    print(f"[evenodd] MG {inner}: even-odd smoother {info[0]['outer_iters']} outer, plain {i_plain[0]['outer_iters']}")
+    r = b - clover.apply_clover(U, np.zeros((geo.volume(dims), 12, 12), complex), to_np(x), 0.02, 1.0, -1, dims)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 2e-10
     mg.close()
