@@ -361,11 +361,16 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
  * eo = 0 (default): n_post_smooth GMRES steps on D e = r from the prolonged correction.
  * eo = 1: even-odd smoothing: t = r - D z for the prolonged correction z, n_post_smooth GMRES
  *   steps from zero on the Schur system of t (Dhat e_e = t_e - D_eo A_oo^-1 t_o, the operator
- *   of qmg_schur_apply), e_o = A_oo^-1 (t_o - D_oe e_e), z += e.  The half-lattice gauge field,
+ *   of qmg_schur_apply), e_o = A_oo^-1 (t_o - D_oe e_e), z += e.
+ * eo = 2: as eo = 1, with the GMRES steps in s-step form (n_post_smooth <= 8; otherwise as 1):
+ *   the same minimisation of ||bhat - Dhat e_e|| over the Krylov space of dimension
+ *   n_post_smooth, from the basis bhat, Dhat bhat, ..., one pass of inner products and an FP64
+ *   normal-equation solve (equilibrated Cholesky; a pivot below 1e-13 ends the basis) on the
+ *   device, instead of n_post_smooth Gram-Schmidt steps.  The half-lattice gauge field,
  *   site term and its inverse are built once (FP64, and in the inner precision when that is
  *   not FP64) from the handle's fields; synchronizes the stream.  Works with every form of
  *   qmg_mg_set_cycle.  The choice is not stored by qmg_mg_save.
- * Errors: EINVAL (null, eo not 0/1), ESHAPE (an odd extent), EBREAKDOWN (a singular site
+ * Errors: EINVAL (null, eo not 0/1/2), ESHAPE (an odd extent), EBREAKDOWN (a singular site
  *   block), ENOMEM, EHIP. */
 qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream);
 

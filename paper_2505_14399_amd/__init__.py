@@ -443,9 +443,10 @@ class MG:
         graph=True captures the cycle into a hipGraph replayed at every application."""
         _check(load_library().qmg_mg_set_cycle(self._h, int(coarse_steps), 1 if graph else 0))
 
-    def set_smoother(self, eo=False):
-        """Even-odd (eo=True) or plain GMRES post-smoothing on the fine level (see qmg.h)."""
-        _check(load_library().qmg_mg_set_smoother(self._h, 1 if eo else 0, _stream()))
+    def set_smoother(self, eo=False, sstep=False):
+        """Even-odd (eo=True) or plain GMRES post-smoothing on the fine level; with sstep the
+        even-odd GMRES steps run in s-step form (see qmg.h)."""
+        _check(load_library().qmg_mg_set_smoother(self._h, (2 if sstep else 1) if eo else 0, _stream()))
 
     def stream_more(self, n_streams):
         """Resume the streaming SVD with n_streams more batches of test vectors (the counter RNG's

@@ -195,7 +195,7 @@ struct KCycle : Precond {
   DevBuf rc, ec, rS, zS, conv;
   std::unique_ptr<KCycleC<S>> Kc;  // level-one K-cycle when a third level exists
   std::unique_ptr<SchurOp> schur;  // even-odd post-smoother: the Schur complement and its buffers
-  DevBuf eo_t, eo_e, eo_o, eo_u, eo_b, eo_xe, eo_xo;
+  DevBuf eo_t, eo_e, eo_o, eo_u, eo_b, eo_xe, eo_xo, eo_basis, eo_c, eo_part;
   long coarse_iters = 0, smooth_iters = 0, cycles = 0;
   int last_coarse = 0;             // coarse steps of the previous cycle (host-checked form)
   hipStream_t gs = nullptr;        // private stream of the captured cycle
@@ -251,7 +251,23 @@ struct KCycle : Precond {
     const DslashArgs a = make_dslash_args(h.g, nrhs, false, false);
     launch_site_eo(p, a, schur->Aio, true, eo_o.p, eo_u.p, st);
     launch_hop_eo(p, a, schur->Ue, schur->Uo, 0, eo_u.p, eo_e.p, eo_b.p, nullptr, nullptr, 1, 0, -1.0, st);
-    gf.solve(*schur, eo_b.p, eo_xe.p, true, nrhs, std::max(1, h.n_post), h.n_post, 0.0, st);
+    const int ns = std::max(1, h.n_post);
+    if (h.eo_smoother == 2 && ns <= 8) {
+      // the same minimisation as GMRES(ns) from zero, over the basis b, Dhat b, ..., Dhat^ns b:
+      // one pass of inner products and an FP64 normal-equation solve on the device instead of
+      // ns Gram-Schmidt steps
+      const size_t L = size_t(12) * (h.g.V / 2);
+      eo_basis.ensure(size_t(ns + 1) * nh * sizeof(S));
+      eo_c.ensure(size_t(ns) * nrhs * sizeof(double2));
+      auto vec = [&](int i) { return static_cast<char*>(eo_basis.p) + size_t(i) * nh * sizeof(S); };
+      Blas<S>::copy(eo_b.p, vec(0), nh, st);
+      for (int i = 0; i < ns; ++i) schur->apply(vec(i), vec(i + 1), nrhs, st);
+      launch_sstep_coeffs(p, eo_basis.p, ns + 1, L, nrhs, eo_c.as<double2>(), eo_part, st);
+      Blas<S>::zero(eo_xe.p, nh, st);
+      Blas<S>::axpy_multi(eo_basis.p, nh, ns, eo_c.as<double2>(), 1.0, eo_xe.p, L, nrhs, st);
+    } else {
+      gf.solve(*schur, eo_b.p, eo_xe.p, true, nrhs, ns, h.n_post, 0.0, st);
+    }
     launch_hop_eo(p, a, schur->Ue, schur->Uo, 1, eo_xe.p, eo_o.p, eo_xo.p, nullptr, schur->Aio, 1, 1, -1.0, st);
     launch_eo_merge_add(p, h.g, eo_xe.p, eo_xo.p, z_s, nrhs, st);
   }
@@ -1784,10 +1800,10 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph) {
 qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream) {
   return guard([&] {
     check_ptr(mg, "mg");
-    QMG_CHECK(eo == 0 || eo == 1, QMG_EINVAL, "eo must be 0 or 1");
+    QMG_CHECK(eo >= 0 && eo <= 2, QMG_EINVAL, "eo must be 0, 1 or 2");
     HierarchyDev& h = mg->h;
     if (!eo) {
-      h.eo_smoother = false;
+      h.eo_smoother = 0;
       return;
     }
     const Geom& g = h.g;
@@ -1807,7 +1823,7 @@ qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream) {
       }
     }
     QMG_HIP(hipStreamSynchronize(stream));
-    h.eo_smoother = true;
+    h.eo_smoother = eo;
   });
 }
 

@@ -7,6 +7,8 @@
 // then x_o = A_oo^-1 (b_o - D_oe x_e).  A site's half-lattice index is its lexicographic index
 // divided by 2.  The hop kernels are in dslash.hip; this file moves fields between the full and
 // the half-lattice layouts and inverts the packed 6 x 6 blocks of the site term.
+#include <algorithm>
+
 #include "qmg_internal.hpp"
 
 namespace qmg {
@@ -203,6 +205,151 @@ __global__ void k_eo_merge_add(const S* __restrict__ even, const S* __restrict__
   stc(full, q, a + b);
 }
 
+// s-step residual minimisation over a Krylov basis p_0 .. p_{m-1} (m <= kSMax; vector i of rhs r
+// at P[(i * nrhs + r) * len]): with p_{j+1} = A p_j, the x = sum_j c_j p_j minimising
+// ||p_0 - A x|| solves the normal equations sum_j <p_{i+1}, p_{j+1}> c_j = <p_{i+1}, p_0>.  One
+// pass forms every inner product <p_i, p_j> (i <= j): per-thread sums in the accumulation
+// precision of S, FP64 across threads and workgroups.
+constexpr int kSMax = 9;
+constexpr int kPairs = kSMax * (kSMax + 1) / 2;
+
+template <class S>
+__global__ __launch_bounds__(256) void k_sstep_gram(const S* __restrict__ P, int m, size_t len, int nrhs,
+                                                    double2* __restrict__ part) {
+  using C = ctype<S>;
+  const int r = blockIdx.y;
+  cplx<C> acc[kPairs];
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q) acc[q] = {C(0), C(0)};
+  for (size_t e = size_t(blockIdx.x) * 256 + threadIdx.x; e < len; e += size_t(gridDim.x) * 256) {
+    cplx<C> v[kSMax];
+#pragma unroll
+    for (int i = 0; i < kSMax; ++i)
+      v[i] = i < m ? ldc(P, (size_t(i) * nrhs + r) * len + e) : cplx<C>{C(0), C(0)};
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < kSMax; ++i)
+#pragma unroll
+      for (int j = i; j < kSMax; ++j, ++q) acc[q] += cmul_conj(v[i], v[j]);
+  }
+  __shared__ double2 red[4][kPairs];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q) {
+    double re = double(acc[q].re), im = double(acc[q].im);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off);
+      im += __shfl_xor(im, off);
+    }
+    if (lane == 0) red[wave][q] = make_double2(re, im);
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < kPairs) {
+    double2 sum = red[0][t];
+    for (int w = 1; w < 4; ++w) {
+      sum.x += red[w][t].x;
+      sum.y += red[w][t].y;
+    }
+    part[(size_t(r) * gridDim.x + blockIdx.x) * kPairs + t] = sum;
+  }
+}
+
+// one workgroup per right-hand side: the workgroup partials of k_sstep_gram summed by 22 slices
+// x 45 pair threads through LDS into Gout[r][pair]
+__global__ __launch_bounds__(1024) void k_sstep_reduce(const double2* __restrict__ part, int nblk,
+                                                       double2* __restrict__ Gout) {
+  constexpr int kSlices = 1024 / kPairs;
+  __shared__ double2 red[kSlices][kPairs];
+  const int r = blockIdx.x, t = threadIdx.x;
+  const int q = t % kPairs, sl = t / kPairs;
+  if (sl < kSlices) {
+    double re = 0, im = 0;
+    for (int b = sl; b < nblk; b += kSlices) {
+      const double2 v = part[(size_t(r) * nblk + b) * kPairs + q];
+      re += v.x;
+      im += v.y;
+    }
+    red[sl][q] = make_double2(re, im);
+  }
+  __syncthreads();
+  if (t < kPairs) {
+    double re = 0, im = 0;
+    for (int w = 0; w < kSlices; ++w) {
+      re += red[w][t].x;
+      im += red[w][t].y;
+    }
+    Gout[size_t(r) * kPairs + t] = make_double2(re, im);
+  }
+}
+
+// one wavefront per right-hand side, one thread solving the s x s normal equations (s = m - 1),
+// equilibrated by the diagonal, by Cholesky in FP64 with compile-time indices (the unused rows
+// of the 8 x 8 factor are predicated off, so it stays in registers); a pivot below 1e-13 of the
+// unit diagonal ends the factor and the remaining coefficients are zero (the basis vectors beyond
+// it add nothing resolvable)
+__global__ __launch_bounds__(64) void k_sstep_solve(const double2* __restrict__ Gin, int m, int nrhs,
+                                                    double2* __restrict__ c) {
+  constexpr int kS = kSMax - 1;
+  const int r = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const double2* G = Gin + size_t(r) * kPairs;
+  const int s = m - 1;
+  auto inner = [&](int i, int j) {  // <p_i, p_j>
+    if (i <= j) {
+      const double2 v = G[i * kSMax - i * (i - 1) / 2 + (j - i)];
+      return cplx<double>{v.x, v.y};
+    }
+    const double2 v = G[j * kSMax - j * (j - 1) / 2 + (i - j)];
+    return cplx<double>{v.x, -v.y};
+  };
+  double dsc[kS];
+#pragma unroll
+  for (int a = 0; a < kS; ++a) {
+    const double d = a < s ? inner(a + 1, a + 1).re : 0.0;
+    dsc[a] = d > 0 ? 1.0 / sqrt(d) : 0.0;
+  }
+  cplx<double> L[kS][kS];
+  double Ld[kS];
+  int se = s;
+#pragma unroll
+  for (int k = 0; k < kS; ++k) {
+    cplx<double> d = k < s ? dsc[k] * dsc[k] * inner(k + 1, k + 1) : cplx<double>{1.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < k; ++j) d -= L[k][j] * conj(L[k][j]);
+    const bool good = !(k < se) || d.re > 1e-13;
+    if (k < se && !good) se = k;
+    Ld[k] = (k < se) ? sqrt(d.re) : 1.0;
+    L[k][k] = {Ld[k], 0.0};
+#pragma unroll
+    for (int i = k + 1; i < kS; ++i) {
+      cplx<double> v = i < s ? dsc[i] * dsc[k] * inner(i + 1, k + 1) : cplx<double>{0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < k; ++j) v -= L[i][j] * conj(L[k][j]);
+      L[i][k] = (1.0 / Ld[k]) * v;
+    }
+  }
+  cplx<double> y[kS];
+#pragma unroll
+  for (int i = 0; i < kS; ++i) {  // L y = D g
+    cplx<double> v = i < se ? dsc[i] * inner(i + 1, 0) : cplx<double>{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < i; ++j) v -= L[i][j] * y[j];
+    y[i] = i < se ? (1.0 / Ld[i]) * v : cplx<double>{0.0, 0.0};
+  }
+#pragma unroll
+  for (int i = kS - 1; i >= 0; --i) {  // L^dag chat = y, c = D chat
+    cplx<double> v = y[i];
+#pragma unroll
+    for (int j = i + 1; j < kS; ++j) v -= cmul_conj(L[j][i], y[j]);
+    y[i] = i < se ? (1.0 / Ld[i]) * v : cplx<double>{0.0, 0.0};
+  }
+#pragma unroll
+  for (int a = 0; a < kS; ++a)
+    if (a < s) c[size_t(a) * nrhs + r] = make_double2(dsc[a] * y[a].re, dsc[a] * y[a].im);
+}
+
 template <class F>
 void dispatch_eo(qmg_prec p, F&& f) {
   switch (p) {
@@ -282,6 +429,22 @@ void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const v
     k_eo_merge_add<S><<<nblk(n), 256, 0, st>>>(static_cast<const S*>(even), static_cast<const S*>(odd),
                                                static_cast<S*>(full), eo_geom(g), n);
   });
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_sstep_coeffs(qmg_prec prec, const void* P, int m, size_t len, int nrhs, double2* c, DevBuf& part,
+                         hipStream_t st) {
+  QMG_CHECK(m >= 2 && m <= kSMax, QMG_EINVAL, "s-step basis of %d vectors (2 .. %d)", m, kSMax);
+  const int nblk = int(std::max<size_t>(1, std::min<size_t>(512, len / (256 * 8))));
+  part.ensure(size_t(nrhs) * (nblk + 1) * kPairs * sizeof(double2));  // partials, then the reduced pairs
+  dispatch_eo(prec, [&](auto tag) {
+    using S = decltype(tag);
+    k_sstep_gram<S><<<dim3(nblk, nrhs), 256, 0, st>>>(static_cast<const S*>(P), m, len, nrhs, part.as<double2>());
+  });
+  QMG_LAUNCH_CHECK();
+  k_sstep_reduce<<<nrhs, 1024, 0, st>>>(part.as<double2>(), nblk, part.as<double2>() + size_t(nrhs) * nblk * kPairs);
+  QMG_LAUNCH_CHECK();
+  k_sstep_solve<<<nrhs, 64, 0, st>>>(part.as<double2>() + size_t(nrhs) * nblk * kPairs, m, nrhs, c);
   QMG_LAUNCH_CHECK();
 }
 

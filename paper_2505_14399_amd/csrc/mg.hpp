@@ -43,7 +43,7 @@ struct HierarchyDev {
   DevBuf A64, Ain, A32;      // packed site term with the clover term, beside U64, Uin, U32 (empty: Wilson)
   // even-odd smoother (qmg_mg_set_smoother): half-lattice gauge, site term and its inverse in
   // FP64 ([0]) and in the inner precision ([1], when it is not F64); site terms empty for Wilson
-  bool eo_smoother = false;
+  int eo_smoother = 0;  // 0: GMRES on D, 1: even-odd with GMRES, 2: even-odd with the s-step form
   DevBuf Ueo[2], Aeo[2], Aieo[2];
   DevBuf bsite, cnb;         // tables
   DevBuf blists;             // [8][nd]: in-block sites per hop direction, intra-block hops first

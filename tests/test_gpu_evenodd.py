@@ -210,8 +210,8 @@ def test_mg_even_odd_smoother_errors(qmg):
     dims = (4, 4, 4, 4)
     U = to_gpu(fields.random_gauge(dims, 0.3, 56))
     mg = qmg.mg_setup_stream_chiral_svd(qmg.Lattice(dims, 0.1, 1.0, -1), U, (2, 2, 2, 2), 8, 4, 4, n_setup_iter=2)
-    with pytest.raises(qmg.QmgError, match="eo must be 0 or 1"):
-        qmg._check(qmg.load_library().qmg_mg_set_smoother(mg.handle, 2, None))
+    with pytest.raises(qmg.QmgError, match="eo must be 0, 1 or 2"):
+        qmg._check(qmg.load_library().qmg_mg_set_smoother(mg.handle, 3, None))
     mg.close()
 
 
@@ -258,3 +258,54 @@ def test_mg_even_odd_smoother_half_storage(qmg, inner):
     r = b - clover.apply_clover(U, np.zeros((geo.volume(dims), 12, 12), complex), to_np(x), 0.02, 1.0, -1, dims)
     assert np.linalg.norm(r) / np.linalg.norm(b) < 2e-10
     mg.close()
+
+
+@pytest.mark.parametrize("clov", [False, True])
+def test_mg_sstep_smoother(qmg, clov):
+    """The s-step form of the even-odd smoother: FP64 solve equals dense LU (D and D^dag), the
+    captured cycle equals the eager one, and it takes about the outer iterations of the GMRES
+    form; the mixed FP32 and BF16 K-cycles reach 1e-10 in the oracle's residual."""
+    dims, block = (4, 4, 4, 8), (2, 2, 2, 2)
+    banner(f"MG s-step smoother clover={clov}")
+    U = fields.random_gauge(dims, 0.3, 61)
+    m = 0.05
+    c = (1.0, 1.0) if clov else None
+    lat = qmg.Lattice(dims, m, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 12, 4, 6, n_setup_iter=8, inner="f64", seed=3,
+                                        c_sw=c)
+    T = clover.clover_term(U, dims, *c) if clov else np.zeros((geo.volume(dims), 12, 12), complex)
+    Dm = clover.dense_clover(U, T, m, 1.0, -1, dims)
+    b = fields.gaussian_spinor(dims, 1, 62)
+    mg.set_smoother(eo=True)
+    _, i_gm = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+    mg.set_smoother(eo=True, sstep=True)
+    x, info = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+    print(f"[evenodd] MG f64 clover={clov}: s-step {info[0]['outer_iters']} outer, GMRES form {i_gm[0]['outer_iters']}")
+    assert info[0]["true_rel_res"] <= 1e-12
+    assert info[0]["outer_iters"] <= i_gm[0]["outer_iters"] + 2
+    assert rel(to_np(x)[0], np.linalg.solve(Dm, b[0].ravel()).reshape(b[0].shape)) < 1e-8
+    xa, _ = qmg.mg_solve(mg, to_gpu(b), tol=1e-12, adjoint=True)
+    assert rel(to_np(xa)[0], np.linalg.solve(np.conj(Dm.T), b[0].ravel()).reshape(b[0].shape)) < 1e-8
+    try:
+        mg.set_cycle(12, graph=False)
+        x_e, info_e = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+        mg.set_cycle(12, graph=True)
+        x_g, info_g = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+    finally:
+        mg.set_cycle(0, graph=False)
+    assert info_e[0]["outer_iters"] == info_g[0]["outer_iters"] and torch.equal(x_e, x_g)
+    mg.close()
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    U = fields.random_gauge(dims, 0.4, 63)
+    lat = qmg.Lattice(dims, 0.02, 1.0, -1)
+    T = clover.clover_term(U, dims, *c) if clov else np.zeros((geo.volume(dims), 12, 12), complex)
+    for inner in ("f32", "bf16"):
+        mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 24, 8, 12, n_setup_iter=16, inner=inner, seed=3,
+                                            c_sw=c)
+        mg.set_smoother(eo=True, sstep=True)
+        b = fields.gaussian_spinor(dims, 2, 64)
+        x, info = qmg.mg_solve(mg, to_gpu(b), tol=1e-10)
+        print(f"[evenodd] MG {inner} clover={clov}: s-step {info[0]['outer_iters']} outer")
+        r = b - clover.apply_clover(U, T, to_np(x), 0.02, 1.0, -1, dims)
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 2e-10
+        mg.close()
