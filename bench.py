@@ -7,8 +7,8 @@ seconds.  One step is one pass of the whole hot path on the workload: setup (Phi
 vectors, GMRES smoothing, chiral split, streaming SVD over all streams, P and R, Galerkin
 coarse operator, the half-lattice fields of the even-odd smoother) followed by the
 MG-preconditioned solve of one Gaussian right-hand side, whose fine-level post-smoother works on
-the even-odd Schur system (`--plain-smoother`: GMRES on D; the line reports the other smoother's
-solve on the same hierarchy beside it).
+the even-odd Schur system with its GMRES(8) steps in s-step form (`--plain-smoother`: GMRES on D;
+the line reports the other smoother's solve on the same hierarchy beside it).
 
 Prints one JSON line.  `value` is the median mixed-precision solve time (s) over the timed
 steps; `roofline` describes the dominant kernel measured live with HIP events over the timed
@@ -224,7 +224,7 @@ def clover_mg(args):
               n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"], c_sw=w["c_sw"])
     eo = not args.plain_smoother
     mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
-    mg.set_smoother(eo=eo)
+    mg.set_smoother(eo=eo, sstep=True)
     q.mg_solve(mg, b, tol=args.tol)
     mg.close()
     torch.cuda.synchronize()
@@ -232,7 +232,7 @@ def clover_mg(args):
     for _ in range(3):
         t0 = time.perf_counter()
         mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
-        mg.set_smoother(eo=eo)
+        mg.set_smoother(eo=eo, sstep=True)
         t1 = time.perf_counter()
         _, inf = q.mg_solve(mg, b, tol=args.tol)
         t2 = time.perf_counter()
@@ -243,7 +243,7 @@ def clover_mg(args):
     if info["true_rel_res"] > args.tol:
         raise SystemExit(f"clover solve did not reach {args.tol}: {info}")
     return {"workload": w["name"], "c_sw": list(w["c_sw"]), "mass": w["mass"],
-            "smoother": "even-odd GMRES(8)" if eo else "GMRES(8)", "setup_s": float(np.median(setups)),
+            "smoother": "even-odd GMRES(8), s-step form" if eo else "GMRES(8)", "setup_s": float(np.median(setups)),
             "solve_s": float(np.median(solves)), "outer_iters": info["outer_iters"],
             "coarse_iters": info["coarse_iters"], "true_rel_res": info["true_rel_res"]}
 
@@ -623,7 +623,7 @@ def main():
     def step():
         t0 = time.perf_counter()
         mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
-        mg.set_smoother(eo=eo_smoother)  # builds the half-lattice fields: part of the setup
+        mg.set_smoother(eo=eo_smoother, sstep=True)  # builds the half-lattice fields: part of the setup
         t1 = time.perf_counter()
         x, info = q.mg_solve(mg, b, tol=args.tol)
         t2 = time.perf_counter()
@@ -654,7 +654,7 @@ def main():
 
     # operation counts of one mixed solve (for the CPU baseline), from an untimed solve
     mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
-    mg.set_smoother(eo=eo_smoother)
+    mg.set_smoother(eo=eo_smoother, sstep=True)
     q.timing_enable(True)
     _, sinfo = q.mg_solve(mg, b, tol=args.tol)
     cnt = {f: q.timing_query(op_name if f == "dslash" else f)["launches"] for f in ("dslash", "coarse_apply",
@@ -663,7 +663,7 @@ def main():
     cnt["dslash"] += q.timing_query("evenodd")["launches"] // 2
     q.timing_enable(False)
     # the other smoother on the same hierarchy, for comparison (untimed region)
-    mg.set_smoother(eo=not eo_smoother)
+    mg.set_smoother(eo=not eo_smoother, sstep=True)
     q.mg_solve(mg, b, tol=args.tol)
     ts_other, other = [], None
     for _ in range(2):
@@ -681,7 +681,7 @@ def main():
     if not args.no_fp64 and w["inner"] != "f64":
         kw64 = dict(setup_kw, inner="f64")
         mg64 = q.mg_setup_stream_chiral_svd(lat, U, **kw64)
-        mg64.set_smoother(eo=eo_smoother)
+        mg64.set_smoother(eo=eo_smoother, sstep=True)
         ts64 = []
         for _ in range(2):
             t0 = time.perf_counter()
@@ -724,7 +724,7 @@ def main():
         "config": {"workload": w["name"], "lattice": list(dims), "xi": w["xi"], "eps": w["eps"],
                    "mass": w["mass"], "bc_t": w["bc_t"], "block": list(w["block"]), "n_test": w["n_test"],
                    "batch": w["batch"], "rank": w["rank"], "nrhs": 1, "tol": args.tol,
-                   "smoother": "even-odd GMRES(8)" if eo_smoother else "GMRES(8)",
+                   "smoother": "even-odd GMRES(8), s-step form" if eo_smoother else "GMRES(8)",
                    **({"c_sw": list(w["c_sw"])} if w.get("c_sw") else {})},
         "setup_s": float(np.median(setups)),
         "solve_fp64": fp64_solve,
