@@ -7,6 +7,11 @@
  * chiral SVD for Wilson fermions in lattice QCD" (arXiv 2505.14399): Eq. (1) (D x = b),
  * Eq. (2) (test vectors), Eq. (3) (chiral split), Eq. (5) (Galerkin coarse operator),
  * Eq. (6) (chiral-SVD prolongator), Eqs. (7)-(8) and Algorithms 3-4 (streaming update).
+ * Beyond the two-level path: up to four levels (qmg_mg_add_level), the clover term of the
+ * action used in Section 4 (qmg_clover_*; mg params c_sw_s / c_sw_t), even-odd (Schur
+ * complement) preconditioning of the fine operator named in Section 1 (qmg_eo_*,
+ * qmg_schur_apply, qmg_eo_solve, the even-odd post-smoother of qmg_mg_set_smoother),
+ * hierarchy checkpoints and resumable streams (qmg_mg_save / _load / _stream_more).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
