@@ -373,7 +373,9 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
  *   normal-equation solve (equilibrated Cholesky; a pivot below 1e-13 ends the basis) on the
  *   device, instead of n_post_smooth Gram-Schmidt steps.  The half-lattice gauge field,
  *   site term and its inverse are built once (FP64, and in the inner precision when that is
- *   not FP64) from the handle's fields; synchronizes the stream.  Works with every form of
+ *   not FP64) from the handle's fields; when every link is SU(3) to 1e-12 (third row = complex
+ *   conjugate of the cross product of the first two) only the first two rows are stored and
+ *   the hop kernels rebuild the third.  Synchronizes the stream.  Works with every form of
  *   qmg_mg_set_cycle.  The choice is not stored by qmg_mg_save.
  * Errors: EINVAL (null, eo not 0/1/2), ESHAPE (an odd extent), EBREAKDOWN (a singular site
  *   block), ENOMEM, EHIP. */

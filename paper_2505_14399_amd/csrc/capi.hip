@@ -93,12 +93,13 @@ struct SchurOp : LinOp {
   qmg_prec p;
   const void *Ue, *Uo, *Ae, *Ao, *Aie, *Aio;
   bool dag;
+  int ne;  // complex entries per stored link: 9, or 6 (two rows of SU(3) links)
   DevBuf tmp;
-  SchurOp(const Geom& g_, qmg_prec p_, const void* Ueo, const void* Aeo, const void* Ainv, bool dag_)
-      : g(g_), p(p_), dag(dag_) {
-    const size_t half = size_t(36) * (g.V / 2) * prec_bytes(p);  // one parity's gauge or packed block
+  SchurOp(const Geom& g_, qmg_prec p_, const void* Ueo, const void* Aeo, const void* Ainv, bool dag_, int ne_ = 9)
+      : g(g_), p(p_), dag(dag_), ne(ne_) {
+    const size_t half = size_t(36) * (g.V / 2) * prec_bytes(p);  // one parity's packed block
     Ue = Ueo;
-    Uo = static_cast<const char*>(Ueo) + half;
+    Uo = static_cast<const char*>(Ueo) + size_t(4) * ne * (g.V / 2) * prec_bytes(p);  // one parity's links
     Ae = Aeo;
     Ao = Aeo ? static_cast<const char*>(Aeo) + half : nullptr;
     Aie = Ainv;
@@ -107,6 +108,7 @@ struct SchurOp : LinOp {
   void apply(const void* in, void* out, int nrhs, hipStream_t st, const int* = nullptr) override {
     tmp.ensure(size_t(nrhs) * len() * prec_bytes(p));
     DslashArgs a = make_dslash_args(g, nrhs, dag, false);
+    a.link_ne = ne;
     launch_hop_eo(p, a, Ue, Uo, 1, in, nullptr, tmp.p, nullptr, Aio, 0, 1, 1.0, st);  // A_oo^-1 D_oe in
     launch_hop_eo(p, a, Ue, Uo, 0, tmp.p, in, out, Ae, nullptr, 2, 0, -1.0, st);      // A_ee in - D_eo (...)
   }
@@ -244,11 +246,12 @@ struct KCycle : Precond {
     const size_t nf = size_t(nrhs) * 12 * h.g.V, nh = nf / 2;
     eo_t.ensure(nf * sizeof(S));
     for (DevBuf* b : {&eo_e, &eo_o, &eo_u, &eo_b, &eo_xe, &eo_xo}) b->ensure(nh * sizeof(S));
-    if (!schur) schur.reset(new SchurOp(h.g, p, h.Ueo[w].p, h.Aeo[w].p, h.Aieo[w].p, false));
+    if (!schur) schur.reset(new SchurOp(h.g, p, h.Ueo[w].p, h.Aeo[w].p, h.Aieo[w].p, false, h.eo_ne));
     D.apply(z_s, eo_t.p, nrhs, st);
     Blas<S>::axpby(1.0, r_s, -1.0, eo_t.p, nf, st);
     launch_eo_split(p, h.g, eo_t.p, eo_e.p, eo_o.p, nrhs, st);
-    const DslashArgs a = make_dslash_args(h.g, nrhs, false, false);
+    DslashArgs a = make_dslash_args(h.g, nrhs, false, false);
+    a.link_ne = h.eo_ne;
     launch_site_eo(p, a, schur->Aio, true, eo_o.p, eo_u.p, st);
     launch_hop_eo(p, a, schur->Ue, schur->Uo, 0, eo_u.p, eo_e.p, eo_b.p, nullptr, nullptr, 1, 0, -1.0, st);
     const int ns = std::max(1, h.n_post);
@@ -1810,11 +1813,16 @@ qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream) {
     QMG_CHECK(g.L[0] % 2 == 0 && g.L[1] % 2 == 0 && g.L[2] % 2 == 0 && g.L[3] % 2 == 0, QMG_ESHAPE,
               "even-odd preconditioning needs every extent even");
     const size_t n = size_t(36) * g.V;
+    if (!h.Ueo[0].p) {
+      // SU(3) links (to 1e-12) are stored as their first two rows: the hop kernels rebuild the
+      // third, and read two thirds of the link bytes
+      h.eo_ne = launch_su3_row_defect(g, h.U64.p, stream) < 1e-12 ? 6 : 9;
+    }
     for (int w = 0; w < (h.inner != QMG_F64 ? 2 : 1); ++w) {
       const qmg_prec p = w ? h.inner : QMG_F64;
       if (!h.Ueo[w].p) {
-        h.Ueo[w].alloc(n * prec_bytes(p));
-        launch_eo_gauge_from_native(g, h.U64.p, h.Ueo[w].p, p, stream);
+        h.Ueo[w].alloc(size_t(4) * h.eo_ne * g.V * prec_bytes(p));
+        launch_eo_gauge_from_native(g, h.U64.p, h.Ueo[w].p, p, stream, h.eo_ne);
       }
       if (h.A64.p && !h.Aeo[w].p) {
         h.Aeo[w].alloc(n * prec_bytes(p));

@@ -46,6 +46,7 @@ DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical
   a.dagger = dagger ? 1 : 0;
   a.canonical = canonical ? 1 : 0;
   a.clov = nullptr;
+  a.link_ne = 9;
   return a;
 }
 
@@ -132,13 +133,26 @@ __device__ inline void su3_mul(const cplx<C>* u, const cplx<C>* h, cplx<C>* w) {
   }
 }
 
-template <class S, bool CANON, int NR, int MU, bool FWD, bool DAG>
+// NE = 6: native links stored as their first two rows ([mu][6][V]); the third row of an SU(3)
+// matrix is the complex conjugate of the cross product of the first two
+template <class S, bool CANON, int NR, int MU, bool FWD, bool DAG, int NE = 9>
 __device__ inline void do_hop(const S* __restrict__ U, const S* __restrict__ in, cplx<ctype<S>> (*acc)[12],
                               int link_site, int nb_site, int rhs0, int V, ctype<S> coef) {
   using C = ctype<S>;
   cplx<C> u[9];
+  if constexpr (NE == 9) {
 #pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = ldc(U, g_idx<CANON>(MU, e, link_site, V));
+    for (int e = 0; e < 9; ++e) u[e] = ldc(U, g_idx<CANON>(MU, e, link_site, V));
+  } else {
+    static_assert(!CANON && NE == 6, "two-row links exist in the native half-lattice layout only");
+#pragma unroll
+    for (int e = 0; e < 6; ++e) u[e] = ldc(U, (size_t(MU) * 6 + e) * V + link_site);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      u[6 + c] = conj(u[c1] * u[3 + c2] - u[c2] * u[3 + c1]);
+    }
+  }
   // forward hop uses (1 - gamma), backward (1 + gamma); D^dag swaps them
   const C s = (FWD != DAG) ? C(-1) : C(1);
 #pragma unroll
@@ -745,7 +759,7 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
 
 // out (parity p) = POST( YM(y) + sgn * H in ), H the hopping part of D (of D^dag with DAG),
 // in on parity 1 - p.  YM: 0 nothing, 1 y, 2 A_p y.  POST: 0 nothing, 1 A_p^-1.
-template <class S, bool DAG, int YM, int POST>
+template <class S, bool DAG, int YM, int POST, int NE = 9>
 __global__ __launch_bounds__(kBlock) void k_hop_eo(const S* __restrict__ Ue, const S* __restrict__ Uo,
                                                    const S* __restrict__ in, const S* __restrict__ y,
                                                    S* __restrict__ out, const S* __restrict__ Ap,
@@ -787,14 +801,14 @@ __global__ __launch_bounds__(kBlock) void k_hop_eo(const S* __restrict__ Ue, con
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[0][k] = {C(0), C(0)};
   const C mh = C(-0.5);
-  do_hop<S, false, 1, 0, true, DAG>(Uown, in, acc, i, xp, rhs, Vh, mh * cw[0]);
-  do_hop<S, false, 1, 0, false, DAG>(Uoth, in, acc, xm, xm, rhs, Vh, mh * cw[0]);
-  do_hop<S, false, 1, 1, true, DAG>(Uown, in, acc, i, yp, rhs, Vh, mh * cw[1]);
-  do_hop<S, false, 1, 1, false, DAG>(Uoth, in, acc, ym, ym, rhs, Vh, mh * cw[1]);
-  do_hop<S, false, 1, 2, true, DAG>(Uown, in, acc, i, zp, rhs, Vh, mh * cw[2]);
-  do_hop<S, false, 1, 2, false, DAG>(Uoth, in, acc, zm, zm, rhs, Vh, mh * cw[2]);
-  do_hop<S, false, 1, 3, true, DAG>(Uown, in, acc, i, tp, rhs, Vh, mh * cw[3] * bt_f);
-  do_hop<S, false, 1, 3, false, DAG>(Uoth, in, acc, tm, tm, rhs, Vh, mh * cw[3] * bt_b);
+  do_hop<S, false, 1, 0, true, DAG, NE>(Uown, in, acc, i, xp, rhs, Vh, mh * cw[0]);
+  do_hop<S, false, 1, 0, false, DAG, NE>(Uoth, in, acc, xm, xm, rhs, Vh, mh * cw[0]);
+  do_hop<S, false, 1, 1, true, DAG, NE>(Uown, in, acc, i, yp, rhs, Vh, mh * cw[1]);
+  do_hop<S, false, 1, 1, false, DAG, NE>(Uoth, in, acc, ym, ym, rhs, Vh, mh * cw[1]);
+  do_hop<S, false, 1, 2, true, DAG, NE>(Uown, in, acc, i, zp, rhs, Vh, mh * cw[2]);
+  do_hop<S, false, 1, 2, false, DAG, NE>(Uoth, in, acc, zm, zm, rhs, Vh, mh * cw[2]);
+  do_hop<S, false, 1, 3, true, DAG, NE>(Uown, in, acc, i, tp, rhs, Vh, mh * cw[3] * bt_f);
+  do_hop<S, false, 1, 3, false, DAG, NE>(Uoth, in, acc, tm, tm, rhs, Vh, mh * cw[3] * bt_b);
   const C sg = C(sgn);
   cplx<C> w[1][12];
 #pragma unroll
@@ -867,7 +881,7 @@ __device__ inline void eo_rows(const S* __restrict__ Ab, const S* __restrict__ A
 // per site: a workgroup covers 64 half-lattice sites, wavefront mu forms the two hops along mu,
 // the partial spinors meet in LDS, and wavefront w then finishes output components
 // 3w .. 3w+2 (rows 3 (w & 1) .. +2 of chirality w >> 1) with the epilogue of k_hop_eo.
-template <class S, bool DAG, int YM, int POST>
+template <class S, bool DAG, int YM, int POST, int NE = 9>
 __global__ __launch_bounds__(kBlock) void k_hop_eo_dir(const S* __restrict__ Ue, const S* __restrict__ Uo,
                                                        const S* __restrict__ in, const S* __restrict__ y,
                                                        S* __restrict__ out, const S* __restrict__ Ap,
@@ -921,20 +935,20 @@ __global__ __launch_bounds__(kBlock) void k_hop_eo_dir(const S* __restrict__ Ue,
     const S* Uoth = p ? Ue : Uo;
     switch (mu) {  // uniform within the wavefront
       case 0:
-        do_hop<S, false, 1, 0, true, DAG>(Uown, in, acc, i, fp, rhs, Vh, cf);
-        do_hop<S, false, 1, 0, false, DAG>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
+        do_hop<S, false, 1, 0, true, DAG, NE>(Uown, in, acc, i, fp, rhs, Vh, cf);
+        do_hop<S, false, 1, 0, false, DAG, NE>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
         break;
       case 1:
-        do_hop<S, false, 1, 1, true, DAG>(Uown, in, acc, i, fp, rhs, Vh, cf);
-        do_hop<S, false, 1, 1, false, DAG>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
+        do_hop<S, false, 1, 1, true, DAG, NE>(Uown, in, acc, i, fp, rhs, Vh, cf);
+        do_hop<S, false, 1, 1, false, DAG, NE>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
         break;
       case 2:
-        do_hop<S, false, 1, 2, true, DAG>(Uown, in, acc, i, fp, rhs, Vh, cf);
-        do_hop<S, false, 1, 2, false, DAG>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
+        do_hop<S, false, 1, 2, true, DAG, NE>(Uown, in, acc, i, fp, rhs, Vh, cf);
+        do_hop<S, false, 1, 2, false, DAG, NE>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
         break;
       default:
-        do_hop<S, false, 1, 3, true, DAG>(Uown, in, acc, i, fp, rhs, Vh, cf);
-        do_hop<S, false, 1, 3, false, DAG>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
+        do_hop<S, false, 1, 3, true, DAG, NE>(Uown, in, acc, i, fp, rhs, Vh, cf);
+        do_hop<S, false, 1, 3, false, DAG, NE>(Uoth, in, acc, bm, bm, rhs, Vh, cbk);
         break;
     }
   }
@@ -1044,7 +1058,7 @@ void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const voi
   // algorithmic traffic: the other parity's spinors and both parities' links once per site of
   // this parity, y when used, the output, and the packed blocks when used
   const double cb = double(prec_bytes(prec));
-  const double bytes = double(Vh) * (a.nrhs * (12.0 + 12.0 + (ym ? 12.0 : 0.0)) + 72.0 +
+  const double bytes = double(Vh) * (a.nrhs * (12.0 + 12.0 + (ym ? 12.0 : 0.0)) + 8.0 * a.link_ne +
                                      ((ym == 2 && Ap) ? 36.0 : 0.0) + ((post && Aip) ? 36.0 : 0.0)) * cb;
   TimedLaunch tl("evenodd/hop", st, bytes, 1320.0 * Vh * a.nrhs);
   auto go = [&](auto tag) {
@@ -1055,22 +1069,30 @@ void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const voi
              static_cast<const S*>(Aip), a, p, float(sgn));
     };
     const int form = ym * 2 + post;  // forms used by the Schur operator, the source and the reconstruction
-    auto pick = [&](auto dag) {
+    auto pick = [&](auto dag, auto ne) {
       constexpr bool D = decltype(dag)::value;
+      constexpr int NE = decltype(ne)::value;
       if (split) {
-        if (form == 1) run(k_hop_eo_dir<S, D, 0, 1>);
-        else if (form == 4) run(k_hop_eo_dir<S, D, 2, 0>);
-        else if (form == 2) run(k_hop_eo_dir<S, D, 1, 0>);
-        else run(k_hop_eo_dir<S, D, 1, 1>);
+        if (form == 1) run(k_hop_eo_dir<S, D, 0, 1, NE>);
+        else if (form == 4) run(k_hop_eo_dir<S, D, 2, 0, NE>);
+        else if (form == 2) run(k_hop_eo_dir<S, D, 1, 0, NE>);
+        else run(k_hop_eo_dir<S, D, 1, 1, NE>);
       } else {
-        if (form == 1) run(k_hop_eo<S, D, 0, 1>);
-        else if (form == 4) run(k_hop_eo<S, D, 2, 0>);
-        else if (form == 2) run(k_hop_eo<S, D, 1, 0>);
-        else run(k_hop_eo<S, D, 1, 1>);
+        if (form == 1) run(k_hop_eo<S, D, 0, 1, NE>);
+        else if (form == 4) run(k_hop_eo<S, D, 2, 0, NE>);
+        else if (form == 2) run(k_hop_eo<S, D, 1, 0, NE>);
+        else run(k_hop_eo<S, D, 1, 1, NE>);
       }
     };
-    if (a.dagger) pick(std::true_type{});
-    else pick(std::false_type{});
+    using N9 = std::integral_constant<int, 9>;
+    using N6 = std::integral_constant<int, 6>;
+    if (a.link_ne == 6) {
+      if (a.dagger) pick(std::true_type{}, N6{});
+      else pick(std::false_type{}, N6{});
+    } else {
+      if (a.dagger) pick(std::true_type{}, N9{});
+      else pick(std::false_type{}, N9{});
+    }
   };
   QMG_CHECK((ym == 0 && post == 1) || (ym == 2 && post == 0) || (ym == 1 && post == 0) || (ym == 1 && post == 1),
             QMG_EINVAL, "even-odd hop form (%d, %d) is not built", ym, post);

@@ -8,6 +8,7 @@
 // divided by 2.  The hop kernels are in dslash.hip; this file moves fields between the full and
 // the half-lattice layouts and inverts the packed 6 x 6 blocks of the site term.
 #include <algorithm>
+#include <cstring>
 
 #include "qmg_internal.hpp"
 
@@ -165,17 +166,42 @@ __global__ __launch_bounds__(128) void k_eo_site_term(const double2* __restrict_
     for (int j = i + 1; j < 6; ++j, ++e) stc(Ainv, dst0 + size_t(e) * Vh, R[i][j]);
 }
 
-// native FP64 gauge [mu][9][V] -> [parity][mu][9][V/2]
+// native FP64 gauge [mu][9][V] -> [parity][mu][ne][V/2] (ne = 9, or 6: rows 0 and 1)
 template <class S>
-__global__ void k_eo_gauge_from_native(const double2* __restrict__ in, S* __restrict__ out, EoGeom g, size_t n) {
+__global__ void k_eo_gauge_from_native(const double2* __restrict__ in, S* __restrict__ out, EoGeom g, size_t n,
+                                       int ne) {
   const size_t q = size_t(blockIdx.x) * 256 + threadIdx.x;
   if (q >= n) return;
   const int site = int(q % g.V);
   const size_t me = q / g.V;  // mu * 9 + e
+  const int mu = int(me / 9), e = int(me % 9);
+  if (e >= ne) return;
   const int Vh = g.V >> 1;
   const int p = site_parity(site, g);
   const double2 v = in[q];
-  stc(out, (size_t(p) * 36 + me) * Vh + (site >> 1), cplx<double>{v.x, v.y});
+  stc(out, ((size_t(p) * 4 + mu) * ne + e) * Vh + (site >> 1), cplx<double>{v.x, v.y});
+}
+
+// max over links of |row 2 - conj(row 0 x row 1)| (FP64), as the bits of a non-negative double
+__global__ void k_su3_row_defect(const double2* __restrict__ U, int V, unsigned long long* __restrict__ out) {
+  const size_t q = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (q >= size_t(4) * V) return;
+  const int site = int(q % V), mu = int(q / V);
+  cplx<double> u[9];
+  for (int e = 0; e < 9; ++e) {
+    const double2 v = U[(size_t(mu) * 9 + e) * V + site];
+    u[e] = {v.x, v.y};
+  }
+  double d = 0;
+  for (int c = 0; c < 3; ++c) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    const cplx<double> r = conj(u[c1] * u[3 + c2] - u[c2] * u[3 + c1]);
+    d = fmax(d, sqrt(norm2(u[6 + c] - r)));
+  }
+  if (!(d == d)) d = 1e300;  // a non-finite link is no SU(3) link
+  unsigned long long bits;
+  memcpy(&bits, &d, sizeof(bits));
+  atomicMax(out, bits);
 }
 
 // native spinors [rhs][12][V] (storage S) -> half fields of each parity, and back (added)
@@ -401,14 +427,29 @@ void launch_eo_unpack_spinor(const Geom& g, const void* even, const void* odd, v
   QMG_LAUNCH_CHECK();
 }
 
-void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_prec prec, hipStream_t st) {
+void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_prec prec, hipStream_t st, int ne) {
+  QMG_CHECK(ne == 9 || ne == 6, QMG_EINVAL, "links carry 9 or 6 complex entries");
   const size_t n = size_t(36) * g.V;
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
     k_eo_gauge_from_native<S><<<nblk(n), 256, 0, st>>>(static_cast<const double2*>(U64), static_cast<S*>(out),
-                                                        eo_geom(g), n);
+                                                        eo_geom(g), n, ne);
   });
   QMG_LAUNCH_CHECK();
+}
+
+double launch_su3_row_defect(const Geom& g, const void* U64, hipStream_t st) {
+  DevBuf m(sizeof(unsigned long long));
+  QMG_HIP(hipMemsetAsync(m.p, 0, sizeof(unsigned long long), st));
+  k_su3_row_defect<<<nblk(size_t(4) * g.V), 256, 0, st>>>(static_cast<const double2*>(U64), g.V,
+                                                           static_cast<unsigned long long*>(m.p));
+  QMG_LAUNCH_CHECK();
+  unsigned long long bits = 0;
+  QMG_HIP(hipMemcpyAsync(&bits, m.p, sizeof(bits), hipMemcpyDeviceToHost, st));
+  QMG_HIP(hipStreamSynchronize(st));
+  double d;
+  std::memcpy(&d, &bits, sizeof(d));
+  return d;
 }
 
 void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even, void* odd, int nrhs, hipStream_t st) {

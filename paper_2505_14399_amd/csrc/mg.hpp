@@ -45,6 +45,7 @@ struct HierarchyDev {
   // FP64 ([0]) and in the inner precision ([1], when it is not F64); site terms empty for Wilson
   int eo_smoother = 0;  // 0: GMRES on D, 1: even-odd with GMRES, 2: even-odd with the s-step form
   DevBuf Ueo[2], Aeo[2], Aieo[2];
+  int eo_ne = 9;  // complex entries per link in Ueo: 9, or 6 for SU(3) links (two rows stored)
   DevBuf bsite, cnb;         // tables
   DevBuf blists;             // [8][nd]: in-block sites per hop direction, intra-block hops first
   DevBuf P64, Pin;           // [d][2][k][N]

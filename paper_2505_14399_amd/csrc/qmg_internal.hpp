@@ -303,6 +303,9 @@ struct DslashArgs {
   // real diagonal in pairs, 3..17: the upper triangle row by row); nullptr: the scalar
   // diagonal term of the Wilson operator
   const void* clov;
+  // complex entries stored per link in the half-lattice gauge field of the even-odd forms: 9, or
+  // 6 (the first two rows of SU(3) links; the third is rebuilt in the kernel)
+  int link_ne;
 };
 DslashArgs make_dslash_args(const Geom& g, int nrhs, bool dagger, bool canonical);
 
@@ -349,8 +352,11 @@ void launch_eo_pack_spinor(const Geom& g, const void* canon, void* even, void* o
                            hipStream_t st);
 void launch_eo_unpack_spinor(const Geom& g, const void* even, const void* odd, void* canon, int nrhs, qmg_prec prec,
                              hipStream_t st);
-// native FP64 gauge [mu][9][V] -> [parity][mu][9][V/2] in prec
-void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_prec prec, hipStream_t st);
+// native FP64 gauge [mu][9][V] -> [parity][mu][ne][V/2] in prec (ne = 9, or 6: the first two rows)
+void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_prec prec, hipStream_t st,
+                                 int ne = 9);
+// largest |third row - conj(row0 x row1)| over the native FP64 gauge field (synchronises)
+double launch_su3_row_defect(const Geom& g, const void* U64, hipStream_t st);
 // native spinors [rhs][12][V] in prec -> half fields of each parity; full += the two halves
 void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even, void* odd, int nrhs, hipStream_t st);
 void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const void* odd, void* full, int nrhs,

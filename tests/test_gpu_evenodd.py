@@ -309,3 +309,24 @@ def test_mg_sstep_smoother(qmg, clov):
         r = b - clover.apply_clover(U, T, to_np(x), 0.02, 1.0, -1, dims)
         assert np.linalg.norm(r) / np.linalg.norm(b) < 2e-10
         mg.close()
+
+
+def test_mg_even_odd_smoother_non_su3_links(qmg):
+    """Links that are not SU(3) (scaled by 1.01) keep all nine entries in the smoother's
+    half-lattice field (the third row cannot be rebuilt): the s-step and Gram-Schmidt forms still
+    solve to the dense LU solution; SU(3) links (two stored rows) give the same solution too."""
+    dims, block = (4, 4, 4, 8), (2, 2, 2, 2)
+    banner("MG even-odd smoother, non-SU(3) links")
+    U = fields.random_gauge(dims, 0.3, 65)
+    b = fields.gaussian_spinor(dims, 1, 66)
+    for scale in (1.0, 1.01):
+        Us = U * scale
+        lat = qmg.Lattice(dims, 0.1, 1.0, -1)
+        mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(Us), block, 12, 4, 6, n_setup_iter=8, inner="f64", seed=3)
+        Dm = clover.dense_clover(Us, np.zeros((geo.volume(dims), 12, 12), complex), 0.1, 1.0, -1, dims)
+        xd = np.linalg.solve(Dm, b[0].ravel()).reshape(b[0].shape)
+        for ss in (False, True):
+            mg.set_smoother(eo=True, sstep=ss)
+            x, info = qmg.mg_solve(mg, to_gpu(b), tol=1e-12)
+            assert info[0]["true_rel_res"] <= 1e-12 and rel(to_np(x)[0], xd) < 1e-8, (scale, ss, info[0])
+        mg.close()
