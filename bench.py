@@ -132,14 +132,10 @@ def traffic_probe(args):
     wc = torch.empty_like(vc)
     for i in range(10):
         q.coarse_apply(mg, vc if i % 2 == 0 else wc, out=wc if i % 2 == 0 else vc)
-    # the even-odd smoother's Schur operator: two hop launches per application
-    Ueo = q.eo_pack_gauge(lat, U, prec)
-    xe, _ = q.eo_pack_spinor(lat, torch.from_numpy(fields.gaussian_spinor(dims, 1, 2)).cuda(), prec)
-    ye = torch.empty_like(xe)
-    c = w.get("c_sw")
-    A, Ai = q.eo_site_term(lat, U, c[0], c[1], prec) if c else (None, None)
-    for i in range(10):
-        q.schur_apply(lat, Ueo, xe if i % 2 == 0 else ye, A, Ai, out=ye if i % 2 == 0 else xe)
+    # one solve with the benchmark's smoother: its even-odd hop launches (every form, in the
+    # smoother's own link storage) are the ones the timed region measures
+    mg.set_smoother(eo=True, sstep=True)
+    q.mg_solve(mg, torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda(), tol=args.tol)
     torch.cuda.synchronize()
     mg.close()
     print(json.dumps({"probe": w["name"], "dims": list(dims), "prec": prec}), flush=True)
@@ -507,7 +503,8 @@ def traffic_from(args):
         _, wv = pick(write, prefix, merge)
         if not fv or not wv:
             continue
-        # the two hop forms of the Schur operator alternate: their mean is the family's launch
+        # the hop forms of the smoother (Schur operator, source, reconstruction) mix in the family:
+        # their mean over the solve's dispatches is the family's launch
         avg = np.mean if fam == "evenodd/hop" else np.median
         fb = float(avg(fv)) * 1024.0 * f_scale
         wb = float(avg(wv)) * 1024.0 * w_scale
