@@ -22,6 +22,7 @@ Modules
   icsvd      chiral split, Algorithm 3 (iCSVD) with LAPACK SVD, Algorithm 2, Algorithm 1
   transfer   prolongator P (Eq. 6), R = P^dagger
   coarse     Galerkin coarse operator (Eq. 5) as a 9-block stencil, coarse apply
+  coarse_evenodd  even-odd (Schur-complement) form of the coarse stencil on the aggregate colouring
   mg         test-vector smoothing (Eq. 2), setup (Algorithm 4), K-cycle, MG solve
   force      gradient of Re<eta, D^-1 b> w.r.t. b and the gauge links
   level      the next coarser level of a coarse stencil (a third level): coarse test
