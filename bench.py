@@ -8,7 +8,10 @@ vectors, GMRES smoothing, chiral split, streaming SVD over all streams, P and R,
 coarse operator, the half-lattice fields of the even-odd smoother) followed by the
 MG-preconditioned solve of one Gaussian right-hand side, whose fine-level post-smoother works on
 the even-odd Schur system with its GMRES(8) steps in s-step form (`--plain-smoother`: GMRES on D;
-the line reports the other smoother's solve on the same hierarchy beside it).
+the line reports the other smoother's solve on the same hierarchy beside it), and whose coarse
+solve runs GMRES(32) on the even-odd Schur complement of D_c where every coarse extent is even
+and the hierarchy has two levels (`--full-coarse`: on D_c; the other coarse solve on the same
+hierarchy is reported beside it).
 
 Prints one JSON line.  `value` is the median mixed-precision solve time (s) over the timed
 steps; `roofline` describes the dominant kernel measured live with HIP events over the timed
@@ -20,8 +23,9 @@ solve) on the same 16^3 x 32 anisotropic lattice with unit clover coefficients a
 tuned for that operator; `evenodd` is the even-odd Schur operator's bandwidth on 32^3 x 64 and
 its GMRES solve against GMRES on the full operator.  `--workload aniso16x32_clover` makes the clover workload the main line.
 
-Counter runs: `bench.py --traffic-probe` runs a 256 MiB device copy (calibration) and then ten
-launches each of the solve's dslash and coarse apply in the solve's launch configuration; run it
+Counter runs: `bench.py --traffic-probe` runs a 256 MiB device copy (calibration), ten launches
+each of the solve's dslash and coarse apply in the solve's launch configuration, and one solve
+with the benchmark's smoother and coarse solve (the even-odd hop and coarse kernels); run it
 under `rocprofv3 --pmc FETCH_SIZE` and, separately, `--pmc WRITE_SIZE`, then
 `bench.py --traffic-from FETCH_DIR WRITE_DIR` writes profiles/traffic.json (bytes per launch,
 scaled by the copy calibration, with the SHA-256 of the kernel source) and a text summary.
@@ -54,9 +58,10 @@ FAMILY_KERNEL = {
     "prolong": ("k_prolong", "transfer.hip"),
     "coarse_build": ("k_build_coarse", "transfer.hip"),
     "evenodd/hop": ("k_hop_eo", "dslash.hip"),
+    "coarse_eo": ("k_coarse_eo_apply", "coarse_evenodd.hip"),
 }
 FAMILIES = ("dslash/site", "dslash/twalk", "dslash/dir", "isvd", "coarse_apply", "prolong", "restrict",
-            "coarse_build", "evenodd/hop")
+            "coarse_build", "evenodd/hop", "coarse_eo")
 CLOVER_FAMILIES = tuple(f.replace("dslash/", "clover/") for f in FAMILIES)
 CLOVER_WORKLOAD = "aniso16x32_clover"
 
@@ -80,6 +85,8 @@ def parse():
                     help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover operator and clover MG leg")
     ap.add_argument("--no-evenodd", action="store_true", help="skip the even-odd preconditioning leg")
+    ap.add_argument("--full-coarse", action="store_true",
+                    help="coarse solve of the K-cycle on D_c (default: on its even-odd Schur complement)")
     ap.add_argument("--plain-smoother", action="store_true",
                     help="GMRES post-smoothing on D instead of the even-odd smoother in the main solve")
     ap.add_argument("--no-dslash-hbm", action="store_true",
@@ -135,6 +142,10 @@ def traffic_probe(args):
     # one solve with the benchmark's smoother: its even-odd hop launches (every form, in the
     # smoother's own link storage) are the ones the timed region measures
     mg.set_smoother(eo=True, sstep=True)
+    try:
+        mg.set_coarse_eo(True)
+    except q.QmgError:
+        pass
     q.mg_solve(mg, torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda(), tol=args.tol)
     torch.cuda.synchronize()
     mg.close()
@@ -496,16 +507,16 @@ def traffic_from(args):
              f"{w_copy / 1024:.0f} KiB for a {COPY_BYTES >> 20} MiB copy -> scale fetch x{f_scale:.3f}, "
              f"write x{w_scale:.3f}"]
     entry = rec.setdefault(w["name"], {})
-    for fam in ("dslash/dir", "dslash/site", "dslash/twalk", "coarse_apply", "evenodd/hop"):
+    for fam in ("dslash/dir", "dslash/site", "dslash/twalk", "coarse_apply", "evenodd/hop", "coarse_eo"):
         prefix, src = FAMILY_KERNEL[fam]
-        merge = fam == "evenodd/hop"
+        merge = fam in ("evenodd/hop", "coarse_eo")
         name, fv = pick(fetch, prefix, merge)
         _, wv = pick(write, prefix, merge)
         if not fv or not wv:
             continue
         # the hop forms of the smoother (Schur operator, source, reconstruction) mix in the family:
         # their mean over the solve's dispatches is the family's launch
-        avg = np.mean if fam == "evenodd/hop" else np.median
+        avg = np.mean if merge else np.median
         fb = float(avg(fv)) * 1024.0 * f_scale
         wb = float(avg(wv)) * 1024.0 * w_scale
         entry[fam] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
@@ -617,10 +628,22 @@ def main():
 
     eo_smoother = not args.plain_smoother
 
+    def coarse_eo(mg):
+        """The Schur-complement coarse solve unless --full-coarse, or where it does not apply (an
+        odd coarse extent, further levels): returns whether it is on."""
+        if args.full_coarse:
+            return False
+        try:
+            mg.set_coarse_eo(True)
+            return True
+        except q.QmgError:
+            return False
+
     def step():
         t0 = time.perf_counter()
         mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
         mg.set_smoother(eo=eo_smoother, sstep=True)  # builds the half-lattice fields: part of the setup
+        coarse_eo(mg)
         t1 = time.perf_counter()
         x, info = q.mg_solve(mg, b, tol=args.tol)
         t2 = time.perf_counter()
@@ -652,6 +675,7 @@ def main():
     # operation counts of one mixed solve (for the CPU baseline), from an untimed solve
     mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
     mg.set_smoother(eo=eo_smoother, sstep=True)
+    ceo_on = coarse_eo(mg)
     q.timing_enable(True)
     _, sinfo = q.mg_solve(mg, b, tol=args.tol)
     cnt = {f: q.timing_query(op_name if f == "dslash" else f)["launches"] for f in ("dslash", "coarse_apply",
@@ -670,6 +694,24 @@ def main():
     other_solve = {"smoother": "plain" if eo_smoother else "even-odd", "s": float(np.median(ts_other)),
                    "outer_iters": other[0]["outer_iters"], "coarse_iters": other[0]["coarse_iters"],
                    "true_rel_res": other[0]["true_rel_res"]}
+    # the other coarse solve (Schur complement or full D_c) with the benchmark's smoother
+    other_coarse = None
+    mg.set_smoother(eo=eo_smoother, sstep=True)
+    if ceo_on or args.full_coarse:
+        try:
+            mg.set_coarse_eo(not ceo_on)
+        except q.QmgError:
+            pass
+        else:
+            q.mg_solve(mg, b, tol=args.tol)
+            ts_oc, oc = [], None
+            for _ in range(2):
+                t0 = time.perf_counter()
+                _, oc = q.mg_solve(mg, b, tol=args.tol)
+                ts_oc.append(time.perf_counter() - t0)
+            other_coarse = {"coarse_solve": "full D_c" if ceo_on else "even-odd Schur complement",
+                            "s": float(np.median(ts_oc)), "outer_iters": oc[0]["outer_iters"],
+                            "coarse_iters": oc[0]["coarse_iters"], "true_rel_res": oc[0]["true_rel_res"]}
     mg.close()
     cnt["vector_ops"] = 12 * (sinfo[0]["smoother_iters"] + sinfo[0]["outer_iters"])
 
@@ -679,6 +721,7 @@ def main():
         kw64 = dict(setup_kw, inner="f64")
         mg64 = q.mg_setup_stream_chiral_svd(lat, U, **kw64)
         mg64.set_smoother(eo=eo_smoother, sstep=True)
+        coarse_eo(mg64)
         ts64 = []
         for _ in range(2):
             t0 = time.perf_counter()
@@ -722,10 +765,13 @@ def main():
                    "mass": w["mass"], "bc_t": w["bc_t"], "block": list(w["block"]), "n_test": w["n_test"],
                    "batch": w["batch"], "rank": w["rank"], "nrhs": 1, "tol": args.tol,
                    "smoother": "even-odd GMRES(8), s-step form" if eo_smoother else "GMRES(8)",
+                   "coarse_solve": "GMRES(32) on the even-odd Schur complement of D_c" if ceo_on
+                   else "GMRES(32) on D_c",
                    **({"c_sw": list(w["c_sw"])} if w.get("c_sw") else {})},
         "setup_s": float(np.median(setups)),
         "solve_fp64": fp64_solve,
         "solve_other_smoother": other_solve,
+        "solve_other_coarse": other_coarse,
         "solve_info": infos[-1],
         "timing_sample": TIMING_SAMPLE,
         "dslash": {"timed_launches": ds["launches"], "avg_launch_us": ds_avg_ms * 1e3, "GBps": ds_gbps,

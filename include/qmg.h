@@ -10,7 +10,8 @@
  * Beyond the two-level path: up to four levels (qmg_mg_add_level), the clover term of the
  * action used in Section 4 (qmg_clover_*; mg params c_sw_s / c_sw_t), even-odd (Schur
  * complement) preconditioning of the fine operator named in Section 1 (qmg_eo_*,
- * qmg_schur_apply, qmg_eo_solve, the even-odd post-smoother of qmg_mg_set_smoother),
+ * qmg_schur_apply, qmg_eo_solve, the even-odd post-smoother of qmg_mg_set_smoother) and of
+ * the coarse operator (qmg_mg_set_coarse_eo, qmg_coarse_schur_apply, qmg_coarse_eo_solve),
  * hierarchy checkpoints and resumable streams (qmg_mg_save / _load / _stream_more).
  *
  * Conventions shared by every entry point
@@ -380,6 +381,38 @@ qmg_status qmg_mg_set_cycle(qmg_mg* mg, int32_t coarse_steps, int32_t graph);
  * Errors: EINVAL (null, eo not 0/1/2), ESHAPE (an odd extent), EBREAKDOWN (a singular site
  *   block), ENOMEM, EHIP. */
 qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream);
+
+/* Even-odd coarse solve (Section 1 names even-odd preconditioning; here it is applied to the
+ * Galerkin operator D_c of Eq. (5)).  The aggregates are coloured by the parity of their coarse
+ * coordinates (every coarse extent must be even, so every hop block of D_c joins aggregates of
+ * opposite colour) and the coarse solve of the K-cycle runs GMRES on the Schur complement
+ *   Dhat_c = Y_ee - Y_eo Y_oo^-1 Y_oe,   rhat_e = r_e - Y_eo Y_oo^-1 r_o,
+ *   v_o = Y_oo^-1 (r_o - Y_oe v_e),
+ * to the coarse tolerance relative to rhat_e.  on = 1 builds (once; again after the coarse
+ * operator is rebuilt) Y_0(j)^-1 Y(j) for every aggregate in FP64 (self blocks inverted by
+ * Gauss-Jordan with partial pivoting) and its inner-precision copy; on = 0 returns to the
+ * full coarse operator.  Synchronizes the stream.  Applies to the host-checked coarse solve of
+ * a two-level hierarchy (qmg_mg_set_cycle with coarse_steps = 0; a further level added later
+ * takes precedence).  Not stored by qmg_mg_save.
+ * Errors: EINVAL (null, on not 0/1, further levels exist), ESHAPE (an odd coarse extent),
+ *   EBREAKDOWN (a singular self block), ENOMEM, EHIP. */
+qmg_status qmg_mg_set_coarse_eo(qmg_mg* mg, int32_t on, hipStream_t stream);
+
+/* out_e = Dhat_c in_e (above) on half coarse vectors [nrhs][d/2][2k] (device, canonical coarse
+ * order within the half: the even-coloured aggregates in increasing index order), prec F64 or
+ * the F32 inner precision.  Needs qmg_mg_set_coarse_eo(mg, 1).  Synchronizes the stream.
+ * Errors: EINVAL (null, aliasing, nrhs < 1, even-odd coarse operator not set up), EDTYPE, ENOMEM,
+ *   EHIP. */
+qmg_status qmg_coarse_schur_apply(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
+                                  hipStream_t stream);
+
+/* D_c x = b (full coarse vectors [nrhs][d][2k], device, FP64) through the Schur complement
+ * above: GMRES(32) from zero on Dhat_c to tol relative to rhat_e within max_iter steps, then the
+ * odd part; *iters = GMRES steps.  Needs qmg_mg_set_coarse_eo(mg, 1).  Synchronizes the stream.
+ * Errors: EINVAL (null, aliasing, bad counts or tol, not set up), ENOCONV (x holds the last
+ *   iterate), ENOMEM, EHIP. */
+qmg_status qmg_coarse_eo_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, double tol,
+                               int32_t max_iter, int32_t* iters, hipStream_t stream);
 
 /* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times the first 64
  * later launches of each instrumented kernel family and then about one in n (picked by a hash

@@ -72,6 +72,9 @@ SIGNATURES = {
     "qmg_schur_apply": [_P, _P, _P, _P, _P, _P, _I, _I, _I, _P],
     "qmg_eo_solve": [_P, _P, _D, _D, _P, _P, _I, _D, _I, _I, _P, _P],
     "qmg_mg_set_smoother": [_P, _I, _P],
+    "qmg_mg_set_coarse_eo": [_P, _I, _P],
+    "qmg_coarse_schur_apply": [_P, _P, _P, _I, _I, _P],
+    "qmg_coarse_eo_solve": [_P, _P, _P, _I, _D, _I, _P, _P],
     "qmg_pack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_unpack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_pack_gauge": [_P, _P, _P, _I, _P],
@@ -448,6 +451,11 @@ class MG:
         even-odd GMRES steps run in s-step form (see qmg.h)."""
         _check(load_library().qmg_mg_set_smoother(self._h, (2 if sstep else 1) if eo else 0, _stream()))
 
+    def set_coarse_eo(self, on=True):
+        """Coarse solve of the K-cycle on the even-odd Schur complement of D_c (on) or on D_c
+        (see qmg.h, qmg_mg_set_coarse_eo)."""
+        _check(load_library().qmg_mg_set_coarse_eo(self._h, 1 if on else 0, _stream()))
+
     def stream_more(self, n_streams):
         """Resume the streaming SVD with n_streams more batches of test vectors (the counter RNG's
         next global indices), then rebuild P, R and D_c."""
@@ -623,6 +631,24 @@ def coarse_apply(mg: MG, v, out=None):
     out = torch.empty_like(v) if out is None else out
     _check(load_library().qmg_coarse_apply(mg.handle, _ptr(v), _ptr(out), v.shape[0], p, _stream()))
     return out
+
+
+def coarse_schur_apply(mg: MG, v_e, out=None):
+    """out_e = Dhat_c v_e on half coarse vectors [nrhs,d/2,2,k] of the even aggregates."""
+    p = _prec_of(v_e)
+    out = torch.empty_like(v_e) if out is None else out
+    _check(load_library().qmg_coarse_schur_apply(mg.handle, _ptr(v_e), _ptr(out), v_e.shape[0], p, _stream()))
+    return out
+
+
+def coarse_eo_solve(mg: MG, b, tol=1e-12, max_iter=5000):
+    """x = D_c^-1 b (FP64, [nrhs,d,2,k]) by GMRES(32) on the even-odd Schur complement; returns
+    (x, GMRES steps)."""
+    x = torch.empty_like(b)
+    it = ctypes.c_int32(0)
+    _check(load_library().qmg_coarse_eo_solve(mg.handle, _ptr(b), _ptr(x), b.shape[0], float(tol), int(max_iter),
+                                              ctypes.byref(it), _stream()))
+    return x, it.value
 
 
 def mg_solve(mg: MG, b, x0=None, tol=1e-10, max_outer=1000, adjoint=False, check=True):

@@ -128,6 +128,44 @@ struct CoarseOp : LinOp {
   qmg_prec prec() const override { return p; }
 };
 
+// even-odd Schur complement of D_c on half coarse vectors [nrhs][d/2][2k] of the even colour:
+// Y_ee v - Y_eo (Y_oo^-1 Y_oe v), the bracket with the Yhat blocks of the odd aggregates
+struct CoarseSchurOp : LinOp {
+  const HierarchyDev& h;
+  qmg_prec p;
+  const void* Y;
+  const void* Yh;
+  DevBuf tmp;
+  CoarseSchurOp(const HierarchyDev& h_, qmg_prec p_, const void* Y_, const void* Yh_) : h(h_), p(p_), Y(Y_), Yh(Yh_) {}
+  void apply(const void* in, void* out, int nrhs, hipStream_t st, const int* = nullptr) override {
+    tmp.ensure(size_t(nrhs) * len() * prec_bytes(p));
+    launch_coarse_eo_apply(p, h, 1, Yh, nullptr, nullptr, in, tmp.p, nrhs, 1.0, st);
+    launch_coarse_eo_apply(p, h, 0, Y, nullptr, in, tmp.p, out, nrhs, -1.0, st);
+  }
+  size_t len() const override { return size_t(h.k) * h.blk.d; }
+  qmg_prec prec() const override { return p; }
+};
+
+// D_c v = r through the Schur complement: rhat_e = r_e - Y_eo Y_oo^-1 r_o, GMRES(32) on
+// Dhat_c v_e = rhat_e to tol (relative to rhat_e) within max_iter steps, v_o = Y_oo^-1 (r_o -
+// Y_oe v_e).  r, v: full coarse vectors; work: six half vectors.  Returns the GMRES result.
+template <class S>
+typename Gmres<S>::Result coarse_eo_solve(const HierarchyDev& h, CoarseSchurOp& A, Gmres<S>& gm, const void* r,
+                                          void* v, int nrhs, int max_iter, double tol, DevBuf* work, hipStream_t st,
+                                          int hint = 0) {
+  constexpr qmg_prec p = StoreTraits<S>::prec;
+  const size_t nh = size_t(nrhs) * A.len();
+  for (int i = 0; i < 6; ++i) work[i].ensure(nh * sizeof(S));
+  void *re = work[0].p, *ro = work[1].p, *w = work[2].p, *rh = work[3].p, *ve = work[4].p, *vo = work[5].p;
+  launch_coarse_eo_split(p, h, r, re, ro, nrhs, st);
+  launch_coarse_eo_apply(p, h, 1, A.Yh, nullptr, ro, nullptr, w, nrhs, 1.0, st);  // Y_oo^-1 r_o
+  launch_coarse_eo_apply(p, h, 0, A.Y, re, nullptr, w, rh, nrhs, -1.0, st);       // rhat_e
+  auto res = gm.solve(A, rh, ve, true, nrhs, 32, max_iter, tol, st, nullptr, hint);
+  launch_coarse_eo_apply(p, h, 1, A.Yh, nullptr, ro, ve, vo, nrhs, -1.0, st);     // v_o
+  launch_coarse_eo_merge(p, h, ve, vo, v, nrhs, st);
+  return res;
+}
+
 // the nine-block stencil of a further level
 struct StencilOp : LinOp {
   int d, k;
@@ -197,6 +235,9 @@ struct KCycle : Precond {
   DevBuf rc, ec, rS, zS, conv;
   std::unique_ptr<KCycleC<S>> Kc;  // level-one K-cycle when a third level exists
   std::unique_ptr<SchurOp> schur;  // even-odd post-smoother: the Schur complement and its buffers
+  std::unique_ptr<CoarseSchurOp> cschur;  // even-odd coarse solve: the coarse Schur complement
+  Gmres<S> gce;
+  DevBuf ceo_work[6];
   DevBuf eo_t, eo_e, eo_o, eo_u, eo_b, eo_xe, eo_xo, eo_basis, eo_c, eo_part;
   long coarse_iters = 0, smooth_iters = 0, cycles = 0;
   int last_coarse = 0;             // coarse steps of the previous cycle (host-checked form)
@@ -224,6 +265,13 @@ struct KCycle : Precond {
       last_coarse = rcs.iters;
     } else if (h.cycle_steps > 0) {
       gc.solve(Dc, rc.p, ec.p, true, nrhs, h.cycle_steps, h.cycle_steps, h.coarse_tol, st, conv.as<int>());
+    } else if (h.coarse_eo) {
+      // the coarse solve on the even-odd Schur complement of D_c
+      if (!cschur) cschur.reset(new CoarseSchurOp(h, p, Dc.Y, p == QMG_F64 ? h.Yh64.p : h.Yhin.p));
+      const int hint = last_coarse > 1 ? last_coarse - 1 : 0;
+      auto rcs = coarse_eo_solve<S>(h, *cschur, gce, rc.p, ec.p, nrhs, h.coarse_max, h.coarse_tol, ceo_work, st, hint);
+      coarse_iters += rcs.iters;
+      last_coarse = rcs.iters;
     } else {
       // first read of the convergence estimates one step before the previous cycle's count
       const int hint = last_coarse > 1 ? last_coarse - 1 : 0;
@@ -525,6 +573,7 @@ void finish_setup(qmg_mg* mg, hipStream_t st) {
     launch_convert(h.P64.p, QMG_F64, h.Pin.p, h.inner, np, st);
     launch_convert(h.Y64.p, QMG_F64, h.Yin.p, h.inner, ny, st);
   }
+  if (h.coarse_eo) build_coarse_eo_blocks(h, st);
   h.sigma.resize(size_t(2) * h.blk.d * h.k);
   QMG_HIP(hipMemcpyAsync(h.sigma.data(), mg->sigma_dev.p, h.sigma.size() * sizeof(double), hipMemcpyDeviceToHost,
                          st));
@@ -1832,6 +1881,64 @@ qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream) {
     }
     QMG_HIP(hipStreamSynchronize(stream));
     h.eo_smoother = eo;
+  });
+}
+
+qmg_status qmg_mg_set_coarse_eo(qmg_mg* mg, int32_t on, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    QMG_CHECK(on == 0 || on == 1, QMG_EINVAL, "on must be 0 or 1");
+    HierarchyDev& h = mg->h;
+    if (!on) {
+      h.coarse_eo = 0;
+      return;
+    }
+    QMG_CHECK(h.levels.empty(), QMG_EINVAL, "the even-odd coarse solve needs a two-level hierarchy");
+    if (!h.ceo_tab.p) build_coarse_eo_tables(h, stream);
+    if (!h.Yh64.p) build_coarse_eo_blocks(h, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+    h.coarse_eo = 1;
+  });
+}
+
+qmg_status qmg_coarse_schur_apply(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
+                                  hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(in != out, QMG_EINVAL, "in and out must not alias");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    const HierarchyDev& h = mg->h;
+    QMG_CHECK(h.coarse_eo, QMG_EINVAL, "coarse_schur_apply: the even-odd coarse operator is not set up");
+    QMG_CHECK(prec == QMG_F64 || (prec == h.inner && prec == QMG_F32), QMG_EDTYPE,
+              "coarse_schur_apply: precision must be F64 or the F32 inner precision");
+    const bool d64 = prec == QMG_F64;
+    CoarseSchurOp A(h, prec, d64 ? h.Y64.p : h.Yin.p, d64 ? h.Yh64.p : h.Yhin.p);
+    A.apply(in, out, nrhs, stream);
+    QMG_HIP(hipStreamSynchronize(stream));  // A's work buffer is released on return
+  });
+}
+
+qmg_status qmg_coarse_eo_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, double tol, int32_t max_iter,
+                               int32_t* iters, hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(b, "b");
+    check_ptr(x, "x");
+    check_ptr(iters, "iters");
+    QMG_CHECK(b != x, QMG_EINVAL, "b and x must not alias");
+    QMG_CHECK(nrhs >= 1 && max_iter >= 1, QMG_EINVAL, "need nrhs >= 1, max_iter >= 1");
+    QMG_CHECK(tol > 0 && tol < 1, QMG_EINVAL, "tol must be in (0, 1)");
+    const HierarchyDev& h = mg->h;
+    QMG_CHECK(h.coarse_eo, QMG_EINVAL, "coarse_eo_solve: the even-odd coarse operator is not set up");
+    CoarseSchurOp A(h, QMG_F64, h.Y64.p, h.Yh64.p);
+    Gmres<double2> gm;
+    DevBuf work[6];
+    auto res = coarse_eo_solve<double2>(h, A, gm, b, x, nrhs, max_iter, tol, work, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+    *iters = res.iters;
+    QMG_CHECK(res.converged, QMG_ENOCONV, "coarse_eo_solve: no convergence in %d steps", max_iter);
   });
 }
 

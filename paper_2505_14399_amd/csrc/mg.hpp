@@ -50,6 +50,11 @@ struct HierarchyDev {
   DevBuf blists;             // [8][nd]: in-block sites per hop direction, intra-block hops first
   DevBuf P64, Pin;           // [d][2][k][N]
   DevBuf Y64, Yin;           // [d][9][2k][2k] column-major blocks
+  // even-odd coarse solve (qmg_mg_set_coarse_eo): the colouring tables and Yhat = Y_0^-1 Y
+  // (slot 0: Y_0^-1) in FP64 and, below FP64, in the inner precision
+  int coarse_eo = 0;
+  DevBuf ceo_tab;            // [d] colour, [d] index in colour, [2][d/2] aggregates, [d][8] neighbour index
+  DevBuf Yh64, Yhin;
   std::vector<double> sigma; // [d][2][k]
   double t_smooth = 0, t_svd = 0, t_coarse = 0, t_total = 0;
   int n_post = 8, coarse_max = 500;
@@ -112,6 +117,19 @@ void build_level_coarse(CoarseLevel& L, const StencilRef& above, hipStream_t st)
 // canonical exports of the third level: P [d][2][N][k] with rows (jb * k1 + i), Y [d][9][2k][2k]
 void launch_level_export_P(const CoarseLevel& L, void* out, hipStream_t st);
 void launch_level_export_Y(const CoarseLevel& L, void* out, hipStream_t st);
+// even-odd coarse operator: colouring tables (ESHAPE if a coarse extent is odd) and Yhat from Y64
+// (EBREAKDOWN if a self block is singular)
+void build_coarse_eo_tables(HierarchyDev& h, hipStream_t st);
+void build_coarse_eo_blocks(HierarchyDev& h, hipStream_t st);
+// one colour of half vectors [nrhs][d/2][2k]: out = [y] + [B_0 a] + sgn sum_s B_s b(nbh), B = Y or
+// Yhat; a null a or b drops the self or the hop slots
+void launch_coarse_eo_apply(qmg_prec prec, const HierarchyDev& h, int colour, const void* B, const void* y,
+                            const void* a, const void* b, void* out, int nrhs, double sgn, hipStream_t st);
+// full coarse vectors [nrhs][d][2k] <-> colours [nrhs][d/2][2k]
+void launch_coarse_eo_split(qmg_prec prec, const HierarchyDev& h, const void* full, void* ev, void* od, int nrhs,
+                            hipStream_t st);
+void launch_coarse_eo_merge(qmg_prec prec, const HierarchyDev& h, const void* ev, const void* od, void* full, int nrhs,
+                            hipStream_t st);
 // Galerkin build in FP64 from U64 and P64 into Y64 (needs a workspace of 8 * d * (2k)^2 double2)
 void build_coarse(HierarchyDev& h, hipStream_t st);
 // chiral split + block gather: fine FP64 native [r][12][V] -> blocks [2d][r][N] FP64

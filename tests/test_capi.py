@@ -184,3 +184,15 @@ def test_even_odd_arguments_are_rejected_without_device_work():
                           ctypes.byref(info), None) == -2
     assert L.qmg_eo_solve(ctypes.byref(lat), dummy, D(0.0), D(0.0), P(32), P(48), 1, D(0.0), 100, 1,
                           ctypes.byref(info), None) == -1
+
+
+def test_coarse_even_odd_arguments_are_rejected_without_device_work():
+    import paper_2505_14399_amd as q
+    L = q.load_library()
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    it = ctypes.c_int32(0)
+    assert L.qmg_mg_set_coarse_eo(None, 1, None) == -1
+    assert L.qmg_coarse_schur_apply(None, P(32), P(48), 1, q.F64, None) == -1
+    assert L.qmg_coarse_eo_solve(None, P(32), P(48), 1, D(1e-10), 100, ctypes.byref(it), None) == -1
+    assert b"mg" in L.qmg_last_error()
