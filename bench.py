@@ -230,6 +230,8 @@ def clover_mg(args):
     kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
               n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"], c_sw=w["c_sw"])
     eo = not args.plain_smoother
+    # the coarse solve stays on the full D_c here: on this workload the Schur-complement coarse
+    # solve took 23 outer iterations (0.027 s) against 9 (0.013 s)
     mg = q.mg_setup_stream_chiral_svd(lat, U, **kw)
     mg.set_smoother(eo=eo, sstep=True)
     q.mg_solve(mg, b, tol=args.tol)
@@ -250,8 +252,9 @@ def clover_mg(args):
     if info["true_rel_res"] > args.tol:
         raise SystemExit(f"clover solve did not reach {args.tol}: {info}")
     return {"workload": w["name"], "c_sw": list(w["c_sw"]), "mass": w["mass"],
-            "smoother": "even-odd GMRES(8), s-step form" if eo else "GMRES(8)", "setup_s": float(np.median(setups)),
-            "solve_s": float(np.median(solves)), "outer_iters": info["outer_iters"],
+            "smoother": "even-odd GMRES(8), s-step form" if eo else "GMRES(8)",
+            "coarse_solve": "full D_c",
+            "setup_s": float(np.median(setups)), "solve_s": float(np.median(solves)), "outer_iters": info["outer_iters"],
             "coarse_iters": info["coarse_iters"], "true_rel_res": info["true_rel_res"]}
 
 

@@ -141,3 +141,32 @@ def test_coarse_eo_errors(qmg):
     with pytest.raises(qmg.QmgError, match="two-level"):
         mg.set_coarse_eo(True)
     mg.close()
+
+
+def test_clover_mg_solve_with_coarse_eo(qmg):
+    """The coarse Schur complement of the Wilson-clover D_c (the site term sits in every Y_0)."""
+    from oracle import clover
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    U = fields.random_gauge(dims, 0.4, 90)
+    m, cs, ct = 0.02, 1.0, 1.0
+    lat = qmg.Lattice(dims, m, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 24, 8, 12, n_setup_iter=16, inner="f32", seed=5,
+                                        c_sw=(cs, ct))
+    T = clover.clover_term(U, dims, cs, ct)
+    P = to_np(mg.prolongator()[0])
+    Yo = coarse.build_coarse(U, P, m, 1.0, -1, dims, block, T=T)
+    mg.set_coarse_eo(True)
+    banner("clover coarse eo")
+    d, k = Yo.shape[0], Yo.shape[2] // 2
+    cd = geo.coarse_dims(dims, block)
+    b = fields.gaussian_coarse(d * 2 * k, 1, 91).reshape(1, d, 2, k)
+    x, _ = qmg.coarse_eo_solve(mg, to_gpu(b), tol=1e-12)
+    ref = np.linalg.solve(coarse.dense_coarse(Yo, cd), b.reshape(1, -1).T).T.reshape(b.shape)
+    assert rel(to_np(x), ref) < 1e-9
+    mg.set_smoother(eo=True, sstep=True)
+    bf = fields.gaussian_spinor(dims, 1, 92)
+    xf, info = qmg.mg_solve(mg, to_gpu(bf), tol=1e-10)
+    print(f"[coarse-eo] clover: outer {info[0]['outer_iters']} coarse {info[0]['coarse_iters']}")
+    r = bf - clover.apply_clover(U, T, to_np(xf), m, 1.0, -1, dims)
+    assert np.linalg.norm(r) / np.linalg.norm(bf) < 2e-10
+    mg.close()
