@@ -172,19 +172,33 @@ __global__ __launch_bounds__(1024) void k_coarse_eo_apply(const S* __restrict__ 
       for (int u = 0; u < PR; ++u) part[(size_t(r) * ns * H + hq) * m + rp * PR + u] = acc[r][u];
   }
   __syncthreads();
+  // each output row is summed by kG consecutive lanes (partials hq = g, g + kG, ...), then a
+  // fixed butterfly over the kG lanes: the same order on every call.  The loop bound is a
+  // multiple of kG and blockDim.x of 64, so a group's lanes are all active together.
+  constexpr int kG = 16;
   const C sg = C(sgn);
-  for (int t = threadIdx.x; t < nr * m; t += blockDim.x) {
-    const int r = t / m, row = t - r * m;
-    const size_t o = (size_t(rhs0 + r) * dh + h) * m + row;
-    cplx<C> s = y ? ldc(y, o) : cplx<C>{C(0), C(0)};
-    for (int hq = 0; hq < ns * H; ++hq) {
-      const cplx<C> v = part[(size_t(r) * ns * H + hq) * m + row];
+  const int nq = ns * H;
+  for (int t = threadIdx.x; t < nr * m * kG; t += blockDim.x) {
+    const int g = t % kG, rr = t / kG;
+    const int r = rr / m, row = rr - r * m;
+    cplx<C> s = {C(0), C(0)};
+    for (int hq = g; hq < nq; hq += kG) {
+      const cplx<C> v = part[(size_t(r) * nq + hq) * m + row];
       if (lo + hq % ns == 0)
         s += v;
       else
         s += sg * v;
     }
-    stc(out, o, s);
+#pragma unroll
+    for (int off = kG / 2; off > 0; off >>= 1) {
+      s.re += __shfl_xor(s.re, off);
+      s.im += __shfl_xor(s.im, off);
+    }
+    if (g == 0) {
+      const size_t o = (size_t(rhs0 + r) * dh + h) * m + row;
+      if (y) s += ldc(y, o);
+      stc(out, o, s);
+    }
   }
 }
 
