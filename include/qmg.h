@@ -393,7 +393,9 @@ qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream);
  * Gauss-Jordan with partial pivoting) and its inner-precision copy; on = 0 returns to the
  * full coarse operator.  Synchronizes the stream.  Applies to the host-checked coarse solve of
  * a two-level hierarchy (qmg_mg_set_cycle with coarse_steps = 0; a further level added later
- * takes precedence).  Not stored by qmg_mg_save.
+ * takes precedence).  Not stored by qmg_mg_save.  With an FP64 K-cycle it reduced the outer
+ * iterations on every operator tried; with a lower-precision K-cycle the outer count can move
+ * either way with the operator (rounding-sensitive), so it is off by default.
  * Errors: EINVAL (null, on not 0/1, further levels exist), ESHAPE (an odd coarse extent),
  *   EBREAKDOWN (a singular self block), ENOMEM, EHIP. */
 qmg_status qmg_mg_set_coarse_eo(qmg_mg* mg, int32_t on, hipStream_t stream);
