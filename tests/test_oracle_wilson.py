@@ -101,3 +101,45 @@ def test_links_are_su3():
     I = np.einsum("mxab,mxcb->mxac", U, np.conj(U))
     assert np.abs(I - np.eye(3)).max() < 1e-13
     assert np.abs(np.linalg.det(U) - 1).max() < 1e-13
+
+
+@pytest.mark.parametrize("dims,xi,bc_t", [((3, 2, 3, 5), 1.0, -1), ((2, 3, 1, 4), 3.5, -1), ((3, 3, 2, 3), 2.0, 1)])
+def test_sampled_sites_equal_dense_rows(dims, xi, bc_t):
+    """apply_wilson_sites (the per-site hop loop that checks full-size GPU runs at sampled sites)
+    against the rows of the dense matrix built entry by entry, for D and D^dagger, on odd
+    extents, every site of the first and last time slice (the boundary wrap) and a random rest."""
+    V = geo.volume(dims)
+    U = fields.random_gauge(dims, 0.6, 17)
+    psi = fields.gaussian_spinor(dims, 1, 17)[0]
+    Dm = wilson.dense_wilson(U, -0.3, xi, bc_t, dims)
+    c = geo.coords(dims)
+    edge = np.nonzero((c[:, 3] == 0) | (c[:, 3] == dims[3] - 1))[0]
+    rng = np.random.default_rng(5)
+    sites = np.unique(np.concatenate([edge, rng.choice(V, size=min(V, 7), replace=False)]))
+    for dag in (False, True):
+        M = Dm.conj().T if dag else Dm
+        want = (M @ psi.ravel()).reshape(V, 4, 3)[sites]
+        got = wilson.apply_wilson_sites(U, psi, sites, -0.3, xi, bc_t, dims, dagger=dag)
+        assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
+
+
+def test_sampled_sites_plane_wave():
+    """At U = 1 a plane wave e^{ipx} u is mapped to D(p) e^{ipx} u (closed form), also at the
+    sites whose t-hops cross the antiperiodic boundary; D^dagger gives D(p)^dagger."""
+    dims = (4, 2, 2, 6)
+    xi, m = 2.5, 0.15
+    c = geo.coords(dims)
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    cw = wilson.hop_weights(xi)
+    sites = np.array([0, 5, 17, geo.volume(dims) - 1, int(geo.lex(np.array([1, 1, 0, 5]), dims))])
+    for n in [(1, 0, 1, 2), (3, 1, 0, 5)]:
+        p = [2 * np.pi * n[mu] / dims[mu] for mu in range(3)] + [(2 * np.pi * n[3] + np.pi) / dims[3]]
+        phase = np.exp(1j * (c @ np.array(p)))
+        psi = phase[:, None, None] * u[None]
+        Dp = (m + sum(cw[mu] * (1 - np.cos(p[mu])) for mu in range(4))) * np.eye(4) \
+            + 1j * sum(cw[mu] * np.sin(p[mu]) * GAMMA[mu] for mu in range(4))
+        for dag, M in ((False, Dp), (True, Dp.conj().T)):
+            want = phase[sites, None, None] * (M @ u)[None]
+            got = wilson.apply_wilson_sites(unit_links(dims), psi, sites, m, xi, -1, dims, dagger=dag)
+            assert np.abs(got - want).max() < 1e-13
