@@ -388,16 +388,19 @@ qmg_status qmg_mg_set_smoother(qmg_mg* mg, int32_t eo, hipStream_t stream);
  * opposite colour) and the coarse solve of the K-cycle runs GMRES on the Schur complement
  *   Dhat_c = Y_ee - Y_eo Y_oo^-1 Y_oe,   rhat_e = r_e - Y_eo Y_oo^-1 r_o,
  *   v_o = Y_oo^-1 (r_o - Y_oe v_e),
- * to the coarse tolerance relative to rhat_e.  on = 1 builds (once; again after the coarse
- * operator is rebuilt) Y_0(j)^-1 Y(j) for every aggregate in FP64 (self blocks inverted by
- * Gauss-Jordan with partial pivoting) and its inner-precision copy; on = 0 returns to the
- * full coarse operator.  Synchronizes the stream.  Applies to the host-checked coarse solve of
+ * to the coarse tolerance relative to rhat_e.  on = 1 builds Y_0(j)^-1 Y(j) for every
+ * aggregate from the current D_c in FP64 (self blocks inverted by Gauss-Jordan with partial
+ * pivoting) and its inner-precision copy, and rebuilds them whenever the coarse operator is
+ * rebuilt (qmg_mg_stream_more); on = 0 returns to the full coarse operator and releases them.
+ * When a build fails (here or inside qmg_mg_stream_more) the blocks are released and the
+ * Schur coarse solve is off.  Synchronizes the stream.  Applies to the host-checked coarse solve of
  * a two-level hierarchy (qmg_mg_set_cycle with coarse_steps = 0; a further level added later
  * takes precedence).  Not stored by qmg_mg_save.  With an FP64 K-cycle it reduced the outer
  * iterations on every operator tried; with a lower-precision K-cycle the outer count can move
  * either way with the operator (rounding-sensitive), so it is off by default.
  * Errors: EINVAL (null, on not 0/1, further levels exist), ESHAPE (an odd coarse extent),
- *   EBREAKDOWN (a singular self block), ENOMEM, EHIP. */
+ *   EBREAKDOWN (a self block whose pivot falls below 1e-13 of its largest entry, or entries
+ *   of Y_0^-1 Y beyond half the largest finite value of the inner storage type), ENOMEM, EHIP. */
 qmg_status qmg_mg_set_coarse_eo(qmg_mg* mg, int32_t on, hipStream_t stream);
 
 /* out_e = Dhat_c in_e (above) on half coarse vectors [nrhs][d/2][2k] (device, canonical coarse

@@ -573,7 +573,11 @@ void finish_setup(qmg_mg* mg, hipStream_t st) {
     launch_convert(h.P64.p, QMG_F64, h.Pin.p, h.inner, np, st);
     launch_convert(h.Y64.p, QMG_F64, h.Yin.p, h.inner, ny, st);
   }
-  if (h.coarse_eo) build_coarse_eo_blocks(h, st);
+  if (h.coarse_eo) {  // Yhat follows the rebuilt D_c; a failed build switches the Schur coarse solve off
+    h.coarse_eo = 0;
+    build_coarse_eo_blocks(h, st);
+    h.coarse_eo = 1;
+  }
   h.sigma.resize(size_t(2) * h.blk.d * h.k);
   QMG_HIP(hipMemcpyAsync(h.sigma.data(), mg->sigma_dev.p, h.sigma.size() * sizeof(double), hipMemcpyDeviceToHost,
                          st));
@@ -1889,13 +1893,15 @@ qmg_status qmg_mg_set_coarse_eo(qmg_mg* mg, int32_t on, hipStream_t stream) {
     check_ptr(mg, "mg");
     QMG_CHECK(on == 0 || on == 1, QMG_EINVAL, "on must be 0 or 1");
     HierarchyDev& h = mg->h;
-    if (!on) {
-      h.coarse_eo = 0;
+    h.coarse_eo = 0;
+    if (!on) {  // the blocks belong to the current D_c only: rebuilt when switched on again
+      h.Yh64.release();
+      h.Yhin.release();
       return;
     }
     QMG_CHECK(h.levels.empty(), QMG_EINVAL, "the even-odd coarse solve needs a two-level hierarchy");
     if (!h.ceo_tab.p) build_coarse_eo_tables(h, stream);
-    if (!h.Yh64.p) build_coarse_eo_blocks(h, stream);
+    build_coarse_eo_blocks(h, stream);  // always from the current D_c; releases them on failure
     QMG_HIP(hipStreamSynchronize(stream));
     h.coarse_eo = 1;
   });

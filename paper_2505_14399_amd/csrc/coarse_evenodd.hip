@@ -14,6 +14,7 @@
 // the hops).  Yhat folds the inverse self blocks into the odd hops: the Schur apply is two
 // launches (u_o = Yhat-hops of v_e; out_e = Y_0 v_e - Y-hops of u_o) that each stream half of
 // the blocks once.
+#include <cstring>
 #include <vector>
 
 #include "mg.hpp"
@@ -26,12 +27,17 @@ namespace {
 // Yhat(j) = Y_0(j)^-1 Y(j) with slot 0 = Y_0(j)^-1, FP64: one workgroup per aggregate,
 // Gauss-Jordan with partial pivoting on [Y_0 | 1] (row-major, m x 2m) in LDS; the left half
 // then stages each hop block for the product.  Column-major blocks in and out.
+// A pivot below 1e-13 of the largest entry of Y_0 (in modulus) marks the block as numerically
+// singular (flag[0] = 1); the largest modulus of a real or imaginary part written to Yhat is
+// returned in flag[1..2] (the bits of a non-negative double, which order like the double).
 __global__ __launch_bounds__(256) void k_coarse_eo_blocks(const double2* __restrict__ Y, double2* __restrict__ Yh,
                                                           int m, int* __restrict__ flag) {
   extern __shared__ unsigned char smem_raw[];
   cplx<double>* a = reinterpret_cast<cplx<double>*>(smem_raw);  // [m][2m]
   cplx<double>* f = a + size_t(m) * 2 * m;                       // [m] elimination factors
   __shared__ int piv, bad;
+  __shared__ double ymax2;
+  __shared__ unsigned long long omax;
   const int j = blockIdx.x, w = 2 * m, tid = threadIdx.x;
   const double2* Yj = Y + size_t(j) * 9 * m * m;
   for (int t = tid; t < m * w; t += 256) {
@@ -43,8 +49,19 @@ __global__ __launch_bounds__(256) void k_coarse_eo_blocks(const double2* __restr
       a[t] = {c - m == i ? 1.0 : 0.0, 0.0};
     }
   }
-  if (tid == 0) bad = 0;
+  if (tid == 0) {
+    bad = 0;
+    omax = 0ull;
+  }
   __syncthreads();
+  if (tid == 0) {
+    double v = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int c = 0; c < m; ++c) v = fmax(v, norm2(a[i * w + c]));
+    ymax2 = v;
+  }
+  __syncthreads();
+  const double tiny2 = 1e-26 * ymax2;  // (1e-13 max |Y_0|)^2
   for (int p = 0; p < m; ++p) {
     if (tid == 0) {
       int best = p;
@@ -57,7 +74,7 @@ __global__ __launch_bounds__(256) void k_coarse_eo_blocks(const double2* __restr
         }
       }
       piv = best;
-      if (!(bv > 1e-280) || !isfinite(bv)) bad = 1;
+      if (!(bv > tiny2) || !(bv > 1e-280) || !isfinite(bv)) bad = 1;
     }
     __syncthreads();
     if (bad) break;  // uniform: every thread reads the same shared value
@@ -88,10 +105,12 @@ __global__ __launch_bounds__(256) void k_coarse_eo_blocks(const double2* __restr
     return;
   }
   double2* out = Yh + size_t(j) * 9 * m * m;
+  double lmax = 0.0;
   for (int t = tid; t < m * m; t += 256) {  // slot 0: the inverse
     const int c = t / m, i = t - c * m;
     const cplx<double> v = a[i * w + m + c];
     out[t] = make_double2(v.re, v.im);
+    lmax = fmax(lmax, fmax(fabs(v.re), fabs(v.im)));
   }
   for (int s = 1; s < 9; ++s) {
     __syncthreads();
@@ -107,8 +126,13 @@ __global__ __launch_bounds__(256) void k_coarse_eo_blocks(const double2* __restr
       cplx<double> acc = {0.0, 0.0};
       for (int l = 0; l < m; ++l) acc += a[i * w + m + l] * a[l * w + c];
       out[size_t(s) * m * m + t] = make_double2(acc.re, acc.im);
+      lmax = fmax(lmax, fmax(fabs(acc.re), fabs(acc.im)));
     }
   }
+  if (!(lmax == lmax)) lmax = 1e308;  // a NaN entry counts as an overflow
+  atomicMax(&omax, static_cast<unsigned long long>(__double_as_longlong(lmax)));
+  __syncthreads();
+  if (tid == 0) atomicMax(reinterpret_cast<unsigned long long*>(flag + 2), omax);
 }
 
 // One colour of the even-odd coarse operator (the form in the file header).  One workgroup per
@@ -283,19 +307,32 @@ void build_coarse_eo_blocks(HierarchyDev& h, hipStream_t st) {
   const int d = h.blk.d, m = 2 * h.k;
   QMG_CHECK(m <= 64, QMG_EINVAL, "even-odd coarse operator supports 2k <= 64");
   const size_t nblk = size_t(d) * 9 * m * m;
+  // a failed or partial build leaves no blocks behind (the caller's coarse_eo flag stays off)
+  h.Yh64.release();
+  h.Yhin.release();
   h.Yh64.alloc(nblk * sizeof(double2));
-  DevBuf flag(sizeof(int));
-  QMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  DevBuf flag(4 * sizeof(int));  // [0] singular block, [2..3] largest |entry| of Yhat (double bits)
+  QMG_HIP(hipMemsetAsync(flag.p, 0, 4 * sizeof(int), st));
   const size_t lds = (size_t(m) * 2 * m + m) * sizeof(double2);
   if (lds > 64 * 1024)
     QMG_HIP(hipFuncSetAttribute((const void*)k_coarse_eo_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 int(lds)));
   k_coarse_eo_blocks<<<d, 256, lds, st>>>(h.Y64.as<double2>(), h.Yh64.as<double2>(), m, flag.as<int>());
   QMG_LAUNCH_CHECK();
-  int bad = 0;
-  QMG_HIP(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  int fl[4] = {0, 0, 0, 0};
+  QMG_HIP(hipMemcpyAsync(fl, flag.p, sizeof(fl), hipMemcpyDeviceToHost, st));
   QMG_HIP(hipStreamSynchronize(st));
-  QMG_CHECK(bad == 0, QMG_EBREAKDOWN, "a coarse self block is singular: no even-odd coarse operator");
+  double ymax = 0.0;
+  std::memcpy(&ymax, fl + 2, sizeof(double));
+  // largest finite value of the inner storage type, with a factor 2 of headroom for the sums
+  const double lim = h.inner == QMG_F16 ? 65504.0 / 2 : 3.0e38 / 2;
+  if (fl[0] != 0 || !(ymax < lim)) {
+    h.Yh64.release();
+    QMG_CHECK(fl[0] == 0, QMG_EBREAKDOWN,
+              "a coarse self block is numerically singular (pivot below 1e-13 of its largest entry)");
+    QMG_CHECK(false, QMG_EBREAKDOWN, "Y_0^-1 Y has entries of modulus %.3g, beyond the %s storage range", ymax,
+              h.inner == QMG_F16 ? "FP16" : "inner");
+  }
   if (h.inner != QMG_F64) {
     h.Yhin.alloc(nblk * prec_bytes(h.inner));
     launch_convert(h.Yh64.p, QMG_F64, h.Yhin.p, h.inner, nblk, st);

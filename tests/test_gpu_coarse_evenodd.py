@@ -89,7 +89,35 @@ def test_coarse_eo_after_more_streams(qmg):
     mg.close()
 
 
-@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_coarse_eo_off_more_streams_on(qmg):
+    """on -> off -> more streams -> on: the Yhat blocks are rebuilt from the new D_c (switching
+    off releases them, so nothing of the old coarse operator survives)."""
+    dims, block, k = (8, 8, 8, 8), (4, 4, 4, 4), 6
+    U = fields.random_gauge(dims, 0.5, 94)
+    lat = qmg.Lattice(dims, -0.1, 1.0, -1)
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), block, 12, 6, k, n_setup_iter=2, inner="f32", seed=4)
+    banner("coarse eo on -> off -> stream_more -> on")
+    mg.set_coarse_eo(True)
+    mg.set_coarse_eo(False)
+    mg.stream_more(1)
+    mg.set_coarse_eo(True)
+    P = to_np(mg.prolongator()[0])
+    Yo = coarse.build_coarse(U, P, -0.1, 1.0, -1, dims, block)
+    cd = geo.coarse_dims(dims, block)
+    d = Yo.shape[0]
+    b = fields.gaussian_coarse(d * 2 * k, 2, 95).reshape(2, d, 2, k)
+    x, _ = qmg.coarse_eo_solve(mg, to_gpu(b), tol=1e-12)
+    ref = np.linalg.solve(coarse.dense_coarse(Yo, cd), b.reshape(2, -1).T).T.reshape(b.shape)
+    assert rel(to_np(x), ref) < 1e-9
+    # the K-cycle's inner-precision Schur blocks follow as well: the solve reaches 1e-10
+    bf = fields.gaussian_spinor(dims, 1, 96)
+    xf, info = qmg.mg_solve(mg, to_gpu(bf), tol=1e-10)
+    r = bf - wilson.apply_wilson(U, to_np(xf), -0.1, 1.0, -1, dims)
+    assert np.linalg.norm(r) / np.linalg.norm(bf) < 2e-10
+    mg.close()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16", "f16"])
 def test_mg_solve_with_coarse_eo(qmg, inner):
     """The K-cycle with the coarse solve on the Schur complement reaches 1e-10 in the oracle's
     residual, with and without the even-odd fine smoother, and D^dagger too."""

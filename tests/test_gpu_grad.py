@@ -78,3 +78,77 @@ def test_gradients_finite_differences(qmg):
         an = float(np.real(np.vdot(g.ravel(), Dl.ravel())))
         print(f"[grad] FD {fd:.10e} analytic {an:.10e} rel {abs(fd - an) / abs(an):.2e}")
         assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_gradients_grad16x32_mixed(qmg):
+    """The differentiation workload as configured: 16^3 x 32, xi = 1, eps = 0.5, m = 0.03, the
+    hierarchy of 4^4 blocks with 48 test vectors in batches of 8 truncated to 24, FP32 inner /
+    FP64 outer solves, loss Re<eta, D^-1 b> with complex Gaussian eta and b.
+    grad_b = lambda is checked against an adjoint solve of an FP64 hierarchy; the link gradient
+    against the oracle's force formula on those FP64 solutions; and directional derivatives along
+    eight random directions and four single link entries supported on the 4^4 sublattice
+    x, y, z in [0, 4), t in {Lt-2, Lt-1, 0, 1} (it straddles the antiperiodic boundary) against
+    central differences, h = 1e-4, of mixed-precision GPU solves on the perturbed links (each
+    with its own hierarchy), to 1e-6."""
+    from fields import workloads
+    from oracle import geometry as geo
+    from paper_2505_14399_amd.autograd import solve
+    w = workloads.get("grad16x32")
+    dims = w["dims"]
+    banner(f"grad16x32 mixed: autograd vs FP64 adjoint, oracle force and central differences {dims}")
+    U = fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])
+    b = fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])
+    eta = fields.gaussian_spinor(dims, 1, w["seed"], stream=fields.ETA_STREAM, tag=w["tag"])
+    lat = qmg.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
+    kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
+              seed=w["seed"])
+    mg = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), inner=w["inner"], **kw)
+    tol = 1e-13
+    Ug = to_gpu(U).requires_grad_(True)
+    bg = to_gpu(b).requires_grad_(True)
+    x = solve(Ug, bg, mg, tol)
+    L = torch.real(torch.sum(torch.conj(to_gpu(eta)) * x))
+    L.backward()
+    g = to_np(Ug.grad)
+    mg64 = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U), inner="f64", **kw)
+    x64, _ = qmg.mg_solve(mg64, to_gpu(b), tol=tol)
+    lam64, _ = qmg.mg_solve(mg64, to_gpu(eta), tol=tol, adjoint=True)
+    mg64.close()
+    x64, lam64 = to_np(x64), to_np(lam64)
+    e_b = rel(to_np(bg.grad), lam64)
+    e_x = rel(to_np(x.detach()), x64)
+    e_u = rel(g, force.link_force(x64, lam64, w["xi"], w["bc_t"], dims))
+    print(f"[grad] grad16x32: x vs FP64 {e_x:.2e}, grad_b vs FP64 adjoint {e_b:.2e}, grad_U vs oracle force "
+          f"{e_u:.2e}")
+    assert e_x < 1e-9 and e_b < 1e-9 and e_u < 1e-9
+    c = geo.coords(dims)
+    mask = (c[:, 0] < 4) & (c[:, 1] < 4) & (c[:, 2] < 4) & np.isin(c[:, 3], [dims[3] - 2, dims[3] - 1, 0, 1])
+    idx = np.nonzero(mask)[0]
+    rng = np.random.default_rng(5)
+    dirs = []
+    for _ in range(8):
+        Dl = np.zeros_like(U)
+        Dl[:, mask] = rng.standard_normal((4, mask.sum(), 3, 3)) + 1j * rng.standard_normal((4, mask.sum(), 3, 3))
+        dirs.append(("direction", Dl))
+    for _ in range(4):
+        Dl = np.zeros_like(U)
+        mu, s, a, bb = rng.integers(4), rng.choice(idx), rng.integers(3), rng.integers(3)
+        Dl[mu, s, a, bb] = np.exp(2j * np.pi * rng.uniform())
+        dirs.append((f"entry mu={mu} site={s} ({a},{bb})", Dl))
+    h = 1e-4
+    worst = 0.0
+    for name, Dl in dirs:
+        Ls = []
+        for sgn in (1, -1):
+            mgp = qmg.mg_setup_stream_chiral_svd(lat, to_gpu(U + sgn * h * Dl), inner=w["inner"], **kw)
+            xp, ip = qmg.mg_solve(mgp, to_gpu(b), tol=tol)
+            mgp.close()
+            assert ip[0]["true_rel_res"] <= tol
+            Ls.append(float(np.real(np.vdot(eta.ravel(), to_np(xp).ravel()))))
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+        an = float(np.real(np.vdot(g.ravel(), Dl.ravel())))
+        err = abs(fd - an) / abs(an)
+        worst = max(worst, err)
+        print(f"[grad] {name}: FD {fd:.12e} analytic {an:.12e} rel {err:.2e}")
+    mg.close()
+    assert worst <= 1e-6

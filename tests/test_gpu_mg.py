@@ -21,9 +21,13 @@ def test_philox_test_vectors(qmg):
         assert np.abs(got[i] - ref).max() < 1e-13
 
 
-# FP32: 16 GMRES steps in single precision; the error against FP64 is stated, bounded loosely
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 5e-4)])
-def test_smoother(qmg, prec, tol):
+# FP64: parity with the oracle's GMRES.  FP32: the 16 GMRES steps in single precision give a
+# different point of the Krylov space (the least-squares problem amplifies the FP32 rounding of
+# the basis); that vector error is stated and gated only by a sanity limit, and what the
+# smoother is for, the reduction of |D psi| by the two GMRES(8) cycles, is gated instead: the
+# FP32 result's |D psi| / |psi| lies within 1e-3 of the FP64 oracle's.
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_smoother(qmg, prec):
     dims = (4, 4, 4, 4)
     banner(f"smoother {prec}")
     U = fields.random_gauge(dims, 0.3, 11)
@@ -34,8 +38,15 @@ def test_smoother(qmg, prec, tol):
     for i in range(3):
         ref = omg.smooth(olat, phi[i], 16)
         err = rel(got[i], ref)
-        print(f"[precision] smoother {prec}: rel err {err:.3e}")
-        assert err < tol
+        res_got = np.linalg.norm(wilson.apply_wilson(U, got[i], 0.05, 1.0, -1, dims)) / np.linalg.norm(got[i])
+        res_ref = np.linalg.norm(wilson.apply_wilson(U, ref, 0.05, 1.0, -1, dims)) / np.linalg.norm(ref)
+        print(f"[precision] smoother {prec}: rel err {err:.3e}, |D psi| / |psi| {res_got:.6e} (FP64 oracle "
+              f"{res_ref:.6e})")
+        if prec == "f64":
+            assert err < 1e-11
+        else:
+            assert err < 1e-2
+            assert res_got <= res_ref * (1 + 1e-3)
 
 
 def _oracle_icsvd(psis, dims, block, k):
