@@ -411,6 +411,20 @@ qmg_status qmg_mg_set_coarse_eo(qmg_mg* mg, int32_t on, hipStream_t stream);
 qmg_status qmg_coarse_schur_apply(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
                                   hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): qmg_coarse_schur_apply with the same arguments,
+ * result and errors, but its intermediate half vector lives in a fixed device array of the
+ * library (QMG_NOALLOC_SCRATCH_BYTES bytes, one per device, held until the process ends), so
+ * the call makes no hipMalloc / hipFree and does not synchronize the stream (asynchronous, like
+ * the apply calls).  The array's address on a device is looked up on the first call on that
+ * device.  Every call on one device shares that array: calls that overlap on one device (on
+ * different streams, or from different threads) race and must be ordered by the caller.
+ * Limit: nrhs * k * d * (16 bytes for F64, 8 for F32) <= QMG_NOALLOC_SCRATCH_BYTES (d
+ * aggregates, k per chirality).  Additional error: ESHAPE when a call needs more than that. */
+#define QMG_NOALLOC_SCRATCH_BYTES (16u << 20)
+qmg_status qmg_coarse_schur_apply_noalloc(const qmg_mg* mg, const void* in, void* out, int32_t nrhs,
+                                          qmg_prec prec, hipStream_t stream);
+
 /* D_c x = b (full coarse vectors [nrhs][d][2k], device, FP64) through the Schur complement
  * above: GMRES(32) from zero on Dhat_c to tol relative to rhat_e within max_iter steps, then the
  * odd part; *iters = GMRES steps.  Needs qmg_mg_set_coarse_eo(mg, 1).  Synchronizes the stream.

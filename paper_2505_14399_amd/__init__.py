@@ -74,6 +74,7 @@ SIGNATURES = {
     "qmg_mg_set_smoother": [_P, _I, _P],
     "qmg_mg_set_coarse_eo": [_P, _I, _P],
     "qmg_coarse_schur_apply": [_P, _P, _P, _I, _I, _P],
+    "qmg_coarse_schur_apply_noalloc": [_P, _P, _P, _I, _I, _P],
     "qmg_coarse_eo_solve": [_P, _P, _P, _I, _D, _I, _P, _P],
     "qmg_pack_spinor": [_P, _P, _P, _I, _I, _P],
     "qmg_unpack_spinor": [_P, _P, _P, _I, _I, _P],
@@ -638,6 +639,16 @@ def coarse_schur_apply(mg: MG, v_e, out=None):
     p = _prec_of(v_e)
     out = torch.empty_like(v_e) if out is None else out
     _check(load_library().qmg_coarse_schur_apply(mg.handle, _ptr(v_e), _ptr(out), v_e.shape[0], p, _stream()))
+    return out
+
+
+def coarse_schur_apply_noalloc(mg: MG, v_e, out):
+    """out_e = Dhat_c v_e like coarse_schur_apply, with the library's fixed scratch array instead
+    of an allocated intermediate (no device allocation, no stream synchronisation): `out` must be
+    given; calls that overlap on one device race (see qmg.h)."""
+    p = _prec_of(v_e)
+    _check(load_library().qmg_coarse_schur_apply_noalloc(mg.handle, _ptr(v_e), _ptr(out), v_e.shape[0], p,
+                                                         _stream()))
     return out
 
 

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <cstdarg>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1923,6 +1924,62 @@ qmg_status qmg_coarse_schur_apply(const qmg_mg* mg, const void* in, void* out, i
     CoarseSchurOp A(h, prec, d64 ? h.Y64.p : h.Yin.p, d64 ? h.Yh64.p : h.Yhin.p);
     A.apply(in, out, nrhs, stream);
     QMG_HIP(hipStreamSynchronize(stream));  // A's work buffer is released on return
+  });
+}
+
+// ---------------------------------------------------------------------------------------
+// qmg_coarse_schur_apply_noalloc: the Schur apply with its intermediate half vector (the
+// Yhat-hops of the input on the odd colour) in a file-scope device array instead of an
+// allocated buffer.  The array's host-side name is no device address: its address on each
+// device is taken once, on the first call on that device, and only that address is passed to
+// the kernels.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(QMG_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_on_current_device() {
+  int dev = 0;
+  QMG_HIP(hipGetDevice(&dev));
+  QMG_CHECK(dev >= 0 && dev < kMaxDevices, QMG_EINVAL, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    QMG_CHECK(e == hipSuccess && ptr, QMG_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+              hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+qmg_status qmg_coarse_schur_apply_noalloc(const qmg_mg* mg, const void* in, void* out, int32_t nrhs, qmg_prec prec,
+                                          hipStream_t stream) {
+  return guard([&] {
+    check_ptr(mg, "mg");
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    QMG_CHECK(in != out, QMG_EINVAL, "in and out must not alias");
+    QMG_CHECK(nrhs >= 1, QMG_EINVAL, "nrhs must be >= 1");
+    const HierarchyDev& h = mg->h;
+    QMG_CHECK(h.coarse_eo, QMG_EINVAL, "coarse_schur_apply_noalloc: the even-odd coarse operator is not set up");
+    QMG_CHECK(prec == QMG_F64 || (prec == h.inner && prec == QMG_F32), QMG_EDTYPE,
+              "coarse_schur_apply_noalloc: precision must be F64 or the F32 inner precision");
+    const size_t need = size_t(nrhs) * size_t(h.k) * size_t(h.blk.d) * prec_bytes(prec);
+    QMG_CHECK(need <= kNoAllocScratchBytes, QMG_ESHAPE,
+              "coarse_schur_apply_noalloc: %d right-hand sides of %d half coarse entries need %zu bytes of scratch, "
+              "above the library's fixed %zu bytes (use qmg_coarse_schur_apply or fewer right-hand sides)",
+              nrhs, h.k * h.blk.d, need, kNoAllocScratchBytes);
+    void* tmp = scratch_on_current_device();
+    const bool d64 = prec == QMG_F64;
+    const void* Y = d64 ? h.Y64.p : h.Yin.p;
+    const void* Yh = d64 ? h.Yh64.p : h.Yhin.p;
+    // the first launch writes every entry of the intermediate, so nothing needs clearing
+    launch_coarse_eo_apply(prec, h, 1, Yh, nullptr, nullptr, in, tmp, nrhs, 1.0, stream);
+    launch_coarse_eo_apply(prec, h, 0, Y, nullptr, in, tmp, out, nrhs, -1.0, stream);
   });
 }
 
