@@ -76,7 +76,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso16x32_fp32")
+    ap.add_argument("--workload", default="batched32x64")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the setup / mixed / FP64 solve lines of the other lattices (16^3x32, 24^3x64)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator solve")
@@ -543,23 +545,45 @@ def recorded_traffic(wname, fam):
     return e["bytes_per_launch"]
 
 
-def cpu_baseline(w, counts):
-    """Time the oracle's unit operations on this workload and scale by the solve's op counts."""
+def _host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, counts, U=None):
+    """The CPU oracle on this host, on a bounded sample of the workload (its unit operations at
+    the workload's shapes, each timed directly), composed into an estimate of the oracle's time
+    for the GPU solve's own operation counts (the oracle is never run on the whole solve here)."""
     import numpy as np
     import fields
-    from oracle import wilson, clover, transfer, coarse, geometry as geo, krylov  # noqa: F401
+    from oracle import wilson, clover, transfer, coarse, icsvd, geometry as geo  # noqa: F401
+    from threadpoolctl import threadpool_info
 
-    dims, block, k = w["dims"], w["block"], w["rank"]
+    dims, block, k, r = w["dims"], w["block"], w["rank"], w["batch"]
     V = geo.volume(dims)
     cd = geo.coarse_dims(dims, block)
     d = geo.volume(cd)
-    N = 6 * int(np.prod(block))
+    nd = int(np.prod(block))
+    N = 6 * nd
     rng = np.random.default_rng(0)
-    U = fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])
+    if U is None:
+        U = fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])
     psi = fields.gaussian_spinor(dims, 1, w["seed"])[0]
-    P, _ = np.linalg.qr(rng.standard_normal((d, 2, N, k)) + 1j * rng.standard_normal((d, 2, N, k)))
-    Y = rng.standard_normal((d, 9, 2 * k, 2 * k)) + 1j * rng.standard_normal((d, 9, 2 * k, 2 * k))
+    m = 2 * k
+    # the coarse operator's values do not change the oracle's work: one random block broadcast
+    Y = np.broadcast_to(rng.standard_normal((1, 9, m, m)) + 1j * rng.standard_normal((1, 9, m, m)), (d, 9, m, m))
     vc = rng.standard_normal((1, d, 2, k)) + 1j * rng.standard_normal((1, d, 2, k))
+    # restrict + prolong and the streaming SVD on a slice of the aggregates (both are independent
+    # per aggregate), scaled to all of them
+    ds = min(d, 512)
+    Ps, _ = np.linalg.qr(rng.standard_normal((ds, 2, N, k)) + 1j * rng.standard_normal((ds, 2, N, k)))
+    sdims = (block[0], block[1], block[2], block[3] * ds)  # ds aggregates stacked along t
+    psis = fields.gaussian_spinor(sdims, 1, 3)[0]
+    nprob = min(2 * d, 256)
+    Phi = [rng.standard_normal((N, k)) + 1j * rng.standard_normal((N, k)) for _ in range(nprob)]
+    Psi = [rng.standard_normal((N, r)) + 1j * rng.standard_normal((N, r)) for _ in range(nprob)]
 
     def tm(f, n):
         t0 = time.perf_counter()
@@ -567,31 +591,128 @@ def cpu_baseline(w, counts):
             f()
         return (time.perf_counter() - t0) / n
 
-    from threadpoolctl import threadpool_limits
     if w.get("c_sw"):  # the clover term is setup work, built once outside the timed calls
         T = clover.clover_term(U, dims, *w["c_sw"])
         apply_D = lambda: clover.apply_clover(U, T, psi, w["mass"], w["xi"], w["bc_t"], dims)  # noqa: E731
     else:
         apply_D = lambda: wilson.apply_wilson(U, psi, w["mass"], w["xi"], w["bc_t"], dims)  # noqa: E731
-    with threadpool_limits(limits=1):  # one host thread: BLAS pools held to one thread
-        t_D = tm(apply_D, 3)
-        t_Dc = tm(lambda: coarse.coarse_apply(Y, vc, cd), 5)
-        t_RP = tm(lambda: transfer.prolong(P, transfer.restrict(P, psi[None], dims, block), dims, block), 2)
-        a, b = psi.ravel(), psi.ravel().copy()
-        t_vec = tm(lambda: (np.vdot(a, b), b + 0.5 * a), 5)
+    t_D = tm(apply_D, 1 if V > 1 << 20 else 3)
+    t_Dc = tm(lambda: coarse.coarse_apply(Y, vc, cd), 1 if d > 4096 else 3)
+    t_RP = tm(lambda: transfer.prolong(Ps, transfer.restrict(Ps, psis[None], sdims, block), sdims, block), 1) * d / ds
+    t_svd = tm(lambda: [icsvd.icsvd_update(Phi[i], Psi[i], k) for i in range(nprob)], 1) * (2 * d) / nprob
+    a, b = psi.ravel(), psi.ravel().copy()
+    t_vec = tm(lambda: (np.vdot(a, b), b + 0.5 * a), 3)
     est = (counts["dslash"] * t_D + counts["coarse_apply"] * t_Dc + counts["restrict"] * t_RP
            + counts["vector_ops"] * t_vec)
-    try:
-        ncpu = len(os.sched_getaffinity(0))
-    except AttributeError:
-        ncpu = os.cpu_count()
+    blas = [f"{p.get('internal_api')}:{p.get('num_threads')}" for p in threadpool_info()]
+    ncpu = _host_cores()
+    ns = w["n_test"] // w["batch"]
+    setup_est = ns * (w["batch"] * (16 + 1) * t_D + t_svd)
     return {
-        "value": est, "unit": "s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle unit operations timed on this workload ({dims}, k={k}): fine D apply "
-                   f"{t_D:.3f}s{' (with the clover term)' if w.get('c_sw') else ''}, coarse apply {t_Dc:.4f}s, restrict+prolong {t_RP:.3f}s, fine vector op "
-                   f"{t_vec:.4f}s; scaled by the GPU solve's operation counts {counts}; one thread (BLAS "
-                   f"pools limited to 1; {ncpu} host cpus visible)"),
+        "value": est, "unit": "s", "cores": ncpu, "kind": "oracle",
+        "sample": (f"oracle unit operations on this workload's shapes ({dims}, k={k}), each timed directly: fine D "
+                   f"apply {t_D:.3f}s{' (with the clover term)' if w.get('c_sw') else ''} (one rhs), coarse apply "
+                   f"{t_Dc:.4f}s ({d} aggregates), restrict+prolong {t_RP:.3f}s (timed on {ds} aggregates, scaled), "
+                   f"one streaming-SVD stream {t_svd:.3f}s (LAPACK per problem, timed on {nprob} of {2 * d} problems, "
+                   f"scaled), fine vector op {t_vec:.4f}s; value = these times x the GPU solve's operation counts "
+                   f"{counts} (coarse Schur launches counted as the fraction of a coarse apply they stream); oracle "
+                   f"setup estimate {setup_est:.1f}s (smoothing applies + {ns} streams); BLAS/LAPACK pools "
+                   f"{blas} over {ncpu} affinity cores, stencil and vector arithmetic single-threaded (NumPy)"),
     }
+
+
+def family_table(families, steps):
+    """Per family: timed launches, calls, average launch ms, device ms per step, algorithmic
+    bytes and flops per launch."""
+    import paper_2505_14399_amd as q
+    out = {}
+    for f in families:
+        t = q.timing_query(f)
+        if not t["launches"]:
+            continue
+        avg = t["ms"] / t["launches"]
+        out[f] = {"launches_timed": t["launches"], "calls": t["calls"], "avg_launch_ms": avg,
+                  "ms_per_step": avg * t["calls"] / steps, "bytes_per_launch": t["bytes"] / t["launches"],
+                  "flops_per_launch": t["flops"] / t["launches"]}
+    return out
+
+
+def roofline_of(fam_name, f, wname):
+    """Roofline object of one family: FP64 flops for the streaming-SVD kernels, else algorithmic
+    bytes over HBM."""
+    avg_s = f["avg_launch_ms"] * 1e-3
+    if fam_name.startswith("isvd") or (f["bytes_per_launch"] == 0 and f["flops_per_launch"] > 0):
+        ach = f["flops_per_launch"] / avg_s / 1e12
+        return {"bound": "mfma" if fam_name.startswith("isvd/gram") else "alu", "achieved": ach,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                "kernel": fam_name, "avg_launch_ms": f["avg_launch_ms"],
+                "algorithmic_flops_per_launch": f["flops_per_launch"]}
+    ach = f["bytes_per_launch"] / avg_s / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBPS,
+            "traffic": recorded_traffic(wname, fam_name), "kernel": fam_name, "avg_launch_ms": f["avg_launch_ms"],
+            "algorithmic_bytes_per_launch": f["bytes_per_launch"]}
+
+
+def make_solver(args, q):
+    eo_smoother = not args.plain_smoother
+
+    def coarse_eo(mg):
+        """The Schur-complement coarse solve unless --full-coarse, or where it does not apply (an
+        odd coarse extent, further levels): returns whether it is on."""
+        if args.full_coarse:
+            return False
+        try:
+            mg.set_coarse_eo(True)
+            return True
+        except q.QmgError:
+            return False
+    return eo_smoother, coarse_eo
+
+
+def measure_config(args, name, steps=2):
+    """Setup and mixed-precision solve of another workload (one warm-up step, then `steps` timed
+    steps) and the FP64 path on the same lattice: medians and iteration counts."""
+    import numpy as np
+    import torch
+    import fields
+    from fields import workloads
+    import paper_2505_14399_amd as q
+
+    w = workloads.get(name)
+    dims = w["dims"]
+    lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
+    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
+    b = torch.from_numpy(workloads.rhs(w)).cuda()
+    eo_smoother, coarse_eo = make_solver(args, q)
+    kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
+              n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, seed=w["seed"], c_sw=w.get("c_sw"))
+    res = {"workload": name, "lattice": list(dims), "mass": w["mass"], "inner": w["inner"], "nrhs": int(b.shape[0])}
+    for inner in (w["inner"], "f64"):
+        setups, solves, info = [], [], None
+        for it in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mg = q.mg_setup_stream_chiral_svd(lat, U, inner=inner, **kw)
+            mg.set_smoother(eo=eo_smoother, sstep=True)
+            coarse_eo(mg)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = q.mg_solve(mg, b, tol=args.tol)
+            t2 = time.perf_counter()
+            mg.close()
+            if it:
+                setups.append(t1 - t0)
+                solves.append(t2 - t1)
+        worst = max(i["true_rel_res"] for i in info)
+        if worst > args.tol:
+            raise SystemExit(f"{name} ({inner}) did not reach {args.tol}: {info}")
+        key = "mixed" if inner != "f64" else "fp64"
+        res[key] = {"setup_s": float(np.median(setups)), "solve_s": float(np.median(solves)),
+                    "outer_iters": info[0]["outer_iters"], "coarse_iters": info[0]["coarse_iters"],
+                    "true_rel_res": worst}
+    del U
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -616,42 +737,33 @@ def main():
     import torch
 
     import fields
+    from fields import workloads
     import paper_2505_14399_amd as q
 
     w = load_workload(args)
     dims = w["dims"]
     lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
-    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
-    b = torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda()
+    U_host = fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])
+    U = torch.from_numpy(U_host).cuda()
+    b = torch.from_numpy(workloads.rhs(w)).cuda()
+    nrhs = int(b.shape[0])
     setup_kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
                     n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"],
                     c_sw=w.get("c_sw"))
-    op_name = "clover" if w.get("c_sw") else "dslash"  # timing families of the fine operator
-    families = CLOVER_FAMILIES if w.get("c_sw") else FAMILIES
-
-    eo_smoother = not args.plain_smoother
-
-    def coarse_eo(mg):
-        """The Schur-complement coarse solve unless --full-coarse, or where it does not apply (an
-        odd coarse extent, further levels): returns whether it is on."""
-        if args.full_coarse:
-            return False
-        try:
-            mg.set_coarse_eo(True)
-            return True
-        except q.QmgError:
-            return False
+    eo_smoother, coarse_eo = make_solver(args, q)
 
     def step():
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
         mg.set_smoother(eo=eo_smoother, sstep=True)  # builds the half-lattice fields: part of the setup
         coarse_eo(mg)
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
         x, info = q.mg_solve(mg, b, tol=args.tol)
         t2 = time.perf_counter()
         mg.close()
-        return t1 - t0, t2 - t1, info[0]
+        return t1 - t0, t2 - t1, info
 
     for _ in range(args.warmup):
         step()
@@ -668,12 +780,12 @@ def main():
         infos.append(info)
     torch.cuda.synchronize()
     T1 = time.perf_counter()
-    fams = {f: q.timing_query(f) for f in families}
-    ds = q.timing_query(op_name)
+    fams = family_table(q.timing_families(), args.steps)
     q.timing_enable(False)
-    for i in infos:
-        if i["true_rel_res"] > args.tol:
-            raise SystemExit(f"solve did not reach {args.tol}: {i}")
+    for info in infos:
+        for i in info:
+            if i["true_rel_res"] > args.tol:
+                raise SystemExit(f"solve did not reach {args.tol}: {i}")
 
     # operation counts of one mixed solve (for the CPU baseline), from an untimed solve
     mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
@@ -681,76 +793,68 @@ def main():
     ceo_on = coarse_eo(mg)
     q.timing_enable(True)
     _, sinfo = q.mg_solve(mg, b, tol=args.tol)
-    cnt = {f: q.timing_query(op_name if f == "dslash" else f)["launches"] for f in ("dslash", "coarse_apply",
-                                                                                      "restrict")}
-    # an even-odd hop does the work of half a fine operator application
-    cnt["dslash"] += q.timing_query("evenodd")["launches"] // 2
+    op_name = "clover" if w.get("c_sw") else "dslash"
+    cnt = {"dslash": q.timing_query(op_name)["calls"] * nrhs, "restrict": q.timing_query("restrict")["calls"],
+           "coarse_apply": q.timing_query("coarse_apply")["calls"]}
+    # an even-odd hop does the work of half a fine operator application per right-hand side, a
+    # coarse Schur launch streams about (slots / 9) of half the coarse operator
+    cnt["dslash"] += q.timing_query("evenodd")["calls"] * nrhs // 2
+    ceo = q.timing_query("coarse_eo")
+    cnt["coarse_apply"] += int(round(ceo["calls"] * 0.5 * 8.5 / 9))
+    cnt["restrict"] *= nrhs
+    cnt["coarse_apply"] *= nrhs
+    cnt["vector_ops"] = 12 * sum(i["smoother_iters"] + i["outer_iters"] for i in sinfo)
     q.timing_enable(False)
-    # the other smoother on the same hierarchy, for comparison (untimed region)
+    # the other smoother and the other coarse solve on the same hierarchy, for comparison
     mg.set_smoother(eo=not eo_smoother, sstep=True)
     q.mg_solve(mg, b, tol=args.tol)
-    ts_other, other = [], None
-    for _ in range(2):
-        t0 = time.perf_counter()
-        _, other = q.mg_solve(mg, b, tol=args.tol)
-        ts_other.append(time.perf_counter() - t0)
-    other_solve = {"smoother": "plain" if eo_smoother else "even-odd", "s": float(np.median(ts_other)),
-                   "outer_iters": other[0]["outer_iters"], "coarse_iters": other[0]["coarse_iters"],
-                   "true_rel_res": other[0]["true_rel_res"]}
-    # the other coarse solve (Schur complement or full D_c) with the benchmark's smoother
+    t0 = time.perf_counter()
+    _, other = q.mg_solve(mg, b, tol=args.tol)
+    other_solve = {"smoother": "plain" if eo_smoother else "even-odd", "s": time.perf_counter() - t0,
+                   "outer_iters": [i["outer_iters"] for i in other], "coarse_iters": other[0]["coarse_iters"],
+                   "true_rel_res": max(i["true_rel_res"] for i in other)}
     other_coarse = None
     mg.set_smoother(eo=eo_smoother, sstep=True)
-    if ceo_on or args.full_coarse:
-        try:
-            mg.set_coarse_eo(not ceo_on)
-        except q.QmgError:
-            pass
-        else:
-            q.mg_solve(mg, b, tol=args.tol)
-            ts_oc, oc = [], None
-            for _ in range(2):
-                t0 = time.perf_counter()
-                _, oc = q.mg_solve(mg, b, tol=args.tol)
-                ts_oc.append(time.perf_counter() - t0)
-            other_coarse = {"coarse_solve": "full D_c" if ceo_on else "even-odd Schur complement",
-                            "s": float(np.median(ts_oc)), "outer_iters": oc[0]["outer_iters"],
-                            "coarse_iters": oc[0]["coarse_iters"], "true_rel_res": oc[0]["true_rel_res"]}
+    try:
+        mg.set_coarse_eo(not ceo_on)
+    except q.QmgError:
+        pass
+    else:
+        q.mg_solve(mg, b, tol=args.tol)
+        t0 = time.perf_counter()
+        _, oc = q.mg_solve(mg, b, tol=args.tol)
+        other_coarse = {"coarse_solve": "full D_c" if ceo_on else "even-odd Schur complement",
+                        "s": time.perf_counter() - t0, "outer_iters": [i["outer_iters"] for i in oc],
+                        "coarse_iters": oc[0]["coarse_iters"], "true_rel_res": max(i["true_rel_res"] for i in oc)}
     mg.close()
-    cnt["vector_ops"] = 12 * (sinfo[0]["smoother_iters"] + sinfo[0]["outer_iters"])
 
-    # FP64 comparator on the same lattice (own FP64 setup, untimed)
+    # FP64 path on the same lattice (own FP64 setup, the same smoother and coarse solve; untimed)
     fp64_solve = None
     if not args.no_fp64 and w["inner"] != "f64":
-        kw64 = dict(setup_kw, inner="f64")
-        mg64 = q.mg_setup_stream_chiral_svd(lat, U, **kw64)
+        mg64 = q.mg_setup_stream_chiral_svd(lat, U, **dict(setup_kw, inner="f64"))
         mg64.set_smoother(eo=eo_smoother, sstep=True)
         coarse_eo(mg64)
+        q.mg_solve(mg64, b, tol=args.tol)  # warm-up of the FP64 kernels
         ts64 = []
         for _ in range(2):
             t0 = time.perf_counter()
             _, i64 = q.mg_solve(mg64, b, tol=args.tol)
             ts64.append(time.perf_counter() - t0)
         mg64.close()
-        fp64_solve = {"s": float(np.median(ts64)), "outer_iters": i64[0]["outer_iters"],
-                      "true_rel_res": i64[0]["true_rel_res"]}
+        fp64_solve = {"s": float(np.median(ts64)), "outer_iters": [i["outer_iters"] for i in i64],
+                      "coarse_iters": i64[0]["coarse_iters"], "true_rel_res": max(i["true_rel_res"] for i in i64)}
+    del U
+    torch.cuda.empty_cache()
 
-    # dominant kernel by summed device time in the timed region
-    dom = max(fams, key=lambda f: fams[f]["ms"] * fams[f]["calls"] / max(1, fams[f]["launches"]))
-    ds_avg_ms = ds["ms"] / max(1, ds["launches"])
-    ds_gbps = ds["bytes"] / max(1, ds["launches"]) / (ds_avg_ms * 1e-3) / 1e9
-    fam = fams[dom]
-    avg_ms = fam["ms"] / max(1, fam["launches"])
-    if dom == "isvd":
-        ach = fam["flops"] / max(1, fam["launches"]) / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "kernel": "isvd", "avg_launch_ms": avg_ms}
-    else:
-        per_launch = fam["bytes"] / max(1, fam["launches"])
-        ach = per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBPS,
-                "traffic": recorded_traffic(w["name"], dom), "kernel": dom, "avg_launch_ms": avg_ms,
-                "algorithmic_bytes_per_launch": per_launch}
-
+    # the dominant kernel family: the largest device time per step
+    dom = max(fams, key=lambda f: fams[f]["ms_per_step"])
+    roof = roofline_of(dom, fams[dom], w["name"])
+    top = sorted(fams, key=lambda f: -fams[f]["ms_per_step"])[:12]
+    op = [f for f in fams if f.startswith(op_name + "/")]
+    op_ms = sum(fams[f]["avg_launch_ms"] * fams[f]["launches_timed"] for f in op)
+    op_bytes = sum(fams[f]["bytes_per_launch"] * fams[f]["launches_timed"] for f in op)
+    op_n = sum(fams[f]["launches_timed"] for f in op)
+    info = infos[-1]
     res = {
         "metric": "MG solve s to rel.res 1e-10 (mixed vs FP64); dslash HBM GB/s; setup s",
         "value": float(np.median(solves)),
@@ -762,11 +866,13 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 inner, f64 outer" if w["inner"] == "f32" else w["inner"],
+        "dtype": "f32 inner, f64 outer" if w["inner"] == "f32" else f"{w['inner']} inner, f64 outer",
         "data": "synthetic",
         "config": {"workload": w["name"], "lattice": list(dims), "xi": w["xi"], "eps": w["eps"],
                    "mass": w["mass"], "bc_t": w["bc_t"], "block": list(w["block"]), "n_test": w["n_test"],
-                   "batch": w["batch"], "rank": w["rank"], "nrhs": 1, "tol": args.tol,
+                   "batch": w["batch"], "rank": w["rank"], "nrhs": nrhs,
+                   "rhs": "12 spin-colour point sources" if w.get("rhs") == "point12" else "1 complex Gaussian",
+                   "tol": args.tol,
                    "smoother": "even-odd GMRES(8), s-step form" if eo_smoother else "GMRES(8)",
                    "coarse_solve": "GMRES(32) on the even-odd Schur complement of D_c" if ceo_on
                    else "GMRES(32) on D_c",
@@ -775,18 +881,22 @@ def main():
         "solve_fp64": fp64_solve,
         "solve_other_smoother": other_solve,
         "solve_other_coarse": other_coarse,
-        "solve_info": infos[-1],
+        "solve_info": {"outer_iters": [i["outer_iters"] for i in info], "coarse_iters": info[0]["coarse_iters"],
+                       "refinements": info[0]["refinements"],
+                       "true_rel_res": max(i["true_rel_res"] for i in info)},
         "timing_sample": TIMING_SAMPLE,
-        "dslash": {"timed_launches": ds["launches"], "avg_launch_us": ds_avg_ms * 1e3, "GBps": ds_gbps,
-                   "frac_hbm": ds_gbps / PEAK_HBM_GBPS},
-        # the streaming SVD of one stream (Gram, small SVD, rotation) in FP64: algorithmic flops
-        # of the Gram passes and the rotation over the timed stream updates
-        "isvd": isvd_rate(fams["isvd"]),
-        # timed launches scaled to every call of the family
-        "kernel_ms_per_step": {f: fams[f]["ms"] * fams[f]["calls"] / fams[f]["launches"] / args.steps
-                               for f in fams if fams[f]["launches"]},
+        "dslash": ({"timed_launches": op_n, "avg_launch_us": op_ms / op_n * 1e3,
+                    "GBps": op_bytes / (op_ms * 1e-3) / 1e9, "frac_hbm": op_bytes / (op_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS}
+                   if op_n else None),
+        "kernel_ms_per_step": {f: round(fams[f]["ms_per_step"], 4) for f in top},
+        "kernel_rates": {f: roofline_of(f, fams[f], w["name"])["frac"] for f in top},
         "roofline": roof,
     }
+    if not args.no_configs:
+        res["configs"] = {}
+        for name in ("aniso16x32_fp32", "iso24x64_bf16"):
+            if name != w["name"]:
+                res["configs"][name] = measure_config(args, name)
     if not args.no_dslash_hbm:
         res["dslash_hbm"] = dslash_hbm()
     if not args.no_clover and not w.get("c_sw"):
@@ -796,7 +906,7 @@ def main():
     if not args.no_evenodd and not w.get("c_sw"):
         res["evenodd"] = evenodd_leg(args)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, cnt)
+        res["cpu_baseline"] = cpu_baseline(w, cnt, U_host)
     print(json.dumps(res), flush=True)
 
 

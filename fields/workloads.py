@@ -30,10 +30,10 @@ WORKLOADS = {
     "iso24x64_bf16": dict(dims=(24, 24, 24, 64), bc_t=-1, eps=0.7, xi=1.0, mass=None,
                           block=(4, 4, 4, 4), n_test=96, batch=16, rank=24,
                           inner="bf16", seed=14399, tag=3),
-    # 32^3x64 with 12 point sources
+    # 32^3x64 with the 12 spin-colour point sources at the origin solved together
     "batched32x64": dict(dims=(32, 32, 32, 64), bc_t=-1, eps=0.6, xi=1.0, mass=0.05,
                          block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
-                         inner="f32", seed=14399, tag=4),
+                         inner="f32", seed=14399, tag=4, rhs="point12"),
     # differentiation workload
     "grad16x32": dict(dims=(16, 16, 16, 32), bc_t=-1, eps=0.5, xi=1.0, mass=0.03,
                       block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
@@ -42,6 +42,15 @@ WORKLOADS = {
 
 _TUNED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                       "tests", "golden", "tuned_masses.json")
+
+
+def rhs(w: dict):
+    """The right-hand sides of a workload: the 12 point sources at the origin, or one complex
+    Gaussian spinor."""
+    import fields
+    if w.get("rhs") == "point12":
+        return fields.point_sources(w["dims"])
+    return fields.gaussian_spinor(w["dims"], 1, w["seed"], tag=w["tag"])
 
 
 def get(name: str) -> dict:

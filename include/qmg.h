@@ -434,11 +434,14 @@ qmg_status qmg_coarse_eo_solve(const qmg_mg* mg, const void* b, void* x, int32_t
                                int32_t max_iter, int32_t* iters, hipStream_t stream);
 
 /* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times the first 64
- * later launches of each instrumented kernel family and then about one in n (picked by a hash
- * of the call index) ("dslash/site", "dslash/twalk", "dslash/dir",
- * "dslash/canonical", "dslash/batched", "isvd", "coarse_apply", "prolong", "restrict",
- * "coarse_build") with a pair of HIP events attached to the dispatch (its own start and end);
- * 0 stops recording.  qmg_timing_query returns, for one family, the launches timed, their
+ * later launches of each kernel family and then about one in n (picked by a hash of the call
+ * index) with a pair of HIP events attached to the dispatch (its own start and end).  Every
+ * kernel of the library belongs to a family: the operators ("dslash/site", "dslash/twalk",
+ * "dslash/dir", "dslash/canonical", "dslash/batched", "clover/...", "evenodd/hop",
+ * "coarse_apply", "coarse_eo", "prolong", "restrict", "level_..."), the Krylov vector kernels
+ * ("blas/mdot_norm", "blas/axpy_scale", "blas/axpy_multi", ..., "krylov/givens", "sstep/..."),
+ * the setup ("setup/philox", "setup/gather", "isvd/...", "coarse_build", ...) and layout
+ * conversions ("layout/...", "eo_layout/...").  0 stops recording.  qmg_timing_query returns, for one family, the launches timed, their
  * summed duration (ms, it synchronizes on the events) and their summed algorithmic bytes and
  * flops; a name without '/' also sums its sub-families ("dslash").  Errors: EINVAL (n < 0). */
 qmg_status qmg_timing_enable(int32_t on);
@@ -446,6 +449,19 @@ qmg_status qmg_timing_query(const char* family, int64_t* launches, double* total
                             double* algo_flops);
 /* Every launch of the family (timed or not) since qmg_timing_enable.  Errors: EINVAL (null). */
 qmg_status qmg_timing_calls(const char* family, int64_t* calls);
+/* The names of every family launched since qmg_timing_enable, newline-separated, into buf
+ * (host, len bytes, NUL-terminated).  Errors: EINVAL (null, len < 1), ESHAPE (buf too short). */
+qmg_status qmg_timing_list(char* buf, int32_t len);
+
+/* Device memory.  The library's buffers (hierarchies, solver workspaces) come from a cache of
+ * freed blocks per device in front of hipMalloc, so repeated setups and solves reuse their
+ * blocks; a block is cached only after the device has finished its work (the wait hipFree
+ * performs), the cache holds at most half of the device memory (environment QMG_CACHE_GB
+ * overrides, 0 disables caching), and a failed hipMalloc releases it and retries.
+ * qmg_memory_trim returns the cache of the current device to the runtime (synchronizes the
+ * device); qmg_memory_cached reports its size in bytes.  Errors: EINVAL (null). */
+qmg_status qmg_memory_trim(void);
+qmg_status qmg_memory_cached(int64_t* bytes);
 
 /* Autotuner.  qmg_autotune(1) (or QMG_TUNE=1 in the environment) makes every kernel with
  * launch variants (the native-layout dslash: one site per thread, 2/4/8 sites per thread

@@ -94,6 +94,9 @@ SIGNATURES = {
     "qmg_timing_enable": [_I],
     "qmg_timing_query": [ctypes.c_char_p, _P, _P, _P, _P],
     "qmg_timing_calls": [ctypes.c_char_p, _P],
+    "qmg_timing_list": [ctypes.c_char_p, _I],
+    "qmg_memory_trim": [],
+    "qmg_memory_cached": [_P],
     "qmg_mg_set_cycle": [_P, _I, _I],
     "qmg_autotune": [_I],
     "qmg_set_dslash_variant": [_I],
@@ -722,6 +725,25 @@ def timing_query(family):
     calls = ctypes.c_int64()
     _check(load_library().qmg_timing_calls(family.encode(), ctypes.byref(calls)))
     return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value, "calls": calls.value}
+
+
+def timing_families():
+    """Names of every kernel family launched since timing_enable."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load_library().qmg_timing_list(buf, len(buf)))
+    return [f for f in buf.value.decode().split("\n") if f]
+
+
+def memory_trim():
+    """Return the library's cached device blocks to the runtime (see qmg.h)."""
+    _check(load_library().qmg_memory_trim())
+
+
+def memory_cached():
+    """Bytes of device memory held by the library's cache on the current device."""
+    n = ctypes.c_int64()
+    _check(load_library().qmg_memory_cached(ctypes.byref(n)))
+    return n.value
 
 
 def autotune(on=True):

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <cstdarg>
 #include <memory>
@@ -416,7 +417,10 @@ __global__ void k_gamma5(S* x, int V, int nrhs) {
 }
 void gamma5_f64(void* x, int V, int nrhs, hipStream_t st) {
   const size_t n = size_t(nrhs) * 6 * V;
-  k_gamma5<double2><<<unsigned((n + 255) / 256), 256, 0, st>>>((double2*)x, V, nrhs);
+  {
+    TimedLaunch tl_("layout/gamma5", st, 2.0 * double(n) * 16, 0.0);
+    launch(k_gamma5<double2>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, (double2*)x, V, nrhs);
+  }
   QMG_LAUNCH_CHECK();
 }
 
@@ -647,6 +651,12 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
   CoarseOp Dc(h, P, h.Yin.p);
   KCycle<F, S> K(h, Din, Dc, h.Pin.p);
   Gmres<F> f;  // flexible GMRES(16) with the K-cycle
+  // Two Gram-Schmidt passes in the FP32 outer solver: with a strong preconditioner each new
+  // Arnoldi vector is nearly in the span of the previous ones, and one pass with the norm from
+  // Pythagoras then loses orthogonality in FP32, so the least-squares estimate claims a residual
+  // the iterate does not have (on 32^3 x 64 point sources: 3 to 12 outer iterations and up to
+  // three refinements depending on the source; with two passes 4 and two for every source)
+  f.set_cgs2(true);
   DevBuf r64(n * sizeof(double2)), rin(n * sizeof(F)), ein(n * sizeof(F)), nrm(nrhs * sizeof(double)),
       bn(nrhs * sizeof(double));
   RedWork rw;
@@ -1657,10 +1667,14 @@ qmg_status qmg_coarse_apply(const qmg_mg* mg, const void* in, void* out, int32_t
   });
 }
 
+// bytes the outer solver's Krylov bases of one group of right-hand sides may hold
+constexpr size_t kBasisBudget = size_t(24) << 30;
+
 qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, double tol, int32_t max_outer,
                         int32_t adjoint, qmg_solve_info* info, hipStream_t stream) {
   bool converged = false;
-  SolveStats ss;
+  std::vector<SolveStats> gss;  // per group of right-hand sides
+  int G = 1;
   double tr = 0, el = 0;
   std::vector<double> rel;
   qmg_status rc = guard([&] {
@@ -1684,10 +1698,26 @@ qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, 
       const double bn = host_norm2(b64.p, n, stream);
       QMG_CHECK(std::isfinite(bn), QMG_ENONFINITE, "right-hand side has non-finite entries");
     }
-    if (h.inner == QMG_F64) solve_f64(h, b64.p, x64.p, nrhs, tol, max_outer, false, stream, ss, converged);
-    else if (h.inner == QMG_F32) solve_mixed<float2>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
-    else if (h.inner == QMG_BF16) solve_mixed<cbf16>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
-    else solve_mixed<chalf>(h, b64.p, x64.p, nrhs, tol, max_outer, stream, ss, converged);
+    // The right-hand sides are solved in groups whose outer-solver bases (restart + 1 basis
+    // vectors and restart preconditioned ones, in the outer solver's type) fit kBasisBudget, one
+    // group after another; every right-hand side has its own Krylov spaces, and a group iterates
+    // until its slowest member has converged.
+    const size_t per_rhs = size_t(2 * 16 + 1) * len * (h.inner == QMG_F64 ? sizeof(double2) : sizeof(float2));
+    G = int(std::max<size_t>(1, std::min<size_t>(size_t(nrhs), kBasisBudget / per_rhs)));
+    converged = true;
+    for (int g0 = 0; g0 < nrhs; g0 += G) {
+      const int ng = std::min(G, nrhs - g0);
+      void* bg = b64.as<double2>() + size_t(g0) * len;
+      void* xg = x64.as<double2>() + size_t(g0) * len;
+      gss.emplace_back();
+      SolveStats& ss = gss.back();
+      bool c = false;
+      if (h.inner == QMG_F64) solve_f64(h, bg, xg, ng, tol, max_outer, false, stream, ss, c);
+      else if (h.inner == QMG_F32) solve_mixed<float2>(h, bg, xg, ng, tol, max_outer, stream, ss, c);
+      else if (h.inner == QMG_BF16) solve_mixed<cbf16>(h, bg, xg, ng, tol, max_outer, stream, ss, c);
+      else solve_mixed<chalf>(h, bg, xg, ng, tol, max_outer, stream, ss, c);
+      converged = converged && c;
+    }
     // true residual in FP64
     WilsonOp D(h.g, QMG_F64, h.U64.p, h.A64.p);
     D.apply(x64.p, r64.p, nrhs, stream);
@@ -1713,6 +1743,8 @@ qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, 
   });
   if (info) {
     for (int i = 0; i < nrhs; ++i) {
+      const size_t gi = size_t(i / G);
+      const SolveStats ss = gi < gss.size() ? gss[gi] : SolveStats{};
       info[i].outer_iters = int(ss.outer);
       info[i].refinements = int(ss.refinements);
       info[i].coarse_iters = int(ss.coarse);
@@ -2010,6 +2042,27 @@ qmg_status qmg_timing_calls(const char* family, int64_t* calls) {
     check_ptr(family, "family");
     check_ptr(calls, "calls");
     *calls = timing_calls(family);
+  });
+}
+
+qmg_status qmg_timing_list(char* buf, int32_t len) {
+  return guard([&] {
+    check_ptr(buf, "buf");
+    QMG_CHECK(len >= 1, QMG_EINVAL, "len must be >= 1");
+    const std::string names = timing_families();
+    QMG_CHECK(names.size() + 1 <= size_t(len), QMG_ESHAPE, "timing_list: %zu bytes needed", names.size() + 1);
+    std::memcpy(buf, names.c_str(), names.size() + 1);
+  });
+}
+
+qmg_status qmg_memory_trim(void) {
+  return guard([&] { dev_trim(); });
+}
+
+qmg_status qmg_memory_cached(int64_t* bytes) {
+  return guard([&] {
+    check_ptr(bytes, "bytes");
+    *bytes = int64_t(dev_cached());
   });
 }
 

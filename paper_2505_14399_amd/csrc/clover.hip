@@ -19,6 +19,7 @@
 // (links at x and seven neighbours, twelve 3 x 3 products), then one thread per (site,
 // chirality) assembles and packs the block.
 #include "qmg_internal.hpp"
+#include "timing.hpp"
 
 namespace qmg {
 
@@ -214,10 +215,16 @@ void launch_clover_field(const Geom& g, const void* U64, double cs, double ct, v
   for (int q = 0; q < 4; ++q) pa.L[q] = g.L[q];
   pa.V = g.V;
   const unsigned nb = unsigned((g.V + 255) / 256);
-  k_clover_leaves<<<dim3(nb, 6), 256, 0, st>>>(static_cast<const double2*>(U64), F.as<double2>(), pa);
+  {
+    TimedLaunch tl_("setup/clover", st, double(g.V) * 6 * 9 * 16 * 4, 0.0);
+    launch(k_clover_leaves, dim3(nb, 6), dim3(256), 0, st, static_cast<const double2*>(U64), F.as<double2>(), pa);
+  }
   QMG_LAUNCH_CHECK();
   AssembleArgs aa{g.V, g.diag(), cs, ct};
-  k_clover_assemble<<<dim3(nb, 2), 256, 0, st>>>(F.as<double2>(), static_cast<double2*>(A64), aa);
+  {
+    TimedLaunch tl_("setup/clover", st, double(g.V) * (6 * 9 + 36) * 16, 0.0);
+    launch(k_clover_assemble, dim3(nb, 2), dim3(256), 0, st, F.as<double2>(), static_cast<double2*>(A64), aa);
+  }
   QMG_LAUNCH_CHECK();
   QMG_HIP(hipStreamSynchronize(st));  // F is released on return
 }

@@ -317,7 +317,11 @@ void build_coarse_eo_blocks(HierarchyDev& h, hipStream_t st) {
   if (lds > 64 * 1024)
     QMG_HIP(hipFuncSetAttribute((const void*)k_coarse_eo_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 int(lds)));
-  k_coarse_eo_blocks<<<d, 256, lds, st>>>(h.Y64.as<double2>(), h.Yh64.as<double2>(), m, flag.as<int>());
+  {
+    TimedLaunch tl_("setup/coarse_eo_blocks", st, double(d) * 18 * m * m * 16, 0.0);
+    launch(k_coarse_eo_blocks, dim3(d), dim3(256), lds, st, h.Y64.as<double2>(), h.Yh64.as<double2>(), m,
+           flag.as<int>());
+  }
   QMG_LAUNCH_CHECK();
   int fl[4] = {0, 0, 0, 0};
   QMG_HIP(hipMemcpyAsync(fl, flag.p, sizeof(fl), hipMemcpyDeviceToHost, st));
@@ -386,8 +390,11 @@ void launch_coarse_eo_split(qmg_prec prec, const HierarchyDev& h, const void* fu
   const size_t n = size_t(nrhs) * d * m;
   dispatch_ceo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_coarse_eo_split<S><<<nblk256(n), 256, 0, st>>>(static_cast<const S*>(full), static_cast<S*>(ev),
-                                                     static_cast<S*>(od), h.ceo_tab.as<int>(), d, m, n);
+    {
+      TimedLaunch tl_("coarse_eo_layout", st, 2.0 * double(n) * sizeof(S), 0.0);
+      launch(k_coarse_eo_split<S>, dim3(nblk256(n)), dim3(256), 0, st, static_cast<const S*>(full),
+             static_cast<S*>(ev), static_cast<S*>(od), h.ceo_tab.as<int>(), d, m, n);
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -398,8 +405,11 @@ void launch_coarse_eo_merge(qmg_prec prec, const HierarchyDev& h, const void* ev
   const size_t n = size_t(nrhs) * d * m;
   dispatch_ceo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_coarse_eo_merge<S><<<nblk256(n), 256, 0, st>>>(static_cast<const S*>(ev), static_cast<const S*>(od),
-                                                     static_cast<S*>(full), h.ceo_tab.as<int>(), d, m, n);
+    {
+      TimedLaunch tl_("coarse_eo_layout", st, 2.0 * double(n) * sizeof(S), 0.0);
+      launch(k_coarse_eo_merge<S>, dim3(nblk256(n)), dim3(256), 0, st, static_cast<const S*>(ev),
+             static_cast<const S*>(od), static_cast<S*>(full), h.ceo_tab.as<int>(), d, m, n);
+    }
   });
   QMG_LAUNCH_CHECK();
 }

@@ -11,6 +11,7 @@
 #include <cstring>
 
 #include "qmg_internal.hpp"
+#include "timing.hpp"
 
 namespace qmg {
 
@@ -234,8 +235,10 @@ __global__ void k_eo_merge_add(const S* __restrict__ even, const S* __restrict__
 // s-step residual minimisation over a Krylov basis p_0 .. p_{m-1} (m <= kSMax; vector i of rhs r
 // at P[(i * nrhs + r) * len]): with p_{j+1} = A p_j, the x = sum_j c_j p_j minimising
 // ||p_0 - A x|| solves the normal equations sum_j <p_{i+1}, p_{j+1}> c_j = <p_{i+1}, p_0>.  One
-// pass forms every inner product <p_i, p_j> (i <= j): per-thread sums in the accumulation
-// precision of S, FP64 across threads and workgroups.
+// pass forms every inner product <p_i, p_j> (i <= j), accumulated in FP64 for every storage
+// type: the normal equations square the condition number of the basis, and FP32 sums (relative
+// error ~1e-7 times the terms per thread) left only the first few basis directions resolvable,
+// which weakened the FP32 K-cycle's smoother (more outer iterations than the FP64 path).
 constexpr int kSMax = 9;
 constexpr int kPairs = kSMax * (kSMax + 1) / 2;
 
@@ -244,14 +247,16 @@ __global__ __launch_bounds__(256) void k_sstep_gram(const S* __restrict__ P, int
                                                     double2* __restrict__ part) {
   using C = ctype<S>;
   const int r = blockIdx.y;
-  cplx<C> acc[kPairs];
+  cplx<double> acc[kPairs];
 #pragma unroll
-  for (int q = 0; q < kPairs; ++q) acc[q] = {C(0), C(0)};
+  for (int q = 0; q < kPairs; ++q) acc[q] = {0.0, 0.0};
   for (size_t e = size_t(blockIdx.x) * 256 + threadIdx.x; e < len; e += size_t(gridDim.x) * 256) {
-    cplx<C> v[kSMax];
+    cplx<double> v[kSMax];
 #pragma unroll
-    for (int i = 0; i < kSMax; ++i)
-      v[i] = i < m ? ldc(P, (size_t(i) * nrhs + r) * len + e) : cplx<C>{C(0), C(0)};
+    for (int i = 0; i < kSMax; ++i) {
+      const cplx<C> t = i < m ? ldc(P, (size_t(i) * nrhs + r) * len + e) : cplx<C>{C(0), C(0)};
+      v[i] = {double(t.re), double(t.im)};
+    }
     int q = 0;
 #pragma unroll
     for (int i = 0; i < kSMax; ++i)
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(256) void k_sstep_gram(const S* __restrict__ P, int
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < kPairs; ++q) {
-    double re = double(acc[q].re), im = double(acc[q].im);
+    double re = acc[q].re, im = acc[q].im;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       re += __shfl_xor(re, off);
@@ -399,8 +404,11 @@ void launch_eo_pack_gauge(const Geom& g, const void* canon, void* out, qmg_prec 
   const size_t n = size_t(36) * g.V;
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_eo_pack_gauge<S><<<nblk(n), 256, 0, st>>>(static_cast<const double2*>(canon), static_cast<S*>(out), eo_geom(g),
-                                                n);
+    {
+      TimedLaunch tl_("layout/eo_gauge", st, double(n) * (16.0 + sizeof(S)), 0.0);
+      launch(k_eo_pack_gauge<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const double2*>(canon),
+             static_cast<S*>(out), eo_geom(g), n);
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -410,8 +418,11 @@ void launch_eo_pack_spinor(const Geom& g, const void* canon, void* even, void* o
   const size_t n = size_t(12) * g.V * nrhs;
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_eo_pack_spinor<S><<<nblk(n), 256, 0, st>>>(static_cast<const double2*>(canon), static_cast<S*>(even),
-                                                 static_cast<S*>(odd), eo_geom(g), n);
+    {
+      TimedLaunch tl_("layout/eo_spinor", st, double(n) * (16.0 + sizeof(S)), 0.0);
+      launch(k_eo_pack_spinor<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const double2*>(canon),
+             static_cast<S*>(even), static_cast<S*>(odd), eo_geom(g), n);
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -421,8 +432,11 @@ void launch_eo_unpack_spinor(const Geom& g, const void* even, const void* odd, v
   const size_t n = size_t(12) * g.V * nrhs;
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_eo_unpack_spinor<S><<<nblk(n), 256, 0, st>>>(static_cast<const S*>(even), static_cast<const S*>(odd),
-                                                   static_cast<double2*>(canon), eo_geom(g), n);
+    {
+      TimedLaunch tl_("layout/eo_spinor", st, double(n) * (16.0 + sizeof(S)), 0.0);
+      launch(k_eo_unpack_spinor<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const S*>(even),
+             static_cast<const S*>(odd), static_cast<double2*>(canon), eo_geom(g), n);
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -432,8 +446,11 @@ void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_
   const size_t n = size_t(36) * g.V;
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_eo_gauge_from_native<S><<<nblk(n), 256, 0, st>>>(static_cast<const double2*>(U64), static_cast<S*>(out),
-                                                        eo_geom(g), n, ne);
+    {
+      TimedLaunch tl_("layout/eo_gauge", st, double(n) * (16.0 + sizeof(S)), 0.0);
+      launch(k_eo_gauge_from_native<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const double2*>(U64),
+             static_cast<S*>(out), eo_geom(g), n, ne);
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -441,8 +458,11 @@ void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_
 double launch_su3_row_defect(const Geom& g, const void* U64, hipStream_t st) {
   DevBuf m(sizeof(unsigned long long));
   QMG_HIP(hipMemsetAsync(m.p, 0, sizeof(unsigned long long), st));
-  k_su3_row_defect<<<nblk(size_t(4) * g.V), 256, 0, st>>>(static_cast<const double2*>(U64), g.V,
-                                                           static_cast<unsigned long long*>(m.p));
+  {
+    TimedLaunch tl_("setup/su3_check", st, double(g.V) * 4 * 9 * 16, 0.0);
+    launch(k_su3_row_defect, dim3(nblk(size_t(4) * g.V)), dim3(256), 0, st, static_cast<const double2*>(U64), g.V,
+           static_cast<unsigned long long*>(m.p));
+  }
   QMG_LAUNCH_CHECK();
   unsigned long long bits = 0;
   QMG_HIP(hipMemcpyAsync(&bits, m.p, sizeof(bits), hipMemcpyDeviceToHost, st));
@@ -456,8 +476,11 @@ void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even,
   const size_t n = size_t(12) * g.V * nrhs;
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_eo_split<S><<<nblk(n), 256, 0, st>>>(static_cast<const S*>(full), static_cast<S*>(even), static_cast<S*>(odd),
-                                           eo_geom(g), n);
+    {
+      TimedLaunch tl_("eo_layout/split", st, 2.0 * double(n) * sizeof(S), 0.0);
+      launch(k_eo_split<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const S*>(full), static_cast<S*>(even),
+             static_cast<S*>(odd), eo_geom(g), n);
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -467,8 +490,11 @@ void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const v
   const size_t n = size_t(12) * g.V * nrhs;
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_eo_merge_add<S><<<nblk(n), 256, 0, st>>>(static_cast<const S*>(even), static_cast<const S*>(odd),
-                                               static_cast<S*>(full), eo_geom(g), n);
+    {
+      TimedLaunch tl_("eo_layout/merge", st, 3.0 * double(n) * sizeof(S), 0.0);
+      launch(k_eo_merge_add<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const S*>(even),
+             static_cast<const S*>(odd), static_cast<S*>(full), eo_geom(g), n);
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -480,12 +506,23 @@ void launch_sstep_coeffs(qmg_prec prec, const void* P, int m, size_t len, int nr
   part.ensure(size_t(nrhs) * (nblk + 1) * kPairs * sizeof(double2));  // partials, then the reduced pairs
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_sstep_gram<S><<<dim3(nblk, nrhs), 256, 0, st>>>(static_cast<const S*>(P), m, len, nrhs, part.as<double2>());
+    {
+      TimedLaunch tl_("sstep/gram", st, double(m + 1) * len * nrhs * sizeof(S), 0.0);
+      launch(k_sstep_gram<S>, dim3(nblk, nrhs), dim3(256), 0, st, static_cast<const S*>(P), m, len, nrhs,
+             part.as<double2>());
+    }
   });
   QMG_LAUNCH_CHECK();
-  k_sstep_reduce<<<nrhs, 1024, 0, st>>>(part.as<double2>(), nblk, part.as<double2>() + size_t(nrhs) * nblk * kPairs);
+  {
+    TimedLaunch tl_("sstep/reduce", st, double(nblk) * nrhs * kPairs * sizeof(double2), 0.0);
+    launch(k_sstep_reduce, dim3(nrhs), dim3(1024), 0, st, part.as<double2>(), nblk,
+           part.as<double2>() + size_t(nrhs) * nblk * kPairs);
+  }
   QMG_LAUNCH_CHECK();
-  k_sstep_solve<<<nrhs, 64, 0, st>>>(part.as<double2>() + size_t(nrhs) * nblk * kPairs, m, nrhs, c);
+  {
+    TimedLaunch tl_("sstep/solve", st, double(nrhs) * kPairs * sizeof(double2), 0.0);
+    launch(k_sstep_solve, dim3(nrhs), dim3(64), 0, st, part.as<double2>() + size_t(nrhs) * nblk * kPairs, m, nrhs, c);
+  }
   QMG_LAUNCH_CHECK();
 }
 
@@ -494,8 +531,12 @@ void launch_eo_site_term(const Geom& g, const void* A64, void* Aeo, void* Ainv, 
   QMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
   dispatch_eo(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_eo_site_term<S><<<dim3(unsigned((g.V + 127) / 128), 2), 128, 0, st>>>(
-        static_cast<const double2*>(A64), static_cast<S*>(Aeo), static_cast<S*>(Ainv), eo_geom(g), flag.as<int>());
+    {
+      TimedLaunch tl_("setup/eo_site_term", st, double(g.V) * 36 * (16.0 + 2 * sizeof(S)), 0.0);
+      launch(k_eo_site_term<S>, dim3(unsigned((g.V + 127) / 128), 2), dim3(128), 0, st,
+             static_cast<const double2*>(A64), static_cast<S*>(Aeo), static_cast<S*>(Ainv), eo_geom(g),
+             flag.as<int>());
+    }
   });
   QMG_LAUNCH_CHECK();
   int h = 0;

@@ -8,6 +8,7 @@
 #include <type_traits>
 
 #include "krylov.hpp"
+#include "timing.hpp"
 
 namespace qmg {
 
@@ -655,15 +656,24 @@ inline int small_nblk(size_t np) { return int(std::min<size_t>(kSmallBlk, std::m
 template <class S, int P>
 struct BlasP {
   static void zero(void* x, size_t n, hipStream_t st) {
-    k_zero<S, P><<<nb256(n / P), 256, 0, st>>>((S*)x, n / P);
+    {
+      TimedLaunch tl_("blas/zero", st, double(n) * sizeof(S), 0.0);
+      launch(k_zero<S, P>, dim3(nb256(n / P)), dim3(256), 0, st, (S*)x, n / P);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void copy(const void* x, void* y, size_t n, hipStream_t st) {
-    k_copy<S, P><<<nb256(n / P), 256, 0, st>>>((const S*)x, (S*)y, n / P);
+    {
+      TimedLaunch tl_("blas/copy", st, 2.0 * double(n) * sizeof(S), 0.0);
+      launch(k_copy<S, P>, dim3(nb256(n / P)), dim3(256), 0, st, (const S*)x, (S*)y, n / P);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void axpby(double a, const void* x, double b, void* y, size_t n, hipStream_t st) {
-    k_axpby<S, P><<<nb256(n / P), 256, 0, st>>>(a, (const S*)x, b, (S*)y, n / P);
+    {
+      TimedLaunch tl_("blas/axpby", st, 3.0 * double(n) * sizeof(S), 0.0);
+      launch(k_axpby<S, P>, dim3(nb256(n / P)), dim3(256), 0, st, a, (const S*)x, b, (S*)y, n / P);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void dot_multi(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
@@ -672,40 +682,65 @@ struct BlasP {
     const size_t np = len / P;
     const int nblk = pick_nblk(np, m * nrhs);
     rw.ensure(size_t(nblk) * m * nrhs, 0);
-    k_dot_partial<S, P><<<dim3(nblk, nrhs, m), RB, 0, st>>>((const S*)X, xstride / P, (const S*)w, np, nrhs, nblk,
-                                                             rw.partial.as<double2>());
+    {
+      TimedLaunch tl_("blas/dot", st, double(m + 1) * len * nrhs * sizeof(S), 0.0);
+      launch(k_dot_partial<S, P>, dim3(nblk, nrhs, m), dim3(RB), 0, st, (const S*)X, xstride / P, (const S*)w, np,
+             nrhs, nblk, rw.partial.as<double2>());
+    }
     QMG_LAUNCH_CHECK();
-    k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out, skip);
+    {
+      TimedLaunch tl_("blas/finalize", st, double(nblk) * (m + 1) * nrhs * sizeof(double2), 0.0);
+      launch(k_finalize2, dim3(m * nrhs), dim3(RB), 0, st, rw.partial.as<double2>(), nblk, out, skip);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void norm2(const void* w, size_t len, int nrhs, double* out, RedWork& rw, hipStream_t st) {
     const size_t np = len / P;
     const int nblk = pick_nblk(np, nrhs);
     rw.ensure(size_t(nblk) * nrhs, 0);
-    k_norm_partial<S, P><<<dim3(nblk, nrhs), RB, 0, st>>>((const S*)w, np, nblk, rw.partial.as<double2>());
+    {
+      TimedLaunch tl_("blas/norm", st, double(len) * nrhs * sizeof(S), 0.0);
+      launch(k_norm_partial<S, P>, dim3(nblk, nrhs), dim3(RB), 0, st, (const S*)w, np, nblk,
+             rw.partial.as<double2>());
+    }
     QMG_LAUNCH_CHECK();
-    k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out, nullptr);
+    {
+      TimedLaunch tl_("blas/finalize", st, double(nblk) * nrhs * sizeof(double2), 0.0);
+      launch(k_finalize1, dim3(nrhs), dim3(RB), 0, st, rw.partial.as<double2>(), nblk, out, nullptr);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void axpy_multi(const void* X, size_t xstride, int m, const double2* c, double sgn, void* w, size_t len,
                          int nrhs, hipStream_t st, const int* skip, const int* mcount) {
     const size_t np = len / P;
-    k_axpy_multi<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, c, sgn, (S*)w, np, nrhs,
-                                                               skip, mcount);
+    {
+      TimedLaunch tl_("blas/axpy_multi", st, double(m + 2) * len * nrhs * sizeof(S), 0.0);
+      launch(k_axpy_multi<S, P>, dim3(nb256(np), nrhs), dim3(256), 0, st, (const S*)X, xstride / P, m, c, sgn, (S*)w,
+             np, nrhs, skip, mcount);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void scale_dev(void* w, const double* n2, int mode, size_t len, int nrhs, hipStream_t st,
                         const int* skip) {
-    k_scale_dev<S, P><<<dim3(nb256(len / P), nrhs), 256, 0, st>>>((S*)w, n2, mode, len / P, skip);
+    {
+      TimedLaunch tl_("blas/scale", st, 2.0 * len * nrhs * sizeof(S), 0.0);
+      launch(k_scale_dev<S, P>, dim3(nb256(len / P), nrhs), dim3(256), 0, st, (S*)w, n2, mode, len / P, skip);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void scale_cdev(void* w, const double2* c, double sgn, size_t len, int nrhs, hipStream_t st) {
-    k_scale_cdev<S, P><<<dim3(nb256(len / P), nrhs), 256, 0, st>>>((S*)w, c, sgn, len / P);
+    {
+      TimedLaunch tl_("blas/scale", st, 2.0 * len * nrhs * sizeof(S), 0.0);
+      launch(k_scale_cdev<S, P>, dim3(nb256(len / P), nrhs), dim3(256), 0, st, (S*)w, c, sgn, len / P);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void caxpy_dev(const double2* c, double sgn, const void* y, void* x, size_t len, int nrhs,
                         hipStream_t st) {
-    k_caxpy_dev<S, P><<<dim3(nb256(len / P), nrhs), 256, 0, st>>>(c, sgn, (const S*)y, (S*)x, len / P);
+    {
+      TimedLaunch tl_("blas/caxpy", st, 3.0 * len * nrhs * sizeof(S), 0.0);
+      launch(k_caxpy_dev<S, P>, dim3(nb256(len / P), nrhs), dim3(256), 0, st, c, sgn, (const S*)y, (S*)x, len / P);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void mdot(const void* X, size_t xstride, int m, const void* w, size_t len, int nrhs, double2* out,
@@ -714,10 +749,16 @@ struct BlasP {
     const int ng = (m + MG - 1) / MG;
     const int nblk = pick_nblk(np, ng * nrhs);
     rw.ensure(size_t(nblk) * m * nrhs, 0);
-    k_mdot<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk,
-                                                       rw.partial.as<double2>(), skip);
+    {
+      TimedLaunch tl_("blas/mdot", st, double(m + 1) * len * nrhs * sizeof(S), 0.0);
+      launch(k_mdot<S, P>, dim3(nblk, nrhs, ng), dim3(RB), 0, st, (const S*)X, xstride / P, m, (const S*)w, np, nrhs,
+             nblk, rw.partial.as<double2>(), skip);
+    }
     QMG_LAUNCH_CHECK();
-    k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, out, skip);
+    {
+      TimedLaunch tl_("blas/finalize", st, double(nblk) * (m + 1) * nrhs * sizeof(double2), 0.0);
+      launch(k_finalize2, dim3(m * nrhs), dim3(RB), 0, st, rw.partial.as<double2>(), nblk, out, skip);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void axpy_then(int mode, const void* X, size_t xstride, int m, const double2* c, double sgn, void* w,
@@ -727,15 +768,27 @@ struct BlasP {
     rw.ensure(size_t(nblk) * std::max(m, 1) * nrhs, 0);
     const CoefSrc src{c, nullptr, 0, nullptr};
     if (mode == 0) {
-      k_axpy_then<S, 0, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride / P, m, src, sgn, (const S*)w,
-                                                                (S*)w, np, nrhs, nblk, rw.partial.as<double2>(), skip);
+      {
+        TimedLaunch tl_("blas/axpy_then", st, double(m + 2) * len * nrhs * sizeof(S), 0.0);
+        launch(k_axpy_then<S, 0, P>, dim3(nblk, nrhs, 1), dim3(RB), 0, st, (const S*)X, xstride / P, m, src, sgn,
+               (const S*)w, (S*)w, np, nrhs, nblk, rw.partial.as<double2>(), skip);
+      }
       QMG_LAUNCH_CHECK();
-      k_finalize2<<<m * nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, (double2*)out, skip);
+      {
+        TimedLaunch tl_("blas/finalize", st, double(nblk) * (m + 1) * nrhs * sizeof(double2), 0.0);
+        launch(k_finalize2, dim3(m * nrhs), dim3(RB), 0, st, rw.partial.as<double2>(), nblk, (double2*)out, skip);
+      }
     } else {
-      k_axpy_then<S, 1, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>((const S*)X, xstride / P, m, src, sgn, (const S*)w,
-                                                                (S*)w, np, nrhs, nblk, rw.partial.as<double2>(), skip);
+      {
+        TimedLaunch tl_("blas/axpy_then", st, double(m + 2) * len * nrhs * sizeof(S), 0.0);
+        launch(k_axpy_then<S, 1, P>, dim3(nblk, nrhs, 1), dim3(RB), 0, st, (const S*)X, xstride / P, m, src, sgn,
+               (const S*)w, (S*)w, np, nrhs, nblk, rw.partial.as<double2>(), skip);
+      }
       QMG_LAUNCH_CHECK();
-      k_finalize1<<<nrhs, RB, 0, st>>>(rw.partial.as<double2>(), nblk, (double*)out, skip);
+      {
+        TimedLaunch tl_("blas/finalize", st, double(nblk) * nrhs * sizeof(double2), 0.0);
+        launch(k_finalize1, dim3(nrhs), dim3(RB), 0, st, rw.partial.as<double2>(), nblk, (double*)out, skip);
+      }
     }
     QMG_LAUNCH_CHECK();
   }
@@ -747,18 +800,27 @@ struct BlasP {
     const int nblk = small ? small_nblk(np) : pick_nblk(np, ng * nrhs);
     rw.ensure(size_t(nblk) * (m + 1) * nrhs, size_t(nrhs));
     double2* part = rw.partial.as<double2>();
-    k_mdot_norm<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk,
-                                                            part, skip);
+    {
+      TimedLaunch tl_("blas/mdot_norm", st, double(m + 1) * len * nrhs * sizeof(S), 0.0);
+      launch(k_mdot_norm<S, P>, dim3(nblk, nrhs, ng), dim3(RB), 0, st, (const S*)X, xstride / P, m, (const S*)w, np,
+             nrhs, nblk, part, skip);
+    }
     QMG_LAUNCH_CHECK();
     CoefSrc src{h, nullptr, 0, nullptr};
     if (small) {
       src = CoefSrc{nullptr, part, nblk, h};
     } else {
-      k_finalize2<<<(m + 1) * nrhs, RB, 0, st>>>(part, nblk, h, skip);
+      {
+        TimedLaunch tl_("blas/finalize", st, double(nblk) * (m + 1) * nrhs * sizeof(double2), 0.0);
+        launch(k_finalize2, dim3((m + 1) * nrhs), dim3(RB), 0, st, part, nblk, h, skip);
+      }
       QMG_LAUNCH_CHECK();
     }
-    k_axpy_scale<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((const S*)X, xstride / P, m, src, (S*)w, np, nrhs, n2,
-                                                               gf, skip);
+    {
+      TimedLaunch tl_("blas/axpy_scale", st, double(m + 2) * len * nrhs * sizeof(S), 0.0);
+      launch(k_axpy_scale<S, P>, dim3(nb256(np), nrhs), dim3(256), 0, st, (const S*)X, xstride / P, m, src, (S*)w, np,
+             nrhs, n2, gf, skip);
+    }
     QMG_LAUNCH_CHECK();
   }
   static void cgs2_small(const void* X, size_t xstride, int m, void* w, size_t len, int nrhs, double2* h1,
@@ -773,19 +835,31 @@ struct BlasP {
     double2* pb = rw.partial2.as<double2>();
     S* wtmp = reinterpret_cast<S*>(pb + size_t(nblk) * m * nrhs);
     // pass 1: partials of X^dag w
-    k_mdot<S, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>((const S*)X, xstride / P, m, (const S*)w, np, nrhs, nblk, pa,
-                                                       skip);
+    {
+      TimedLaunch tl_("blas/mdot", st, double(m + 1) * len * nrhs * sizeof(S), 0.0);
+      launch(k_mdot<S, P>, dim3(nblk, nrhs, ng), dim3(RB), 0, st, (const S*)X, xstride / P, m, (const S*)w, np, nrhs,
+             nblk, pa, skip);
+    }
     QMG_LAUNCH_CHECK();
     // w' = w - X h1 (h1 summed from pa) into wtmp, partials of X^dag w' into pb
-    k_axpy_then<S, 0, P><<<dim3(nblk, nrhs, ng), RB, 0, st>>>(
-        (const S*)X, xstride / P, m, CoefSrc{nullptr, pa, nblk, h1}, -1.0, (const S*)w, wtmp, np, nrhs, nblk, pb, skip);
+    {
+      TimedLaunch tl_("blas/axpy_then", st, double(m + 2) * len * nrhs * sizeof(S), 0.0);
+      launch(k_axpy_then<S, 0, P>, dim3(nblk, nrhs, ng), dim3(RB), 0, st, (const S*)X, xstride / P, m,
+             CoefSrc{nullptr, pa, nblk, h1}, -1.0, (const S*)w, wtmp, np, nrhs, nblk, pb, skip);
+    }
     QMG_LAUNCH_CHECK();
     // w = w' - X h2 (h2 summed from pb), partial |w|^2 into pa
-    k_axpy_then<S, 1, P><<<dim3(nblk, nrhs, 1), RB, 0, st>>>(
-        (const S*)X, xstride / P, m, CoefSrc{nullptr, pb, nblk, h2}, -1.0, (const S*)wtmp, (S*)w, np, nrhs, nblk, pa, skip);
+    {
+      TimedLaunch tl_("blas/axpy_then", st, double(m + 2) * len * nrhs * sizeof(S), 0.0);
+      launch(k_axpy_then<S, 1, P>, dim3(nblk, nrhs, 1), dim3(RB), 0, st, (const S*)X, xstride / P, m,
+             CoefSrc{nullptr, pb, nblk, h2}, -1.0, (const S*)wtmp, (S*)w, np, nrhs, nblk, pa, skip);
+    }
     QMG_LAUNCH_CHECK();
-    k_scale_norm<S, P><<<dim3(nb256(np), nrhs), 256, 0, st>>>((S*)w, CoefSrc{nullptr, pa, nblk, nullptr}, np, nrhs,
-                                                              n2, skip);
+    {
+      TimedLaunch tl_("blas/scale", st, 2.0 * len * nrhs * sizeof(S), 0.0);
+      launch(k_scale_norm<S, P>, dim3(nb256(np), nrhs), dim3(256), 0, st, (S*)w, CoefSrc{nullptr, pa, nblk, nullptr},
+             np, nrhs, n2, skip);
+    }
     QMG_LAUNCH_CHECK();
   }
 };
@@ -1017,7 +1091,7 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
                                           Precond* M) {
   // FP64 keeps two Gram-Schmidt passes (parity with the FP64 reference to ~1e-12); lower
   // storage precisions use one pass with the Pythagorean norm, which halves the basis traffic
-  constexpr bool kCgs2 = std::is_same<S, double2>::value;
+  const bool kCgs2 = cgs2_;
   // with a tolerance the host reads the convergence estimates once per kBatch Arnoldi steps
   // (steps past the converged one are discarded); without one (fixed step count) the cycle
   // runs without any host round trip: rotations and the small triangular solve are on the device
@@ -1063,10 +1137,17 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
     const double* nb2 = first_cycle ? (x_zero ? nrm : nb) : nullptr;
     if (packable_vec<S>(len, V)) {
       constexpr int P = kPack<S>;
-      k_gv_start<S, P><<<dim3(unsigned((len / P + 255) / 256), nrhs), 256, 0, st>>>(V, nrm, len / P, gst, m, nb2,
-                                                                                     conv);
+      {
+        TimedLaunch tl_("krylov/givens", st, double(len) * nrhs * sizeof(S), 0.0);
+        launch(k_gv_start<S, P>, dim3(unsigned((len / P + 255) / 256), nrhs), dim3(256), 0, st, V, nrm, len / P, gst,
+               m, nb2, conv);
+      }
     } else {
-      k_gv_start<S, 1><<<dim3(unsigned((len + 255) / 256), nrhs), 256, 0, st>>>(V, nrm, len, gst, m, nb2, conv);
+      {
+        TimedLaunch tl_("krylov/givens", st, double(len) * nrhs * sizeof(S), 0.0);
+        launch(k_gv_start<S, 1>, dim3(unsigned((len + 255) / 256), nrhs), dim3(256), 0, st, V, nrm, len, gst, m, nb2,
+               conv);
+      }
     }
     QMG_LAUNCH_CHECK();
   };
@@ -1110,7 +1191,11 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
         fused = Blas<S>::cgs1_step(V, vs, j + 1, vn, len, nrhs, h1, cn, rw_, st, gst, m, col + est_off, tol, conv);
       }
       if (!fused) {
-        k_gv_step<<<nrhs, 64, 0, st>>>(gst, m, nrhs, j, col, kCgs2 ? 1 : 0, col + est_off, tol, conv);
+        {
+          TimedLaunch tl_("krylov/givens", st, 0.0, 0.0);
+          launch(k_gv_step, dim3(nrhs), dim3(64), 0, st, gst, m, nrhs, j, col, kCgs2 ? 1 : 0, col + est_off, tol,
+                 conv);
+        }
         QMG_LAUNCH_CHECK();
       }
       jdone = j + 1;
@@ -1154,7 +1239,10 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
     if (jdone > 0) {
       // x += V y with y = R^-1 g over the accepted columns (zero beyond each rhs's last valid one)
       int* nvd = reinterpret_cast<int*>(yd + size_t(m + 1) * nrhs);
-      k_gv_solve<<<nrhs, 64, 0, st>>>(gst, m, nrhs, jdone, yd, nvd);
+      {
+        TimedLaunch tl_("krylov/givens", st, 0.0, 0.0);
+        launch(k_gv_solve, dim3(nrhs), dim3(64), 0, st, gst, m, nrhs, jdone, yd, nvd);
+      }
       QMG_LAUNCH_CHECK();
       Blas<S>::axpy_multi(M ? Z : V, vs, jdone, yd, 1.0, x, len, nrhs, st, nullptr, nvd);
     }

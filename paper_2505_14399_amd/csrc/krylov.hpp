@@ -7,6 +7,8 @@
 // except the one that reads the small Hessenberg column for the convergence test.
 #pragma once
 
+#include <type_traits>
+
 #include "qmg_internal.hpp"
 
 namespace qmg {
@@ -112,8 +114,12 @@ class Gmres {
   // applications (the solution is updated with the z_j).
   Result solve(LinOp& A, const void* b, void* x, bool x_zero, int nrhs, int restart, int max_iter, double tol,
                hipStream_t st, int* conv = nullptr, int first_check = 0, Precond* M = nullptr);
+  // Arnoldi orthogonalisation: two classical Gram-Schmidt passes (default in FP64) or one pass
+  // with the norm from Pythagoras (default below FP64)
+  void set_cgs2(bool on) { cgs2_ = on; }
 
  private:
+  bool cgs2_ = std::is_same<S, double2>::value;
   void ensure(size_t len, int nrhs, int restart);
   DevBuf V_, Z_, H_, h1_, h2_, nrm_, y_, r_, cols_, gst_;
   PinnedBuf hb_;

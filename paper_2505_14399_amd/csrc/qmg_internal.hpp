@@ -226,6 +226,13 @@ struct Blocking {
 // ----------------------------------------------------------------------------------------
 // device memory owned by the library
 
+// the library's device allocator (alloc.hip): a per-device cache of freed blocks in front of
+// hipMalloc; dev_free waits for the device before a block can be handed out again
+void* dev_alloc(size_t n);  // throws ENOMEM
+void dev_free(void* p);
+void dev_trim();            // release the cache of the current device
+size_t dev_cached();        // bytes held by the cache of the current device
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -242,17 +249,12 @@ struct DevBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) return;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) {
-      p = nullptr;
-      set_error("hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
-      throw Error{QMG_ENOMEM};
-    }
+    p = dev_alloc(n);
     bytes = n;
   }
   void ensure(size_t n) { if (n > bytes) alloc(n); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
     bytes = 0;
   }

@@ -118,6 +118,16 @@ int64_t timing_calls(const char* family) {
   return n;
 }
 
+std::string timing_families() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::string out;
+  for (auto& kv : g_fam) {
+    if (!out.empty()) out += '\n';
+    out += kv.first;
+  }
+  return out;
+}
+
 void timing_query(const char* family, int64_t* n, double* ms, double* bytes, double* flops) {
   std::lock_guard<std::mutex> lk(g_mu);
   *n = 0;

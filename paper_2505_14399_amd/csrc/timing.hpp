@@ -3,6 +3,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <string>
+
 #include "qmg_internal.hpp"
 
 namespace qmg {
@@ -11,6 +13,7 @@ bool timing_on();
 void timing_enable(int every);  // 0: off; n >= 1: time every n-th launch of each family
 void timing_query(const char* family, int64_t* n, double* ms, double* bytes, double* flops);
 int64_t timing_calls(const char* family);  // every launch since timing was enabled, timed or not
+std::string timing_families();              // newline-separated names of the families launched
 
 // RAII scope around one instrumented launch; events exist only while timing is enabled.
 // With kernel = true (default) the pair is attached to the next kernel started through

@@ -991,26 +991,39 @@ void build_coarse(HierarchyDev& h, hipStream_t st) {
 
 void launch_chiral_gather(const HierarchyDev& h, const void* fine, void* blocks, int r, hipStream_t st) {
   dim3 grid(cdiv(h.blk.N, 256), r, 2 * h.blk.d);
-  k_chiral_gather<<<grid, 256, 0, st>>>((const double2*)fine, (double2*)blocks, h.bsite.as<int>(), h.blk.nd,
-                                        h.blk.N, r, h.g.V);
+  {
+    TimedLaunch tl_("setup/gather", st, double(r) * h.g.V * 12 * 2 * 16, 0.0);
+    launch(k_chiral_gather, dim3(grid), dim3(256), 0, st, (const double2*)fine, (double2*)blocks, h.bsite.as<int>(),
+           h.blk.nd, h.blk.N, r, h.g.V);
+  }
   QMG_LAUNCH_CHECK();
 }
 
 void launch_export_P(const HierarchyDev& h, void* out, hipStream_t st) {
   const size_t n = size_t(h.blk.d) * 2 * h.blk.N * h.k;
-  k_export_P<<<cdiv(n, 256), 256, 0, st>>>(h.P64.as<double2>(), (double2*)out, h.blk.nd, h.blk.N, h.k, n);
+  {
+    TimedLaunch tl_("export", st, 2.0 * double(n) * 16, 0.0);
+    launch(k_export_P, dim3(cdiv(n, 256)), dim3(256), 0, st, h.P64.as<double2>(), (double2*)out, h.blk.nd, h.blk.N,
+           h.k, n);
+  }
   QMG_LAUNCH_CHECK();
 }
 
 void launch_export_Y(const HierarchyDev& h, void* out, hipStream_t st) {
   const int m = 2 * h.k;
   const size_t n = size_t(h.blk.d) * 9 * m * m;
-  k_export_Y<<<cdiv(n, 256), 256, 0, st>>>(h.Y64.as<double2>(), (double2*)out, m, n);
+  {
+    TimedLaunch tl_("export", st, 2.0 * double(n) * 16, 0.0);
+    launch(k_export_Y, dim3(cdiv(n, 256)), dim3(256), 0, st, h.Y64.as<double2>(), (double2*)out, m, n);
+  }
   QMG_LAUNCH_CHECK();
 }
 
 void launch_philox_native(const Geom& g, uint64_t seed, int v0, int n, void* out, hipStream_t st) {
-  k_philox<<<dim3(cdiv(g.V, 256), n), 256, 0, st>>>((double2*)out, seed, v0, g.V);
+  {
+    TimedLaunch tl_("setup/philox", st, double(n) * g.V * 12 * 16, 0.0);
+    launch(k_philox, dim3(cdiv(g.V, 256), n), dim3(256), 0, st, (double2*)out, seed, v0, g.V);
+  }
   QMG_LAUNCH_CHECK();
 }
 
@@ -1031,9 +1044,11 @@ void launch_link_force(const Geom& g, const void* x, const void* lam, void* dU, 
     QMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gamma), gm, sizeof(gm)));
     init = true;
   }
-  k_link_force<<<dim3(cdiv(g.V, 256), 4), 256, 0, st>>>((const double2*)x, (const double2*)lam, (double2*)dU,
-                                                         g.L[0], g.L[1], g.L[2], g.L[3], g.bc_t, g.cw(0), g.cw(3),
-                                                         nrhs, g.V);
+  {
+    TimedLaunch tl_("force", st, double(g.V) * (nrhs * 48.0 + 72.0) * 8, 0.0);
+    launch(k_link_force, dim3(cdiv(g.V, 256), 4), dim3(256), 0, st, (const double2*)x, (const double2*)lam,
+           (double2*)dU, g.L[0], g.L[1], g.L[2], g.L[3], g.bc_t, g.cw(0), g.cw(3), nrhs, g.V);
+  }
   QMG_LAUNCH_CHECK();
 }
 
@@ -1044,7 +1059,10 @@ void launch_pack_spinor(const void* canon, qmg_prec pc, void* native, qmg_prec p
     using Sc = decltype(tc);
     dispatch_prec(pn, [&](auto tn) {
       using Sn = decltype(tn);
-      k_pack_spinor<Sc, Sn><<<cdiv(n, 256), 256, 0, st>>>((const Sc*)canon, (Sn*)native, V, n);
+      {
+        TimedLaunch tl_("layout/spinor", st, double(n) * (sizeof(Sc) + sizeof(Sn)), 0.0);
+        launch(k_pack_spinor<Sc, Sn>, dim3(cdiv(n, 256)), dim3(256), 0, st, (const Sc*)canon, (Sn*)native, V, n);
+      }
     });
   });
   QMG_LAUNCH_CHECK();
@@ -1056,7 +1074,10 @@ void launch_unpack_spinor(const void* native, qmg_prec pn, void* canon, qmg_prec
     using Sn = decltype(tn);
     dispatch_prec(pc, [&](auto tc) {
       using Sc = decltype(tc);
-      k_unpack_spinor<Sn, Sc><<<cdiv(n, 256), 256, 0, st>>>((const Sn*)native, (Sc*)canon, V, n);
+      {
+        TimedLaunch tl_("layout/spinor", st, double(n) * (sizeof(Sc) + sizeof(Sn)), 0.0);
+        launch(k_unpack_spinor<Sn, Sc>, dim3(cdiv(n, 256)), dim3(256), 0, st, (const Sn*)native, (Sc*)canon, V, n);
+      }
     });
   });
   QMG_LAUNCH_CHECK();
@@ -1065,7 +1086,10 @@ void launch_pack_gauge(const void* canon, void* native, qmg_prec prec, int V, hi
   const size_t n = size_t(4) * V * 9;
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_pack_gauge<S><<<cdiv(n, 256), 256, 0, st>>>((const double2*)canon, (S*)native, V, n);
+    {
+      TimedLaunch tl_("layout/gauge", st, double(n) * (16.0 + sizeof(S)), 0.0);
+      launch(k_pack_gauge<S>, dim3(cdiv(n, 256)), dim3(256), 0, st, (const double2*)canon, (S*)native, V, n);
+    }
   });
   QMG_LAUNCH_CHECK();
 }
@@ -1075,7 +1099,10 @@ void launch_convert(const void* in, qmg_prec pin, void* out, qmg_prec pout, size
     using Si = decltype(ti);
     dispatch_prec(pout, [&](auto to) {
       using So = decltype(to);
-      k_convert<Si, So><<<cdiv(n, 256), 256, 0, st>>>((const Si*)in, (So*)out, n);
+      {
+        TimedLaunch tl_("layout/convert", st, double(n) * (sizeof(Si) + sizeof(So)), 0.0);
+        launch(k_convert<Si, So>, dim3(cdiv(n, 256)), dim3(256), 0, st, (const Si*)in, (So*)out, n);
+      }
     });
   });
   QMG_LAUNCH_CHECK();
@@ -1084,14 +1111,20 @@ void launch_convert(const void* in, qmg_prec pin, void* out, qmg_prec pout, size
 // ---------------------------------------------------------------------------------------
 // third level: launchers
 void launch_philox_coarse(uint64_t seed, int v0, int n, int d, int m, int level, void* out, hipStream_t st) {
-  k_philox_coarse<<<dim3(cdiv(d, 256), n), 256, 0, st>>>((double2*)out, seed, v0, d, m, level);
+  {
+    TimedLaunch tl_("level/philox", st, double(n) * d * m * 16, 0.0);
+    launch(k_philox_coarse, dim3(cdiv(d, 256), n), dim3(256), 0, st, (double2*)out, seed, v0, d, m, level);
+  }
   QMG_LAUNCH_CHECK();
 }
 
 void launch_level_gather(const CoarseLevel& L, const void* v, void* blocks, int r, hipStream_t st) {
   const int d1 = L.d * L.nd;
-  k_level_gather<<<dim3(cdiv(L.N, 256), r, 2 * L.d), 256, 0, st>>>((const double2*)v, (double2*)blocks,
-                                                                    L.bsite.as<int>(), L.nd, L.k1, d1, r);
+  {
+    TimedLaunch tl_("level/gather", st, double(r) * d1 * L.k1 * 2 * 2 * 16, 0.0);
+    launch(k_level_gather, dim3(cdiv(L.N, 256), r, 2 * L.d), dim3(256), 0, st, (const double2*)v, (double2*)blocks,
+           L.bsite.as<int>(), L.nd, L.k1, d1, r);
+  }
   QMG_LAUNCH_CHECK();
 }
 
@@ -1102,8 +1135,8 @@ void launch_level_prolong(qmg_prec prec, const CoarseLevel& L, int d1, const voi
                  8.0 * 2.0 * L.d * L.k * L.N * nrhs);
   dispatch_prec(prec, [&](auto tag) {
     using S = decltype(tag);
-    k_level_prolong<S><<<dim3(cdiv(L.N, 256), 2 * L.d, nrhs), 256, 0, st>>>(
-        (const S*)P, (const S*)v2, (S*)v1, L.bsite.as<int>(), L.nd, L.k1, L.k, d1, L.d);
+    launch(k_level_prolong<S>, dim3(cdiv(L.N, 256), 2 * L.d, nrhs), dim3(256), 0, st, (const S*)P, (const S*)v2,
+           (S*)v1, L.bsite.as<int>(), L.nd, L.k1, L.k, d1, L.d);
   });
   QMG_LAUNCH_CHECK();
 }
@@ -1117,8 +1150,8 @@ void launch_level_restrict(qmg_prec prec, const CoarseLevel& L, int d1, const vo
     using S = decltype(tag);
     const size_t lds = size_t(L.N) * sizeof(cplx<ctype<S>>);
     QMG_CHECK(lds <= 64 * 1024, QMG_ESHAPE, "level restrict: block of %d rows too large", L.N);
-    k_level_restrict<S><<<dim3(2 * L.d, nrhs), 256, lds, st>>>((const S*)P, (const S*)v1, (S*)v2, L.bsite.as<int>(),
-                                                                 L.nd, L.k1, L.k, d1, L.d);
+    launch(k_level_restrict<S>, dim3(2 * L.d, nrhs), dim3(256), uint32_t(lds), st, (const S*)P, (const S*)v1,
+           (S*)v2, L.bsite.as<int>(), L.nd, L.k1, L.k, d1, L.d);
   });
   QMG_LAUNCH_CHECK();
 }
@@ -1150,14 +1183,21 @@ void build_level_coarse(CoarseLevel& L, const StencilRef& h, hipStream_t st) {
 
 void launch_level_export_P(const CoarseLevel& L, void* out, hipStream_t st) {
   const size_t n = size_t(2) * L.d * L.N * L.k;
-  k_level_export_P<<<cdiv(n, 256), 256, 0, st>>>(L.P64.as<double2>(), (double2*)out, L.nd, L.k1, L.k, n);
+  {
+    TimedLaunch tl_("export", st, 2.0 * double(n) * 16, 0.0);
+    launch(k_level_export_P, dim3(cdiv(n, 256)), dim3(256), 0, st, L.P64.as<double2>(), (double2*)out, L.nd, L.k1,
+           L.k, n);
+  }
   QMG_LAUNCH_CHECK();
 }
 
 void launch_level_export_Y(const CoarseLevel& L, void* out, hipStream_t st) {
   const int m = 2 * L.k;
   const size_t n = size_t(L.d) * 9 * m * m;
-  k_export_Y<<<cdiv(n, 256), 256, 0, st>>>(L.Y64.as<double2>(), (double2*)out, m, n);
+  {
+    TimedLaunch tl_("export", st, 2.0 * double(n) * 16, 0.0);
+    launch(k_export_Y, dim3(cdiv(n, 256)), dim3(256), 0, st, L.Y64.as<double2>(), (double2*)out, m, n);
+  }
   QMG_LAUNCH_CHECK();
 }
 
