@@ -492,6 +492,47 @@ double host_norm2(const void* dev, size_t n_complex, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------------------
+// s-step form of the smoothing GMRES(8) cycles (storage below FP64): per cycle, from the
+// residual r, the shifted basis p_0 = r, p_{i+1} = (D - d) p_i (d = m + 1 + 3/xi, the diagonal
+// term, which centres the spectrum and keeps the powers better conditioned; the Krylov space is
+// that of D) is formed with the same eight operator applications as eight GMRES steps, one pass
+// gives every <p_i, p_j>, and the 8 x 8 normal equations of min ||r - D sum_j c_j p_j|| are
+// solved in FP64 on the device: the minimisation of GMRES(8) over the same space, with one
+// reduction instead of eight Gram-Schmidt steps over a growing basis.  The next cycle's residual
+// r - sum_j c_j (p_{j+1} + d p_j) comes from the basis, without another operator application.
+template <class S>
+void smooth_sstep(const Geom& g, LinOp& D, LinOp* H, int r, int n_iter, const void* b, void* x, DevBuf& basis,
+                  DevBuf& coef, DevBuf& part, DevBuf& e, hipStream_t st) {
+  constexpr qmg_prec P = StoreTraits<S>::prec;
+  constexpr int s = 8;
+  const size_t len = size_t(12) * g.V, n = len * r, vb = n * sizeof(S);
+  const double d = g.diag();
+  basis.ensure((s + 1) * vb);
+  coef.ensure(size_t(s) * r * sizeof(double2));
+  e.ensure(vb);
+  auto vec = [&](int i) { return static_cast<char*>(basis.p) + size_t(i) * vb; };
+  Blas<S>::zero(x, n, st);
+  Blas<S>::copy(b, vec(0), n, st);
+  for (int cyc = 0; cyc < n_iter / s; ++cyc) {
+    for (int i = 0; i < s; ++i) {
+      if (H) {
+        H->apply(vec(i), vec(i + 1), r, st);  // the hopping part: D - d directly
+      } else {
+        D.apply(vec(i), vec(i + 1), r, st);
+        Blas<S>::axpby(-d, vec(i), 1.0, vec(i + 1), n, st);
+      }
+    }
+    launch_sstep_coeffs(P, basis.p, s + 1, len, r, coef.as<double2>(), part, st, d);
+    Blas<S>::zero(e.p, n, st);
+    Blas<S>::axpy_multi(basis.p, n, s, coef.as<double2>(), 1.0, e.p, len, r, st);  // e = sum_j c_j p_j
+    Blas<S>::axpby(1.0, e.p, 1.0, x, n, st);
+    if (cyc + 1 < n_iter / s) {  // r <- r - sum_j c_j p_{j+1} - d e
+      Blas<S>::axpy_multi(vec(1), n, s, coef.as<double2>(), -1.0, vec(0), len, r, st);
+      Blas<S>::axpby(-d, e.p, 1.0, vec(0), n, st);
+    }
+  }
+}
+
 // Eq. (2) smoothing of r test vectors held in native FP64 `phi` (in place: phi <- psi/|psi|),
 // computed in storage precision S.
 template <class S>
@@ -511,7 +552,17 @@ void smooth_native(const Geom& g, const void* Uin, const void* Ain, void* phi, i
     }
     D.apply(phi_in, b_in.p, r, st);                         // b = D phi
     Blas<S>::axpby(0.0, b_in.p, -1.0, b_in.p, n, st);      // b = -D phi
-    gm.solve(D, b_in.p, x_in.p, true, r, 8, n_iter, 0.0, st);  // D psi' = -D phi
+    if (P != QMG_F64 && n_iter % 8 == 0) {
+      // below FP64 the cycles run in s-step form; an FP64 setup keeps the Gram-Schmidt cycles
+      // that the CPU reference follows step by step
+      Geom gh = g;
+      gh.mass = -(1.0 + 3.0 / g.xi);  // diagonal term zero: the hopping part D - d
+      WilsonOp Hop(gh, P, Uin, nullptr);
+      DevBuf basis, coef, part, e;
+      smooth_sstep<S>(g, D, Ain ? nullptr : &Hop, r, n_iter, b_in.p, x_in.p, basis, coef, part, e, st);
+    } else {
+      gm.solve(D, b_in.p, x_in.p, true, r, 8, n_iter, 0.0, st);  // D psi' = -D phi
+    }
     if (P != QMG_F64) {
       launch_convert(x_in.p, P, tmp64.p, QMG_F64, n, st);
       Blas<double2>::axpby(1.0, tmp64.p, 1.0, phi, n, st);
@@ -2074,8 +2125,11 @@ qmg_status qmg_set_dslash_variant(int32_t v) {
   return guard([&] {
     const int z = v / 1000, nr = (v % 1000) / 100, tch = v % 100;
     const bool tw = v > 100 && z <= 1 && (nr == 2 || nr == 3) && (tch == 2 || tch == 4 || tch == 8);
-    QMG_CHECK(tw || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64, QMG_EINVAL,
-              "dslash variant must be 0, 1, 2, 4, 8, 16, 32, 64 or a multi-rhs t-walking code "
+    const bool hop_nr = v >= 501 && v <= 504;  // even-odd hop: 1 .. 4 right-hand sides per thread
+    QMG_CHECK(tw || hop_nr || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64,
+              QMG_EINVAL,
+              "dslash variant must be 0, 1, 2, 4, 8, 16, 32, 64, an even-odd hop code 500 + NR (NR in 1..4) or a "
+              "multi-rhs t-walking code "
               "1000 z + 100 NR + TCH (z in {0,1}, NR in {2,3}, TCH in {2,4,8})");
     set_dslash_variant(v);
   });

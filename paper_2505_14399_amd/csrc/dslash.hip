@@ -759,16 +759,19 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
 
 // out (parity p) = POST( YM(y) + sgn * H in ), H the hopping part of D (of D^dag with DAG),
 // in on parity 1 - p.  YM: 0 nothing, 1 y, 2 A_p y.  POST: 0 nothing, 1 A_p^-1.
-template <class S, bool DAG, int YM, int POST, int NE = 9>
+// Each thread forms NR right-hand sides rhs_base + NR g .. + NR - 1 of its site, so every link
+// is loaded once for all NR of them; the NR-groups of a tile are adjacent in the (XCD-aware)
+// workgroup order, so the groups of one tile run on one XCD and meet its links in that L2.
+template <class S, bool DAG, int YM, int POST, int NE = 9, int NR = 1>
 __global__ __launch_bounds__(kBlock) void k_hop_eo(const S* __restrict__ Ue, const S* __restrict__ Uo,
                                                    const S* __restrict__ in, const S* __restrict__ y,
                                                    S* __restrict__ out, const S* __restrict__ Ap,
-                                                   const S* __restrict__ Aip, DslashArgs a, int p, float sgn) {
+                                                   const S* __restrict__ Aip, DslashArgs a, int p, float sgn,
+                                                   int rhs_base, int ngroup) {
   using C = ctype<S>;
   const int Vh = a.V >> 1;
-  const int ntile = (Vh + kBlock - 1) / kBlock;
   const int wg = xcd_tile(blockIdx.x, gridDim.x);
-  const int tile = wg % ntile, rhs = wg / ntile;
+  const int tile = wg / ngroup, rhs = rhs_base + NR * (wg % ngroup);
   const int i = tile * kBlock + threadIdx.x;
   if (i >= Vh) return;
   const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
@@ -797,52 +800,64 @@ __global__ __launch_bounds__(kBlock) void k_hop_eo(const S* __restrict__ Ue, con
   }
   const C bt_f = (a.bc_t < 0 && t == L3 - 1) ? C(-1) : C(1);
   const C bt_b = (a.bc_t < 0 && t == 0) ? C(-1) : C(1);
-  cplx<C> acc[1][12];
+  cplx<C> w[NR][12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[0][k] = {C(0), C(0)};
-  const C mh = C(-0.5);
-  do_hop<S, false, 1, 0, true, DAG, NE>(Uown, in, acc, i, xp, rhs, Vh, mh * cw[0]);
-  do_hop<S, false, 1, 0, false, DAG, NE>(Uoth, in, acc, xm, xm, rhs, Vh, mh * cw[0]);
-  do_hop<S, false, 1, 1, true, DAG, NE>(Uown, in, acc, i, yp, rhs, Vh, mh * cw[1]);
-  do_hop<S, false, 1, 1, false, DAG, NE>(Uoth, in, acc, ym, ym, rhs, Vh, mh * cw[1]);
-  do_hop<S, false, 1, 2, true, DAG, NE>(Uown, in, acc, i, zp, rhs, Vh, mh * cw[2]);
-  do_hop<S, false, 1, 2, false, DAG, NE>(Uoth, in, acc, zm, zm, rhs, Vh, mh * cw[2]);
-  do_hop<S, false, 1, 3, true, DAG, NE>(Uown, in, acc, i, tp, rhs, Vh, mh * cw[3] * bt_f);
-  do_hop<S, false, 1, 3, false, DAG, NE>(Uoth, in, acc, tm, tm, rhs, Vh, mh * cw[3] * bt_b);
-  const C sg = C(sgn);
-  cplx<C> w[1][12];
+  for (int r = 0; r < NR; ++r)
 #pragma unroll
-  for (int k = 0; k < 12; ++k) w[0][k] = sg * acc[0][k];
+    for (int k = 0; k < 12; ++k) w[r][k] = {C(0), C(0)};
+  const C mh = C(-0.5) * C(sgn);
+  do_hop<S, false, NR, 0, true, DAG, NE>(Uown, in, w, i, xp, rhs, Vh, mh * cw[0]);
+  do_hop<S, false, NR, 0, false, DAG, NE>(Uoth, in, w, xm, xm, rhs, Vh, mh * cw[0]);
+  do_hop<S, false, NR, 1, true, DAG, NE>(Uown, in, w, i, yp, rhs, Vh, mh * cw[1]);
+  do_hop<S, false, NR, 1, false, DAG, NE>(Uoth, in, w, ym, ym, rhs, Vh, mh * cw[1]);
+  do_hop<S, false, NR, 2, true, DAG, NE>(Uown, in, w, i, zp, rhs, Vh, mh * cw[2]);
+  do_hop<S, false, NR, 2, false, DAG, NE>(Uoth, in, w, zm, zm, rhs, Vh, mh * cw[2]);
+  do_hop<S, false, NR, 3, true, DAG, NE>(Uown, in, w, i, tp, rhs, Vh, mh * cw[3] * bt_f);
+  do_hop<S, false, NR, 3, false, DAG, NE>(Uoth, in, w, tm, tm, rhs, Vh, mh * cw[3] * bt_b);
   if constexpr (YM == 1) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) w[0][k] += ldc(y, sp_idx<false>(rhs, k, i, Vh));
-  } else if constexpr (YM == 2) {
-    cplx<C> yv[1][12];
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int k = 0; k < 12; ++k) yv[0][k] = ldc(y, sp_idx<false>(rhs, k, i, Vh));
+      for (int k = 0; k < 12; ++k) w[r][k] += ldc(y, sp_idx<false>(rhs + r, k, i, Vh));
+  } else if constexpr (YM == 2) {
     if (Ap) {
-      clover_acc<S, 1>(Ap, i, Vh, yv, w);
+      cplx<C> yv[NR][12];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) yv[r][k] = ldc(y, sp_idx<false>(rhs + r, k, i, Vh));
+      clover_acc<S, NR>(Ap, i, Vh, yv, w);
     } else {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) w[0][k] += diag * yv[0][k];
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[r][k] += diag * ldc(y, sp_idx<false>(rhs + r, k, i, Vh));
     }
   }
   if constexpr (POST == 1) {
     if (Aip) {
-      cplx<C> r[1][12];
+      cplx<C> o[NR][12];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) r[0][k] = {C(0), C(0)};
-      clover_acc<S, 1>(Aip, i, Vh, w, r);
+      for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int k = 0; k < 12; ++k) w[0][k] = r[0][k];
+        for (int k = 0; k < 12; ++k) o[r][k] = {C(0), C(0)};
+      clover_acc<S, NR>(Aip, i, Vh, w, o);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[r][k] = o[r][k];
     } else {
       const C inv = C(1) / diag;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) w[0][k] = inv * w[0][k];
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[r][k] = inv * w[r][k];
     }
   }
 #pragma unroll
-  for (int k = 0; k < 12; ++k) stc(out, sp_idx<false>(rhs, k, i, Vh), w[0][k]);
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) stc(out, sp_idx<false>(rhs + r, k, i, Vh), w[r][k]);
 }
 
 // Rows I0 .. I0+2 of one chirality of the even-odd epilogue: x holds sgn H in (+ y with YM = 1)
@@ -1039,6 +1054,10 @@ void launch_dslash(qmg_prec prec, const void* U, const void* in, void* out, cons
   }
 }
 
+// right-hand sides per thread of the even-odd hop for several right-hand sides (links loaded
+// once for all of them)
+constexpr int kHopNR = 2;
+
 void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const void* Uo, int p, const void* in,
                    const void* y, void* out, const void* Ap, const void* Aip, int ym, int post, double sgn,
                    hipStream_t st) {
@@ -1054,7 +1073,15 @@ void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const voi
   const bool split =
       a.tchunk == 16 || (a.tchunk != 1 && with_site_term && long(Vh) * a.nrhs < (1L << 19));
   const int per_wg = split ? kBlock / 4 : kBlock;
-  const dim3 grid(unsigned((Vh + per_wg - 1) / per_wg) * unsigned(a.nrhs));
+  const unsigned ntile = unsigned((Vh + per_wg - 1) / per_wg);
+  const dim3 grid(ntile * unsigned(a.nrhs));
+  // right-hand sides per thread of the one-site-per-thread form: forced with the launch-variant
+  // codes 501 .. 504, else HOP_NR (FP32 storage and below) once there are enough of them
+  int nr = 1;
+  if (!split) {
+    if (a.tchunk >= 501 && a.tchunk <= 504) nr = a.tchunk - 500;
+    else if (prec != QMG_F64 && a.nrhs >= 2) nr = std::min(a.nrhs, kHopNR);
+  }
   // algorithmic traffic: the other parity's spinors and both parities' links once per site of
   // this parity, y when used, the output, and the packed blocks when used
   const double cb = double(prec_bytes(prec));
@@ -1068,6 +1095,18 @@ void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const voi
              static_cast<const S*>(in), static_cast<const S*>(y), static_cast<S*>(out), static_cast<const S*>(Ap),
              static_cast<const S*>(Aip), a, p, float(sgn));
     };
+    // one-site-per-thread form: full groups of NR right-hand sides, then the rest one per thread
+    auto run_nr = [&](auto k_nr, auto k_1) {
+      const int ng = a.nrhs / nr, done = ng * nr;
+      auto go1 = [&](auto kern, int base, int groups) {
+        launch(kern, dim3(ntile * unsigned(groups)), dim3(kBlock), 0, st, static_cast<const S*>(Ue),
+               static_cast<const S*>(Uo), static_cast<const S*>(in), static_cast<const S*>(y), static_cast<S*>(out),
+               static_cast<const S*>(Ap), static_cast<const S*>(Aip), a, p, float(sgn), base, groups);
+      };
+      if (nr > 1 && ng > 0) go1(k_nr, 0, ng);
+      if (nr == 1) go1(k_1, 0, a.nrhs);
+      else if (done < a.nrhs) go1(k_1, done, a.nrhs - done);
+    };
     const int form = ym * 2 + post;  // forms used by the Schur operator, the source and the reconstruction
     auto pick = [&](auto dag, auto ne) {
       constexpr bool D = decltype(dag)::value;
@@ -1077,12 +1116,23 @@ void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const voi
         else if (form == 4) run(k_hop_eo_dir<S, D, 2, 0, NE>);
         else if (form == 2) run(k_hop_eo_dir<S, D, 1, 0, NE>);
         else run(k_hop_eo_dir<S, D, 1, 1, NE>);
-      } else {
-        if (form == 1) run(k_hop_eo<S, D, 0, 1, NE>);
-        else if (form == 4) run(k_hop_eo<S, D, 2, 0, NE>);
-        else if (form == 2) run(k_hop_eo<S, D, 1, 0, NE>);
-        else run(k_hop_eo<S, D, 1, 1, NE>);
+        return;
       }
+      auto by_nr = [&](auto ym_c, auto post_c) {
+        constexpr int YM = decltype(ym_c)::value, PO = decltype(post_c)::value;
+        auto k1 = k_hop_eo<S, D, YM, PO, NE, 1>;
+        if (nr == 2) run_nr(k_hop_eo<S, D, YM, PO, NE, 2>, k1);
+        else if (nr == 3) run_nr(k_hop_eo<S, D, YM, PO, NE, 3>, k1);
+        else if (nr == 4) run_nr(k_hop_eo<S, D, YM, PO, NE, 4>, k1);
+        else run_nr(k1, k1);
+      };
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      using I2 = std::integral_constant<int, 2>;
+      if (form == 1) by_nr(I0{}, I1{});
+      else if (form == 4) by_nr(I2{}, I0{});
+      else if (form == 2) by_nr(I1{}, I0{});
+      else by_nr(I1{}, I1{});
     };
     using N9 = std::integral_constant<int, 9>;
     using N6 = std::integral_constant<int, 6>;

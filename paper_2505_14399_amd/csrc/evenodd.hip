@@ -320,20 +320,28 @@ __global__ __launch_bounds__(1024) void k_sstep_reduce(const double2* __restrict
 // of the 8 x 8 factor are predicated off, so it stays in registers); a pivot below 1e-13 of the
 // unit diagonal ends the factor and the remaining coefficients are zero (the basis vectors beyond
 // it add nothing resolvable)
+// With a shifted basis p_{j+1} = (A - d) p_j the images are w_j = A p_j = p_{j+1} + d p_j, and
+// the products <w_i, w_j>, <w_i, p_0> follow from the same inner products of the p's (d real;
+// d = 0 is the plain basis).
 __global__ __launch_bounds__(64) void k_sstep_solve(const double2* __restrict__ Gin, int m, int nrhs,
-                                                    double2* __restrict__ c) {
+                                                    double2* __restrict__ c, double d) {
   constexpr int kS = kSMax - 1;
   const int r = blockIdx.x;
   if (threadIdx.x != 0) return;
   const double2* G = Gin + size_t(r) * kPairs;
   const int s = m - 1;
-  auto inner = [&](int i, int j) {  // <p_i, p_j>
+  auto gp = [&](int i, int j) {  // <p_i, p_j>
     if (i <= j) {
       const double2 v = G[i * kSMax - i * (i - 1) / 2 + (j - i)];
       return cplx<double>{v.x, v.y};
     }
     const double2 v = G[j * kSMax - j * (j - 1) / 2 + (i - j)];
     return cplx<double>{v.x, -v.y};
+  };
+  // inner(i + 1, j + 1) = <w_i, w_j>, inner(i + 1, 0) = <w_i, p_0>
+  auto inner = [&](int i, int j) {
+    if (j == 0) return gp(i, 0) + d * gp(i - 1, 0);
+    return gp(i, j) + d * (gp(i, j - 1) + gp(i - 1, j)) + (d * d) * gp(i - 1, j - 1);
   };
   double dsc[kS];
 #pragma unroll
@@ -500,7 +508,7 @@ void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const v
 }
 
 void launch_sstep_coeffs(qmg_prec prec, const void* P, int m, size_t len, int nrhs, double2* c, DevBuf& part,
-                         hipStream_t st) {
+                         hipStream_t st, double shift) {
   QMG_CHECK(m >= 2 && m <= kSMax, QMG_EINVAL, "s-step basis of %d vectors (2 .. %d)", m, kSMax);
   const int nblk = int(std::max<size_t>(1, std::min<size_t>(512, len / (256 * 8))));
   part.ensure(size_t(nrhs) * (nblk + 1) * kPairs * sizeof(double2));  // partials, then the reduced pairs
@@ -521,7 +529,8 @@ void launch_sstep_coeffs(qmg_prec prec, const void* P, int m, size_t len, int nr
   QMG_LAUNCH_CHECK();
   {
     TimedLaunch tl_("sstep/solve", st, double(nrhs) * kPairs * sizeof(double2), 0.0);
-    launch(k_sstep_solve, dim3(nrhs), dim3(64), 0, st, part.as<double2>() + size_t(nrhs) * nblk * kPairs, m, nrhs, c);
+    launch(k_sstep_solve, dim3(nrhs), dim3(64), 0, st, part.as<double2>() + size_t(nrhs) * nblk * kPairs, m, nrhs, c,
+           shift);
   }
   QMG_LAUNCH_CHECK();
 }

@@ -364,11 +364,11 @@ void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even,
 void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const void* odd, void* full, int nrhs,
                          hipStream_t st);
 // s-step residual minimisation: c[j * nrhs + r] (device, j < m - 1) minimising
-// ||p_0 - sum_j c_j p_{j+1}|| over a basis p_0 .. p_{m-1} (m <= 9, vector i of rhs r at
-// P + (i * nrhs + r) * len, storage prec); with p_{j+1} = A p_j, x = sum_j c_j p_j minimises
-// ||p_0 - A x|| over the Krylov space.  part: work buffer (sized here)
+// ||p_0 - sum_j c_j w_j||, w_j = p_{j+1} + shift p_j, over a basis p_0 .. p_{m-1} (m <= 9, vector
+// i of rhs r at P + (i * nrhs + r) * len, storage prec); with p_{j+1} = (A - shift) p_j,
+// x = sum_j c_j p_j minimises ||p_0 - A x|| over the Krylov space.  part: work buffer (sized here)
 void launch_sstep_coeffs(qmg_prec prec, const void* P, int m, size_t len, int nrhs, double2* c, DevBuf& part,
-                         hipStream_t st);
+                         hipStream_t st, double shift = 0.0);
 // the full-lattice packed FP64 site term -> its half-lattice copy and inverse in prec (synchronises;
 // EBREAKDOWN if a block is singular)
 void launch_eo_site_term(const Geom& g, const void* A64, void* Aeo, void* Ainv, qmg_prec prec, hipStream_t st);
