@@ -1718,8 +1718,9 @@ qmg_status qmg_coarse_apply(const qmg_mg* mg, const void* in, void* out, int32_t
   });
 }
 
-// bytes the outer solver's Krylov bases of one group of right-hand sides may hold
-constexpr size_t kBasisBudget = size_t(24) << 30;
+// bytes the outer solver's Krylov bases of one group of right-hand sides may hold (four FP32
+// right-hand sides of 32^3 x 64: 26.6 GB)
+constexpr size_t kBasisBudget = size_t(28) << 30;
 
 qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, double tol, int32_t max_outer,
                         int32_t adjoint, qmg_solve_info* info, hipStream_t stream) {

@@ -372,11 +372,11 @@ void launch_coarse_eo_apply(qmg_prec prec, const HierarchyDev& h, int colour, co
              nbh, dh, m, nrhs, H, lo, ns, sgn);
     };
     if (m % PK == 0) {
-      if (nrhs >= 4) go(k_coarse_eo_apply<S, 4, PK>, 4, PK);
+      if (nrhs >= 3) go(k_coarse_eo_apply<S, 4, PK>, 4, PK);
       else if (nrhs == 2) go(k_coarse_eo_apply<S, 2, PK>, 2, PK);
       else go(k_coarse_eo_apply<S, 1, PK>, 1, PK);
     } else {
-      if (nrhs >= 4) go(k_coarse_eo_apply<S, 4, 1>, 4, 1);
+      if (nrhs >= 3) go(k_coarse_eo_apply<S, 4, 1>, 4, 1);
       else if (nrhs == 2) go(k_coarse_eo_apply<S, 2, 1>, 2, 1);
       else go(k_coarse_eo_apply<S, 1, 1>, 1, 1);
     }

@@ -867,11 +867,13 @@ void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const v
     using one = std::integral_constant<int, 1>;
     using four = std::integral_constant<int, 4>;
     using pk = std::integral_constant<int, PK>;
+    // groups of four right-hand sides (the last one ragged) read P once per group: already
+    // from two right-hand sides on, since P is larger than the vectors
     if (packed) {
-      if (nrhs >= 4) go(pk{}, four{});
+      if (nrhs >= 2) go(pk{}, four{});
       else go(pk{}, one{});
     } else {
-      if (nrhs >= 4) go(one{}, four{});
+      if (nrhs >= 2) go(one{}, four{});
       else go(one{}, one{});
     }
   });
@@ -896,7 +898,7 @@ void launch_restrict(qmg_prec prec, const HierarchyDev& h, const void* P, const 
     using one = std::integral_constant<int, 1>;
     using four = std::integral_constant<int, 4>;
     using pk = std::integral_constant<int, PK>;
-    const bool multi = nrhs >= 4 && size_t(4) * h.blk.N * sizeof(cplx<ctype<S>>) <= 96 * 1024;
+    const bool multi = nrhs >= 2 && size_t(4) * h.blk.N * sizeof(cplx<ctype<S>>) <= 96 * 1024;
     if (packed) {
       if (multi) go(pk{}, four{});
       else go(pk{}, one{});
@@ -934,11 +936,11 @@ void launch_stencil_apply(qmg_prec prec, int d, int k, const int* cnb, const voi
     };
     const bool packed = m % PK == 0;
     if (packed) {
-      if (nrhs >= 4) go(k_coarse_apply<S, 4, PK>, 4, PK);
+      if (nrhs >= 3) go(k_coarse_apply<S, 4, PK>, 4, PK);
       else if (nrhs == 2) go(k_coarse_apply<S, 2, PK>, 2, PK);
       else go(k_coarse_apply<S, 1, PK>, 1, PK);
     } else {
-      if (nrhs >= 4) go(k_coarse_apply<S, 4, 1>, 4, 1);
+      if (nrhs >= 3) go(k_coarse_apply<S, 4, 1>, 4, 1);
       else if (nrhs == 2) go(k_coarse_apply<S, 2, 1>, 2, 1);
       else go(k_coarse_apply<S, 1, 1>, 1, 1);
     }
