@@ -641,9 +641,9 @@ def roofline_of(fam_name, f, wname):
     """Roofline object of one family: FP64 flops for the streaming-SVD kernels, else algorithmic
     bytes over HBM."""
     avg_s = f["avg_launch_ms"] * 1e-3
-    if fam_name.startswith("isvd") or (f["bytes_per_launch"] == 0 and f["flops_per_launch"] > 0):
+    if fam_name == "isvd/small" or (f["bytes_per_launch"] == 0 and f["flops_per_launch"] > 0):
         ach = f["flops_per_launch"] / avg_s / 1e12
-        return {"bound": "mfma" if fam_name.startswith("isvd/gram") else "alu", "achieved": ach,
+        return {"bound": "alu", "achieved": ach,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
                 "kernel": fam_name, "avg_launch_ms": f["avg_launch_ms"],
                 "algorithmic_flops_per_launch": f["flops_per_launch"]}

@@ -40,6 +40,12 @@ WORKLOADS = {
                       inner="f32", seed=14399, tag=5),
 }
 
+# the 64 independent small lattices of the batched workload: L^4 with L uniform in {8, 10, 12}
+# (even, so 2^4 aggregates divide them), masses uniform in [0.01, 0.1], roughness 0.3, xi = 1,
+# antiperiodic t, the 4^4 workload's multigrid parameters (2^4 blocks; 16 / 4 / 8), FP32 inner
+SMALL_LATTICES = dict(n=64, sizes=(8, 10, 12), mass_range=(0.01, 0.1), eps=0.3, xi=1.0, bc_t=-1,
+                      block=(2, 2, 2, 2), n_test=16, batch=4, rank=8, inner="f32", seed=14399, tag=6)
+
 _TUNED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                       "tests", "golden", "tuned_masses.json")
 
@@ -51,6 +57,15 @@ def rhs(w: dict):
     if w.get("rhs") == "point12":
         return fields.point_sources(w["dims"])
     return fields.gaussian_spinor(w["dims"], 1, w["seed"], tag=w["tag"])
+
+
+def small_lattices(n=None):
+    """[(dims, mass, gauge-field tag)] of the batched small-lattice workload (first n of them)."""
+    import fields
+    w = SMALL_LATTICES
+    Ls, ms = fields.batched_lattice_params(w["n"], w["seed"], w["sizes"], w["mass_range"])
+    out = [((L, L, L, L), m, w["tag"] * 1000 + i) for i, (L, m) in enumerate(zip(Ls, ms))]
+    return out[:n] if n else out
 
 
 def get(name: str) -> dict:

@@ -433,6 +433,46 @@ qmg_status qmg_coarse_schur_apply_noalloc(const qmg_mg* mg, const void* in, void
 qmg_status qmg_coarse_eo_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, double tol,
                                int32_t max_iter, int32_t* iters, hipStream_t stream);
 
+/* Many independent small lattices in one hierarchy object (batching form 2: many lattices of
+ * uneven size, each with its own extents, boundary, mass, anisotropy and gauge field; one aggregate
+ * shape, test-vector count, batch and rank for all).  Every step of Algorithm 4 with Algorithm 3
+ * (Philox test vectors, the Eq. (2) smoothing, the chiral split and gather, the streaming SVD over
+ * all (aggregate, chirality) problems of all lattices, the Galerkin blocks of Eq. (5)) and every
+ * step of the K-cycle solve runs as shared launches over all lattices: the fine fields of the
+ * lattices are zero-padded to a common volume and stacked, each (lattice, right-hand side) pair is
+ * one column of the Krylov solvers (inner products, norms and convergence per lattice).  The
+ * Galerkin blocks are formed by probing (colour-separated unit coarse vectors prolonged, the fine
+ * operator applied, restricted) in FP64.  Wilson operator only; K-cycle in FP64 or FP32 (then
+ * inside FP64 defect correction, the smoothing below FP64 in s-step form as in the single-lattice
+ * setup); plain GMRES post-smoothing on D; coarse GMRES(32).
+ * qmg_batch_setup: lats host array of n_lat descriptors; U host array of n_lat device pointers to
+ *   canonical FP64 gauge fields [4][V_l][3][3]; params as qmg_mg_setup_stream_chiral_svd (block
+ *   dividing every lattice's extents with every coarse extent >= 3, test_vectors NULL, no clover
+ *   coefficients, inner_prec F64 or F32, rank <= 32, rank + batch <= 64).  Test vector i of
+ *   every lattice is the counter-based generator's vector i for that lattice's volume, as in the
+ *   single-lattice setup with the same seed.  Synchronizes the stream.
+ * qmg_batch_solve: rhs, x host arrays of n_lat device pointers to canonical FP64 spinors
+ *   [nrhs][V_l][4][3] (x written); every lattice and right-hand side to a true FP64 relative
+ *   residual tol; info (optional) [n_lat * nrhs], lattice-major (the iteration counts are those of
+ *   the shared solve).  Synchronizes the stream.
+ * qmg_batch_get_prolongator / _get_coarse: lattice lat's P [d_l][2][N][k] (rows in the canonical
+ *   order of qmg_mg_get_prolongator) and sigma [d_l][2][k] (host), and its Galerkin blocks
+ *   [d_l][9][2k][2k] (row-major, FP64, device).  qmg_batch_query: d_l and k.
+ *   qmg_batch_setup_times: seconds of smoothing, streaming SVD, coarse build and the whole setup.
+ * Errors: EINVAL (null, counts), ESHAPE (extents, block, rank), EDTYPE, ENOTIMPL (clover),
+ *   ENONFINITE (non-finite links or residuals), ENOCONV, ENOMEM, EHIP. */
+typedef struct qmg_batch qmg_batch;
+qmg_status qmg_batch_setup(int32_t n_lat, const qmg_lattice* lats, const void* const* U,
+                           const qmg_mg_params* params, qmg_batch** out, hipStream_t stream);
+qmg_status qmg_batch_solve(const qmg_batch* b, const void* const* rhs, void* const* x, int32_t nrhs,
+                           double tol, int32_t max_outer, qmg_solve_info* info, hipStream_t stream);
+qmg_status qmg_batch_query(const qmg_batch* b, int32_t lat, int32_t* n_agg, int32_t* rank);
+qmg_status qmg_batch_get_prolongator(const qmg_batch* b, int32_t lat, void* P, double* sigma,
+                                     hipStream_t stream);
+qmg_status qmg_batch_get_coarse(const qmg_batch* b, int32_t lat, void* Y, hipStream_t stream);
+qmg_status qmg_batch_setup_times(const qmg_batch* b, double* t);
+void qmg_batch_destroy(qmg_batch* b);
+
 /* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times the first 64
  * later launches of each kernel family and then about one in n (picked by a hash of the call
  * index) with a pair of HIP events attached to the dispatch (its own start and end).  Every

@@ -113,6 +113,13 @@ SIGNATURES = {
     "qmg_mg_load": [ctypes.c_char_p, _P, _P, _P],
     "qmg_mg_get_params": [_P, _P, _P],
     "qmg_mg_destroy": [_P],
+    "qmg_batch_setup": [_I, _P, _P, _P, _P, _P],
+    "qmg_batch_solve": [_P, _P, _P, _I, _D, _I, _P, _P],
+    "qmg_batch_query": [_P, _I, _P, _P],
+    "qmg_batch_get_prolongator": [_P, _I, _P, _P, _P],
+    "qmg_batch_get_coarse": [_P, _I, _P, _P],
+    "qmg_batch_setup_times": [_P, _P],
+    "qmg_batch_destroy": [_P],
     "qmg_last_error": [],
     "qmg_version": [],
 }
@@ -136,6 +143,7 @@ def load_library(path: str = LIB_PATH):
     lib.qmg_last_error.restype = ctypes.c_char_p
     lib.qmg_version.restype = ctypes.c_char_p
     lib.qmg_mg_destroy.restype = None
+    lib.qmg_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -563,6 +571,95 @@ def mg_setup_stream_chiral_svd(lat: Lattice, U, block, n_test, batch, rank, n_se
     s = lat.c()
     _check(lib.qmg_mg_setup_stream_chiral_svd(ctypes.byref(s), _ptr(U), ctypes.byref(p), ctypes.byref(h), _stream()))
     return MG(h, lat, p)
+
+
+class Batch:
+    """Multigrid hierarchies of many small lattices built and solved together (qmg_batch_*)."""
+
+    def __init__(self, handle, lats, params):
+        self._h = handle
+        self.lats = list(lats)
+        self.params = params
+
+    def close(self):
+        if self._h:
+            load_library().qmg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, lat):
+        d, k = ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().qmg_batch_query(self._h, int(lat), ctypes.byref(d), ctypes.byref(k)))
+        return d.value, k.value
+
+    def prolongator(self, lat):
+        """(P [d,2,N,k] complex128 on the GPU in the canonical row order, sigma [d,2,k]) of lattice lat."""
+        import numpy as np
+        d, k = self.query(lat)
+        N = 6 * int(torch.tensor(self.params.block[:]).prod())
+        P = torch.empty((d, 2, N, k), dtype=torch.complex128, device="cuda")
+        sig = np.empty((d, 2, k))
+        _check(load_library().qmg_batch_get_prolongator(self._h, int(lat), _ptr(P), sig.ctypes.data_as(ctypes.c_void_p),
+                                                        _stream()))
+        return P, sig
+
+    def coarse_blocks(self, lat):
+        d, k = self.query(lat)
+        Y = torch.empty((d, 9, 2 * k, 2 * k), dtype=torch.complex128, device="cuda")
+        _check(load_library().qmg_batch_get_coarse(self._h, int(lat), _ptr(Y), _stream()))
+        return Y
+
+    def setup_times(self):
+        t = (ctypes.c_double * 4)()
+        _check(load_library().qmg_batch_setup_times(self._h, t))
+        return {"smooth": t[0], "svd": t[1], "coarse": t[2], "total": t[3]}
+
+
+def batch_setup(lats: Sequence[Lattice], Us, block, n_test, batch, rank, n_setup_iter=16, n_post_smooth=8,
+                coarse_tol=0.03, coarse_max_iter=500, inner="f32", seed=0) -> Batch:
+    """Hierarchies of many lattices at once (qmg_batch_setup).  Us: complex128 [4,V_l,3,3] per lattice."""
+    lib = load_library()
+    n = len(lats)
+    if len(Us) != n or n == 0:
+        raise ValueError("need one gauge field per lattice")
+    for U in Us:
+        if U.dtype != torch.complex128:
+            raise TypeError("setup takes FP64 canonical gauge fields")
+    p = qmg_mg_params()
+    for i in range(4):
+        p.block[i] = int(block[i])
+    p.n_test, p.batch, p.rank = int(n_test), int(batch), int(rank)
+    p.n_setup_iter, p.n_post_smooth = int(n_setup_iter), int(n_post_smooth)
+    p.coarse_tol, p.coarse_max_iter = float(coarse_tol), int(coarse_max_iter)
+    p.inner_prec = _PREC[inner]
+    p.seed = int(seed)
+    arr = (qmg_lattice * n)(*[l.c() for l in lats])
+    ptrs = (ctypes.c_void_p * n)(*[_ptr(U).value for U in Us])
+    h = ctypes.c_void_p()
+    _check(lib.qmg_batch_setup(n, arr, ptrs, ctypes.byref(p), ctypes.byref(h), _stream()))
+    return Batch(h, lats, p)
+
+
+def batch_solve(bt: Batch, bs, tol=1e-10, max_outer=1000, check=True):
+    """x_l = D_l^-1 b_l for every lattice: bs complex128 [nrhs,V_l,4,3] per lattice.  Returns (xs, info)
+    with info a list (per lattice) of lists (per right-hand side) of dicts."""
+    n = len(bt.lats)
+    nrhs = int(bs[0].shape[0])
+    xs = [torch.empty_like(b) for b in bs]
+    infos = (qmg_solve_info * (n * nrhs))()
+    bp = (ctypes.c_void_p * n)(*[_ptr(b).value for b in bs])
+    xp = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+    rc = load_library().qmg_batch_solve(bt._h, bp, xp, nrhs, float(tol), int(max_outer), infos, _stream())
+    out = [[{f: getattr(infos[l * nrhs + r], f) for f, _ in qmg_solve_info._fields_} for r in range(nrhs)]
+           for l in range(n)]
+    if check:
+        _check(rc)
+    return xs, out
 
 
 def mg_load(path, U) -> MG:

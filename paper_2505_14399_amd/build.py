@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqmg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["alloc.hip", "dslash.hip", "clover.hip", "evenodd.hip", "coarse_evenodd.hip", "krylov.hip", "transfer.hip", "isvd.hip", "capi.hip", "timing.hip", "tune.hip"]
+SOURCES = ["alloc.hip", "dslash.hip", "clover.hip", "evenodd.hip", "coarse_evenodd.hip", "krylov.hip", "transfer.hip", "isvd.hip", "capi.hip", "batch.hip", "timing.hip", "tune.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

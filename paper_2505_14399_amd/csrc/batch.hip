@@ -1,0 +1,816 @@
+// Multigrid over many independent small lattices at once (each with its own extents, mass and
+// gauge field; one aggregate shape and rank for all): the setup of Algorithm 4 with the
+// streaming SVD of Algorithm 3 and the K-cycle solve of every lattice run as shared launches.
+//
+// Layouts: the fine fields of all lattices are zero-padded to a common volume Vpad and stacked,
+// lattice-major: gauge [l][4][9][Vpad], spinors [l][nr][12][Vpad]; the coarse vectors likewise
+// to a common aggregate count dmax: [l][nr][dmax][2k].  Every (lattice, right-hand side) pair is
+// one column of the Krylov solvers, so inner products, norms and convergence tests are per
+// lattice (the padding is zero and stays zero), while every operator, transfer and vector kernel
+// is one launch over all lattices.  The aggregates of all lattices are numbered globally
+// (lattice-major, J = aoff[l] + j): the prolongator [J][2][k][N] and the coarse blocks
+// [J][9][2k][2k] are the per-lattice arrays of a single hierarchy concatenated, so the streaming
+// SVD runs over all of them in its usual launches.
+//
+// The Galerkin blocks Y_s(j) = P_j^dag D P_{j+s} (Eq. (5)) are formed by probing: the coarse
+// lattice of every lattice is coloured so that an aggregate and its eight neighbours all have
+// different colours; for colour c and coarse component q the vector that is 1 on component q of
+// every aggregate of colour c is prolonged, the fine operator applied and the result restricted,
+// and the restricted value on aggregate j' is column q of Y_s(j'), s the slot of the unique
+// colour-c aggregate in the neighbourhood of j'.  In FP64 this is R D P to rounding, with the
+// boundary signs and the diagonal term included by the fine operator itself.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "krylov.hpp"
+#include "mg.hpp"
+#include "timing.hpp"
+
+struct qmg_batch;
+
+namespace qmg {
+
+namespace {
+
+constexpr int kMaxRank = 32;  // 2k <= 64 coarse components per aggregate
+
+// canonical FP64 gauge [4][V][3][3] -> padded native [4][9][Vpad]
+__global__ void k_b_pack_gauge(const double2* __restrict__ canon, double2* __restrict__ out, int V, int Vpad) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int me = blockIdx.y;  // mu * 9 + e
+  if (site >= Vpad) return;
+  const int mu = me / 9, e = me - 9 * mu;
+  out[size_t(me) * Vpad + site] = site < V ? canon[(size_t(mu) * V + site) * 9 + e] : make_double2(0.0, 0.0);
+}
+
+// canonical FP64 spinors [nrhs][V][12] <-> padded native [nrhs][12][Vpad]
+__global__ void k_b_pack_spinor(const double2* __restrict__ canon, double2* __restrict__ out, int V, int Vpad) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int rc = blockIdx.y;  // rhs * 12 + comp
+  if (site >= Vpad) return;
+  const int rhs = rc / 12, c = rc - 12 * rhs;
+  out[size_t(rc) * Vpad + site] = site < V ? canon[(size_t(rhs) * V + site) * 12 + c] : make_double2(0.0, 0.0);
+}
+__global__ void k_b_unpack_spinor(const double2* __restrict__ nat, double2* __restrict__ canon, int V, int Vpad) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int rc = blockIdx.y;
+  if (site >= V) return;
+  const int rhs = rc / 12, c = rc - 12 * rhs;
+  canon[(size_t(rhs) * V + site) * 12 + c] = nat[size_t(rc) * Vpad + site];
+}
+
+// chiral split and block gather of r test vectors of every lattice: blocks [(J, alpha)][r][N],
+// row = s6 * nd + ib (the row order of the single-lattice gather)
+__global__ void k_b_gather(const double2* __restrict__ fine, double2* __restrict__ blocks, const int* __restrict__ gsite,
+                           const int* __restrict__ jinfo, int nd, int N, int r, int Vpad) {
+  const int row = blockIdx.z * 256 + threadIdx.x;
+  const int v = blockIdx.y, ja = blockIdx.x;  // the (aggregate, chirality) count may exceed 65535
+  if (row >= N) return;
+  const int J = ja >> 1, a = ja & 1, l = jinfo[2 * J];
+  const int s6 = row / nd, ib = row - s6 * nd;
+  const int site = gsite[size_t(J) * nd + ib];
+  blocks[(size_t(ja) * r + v) * N + row] = fine[((size_t(l) * r + v) * 12 + 6 * a + s6) * Vpad + site];
+}
+
+// fine = P coarse: one thread per (row of (J, alpha), rhs); fine padding is not touched
+template <class S>
+__global__ __launch_bounds__(256) void k_b_prolong(const S* __restrict__ P, const S* __restrict__ vc,
+                                                   S* __restrict__ fine, const int* __restrict__ gsite,
+                                                   const int* __restrict__ jinfo, int nd, int N, int k, int dmax,
+                                                   int Vpad, int nrhs) {
+  using C = ctype<S>;
+  const int row = blockIdx.y * 256 + threadIdx.x;
+  const int ja = blockIdx.x, rhs = blockIdx.z;  // the (aggregate, chirality) count may exceed 65535
+  if (row >= N) return;
+  const int J = ja >> 1, a = ja & 1, l = jinfo[2 * J], j = jinfo[2 * J + 1];
+  const size_t col = size_t(l) * nrhs + rhs;
+  const S* Pc = P + size_t(ja) * k * N;
+  const S* v = vc + (col * dmax + j) * 2 * k + a * k;
+  cplx<C> acc = {C(0), C(0)};
+  for (int i = 0; i < k; ++i) acc += ldc(Pc, size_t(i) * N + row) * ldc(v, i);
+  const int s6 = row / nd, ib = row - s6 * nd;
+  stc(fine, (col * 12 + 6 * a + s6) * Vpad + gsite[size_t(J) * nd + ib], acc);
+}
+
+// coarse = P^dag fine: one wavefront per ((J, alpha), rhs); the block's N fine entries are staged
+// in LDS and lane i < k forms component i
+template <class S>
+__global__ __launch_bounds__(64) void k_b_restrict(const S* __restrict__ P, const S* __restrict__ fine,
+                                                   S* __restrict__ vc, const int* __restrict__ gsite,
+                                                   const int* __restrict__ jinfo, int nd, int N, int k, int dmax,
+                                                   int Vpad, int nrhs) {
+  using C = ctype<S>;
+  extern __shared__ unsigned char smem[];
+  cplx<C>* psi = reinterpret_cast<cplx<C>*>(smem);  // [N]
+  const int ja = blockIdx.x, rhs = blockIdx.y;
+  const int J = ja >> 1, a = ja & 1, l = jinfo[2 * J], j = jinfo[2 * J + 1];
+  const size_t col = size_t(l) * nrhs + rhs;
+  for (int row = threadIdx.x; row < N; row += 64) {
+    const int s6 = row / nd, ib = row - s6 * nd;
+    psi[row] = ldc(fine, (col * 12 + 6 * a + s6) * Vpad + gsite[size_t(J) * nd + ib]);
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i >= k) return;
+  const S* Pc = P + (size_t(ja) * k + i) * N;
+  cplx<C> acc = {C(0), C(0)};
+  for (int row = 0; row < N; ++row) acc += cmul_conj(ldc(Pc, row), psi[row]);
+  stc(vc, (col * dmax + j) * 2 * k + a * k + i, acc);
+}
+
+// out = D_c in on the padded coarse columns: one workgroup per (aggregate slot j < dmax,
+// column); the nine inputs (self, then the eight neighbours) are staged in LDS, thread `row`
+// forms one output component; padding aggregates give zeros
+template <class S>
+__global__ __launch_bounds__(64) void k_b_coarse_apply(const S* __restrict__ Y, const S* __restrict__ in,
+                                                       S* __restrict__ out, const int* __restrict__ cnb,
+                                                       const int* __restrict__ jinfo, const int* __restrict__ dl,
+                                                       const int* __restrict__ aoff, int m, int dmax, int nrhs) {
+  using C = ctype<S>;
+  __shared__ cplx<C> v[9][2 * kMaxRank];
+  const int j = blockIdx.x, col = blockIdx.y, l = col / nrhs;
+  const int row = threadIdx.x;
+  const size_t ob = (size_t(col) * dmax + j) * m;
+  if (j >= dl[l]) {
+    if (row < m) stc(out, ob + row, cplx<C>{C(0), C(0)});
+    return;
+  }
+  const int J = aoff[l] + j;
+  for (int t = threadIdx.x; t < 9 * m; t += 64) {
+    const int s = t / m, c = t - s * m;
+    const int jn = s == 0 ? j : jinfo[2 * cnb[size_t(J) * 8 + s - 1] + 1];
+    v[s][c] = ldc(in, (size_t(col) * dmax + jn) * m + c);
+  }
+  __syncthreads();
+  if (row >= m) return;
+  cplx<C> acc = {C(0), C(0)};
+  const S* YJ = Y + size_t(J) * 9 * m * m;
+  for (int s = 0; s < 9; ++s)
+    for (int c = 0; c < m; ++c) acc += ldc(YJ, (size_t(s) * m + c) * m + row) * v[s][c];
+  stc(out, ob + row, acc);
+}
+
+// probing vectors: component q0 + q' of every aggregate of colour c is 1 in column (l, q')
+__global__ void k_b_probe_scatter(double2* __restrict__ vc, const int* __restrict__ colour, int c, int q0, int nq,
+                                  const int* __restrict__ jinfo, int dmax, int m, int DT) {
+  const int J = blockIdx.x * 256 + threadIdx.x;
+  if (J >= DT || colour[J] != c) return;
+  const int l = jinfo[2 * J], j = jinfo[2 * J + 1];
+  for (int q = 0; q < nq; ++q) vc[((size_t(l) * nq + q) * dmax + j) * m + q0 + q] = make_double2(1.0, 0.0);
+}
+
+// columns q0 .. q0 + nq - 1 of Y_s(J') from the restricted probes, for the slots whose aggregate
+// has colour c
+__global__ void k_b_probe_extract(const double2* __restrict__ u, double2* __restrict__ Y, const int* __restrict__ colour,
+                                  int c, int q0, int nq, const int* __restrict__ cnb, const int* __restrict__ jinfo,
+                                  int dmax, int m) {
+  const int Jp = blockIdx.x, s = blockIdx.y;
+  const int J = s == 0 ? Jp : cnb[size_t(Jp) * 8 + s - 1];
+  if (colour[J] != c) return;
+  const int l = jinfo[2 * Jp], jp = jinfo[2 * Jp + 1];
+  for (int t = threadIdx.x; t < nq * m; t += blockDim.x) {
+    const int q = t / m, row = t - q * m;
+    Y[((size_t(Jp) * 9 + s) * m + q0 + q) * m + row] = u[((size_t(l) * nq + q) * dmax + jp) * m + row];
+  }
+}
+
+template <class F>
+void dispatch_b(qmg_prec p, F&& f) {
+  if (p == QMG_F64) f(double2{});
+  else f(float2{});
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// the many-lattice hierarchy
+
+struct BatchDev {
+  int nl = 0, Vpad = 0, k = 0, nd = 0, N = 0, DT = 0, dmax = 0;
+  int blk[4] = {1, 1, 1, 1};
+  qmg_prec inner = QMG_F32;
+  int n_post = 8, coarse_max = 500;
+  double coarse_tol = 0.03;
+  std::vector<Geom> geo;
+  std::vector<int> d, aoff, V;
+  DevBuf lat;                 // BatchLattice[nl], a.V = Vpad
+  DevBuf Vl, dl, aoffd;       // int[nl]
+  DevBuf U64, Uin;            // [l][4][9][Vpad]
+  DevBuf gsite, jinfo, cnb;   // [DT][nd], [DT][2] (lattice, local index), [DT][8] (global)
+  DevBuf P64, Pin;            // [DT][2][k][N]
+  DevBuf Y64, Yin;            // [DT][9][2k][2k] column-major blocks
+  DevBuf sigma;               // [DT][2][k]
+  std::vector<double> sigma_h;
+  double t_smooth = 0, t_svd = 0, t_coarse = 0, t_total = 0;
+  size_t fine_len() const { return size_t(12) * Vpad; }
+  size_t coarse_len() const { return size_t(2) * k * dmax; }
+};
+
+namespace {
+
+// D of every lattice on padded columns (nl * nr columns of 12 Vpad complex numbers)
+struct BatchOp : LinOp {
+  const BatchDev& b;
+  qmg_prec p;
+  const void* U;
+  BatchOp(const BatchDev& b_, qmg_prec p_, const void* U_) : b(b_), p(p_), U(U_) {}
+  void apply(const void* in, void* out, int ncol, hipStream_t st, const int* = nullptr) override {
+    const int nr = ncol / b.nl;
+    double sites = 0;
+    for (int v : b.V) sites += v;
+    launch_dslash_padded(p, b.lat.as<BatchLattice>(), b.nl, nr, b.Vpad, U, in, out, false,
+                         sites * (24.0 * nr + 36.0) * prec_bytes(p), 1368.0 * sites * nr, st);
+  }
+  size_t len() const override { return b.fine_len(); }
+  qmg_prec prec() const override { return p; }
+};
+
+struct BatchCoarseOp : LinOp {
+  const BatchDev& b;
+  qmg_prec p;
+  const void* Y;
+  BatchCoarseOp(const BatchDev& b_, qmg_prec p_, const void* Y_) : b(b_), p(p_), Y(Y_) {}
+  void apply(const void* in, void* out, int ncol, hipStream_t st, const int* = nullptr) override {
+    const int nr = ncol / b.nl, m = 2 * b.k;
+    TimedLaunch tl("coarse_apply/batched", st, double(b.DT) * (9.0 * m * m + m * 2.0 * nr) * prec_bytes(p),
+                   8.0 * 9.0 * m * m * b.DT * nr);
+    dispatch_b(p, [&](auto tag) {
+      using S = decltype(tag);
+      launch(k_b_coarse_apply<S>, dim3(b.dmax, ncol), dim3(64), 0, st, static_cast<const S*>(Y),
+             static_cast<const S*>(in), static_cast<S*>(out), b.cnb.as<int>(), b.jinfo.as<int>(), b.dl.as<int>(),
+             b.aoffd.as<int>(), m, b.dmax, nr);
+    });
+    QMG_LAUNCH_CHECK();
+  }
+  size_t len() const override { return b.coarse_len(); }
+  qmg_prec prec() const override { return p; }
+};
+
+void b_prolong(const BatchDev& b, qmg_prec p, const void* P, const void* vc, void* fine, int nr, hipStream_t st) {
+  double sites = 0;
+  for (int v : b.V) sites += v;
+  TimedLaunch tl("prolong/batched", st, sites * (12.0 * b.k + 12.0 * nr) * prec_bytes(p), 8.0 * 12.0 * b.k * sites * nr);
+  dispatch_b(p, [&](auto tag) {
+    using S = decltype(tag);
+    launch(k_b_prolong<S>, dim3(2 * b.DT, unsigned((b.N + 255) / 256), nr), dim3(256), 0, st, static_cast<const S*>(P),
+           static_cast<const S*>(vc), static_cast<S*>(fine), b.gsite.as<int>(), b.jinfo.as<int>(), b.nd, b.N, b.k,
+           b.dmax, b.Vpad, nr);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+// the restricted columns' padding aggregates are cleared first
+void b_restrict(const BatchDev& b, qmg_prec p, const void* P, const void* fine, void* vc, int nr, hipStream_t st) {
+  double sites = 0;
+  for (int v : b.V) sites += v;
+  dispatch_b(p, [&](auto tag) {
+    using S = decltype(tag);
+    Blas<S>::zero(vc, b.coarse_len() * b.nl * nr, st);
+    TimedLaunch tl("restrict/batched", st, sites * (12.0 * b.k + 12.0 * nr) * prec_bytes(p),
+                   8.0 * 12.0 * b.k * sites * nr);
+    launch(k_b_restrict<S>, dim3(2 * b.DT, nr), dim3(64), uint32_t(b.N * sizeof(cplx<ctype<S>>)), st,
+           static_cast<const S*>(P), static_cast<const S*>(fine), static_cast<S*>(vc), b.gsite.as<int>(),
+           b.jinfo.as<int>(), b.nd, b.N, b.k, b.dmax, b.Vpad, nr);
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+// Galerkin blocks by probing (file header); FP64
+void b_build_coarse(BatchDev& b, const std::vector<int>& colour_h, int ncolour, hipStream_t st) {
+  const int m = 2 * b.k;
+  DevBuf colour(colour_h.size() * sizeof(int));
+  QMG_HIP(hipMemcpy(colour.p, colour_h.data(), colour_h.size() * sizeof(int), hipMemcpyHostToDevice));
+  b.Y64.alloc(size_t(b.DT) * 9 * m * m * sizeof(double2));
+  const int nq = std::min(m, 8);  // coarse components probed per pass
+  DevBuf vc(b.coarse_len() * b.nl * nq * sizeof(double2)), u(vc.bytes);
+  DevBuf f1(b.fine_len() * b.nl * nq * sizeof(double2)), f2(f1.bytes);
+  BatchOp D(b, QMG_F64, b.U64.p);
+  TimedLaunch tl("coarse_build/batched", st, 0.0, 0.0, false);
+  for (int c = 0; c < ncolour; ++c)
+    for (int q0 = 0; q0 < m; q0 += nq) {
+      const int q = std::min(nq, m - q0);
+      Blas<double2>::zero(vc.p, b.coarse_len() * b.nl * q, st);
+      launch(k_b_probe_scatter, dim3(unsigned((b.DT + 255) / 256)), dim3(256), 0, st, vc.as<double2>(),
+             colour.as<int>(), c, q0, q, b.jinfo.as<int>(), b.dmax, m, b.DT);
+      QMG_LAUNCH_CHECK();
+      Blas<double2>::zero(f1.p, b.fine_len() * b.nl * q, st);  // the padding of the prolonged probes
+      b_prolong(b, QMG_F64, b.P64.p, vc.p, f1.p, q, st);
+      D.apply(f1.p, f2.p, b.nl * q, st);
+      b_restrict(b, QMG_F64, b.P64.p, f2.p, u.p, q, st);
+      launch(k_b_probe_extract, dim3(b.DT, 9), dim3(256), 0, st, u.as<double2>(), b.Y64.as<double2>(),
+             colour.as<int>(), c, q0, q, b.cnb.as<int>(), b.jinfo.as<int>(), b.dmax, m);
+      QMG_LAUNCH_CHECK();
+    }
+}
+
+// Greedy colouring of one coarse lattice: an aggregate and its eight neighbours all differ
+// (two aggregates conflict when one is within two +-mu steps of the other).
+int colour_coarse(const int cL[4], std::vector<int>& col) {
+  const int d = cL[0] * cL[1] * cL[2] * cL[3];
+  col.assign(d, -1);
+  int ncol = 0;
+  auto idx = [&](const int c[4]) { return c[0] + cL[0] * (c[1] + cL[1] * (c[2] + cL[2] * c[3])); };
+  std::vector<char> used;
+  for (int j = 0; j < d; ++j) {
+    int c[4], rem = j;
+    for (int q = 0; q < 4; ++q) {
+      c[q] = rem % cL[q];
+      rem /= cL[q];
+    }
+    used.assign(size_t(ncol) + 1, 0);
+    for (int s1 = 0; s1 < 9; ++s1)
+      for (int s2 = 0; s2 < 9; ++s2) {
+        int cc[4] = {c[0], c[1], c[2], c[3]};
+        for (int sv : {s1, s2}) {
+          if (sv == 0) continue;
+          const int mu = (sv - 1) & 3, step = sv <= 4 ? 1 : -1;
+          cc[mu] = (cc[mu] + step + cL[mu]) % cL[mu];
+        }
+        const int o = idx(cc);
+        if (o != j && col[o] >= 0) used[col[o]] = 1;
+      }
+    int k = 0;
+    while (k < ncol && used[k]) ++k;
+    col[j] = k;
+    ncol = std::max(ncol, k + 1);
+  }
+  return ncol;
+}
+
+// K-cycle over all lattices: restrict, coarse GMRES(32) to the coarse tolerance (per column),
+// prolong, GMRES(n_post) post-smoothing from the prolonged correction; storage S = outer type
+template <class S>
+struct BatchKCycle : Precond {
+  const BatchDev& b;
+  BatchOp& D;
+  BatchCoarseOp& Dc;
+  const void* P;
+  Gmres<S> gc, gf;
+  DevBuf rc, ec;
+  long coarse_iters = 0, smooth_iters = 0;
+  BatchKCycle(const BatchDev& b_, BatchOp& D_, BatchCoarseOp& Dc_, const void* P_) : b(b_), D(D_), Dc(Dc_), P(P_) {}
+  void apply(const void* r, void* z, int ncol, hipStream_t st) override {
+    constexpr qmg_prec p = StoreTraits<S>::prec;
+    const int nr = ncol / b.nl;
+    rc.ensure(b.coarse_len() * ncol * sizeof(S));
+    ec.ensure(b.coarse_len() * ncol * sizeof(S));
+    b_restrict(b, p, P, r, rc.p, nr, st);
+    auto res = gc.solve(Dc, rc.p, ec.p, true, ncol, 32, b.coarse_max, b.coarse_tol, st);
+    coarse_iters += res.iters;
+    Blas<S>::zero(z, b.fine_len() * ncol, st);
+    b_prolong(b, p, P, ec.p, z, nr, st);
+    gf.solve(D, r, z, false, ncol, std::max(1, b.n_post), b.n_post, 0.0, st);
+    smooth_iters += b.n_post;
+  }
+};
+
+using Clock = std::chrono::steady_clock;
+double secs(Clock::time_point a, Clock::time_point c) { return std::chrono::duration<double>(c - a).count(); }
+
+}  // namespace
+
+// setup of every lattice (Algorithm 4 with Algorithm 3): Philox test vectors, smoothing,
+// streaming SVD over all (aggregate, chirality) problems of all lattices, Galerkin blocks
+void batch_setup(BatchDev& b, const qmg_mg_params& prm, hipStream_t st) {
+  const auto t0 = Clock::now();
+  const int r = prm.batch, ns = prm.n_test / prm.batch;
+  const size_t cols = size_t(b.nl) * r;
+  const size_t nf = b.fine_len() * cols;
+  b.P64.alloc(size_t(2) * b.DT * b.k * b.N * sizeof(double2));
+  b.sigma.alloc(size_t(2) * b.DT * b.k * sizeof(double));
+  DevBuf phi(nf * sizeof(double2)), blocks(size_t(2) * b.DT * r * b.N * sizeof(double2));
+  DevBuf xs, bs, tmp, basis, coef, part, e;
+  Gmres<double2> g64;
+  int kp = 0;
+  double mean_diag = 0;
+  for (const Geom& g : b.geo) mean_diag += g.diag() / b.nl;
+  for (int s = 0; s < ns; ++s) {
+    const auto a0 = Clock::now();
+    launch_philox_padded(prm.seed, s * r, r, b.nl, b.Vl.as<int>(), b.Vpad, phi.p, st);
+    if (prm.n_setup_iter > 0) {
+      // Eq. (2) per lattice and test vector: n_setup GMRES(8) steps on D psi' = -D phi, psi = phi + psi'
+      if (b.inner == QMG_F64) {
+        BatchOp D(b, QMG_F64, b.U64.p);
+        bs.ensure(nf * sizeof(double2));
+        xs.ensure(nf * sizeof(double2));
+        D.apply(phi.p, bs.p, int(cols), st);
+        Blas<double2>::axpby(0.0, bs.p, -1.0, bs.p, nf, st);
+        g64.solve(D, bs.p, xs.p, true, int(cols), 8, prm.n_setup_iter, 0.0, st);
+        Blas<double2>::axpby(1.0, xs.p, 1.0, phi.p, nf, st);
+      } else {
+        QMG_CHECK(prm.n_setup_iter % 8 == 0, QMG_EINVAL, "batched setup below FP64: n_setup_iter must be a multiple of 8");
+        BatchOp D(b, QMG_F32, b.Uin.p);
+        bs.ensure(nf * sizeof(float2));
+        xs.ensure(nf * sizeof(float2));
+        tmp.ensure(nf * sizeof(double2));
+        launch_convert(phi.p, QMG_F64, xs.p, QMG_F32, nf, st);
+        D.apply(xs.p, bs.p, int(cols), st);
+        Blas<float2>::axpby(0.0, bs.p, -1.0, bs.p, nf, st);
+        smooth_sstep<float2>(b.fine_len(), mean_diag, D, nullptr, int(cols), prm.n_setup_iter, bs.p, xs.p, basis, coef,
+                             part, e, st);
+        launch_convert(xs.p, QMG_F32, tmp.p, QMG_F64, nf, st);
+        Blas<double2>::axpby(1.0, tmp.p, 1.0, phi.p, nf, st);
+      }
+    }
+    {  // psi / |psi| per lattice and test vector
+      RedWork rw;
+      DevBuf nrm(cols * sizeof(double));
+      Blas<double2>::norm2(phi.p, b.fine_len(), int(cols), nrm.as<double>(), rw, st);
+      Blas<double2>::scale_dev(phi.p, nrm.as<double>(), 0, b.fine_len(), int(cols), st);
+    }
+    const auto a1 = Clock::now();
+    {
+      TimedLaunch tl_("setup/gather", st, double(cols) * b.Vpad * 12 * 2 * 16, 0.0);
+      launch(k_b_gather, dim3(2 * b.DT, r, unsigned((b.N + 255) / 256)), dim3(256), 0, st,
+             static_cast<const double2*>(phi.p), blocks.as<double2>(), b.gsite.as<int>(), b.jinfo.as<int>(), b.nd, b.N,
+             r, b.Vpad);
+    }
+    QMG_LAUNCH_CHECK();
+    kp = isvd_stream(2 * b.DT, b.N, b.k, b.P64, blocks.p, r, kp, b.sigma, st);
+    QMG_HIP(hipStreamSynchronize(st));
+    b.t_smooth += secs(a0, a1);
+    b.t_svd += secs(a1, Clock::now());
+  }
+  QMG_CHECK(kp == b.k, QMG_ESHAPE, "streaming SVD ended with %d < k columns", kp);
+  const auto c0 = Clock::now();
+  // colouring of every coarse lattice (host), Galerkin blocks by probing
+  std::vector<int> colour(b.DT);
+  int ncol = 0;
+  for (int l = 0; l < b.nl; ++l) {
+    int cL[4];
+    for (int q = 0; q < 4; ++q) cL[q] = b.geo[l].L[q] / b.blk[q];
+    std::vector<int> c1;
+    ncol = std::max(ncol, colour_coarse(cL, c1));
+    std::copy(c1.begin(), c1.end(), colour.begin() + b.aoff[l]);
+  }
+  b_build_coarse(b, colour, ncol, st);
+  if (b.inner != QMG_F64) {
+    const int m = 2 * b.k;
+    const size_t np = size_t(2) * b.DT * b.k * b.N, ny = size_t(b.DT) * 9 * m * m;
+    b.Pin.alloc(np * sizeof(float2));
+    b.Yin.alloc(ny * sizeof(float2));
+    launch_convert(b.P64.p, QMG_F64, b.Pin.p, QMG_F32, np, st);
+    launch_convert(b.Y64.p, QMG_F64, b.Yin.p, QMG_F32, ny, st);
+  }
+  b.sigma_h.resize(size_t(2) * b.DT * b.k);
+  QMG_HIP(hipMemcpyAsync(b.sigma_h.data(), b.sigma.p, b.sigma_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  QMG_HIP(hipStreamSynchronize(st));
+  b.t_coarse = secs(c0, Clock::now());
+  b.t_total = secs(t0, Clock::now());
+}
+
+// x = D^-1 b for every lattice and right-hand side (padded native FP64 in place in x64):
+// FP64 flexible GMRES(16) with the FP64 K-cycle, or FP64 defect correction around an FP32
+// flexible GMRES(16) (two Gram-Schmidt passes) whose K-cycle is stored in FP32; per-column
+// relative residuals in FP64 until every column is at or below tol.
+void batch_solve(const BatchDev& b, const void* b64, void* x64, int nr, double tol, int max_outer, hipStream_t st,
+                 long* stats /* outer, refinements, coarse, smoother */) {
+  const int ncol = b.nl * nr;
+  const size_t len = b.fine_len(), n = len * ncol;
+  BatchOp D64(b, QMG_F64, b.U64.p);
+  if (b.inner == QMG_F64) {
+    BatchCoarseOp Dc(b, QMG_F64, b.Y64.p);
+    BatchKCycle<double2> K(b, D64, Dc, b.P64.p);
+    Gmres<double2> f;
+    auto res = f.solve(D64, b64, x64, true, ncol, 16, max_outer, tol, st, nullptr, 0, &K);
+    stats[0] += res.iters;
+    stats[1] += 1;
+    stats[2] += K.coarse_iters;
+    stats[3] += K.smooth_iters;
+    return;
+  }
+  BatchOp D32(b, QMG_F32, b.Uin.p);
+  BatchCoarseOp Dc(b, QMG_F32, b.Yin.p);
+  BatchKCycle<float2> K(b, D32, Dc, b.Pin.p);
+  Gmres<float2> f;
+  f.set_cgs2(true);
+  DevBuf r64(n * sizeof(double2)), rin(n * sizeof(float2)), ein(n * sizeof(float2)), nrm(ncol * sizeof(double)),
+      bn(ncol * sizeof(double));
+  RedWork rw;
+  std::vector<double> hb(ncol), hr(ncol);
+  Blas<double2>::zero(x64, n, st);
+  Blas<double2>::norm2(b64, len, ncol, bn.as<double>(), rw, st);
+  QMG_HIP(hipMemcpyAsync(hb.data(), bn.p, ncol * sizeof(double), hipMemcpyDeviceToHost, st));
+  std::vector<double> hist;
+  for (int ref = 0; ref < 40 && stats[0] < max_outer; ++ref) {
+    D64.apply(x64, r64.p, ncol, st);
+    Blas<double2>::axpby(1.0, b64, -1.0, r64.p, n, st);
+    Blas<double2>::norm2(r64.p, len, ncol, nrm.as<double>(), rw, st);
+    QMG_HIP(hipMemcpyAsync(hr.data(), nrm.p, ncol * sizeof(double), hipMemcpyDeviceToHost, st));
+    QMG_HIP(hipStreamSynchronize(st));
+    double worst = 0;
+    for (int i = 0; i < ncol; ++i) {
+      QMG_CHECK(std::isfinite(hr[i]), QMG_ENONFINITE, "non-finite residual in defect correction");
+      worst = std::max(worst, hb[i] > 0 ? std::sqrt(hr[i] / hb[i]) : 0.0);
+    }
+    hist.push_back(worst);
+    if (worst <= tol) break;
+    Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 0, len, ncol, st);
+    launch_convert(r64.p, QMG_F64, rin.p, QMG_F32, n, st);
+    auto res = f.solve(D32, rin.p, ein.p, true, ncol, 16, int(max_outer - stats[0]), 1e-5, st, nullptr, 0, &K);
+    stats[0] += res.iters;
+    stats[1] += 1;
+    launch_convert(ein.p, QMG_F32, r64.p, QMG_F64, n, st);
+    Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 1, len, ncol, st);
+    Blas<double2>::axpby(1.0, r64.p, 1.0, x64, n, st);
+  }
+  stats[2] += K.coarse_iters;
+  stats[3] += K.smooth_iters;
+}
+
+}  // namespace qmg
+
+// ---------------------------------------------------------------------------------------
+// C ABI
+
+struct qmg_batch {
+  qmg::BatchDev b;
+  qmg_mg_params params{};
+};
+
+using namespace qmg;
+
+namespace {
+
+// a DevBuf pointing at memory it does not own for the lifetime of the guard (never freed by it)
+struct Borrowed {
+  DevBuf& d;
+  Borrowed(DevBuf& d_, void* p) : d(d_) { d.p = p; }
+  ~Borrowed() {
+    d.p = nullptr;
+    d.bytes = 0;
+  }
+};
+
+template <class Fn>
+qmg_status bguard(Fn&& f) {
+  try {
+    f();
+    return QMG_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return QMG_ENOMEM;
+  } catch (...) {
+    set_error("unexpected exception");
+    return QMG_EINVAL;
+  }
+}
+
+}  // namespace
+
+qmg_status qmg_batch_setup(int32_t n_lat, const qmg_lattice* lats, const void* const* U, const qmg_mg_params* p,
+                           qmg_batch** out, hipStream_t stream) {
+  return bguard([&] {
+    QMG_CHECK(lats && U && p && out, QMG_EINVAL, "null argument");
+    QMG_CHECK(n_lat >= 1 && n_lat <= 4096, QMG_EINVAL, "n_lat must be in [1, 4096]");
+    QMG_CHECK(p->inner_prec == QMG_F64 || p->inner_prec == QMG_F32, QMG_EDTYPE,
+              "batched hierarchies store their K-cycle in FP64 or FP32");
+    QMG_CHECK(p->c_sw_s == 0.0 && p->c_sw_t == 0.0, QMG_ENOTIMPL, "batched hierarchies are Wilson only");
+    QMG_CHECK(p->test_vectors == nullptr, QMG_EINVAL, "batched hierarchies draw their test vectors from the Philox generator");
+    QMG_CHECK(p->batch >= 1 && p->n_test >= p->batch && p->n_test % p->batch == 0, QMG_ESHAPE,
+              "n_test must be a positive multiple of batch");
+    QMG_CHECK(p->rank >= 1 && p->rank <= kMaxRank && p->rank <= p->n_test, QMG_ESHAPE, "rank must be in [1, %d] and <= n_test",
+              kMaxRank);
+    QMG_CHECK(p->rank + p->batch <= 64, QMG_ESHAPE, "rank + batch must be <= 64");
+    QMG_CHECK(p->n_setup_iter >= 0 && p->n_post_smooth >= 1 && p->coarse_tol > 0 && p->coarse_tol < 1 &&
+                  p->coarse_max_iter >= 1,
+              QMG_EINVAL, "bad smoother or coarse-solve parameters");
+    std::unique_ptr<qmg_batch> h(new qmg_batch);
+    BatchDev& b = h->b;
+    h->params = *p;
+    b.nl = n_lat;
+    b.k = p->rank;
+    b.inner = static_cast<qmg_prec>(p->inner_prec);
+    b.n_post = p->n_post_smooth;
+    b.coarse_tol = p->coarse_tol;
+    b.coarse_max = p->coarse_max_iter;
+    b.nd = 1;
+    for (int q = 0; q < 4; ++q) {
+      b.blk[q] = p->block[q];
+      QMG_CHECK(b.blk[q] >= 1, QMG_ESHAPE, "block extents must be >= 1");
+      b.nd *= b.blk[q];
+    }
+    b.N = 6 * b.nd;
+    QMG_CHECK(b.k <= b.N, QMG_ESHAPE, "rank above the rows of an aggregate");
+    std::vector<BatchLattice> desc(n_lat);
+    int DT = 0;
+    for (int l = 0; l < n_lat; ++l) {
+      QMG_CHECK(U[l], QMG_EINVAL, "gauge field %d is NULL", l);
+      Geom g = make_geom(&lats[l]);
+      for (int q = 0; q < 4; ++q) {
+        QMG_CHECK(g.L[q] % b.blk[q] == 0, QMG_ESHAPE, "lattice %d: block does not divide the extents", l);
+        QMG_CHECK(g.L[q] / b.blk[q] >= 3, QMG_ESHAPE,
+                  "lattice %d: every coarse extent must be >= 3 (eight distinct neighbour aggregates)", l);
+      }
+      b.geo.push_back(g);
+      b.V.push_back(g.V);
+      b.Vpad = std::max(b.Vpad, g.V);
+      b.d.push_back(g.V / b.nd);
+      b.aoff.push_back(DT);
+      DT += g.V / b.nd;
+      b.dmax = std::max(b.dmax, g.V / b.nd);
+    }
+    b.DT = DT;
+    b.Vpad = (b.Vpad + 255) / 256 * 256;
+    // tables: descriptors, volumes, aggregates, global neighbour aggregates
+    std::vector<int> gsite(size_t(DT) * b.nd), jinfo(size_t(2) * DT), cnb(size_t(8) * DT);
+    for (int l = 0; l < n_lat; ++l) {
+      const Geom& g = b.geo[l];
+      desc[l].a = make_dslash_args(g, 1, false, false);
+      desc[l].a.V = b.Vpad;
+      desc[l].tile0 = 0;
+      int cL[4];
+      for (int q = 0; q < 4; ++q) cL[q] = g.L[q] / b.blk[q];
+      for (int site = 0; site < g.V; ++site) {
+        int c[4], rem = site;
+        for (int q = 0; q < 4; ++q) {
+          c[q] = rem % g.L[q];
+          rem /= g.L[q];
+        }
+        int cj[4], ci[4];
+        for (int q = 0; q < 4; ++q) {
+          cj[q] = c[q] / b.blk[q];
+          ci[q] = c[q] % b.blk[q];
+        }
+        const int j = cj[0] + cL[0] * (cj[1] + cL[1] * (cj[2] + cL[2] * cj[3]));
+        const int ib = ci[0] + b.blk[0] * (ci[1] + b.blk[1] * (ci[2] + b.blk[2] * ci[3]));
+        gsite[size_t(b.aoff[l] + j) * b.nd + ib] = site;
+      }
+      for (int j = 0; j < b.d[l]; ++j) {
+        const int J = b.aoff[l] + j;
+        jinfo[2 * J] = l;
+        jinfo[2 * J + 1] = j;
+        int c[4], rem = j;
+        for (int q = 0; q < 4; ++q) {
+          c[q] = rem % cL[q];
+          rem /= cL[q];
+        }
+        for (int dir = 0; dir < 8; ++dir) {
+          const int mu = dir & 3, step = dir < 4 ? 1 : -1;
+          int cc[4] = {c[0], c[1], c[2], c[3]};
+          cc[mu] = (cc[mu] + step + cL[mu]) % cL[mu];
+          cnb[size_t(J) * 8 + dir] = b.aoff[l] + cc[0] + cL[0] * (cc[1] + cL[1] * (cc[2] + cL[2] * cc[3]));
+        }
+      }
+    }
+    auto upload = [&](DevBuf& d, const void* src, size_t bytes) {
+      d.alloc(bytes);
+      QMG_HIP(hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice));
+    };
+    upload(b.lat, desc.data(), desc.size() * sizeof(BatchLattice));
+    upload(b.Vl, b.V.data(), b.V.size() * sizeof(int));
+    upload(b.dl, b.d.data(), b.d.size() * sizeof(int));
+    upload(b.aoffd, b.aoff.data(), b.aoff.size() * sizeof(int));
+    upload(b.gsite, gsite.data(), gsite.size() * sizeof(int));
+    upload(b.jinfo, jinfo.data(), jinfo.size() * sizeof(int));
+    upload(b.cnb, cnb.data(), cnb.size() * sizeof(int));
+    // gauge fields: padded native FP64 (and FP32)
+    b.U64.alloc(size_t(n_lat) * 36 * b.Vpad * sizeof(double2));
+    for (int l = 0; l < n_lat; ++l) {
+      launch(k_b_pack_gauge, dim3(unsigned(b.Vpad / 256), 36), dim3(256), 0, stream, static_cast<const double2*>(U[l]),
+             b.U64.as<double2>() + size_t(l) * 36 * b.Vpad, b.V[l], b.Vpad);
+      QMG_LAUNCH_CHECK();
+    }
+    {
+      const double un = [&] {
+        RedWork rw;
+        DevBuf nr(sizeof(double));
+        Blas<double2>::norm2(b.U64.p, size_t(n_lat) * 36 * b.Vpad, 1, nr.as<double>(), rw, stream);
+        double v = 0;
+        QMG_HIP(hipMemcpyAsync(&v, nr.p, sizeof(double), hipMemcpyDeviceToHost, stream));
+        QMG_HIP(hipStreamSynchronize(stream));
+        return v;
+      }();
+      QMG_CHECK(std::isfinite(un), QMG_ENONFINITE, "gauge fields have non-finite entries");
+    }
+    if (b.inner == QMG_F32) {
+      b.Uin.alloc(size_t(n_lat) * 36 * b.Vpad * sizeof(float2));
+      launch_convert(b.U64.p, QMG_F64, b.Uin.p, QMG_F32, size_t(n_lat) * 36 * b.Vpad, stream);
+    }
+    batch_setup(b, *p, stream);
+    *out = h.release();
+  });
+}
+
+qmg_status qmg_batch_solve(const qmg_batch* h, const void* const* rhs, void* const* x, int32_t nrhs, double tol,
+                           int32_t max_outer, qmg_solve_info* info, hipStream_t stream) {
+  long stats[4] = {0, 0, 0, 0};
+  std::vector<double> rel;
+  double el = 0;
+  qmg_status rc = bguard([&] {
+    QMG_CHECK(h && rhs && x, QMG_EINVAL, "null argument");
+    QMG_CHECK(nrhs >= 1 && max_outer >= 1, QMG_EINVAL, "need nrhs >= 1 and max_outer >= 1");
+    QMG_CHECK(tol > 0 && tol < 1, QMG_EINVAL, "tol must be in (0, 1)");
+    const BatchDev& b = h->b;
+    for (int l = 0; l < b.nl; ++l) QMG_CHECK(rhs[l] && x[l], QMG_EINVAL, "right-hand side or solution %d is NULL", l);
+    const auto t0 = Clock::now();
+    const int ncol = b.nl * nrhs;
+    const size_t len = b.fine_len(), n = len * ncol;
+    DevBuf b64(n * sizeof(double2)), x64(n * sizeof(double2)), r64(n * sizeof(double2));
+    for (int l = 0; l < b.nl; ++l) {
+      launch(k_b_pack_spinor, dim3(unsigned(b.Vpad / 256), 12 * nrhs), dim3(256), 0, stream,
+             static_cast<const double2*>(rhs[l]), b64.as<double2>() + size_t(l) * nrhs * len, b.V[l], b.Vpad);
+      QMG_LAUNCH_CHECK();
+    }
+    RedWork rw;
+    DevBuf nr(2 * size_t(ncol) * sizeof(double));
+    Blas<double2>::norm2(b64.p, len, ncol, nr.as<double>() + ncol, rw, stream);
+    batch_solve(b, b64.p, x64.p, nrhs, tol, max_outer, stream, stats);
+    BatchOp D(b, QMG_F64, b.U64.p);
+    D.apply(x64.p, r64.p, ncol, stream);
+    Blas<double2>::axpby(1.0, b64.p, -1.0, r64.p, n, stream);
+    Blas<double2>::norm2(r64.p, len, ncol, nr.as<double>(), rw, stream);
+    std::vector<double> hn(2 * size_t(ncol));
+    QMG_HIP(hipMemcpyAsync(hn.data(), nr.p, hn.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    for (int l = 0; l < b.nl; ++l) {
+      launch(k_b_unpack_spinor, dim3(unsigned((b.V[l] + 255) / 256), 12 * nrhs), dim3(256), 0, stream,
+             x64.as<double2>() + size_t(l) * nrhs * len, static_cast<double2*>(x[l]), b.V[l], b.Vpad);
+      QMG_LAUNCH_CHECK();
+    }
+    QMG_HIP(hipStreamSynchronize(stream));
+    double worst = 0;
+    rel.resize(ncol);
+    for (int i = 0; i < ncol; ++i) {
+      rel[i] = hn[ncol + i] > 0 ? std::sqrt(hn[i] / hn[ncol + i]) : 0.0;
+      QMG_CHECK(std::isfinite(rel[i]), QMG_ENONFINITE, "non-finite final residual");
+      worst = std::max(worst, rel[i]);
+    }
+    el = secs(t0, Clock::now());
+    QMG_CHECK(worst <= tol, QMG_ENOCONV, "batched solve stopped at relative residual %.3e > tol %.3e", worst, tol);
+  });
+  if (info && h) {
+    const int ncol = h->b.nl * nrhs;
+    for (int i = 0; i < ncol; ++i) {
+      info[i] = qmg_solve_info{};
+      info[i].outer_iters = int(stats[0]);
+      info[i].refinements = int(stats[1]);
+      info[i].coarse_iters = int(stats[2]);
+      info[i].smoother_iters = int(stats[3]);
+      info[i].true_rel_res = i < int(rel.size()) ? rel[i] : -1.0;
+      info[i].seconds = el;
+    }
+  }
+  return rc;
+}
+
+qmg_status qmg_batch_query(const qmg_batch* h, int32_t lat, int32_t* n_agg, int32_t* rank) {
+  return bguard([&] {
+    QMG_CHECK(h && n_agg && rank, QMG_EINVAL, "null argument");
+    QMG_CHECK(lat >= 0 && lat < h->b.nl, QMG_EINVAL, "lattice index out of range");
+    *n_agg = h->b.d[lat];
+    *rank = h->b.k;
+  });
+}
+
+qmg_status qmg_batch_get_prolongator(const qmg_batch* h, int32_t lat, void* P, double* sigma, hipStream_t stream) {
+  return bguard([&] {
+    QMG_CHECK(h, QMG_EINVAL, "null handle");
+    const BatchDev& b = h->b;
+    QMG_CHECK(lat >= 0 && lat < b.nl, QMG_EINVAL, "lattice index out of range");
+    const size_t off = size_t(2) * b.aoff[lat], np = size_t(2) * b.d[lat];
+    if (P) {
+      HierarchyDev tmp;  // export in the CPU reference's row order, through the single-lattice layout
+      tmp.blk.nd = b.nd;
+      tmp.blk.N = b.N;
+      tmp.blk.d = b.d[lat];
+      tmp.k = b.k;
+      Borrowed hold(tmp.P64, b.P64.as<double2>() + off * b.k * b.N);
+      launch_export_P(tmp, P, stream);
+      QMG_HIP(hipStreamSynchronize(stream));
+    }
+    if (sigma) std::memcpy(sigma, b.sigma_h.data() + off * b.k, np * b.k * sizeof(double));
+  });
+}
+
+qmg_status qmg_batch_get_coarse(const qmg_batch* h, int32_t lat, void* Y, hipStream_t stream) {
+  return bguard([&] {
+    QMG_CHECK(h && Y, QMG_EINVAL, "null argument");
+    const BatchDev& b = h->b;
+    QMG_CHECK(lat >= 0 && lat < b.nl, QMG_EINVAL, "lattice index out of range");
+    HierarchyDev tmp;
+    tmp.blk.d = b.d[lat];
+    tmp.k = b.k;
+    const int m = 2 * b.k;
+    Borrowed hold(tmp.Y64, b.Y64.as<double2>() + size_t(b.aoff[lat]) * 9 * m * m);
+    launch_export_Y(tmp, Y, stream);
+    QMG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+qmg_status qmg_batch_setup_times(const qmg_batch* h, double* t) {
+  return bguard([&] {
+    QMG_CHECK(h && t, QMG_EINVAL, "null argument");
+    t[0] = h->b.t_smooth;
+    t[1] = h->b.t_svd;
+    t[2] = h->b.t_coarse;
+    t[3] = h->b.t_total;
+  });
+}
+
+void qmg_batch_destroy(qmg_batch* h) { delete h; }

@@ -311,6 +311,30 @@ __global__ __launch_bounds__(kBlock) void k_dslash_batched(const BatchLattice* _
   site_dslash<S, false, 1, DAG>(U[lo], in[lo], out[lo], b.a, site, rhs);
 }
 
+// Many lattices in padded layouts (one hierarchy over many small lattices): lattice l's links at
+// U + l * 36 Vpad ([4][9][Vpad]) and its nr spinors at in / out + l * nr * 12 Vpad
+// ([nr][12][Vpad]); lat[l].a carries the lattice's extents and coefficients with a.V = Vpad (the
+// stride).  Grid: nl * nr * ceil(Vpad / 256) workgroups; sites at and beyond the lattice's
+// volume are written as zeros, so every output column is zero-padded.
+template <class S, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_dslash_padded(const BatchLattice* __restrict__ lat, const S* __restrict__ U,
+                                                          const S* __restrict__ in, S* __restrict__ out, int nr,
+                                                          int ntile) {
+  const int wg = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = wg % ntile, col = wg / ntile;
+  const int l = col / nr, rhs = col - l * nr;
+  const DslashArgs& a = lat[l].a;
+  const int Vpad = a.V;
+  const int site = tile * kBlock + threadIdx.x;
+  if (site >= Vpad) return;
+  const size_t base = size_t(l) * nr * 12 * Vpad;
+  if (site >= a.L[0] * a.L[1] * a.L[2] * a.L[3]) {
+    for (int k = 0; k < 12; ++k) stc(out + base, sp_idx<false>(rhs, k, site, Vpad), cplx<ctype<S>>{0, 0});
+    return;
+  }
+  site_dslash<S, false, 1, DAG>(U + size_t(l) * 36 * Vpad, in + base, out + base, a, site, rhs);
+}
+
 // Native-layout kernel that walks along t.  Thread (spatial site, t-chunk, group of NR
 // right-hand sides) computes the TCH sites t0 .. t0+TCH-1 of its column for NR right-hand
 // sides; each link is loaded once for all NR of them.  The spinor of the next slice, loaded
@@ -1034,6 +1058,29 @@ void launch_dslash_batched(qmg_prec prec, const BatchLattice* lat_dev, int n_lat
       launch(k_dslash_batched<S, true>, dim3(total_tiles), dim3(kBlock), 0, st, lat_dev, n_lat, U, in, out);
     else
       launch(k_dslash_batched<S, false>, dim3(total_tiles), dim3(kBlock), 0, st, lat_dev, n_lat, U, in, out);
+  };
+  switch (prec) {
+    case QMG_F64: go(double2{}); break;
+    case QMG_F32: go(float2{}); break;
+    case QMG_BF16: go(cbf16{}); break;
+    case QMG_F16: go(chalf{}); break;
+  }
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_dslash_padded(qmg_prec prec, const BatchLattice* lat_dev, int nl, int nr, int Vpad, const void* U,
+                          const void* in, void* out, bool dagger, double bytes, double flops, hipStream_t st) {
+  TimedLaunch tl("dslash/padded", st, bytes, flops);
+  const int ntile = (Vpad + kBlock - 1) / kBlock;
+  const dim3 grid(unsigned(ntile) * unsigned(nl) * unsigned(nr));
+  auto go = [&](auto tag) {
+    using S = decltype(tag);
+    if (dagger)
+      launch(k_dslash_padded<S, true>, grid, dim3(kBlock), 0, st, lat_dev, static_cast<const S*>(U),
+             static_cast<const S*>(in), static_cast<S*>(out), nr, ntile);
+    else
+      launch(k_dslash_padded<S, false>, grid, dim3(kBlock), 0, st, lat_dev, static_cast<const S*>(U),
+             static_cast<const S*>(in), static_cast<S*>(out), nr, ntile);
   };
   switch (prec) {
     case QMG_F64: go(double2{}); break;

@@ -517,11 +517,11 @@ __global__ __launch_bounds__(T) void k_isvd_rotate_rows(double2* __restrict__ Ug
                                                         const double2* __restrict__ AB, IsvdArgs a) {
   __shared__ cd Ms[WM * MAXW];
   const int N = a.N, kp = a.kp, w = a.w, kn = a.kn, k = a.k, r = a.r;
-  const int p = blockIdx.y;
+  const int p = blockIdx.x;  // problems on x: their count may exceed the 65535 of a y extent
   const double2* ab = AB + size_t(p) * w * kn;
   for (int e = threadIdx.x; e < w * kn; e += T) Ms[e] = ld2(ab, e);
   __syncthreads();
-  const int row = blockIdx.x * T + threadIdx.x;
+  const int row = blockIdx.y * T + threadIdx.x;
   if (row >= N) return;
   double2* U = Ug + size_t(p) * k * N;
   const double2* Psi = Psig + size_t(p) * r * N;
@@ -580,31 +580,46 @@ void launch_rows(const IsvdArgs& a, int ncu, size_t lg, size_t lr, DevBuf& P64, 
   set_lds((const void*)k_isvd_rotate<NPF>, lr);
   const int grid = std::min(a.nprob, 4 * ncu);
   const int ntile = ((a.w + 1) / 2) * ((a.r + 1) / 2);
-  if (gram_on_mfma(a.w, a.r)) {
-    if (a.w <= 32) {
-      set_lds((const void*)k_isvd_gram_mfma<NPF, 2>, lg);
-      k_isvd_gram_mfma<NPF, 2><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+  const double Nn = double(a.N) * a.nprob;
+  double2* U = P64.as<double2>();
+  const double2* Psi = static_cast<const double2*>(blocks);
+  {
+    // two row passes over U (kp columns) and Psi (r columns); the Gram products of both passes
+    // and the residual R = Psi - U X
+    TimedLaunch tl("isvd/gram", st, Nn * 16.0 * 2.0 * (a.kp + a.r),
+                   Nn * 8.0 * (2.0 * double(a.w) * a.r + double(a.kp) * a.r));
+    auto go = [&](auto kern) {
+      set_lds((const void*)kern, lg);
+      launch(kern, dim3(grid), dim3(T), uint32_t(lg), st, U, Psi, small.as<double2>(), a);
+    };
+    if (gram_on_mfma(a.w, a.r)) {
+      if (a.w <= 32) go(k_isvd_gram_mfma<NPF, 2>);
+      else go(k_isvd_gram_mfma<NPF, 4>);
+    } else if (ntile <= T) {
+      go(k_isvd_gram<NPF, 1>);
     } else {
-      set_lds((const void*)k_isvd_gram_mfma<NPF, 4>, lg);
-      k_isvd_gram_mfma<NPF, 4><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
+      go(k_isvd_gram<NPF, 4>);
     }
-  } else if (ntile <= T) {
-    set_lds((const void*)k_isvd_gram<NPF, 1>, lg);
-    k_isvd_gram<NPF, 1><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
-  } else {
-    set_lds((const void*)k_isvd_gram<NPF, 4>, lg);
-    k_isvd_gram<NPF, 4><<<grid, T, lg, st>>>(P64.as<double2>(), (const double2*)blocks, small.as<double2>(), a);
   }
   QMG_LAUNCH_CHECK();
-  k_isvd_small<<<a.nprob, TW, ls, st>>>(small.as<double2>(), sigma_dev.as<double>(), AB.as<double2>(), a);
+  {
+    // the w x w core per problem: Cholesky and one-sided Jacobi, counted as six sweeps of
+    // w (w - 1) / 2 rotations of two length-w columns of K^dag and of the rotation accumulator
+    const double w3 = double(a.w) * a.w * a.w;
+    TimedLaunch tl("isvd/small", st, double(a.nprob) * (small_stride(a.kp, a.r) + double(a.w) * a.kn) * 16.0,
+                   double(a.nprob) * 120.0 * w3);
+    launch(k_isvd_small, dim3(a.nprob), dim3(TW), uint32_t(ls), st, static_cast<const double2*>(small.as<double2>()),
+           sigma_dev.as<double>(), AB.as<double2>(), a);
+  }
   QMG_LAUNCH_CHECK();
-  const dim3 rgrid((a.N + T - 1) / T, a.nprob);
-  if (a.w <= 32) {
-    k_isvd_rotate_rows<32><<<rgrid, T, 0, st>>>(P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
-  } else if (a.w <= 48) {
-    k_isvd_rotate_rows<48><<<rgrid, T, 0, st>>>(P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
-  } else {
-    k_isvd_rotate<NPF><<<grid, T, lr, st>>>(P64.as<double2>(), (const double2*)blocks, AB.as<double2>(), a);
+  {
+    // U_new = U A + Psi B in place: U and Psi read once, U_new written
+    TimedLaunch tl("isvd/rotate", st, Nn * 16.0 * (a.kp + a.r + a.kn), Nn * 8.0 * double(a.w) * a.kn);
+    const dim3 rgrid(a.nprob, (a.N + T - 1) / T);
+    const double2* ABc = AB.as<double2>();
+    if (a.w <= 32) launch(k_isvd_rotate_rows<32>, rgrid, dim3(T), 0, st, U, Psi, ABc, a);
+    else if (a.w <= 48) launch(k_isvd_rotate_rows<48>, rgrid, dim3(T), 0, st, U, Psi, ABc, a);
+    else launch(k_isvd_rotate<NPF>, dim3(grid), dim3(T), uint32_t(lr), st, U, Psi, ABc, a);
   }
   QMG_LAUNCH_CHECK();
 }
@@ -633,15 +648,10 @@ int isvd_stream(int nprob, int N, int k, DevBuf& P64, const void* blocks, int r,
   DevBuf AB(size_t(a.nprob) * w * kn * sizeof(double2));
   // algorithmic: read U (kp cols) and Psi (r cols) in the two Gram passes and the rotation,
   // write U (kn cols); flops of the Gram passes, the residual and the rotation
-  const double Nn = double(a.N) * a.nprob;
-  {
-    TimedLaunch tl("isvd", st, Nn * 16.0 * (3.0 * (kp + r) + kn),
-                   Nn * 8.0 * (2.0 * double(w) * r + double(kp) * r + double(w) * kn), false);
-    const int need = (w * CH + T - 1) / T;  // prefetch registers needed
-    if (need <= 4) launch_rows<4>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
-    else if (need <= 8) launch_rows<8>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
-    else launch_rows<PF>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
-  }
+  const int need = (w * CH + T - 1) / T;  // prefetch registers needed
+  if (need <= 4) launch_rows<4>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
+  else if (need <= 8) launch_rows<8>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
+  else launch_rows<PF>(a, ncu, lg, lr, P64, blocks, small, AB, sigma_dev, ls, st);
   QMG_HIP(hipStreamSynchronize(st));  // scratch buffers are released on return
   return kn;
 }

@@ -985,6 +985,53 @@ template struct Blas<float2>;
 template struct Blas<cbf16>;
 template struct Blas<chalf>;
 
+// s-step form of the smoothing GMRES(8) cycles (storage below FP64): per cycle, from the
+// residual r, the shifted basis p_0 = r, p_{i+1} = (D - d) p_i (d the diagonal term m + 1 + 3/xi,
+// which centres the spectrum and keeps the powers better conditioned; the Krylov space is
+// that of D) is formed with the same eight operator applications as eight GMRES steps, one pass
+// gives every <p_i, p_j>, and the 8 x 8 normal equations of min ||r - D sum_j c_j p_j|| are
+// solved in FP64 on the device: the minimisation of GMRES(8) over the same space, with one
+// reduction instead of eight Gram-Schmidt steps over a growing basis.  The next cycle's residual
+// r - sum_j c_j (p_{j+1} + d p_j) comes from the basis, without another operator application.
+template <class S>
+void smooth_sstep(size_t len, double d, LinOp& D, LinOp* H, int r, int n_iter, const void* b, void* x, DevBuf& basis,
+                  DevBuf& coef, DevBuf& part, DevBuf& e, hipStream_t st) {
+  constexpr qmg_prec P = StoreTraits<S>::prec;
+  constexpr int s = 8;
+  const size_t n = len * r, vb = n * sizeof(S);
+  basis.ensure((s + 1) * vb);
+  coef.ensure(size_t(s) * r * sizeof(double2));
+  e.ensure(vb);
+  auto vec = [&](int i) { return static_cast<char*>(basis.p) + size_t(i) * vb; };
+  Blas<S>::zero(x, n, st);
+  Blas<S>::copy(b, vec(0), n, st);
+  for (int cyc = 0; cyc < n_iter / s; ++cyc) {
+    for (int i = 0; i < s; ++i) {
+      if (H) {
+        H->apply(vec(i), vec(i + 1), r, st);  // the hopping part: D - d directly
+      } else {
+        D.apply(vec(i), vec(i + 1), r, st);
+        Blas<S>::axpby(-d, vec(i), 1.0, vec(i + 1), n, st);
+      }
+    }
+    launch_sstep_coeffs(P, basis.p, s + 1, len, r, coef.as<double2>(), part, st, d);
+    Blas<S>::zero(e.p, n, st);
+    Blas<S>::axpy_multi(basis.p, n, s, coef.as<double2>(), 1.0, e.p, len, r, st);  // e = sum_j c_j p_j
+    Blas<S>::axpby(1.0, e.p, 1.0, x, n, st);
+    if (cyc + 1 < n_iter / s) {  // r <- r - sum_j c_j p_{j+1} - d e
+      Blas<S>::axpy_multi(vec(1), n, s, coef.as<double2>(), -1.0, vec(0), len, r, st);
+      Blas<S>::axpby(-d, e.p, 1.0, vec(0), n, st);
+    }
+  }
+}
+
+template void smooth_sstep<float2>(size_t, double, LinOp&, LinOp*, int, int, const void*, void*, DevBuf&, DevBuf&,
+                                   DevBuf&, DevBuf&, hipStream_t);
+template void smooth_sstep<cbf16>(size_t, double, LinOp&, LinOp*, int, int, const void*, void*, DevBuf&, DevBuf&,
+                                  DevBuf&, DevBuf&, hipStream_t);
+template void smooth_sstep<chalf>(size_t, double, LinOp&, LinOp*, int, int, const void*, void*, DevBuf&, DevBuf&,
+                                  DevBuf&, DevBuf&, hipStream_t);
+
 // ---------------------------------------------------------------------------------------
 // GMRES
 

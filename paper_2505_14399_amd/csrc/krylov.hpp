@@ -128,4 +128,11 @@ class Gmres {
   int nrhs_ = 0, restart_ = 0;
 };
 
+// s-step form of n_iter (a multiple of 8) restarted GMRES(8) steps on D x = b from zero, with the
+// shifted basis p_{i+1} = (D - d) p_i (H, when given, applies D - d directly); r right-hand sides
+// of len complex numbers; the buffers are work space (sized here).  Instantiated below FP64.
+template <class S>
+void smooth_sstep(size_t len, double d, LinOp& D, LinOp* H, int r, int n_iter, const void* b, void* x, DevBuf& basis,
+                  DevBuf& coef, DevBuf& part, DevBuf& e, hipStream_t st);
+
 }  // namespace qmg

@@ -146,6 +146,9 @@ void launch_export_P(const HierarchyDev& h, void* out, hipStream_t st);
 void launch_export_Y(const HierarchyDev& h, void* out, hipStream_t st);
 // Philox4x32-10 Gaussian test vectors into native FP64 [n][12][V]
 void launch_philox_native(const Geom& g, uint64_t seed, int v0, int n, void* out, hipStream_t st);
+// the same test vectors for nl lattices of volumes Vl (device int[nl]) in the padded layout
+// [l][n][12][Vpad] (zero beyond each lattice's volume)
+void launch_philox_padded(uint64_t seed, int v0, int n, int nl, const int* Vl, int Vpad, void* out, hipStream_t st);
 // link force: canonical FP64 x, lambda -> canonical FP64 dU
 void launch_link_force(const Geom& g, const void* x, const void* lam, void* dU, int nrhs, hipStream_t st);
 

@@ -321,6 +321,9 @@ struct BatchLattice {
 void launch_dslash_batched(qmg_prec prec, const BatchLattice* lat_dev, int n_lat, int total_tiles,
                            const void* const* U, const void* const* in, void* const* out, bool dagger,
                            double bytes, double flops, hipStream_t st);
+// many lattices in padded layouts (see k_dslash_padded): nl lattices of nr spinors each
+void launch_dslash_padded(qmg_prec prec, const BatchLattice* lat_dev, int nl, int nr, int Vpad, const void* U,
+                          const void* in, void* out, bool dagger, double bytes, double flops, hipStream_t st);
 void set_dslash_variant(int v);
 
 // out = D in (or D^dag) ; U in the same storage type and layout as the spinors

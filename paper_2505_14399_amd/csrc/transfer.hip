@@ -547,6 +547,32 @@ __global__ void k_philox(double2* __restrict__ out, uint64_t seed, int v0, int V
   }
 }
 
+// The same generator for many lattices in padded layouts: vector v of lattice l (blockIdx.z)
+// at [(l n + v) 12 + comp][Vpad]; sites at and beyond the lattice's volume are zero.
+__global__ void k_philox_padded(double2* __restrict__ out, uint64_t seed, int v0, int n, const int* __restrict__ Vl,
+                                int Vpad) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int vi = blockIdx.y, l = blockIdx.z;
+  if (site >= Vpad) return;
+  double2* o = out + size_t(l) * n * 12 * Vpad;
+  if (site >= Vl[l]) {
+    for (int c = 0; c < 12; ++c) o[(size_t(vi) * 12 + c) * Vpad + site] = make_double2(0.0, 0.0);
+    return;
+  }
+  const uint32_t k0 = uint32_t(seed & 0xffffffffu), k1 = uint32_t(seed >> 32);
+  const double twopi = 2.0 * M_PI;
+  for (int g = 0; g < 6; ++g) {
+    uint32_t c[4] = {uint32_t(site), uint32_t(g), uint32_t(v0 + vi), 0u};
+    philox4x32_10(c, k0, k1);
+    double u[4];
+    for (int q = 0; q < 4; ++q) u[q] = (double(c[q]) + 0.5) * 0x1p-32;
+    const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    const double t0 = twopi * u[1], t1 = twopi * u[3];
+    o[(size_t(vi) * 12 + 2 * g) * Vpad + site] = make_double2(r0 * cos(t0), r0 * sin(t0));
+    o[(size_t(vi) * 12 + 2 * g + 1) * Vpad + site] = make_double2(r1 * cos(t1), r1 * sin(t1));
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // link force, canonical FP64
 __constant__ double2 c_gamma[4][16];  // gamma_mu, row-major 4x4
@@ -1017,6 +1043,14 @@ void launch_export_Y(const HierarchyDev& h, void* out, hipStream_t st) {
   {
     TimedLaunch tl_("export", st, 2.0 * double(n) * 16, 0.0);
     launch(k_export_Y, dim3(cdiv(n, 256)), dim3(256), 0, st, h.Y64.as<double2>(), (double2*)out, m, n);
+  }
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_philox_padded(uint64_t seed, int v0, int n, int nl, const int* Vl, int Vpad, void* out, hipStream_t st) {
+  {
+    TimedLaunch tl_("setup/philox", st, double(nl) * n * Vpad * 12 * 16, 0.0);
+    launch(k_philox_padded, dim3(cdiv(Vpad, 256), n, nl), dim3(256), 0, st, (double2*)out, seed, v0, n, Vl, Vpad);
   }
   QMG_LAUNCH_CHECK();
 }
