@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batched32x64")
+    ap.add_argument("--no-small", action="store_true",
+                    help="leave out the 64 small lattices of the batched workload")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the setup / mixed / FP64 solve lines of the other lattices (16^3x32, 24^3x64)")
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -552,7 +554,7 @@ def _host_cores():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(w, counts, U=None):
+def cpu_baseline(w, counts, U=None, small=None):
     """The CPU oracle on this host, on a bounded sample of the workload (its unit operations at
     the workload's shapes, each timed directly), composed into an estimate of the oracle's time
     for the GPU solve's own operation counts (the oracle is never run on the whole solve here)."""
@@ -604,6 +606,22 @@ def cpu_baseline(w, counts, U=None):
     t_vec = tm(lambda: (np.vdot(a, b), b + 0.5 * a), 3)
     est = (counts["dslash"] * t_D + counts["coarse_apply"] * t_Dc + counts["restrict"] * t_RP
            + counts["vector_ops"] * t_vec)
+    small_txt = ""
+    if small:  # the small lattices: the oracle's D apply per size times the fine applies of their solve
+        from collections import Counter
+        sizes = Counter(d[0] for d, _, _ in small["spec"])
+        t_L = {}
+        for L in sizes:
+            dL = (L,) * 4
+            UL = fields.random_gauge(dL, 0.3, 1)
+            pL = fields.gaussian_spinor(dL, 1, 1)[0]
+            t_L[L] = tm(lambda: wilson.apply_wilson(UL, pL, 0.05, 1.0, -1, dL), 2)
+        applies = small["outer"] * (1 + 8) + small["refinements"] + 1
+        est_small = applies * sum(n * t_L[L] for L, n in sizes.items())
+        est += est_small
+        small_txt = (f"; plus the {len(small['spec'])} small lattices: oracle D apply per size "
+                     f"{ {L: round(t, 4) for L, t in t_L.items()} } s x {applies} fine applies each (their batched "
+                     f"solve's outer iterations x 9 + refinements; coarse work not counted) = {est_small:.1f}s")
     blas = [f"{p.get('internal_api')}:{p.get('num_threads')}" for p in threadpool_info()]
     ncpu = _host_cores()
     ns = w["n_test"] // w["batch"]
@@ -617,7 +635,8 @@ def cpu_baseline(w, counts, U=None):
                    f"scaled), fine vector op {t_vec:.4f}s; value = these times x the GPU solve's operation counts "
                    f"{counts} (coarse Schur launches counted as the fraction of a coarse apply they stream); oracle "
                    f"setup estimate {setup_est:.1f}s (smoothing applies + {ns} streams); BLAS/LAPACK pools "
-                   f"{blas} over {ncpu} affinity cores, stencil and vector arithmetic single-threaded (NumPy)"),
+                   f"{blas} over {ncpu} affinity cores, stencil and vector arithmetic single-threaded (NumPy)"
+                   f"{small_txt}"),
     }
 
 
@@ -751,6 +770,19 @@ def main():
                     n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"],
                     c_sw=w.get("c_sw"))
     eo_smoother, coarse_eo = make_solver(args, q)
+    # the 64 independent small lattices of the batched workload: one hierarchy object whose
+    # setups and solves run in shared launches over all of them
+    small = None
+    if w.get("small_lattices") and not args.no_small:
+        sw = workloads.SMALL_LATTICES
+        spec = workloads.small_lattices()
+        small = {"spec": spec, "lats": [q.Lattice(d, m, sw["xi"], sw["bc_t"]) for d, m, _ in spec],
+                 "U_host": [fields.random_gauge(d, sw["eps"], sw["seed"], t) for d, _, t in spec],
+                 "b": [torch.from_numpy(fields.gaussian_spinor(d, 1, sw["seed"], tag=500 + i)).cuda()
+                       for i, (d, _, _) in enumerate(spec)],
+                 "kw": dict(block=sw["block"], n_test=sw["n_test"], batch=sw["batch"], rank=sw["rank"],
+                            n_setup_iter=16, seed=sw["seed"], inner=sw["inner"])}
+        small["U"] = [torch.from_numpy(u).cuda() for u in small["U_host"]]
 
     def step():
         torch.cuda.synchronize()
@@ -763,21 +795,37 @@ def main():
         x, info = q.mg_solve(mg, b, tol=args.tol)
         t2 = time.perf_counter()
         mg.close()
-        return t1 - t0, t2 - t1, info
+        part = {"setup_s": t1 - t0, "solve_s": t2 - t1}
+        if small:
+            t3 = time.perf_counter()
+            bt = q.batch_setup(small["lats"], small["U"], **small["kw"])
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            _, sinf = q.batch_solve(bt, small["b"], tol=args.tol)
+            t5 = time.perf_counter()
+            bt.close()
+            part.update(small_setup_s=t4 - t3, small_solve_s=t5 - t4,
+                        small_info={"outer_iters": sinf[0][0]["outer_iters"], "refinements": sinf[0][0]["refinements"],
+                                    "coarse_iters": sinf[0][0]["coarse_iters"],
+                                    "true_rel_res": max(i[0]["true_rel_res"] for i in sinf)})
+            info = info + [{"true_rel_res": part["small_info"]["true_rel_res"]}]
+        return part["setup_s"] + part.get("small_setup_s", 0.0), part["solve_s"] + part.get("small_solve_s", 0.0), \
+            info, part
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     # about one launch in 8 of each kernel family is timed with events attached to the dispatch
     q.timing_enable(True, every=TIMING_SAMPLE)
-    setups, solves, infos = [], [], []
+    setups, solves, infos, parts = [], [], [], []
     torch.cuda.synchronize()
     T0 = time.perf_counter()
     for _ in range(args.steps):
-        ts, tv, info = step()
+        ts, tv, info, part = step()
         setups.append(ts)
         solves.append(tv)
         infos.append(info)
+        parts.append(part)
     torch.cuda.synchronize()
     T1 = time.perf_counter()
     fams = family_table(q.timing_families(), args.steps)
@@ -786,6 +834,7 @@ def main():
         for i in info:
             if i["true_rel_res"] > args.tol:
                 raise SystemExit(f"solve did not reach {args.tol}: {i}")
+    info = infos[-1][:nrhs]
 
     # operation counts of one mixed solve (for the CPU baseline), from an untimed solve
     mg = q.mg_setup_stream_chiral_svd(lat, U, **setup_kw)
@@ -828,8 +877,16 @@ def main():
                         "coarse_iters": oc[0]["coarse_iters"], "true_rel_res": max(i["true_rel_res"] for i in oc)}
     mg.close()
 
-    # FP64 path on the same lattice (own FP64 setup, the same smoother and coarse solve; untimed)
+    # FP64 path on the same lattices (own FP64 setup, the same smoother and coarse solve; untimed)
     fp64_solve = None
+    if not args.no_fp64 and w["inner"] != "f64" and small:
+        bt = q.batch_setup(small["lats"], small["U"], **dict(small["kw"], inner="f64"))
+        q.batch_solve(bt, small["b"], tol=args.tol)
+        t0 = time.perf_counter()
+        _, s64 = q.batch_solve(bt, small["b"], tol=args.tol)
+        small_fp64 = {"s": time.perf_counter() - t0, "outer_iters": s64[0][0]["outer_iters"],
+                      "true_rel_res": max(i[0]["true_rel_res"] for i in s64)}
+        bt.close()
     if not args.no_fp64 and w["inner"] != "f64":
         mg64 = q.mg_setup_stream_chiral_svd(lat, U, **dict(setup_kw, inner="f64"))
         mg64.set_smoother(eo=eo_smoother, sstep=True)
@@ -843,6 +900,9 @@ def main():
         mg64.close()
         fp64_solve = {"s": float(np.median(ts64)), "outer_iters": [i["outer_iters"] for i in i64],
                       "coarse_iters": i64[0]["coarse_iters"], "true_rel_res": max(i["true_rel_res"] for i in i64)}
+        if small:
+            fp64_solve = {"s": fp64_solve["s"] + small_fp64["s"], "lattice32x64": fp64_solve,
+                          "small_lattices": small_fp64}
     del U
     torch.cuda.empty_cache()
 
@@ -854,7 +914,6 @@ def main():
     op_ms = sum(fams[f]["avg_launch_ms"] * fams[f]["launches_timed"] for f in op)
     op_bytes = sum(fams[f]["bytes_per_launch"] * fams[f]["launches_timed"] for f in op)
     op_n = sum(fams[f]["launches_timed"] for f in op)
-    info = infos[-1]
     res = {
         "metric": "MG solve s to rel.res 1e-10 (mixed vs FP64); dslash HBM GB/s; setup s",
         "value": float(np.median(solves)),
@@ -876,8 +935,20 @@ def main():
                    "smoother": "even-odd GMRES(8), s-step form" if eo_smoother else "GMRES(8)",
                    "coarse_solve": "GMRES(32) on the even-odd Schur complement of D_c" if ceo_on
                    else "GMRES(32) on D_c",
+                   **({"small_lattices": "64 lattices L^4, L in {8, 10, 12}, masses uniform in [0.01, 0.1], eps 0.3, "
+                                         "2^4 blocks, 16 / 4 / 8, FP32 inner, one Gaussian rhs each, all in one "
+                                         "batched hierarchy"} if small else {}),
                    **({"c_sw": list(w["c_sw"])} if w.get("c_sw") else {})},
         "setup_s": float(np.median(setups)),
+        "parts": {"lattice32x64" if small else w["name"]: {
+                      "setup_s": float(np.median([p["setup_s"] for p in parts])),
+                      "solve_s": float(np.median([p["solve_s"] for p in parts]))},
+                  **({"small_lattices": {
+                      "lattices": len(small["spec"]), "sites": int(sum(d[0] ** 4 for d, _, _ in small["spec"])),
+                      "extents": "L^4, L in {8, 10, 12}", "mass_range": [0.01, 0.1],
+                      "setup_s": float(np.median([p["small_setup_s"] for p in parts])),
+                      "solve_s": float(np.median([p["small_solve_s"] for p in parts])),
+                      **parts[-1]["small_info"]}} if small else {})},
         "solve_fp64": fp64_solve,
         "solve_other_smoother": other_solve,
         "solve_other_coarse": other_coarse,
@@ -906,7 +977,11 @@ def main():
     if not args.no_evenodd and not w.get("c_sw"):
         res["evenodd"] = evenodd_leg(args)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, cnt, U_host)
+        sm = None
+        if small:
+            sm = {"spec": small["spec"], "outer": parts[-1]["small_info"]["outer_iters"],
+                  "refinements": parts[-1]["small_info"]["refinements"]}
+        res["cpu_baseline"] = cpu_baseline(w, cnt, U_host, sm)
     print(json.dumps(res), flush=True)
 
 

@@ -480,8 +480,10 @@ void qmg_batch_destroy(qmg_batch* b);
  * "dslash/dir", "dslash/canonical", "dslash/batched", "clover/...", "evenodd/hop",
  * "coarse_apply", "coarse_eo", "prolong", "restrict", "level_..."), the Krylov vector kernels
  * ("blas/mdot_norm", "blas/axpy_scale", "blas/axpy_multi", ..., "krylov/givens", "sstep/..."),
- * the setup ("setup/philox", "setup/gather", "isvd/...", "coarse_build", ...) and layout
- * conversions ("layout/...", "eo_layout/...").  0 stops recording.  qmg_timing_query returns, for one family, the launches timed, their
+ * the setup ("setup/philox", "setup/gather", "isvd/...", "coarse_build", ...), layout
+ * conversions ("layout/...", "eo_layout/...") and the many-lattice hierarchy ("batch/dslash",
+ * "batch/prolong", "batch/restrict", "batch/coarse_apply", "batch/coarse_build", "batch/gather",
+ * "batch/philox").  0 stops recording.  qmg_timing_query returns, for one family, the launches timed, their
  * summed duration (ms, it synchronizes on the events) and their summed algorithmic bytes and
  * flops; a name without '/' also sums its sub-families ("dslash").  Errors: EINVAL (n < 0). */
 qmg_status qmg_timing_enable(int32_t on);

@@ -12,13 +12,8 @@
 // [J][9][2k][2k] are the per-lattice arrays of a single hierarchy concatenated, so the streaming
 // SVD runs over all of them in its usual launches.
 //
-// The Galerkin blocks Y_s(j) = P_j^dag D P_{j+s} (Eq. (5)) are formed by probing: the coarse
-// lattice of every lattice is coloured so that an aggregate and its eight neighbours all have
-// different colours; for colour c and coarse component q the vector that is 1 on component q of
-// every aggregate of colour c is prolonged, the fine operator applied and the result restricted,
-// and the restricted value on aggregate j' is column q of Y_s(j'), s the slot of the unique
-// colour-c aggregate in the neighbourhood of j'.  In FP64 this is R D P to rounding, with the
-// boundary signs and the diagonal term included by the fine operator itself.
+// The Galerkin blocks Y_s(j) = P_j^dag D P_{j+s} (Eq. (5)) are formed directly from the
+// prolongator and the links, one workgroup per (aggregate, slot), in FP64.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -154,27 +149,117 @@ __global__ __launch_bounds__(64) void k_b_coarse_apply(const S* __restrict__ Y, 
   stc(out, ob + row, acc);
 }
 
-// probing vectors: component q0 + q' of every aggregate of colour c is 1 in column (l, q')
-__global__ void k_b_probe_scatter(double2* __restrict__ vc, const int* __restrict__ colour, int c, int q0, int nq,
-                                  const int* __restrict__ jinfo, int dmax, int m, int DT) {
-  const int J = blockIdx.x * 256 + threadIdx.x;
-  if (J >= DT || colour[J] != c) return;
-  const int l = jinfo[2 * J], j = jinfo[2 * J + 1];
-  for (int q = 0; q < nq; ++q) vc[((size_t(l) * nq + q) * dmax + j) * m + q0 + q] = make_double2(1.0, 0.0);
+// Galerkin blocks directly (Eq. (5)): Y_s(J) = sum over the sites x of J of P_J(x)^dag W_s(x),
+// W_s(x) = sum of H P_J'(x') over the hops x -> x' of slot s, H the hop term of D
+// (-1/2 c_mu s_mu (1 -+ gamma_mu) (x) U); slot 0 holds the diagonal term and the hops that stay
+// inside the block, slot 1 + dir the hops in direction dir that leave it (every coarse extent is
+// >= 3, so such a hop lands in the neighbour aggregate cnb[J][dir]).  One workgroup per
+// (aggregate J, slot s) takes the sites of J in batches of nb = 256 / 2k: thread (site, column c)
+// forms column c of W_s(x) (12 x 2k) in LDS, then thread (row, col) adds
+// sum over the batch's sites and the six components of row's chirality of conj(P_J(x)) W_s(x).
+// P_J(x) is the 12 x 2k matrix of the rows of site x: chirality alpha's columns are nonzero on its
+// six components only.
+__constant__ double2 c_bgamma[4][16];  // gamma_mu (chiral basis), row-major 4 x 4
+
+__device__ inline cplx<double> b_p(const double2* __restrict__ P, int J, int comp, int col, int ib, int k, int nd,
+                                   int N) {
+  const int a = col / k, i = col - a * k;
+  if (comp / 6 != a) return {0.0, 0.0};
+  const double2 v = P[((size_t(J) * 2 + a) * k + i) * N + (comp - 6 * a) * nd + ib];
+  return {v.x, v.y};
 }
 
-// columns q0 .. q0 + nq - 1 of Y_s(J') from the restricted probes, for the slots whose aggregate
-// has colour c
-__global__ void k_b_probe_extract(const double2* __restrict__ u, double2* __restrict__ Y, const int* __restrict__ colour,
-                                  int c, int q0, int nq, const int* __restrict__ cnb, const int* __restrict__ jinfo,
-                                  int dmax, int m) {
-  const int Jp = blockIdx.x, s = blockIdx.y;
-  const int J = s == 0 ? Jp : cnb[size_t(Jp) * 8 + s - 1];
-  if (colour[J] != c) return;
-  const int l = jinfo[2 * Jp], jp = jinfo[2 * Jp + 1];
-  for (int t = threadIdx.x; t < nq * m; t += blockDim.x) {
-    const int q = t / m, row = t - q * m;
-    Y[((size_t(Jp) * 9 + s) * m + q0 + q) * m + row] = u[((size_t(l) * nq + q) * dmax + jp) * m + row];
+__global__ __launch_bounds__(256) void k_b_galerkin(const double2* __restrict__ U, const double2* __restrict__ P,
+                                                    double2* __restrict__ Y, const int* __restrict__ gsite,
+                                                    const int* __restrict__ jinfo, const int* __restrict__ cnb,
+                                                    const int* __restrict__ aoff, const BatchLattice* __restrict__ lat,
+                                                    int b0, int b1, int b2, int b3, int nd, int N, int k) {
+  __shared__ cplx<double> W[256 * 12];  // [site in batch][component][column]
+  const int J = blockIdx.x, s = blockIdx.y, m = 2 * k, tid = threadIdx.x;
+  const int nb = 256 / m;
+  const int l = jinfo[2 * J];
+  const DslashArgs& a = lat[l].a;
+  const int L[4] = {a.L[0], a.L[1], a.L[2], a.L[3]}, bb[4] = {b0, b1, b2, b3};
+  const int Vpad = a.V;
+  const double2* Ul = U + size_t(l) * 36 * Vpad;
+  constexpr int kPer = (4 * kMaxRank * kMaxRank + 255) / 256;  // (row, col) pairs per thread
+  cplx<double> acc[kPer];
+  for (int q = 0; q < kPer; ++q) acc[q] = {0.0, 0.0};
+  for (int ib0 = 0; ib0 < nd; ib0 += nb) {
+    const int nbs = min(nb, nd - ib0);
+    __syncthreads();  // the previous batch's W is no longer read
+    if (tid < nbs * m) {
+      const int sb = tid / m, col = tid - sb * m, ib = ib0 + sb;
+      const int x = gsite[size_t(J) * nd + ib];
+      int c[4], rem = x;
+      for (int q = 0; q < 4; ++q) {
+        c[q] = rem % L[q];
+        rem /= L[q];
+      }
+      cplx<double> w[12];
+      for (int comp = 0; comp < 12; ++comp)
+        w[comp] = s == 0 ? a.diag_d * b_p(P, J, comp, col, ib, k, nd, N) : cplx<double>{0.0, 0.0};
+      for (int dir = (s == 0 ? 0 : s - 1); dir < (s == 0 ? 8 : s); ++dir) {
+        const int mu = dir & 3;
+        const bool fwd = dir < 4;
+        int cn[4] = {c[0], c[1], c[2], c[3]};
+        cn[mu] = (cn[mu] + (fwd ? 1 : -1) + L[mu]) % L[mu];
+        int cj[4], ci[4];
+        for (int q = 0; q < 4; ++q) {
+          cj[q] = cn[q] / bb[q];
+          ci[q] = cn[q] - cj[q] * bb[q];
+        }
+        const int Jn = aoff[l] + cj[0] + (L[0] / bb[0]) * (cj[1] + (L[1] / bb[1]) * (cj[2] + (L[2] / bb[2]) * cj[3]));
+        if (s == 0 ? Jn != J : (Jn == J || Jn != cnb[size_t(J) * 8 + dir])) continue;
+        const int ibn = ci[0] + bb[0] * (ci[1] + bb[1] * (ci[2] + bb[2] * ci[3]));
+        const int xn = cn[0] + L[0] * (cn[1] + L[1] * (cn[2] + L[2] * cn[3]));
+        // boundary sign: t-hops across t = Lt - 1 <-> 0 with antiperiodic time
+        const bool wrap = mu == 3 && ((fwd && c[3] == L[3] - 1) || (!fwd && c[3] == 0));
+        const double coef = -0.5 * a.cw_d[mu] * ((wrap && a.bc_t < 0) ? -1.0 : 1.0);
+        // spin: h = (1 -+ gamma_mu) v; colour: U_mu(x) h (forward) or U_mu(x - mu)^dag h (backward)
+        cplx<double> v[12], h[12];
+        for (int comp = 0; comp < 12; ++comp) v[comp] = b_p(P, Jn, comp, col, ibn, k, nd, N);
+        const double sg = fwd ? -1.0 : 1.0;
+        for (int sp = 0; sp < 4; ++sp)
+          for (int cc = 0; cc < 3; ++cc) {
+            cplx<double> t = v[3 * sp + cc];
+            for (int tp = 0; tp < 4; ++tp) {
+              const double2 g = c_bgamma[mu][sp * 4 + tp];
+              if (g.x != 0.0 || g.y != 0.0) t += sg * (cplx<double>{g.x, g.y} * v[3 * tp + cc]);
+            }
+            h[3 * sp + cc] = t;
+          }
+        const int ls = fwd ? x : xn;
+        for (int ca = 0; ca < 3; ++ca)
+          for (int cb = 0; cb < 3; ++cb) {
+            const double2 ut = fwd ? Ul[(size_t(mu) * 9 + 3 * ca + cb) * Vpad + ls]
+                                   : Ul[(size_t(mu) * 9 + 3 * cb + ca) * Vpad + ls];
+            const cplx<double> u = {ut.x, fwd ? ut.y : -ut.y};
+            for (int sp = 0; sp < 4; ++sp) w[3 * sp + ca] += coef * (u * h[3 * sp + cb]);
+          }
+      }
+      for (int comp = 0; comp < 12; ++comp) W[(sb * 12 + comp) * m + col] = w[comp];
+    }
+    __syncthreads();
+    for (int q = 0; q < kPer; ++q) {
+      const int t = tid + 256 * q;
+      if (t >= m * m) break;
+      const int row = t / m, col = t - row * m, ar = row / k, ir = row - ar * k;
+      const double2* Pr = P + ((size_t(J) * 2 + ar) * k + ir) * N;
+      cplx<double> sum = {0.0, 0.0};
+      for (int sb = 0; sb < nbs; ++sb)
+        for (int c6 = 0; c6 < 6; ++c6) {
+          const double2 pv = Pr[c6 * nd + ib0 + sb];
+          sum += cmul_conj(cplx<double>{pv.x, pv.y}, W[(sb * 12 + 6 * ar + c6) * m + col]);
+        }
+      acc[q] += sum;
+    }
+  }
+  for (int q = 0; q < kPer; ++q) {
+    const int t = tid + 256 * q;
+    if (t >= m * m) break;
+    const int row = t / m, col = t - row * m;
+    Y[((size_t(J) * 9 + s) * m + col) * m + row] = make_double2(acc[q].re, acc[q].im);
   }
 }
 
@@ -236,7 +321,7 @@ struct BatchCoarseOp : LinOp {
   BatchCoarseOp(const BatchDev& b_, qmg_prec p_, const void* Y_) : b(b_), p(p_), Y(Y_) {}
   void apply(const void* in, void* out, int ncol, hipStream_t st, const int* = nullptr) override {
     const int nr = ncol / b.nl, m = 2 * b.k;
-    TimedLaunch tl("coarse_apply/batched", st, double(b.DT) * (9.0 * m * m + m * 2.0 * nr) * prec_bytes(p),
+    TimedLaunch tl("batch/coarse_apply", st, double(b.DT) * (9.0 * m * m + m * 2.0 * nr) * prec_bytes(p),
                    8.0 * 9.0 * m * m * b.DT * nr);
     dispatch_b(p, [&](auto tag) {
       using S = decltype(tag);
@@ -253,7 +338,7 @@ struct BatchCoarseOp : LinOp {
 void b_prolong(const BatchDev& b, qmg_prec p, const void* P, const void* vc, void* fine, int nr, hipStream_t st) {
   double sites = 0;
   for (int v : b.V) sites += v;
-  TimedLaunch tl("prolong/batched", st, sites * (12.0 * b.k + 12.0 * nr) * prec_bytes(p), 8.0 * 12.0 * b.k * sites * nr);
+  TimedLaunch tl("batch/prolong", st, sites * (12.0 * b.k + 12.0 * nr) * prec_bytes(p), 8.0 * 12.0 * b.k * sites * nr);
   dispatch_b(p, [&](auto tag) {
     using S = decltype(tag);
     launch(k_b_prolong<S>, dim3(2 * b.DT, unsigned((b.N + 255) / 256), nr), dim3(256), 0, st, static_cast<const S*>(P),
@@ -270,7 +355,7 @@ void b_restrict(const BatchDev& b, qmg_prec p, const void* P, const void* fine, 
   dispatch_b(p, [&](auto tag) {
     using S = decltype(tag);
     Blas<S>::zero(vc, b.coarse_len() * b.nl * nr, st);
-    TimedLaunch tl("restrict/batched", st, sites * (12.0 * b.k + 12.0 * nr) * prec_bytes(p),
+    TimedLaunch tl("batch/restrict", st, sites * (12.0 * b.k + 12.0 * nr) * prec_bytes(p),
                    8.0 * 12.0 * b.k * sites * nr);
     launch(k_b_restrict<S>, dim3(2 * b.DT, nr), dim3(64), uint32_t(b.N * sizeof(cplx<ctype<S>>)), st,
            static_cast<const S*>(P), static_cast<const S*>(fine), static_cast<S*>(vc), b.gsite.as<int>(),
@@ -279,66 +364,31 @@ void b_restrict(const BatchDev& b, qmg_prec p, const void* P, const void* fine, 
   QMG_LAUNCH_CHECK();
 }
 
-// Galerkin blocks by probing (file header); FP64
-void b_build_coarse(BatchDev& b, const std::vector<int>& colour_h, int ncolour, hipStream_t st) {
-  const int m = 2 * b.k;
-  DevBuf colour(colour_h.size() * sizeof(int));
-  QMG_HIP(hipMemcpy(colour.p, colour_h.data(), colour_h.size() * sizeof(int), hipMemcpyHostToDevice));
-  b.Y64.alloc(size_t(b.DT) * 9 * m * m * sizeof(double2));
-  const int nq = std::min(m, 8);  // coarse components probed per pass
-  DevBuf vc(b.coarse_len() * b.nl * nq * sizeof(double2)), u(vc.bytes);
-  DevBuf f1(b.fine_len() * b.nl * nq * sizeof(double2)), f2(f1.bytes);
-  BatchOp D(b, QMG_F64, b.U64.p);
-  TimedLaunch tl("coarse_build/batched", st, 0.0, 0.0, false);
-  for (int c = 0; c < ncolour; ++c)
-    for (int q0 = 0; q0 < m; q0 += nq) {
-      const int q = std::min(nq, m - q0);
-      Blas<double2>::zero(vc.p, b.coarse_len() * b.nl * q, st);
-      launch(k_b_probe_scatter, dim3(unsigned((b.DT + 255) / 256)), dim3(256), 0, st, vc.as<double2>(),
-             colour.as<int>(), c, q0, q, b.jinfo.as<int>(), b.dmax, m, b.DT);
-      QMG_LAUNCH_CHECK();
-      Blas<double2>::zero(f1.p, b.fine_len() * b.nl * q, st);  // the padding of the prolonged probes
-      b_prolong(b, QMG_F64, b.P64.p, vc.p, f1.p, q, st);
-      D.apply(f1.p, f2.p, b.nl * q, st);
-      b_restrict(b, QMG_F64, b.P64.p, f2.p, u.p, q, st);
-      launch(k_b_probe_extract, dim3(b.DT, 9), dim3(256), 0, st, u.as<double2>(), b.Y64.as<double2>(),
-             colour.as<int>(), c, q0, q, b.cnb.as<int>(), b.jinfo.as<int>(), b.dmax, m);
-      QMG_LAUNCH_CHECK();
-    }
-}
-
-// Greedy colouring of one coarse lattice: an aggregate and its eight neighbours all differ
-// (two aggregates conflict when one is within two +-mu steps of the other).
-int colour_coarse(const int cL[4], std::vector<int>& col) {
-  const int d = cL[0] * cL[1] * cL[2] * cL[3];
-  col.assign(d, -1);
-  int ncol = 0;
-  auto idx = [&](const int c[4]) { return c[0] + cL[0] * (c[1] + cL[1] * (c[2] + cL[2] * c[3])); };
-  std::vector<char> used;
-  for (int j = 0; j < d; ++j) {
-    int c[4], rem = j;
-    for (int q = 0; q < 4; ++q) {
-      c[q] = rem % cL[q];
-      rem /= cL[q];
-    }
-    used.assign(size_t(ncol) + 1, 0);
-    for (int s1 = 0; s1 < 9; ++s1)
-      for (int s2 = 0; s2 < 9; ++s2) {
-        int cc[4] = {c[0], c[1], c[2], c[3]};
-        for (int sv : {s1, s2}) {
-          if (sv == 0) continue;
-          const int mu = (sv - 1) & 3, step = sv <= 4 ? 1 : -1;
-          cc[mu] = (cc[mu] + step + cL[mu]) % cL[mu];
-        }
-        const int o = idx(cc);
-        if (o != j && col[o] >= 0) used[col[o]] = 1;
-      }
-    int k = 0;
-    while (k < ncol && used[k]) ++k;
-    col[j] = k;
-    ncol = std::max(ncol, k + 1);
+// Galerkin blocks from P and the links (k_b_galerkin), FP64
+void b_build_coarse_direct(BatchDev& b, hipStream_t st) {
+  static bool init = false;
+  if (!init) {  // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]
+    double2 gm[4][16] = {};
+    auto set = [&](int mu, int r, int c, double re, double im) { gm[mu][r * 4 + c] = make_double2(re, im); };
+    set(0, 0, 3, 0, -1); set(0, 1, 2, 0, -1); set(0, 2, 1, 0, 1); set(0, 3, 0, 0, 1);
+    set(1, 0, 3, -1, 0); set(1, 1, 2, 1, 0); set(1, 2, 1, 1, 0); set(1, 3, 0, -1, 0);
+    set(2, 0, 2, 0, -1); set(2, 1, 3, 0, 1); set(2, 2, 0, 0, 1); set(2, 3, 1, 0, -1);
+    set(3, 0, 2, 1, 0); set(3, 1, 3, 1, 0); set(3, 2, 0, 1, 0); set(3, 3, 1, 1, 0);
+    QMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_bgamma), gm, sizeof(gm)));
+    init = true;
   }
-  return ncol;
+  const int m = 2 * b.k;
+  b.Y64.alloc(size_t(b.DT) * 9 * m * m * sizeof(double2));
+  double sites = 0;
+  for (int v : b.V) sites += v;
+  // bytes: the blocks written, P and the links read once; flops: per site and slot the 6 x m by
+  // 6 x m products of each chirality and the hops applied to the 12 x m columns of P
+  TimedLaunch tl("batch/coarse_build", st, double(b.DT) * (9.0 * m * m + 6.0 * m * b.nd + 36.0 * b.nd) * 16.0,
+                 sites * 9.0 * (48.0 * m * m + 400.0 * m));
+  launch(k_b_galerkin, dim3(b.DT, 9), dim3(256), 0, st, b.U64.as<double2>(), b.P64.as<double2>(), b.Y64.as<double2>(),
+         b.gsite.as<int>(), b.jinfo.as<int>(), b.cnb.as<int>(), b.aoffd.as<int>(), b.lat.as<BatchLattice>(), b.blk[0],
+         b.blk[1], b.blk[2], b.blk[3], b.nd, b.N, b.k);
+  QMG_LAUNCH_CHECK();
 }
 
 // K-cycle over all lattices: restrict, coarse GMRES(32) to the coarse tolerance (per column),
@@ -424,7 +474,7 @@ void batch_setup(BatchDev& b, const qmg_mg_params& prm, hipStream_t st) {
     }
     const auto a1 = Clock::now();
     {
-      TimedLaunch tl_("setup/gather", st, double(cols) * b.Vpad * 12 * 2 * 16, 0.0);
+      TimedLaunch tl_("batch/gather", st, double(cols) * b.Vpad * 12 * 2 * 16, 0.0);
       launch(k_b_gather, dim3(2 * b.DT, r, unsigned((b.N + 255) / 256)), dim3(256), 0, st,
              static_cast<const double2*>(phi.p), blocks.as<double2>(), b.gsite.as<int>(), b.jinfo.as<int>(), b.nd, b.N,
              r, b.Vpad);
@@ -437,17 +487,7 @@ void batch_setup(BatchDev& b, const qmg_mg_params& prm, hipStream_t st) {
   }
   QMG_CHECK(kp == b.k, QMG_ESHAPE, "streaming SVD ended with %d < k columns", kp);
   const auto c0 = Clock::now();
-  // colouring of every coarse lattice (host), Galerkin blocks by probing
-  std::vector<int> colour(b.DT);
-  int ncol = 0;
-  for (int l = 0; l < b.nl; ++l) {
-    int cL[4];
-    for (int q = 0; q < 4; ++q) cL[q] = b.geo[l].L[q] / b.blk[q];
-    std::vector<int> c1;
-    ncol = std::max(ncol, colour_coarse(cL, c1));
-    std::copy(c1.begin(), c1.end(), colour.begin() + b.aoff[l]);
-  }
-  b_build_coarse(b, colour, ncol, st);
+  b_build_coarse_direct(b, st);
   if (b.inner != QMG_F64) {
     const int m = 2 * b.k;
     const size_t np = size_t(2) * b.DT * b.k * b.N, ny = size_t(b.DT) * 9 * m * m;

@@ -1070,7 +1070,7 @@ void launch_dslash_batched(qmg_prec prec, const BatchLattice* lat_dev, int n_lat
 
 void launch_dslash_padded(qmg_prec prec, const BatchLattice* lat_dev, int nl, int nr, int Vpad, const void* U,
                           const void* in, void* out, bool dagger, double bytes, double flops, hipStream_t st) {
-  TimedLaunch tl("dslash/padded", st, bytes, flops);
+  TimedLaunch tl("batch/dslash", st, bytes, flops);
   const int ntile = (Vpad + kBlock - 1) / kBlock;
   const dim3 grid(unsigned(ntile) * unsigned(nl) * unsigned(nr));
   auto go = [&](auto tag) {

@@ -1049,7 +1049,7 @@ void launch_export_Y(const HierarchyDev& h, void* out, hipStream_t st) {
 
 void launch_philox_padded(uint64_t seed, int v0, int n, int nl, const int* Vl, int Vpad, void* out, hipStream_t st) {
   {
-    TimedLaunch tl_("setup/philox", st, double(nl) * n * Vpad * 12 * 16, 0.0);
+    TimedLaunch tl_("batch/philox", st, double(nl) * n * Vpad * 12 * 16, 0.0);
     launch(k_philox_padded, dim3(cdiv(Vpad, 256), n, nl), dim3(256), 0, st, (double2*)out, seed, v0, n, Vl, Vpad);
   }
   QMG_LAUNCH_CHECK();

@@ -1,7 +1,7 @@
 """GPU parity of the many-lattice hierarchy (qmg_batch_*): the setups and solves of several
 independent lattices of different extents and masses run in shared launches, and each lattice is
 checked against the CPU oracle run on that lattice alone: the streaming-SVD prolongator (projector
-per aggregate and chirality), the Galerkin blocks of Eq. (5) (formed by probing on the GPU) and
+per aggregate and chirality), the Galerkin blocks of Eq. (5) (formed from P and the links on the GPU) and
 the solution (dense LU where the lattice is small enough, the oracle's residual otherwise)."""
 import numpy as np
 import pytest
