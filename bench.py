@@ -23,15 +23,15 @@ solve) on the same 16^3 x 32 anisotropic lattice with unit clover coefficients a
 tuned for that operator; `evenodd` is the even-odd Schur operator's bandwidth on 32^3 x 64 and
 its GMRES solve against GMRES on the full operator.  `--workload aniso16x32_clover` makes the clover workload the main line.
 
-Counter runs: `bench.py --traffic-probe` runs a 256 MiB device copy (calibration), ten launches
-each of the solve's dslash and coarse apply in the solve's launch configuration, and one solve
-with the benchmark's smoother and coarse solve (the even-odd hop and coarse kernels); run it
+Counter runs: `bench.py --traffic-probe` runs three 256 MiB device copies (calibration) and one
+step of the benchmark as timed; run it
 under `rocprofv3 --pmc FETCH_SIZE` and, separately, `--pmc WRITE_SIZE`, then
 `bench.py --traffic-from FETCH_DIR WRITE_DIR` writes profiles/traffic.json (bytes per launch,
 scaled by the copy calibration, with the SHA-256 of the kernel source) and a text summary.
 `roofline.traffic` is filled from that record while the kernel source is unchanged.
 """
 import argparse
+from types import SimpleNamespace
 import csv
 import glob
 import hashlib
@@ -46,7 +46,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
-TIMING_SAMPLE = 8  # time about one launch in 8 of each kernel family in the timed region
+TIMING_SAMPLE = 4  # time about one launch in 4 of each kernel family in the timed region
 COPY_BYTES = 256 << 20
 # timing family -> (kernel symbol prefix in counter output, source file)
 FAMILY_KERNEL = {
@@ -59,11 +59,184 @@ FAMILY_KERNEL = {
     "coarse_build": ("k_build_coarse", "transfer.hip"),
     "evenodd/hop": ("k_hop_eo", "dslash.hip"),
     "coarse_eo": ("k_coarse_eo_apply", "coarse_evenodd.hip"),
+    "sstep/gram": ("k_sstep_gram", "evenodd.hip"),
+    "blas/axpby": ("k_axpby<", "krylov.hip"),
+    "blas/axpy_multi": ("k_axpy_multi", "krylov.hip"),
+    "batch/dslash": ("k_dslash_padded", "dslash.hip"),
+    "batch/coarse_build": ("k_b_galerkin", "batch.hip"),
 }
 FAMILIES = ("dslash/site", "dslash/twalk", "dslash/dir", "isvd", "coarse_apply", "prolong", "restrict",
             "coarse_build", "evenodd/hop", "coarse_eo")
 CLOVER_FAMILIES = tuple(f.replace("dslash/", "clover/") for f in FAMILIES)
 CLOVER_WORKLOAD = "aniso16x32_clover"
+
+
+def progress(msg):
+    """One line on stderr per finished phase (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+_ROCTX = []
+
+
+def roctx(push=None):
+    """roctx range around the timed region, so that a kernel trace (rocprofv3 --marker-trace) can
+    be cut to it; a no-op without the profiler library."""
+    import ctypes
+    if not _ROCTX:
+        try:
+            lib = ctypes.CDLL("librocprofiler-sdk-roctx.so.1")
+            lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+            _ROCTX.append(lib)
+        except OSError:
+            _ROCTX.append(None)
+    lib = _ROCTX[0]
+    if lib is None:
+        return
+    if push:
+        lib.roctxRangePushA(push.encode())
+    else:
+        lib.roctxRangePop()
+
+
+def trace_summary(args):
+    """Per-kernel and per-family device time inside the timed region (the roctx range
+    "bench/timed") from a rocprofv3 --kernel-trace --marker-trace CSV output folder."""
+    d = args.trace_summary
+    ktr = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+    mtr = glob.glob(os.path.join(d, "**", "*marker_api_trace.csv"), recursive=True)
+    if not ktr or not mtr:
+        raise SystemExit(f"need *kernel_trace.csv and *marker_api_trace.csv under {d}")
+    t0, t1 = None, None
+    for f in mtr:
+        for r in csv.DictReader(open(f)):
+            if any(v == "bench/timed" for v in r.values()):
+                a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+                t0 = a if t0 is None else min(t0, a)
+                t1 = b if t1 is None else max(t1, b)
+    if t0 is None:
+        raise SystemExit("no bench/timed range in the marker trace")
+    per = {}
+    for f in ktr:
+        for r in csv.DictReader(open(f)):
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            if a >= t0 and b <= t1:
+                e = per.setdefault(r["Kernel_Name"], [0, 0])
+                e[0] += 1
+                e[1] += b - a
+    short = lambda n: n.replace("qmg::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+    total = sum(v[1] for v in per.values())
+    steps = args.steps
+    out = [f"timed region {(t1 - t0) * 1e-9:.3f} s ({steps} steps), kernel time {total * 1e-9:.3f} s, "
+           f"{sum(v[0] for v in per.values())} dispatches", "",
+           "| family | kernel instances | dispatches | ms per step | average launch us |", "|---|---:|---:|---:|---:|"]
+    for fam, (prefix, _) in FAMILY_KERNEL.items():
+        ks = [k for k in per if short(k).startswith(prefix)]
+        if not ks:
+            continue
+        n = sum(per[k][0] for k in ks)
+        t = sum(per[k][1] for k in ks)
+        out.append(f"| {fam} | {len(ks)} | {n} | {t * 1e-6 / steps:.2f} | {t / n * 1e-3:.1f} |")
+    out += ["", "| kernel | dispatches | ms per step | average us |", "|---|---:|---:|---:|"]
+    for k, (n, t) in sorted(per.items(), key=lambda kv: -kv[1][1])[:30]:
+        out.append(f"| `{short(k)[:100]}` | {n} | {t * 1e-6 / steps:.2f} | {t / n * 1e-3:.1f} |")
+    print("\n".join(out))
+
+
+DSLASH_VARIANTS = {1: (8, 10008, 16), 4: (208, 1208, 11208, 8, 10008), 12: (308, 1308, 11308, 1208, 11208, 8, 10008)}
+
+
+def dslash_variants(args):
+    """The Wilson stencil's launch forms on 32^3 x 64 (FP32, random links) at 1, 4 and 12
+    right-hand sides: per form the average launch (HIP events, 10 launches after 3 warm-up
+    launches), its algorithmic bandwidth and its largest deviation from the first form.  With
+    --launch-only every form is launched three times and nothing is timed (for counter runs:
+    the dispatches come in the order of DSLASH_VARIANTS)."""
+    import torch
+    import paper_2505_14399_amd as q
+
+    if args.launch_only:  # calibration copies for the counter runs
+        a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    lat = q.Lattice(DSLASH_HBM_DIMS, -0.2, 1.0, -1)
+    V = lat.volume
+    g = torch.Generator(device="cuda").manual_seed(9)
+    U = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
+    Un = q.pack_gauge(lat, U, "f32")
+    del U
+    try:
+        for nrhs, forms in DSLASH_VARIANTS.items():
+            x = q.pack_spinor(lat, torch.randn(nrhs, V, 4, 3, dtype=torch.complex128, device="cuda", generator=g), "f32")
+            y = torch.empty_like(x)
+            ref = None
+            for v in forms:
+                q.set_dslash_variant(v)
+                q.wilson_apply(lat, Un, x, layout="native", out=y)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = y.clone()
+                err = float((y - ref).abs().max() / ref.abs().max())
+                row = {"nrhs": nrhs, "form": v, "max_dev": err}
+                if args.launch_only:
+                    for _ in range(2):
+                        q.wilson_apply(lat, Un, x, layout="native", out=y)
+                    torch.cuda.synchronize()
+                else:
+                    for _ in range(3):
+                        q.wilson_apply(lat, Un, x, layout="native", out=y)
+                    q.timing_enable(True)
+                    for _ in range(10):
+                        q.wilson_apply(lat, Un, x, layout="native", out=y)
+                    t = q.timing_query("dslash")
+                    q.timing_enable(False)
+                    ms = t["ms"] / t["launches"]
+                    row.update(us=round(ms * 1e3, 1), algorithmic_MB=round(t["bytes"] / t["launches"] / 1e6, 1),
+                               GBps=round(t["bytes"] / t["launches"] / (ms * 1e-3) / 1e9))
+                print(json.dumps(row), flush=True)
+            del x, y, ref
+    finally:
+        q.set_dslash_variant(0)
+
+
+def variants_from(args):
+    """FETCH_SIZE / WRITE_SIZE of the --dslash-variants --launch-only run, per (rhs count, form):
+    the stencil dispatches in launch order, three per form, scaled by the copy calibration and
+    set against the algorithmic bytes (spinor in and out per site and rhs, four links per site)."""
+    import numpy as np
+
+    def rows(d, counter):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") == counter:
+                    out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        out.sort()
+        copy = [v for _, n, v in out if "copyBuffer" in n][:3]  # the calibration copies come first
+        scale = COPY_BYTES / (float(np.median(copy)) * 1024.0)
+        st = [v * 1024.0 * scale for _, n, v in out if "k_dslash" in n]
+        return st, scale
+
+    fe, fs = rows(args.variants_from[0], "FETCH_SIZE")
+    wr, ws = rows(args.variants_from[1], "WRITE_SIZE")
+    V = 1
+    for L in DSLASH_HBM_DIMS:
+        V *= L
+    print(f"# copy calibration: fetch x{fs:.3f}, write x{ws:.3f}")
+    print("| rhs | form | fetch MB | write MB | algorithmic read MB | fetch / algorithmic read |")
+    print("|---:|---:|---:|---:|---:|---:|")
+    i = 0
+    for nrhs, forms in DSLASH_VARIANTS.items():
+        for v in forms:
+            f = float(np.mean(fe[i + 1:i + 3]))
+            w = float(np.mean(wr[i + 1:i + 3]))
+            i += 3
+            alg = V * (12.0 * nrhs + 36.0) * 8.0
+            print(f"| {nrhs} | {v} | {f / 1e6:.0f} | {w / 1e6:.0f} | {alg / 1e6:.0f} | {f / alg:.2f} |")
 
 
 def source_sha(fname):
@@ -86,7 +259,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator solve")
     ap.add_argument("--mass", type=float, default=None, help="override the workload's quark mass")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="copy calibration plus ten launches each of the solve's dslash and coarse apply")
+                    help="copy calibration plus one benchmark step (for the FETCH_SIZE / WRITE_SIZE counter runs)")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover operator and clover MG leg")
     ap.add_argument("--no-evenodd", action="store_true", help="skip the even-odd preconditioning leg")
     ap.add_argument("--full-coarse", action="store_true",
@@ -101,6 +274,15 @@ def parse():
     ap.add_argument("--compare-setups", action="store_true",
                     help="Regular / CSVD / streaming (iCSVD) setups on the workload: iterations per level, "
                          "setup and solve seconds, leading singular values (prints a table and JSON lines)")
+    ap.add_argument("--dslash-variants", action="store_true",
+                    help="time the stencil's launch forms on 32^3x64 (FP32) at 1, 4 and 12 right-hand sides")
+    ap.add_argument("--launch-only", action="store_true",
+                    help="with --dslash-variants: launch each form three times, time nothing (counter runs)")
+    ap.add_argument("--variants-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="counter output of --dslash-variants --launch-only: traffic per launch form")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="per-kernel and per-family device time inside the timed region from rocprofv3 "
+                         "--kernel-trace --marker-trace CSV output (--steps: the run's timed steps)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="read rocprofv3 FETCH_SIZE / WRITE_SIZE counter output and write profiles/traffic.json")
     return ap.parse_args()
@@ -114,12 +296,11 @@ def load_workload(args):
 
 
 def traffic_probe(args):
-    """Launch sequence measured by the counter runs (nothing is timed here)."""
+    """Launch sequence measured by the counter runs (nothing is timed here): three 256 MiB device
+    copies (calibration), then one step of the benchmark exactly as timed (setup and solve of
+    the main lattice, and of the small lattices where the workload has them)."""
     import torch
-    import fields
-    import paper_2505_14399_amd as q
 
-    w = load_workload(args)
     a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
     a.fill_(1)
     b = torch.empty_like(a)
@@ -127,33 +308,11 @@ def traffic_probe(args):
         b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    dims = w["dims"]
-    lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
-    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
-    mg = q.mg_setup_stream_chiral_svd(lat, U, block=w["block"], n_test=w["n_test"], batch=w["batch"],
-                                      rank=w["rank"], n_setup_iter=16, inner=w["inner"], seed=w["seed"])
-    prec = w["inner"]
-    Un = q.pack_gauge(lat, U, prec)
-    x = q.pack_spinor(lat, torch.from_numpy(fields.gaussian_spinor(dims, 1, 1)).cuda(), prec)
-    y = torch.empty_like(x)
-    for i in range(10):  # the K-cycle's inner dslash: native layout, one right-hand side
-        q.wilson_apply(lat, Un, x if i % 2 == 0 else y, layout="native", out=y if i % 2 == 0 else x)
-    cdt = torch.complex64 if prec == "f32" else torch.complex128
-    vc = torch.randn(1, mg.n_agg, 2, mg.rank, dtype=cdt, device="cuda")
-    wc = torch.empty_like(vc)
-    for i in range(10):
-        q.coarse_apply(mg, vc if i % 2 == 0 else wc, out=wc if i % 2 == 0 else vc)
-    # one solve with the benchmark's smoother: its even-odd hop launches (every form, in the
-    # smoother's own link storage) are the ones the timed region measures
-    mg.set_smoother(eo=True, sstep=True)
-    try:
-        mg.set_coarse_eo(True)
-    except q.QmgError:
-        pass
-    q.mg_solve(mg, torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda(), tol=args.tol)
+    P = prepare(args)
+    _, _, info, _ = P.step()
     torch.cuda.synchronize()
-    mg.close()
-    print(json.dumps({"probe": w["name"], "dims": list(dims), "prec": prec}), flush=True)
+    print(json.dumps({"probe": P.w["name"], "dims": list(P.dims), "prec": P.w["inner"],
+                      "worst_rel_res": max(i["true_rel_res"] for i in info)}), flush=True)
 
 
 # dslash bandwidth on a lattice whose fields do not fit the 256 MB MALL (the workload's own
@@ -514,24 +673,22 @@ def traffic_from(args):
              f"{w_copy / 1024:.0f} KiB for a {COPY_BYTES >> 20} MiB copy -> scale fetch x{f_scale:.3f}, "
              f"write x{w_scale:.3f}"]
     entry = rec.setdefault(w["name"], {})
-    for fam in ("dslash/dir", "dslash/site", "dslash/twalk", "coarse_apply", "evenodd/hop", "coarse_eo"):
+    for fam in FAMILY_KERNEL:
         prefix, src = FAMILY_KERNEL[fam]
-        merge = fam in ("evenodd/hop", "coarse_eo")
-        name, fv = pick(fetch, prefix, merge)
-        _, wv = pick(write, prefix, merge)
+        name, fv = pick(fetch, prefix, True)
+        _, wv = pick(write, prefix, True)
         if not fv or not wv:
             continue
-        # the hop forms of the smoother (Schur operator, source, reconstruction) mix in the family:
-        # their mean over the solve's dispatches is the family's launch
-        avg = np.mean if merge else np.median
-        fb = float(avg(fv)) * 1024.0 * f_scale
-        wb = float(avg(wv)) * 1024.0 * w_scale
+        # every instance of the family's kernel in the step (forms, precisions, right-hand-side
+        # counts) mixes as in the timed region: the mean over the step's dispatches is the
+        # family's launch, as bench.py's timed averages are
+        fb = float(np.mean(fv)) * 1024.0 * f_scale
+        wb = float(np.mean(wv)) * 1024.0 * w_scale
         entry[fam] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
                       "dispatches": [len(fv), len(wv)], "kernel": name, "source": src,
                       "source_sha256": source_sha(src)}
         lines.append(f"{fam:14s} {name[:70]}: fetch {fb / 1e6:.2f} MB + write {wb / 1e6:.2f} MB = "
-                     f"{(fb + wb) / 1e6:.2f} MB per launch ({'mean' if merge else 'median'} of {len(fv)}/{len(wv)} "
-                     f"dispatches)")
+                     f"{(fb + wb) / 1e6:.2f} MB per launch (mean of {len(fv)}/{len(wv)} dispatches)")
     os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
     json.dump(rec, open(TRAFFIC_JSON, "w"), indent=1)
     print("\n".join(lines))
@@ -734,25 +891,10 @@ def measure_config(args, name, steps=2):
     return res
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the solver path is not sharded "
-              f"across GPUs", file=sys.stderr)
-        sys.exit(2)
-    if args.traffic_from:
-        traffic_from(args)
-        return
-    if args.traffic_probe:
-        traffic_probe(args)
-        return
-    if args.compare_setups:
-        compare_setups(args)
-        return
-    if args.levels:
-        compare_levels(args)
-        return
-    import numpy as np
+def prepare(args):
+    """The workload's fields and right-hand sides on the device, and one step of the benchmark:
+    setup and mixed-precision solve of the main lattice, then (batched workload) the setups and
+    solves of the 64 small lattices in shared launches."""
     import torch
 
     import fields
@@ -812,13 +954,56 @@ def main():
         return part["setup_s"] + part.get("small_setup_s", 0.0), part["solve_s"] + part.get("small_solve_s", 0.0), \
             info, part
 
-    for _ in range(args.warmup):
+    return SimpleNamespace(w=w, dims=dims, lat=lat, U_host=U_host, U=U, b=b, nrhs=nrhs, setup_kw=setup_kw,
+                           eo_smoother=eo_smoother, coarse_eo=coarse_eo, small=small, step=step)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the solver path is not sharded "
+              f"across GPUs", file=sys.stderr)
+        sys.exit(2)
+    if args.traffic_from:
+        traffic_from(args)
+        return
+    if args.trace_summary:
+        trace_summary(args)
+        return
+    if args.variants_from:
+        variants_from(args)
+        return
+    if args.dslash_variants:
+        dslash_variants(args)
+        return
+    if args.traffic_probe:
+        traffic_probe(args)
+        return
+    if args.compare_setups:
+        compare_setups(args)
+        return
+    if args.levels:
+        compare_levels(args)
+        return
+    import numpy as np
+    import torch
+
+    import fields
+    from fields import workloads
+    import paper_2505_14399_amd as q
+
+    P = prepare(args)
+    w, dims, lat, U_host, U, b, nrhs = P.w, P.dims, P.lat, P.U_host, P.U, P.b, P.nrhs
+    setup_kw, eo_smoother, coarse_eo, small, step = P.setup_kw, P.eo_smoother, P.coarse_eo, P.small, P.step
+    for i in range(args.warmup):
         step()
+        progress(f"warm-up step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    # about one launch in 8 of each kernel family is timed with events attached to the dispatch
+    # about one launch in TIMING_SAMPLE of each kernel family is timed with events attached to the dispatch
     q.timing_enable(True, every=TIMING_SAMPLE)
     setups, solves, infos, parts = [], [], [], []
     torch.cuda.synchronize()
+    roctx("bench/timed")
     T0 = time.perf_counter()
     for _ in range(args.steps):
         ts, tv, info, part = step()
@@ -826,8 +1011,10 @@ def main():
         solves.append(tv)
         infos.append(info)
         parts.append(part)
+        progress(f"timed step {len(parts)}/{args.steps} done: setup {ts:.3f} s, solve {tv:.3f} s")
     torch.cuda.synchronize()
     T1 = time.perf_counter()
+    roctx()
     fams = family_table(q.timing_families(), args.steps)
     q.timing_enable(False)
     for info in infos:
@@ -968,14 +1155,18 @@ def main():
         for name in ("aniso16x32_fp32", "iso24x64_bf16"):
             if name != w["name"]:
                 res["configs"][name] = measure_config(args, name)
+                progress(f"config {name} done")
     if not args.no_dslash_hbm:
         res["dslash_hbm"] = dslash_hbm()
+        progress("dslash bandwidth done")
     if not args.no_clover and not w.get("c_sw"):
         res["clover"] = {"mg": clover_mg(args)}
         if not args.no_dslash_hbm:
             res["clover"]["dslash_hbm"] = dslash_hbm(clover=True)
+        progress("clover leg done")
     if not args.no_evenodd and not w.get("c_sw"):
         res["evenodd"] = evenodd_leg(args)
+        progress("even-odd leg done")
     if not args.no_cpu_baseline:
         sm = None
         if small:

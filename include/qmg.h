@@ -473,9 +473,9 @@ qmg_status qmg_batch_get_coarse(const qmg_batch* b, int32_t lat, void* Y, hipStr
 qmg_status qmg_batch_setup_times(const qmg_batch* b, double* t);
 void qmg_batch_destroy(qmg_batch* b);
 
-/* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times the first 64
- * later launches of each kernel family and then about one in n (picked by a hash of the call
- * index) with a pair of HIP events attached to the dispatch (its own start and end).  Every
+/* Measurement hooks.  qmg_timing_enable(n), n >= 1, clears the record and times the first later
+ * launch of each kernel family and then about one in n (picked by a hash of the call index)
+ * with a pair of HIP events attached to the dispatch (its own start and end).  Every
  * kernel of the library belongs to a family: the operators ("dslash/site", "dslash/twalk",
  * "dslash/dir", "dslash/canonical", "dslash/batched", "clover/...", "evenodd/hop",
  * "coarse_apply", "coarse_eo", "prolong", "restrict", "level_..."), the Krylov vector kernels

@@ -169,6 +169,7 @@ __device__ inline cplx<double> b_p(const double2* __restrict__ P, int J, int com
   return {v.x, v.y};
 }
 
+template <int KPER>  // (row, col) pairs per thread: ceil((2k)^2 / 256)
 __global__ __launch_bounds__(256) void k_b_galerkin(const double2* __restrict__ U, const double2* __restrict__ P,
                                                     double2* __restrict__ Y, const int* __restrict__ gsite,
                                                     const int* __restrict__ jinfo, const int* __restrict__ cnb,
@@ -182,9 +183,8 @@ __global__ __launch_bounds__(256) void k_b_galerkin(const double2* __restrict__ 
   const int L[4] = {a.L[0], a.L[1], a.L[2], a.L[3]}, bb[4] = {b0, b1, b2, b3};
   const int Vpad = a.V;
   const double2* Ul = U + size_t(l) * 36 * Vpad;
-  constexpr int kPer = (4 * kMaxRank * kMaxRank + 255) / 256;  // (row, col) pairs per thread
-  cplx<double> acc[kPer];
-  for (int q = 0; q < kPer; ++q) acc[q] = {0.0, 0.0};
+  cplx<double> acc[KPER];
+  for (int q = 0; q < KPER; ++q) acc[q] = {0.0, 0.0};
   for (int ib0 = 0; ib0 < nd; ib0 += nb) {
     const int nbs = min(nb, nd - ib0);
     __syncthreads();  // the previous batch's W is no longer read
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void k_b_galerkin(const double2* __restrict__ 
       for (int comp = 0; comp < 12; ++comp) W[(sb * 12 + comp) * m + col] = w[comp];
     }
     __syncthreads();
-    for (int q = 0; q < kPer; ++q) {
+    for (int q = 0; q < KPER; ++q) {
       const int t = tid + 256 * q;
       if (t >= m * m) break;
       const int row = t / m, col = t - row * m, ar = row / k, ir = row - ar * k;
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_b_galerkin(const double2* __restrict__ 
       acc[q] += sum;
     }
   }
-  for (int q = 0; q < kPer; ++q) {
+  for (int q = 0; q < KPER; ++q) {
     const int t = tid + 256 * q;
     if (t >= m * m) break;
     const int row = t / m, col = t - row * m;
@@ -385,9 +385,16 @@ void b_build_coarse_direct(BatchDev& b, hipStream_t st) {
   // 6 x m products of each chirality and the hops applied to the 12 x m columns of P
   TimedLaunch tl("batch/coarse_build", st, double(b.DT) * (9.0 * m * m + 6.0 * m * b.nd + 36.0 * b.nd) * 16.0,
                  sites * 9.0 * (48.0 * m * m + 400.0 * m));
-  launch(k_b_galerkin, dim3(b.DT, 9), dim3(256), 0, st, b.U64.as<double2>(), b.P64.as<double2>(), b.Y64.as<double2>(),
-         b.gsite.as<int>(), b.jinfo.as<int>(), b.cnb.as<int>(), b.aoffd.as<int>(), b.lat.as<BatchLattice>(), b.blk[0],
-         b.blk[1], b.blk[2], b.blk[3], b.nd, b.N, b.k);
+  auto go = [&](auto kern) {
+    launch(kern, dim3(b.DT, 9), dim3(256), 0, st, b.U64.as<double2>(), b.P64.as<double2>(), b.Y64.as<double2>(),
+           b.gsite.as<int>(), b.jinfo.as<int>(), b.cnb.as<int>(), b.aoffd.as<int>(), b.lat.as<BatchLattice>(),
+           b.blk[0], b.blk[1], b.blk[2], b.blk[3], b.nd, b.N, b.k);
+  };
+  // accumulators sized to the block: a fixed 16 pairs per thread spills at small ranks
+  if (m <= 16) go(k_b_galerkin<1>);
+  else if (m <= 32) go(k_b_galerkin<4>);
+  else if (m <= 48) go(k_b_galerkin<9>);
+  else go(k_b_galerkin<16>);
   QMG_LAUNCH_CHECK();
 }
 

@@ -2084,14 +2084,15 @@ qmg_status qmg_autotune(int32_t on) {
 
 qmg_status qmg_set_dslash_variant(int32_t v) {
   return guard([&] {
-    const int z = v / 1000, nr = (v % 1000) / 100, tch = v % 100;
-    const bool tw = v > 100 && z <= 1 && (nr == 2 || nr == 3) && (tch == 2 || tch == 4 || tch == 8);
-    const bool hop_nr = v >= 501 && v <= 504;  // even-odd hop: 1 .. 4 right-hand sides per thread
-    QMG_CHECK(tw || hop_nr || v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64,
-              QMG_EINVAL,
-              "dslash variant must be 0, 1, 2, 4, 8, 16, 32, 64, an even-odd hop code 500 + NR (NR in 1..4) or a "
-              "multi-rhs t-walking code "
-              "1000 z + 100 NR + TCH (z in {0,1}, NR in {2,3}, TCH in {2,4,8})");
+    const int cm = v >= 10000 ? 1 : 0, u = v % 10000;  // 10000 + a t-walking code: t-chunk-major order
+    const int z = u / 1000, nr = (u % 1000) / 100, tch = u % 100;
+    const bool tw = u > 100 && z <= 1 && (nr == 2 || nr == 3) && (tch == 2 || tch == 4 || tch == 8);
+    const bool hop_nr = !cm && v >= 501 && v <= 504;  // even-odd hop: 1 .. 4 right-hand sides per thread
+    const bool plain = !cm && (v == 0 || v == 1 || v == 16 || v == 32 || v == 64);
+    QMG_CHECK(v < 20000 && (tw || hop_nr || plain || u == 2 || u == 4 || u == 8), QMG_EINVAL,
+              "dslash variant must be 0, 1, 2, 4, 8, 16, 32, 64, an even-odd hop code 500 + NR (NR in 1..4), a "
+              "multi-rhs t-walking code 1000 z + 100 NR + TCH (z in {0,1}, NR in {2,3}, TCH in {2,4,8}), or "
+              "10000 + a t-walking code (2, 4, 8 or multi-rhs) for the t-chunk-major workgroup order");
     set_dslash_variant(v);
   });
 }

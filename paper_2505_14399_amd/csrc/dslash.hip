@@ -347,13 +347,20 @@ __global__ __launch_bounds__(kBlock) void k_dslash_padded(const BatchLattice* __
 // the tiles holding a site's z-neighbours run next to it.
 template <class S, int TCH, int NR, bool DAG, bool CLOV = false>
 __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, const S* __restrict__ in,
-                                                     S* __restrict__ out, DslashArgs a, int ntile_s, int zfast) {
+                                                     S* __restrict__ out, DslashArgs a, int ntile_s, int zfast,
+                                                     int cmaj) {
   using C = ctype<S>;
   const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
   const int Vs = L0 * L1 * L2, V = a.V;
   const int ng = a.nrhs / NR;
-  const int wg = xcd_tile(blockIdx.x, gridDim.x);
   const int per_chunk = ntile_s * ng;
+  int wg;
+  if (cmaj) {  // t-chunk major in dispatch order (all XCDs on one chunk), XCD-local tiles within it
+    const int ch = blockIdx.x / per_chunk;
+    wg = ch * per_chunk + xcd_tile(blockIdx.x - ch * per_chunk, per_chunk);
+  } else {
+    wg = xcd_tile(blockIdx.x, gridDim.x);
+  }
   const int chunk = wg / per_chunk, r0 = wg - chunk * per_chunk;
   const int ts = r0 / ng, g = r0 - ts * ng;
   int xs;  // spatial site
@@ -629,7 +636,8 @@ void launch_t(const void* U, const void* in, void* out, const DslashArgs& a, hip
 }
 
 template <class S, int TCH, int NR>
-void launch_tw(const void* U, const void* in, void* out, const DslashArgs& a, int zfast, hipStream_t st) {
+void launch_tw(const void* U, const void* in, void* out, const DslashArgs& a, int zfast, hipStream_t st,
+               int cmaj = 0) {
   const int Vs = a.L[0] * a.L[1] * a.L[2];
   const int ntile_s = zfast ? ((a.L[0] * a.L[1] + kBlock - 1) / kBlock) * a.L[2] : (Vs + kBlock - 1) / kBlock;
   const int nchunk = a.L[3] / TCH;
@@ -637,17 +645,18 @@ void launch_tw(const void* U, const void* in, void* out, const DslashArgs& a, in
   if constexpr (sizeof(S) >= 8) {  // the site-term forms exist for FP32 and FP64 storage
     if (a.clov) {
       if (a.dagger)
-        launch(k_dslash_t<S, TCH, NR, true, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
+        launch(k_dslash_t<S, TCH, NR, true, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast, cmaj);
       else
-        launch(k_dslash_t<S, TCH, NR, false, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
+        launch(k_dslash_t<S, TCH, NR, false, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast,
+               cmaj);
       QMG_LAUNCH_CHECK();
       return;
     }
   }
   if (a.dagger)
-    launch(k_dslash_t<S, TCH, NR, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
+    launch(k_dslash_t<S, TCH, NR, true>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast, cmaj);
   else
-    launch(k_dslash_t<S, TCH, NR, false>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast);
+    launch(k_dslash_t<S, TCH, NR, false>, grid, dim3(kBlock), 0, st, U, in, out, a, ntile_s, zfast, cmaj);
   QMG_LAUNCH_CHECK();
 }
 
@@ -660,16 +669,16 @@ inline bool twx_code(int v) {
 }
 
 template <class S>
-void run_twx(int v, const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st) {
+void run_twx(int v, const void* U, const void* in, void* out, const DslashArgs& a, hipStream_t st, int cm) {
   if constexpr (sizeof(S) != 8) {
     set_error("dslash launch form %d needs FP32 storage", v);
   } else {
     const int z = v / 1000, nr = (v % 1000) / 100, tch = v % 100;
     auto go = [&](auto nrc) {
       constexpr int NR = decltype(nrc)::value;
-      if (tch == 2) launch_tw<S, 2, NR>(U, in, out, a, z, st);
-      else if (tch == 4) launch_tw<S, 4, NR>(U, in, out, a, z, st);
-      else launch_tw<S, 8, NR>(U, in, out, a, z, st);
+      if (tch == 2) launch_tw<S, 2, NR>(U, in, out, a, z, st, cm);
+      else if (tch == 4) launch_tw<S, 4, NR>(U, in, out, a, z, st, cm);
+      else launch_tw<S, 8, NR>(U, in, out, a, z, st, cm);
     };
     if (nr == 2) go(std::integral_constant<int, 2>{});
     else go(std::integral_constant<int, 3>{});
@@ -694,7 +703,7 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   // that many sites per thread along t, 16 = direction-split (four threads per site), 32/64 =
   // one site per thread for 2/4 right-hand sides at once (links loaded once for all of them),
   // 1000 z + 100 NR + TCH = t-walking with NR = 2 or 3 right-hand sides per thread (FP32; z:
-  // z-fastest tile order).  Default heuristic: for several right-hand sides in FP32 the
+  // z-fastest tile order); 10000 + a t-walking code: the same in t-chunk-major workgroup order.  Default heuristic: for several right-hand sides in FP32 the
   // multi-RHS t-walk (3 per thread when nrhs is a multiple of 3, else 2); otherwise the longest
   // t-chunk that still gives >= 1024 workgroups, else the direction split when one thread per
   // site would leave the GPU short of wavefronts.  With the autotuner enabled every valid
@@ -705,24 +714,30 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
   const long wg1 = long((Vs + kBlock - 1) / kBlock) * a.nrhs;  // workgroups per t-slice
   const int Lt = a.L[3];
   auto run = [&](int v) {
+    const int cm = v / 10000;  // 10000 + code: the t-walks in t-chunk-major workgroup order
+    v %= 10000;
     const int f = v == 16 ? 0 : (v == 1 || v == 32 || v == 64) ? 1 : 2;
     static const char* const fams[2][3] = {{"dslash/dir", "dslash/site", "dslash/twalk"},
                                            {"clover/dir", "clover/site", "clover/twalk"}};
     TimedLaunch tl(fams[clov ? 1 : 0][f], st, bytes, flops);
     switch (v) {
-      case 8: launch_tw<S, 8, 1>(U, in, out, a, 0, st); break;
-      case 4: launch_tw<S, 4, 1>(U, in, out, a, 0, st); break;
-      case 2: launch_tw<S, 2, 1>(U, in, out, a, 0, st); break;
+      case 8: launch_tw<S, 8, 1>(U, in, out, a, 0, st, cm); break;
+      case 4: launch_tw<S, 4, 1>(U, in, out, a, 0, st, cm); break;
+      case 2: launch_tw<S, 2, 1>(U, in, out, a, 0, st, cm); break;
       case 16: launch_dir<S>(U, in, out, a, st); break;
       case 32: launch_t<S, false, 2>(U, in, out, a, st); break;
       case 64: launch_t<S, false, 4>(U, in, out, a, st); break;
       default:
-        if (v > 100) run_twx<S>(v, U, in, out, a, st);
+        if (v > 100) run_twx<S>(v, U, in, out, a, st, cm);
         else launch_t<S, false, 1>(U, in, out, a, st);
         break;
     }
   };
   auto valid = [&](int v) {
+    if (v >= 10000) {
+      v -= 10000;
+      if (v < 2 || v == 16 || v == 32 || v == 64 || v >= 10000) return false;
+    }
     if (v == 16) return true;
     if (clov && (sizeof(S) == 4 || v == 32 || v == 64)) return false;
     if (v == 1) return true;
@@ -754,6 +769,10 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     const int tch = (nr == 3 && Lt % 8 == 0) ? 8 : Lt % 4 == 0 ? 4 : 2;
     if (nr && valid(1000 * z + 100 * nr + tch)) choice = 1000 * z + 100 * nr + tch;
   }
+  // t-walks in t-chunk-major order: every XCD works on the same t-chunk, so the neighbour
+  // re-reads that miss an XCD's L2 meet the chunk in the last-level cache (measured at
+  // 32^3x64: 4 rhs 824 -> 773 us, 1 and 12 rhs within 2-4%)
+  if ((choice == 2 || choice == 4 || choice == 8 || choice > 100) && valid(10000 + choice)) choice += 10000;
   if (tune_enabled()) {
     const std::string key = "dslash/" + std::to_string(int(StoreTraits<S>::prec)) + "/" + std::to_string(a.L[0]) +
                             "x" + std::to_string(a.L[1]) + "x" + std::to_string(a.L[2]) + "x" +
@@ -763,9 +782,10 @@ void launch_s(const void* U, const void* in, void* out, const DslashArgs& a, hip
     if (cached > 0) {
       choice = cached;
     } else {
-      int cand[24], n = 0;
+      int cand[48], n = 0;
       for (int v : {1, 16, 2, 4, 8, 32, 64, 202, 204, 208, 302, 304, 308, 1202, 1204, 1208, 1302, 1304, 1308})
-        if (valid(v)) cand[n++] = v;
+        for (int c : {0, 10000})
+          if ((c == 0 || (v != 1 && v != 16 && v != 32 && v != 64)) && valid(c + v)) cand[n++] = c + v;
       choice = tune_measure(key, cand, n, st, run);
     }
   }

@@ -1,10 +1,11 @@
 // Optional per-kernel-family timing: when enabled, each launch of an instrumented kernel gets
 // a pair of HIP events (attached to the dispatch itself, so they hold the kernel's own start
 // and end), and the launcher adds the algorithmic bytes and flops of that launch.  Off by
-// default (no events are recorded).  With sampling n > 1, after its first 64 launches about one
-// launch in n of each family, picked by a hash of its call index, is timed (and its bytes and
-// flops added), which keeps the event traffic out of the measured region; every call is
-// counted.
+// default (no events are recorded).  With sampling n > 1, the first launch of each family and
+// then about one launch in n, picked by a hash of its call index (so the sample does not lean
+// towards the launches at the start of a measured region, or follow a periodic launch pattern),
+// is timed (and its bytes and flops added), which keeps the event traffic out of the measured
+// region; every call is counted.
 // Family names may have a sub-name after '/' (one per launch form, e.g. "dslash/dir"); a query
 // for "dslash" sums every "dslash/..." family.
 #include <map>
@@ -24,7 +25,7 @@ struct Family {
 std::mutex g_mu;
 bool g_on = false;
 int g_every = 1;
-constexpr long kAlwaysTimed = 64;  // the first launches of a family are always timed
+constexpr long kAlwaysTimed = 1;  // the first launch of a family is always timed
 std::map<std::string, Family> g_fam;
 std::vector<hipEvent_t> g_pool;
 

@@ -88,7 +88,7 @@ def test_dslash_full_size_sampled(qmg, dims, nrhs):
         assert rel(got[r], ref) < 1e-6
 
 
-@pytest.mark.parametrize("variant", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("variant", [1, 2, 4, 8, 16, 32, 64, 10002, 10008])
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 1e-6), ("bf16", 1e-2)])
 def test_dslash_every_launch_variant(qmg, variant, prec, tol):
     """Each native launch form (site-parallel, t-walking with 2/4/8 sites per thread, four
@@ -111,10 +111,11 @@ def test_dslash_every_launch_variant(qmg, variant, prec, tol):
         qmg.set_dslash_variant(0)
 
 
-@pytest.mark.parametrize("variant", [202, 204, 208, 302, 304, 308, 1202, 1204, 1208, 1302, 1304, 1308])
+@pytest.mark.parametrize("variant", [202, 204, 208, 302, 304, 308, 1202, 1204, 1208, 1302, 1304, 1308, 10204, 11308])
 def test_dslash_multi_rhs_twalk_variants(qmg, variant):
-    """t-walking with 2 or 3 right-hand sides per thread (FP32), both tile orders, on a lattice
-    whose xy-planes hold whole 256-site tiles and on one whose planes end in a partial tile."""
+    """t-walking with 2 or 3 right-hand sides per thread (FP32), both tile orders and both
+    workgroup orders (10000 +: t-chunk-major), on a lattice whose xy-planes hold whole 256-site
+    tiles and on one whose planes end in a partial tile."""
     for dims in ((16, 16, 4, 8), (12, 10, 6, 8)):
         nrhs = 6
         banner(f"dslash multi-rhs t-walk {variant} {dims}")
