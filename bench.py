@@ -258,6 +258,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator solve")
     ap.add_argument("--mass", type=float, default=None, help="override the workload's quark mass")
+    ap.add_argument("--inner", default=None, choices=("f64", "f32", "bf16", "f16"),
+                    help="override the workload's K-cycle storage precision (--critical-table, --compare-setups)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="copy calibration plus one benchmark step (for the FETCH_SIZE / WRITE_SIZE counter runs)")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover operator and clover MG leg")
@@ -271,6 +273,12 @@ def parse():
     ap.add_argument("--levels", action="store_true",
                     help="two- vs three- vs four-level solve on the workload (further levels: 2^4 blocks of "
                          "the level above, 48 test vectors in batches of 8, rank 24)")
+    ap.add_argument("--critical-table", action="store_true",
+                    help="Regular / CSVD / iCSVD (n_s = 4, 8, 12, 16) on a --n-levels hierarchy of the workload "
+                         "(near-critical comparison: --workload critical16x32_clover)")
+    ap.add_argument("--n-levels", type=int, default=4, help="levels of the --critical-table hierarchies (2..4)")
+    ap.add_argument("--max-streams", type=int, default=16,
+                    help="--critical-table: leave out the iCSVD rows with more streams than this")
     ap.add_argument("--compare-setups", action="store_true",
                     help="Regular / CSVD / streaming (iCSVD) setups on the workload: iterations per level, "
                          "setup and solve seconds, leading singular values (prints a table and JSON lines)")
@@ -291,8 +299,12 @@ def parse():
 def load_workload(args):
     from fields import workloads
     if args.mass is not None:
-        return dict(workloads.WORKLOADS[args.workload], name=args.workload, mass=args.mass)
-    return workloads.get(args.workload)
+        w = dict(workloads.WORKLOADS[args.workload], name=args.workload, mass=args.mass)
+    else:
+        w = dict(workloads.get(args.workload))
+    if getattr(args, "inner", None):
+        w["inner"] = args.inner
+    return w
 
 
 def traffic_probe(args):
@@ -549,6 +561,96 @@ def compare_setups(args):
     for x in rows:
         sv = x["sigma_agg0"][0]
         print(f"{x['method']:8s} m={x['m']:3d} r={x['r']:2d}: " + " ".join(f"{v:.3g}" for v in sv))
+
+
+# setup methods of the near-critical comparison: (name, test vectors per level, vectors per
+# stream); Regular keeps k = 24 vectors, CSVD truncates one batch of 48 (the largest batch the
+# streaming SVD takes), iCSVD streams n_s batches of 24 (n_s = 4, 8, 12, 16), the same at every
+# level
+# relative tolerances of the solves on levels 2 and 3 in the near-critical comparison (level 1:
+# the hierarchy's coarse_tol, 0.03), the loosened criteria the comparison needs there
+LEVEL_TOLS = {2: 0.06, 3: 0.6}
+CRITICAL_METHODS = (("Regular", 24, 24), ("CSVD", 48, 48), ("iCSVD n_s=4", 96, 24), ("iCSVD n_s=8", 192, 24),
+                    ("iCSVD n_s=12", 288, 24), ("iCSVD n_s=16", 384, 24))
+
+
+def critical_table(args):
+    """Setup methods on a four-level hierarchy (levels 2 and 3 on 2^4 blocks of the level above,
+    rank 24 everywhere, each level built by the method under test): per method one untimed
+    setup + solve, then a timed setup and the median of three solves; iterations per level
+    (l = 0 outer flexible GMRES, l = 1..3 the Krylov iterations on the coarse levels, summed over
+    the solve) and per iteration of the level above."""
+    import numpy as np
+    import torch
+
+    import fields
+    import paper_2505_14399_amd as q
+
+    w = load_workload(args)
+    dims = w["dims"]
+    lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
+    U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
+    b = torch.from_numpy(fields.gaussian_spinor(dims, 1, w["seed"], tag=w["tag"])).cuda()
+    k = w["rank"]
+    rows = []
+
+    def build(m, r):
+        mg = q.mg_setup_stream_chiral_svd(lat, U, block=w["block"], n_test=m, batch=r, rank=k, n_setup_iter=16,
+                                          n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"],
+                                          seed=w["seed"], c_sw=w.get("c_sw"))
+        for lv in range(2, args.n_levels):
+            ext = mg.levels[lv - 1]["dims"] if lv > 2 else tuple(e // bb for e, bb in zip(dims, w["block"]))
+            blk = tuple(2 if e % 2 == 0 else 3 if e % 3 == 0 else 1 for e in ext)
+            mg.add_level(block=blk, n_test=m, batch=r, rank=k, n_setup_iter=16)
+            mg.set_level_tol(lv, LEVEL_TOLS[lv])
+        return mg
+
+    for name, m, r in CRITICAL_METHODS:
+        if m // r > args.max_streams:
+            continue
+        progress(f"critical table: {name} (n_test {m}, batch {r})")
+        mg = build(m, r)
+        q.mg_solve(mg, b, tol=args.tol)
+        mg.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mg = build(m, r)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        ts, info = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, info = q.mg_solve(mg, b, tol=args.tol)
+            ts.append(time.perf_counter() - t0)
+            progress(f"  solve {len(ts)}/3: {ts[-1]:.3f} s")
+        dims_l = {lv: list(mg.levels[lv]["dims"]) for lv in mg.levels}
+        mg.close()
+        i0 = info[0]
+        if i0["true_rel_res"] > args.tol:
+            raise SystemExit(f"{name}: solve did not reach {args.tol}: {i0}")
+        it = [i0["outer_iters"], i0["coarse_iters"], i0["coarse2_iters"], i0["coarse3_iters"]][:args.n_levels]
+        row = {"method": name, "m": m, "r": r, "n_s": m // r, "k": k, "levels": args.n_levels, "level_dims": dims_l,
+               "setup_s": t_setup, "solve_s": float(np.median(ts)), "iters": it,
+               "per_level_above": [it[i] / max(1, it[i - 1]) for i in range(1, len(it))],
+               "true_rel_res": i0["true_rel_res"]}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    print(f"\n# {w['name']} {dims}, mass {w['mass']:.8f}, c_sw {w.get('c_sw')}, k = {k}, {args.n_levels} levels, "
+          f"inner {w['inner']}, tol {args.tol}, level tolerances 0.03 (l = 1), "
+          + ", ".join(f"{LEVEL_TOLS[lv]} (l = {lv})" for lv in range(2, args.n_levels)))
+    print("| level | " + " | ".join(x["method"] for x in rows) + " |")
+    print("|---|" + "---:|" * len(rows))
+    for lv in range(args.n_levels):
+        print(f"| l = {lv} | " + " | ".join(str(x["iters"][lv]) for x in rows) + " |")
+    print("\nPer iteration of the level above:\n")
+    print("| level | " + " | ".join(x["method"] for x in rows) + " |")
+    print("|---|" + "---:|" * len(rows))
+    for lv in range(1, args.n_levels):
+        print(f"| l = {lv} | " + " | ".join(f"{x['per_level_above'][lv - 1]:.2f}" for x in rows) + " |")
+    print("\n| | " + " | ".join(x["method"] for x in rows) + " |")
+    print("|---|" + "---:|" * len(rows))
+    print("| setup s | " + " | ".join(f"{x['setup_s']:.3f}" for x in rows) + " |")
+    print("| solve s | " + " | ".join(f"{x['solve_s']:.3f}" for x in rows) + " |")
 
 
 LEVEL2 = dict(block=(2, 2, 2, 2), n_test=48, batch=8, rank=24, n_setup_iter=16)
@@ -981,6 +1083,9 @@ def main():
         return
     if args.compare_setups:
         compare_setups(args)
+        return
+    if args.critical_table:
+        critical_table(args)
         return
     if args.levels:
         compare_levels(args)

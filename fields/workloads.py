@@ -26,6 +26,13 @@ WORKLOADS = {
     "aniso16x32_clover": dict(dims=(16, 16, 16, 32), bc_t=-1, eps=0.6, xi=3.5, mass=None, c_sw=(1.0, 1.0),
                               block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
                               inner="f32", seed=14399, tag=2),
+    # the same clover operator at its critical point: the leftmost eigenvalue of D_sw(0) on
+    # these fields is real (searched on the full lattice), and the mass puts it 1e-3 inside
+    # the right half plane, |lambda_min| = 1e-3 (the near-critical regime of the setup-method
+    # comparison; four levels)
+    "critical16x32_clover": dict(dims=(16, 16, 16, 32), bc_t=-1, eps=0.6, xi=3.5, mass=None, c_sw=(1.0, 1.0),
+                                 block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
+                                 inner="f32", seed=14399, tag=2),
     # 24^3x64 isotropic, BF16 storage with FP32 accumulation
     "iso24x64_bf16": dict(dims=(24, 24, 24, 64), bc_t=-1, eps=0.7, xi=1.0, mass=None,
                           block=(4, 4, 4, 4), n_test=96, batch=16, rank=24,

@@ -234,6 +234,12 @@ qmg_status qmg_mg_solve(const qmg_mg* mg, const void* b, void* x, int32_t nrhs, 
  * Errors: EINVAL (null, already four levels, device-exit cycle set), ESHAPE, ENOMEM, EHIP. */
 qmg_status qmg_mg_add_level(qmg_mg* mg, const int32_t* block, int32_t n_test, int32_t batch, int32_t rank,
                             int32_t n_setup_iter, uint64_t seed, hipStream_t stream);
+/* Relative tolerance of the Krylov solve on level l >= 2 inside the K-cycle of level l - 1
+ * (default 0: the hierarchy's coarse_tol, which level 1 always uses).  Near the critical mass
+ * the lower levels of a deep hierarchy are solved more loosely (Section 4: 0.06 on l = 2 and
+ * 0.6 on l = 3 for four levels).  A solve-time setting: not stored by qmg_mg_save, kept by
+ * qmg_mg_stream_more.  Errors: EINVAL (null, no level l, tol outside [0, 1)). */
+qmg_status qmg_mg_set_level_tol(qmg_mg* mg, int32_t level, double tol);
 /* Level l >= 2: extents [4], aggregate count and rank (EINVAL when the hierarchy has no level l). */
 qmg_status qmg_mg_level_query(const qmg_mg* mg, int32_t level, int32_t* coarse_dims, int32_t* n_agg,
                               int32_t* rank);

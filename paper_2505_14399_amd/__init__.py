@@ -104,6 +104,7 @@ SIGNATURES = {
     "qmg_tune_load": [ctypes.c_char_p],
     "qmg_mg_stream_more": [_P, _I, _P],
     "qmg_mg_add_level": [_P, _P, _I, _I, _I, _I, ctypes.c_uint64, _P],
+    "qmg_mg_set_level_tol": [_P, _I, ctypes.c_double],
     "qmg_mg_level_query": [_P, _I, _P, _P, _P],
     "qmg_mg_level_get": [_P, _I, _P, _P, _P, _P],
     "qmg_level_prolong": [_P, _I, _P, _P, _I, _I, _P],
@@ -489,6 +490,10 @@ class MG:
         self.levels[lvl] = {"dims": tuple(cd), "n_agg": d.value, "rank": k.value,
                             "block": tuple(int(b) for b in block)}
         return lvl
+
+    def set_level_tol(self, level, tol):
+        """Relative tolerance of the Krylov solve on level >= 2 (0: the coarse tolerance)."""
+        _check(load_library().qmg_mg_set_level_tol(self._h, int(level), float(tol)))
 
     def _above(self, level):
         """(n_agg, rank) of the level above `level`."""

@@ -212,7 +212,8 @@ struct KCycleC : Precond {
     e2.ensure(n2 * sizeof(S));
     launch_level_restrict(p, L, d1, P2, r1, r2.p, nrhs, st);
     const int hint = last > 1 ? last - 1 : 0;
-    auto res = g2.solve(own, r2.p, e2.p, true, nrhs, 32, h.coarse_max, h.coarse_tol, st, nullptr, hint, next.get());
+    const double tol2 = L.tol > 0 ? L.tol : h.coarse_tol;
+    auto res = g2.solve(own, r2.p, e2.p, true, nrhs, 32, h.coarse_max, tol2, st, nullptr, hint, next.get());
     coarse_iters += res.iters;
     last = res.iters;
     launch_level_prolong(p, L, d1, P2, e2.p, z1, nrhs, st);
@@ -1486,6 +1487,15 @@ qmg_status qmg_mg_level_query(const qmg_mg* mg, int32_t level, int32_t* coarse_d
       for (int q = 0; q < 4; ++q) coarse_dims[q] = L.cL[q];
     if (n_agg) *n_agg = L.d;
     if (rank) *rank = L.k;
+  });
+}
+
+qmg_status qmg_mg_set_level_tol(qmg_mg* mg, int32_t level, double tol) {
+  return guard([&] {
+    const CoarseLevel& L = level_at(mg, level);
+    QMG_CHECK(tol >= 0 && tol < 1, QMG_EINVAL, "level tolerance must be in [0, 1) (0: the coarse tolerance)");
+    mg->h.levels[level - 2]->tol = tol;
+    (void)L;
   });
 }
 

@@ -250,12 +250,33 @@ __global__ __launch_bounds__(256) void k_sstep_gram(const S* __restrict__ P, int
   cplx<double> acc[kPairs];
 #pragma unroll
   for (int q = 0; q < kPairs; ++q) acc[q] = {0.0, 0.0};
-  for (size_t e = size_t(blockIdx.x) * 256 + threadIdx.x; e < len; e += size_t(gridDim.x) * 256) {
-    cplx<double> v[kSMax];
+  // storage below FP64: the next element's values are loaded before this element's products
+  // (one element ahead), so each wavefront has a load in flight while its FP64 products run
+  // (FP64 storage has no registers to spare for it)
+  constexpr bool kAhead = sizeof(C) < 8;
+  const size_t stride = size_t(gridDim.x) * 256;
+  size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+  cplx<C> nx[kSMax];
+  if constexpr (kAhead) {
 #pragma unroll
-    for (int i = 0; i < kSMax; ++i) {
-      const cplx<C> t = i < m ? ldc(P, (size_t(i) * nrhs + r) * len + e) : cplx<C>{C(0), C(0)};
-      v[i] = {double(t.re), double(t.im)};
+    for (int i = 0; i < kSMax; ++i)
+      nx[i] = (i < m && e < len) ? ldc(P, (size_t(i) * nrhs + r) * len + e) : cplx<C>{C(0), C(0)};
+  }
+  for (; e < len; e += stride) {
+    cplx<double> v[kSMax];
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int i = 0; i < kSMax; ++i) v[i] = {double(nx[i].re), double(nx[i].im)};
+      const size_t en = e + stride;
+#pragma unroll
+      for (int i = 0; i < kSMax; ++i)
+        nx[i] = (i < m && en < len) ? ldc(P, (size_t(i) * nrhs + r) * len + en) : cplx<C>{C(0), C(0)};
+    } else {
+#pragma unroll
+      for (int i = 0; i < kSMax; ++i) {
+        const cplx<C> t = i < m ? ldc(P, (size_t(i) * nrhs + r) * len + e) : cplx<C>{C(0), C(0)};
+        v[i] = {double(t.re), double(t.im)};
+      }
     }
     int q = 0;
 #pragma unroll

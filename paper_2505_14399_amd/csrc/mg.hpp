@@ -30,6 +30,7 @@ struct CoarseLevel {
   int n_test = 0, batch = 0, n_setup_iter = 0, streams_done = 0, kp = 0;
   uint64_t seed = 0;
   double t_total = 0;
+  double tol = 0;  // relative tolerance of the Krylov solve on this level (0: the hierarchy's coarse_tol)
 };
 
 struct HierarchyDev {

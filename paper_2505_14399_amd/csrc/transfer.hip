@@ -997,7 +997,10 @@ void build_coarse(HierarchyDev& h, hipStream_t st) {
   DevBuf W(size_t(8) * h.blk.d * nent * sizeof(double2));
   // per site: Px (12 k) + HP (24 k) + link (9) complex, + coefficient and 5 ints
   const size_t per_site = size_t(12 * h.k + 24 * h.k + 9) * sizeof(cplx<double>) + sizeof(double) + 5 * sizeof(int);
-  const int NS = int(std::max<size_t>(1, std::min<size_t>(16, (110 * 1024) / per_site)));
+  // sites staged per phase within 76 KB of LDS, so that two workgroups share a CU (their
+  // register use allows two) and one's loads overlap the other's products: at 32^3 x 64, k = 24
+  // (5 sites) 70 ms against 106 ms with 110 KB (one workgroup per CU); smaller budgets are slower
+  const int NS = int(std::max<size_t>(1, std::min<size_t>(16, (76 * 1024) / per_site)));
   const size_t lds = per_site * NS;
   auto go = [&](auto kern) {
     if (lds > 64 * 1024) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,

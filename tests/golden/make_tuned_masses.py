@@ -11,6 +11,8 @@ smaller lattice with the same roughness, anisotropy and seed (8^3 x 16 for the a
 16^3 x 32 workload, 12^3 x 16 for the isotropic 24^3 x 64 one), with a margin that covers the
 finite-volume shift of the edge.  For a workload with clover coefficients the operator
 searched is D_sw(0) = D(0) + T (oracle.clover), whose left edge moves with the clover term.
+For the critical workload the search runs on the full lattice and the margin is 1e-3: there the
+leftmost eigenvalue is real, so |lambda_min| = 1e-3 at the tuned mass.
 Uses only oracle/ and fields/.
 Run: python tests/golden/make_tuned_masses.py [workload ...]   (default: every tuned workload)
 """
@@ -97,7 +99,10 @@ def main():
             # the clover term moves the left edge onto the real axis (0.255 here, against
             # 0.694 +- 0.107i without it), so the margin alone sets |lambda_min|: 0.1 gives the
             # clover workload about the |lambda_min| of the Wilson one (0.108)
-            ("aniso16x32_clover", (8, 8, 8, 16), 0.1))
+            ("aniso16x32_clover", (8, 8, 8, 16), 0.1),
+            # the same fields at the critical point: searched on the full 16^3 x 32 lattice (the
+            # edge is real there, 0.2745, so the margin is |lambda_min| itself)
+            ("critical16x32_clover", None, 1e-3))
     for name, small, margin in todo:
         if len(sys.argv) > 1 and name not in sys.argv[1:]:
             continue

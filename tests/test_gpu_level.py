@@ -108,6 +108,10 @@ def test_level_errors(qmg):
     mg.add_level((1, 1, 1, 2), 8, 4, 4, n_setup_iter=2)
     with pytest.raises(qmg.QmgError, match="four levels"):
         mg.add_level((1, 1, 1, 1), 8, 4, 4)
+    for lv, t in ((1, 0.1), (4, 0.1), (2, 1.0), (2, -0.1)):
+        with pytest.raises(qmg.QmgError):
+            mg.set_level_tol(lv, t)
+    mg.set_level_tol(3, 0.0)
     mg.close()
 
 
@@ -169,5 +173,14 @@ def test_fourth_level_matches_oracle(qmg):
     assert rel(to_np(x4), to_np(x2)) < 1e-8
     print(f"[levels] four levels: {i4[0]['outer_iters']} / {i4[0]['coarse_iters']} / {i4[0]['coarse2_iters']} / "
           f"{i4[0]['coarse3_iters']}")
+    # looser solves on the lower levels (0.06 on level 2, 0.6 on level 3): fewer iterations there,
+    # the same solution
+    mg.set_level_tol(2, 0.06)
+    mg.set_level_tol(3, 0.6)
+    x4l, i4l = qmg.mg_solve(mg, b, tol=1e-12)
+    assert i4l[0]["true_rel_res"] < 1e-12 and rel(to_np(x4l), to_np(x2)) < 1e-8
+    assert i4l[0]["coarse3_iters"] < i4[0]["coarse3_iters"]
+    print(f"[levels] four levels, level tolerances 0.06 / 0.6: {i4l[0]['outer_iters']} / {i4l[0]['coarse_iters']} / "
+          f"{i4l[0]['coarse2_iters']} / {i4l[0]['coarse3_iters']}")
     mg.close()
     mg2.close()
