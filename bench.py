@@ -143,7 +143,9 @@ def trace_summary(args):
     print("\n".join(out))
 
 
-DSLASH_VARIANTS = {1: (8, 10008, 16), 4: (208, 1208, 11208, 8, 10008), 12: (308, 1308, 11308, 1208, 11208, 8, 10008)}
+DSLASH_VARIANTS = {1: (8, 10008, 16), 4: (208, 1208, 11208, 8, 10008),
+                   8: (11204, 11208, 10204, 10208, 1204, 10008, 10004),
+                   12: (308, 1308, 11308, 1208, 11208, 8, 10008)}
 
 
 def dslash_variants(args):

@@ -304,21 +304,22 @@ struct KCycle : Precond {
     DslashArgs a = make_dslash_args(h.g, nrhs, false, false);
     a.link_ne = h.eo_ne;
     launch_site_eo(p, a, schur->Aio, true, eo_o.p, eo_u.p, st);
-    launch_hop_eo(p, a, schur->Ue, schur->Uo, 0, eo_u.p, eo_e.p, eo_b.p, nullptr, nullptr, 1, 0, -1.0, st);
     const int ns = std::max(1, h.n_post);
-    if (h.eo_smoother == 2 && ns <= 8) {
+    const bool sstep = h.eo_smoother == 2 && ns <= 8;
+    const size_t L = size_t(12) * (h.g.V / 2);
+    if (sstep) eo_basis.ensure(size_t(ns + 1) * nh * sizeof(S));
+    // the Schur source goes straight into the first basis vector of the s-step form
+    void* bsrc = sstep ? eo_basis.p : eo_b.p;
+    launch_hop_eo(p, a, schur->Ue, schur->Uo, 0, eo_u.p, eo_e.p, bsrc, nullptr, nullptr, 1, 0, -1.0, st);
+    if (sstep) {
       // the same minimisation as GMRES(ns) from zero, over the basis b, Dhat b, ..., Dhat^ns b:
       // one pass of inner products and an FP64 normal-equation solve on the device instead of
-      // ns Gram-Schmidt steps
-      const size_t L = size_t(12) * (h.g.V / 2);
-      eo_basis.ensure(size_t(ns + 1) * nh * sizeof(S));
+      // ns Gram-Schmidt steps; x_e = sum_j c_j p_j in one pass without clearing x_e first
       eo_c.ensure(size_t(ns) * nrhs * sizeof(double2));
       auto vec = [&](int i) { return static_cast<char*>(eo_basis.p) + size_t(i) * nh * sizeof(S); };
-      Blas<S>::copy(eo_b.p, vec(0), nh, st);
       for (int i = 0; i < ns; ++i) schur->apply(vec(i), vec(i + 1), nrhs, st);
       launch_sstep_coeffs(p, eo_basis.p, ns + 1, L, nrhs, eo_c.as<double2>(), eo_part, st);
-      Blas<S>::zero(eo_xe.p, nh, st);
-      Blas<S>::axpy_multi(eo_basis.p, nh, ns, eo_c.as<double2>(), 1.0, eo_xe.p, L, nrhs, st);
+      sstep_update<S>(eo_basis.p, nh, ns, eo_c.as<double2>(), 0.0, eo_xe.p, nullptr, L, nrhs, false, false, st);
     } else {
       gf.solve(*schur, eo_b.p, eo_xe.p, true, nrhs, ns, h.n_post, 0.0, st);
     }

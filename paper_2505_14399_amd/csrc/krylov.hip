@@ -985,6 +985,38 @@ template struct Blas<float2>;
 template struct Blas<cbf16>;
 template struct Blas<chalf>;
 
+// The update that closes one s-step cycle, in one pass over the basis p_0 .. p_s of each
+// right-hand side (p_0 is the residual): x += sum_j c_j p_j (x = ... when add is 0, without
+// reading x) and, unless it is the last cycle,
+// p_0 <- p_0 - sum_j c_j D p_j with D p_j = p_{j+1} + d p_j (the shifted basis), accumulated in
+// the storage type's arithmetic precision.  Each thread reads and writes only its own element,
+// so p_0 is updated in place.
+template <class S>
+__global__ __launch_bounds__(256) void k_sstep_update(const S* basis, size_t vstride, int s,
+                                                      const double2* __restrict__ c, double d, S* __restrict__ x,
+                                                      S* p0, size_t len, int nrhs, int res, int add) {
+  using C = ctype<S>;
+  const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+  const int r = blockIdx.y;
+  if (e >= len) return;
+  const size_t off = size_t(r) * len + e;
+  cplx<C> p[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) p[i] = i <= s ? ldc(basis, size_t(i) * vstride + off) : cplx<C>{C(0), C(0)};
+  cplx<C> ax = add ? ldc(x, off) : cplx<C>{C(0), C(0)}, ar = p[0];
+  const C dd = C(d);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (j >= s) break;
+    const double2 cj = c[size_t(j) * nrhs + r];
+    const cplx<C> cc = {C(cj.x), C(cj.y)};
+    ax += cc * p[j];
+    ar -= cc * (p[j + 1] + dd * p[j]);
+  }
+  stc(x, off, ax);
+  if (res) stc(p0, off, ar);
+}
+
 // s-step form of the smoothing GMRES(8) cycles (storage below FP64): per cycle, from the
 // residual r, the shifted basis p_0 = r, p_{i+1} = (D - d) p_i (d the diagonal term m + 1 + 3/xi,
 // which centres the spectrum and keeps the powers better conditioned; the Krylov space is
@@ -992,7 +1024,8 @@ template struct Blas<chalf>;
 // gives every <p_i, p_j>, and the 8 x 8 normal equations of min ||r - D sum_j c_j p_j|| are
 // solved in FP64 on the device: the minimisation of GMRES(8) over the same space, with one
 // reduction instead of eight Gram-Schmidt steps over a growing basis.  The next cycle's residual
-// r - sum_j c_j (p_{j+1} + d p_j) comes from the basis, without another operator application.
+// r - sum_j c_j (p_{j+1} + d p_j) comes from the basis, without another operator application;
+// it and the update of x are one pass over the basis (k_sstep_update).
 template <class S>
 void smooth_sstep(size_t len, double d, LinOp& D, LinOp* H, int r, int n_iter, const void* b, void* x, DevBuf& basis,
                   DevBuf& coef, DevBuf& part, DevBuf& e, hipStream_t st) {
@@ -1001,9 +1034,9 @@ void smooth_sstep(size_t len, double d, LinOp& D, LinOp* H, int r, int n_iter, c
   const size_t n = len * r, vb = n * sizeof(S);
   basis.ensure((s + 1) * vb);
   coef.ensure(size_t(s) * r * sizeof(double2));
-  e.ensure(vb);
+  (void)e;
   auto vec = [&](int i) { return static_cast<char*>(basis.p) + size_t(i) * vb; };
-  Blas<S>::zero(x, n, st);
+  if (n_iter / s == 0) Blas<S>::zero(x, n, st);  // otherwise the first cycle writes x
   Blas<S>::copy(b, vec(0), n, st);
   for (int cyc = 0; cyc < n_iter / s; ++cyc) {
     for (int i = 0; i < s; ++i) {
@@ -1015,15 +1048,30 @@ void smooth_sstep(size_t len, double d, LinOp& D, LinOp* H, int r, int n_iter, c
       }
     }
     launch_sstep_coeffs(P, basis.p, s + 1, len, r, coef.as<double2>(), part, st, d);
-    Blas<S>::zero(e.p, n, st);
-    Blas<S>::axpy_multi(basis.p, n, s, coef.as<double2>(), 1.0, e.p, len, r, st);  // e = sum_j c_j p_j
-    Blas<S>::axpby(1.0, e.p, 1.0, x, n, st);
-    if (cyc + 1 < n_iter / s) {  // r <- r - sum_j c_j p_{j+1} - d e
-      Blas<S>::axpy_multi(vec(1), n, s, coef.as<double2>(), -1.0, vec(0), len, r, st);
-      Blas<S>::axpby(-d, e.p, 1.0, vec(0), n, st);
-    }
+    sstep_update<S>(basis.p, n, s, coef.as<double2>(), d, x, vec(0), len, r, cyc + 1 < n_iter / s, cyc > 0, st);
   }
 }
+
+template <class S>
+void sstep_update(const void* basis, size_t vstride, int s, const double2* c, double d, void* x, void* p0, size_t len,
+                  int nrhs, bool res, bool add, hipStream_t st) {
+  const double n = double(len) * nrhs;
+  {
+    TimedLaunch tl_("sstep/update", st, double(s + 2 + (add ? 1 : 0) + (res ? 2 : 0)) * n * sizeof(S),
+                    8.0 * (res ? 2 : 1) * s * n);
+    launch(k_sstep_update<S>, dim3(unsigned((len + 255) / 256), nrhs), dim3(256), 0, st, static_cast<const S*>(basis),
+           vstride, s, c, d, static_cast<S*>(x), static_cast<S*>(p0), len, nrhs, res ? 1 : 0, add ? 1 : 0);
+  }
+  QMG_LAUNCH_CHECK();
+}
+template void sstep_update<double2>(const void*, size_t, int, const double2*, double, void*, void*, size_t, int, bool,
+                                    bool, hipStream_t);
+template void sstep_update<float2>(const void*, size_t, int, const double2*, double, void*, void*, size_t, int, bool,
+                                   bool, hipStream_t);
+template void sstep_update<cbf16>(const void*, size_t, int, const double2*, double, void*, void*, size_t, int, bool,
+                                  bool, hipStream_t);
+template void sstep_update<chalf>(const void*, size_t, int, const double2*, double, void*, void*, size_t, int, bool,
+                                  bool, hipStream_t);
 
 template void smooth_sstep<float2>(size_t, double, LinOp&, LinOp*, int, int, const void*, void*, DevBuf&, DevBuf&,
                                    DevBuf&, DevBuf&, hipStream_t);

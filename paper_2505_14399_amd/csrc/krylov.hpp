@@ -135,4 +135,11 @@ template <class S>
 void smooth_sstep(size_t len, double d, LinOp& D, LinOp* H, int r, int n_iter, const void* b, void* x, DevBuf& basis,
                   DevBuf& coef, DevBuf& part, DevBuf& e, hipStream_t st);
 
+// One pass over the s-step basis p_0 .. p_s (vectors vstride apart, nrhs right-hand sides of len
+// complex numbers each, coefficients c[j * nrhs + rhs]): x += sum_j c_j p_j (x = ... without
+// add) and, with res, p_0 -= sum_j c_j (p_{j+1} + d p_j) in place.  s <= 8.
+template <class S>
+void sstep_update(const void* basis, size_t vstride, int s, const double2* c, double d, void* x, void* p0, size_t len,
+                  int nrhs, bool res, bool add, hipStream_t st);
+
 }  // namespace qmg
