@@ -357,7 +357,9 @@ def dslash_hbm(clover=False):
         A = None
     Un = q.pack_gauge(lat, U, "f32")
     del U
-    out = {"lattice": list(DSLASH_HBM_DIMS), "prec": "f32", "launch": "default form", "per_rhs": {}}
+    # target_frac: the stencil's bandwidth goal, 0.70 of the HBM peak at 1 and at 12 rhs
+    out = {"lattice": list(DSLASH_HBM_DIMS), "prec": "f32", "launch": "default form", "target_frac": 0.70,
+           "per_rhs": {}}
 
     def apply(x, y):
         if clover:
@@ -933,13 +935,14 @@ def roofline_of(fam_name, f, wname):
             "algorithmic_bytes_per_launch": f["bytes_per_launch"]}
 
 
-def make_solver(args, q):
+def make_solver(args, q, w=None):
     eo_smoother = not args.plain_smoother
 
     def coarse_eo(mg):
-        """The Schur-complement coarse solve unless --full-coarse, or where it does not apply (an
-        odd coarse extent, further levels): returns whether it is on."""
-        if args.full_coarse:
+        """The Schur-complement coarse solve unless --full-coarse, the workload's own choice
+        (coarse_solve = "full"), or where it does not apply (an odd coarse extent, further levels):
+        returns whether it is on."""
+        if args.full_coarse or (w is not None and w.get("coarse_solve") == "full"):
             return False
         try:
             mg.set_coarse_eo(True)
@@ -963,7 +966,7 @@ def measure_config(args, name, steps=2):
     lat = q.Lattice(dims, w["mass"], w["xi"], w["bc_t"])
     U = torch.from_numpy(fields.random_gauge(dims, w["eps"], w["seed"], w["tag"])).cuda()
     b = torch.from_numpy(workloads.rhs(w)).cuda()
-    eo_smoother, coarse_eo = make_solver(args, q)
+    eo_smoother, coarse_eo = make_solver(args, q, w)
     kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
               n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, seed=w["seed"], c_sw=w.get("c_sw"))
     res = {"workload": name, "lattice": list(dims), "mass": w["mass"], "inner": w["inner"], "nrhs": int(b.shape[0])}
@@ -1015,7 +1018,7 @@ def prepare(args):
     setup_kw = dict(block=w["block"], n_test=w["n_test"], batch=w["batch"], rank=w["rank"], n_setup_iter=16,
                     n_post_smooth=8, coarse_tol=0.03, coarse_max_iter=500, inner=w["inner"], seed=w["seed"],
                     c_sw=w.get("c_sw"))
-    eo_smoother, coarse_eo = make_solver(args, q)
+    eo_smoother, coarse_eo = make_solver(args, q, w)
     # the 64 independent small lattices of the batched workload: one hierarchy object whose
     # setups and solves run in shared launches over all of them
     small = None

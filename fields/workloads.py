@@ -40,7 +40,11 @@ WORKLOADS = {
     # 32^3x64 with the 12 spin-colour point sources at the origin solved together
     "batched32x64": dict(dims=(32, 32, 32, 64), bc_t=-1, eps=0.6, xi=1.0, mass=0.05,
                          block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
-                         inner="f32", seed=14399, tag=4, rhs="point12", small_lattices=True),
+                         inner="f32", seed=14399, tag=4, rhs="point12", small_lattices=True,
+                         # coarse solve on D_c itself: on this workload (4 outer iterations per
+                         # source) it beats the Schur-complement coarse solve, whose blocks also
+                         # cost 30 ms of setup
+                         coarse_solve="full"),
     # differentiation workload
     "grad16x32": dict(dims=(16, 16, 16, 32), bc_t=-1, eps=0.5, xi=1.0, mass=0.03,
                       block=(4, 4, 4, 4), n_test=48, batch=8, rank=24,
