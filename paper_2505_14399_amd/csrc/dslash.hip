@@ -1154,7 +1154,10 @@ void launch_hop_eo(qmg_prec prec, const DslashArgs& a, const void* Ue, const voi
   const double cb = double(prec_bytes(prec));
   const double bytes = double(Vh) * (a.nrhs * (12.0 + 12.0 + (ym ? 12.0 : 0.0)) + 8.0 * a.link_ne +
                                      ((ym == 2 && Ap) ? 36.0 : 0.0) + ((post && Aip) ? 36.0 : 0.0)) * cb;
-  TimedLaunch tl("evenodd/hop", st, bytes, 1320.0 * Vh * a.nrhs);
+  // full groups of nr right-hand sides and a one-per-thread rest are two launches: time the pair
+  // as one (events on the stream around both) rather than the first launch alone
+  const bool two = nr > 1 && a.nrhs >= nr && a.nrhs % nr != 0;
+  TimedLaunch tl("evenodd/hop", st, bytes, 1320.0 * Vh * a.nrhs, !two);
   auto go = [&](auto tag) {
     using S = decltype(tag);
     auto run = [&](auto kern) {
