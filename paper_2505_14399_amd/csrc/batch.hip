@@ -283,6 +283,7 @@ struct BatchDev {
   std::vector<Geom> geo;
   std::vector<int> d, aoff, V;
   DevBuf lat;                 // BatchLattice[nl], a.V = Vpad
+  std::vector<BatchLattice> lat_h;  // the same descriptors on the host
   DevBuf Vl, dl, aoffd;       // int[nl]
   DevBuf U64, Uin;            // [l][4][9][Vpad]
   DevBuf gsite, jinfo, cnb;   // [DT][nd], [DT][2] (lattice, local index), [DT][8] (global)
@@ -302,13 +303,15 @@ struct BatchOp : LinOp {
   const BatchDev& b;
   qmg_prec p;
   const void* U;
-  BatchOp(const BatchDev& b_, qmg_prec p_, const void* U_) : b(b_), p(p_), U(U_) {}
+  const BatchLattice* lat;  // descriptors (default: the lattices' own; the setup's shifted copy)
+  BatchOp(const BatchDev& b_, qmg_prec p_, const void* U_, const BatchLattice* lat_ = nullptr)
+      : b(b_), p(p_), U(U_), lat(lat_ ? lat_ : b_.lat.as<BatchLattice>()) {}
   void apply(const void* in, void* out, int ncol, hipStream_t st, const int* = nullptr) override {
     const int nr = ncol / b.nl;
     double sites = 0;
     for (int v : b.V) sites += v;
-    launch_dslash_padded(p, b.lat.as<BatchLattice>(), b.nl, nr, b.Vpad, U, in, out, false,
-                         sites * (24.0 * nr + 36.0) * prec_bytes(p), 1368.0 * sites * nr, st);
+    launch_dslash_padded(p, lat, b.nl, nr, b.Vpad, U, in, out, false, sites * (24.0 * nr + 36.0) * prec_bytes(p),
+                         1368.0 * sites * nr, st);
   }
   size_t len() const override { return b.fine_len(); }
   qmg_prec prec() const override { return p; }
@@ -440,7 +443,7 @@ void batch_setup(BatchDev& b, const qmg_mg_params& prm, hipStream_t st) {
   b.P64.alloc(size_t(2) * b.DT * b.k * b.N * sizeof(double2));
   b.sigma.alloc(size_t(2) * b.DT * b.k * sizeof(double));
   DevBuf phi(nf * sizeof(double2)), blocks(size_t(2) * b.DT * r * b.N * sizeof(double2));
-  DevBuf xs, bs, tmp, basis, coef, part, e;
+  DevBuf xs, bs, tmp, basis, coef, part, e, latH;
   Gmres<double2> g64;
   int kp = 0;
   double mean_diag = 0;
@@ -461,13 +464,26 @@ void batch_setup(BatchDev& b, const qmg_mg_params& prm, hipStream_t st) {
       } else {
         QMG_CHECK(prm.n_setup_iter % 8 == 0, QMG_EINVAL, "batched setup below FP64: n_setup_iter must be a multiple of 8");
         BatchOp D(b, QMG_F32, b.Uin.p);
+        // D - d with d the lattices' mean diagonal term, in the stencil itself: each lattice's
+        // diagonal coefficient becomes its own diagonal term minus d (the shifted s-step basis
+        // then needs no separate vector update per step)
+        if (!latH.p) {
+          std::vector<BatchLattice> sh = b.lat_h;
+          for (auto& x : sh) {
+            x.a.diag_d -= mean_diag;
+            x.a.diag_f = float(x.a.diag_d);
+          }
+          latH.alloc(sh.size() * sizeof(BatchLattice));
+          QMG_HIP(hipMemcpy(latH.p, sh.data(), sh.size() * sizeof(BatchLattice), hipMemcpyHostToDevice));
+        }
+        BatchOp H(b, QMG_F32, b.Uin.p, latH.as<BatchLattice>());
         bs.ensure(nf * sizeof(float2));
         xs.ensure(nf * sizeof(float2));
         tmp.ensure(nf * sizeof(double2));
         launch_convert(phi.p, QMG_F64, xs.p, QMG_F32, nf, st);
         D.apply(xs.p, bs.p, int(cols), st);
         Blas<float2>::axpby(0.0, bs.p, -1.0, bs.p, nf, st);
-        smooth_sstep<float2>(b.fine_len(), mean_diag, D, nullptr, int(cols), prm.n_setup_iter, bs.p, xs.p, basis, coef,
+        smooth_sstep<float2>(b.fine_len(), mean_diag, D, &H, int(cols), prm.n_setup_iter, bs.p, xs.p, basis, coef,
                              part, e, st);
         launch_convert(xs.p, QMG_F32, tmp.p, QMG_F64, nf, st);
         Blas<double2>::axpby(1.0, tmp.p, 1.0, phi.p, nf, st);
@@ -710,6 +726,7 @@ qmg_status qmg_batch_setup(int32_t n_lat, const qmg_lattice* lats, const void* c
       d.alloc(bytes);
       QMG_HIP(hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice));
     };
+    b.lat_h = desc;
     upload(b.lat, desc.data(), desc.size() * sizeof(BatchLattice));
     upload(b.Vl, b.V.data(), b.V.size() * sizeof(int));
     upload(b.dl, b.d.data(), b.d.size() * sizeof(int));

@@ -316,23 +316,28 @@ __global__ __launch_bounds__(kBlock) void k_dslash_batched(const BatchLattice* _
 // ([nr][12][Vpad]); lat[l].a carries the lattice's extents and coefficients with a.V = Vpad (the
 // stride).  Grid: nl * nr * ceil(Vpad / 256) workgroups; sites at and beyond the lattice's
 // volume are written as zeros, so every output column is zero-padded.
-template <class S, bool DAG>
+// A thread forms NR right-hand sides of its site (links loaded once for all of them); the
+// groups of a tile are adjacent in the schedule.
+template <class S, bool DAG, int NR>
 __global__ __launch_bounds__(kBlock) void k_dslash_padded(const BatchLattice* __restrict__ lat, const S* __restrict__ U,
                                                           const S* __restrict__ in, S* __restrict__ out, int nr,
                                                           int ntile) {
   const int wg = xcd_tile(blockIdx.x, gridDim.x);
-  const int tile = wg % ntile, col = wg / ntile;
-  const int l = col / nr, rhs = col - l * nr;
+  const int ng = nr / NR;
+  const int g = wg % ng, tc = wg / ng;
+  const int tile = tc % ntile, l = tc / ntile;
+  const int rhs0 = g * NR;
   const DslashArgs& a = lat[l].a;
   const int Vpad = a.V;
   const int site = tile * kBlock + threadIdx.x;
   if (site >= Vpad) return;
   const size_t base = size_t(l) * nr * 12 * Vpad;
   if (site >= a.L[0] * a.L[1] * a.L[2] * a.L[3]) {
-    for (int k = 0; k < 12; ++k) stc(out + base, sp_idx<false>(rhs, k, site, Vpad), cplx<ctype<S>>{0, 0});
+    for (int r = 0; r < NR; ++r)
+      for (int k = 0; k < 12; ++k) stc(out + base, sp_idx<false>(rhs0 + r, k, site, Vpad), cplx<ctype<S>>{0, 0});
     return;
   }
-  site_dslash<S, false, 1, DAG>(U + size_t(l) * 36 * Vpad, in + base, out + base, a, site, rhs);
+  site_dslash<S, false, NR, DAG>(U + size_t(l) * 36 * Vpad, in + base, out + base, a, site, rhs0);
 }
 
 // Native-layout kernel that walks along t.  Thread (spatial site, t-chunk, group of NR
@@ -1092,15 +1097,24 @@ void launch_dslash_padded(qmg_prec prec, const BatchLattice* lat_dev, int nl, in
                           const void* in, void* out, bool dagger, double bytes, double flops, hipStream_t st) {
   TimedLaunch tl("batch/dslash", st, bytes, flops);
   const int ntile = (Vpad + kBlock - 1) / kBlock;
-  const dim3 grid(unsigned(ntile) * unsigned(nl) * unsigned(nr));
   auto go = [&](auto tag) {
     using S = decltype(tag);
-    if (dagger)
-      launch(k_dslash_padded<S, true>, grid, dim3(kBlock), 0, st, lat_dev, static_cast<const S*>(U),
-             static_cast<const S*>(in), static_cast<S*>(out), nr, ntile);
-    else
-      launch(k_dslash_padded<S, false>, grid, dim3(kBlock), 0, st, lat_dev, static_cast<const S*>(U),
-             static_cast<const S*>(in), static_cast<S*>(out), nr, ntile);
+    auto run = [&](auto nrc) {
+      constexpr int NR = decltype(nrc)::value;
+      const dim3 g(unsigned(ntile) * unsigned(nl) * unsigned(nr / NR));
+      if (dagger)
+        launch(k_dslash_padded<S, true, NR>, g, dim3(kBlock), 0, st, lat_dev, static_cast<const S*>(U),
+               static_cast<const S*>(in), static_cast<S*>(out), nr, ntile);
+      else
+        launch(k_dslash_padded<S, false, NR>, g, dim3(kBlock), 0, st, lat_dev, static_cast<const S*>(U),
+               static_cast<const S*>(in), static_cast<S*>(out), nr, ntile);
+    };
+    // several right-hand sides per thread in FP32 storage (the setup's test-vector batches)
+    if constexpr (sizeof(S) == 8) {
+      if (nr % 4 == 0) return run(std::integral_constant<int, 4>{});
+      if (nr % 2 == 0) return run(std::integral_constant<int, 2>{});
+    }
+    run(std::integral_constant<int, 1>{});
   };
   switch (prec) {
     case QMG_F64: go(double2{}); break;
