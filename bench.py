@@ -168,7 +168,7 @@ def dslash_variants(args):
     lat = q.Lattice(DSLASH_HBM_DIMS, -0.2, 1.0, -1)
     V = lat.volume
     g = torch.Generator(device="cuda").manual_seed(9)
-    U = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
+    U = random_su3_device(V, 0.6, g)
     Un = q.pack_gauge(lat, U, "f32")
     del U
     try:
@@ -336,6 +336,17 @@ def traffic_probe(args):
 DSLASH_HBM_DIMS = (32, 32, 32, 64)
 
 
+def random_su3_device(V, eps, g):
+    """[4, V, 3, 3] complex128 SU(3) links on the device: exp(i eps H), H traceless hermitian with
+    Gaussian entries (bandwidth legs only; the workloads' fields come from fields.random_gauge)."""
+    import torch
+    H = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
+    H = (H + H.conj().transpose(-1, -2)) / 2
+    tr = torch.diagonal(H, dim1=-2, dim2=-1).sum(-1) / 3
+    H = H - tr[..., None, None] * torch.eye(3, dtype=H.dtype, device=H.device)
+    return torch.linalg.matrix_exp(1j * eps * H)
+
+
 def dslash_hbm(clover=False):
     """Algorithmic bandwidth of the default launch form on 32^3 x 64 (FP32 storage): per site and
     right-hand side the spinor in and out, per site the four links (and with the clover term the
@@ -348,13 +359,10 @@ def dslash_hbm(clover=False):
     lat = q.Lattice(DSLASH_HBM_DIMS, -0.2, 1.0, -1)
     V = lat.volume
     g = torch.Generator(device="cuda").manual_seed(7)
-    if clover:  # a near-unit field, so that the clover term is of natural size
-        H = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
-        U = torch.linalg.matrix_exp(0.3j * (H + H.conj().transpose(-1, -2)) / 2)
-        A = q.clover_field(lat, U, 1.0, 1.0, "f32")
-    else:
-        U = torch.randn(4, V, 3, 3, dtype=torch.complex128, device="cuda", generator=g)
-        A = None
+    # random SU(3) links exp(i eps H), H traceless hermitian (eps 0.6 as the workloads; 0.3 for
+    # the clover leg, a near-unit field, so that the clover term is of natural size)
+    U = random_su3_device(V, 0.3 if clover else 0.6, g)
+    A = q.clover_field(lat, U, 1.0, 1.0, "f32") if clover else None
     Un = q.pack_gauge(lat, U, "f32")
     del U
     # target_frac: the stencil's bandwidth goal, 0.70 of the HBM peak at 1 and at 12 rhs
