@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -369,16 +370,24 @@ void b_restrict(const BatchDev& b, qmg_prec p, const void* P, const void* fine, 
 
 // Galerkin blocks from P and the links (k_b_galerkin), FP64
 void b_build_coarse_direct(BatchDev& b, hipStream_t st) {
-  static bool init = false;
-  if (!init) {  // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]
-    double2 gm[4][16] = {};
-    auto set = [&](int mu, int r, int c, double re, double im) { gm[mu][r * 4 + c] = make_double2(re, im); };
-    set(0, 0, 3, 0, -1); set(0, 1, 2, 0, -1); set(0, 2, 1, 0, 1); set(0, 3, 0, 0, 1);
-    set(1, 0, 3, -1, 0); set(1, 1, 2, 1, 0); set(1, 2, 1, 1, 0); set(1, 3, 0, -1, 0);
-    set(2, 0, 2, 0, -1); set(2, 1, 3, 0, 1); set(2, 2, 0, 0, 1); set(2, 3, 1, 0, -1);
-    set(3, 0, 2, 1, 0); set(3, 1, 3, 1, 0); set(3, 2, 0, 1, 0); set(3, 3, 1, 1, 0);
-    QMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_bgamma), gm, sizeof(gm)));
-    init = true;
+  // __constant__ memory is per device: upload once on every device the library runs on
+  static std::mutex init_mu;
+  static bool init[64] = {};
+  {
+    int dev = 0;
+    QMG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> init_lk(init_mu);
+    if (dev < 0 || dev >= 64 || !init[dev]) {
+      // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]
+      double2 gm[4][16] = {};
+      auto set = [&](int mu, int r, int c, double re, double im) { gm[mu][r * 4 + c] = make_double2(re, im); };
+      set(0, 0, 3, 0, -1); set(0, 1, 2, 0, -1); set(0, 2, 1, 0, 1); set(0, 3, 0, 0, 1);
+      set(1, 0, 3, -1, 0); set(1, 1, 2, 1, 0); set(1, 2, 1, 1, 0); set(1, 3, 0, -1, 0);
+      set(2, 0, 2, 0, -1); set(2, 1, 3, 0, 1); set(2, 2, 0, 0, 1); set(2, 3, 1, 0, -1);
+      set(3, 0, 2, 1, 0); set(3, 1, 3, 1, 0); set(3, 2, 0, 1, 0); set(3, 3, 1, 1, 0);
+      QMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_bgamma), gm, sizeof(gm)));
+      if (dev >= 0 && dev < 64) init[dev] = true;
+    }
   }
   const int m = 2 * b.k;
   b.Y64.alloc(size_t(b.DT) * 9 * m * m * sizeof(double2));

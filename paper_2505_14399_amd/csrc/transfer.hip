@@ -1,6 +1,7 @@
 // Transfer operators P and R = P^dagger (Eq. (6)), the Galerkin coarse operator D_c = R D P
 // (Eq. (5)) and its application, plus the layout kernels of the hierarchy.
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "mg.hpp"
@@ -1067,21 +1068,28 @@ void launch_philox_native(const Geom& g, uint64_t seed, int v0, int n, void* out
 }
 
 void launch_link_force(const Geom& g, const void* x, const void* lam, void* dU, int nrhs, hipStream_t st) {
-  static bool init = false;
-  if (!init) {
-    // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]
-    double2 gm[4][16] = {};
-    auto set = [&](int mu, int r, int c, double re, double im) { gm[mu][r * 4 + c] = make_double2(re, im); };
-    // -i sigma_1 = [[0,-i],[-i,0]] ; i sigma_1 = [[0,i],[i,0]]
-    set(0, 0, 3, 0, -1); set(0, 1, 2, 0, -1); set(0, 2, 1, 0, 1); set(0, 3, 0, 0, 1);
-    // -i sigma_2 = [[0,-1],[1,0]] ; i sigma_2 = [[0,1],[-1,0]]
-    set(1, 0, 3, -1, 0); set(1, 1, 2, 1, 0); set(1, 2, 1, 1, 0); set(1, 3, 0, -1, 0);
-    // -i sigma_3 = [[-i,0],[0,i]] ; i sigma_3 = [[i,0],[0,-i]]
-    set(2, 0, 2, 0, -1); set(2, 1, 3, 0, 1); set(2, 2, 0, 0, 1); set(2, 3, 1, 0, -1);
-    // gamma_t
-    set(3, 0, 2, 1, 0); set(3, 1, 3, 1, 0); set(3, 2, 0, 1, 0); set(3, 3, 1, 1, 0);
-    QMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gamma), gm, sizeof(gm)));
-    init = true;
+  // __constant__ memory is per device: upload once on every device the library runs on
+  static std::mutex init_mu;
+  static bool init[64] = {};
+  {
+    int dev = 0;
+    QMG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> init_lk(init_mu);
+    if (dev < 0 || dev >= 64 || !init[dev]) {
+      // chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]
+      double2 gm[4][16] = {};
+      auto set = [&](int mu, int r, int c, double re, double im) { gm[mu][r * 4 + c] = make_double2(re, im); };
+      // -i sigma_1 = [[0,-i],[-i,0]] ; i sigma_1 = [[0,i],[i,0]]
+      set(0, 0, 3, 0, -1); set(0, 1, 2, 0, -1); set(0, 2, 1, 0, 1); set(0, 3, 0, 0, 1);
+      // -i sigma_2 = [[0,-1],[1,0]] ; i sigma_2 = [[0,1],[-1,0]]
+      set(1, 0, 3, -1, 0); set(1, 1, 2, 1, 0); set(1, 2, 1, 1, 0); set(1, 3, 0, -1, 0);
+      // -i sigma_3 = [[-i,0],[0,i]] ; i sigma_3 = [[i,0],[0,-i]]
+      set(2, 0, 2, 0, -1); set(2, 1, 3, 0, 1); set(2, 2, 0, 0, 1); set(2, 3, 1, 0, -1);
+      // gamma_t
+      set(3, 0, 2, 1, 0); set(3, 1, 3, 1, 0); set(3, 2, 0, 1, 0); set(3, 3, 1, 1, 0);
+      QMG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gamma), gm, sizeof(gm)));
+      if (dev >= 0 && dev < 64) init[dev] = true;
+    }
   }
   {
     TimedLaunch tl_("force", st, double(g.V) * (nrhs * 48.0 + 72.0) * 8, 0.0);
