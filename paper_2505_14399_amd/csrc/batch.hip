@@ -118,35 +118,40 @@ __global__ __launch_bounds__(64) void k_b_restrict(const S* __restrict__ P, cons
   stc(vc, (col * dmax + j) * 2 * k + a * k + i, acc);
 }
 
-// out = D_c in on the padded coarse columns: one workgroup per (aggregate slot j < dmax,
-// column); the nine inputs (self, then the eight neighbours) are staged in LDS, thread `row`
-// forms one output component; padding aggregates give zeros
+// out = D_c in on the padded coarse columns: one workgroup of 64 threads per (64 / 2k aggregate
+// slots, column), so that every lane works at small ranks (2k = 16: four aggregates); the nine
+// inputs of each aggregate (self, then the eight neighbours) are staged in LDS, thread
+// (aggregate, row) forms one output component; padding aggregates give zeros
 template <class S>
 __global__ __launch_bounds__(64) void k_b_coarse_apply(const S* __restrict__ Y, const S* __restrict__ in,
                                                        S* __restrict__ out, const int* __restrict__ cnb,
                                                        const int* __restrict__ jinfo, const int* __restrict__ dl,
                                                        const int* __restrict__ aoff, int m, int dmax, int nrhs) {
   using C = ctype<S>;
-  __shared__ cplx<C> v[9][2 * kMaxRank];
-  const int j = blockIdx.x, col = blockIdx.y, l = col / nrhs;
-  const int row = threadIdx.x;
-  const size_t ob = (size_t(col) * dmax + j) * m;
-  if (j >= dl[l]) {
-    if (row < m) stc(out, ob + row, cplx<C>{C(0), C(0)});
-    return;
-  }
-  const int J = aoff[l] + j;
-  for (int t = threadIdx.x; t < 9 * m; t += 64) {
-    const int s = t / m, c = t - s * m;
-    const int jn = s == 0 ? j : jinfo[2 * cnb[size_t(J) * 8 + s - 1] + 1];
-    v[s][c] = ldc(in, (size_t(col) * dmax + jn) * m + c);
+  __shared__ cplx<C> v[9 * 64];  // [aggregate in workgroup][slot][component], apw * m <= 64
+  const int apw = 64 / m;        // aggregates per workgroup
+  const int jb = blockIdx.x * apw, col = blockIdx.y, l = col / nrhs;
+  const int nd = dl[l];
+  for (int t = threadIdx.x; t < apw * 9 * m; t += 64) {
+    const int aa = t / (9 * m), rem = t - aa * 9 * m;
+    const int sl = rem / m, c = rem - sl * m, jj = jb + aa;
+    if (jj >= nd) continue;
+    const int jn = sl == 0 ? jj : jinfo[2 * cnb[size_t(aoff[l] + jj) * 8 + sl - 1] + 1];
+    v[t] = ldc(in, (size_t(col) * dmax + jn) * m + c);
   }
   __syncthreads();
-  if (row >= m) return;
+  const int a = threadIdx.x / m, row = threadIdx.x - a * m, j = jb + a;
+  if (a >= apw || j >= dmax) return;
+  const size_t ob = (size_t(col) * dmax + j) * m;
+  if (j >= nd) {
+    stc(out, ob + row, cplx<C>{C(0), C(0)});
+    return;
+  }
   cplx<C> acc = {C(0), C(0)};
-  const S* YJ = Y + size_t(J) * 9 * m * m;
-  for (int s = 0; s < 9; ++s)
-    for (int c = 0; c < m; ++c) acc += ldc(YJ, (size_t(s) * m + c) * m + row) * v[s][c];
+  const S* YJ = Y + size_t(aoff[l] + j) * 9 * m * m;
+  const cplx<C>* va = v + size_t(a) * 9 * m;
+  for (int sl = 0; sl < 9; ++sl)
+    for (int c = 0; c < m; ++c) acc += ldc(YJ, (size_t(sl) * m + c) * m + row) * va[sl * m + c];
   stc(out, ob + row, acc);
 }
 
@@ -329,7 +334,8 @@ struct BatchCoarseOp : LinOp {
                    8.0 * 9.0 * m * m * b.DT * nr);
     dispatch_b(p, [&](auto tag) {
       using S = decltype(tag);
-      launch(k_b_coarse_apply<S>, dim3(b.dmax, ncol), dim3(64), 0, st, static_cast<const S*>(Y),
+      launch(k_b_coarse_apply<S>, dim3(unsigned((b.dmax + 64 / m - 1) / (64 / m)), ncol), dim3(64), 0, st,
+             static_cast<const S*>(Y),
              static_cast<const S*>(in), static_cast<S*>(out), b.cnb.as<int>(), b.jinfo.as<int>(), b.dl.as<int>(),
              b.aoffd.as<int>(), m, b.dmax, nr);
     });
