@@ -523,8 +523,11 @@ qmg_status qmg_autotune(int32_t on);
  * direction; 32, 64: one site per thread for 2 or 4 right-hand sides at once, used when nrhs is
  * a multiple; 1000 z + 100 NR + TCH with z in {0, 1}, NR in {2, 3}, TCH in {2, 4, 8}: TCH sites
  * along t for NR right-hand sides per thread, FP32 storage only, z = 1 orders the tiles z-fastest;
- * a variant that does not apply to a call falls back to the automatic choice); 0 restores the
- * automatic choice.  Any other value gives QMG_EINVAL.
+ * 10000 + a t-walking code: the same with the workgroups in t-chunk-major order; for the
+ * even-odd hop, 500 + NR (NR in 1..4 right-hand sides per thread) or 7ZT (tiles in patches of
+ * Z x T (z, t) planes, Z and T in {1, 2, 4, 8}, where whole tiles fill a plane; 700:
+ * lexicographic order); a variant that does not apply to a call falls back to the automatic
+ * choice); 0 restores the automatic choice.  Any other value gives QMG_EINVAL.
  * For tests and tuning studies. */
 qmg_status qmg_set_dslash_variant(int32_t variant);
 qmg_status qmg_tune_save(const char* path);

@@ -2099,9 +2099,12 @@ qmg_status qmg_set_dslash_variant(int32_t v) {
     const int z = u / 1000, nr = (u % 1000) / 100, tch = u % 100;
     const bool tw = u > 100 && z <= 1 && (nr == 2 || nr == 3) && (tch == 2 || tch == 4 || tch == 8);
     const bool hop_nr = !cm && v >= 501 && v <= 504;  // even-odd hop: 1 .. 4 right-hand sides per thread
+    auto p2 = [](int q) { return q == 1 || q == 2 || q == 4 || q == 8; };
+    const bool hop_order = !cm && (v == 700 || (v > 700 && v < 800 && p2((v / 10) % 10) && p2(v % 10)));
     const bool plain = !cm && (v == 0 || v == 1 || v == 16 || v == 32 || v == 64);
-    QMG_CHECK(v < 20000 && (tw || hop_nr || plain || u == 2 || u == 4 || u == 8), QMG_EINVAL,
-              "dslash variant must be 0, 1, 2, 4, 8, 16, 32, 64, an even-odd hop code 500 + NR (NR in 1..4), a "
+    QMG_CHECK(v < 20000 && (tw || hop_nr || hop_order || plain || u == 2 || u == 4 || u == 8), QMG_EINVAL,
+              "dslash variant must be 0, 1, 2, 4, 8, 16, 32, 64, an even-odd hop code 500 + NR (NR in 1..4) or "
+              "7ZT (tile order over patches of Z x T planes, Z and T in {1, 2, 4, 8}; 700 lexicographic), a "
               "multi-rhs t-walking code 1000 z + 100 NR + TCH (z in {0,1}, NR in {2,3}, TCH in {2,4,8}), or "
               "10000 + a t-walking code (2, 4, 8 or multi-rhs) for the t-chunk-major workgroup order");
     set_dslash_variant(v);

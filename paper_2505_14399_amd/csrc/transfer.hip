@@ -13,18 +13,31 @@ namespace {
 
 inline unsigned cdiv(size_t a, size_t b) { return unsigned((a + b - 1) / b); }
 
+// XCD-local index of workgroup b of nb: the hardware deals workgroups to the eight XCDs round
+// robin (b % 8), so this numbering gives each XCD one contiguous range.  The transfers use it
+// so that neighbouring aggregates, whose blocks share cache lines of the fine vectors (4 sites
+// of a 128-byte line of 16 in FP32), run on one XCD and meet those lines in its L2.
+__device__ inline int xcd_local(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + min(x, rem) + i;
+}
+
 // ---------------------------------------------------------------------------------------
 // prolong: one thread per pack of PR rows of a (j, alpha) block, for NR right-hand sides; the
 // k coarse coefficients of those right-hand sides are staged in LDS, so P is read once per
 // group of right-hand sides.  Rows are s6 * nd + ib; the fine site is bsite[j][ib].
+// Grid: one dimension of npack * 2d * groups workgroups, in XCD-local order (row packs of a
+// block, then the blocks, then the groups of right-hand sides).
 template <class S, int PR, int NR>
 __global__ __launch_bounds__(256) void k_prolong(const S* __restrict__ P, const S* __restrict__ vc,
                                                  S* __restrict__ fine, const int* __restrict__ bsite, int nd, int N,
-                                                 int k, int d, int V, int nrhs) {
+                                                 int k, int d, int V, int nrhs, int npack) {
   using C = ctype<S>;
   __shared__ cplx<C> cv[NR][64];
-  const int ja = blockIdx.y;  // j * 2 + alpha
-  const int rhs0 = blockIdx.z * NR;
+  const int wg = xcd_local(blockIdx.x, gridDim.x);
+  const int pk = wg % npack, rest = wg / npack;
+  const int ja = rest % (2 * d);  // j * 2 + alpha
+  const int rhs0 = (rest / (2 * d)) * NR;
   const int nr = min(NR, nrhs - rhs0);
   const int j = ja >> 1, a = ja & 1;
   for (int t = threadIdx.x; t < NR * k; t += 256) {
@@ -32,7 +45,7 @@ __global__ __launch_bounds__(256) void k_prolong(const S* __restrict__ P, const 
     cv[r][i] = r < nr ? ldc(vc, (size_t(rhs0 + r) * d + j) * 2 * k + a * k + i) : cplx<C>{C(0), C(0)};
   }
   __syncthreads();
-  const int rp = blockIdx.x * 256 + threadIdx.x;  // row pack
+  const int rp = pk * 256 + threadIdx.x;  // row pack
   if (rp * PR >= N) return;
   const S* Pc = P + size_t(ja) * k * N;
   const size_t np = N / PR;
@@ -89,7 +102,7 @@ __global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const
   extern __shared__ unsigned char smem[];
   cplx<C>* psi = reinterpret_cast<cplx<C>*>(smem);  // [NR][N]
   __shared__ cplx<C> red[4][KC * NR];
-  const int ja = blockIdx.x, rhs0 = blockIdx.y * NR;
+  const int ja = xcd_local(blockIdx.x, gridDim.x), rhs0 = blockIdx.y * NR;
   const int nr = min(NR, nrhs - rhs0);
   const int j = ja >> 1, a = ja & 1;
   for (int t = threadIdx.x; t < NR * N; t += 256) {
@@ -887,9 +900,11 @@ void launch_prolong(qmg_prec prec, const HierarchyDev& h, const void* P, const v
     const bool packed = row_pack<S>(h.blk.N) == PK;
     auto go = [&](auto pr, auto nrt) {
       constexpr int PR = decltype(pr)::value, NR = decltype(nrt)::value;
-      dim3 grid(cdiv(h.blk.N / PR, 256), 2 * h.blk.d, cdiv(nrhs, NR));
-      launch(k_prolong<S, PR, NR>, grid, dim3(256), 0, st, P, coarse, fine, h.bsite.as<int>(), h.blk.nd, h.blk.N,
-             h.k, h.blk.d, h.g.V, nrhs);
+      const int npack = int(cdiv(h.blk.N / PR, 256));
+      const size_t nwg = size_t(npack) * 2 * h.blk.d * cdiv(nrhs, NR);
+      QMG_CHECK(nwg < (size_t(1) << 31), QMG_EINVAL, "prolong: grid too large");
+      launch(k_prolong<S, PR, NR>, dim3(unsigned(nwg)), dim3(256), 0, st, P, coarse, fine, h.bsite.as<int>(),
+             h.blk.nd, h.blk.N, h.k, h.blk.d, h.g.V, nrhs, npack);
     };
     using one = std::integral_constant<int, 1>;
     using four = std::integral_constant<int, 4>;

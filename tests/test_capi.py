@@ -93,9 +93,11 @@ def test_dslash_variant_codes_are_validated():
     import paper_2505_14399_amd as q
     L = q.load_library()
     try:
-        for v in (0, 1, 2, 4, 8, 16, 32, 64, 202, 204, 208, 302, 304, 308, 1202, 1208, 1304, 10002, 10008, 11308):
+        for v in (0, 1, 2, 4, 8, 16, 32, 64, 202, 204, 208, 302, 304, 308, 1202, 1208, 1304, 10002, 10008, 11308,
+                  501, 504, 700, 711, 744, 718, 781):
             assert L.qmg_set_dslash_variant(v) == 0, v
-        for v in (-1, 3, 5, 100, 102, 108, 206, 402, 2204, 1102, 99999, 10001, 10016, 10032, 10501, 20008):
+        for v in (-1, 3, 5, 100, 102, 108, 206, 402, 2204, 1102, 99999, 10001, 10016, 10032, 10501, 20008,
+                  505, 701, 734, 770, 799, 10744):
             assert L.qmg_set_dslash_variant(v) == -1, v
     finally:
         assert L.qmg_set_dslash_variant(0) == 0

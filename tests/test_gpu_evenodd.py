@@ -105,6 +105,40 @@ def test_schur_apply_matches_oracle(qmg, dims, clov, m, xi, prec, tol):
         assert rel(to_np(a), to_np(b)) < tol
 
 
+@pytest.mark.parametrize("dims", [(16, 32, 4, 8), (32, 16, 8, 4)])
+def test_schur_apply_blocked_tile_orders(qmg, dims):
+    """The hop's blocked (z, t) tile orders (launch-variant codes 7ZT) on lattices whose planes
+    hold whole tiles: against the oracle's Schur complement, and bit for bit equal to the
+    lexicographic order (700), since only the workgroup schedule changes; 1 to 4 right-hand
+    sides (full groups of two per thread and a one-per-thread rest), Wilson and clover."""
+    U = fields.random_gauge(dims, 0.6, 61)
+    m, xi = -0.1, 1.5
+    for clov in (False, True):
+        cs, ct = (1.1, 0.9) if clov else (0.0, 0.0)
+        T = clover.clover_term(U, dims, cs, ct) if clov else None
+        eo = evenodd.EvenOdd(U, dims, m, xi, -1, T)
+        lat = qmg.Lattice(dims, m, xi, -1)
+        Ueo = qmg.eo_pack_gauge(lat, to_gpu(U), "f32")
+        A, Ai = qmg.eo_site_term(lat, to_gpu(U), cs, ct, "f32") if clov else (None, None)
+        for nrhs in (1, 3, 4):
+            x = fields.gaussian_spinor(dims, nrhs, 62 + nrhs)
+            xe, _ = qmg.eo_pack_spinor(lat, to_gpu(x), "f32")
+            for dag in (False, True):
+                ref = eo.schur(evenodd.restrict_parity(x, eo.par, 0), dagger=dag)
+                base = None
+                try:
+                    for form in (700, 0, 711, 722, 744, 718, 781, 748):
+                        banner(f"schur blocked order {dims} clover={clov} form={form} nrhs={nrhs} dag={dag}")
+                        qmg.set_dslash_variant(form)
+                        got = to_np(qmg.schur_apply(lat, Ueo, xe, A, Ai, dagger=dag))
+                        if base is None:
+                            base = got
+                            assert rel(_full(lat, qmg, qmg.schur_apply(lat, Ueo, xe, A, Ai, dagger=dag)), ref) < 1e-6
+                        assert np.array_equal(got, base), form
+                finally:
+                    qmg.set_dslash_variant(0)
+
+
 @pytest.mark.parametrize("clov", [False, True])
 def test_eo_solve(qmg, clov):
     """The preconditioned solve and the full-lattice GMRES reach 1e-10 in the oracle's residual,
