@@ -105,11 +105,30 @@ __global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const
   const int ja = xcd_local(blockIdx.x, gridDim.x), rhs0 = blockIdx.y * NR;
   const int nr = min(NR, nrhs - rhs0);
   const int j = ja >> 1, a = ja & 1;
-  for (int t = threadIdx.x; t < NR * N; t += 256) {
-    const int r = t / N, row = t - r * N;
-    const int s6 = row / nd, ib = row - s6 * nd;
-    const int site = bsite[size_t(j) * nd + ib];
-    psi[t] = r < nr ? ldc(fine, (size_t(rhs0 + r) * 12 + 6 * a + s6) * V + site) : cplx<C>{C(0), C(0)};
+  // the gather: GU rows per thread and pass, their fine sites first and then all GU x NR spinor
+  // components, so that the loads of a pass are in flight together (two memory round trips per
+  // pass rather than two per element)
+  constexpr int GU = 6;
+  for (int base = 0; base < N; base += 256 * GU) {
+    size_t off[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int row = base + u * 256 + threadIdx.x;
+      off[u] = 0;
+      if (row < N) {
+        const int s6 = row / nd, ib = row - s6 * nd;
+        off[u] = size_t(6 * a + s6) * V + bsite[size_t(j) * nd + ib];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int row = base + u * 256 + threadIdx.x;
+      if (row < N) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          psi[size_t(r) * N + row] = r < nr ? ldc(fine, size_t(rhs0 + r) * 12 * V + off[u]) : cplx<C>{C(0), C(0)};
+      }
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -122,11 +141,19 @@ __global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const
     for (int q = 0; q < KC; ++q)
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[q][r] = {C(0), C(0)};
-    for (size_t rp = threadIdx.x; rp < np; rp += 256) {
-      Pk<S, PR> pv[KC];
+    // P loads one row pack ahead of the arithmetic
+    Pk<S, PR> pv[KC], pn[KC];
+    if (threadIdx.x < np) {
 #pragma unroll
       for (int q = 0; q < KC; ++q)
-        if (q < kc) pv[q] = ldp<S, PR>(Pb, size_t(i0 + q) * np + rp);
+        if (q < kc) pv[q] = ldp<S, PR>(Pb, size_t(i0 + q) * np + threadIdx.x);
+    }
+    for (size_t rp = threadIdx.x; rp < np; rp += 256) {
+      if (rp + 256 < np) {
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+          if (q < kc) pn[q] = ldp<S, PR>(Pb, size_t(i0 + q) * np + rp + 256);
+      }
 #pragma unroll
       for (int u = 0; u < PR; ++u) {
         cplx<C> ps[NR];
@@ -141,6 +168,8 @@ __global__ __launch_bounds__(256) void k_restrict(const S* __restrict__ P, const
           }
         }
       }
+#pragma unroll
+      for (int q = 0; q < KC; ++q) pv[q] = pn[q];
     }
 #pragma unroll
     for (int q = 0; q < KC; ++q)
