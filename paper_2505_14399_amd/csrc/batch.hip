@@ -576,8 +576,7 @@ void batch_solve(const BatchDev& b, const void* b64, void* x64, int nr, double t
   std::vector<double> hist;
   for (int ref = 0; ref < 40 && stats[0] < max_outer; ++ref) {
     D64.apply(x64, r64.p, ncol, st);
-    Blas<double2>::axpby(1.0, b64, -1.0, r64.p, n, st);
-    Blas<double2>::norm2(r64.p, len, ncol, nrm.as<double>(), rw, st);
+    dc_residual(b64, r64.p, len, ncol, nrm.as<double>(), rw, st);  // r = b - D x in FP64 and |r|^2
     QMG_HIP(hipMemcpyAsync(hr.data(), nrm.p, ncol * sizeof(double), hipMemcpyDeviceToHost, st));
     QMG_HIP(hipStreamSynchronize(st));
     double worst = 0;
@@ -587,14 +586,11 @@ void batch_solve(const BatchDev& b, const void* b64, void* x64, int nr, double t
     }
     hist.push_back(worst);
     if (worst <= tol) break;
-    Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 0, len, ncol, st);
-    launch_convert(r64.p, QMG_F64, rin.p, QMG_F32, n, st);
+    dc_normalise(r64.p, nrm.as<double>(), rin.p, len, ncol, st);
     auto res = f.solve(D32, rin.p, ein.p, true, ncol, 16, int(max_outer - stats[0]), 1e-5, st, nullptr, 0, &K);
     stats[0] += res.iters;
     stats[1] += 1;
-    launch_convert(ein.p, QMG_F32, r64.p, QMG_F64, n, st);
-    Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 1, len, ncol, st);
-    Blas<double2>::axpby(1.0, r64.p, 1.0, x64, n, st);
+    dc_accumulate(ein.p, nrm.as<double>(), x64, len, ncol, st);
   }
   stats[2] += K.coarse_iters;
   stats[3] += K.smooth_iters;

@@ -694,8 +694,7 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
   } acc{ss, K, st};
   for (int ref = 0; ref < 40 && ss.outer < max_outer; ++ref) {
     D64.apply(x64, r64.p, nrhs, st);
-    Blas<double2>::axpby(1.0, b64, -1.0, r64.p, n, st);  // r = b - D x in FP64
-    Blas<double2>::norm2(r64.p, len, nrhs, nrm.as<double>(), rw, st);
+    dc_residual(b64, r64.p, len, nrhs, nrm.as<double>(), rw, st);  // r = b - D x in FP64 and |r|^2
     QMG_HIP(hipMemcpyAsync(hr.data(), nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     QMG_HIP(hipStreamSynchronize(st));
     double worst = 0;
@@ -718,15 +717,12 @@ void solve_mixed(const HierarchyDev& h, const void* b64, void* x64, int nrhs, do
       return;
     }
     // r / |r| in the inner precision
-    Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 0, len, nrhs, st);
-    launch_convert(r64.p, QMG_F64, rin.p, QMG_F32, n, st);
+    dc_normalise(r64.p, nrm.as<double>(), rin.p, len, nrhs, st);
     auto res = f.solve(D32, rin.p, ein.p, true, nrhs, 16, int(max_outer - ss.outer), inner_tol, st, nullptr, 0, &K);
     ss.outer += res.iters;
     ss.refinements += 1;
     // x += |r| e
-    launch_convert(ein.p, QMG_F32, r64.p, QMG_F64, n, st);
-    Blas<double2>::scale_dev(r64.p, nrm.as<double>(), 1, len, nrhs, st);
-    Blas<double2>::axpby(1.0, r64.p, 1.0, x64, n, st);
+    dc_accumulate(ein.p, nrm.as<double>(), x64, len, nrhs, st);
   }
 }
 

@@ -1348,6 +1348,96 @@ typename Gmres<S>::Result Gmres<S>::solve(LinOp& A, const void* b, void* x, bool
   return res;
 }
 
+// ---------------------------------------------------------------------------------------
+// Defect correction between the FP64 outer residual and the FP32 inner solve: each step is one
+// pass over its vectors instead of two or three (subtraction then norm; scale then conversion;
+// conversion, scale and update), with the same roundings as the separate passes.
+namespace {
+
+// r = b - r with the partial sums of |r|^2 over the slices and in the order of k_norm_partial
+// (FP64 packs are single complex numbers), so the norms equal those of a separate norm pass
+__global__ __launch_bounds__(RB) void k_dc_residual(const double2* __restrict__ b, double2* __restrict__ r,
+                                                    size_t len, int nblk, double2* __restrict__ partial) {
+  const int blk = blockIdx.x, c = blockIdx.y;
+  double2 acc = make_double2(0.0, 0.0);
+  for (size_t e = size_t(blk) * RB + threadIdx.x; e < len; e += size_t(nblk) * RB) {
+    const size_t i = size_t(c) * len + e;
+    const double2 bv = b[i], rv = r[i];
+    const double ar = bv.x - rv.x, ai = bv.y - rv.y;
+    r[i] = make_double2(ar, ai);
+    acc.x += ar * ar + ai * ai;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[size_t(c) * nblk + blk] = acc;
+}
+
+// out = FP32(r / sqrt(n2)) per column (zero for a zero norm): the scaled value is rounded to
+// FP64 first, as a scale pass followed by a conversion would
+__global__ void k_dc_normalise(const double2* __restrict__ r, const double* __restrict__ n2, float2* __restrict__ out,
+                               size_t len) {
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (e >= len) return;
+  const double v = n2[c];
+  const double f = (v > 0.0) ? 1.0 / sqrt(v) : 0.0;
+  const size_t i = size_t(c) * len + e;
+  const double2 x = r[i];
+  const double xr = f * x.x, xi = f * x.y;
+  out[i] = make_float2(float(xr), float(xi));
+}
+
+// x += sqrt(n2) e per column, e in FP32: the product is rounded before the sum (no fused
+// multiply-add), as a scale pass followed by an update pass would
+__global__ void k_dc_accumulate(const float2* __restrict__ ev, const double* __restrict__ n2, double2* __restrict__ x,
+                                size_t len) {
+#pragma clang fp contract(off)
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (e >= len) return;
+  const double f = sqrt(n2[c]);
+  const size_t i = size_t(c) * len + e;
+  const float2 u = ev[i];
+  const double tr = f * double(u.x), ti = f * double(u.y);
+  double2 xv = x[i];
+  xv.x = tr + xv.x;
+  xv.y = ti + xv.y;
+  x[i] = xv;
+}
+
+}  // namespace
+
+void dc_residual(const void* b64, void* r64, size_t len, int nrhs, double* n2, RedWork& rw, hipStream_t st) {
+  const int nblk = pick_nblk(len, nrhs);
+  rw.ensure(size_t(nblk) * nrhs, 0);
+  {
+    TimedLaunch tl_("blas/dc_residual", st, 3.0 * double(len) * nrhs * sizeof(double2), 0.0);
+    launch(k_dc_residual, dim3(nblk, nrhs), dim3(RB), 0, st, (const double2*)b64, (double2*)r64, len, nblk,
+           rw.partial.as<double2>());
+  }
+  QMG_LAUNCH_CHECK();
+  {
+    TimedLaunch tl_("blas/finalize", st, double(nblk) * nrhs * sizeof(double2), 0.0);
+    launch(k_finalize1, dim3(nrhs), dim3(RB), 0, st, rw.partial.as<double2>(), nblk, n2, nullptr);
+  }
+  QMG_LAUNCH_CHECK();
+}
+
+void dc_normalise(const void* r64, const double* n2, void* rin, size_t len, int nrhs, hipStream_t st) {
+  {
+    TimedLaunch tl_("blas/dc_normalise", st, double(len) * nrhs * (sizeof(double2) + sizeof(float2)), 0.0);
+    launch(k_dc_normalise, dim3(nb256(len), nrhs), dim3(256), 0, st, (const double2*)r64, n2, (float2*)rin, len);
+  }
+  QMG_LAUNCH_CHECK();
+}
+
+void dc_accumulate(const void* ein, const double* n2, void* x64, size_t len, int nrhs, hipStream_t st) {
+  {
+    TimedLaunch tl_("blas/dc_accumulate", st, double(len) * nrhs * (sizeof(float2) + 2.0 * sizeof(double2)), 0.0);
+    launch(k_dc_accumulate, dim3(nb256(len), nrhs), dim3(256), 0, st, (const float2*)ein, n2, (double2*)x64, len);
+  }
+  QMG_LAUNCH_CHECK();
+}
+
 template class Gmres<double2>;
 template class Gmres<float2>;
 template class Gmres<cbf16>;

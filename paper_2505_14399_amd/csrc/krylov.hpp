@@ -142,4 +142,13 @@ template <class S>
 void sstep_update(const void* basis, size_t vstride, int s, const double2* c, double d, void* x, void* p0, size_t len,
                   int nrhs, bool res, bool add, hipStream_t st);
 
+// Defect correction between an FP64 outer residual and an FP32 inner solve, nrhs columns of len
+// complex numbers, one pass over the vectors per call:
+//   dc_residual:   r = b - r (r holds D x on entry) and n2[c] = |r_c|^2, FP64 (device);
+//   dc_normalise:  rin = FP32(r / |r|) per column (zero for a zero norm), from n2;
+//   dc_accumulate: x += |r| e per column, e the FP32 inner solution, x in FP64.
+void dc_residual(const void* b64, void* r64, size_t len, int nrhs, double* n2, RedWork& rw, hipStream_t st);
+void dc_normalise(const void* r64, const double* n2, void* rin, size_t len, int nrhs, hipStream_t st);
+void dc_accumulate(const void* ein, const double* n2, void* x64, size_t len, int nrhs, hipStream_t st);
+
 }  // namespace qmg
