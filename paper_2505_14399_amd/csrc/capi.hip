@@ -299,8 +299,7 @@ struct KCycle : Precond {
     for (DevBuf* b : {&eo_e, &eo_o, &eo_u, &eo_b, &eo_xe, &eo_xo}) b->ensure(nh * sizeof(S));
     if (!schur) schur.reset(new SchurOp(h.g, p, h.Ueo[w].p, h.Aeo[w].p, h.Aieo[w].p, false, h.eo_ne));
     D.apply(z_s, eo_t.p, nrhs, st);
-    Blas<S>::axpby(1.0, r_s, -1.0, eo_t.p, nf, st);
-    launch_eo_split(p, h.g, eo_t.p, eo_e.p, eo_o.p, nrhs, st);
+    launch_eo_split_sub(p, h.g, r_s, eo_t.p, eo_e.p, eo_o.p, nrhs, st);  // t = r - D z by parity
     DslashArgs a = make_dslash_args(h.g, nrhs, false, false);
     a.link_ne = h.eo_ne;
     launch_site_eo(p, a, schur->Aio, true, eo_o.p, eo_u.p, st);

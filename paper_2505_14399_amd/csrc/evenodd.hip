@@ -218,6 +218,20 @@ __global__ void k_eo_split(const S* __restrict__ full, S* __restrict__ even, S* 
   dst[rk * Vh + (site >> 1)] = full[q];
 }
 
+// half fields of r - t (native spinors r, t): the difference rounded to the storage type once,
+// as a subtraction pass followed by a split would
+template <class S>
+__global__ void k_eo_split_sub(const S* __restrict__ r, const S* __restrict__ t, S* __restrict__ even,
+                               S* __restrict__ odd, EoGeom g, size_t n) {
+  const size_t q = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int site = int(q % g.V);
+  const size_t rk = q / g.V;  // rhs * 12 + component
+  const int Vh = g.V >> 1;
+  S* dst = site_parity(site, g) ? odd : even;
+  stc(dst, rk * Vh + (site >> 1), ldc(r, q) - ldc(t, q));
+}
+
 template <class S>
 __global__ void k_eo_merge_add(const S* __restrict__ even, const S* __restrict__ odd, S* __restrict__ full, EoGeom g,
                                size_t n) {
@@ -509,6 +523,20 @@ void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even,
       TimedLaunch tl_("eo_layout/split", st, 2.0 * double(n) * sizeof(S), 0.0);
       launch(k_eo_split<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const S*>(full), static_cast<S*>(even),
              static_cast<S*>(odd), eo_geom(g), n);
+    }
+  });
+  QMG_LAUNCH_CHECK();
+}
+
+void launch_eo_split_sub(qmg_prec prec, const Geom& g, const void* r, const void* t, void* even, void* odd, int nrhs,
+                         hipStream_t st) {
+  const size_t n = size_t(12) * g.V * nrhs;
+  dispatch_eo(prec, [&](auto tag) {
+    using S = decltype(tag);
+    {
+      TimedLaunch tl_("eo_layout/split", st, 3.0 * double(n) * sizeof(S), 0.0);
+      launch(k_eo_split_sub<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const S*>(r), static_cast<const S*>(t),
+             static_cast<S*>(even), static_cast<S*>(odd), eo_geom(g), n);
     }
   });
   QMG_LAUNCH_CHECK();

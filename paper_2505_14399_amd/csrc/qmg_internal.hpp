@@ -366,6 +366,9 @@ double launch_su3_row_defect(const Geom& g, const void* U64, hipStream_t st);
 void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even, void* odd, int nrhs, hipStream_t st);
 void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const void* odd, void* full, int nrhs,
                          hipStream_t st);
+// half fields of r - t, rounded once to the storage type
+void launch_eo_split_sub(qmg_prec prec, const Geom& g, const void* r, const void* t, void* even, void* odd, int nrhs,
+                         hipStream_t st);
 // s-step residual minimisation: c[j * nrhs + r] (device, j < m - 1) minimising
 // ||p_0 - sum_j c_j w_j||, w_j = p_{j+1} + shift p_j, over a basis p_0 .. p_{m-1} (m <= 9, vector
 // i of rhs r at P + (i * nrhs + r) * len, storage prec); with p_{j+1} = (A - shift) p_j,
