@@ -288,13 +288,16 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
   // J (the accumulated rotations) takes G's space: G is last read by the Cholesky step, J is
   // first written after it
   const int gj = max(r * r, we * we);
-  cd* X = reinterpret_cast<cd*>(smem_raw);  // [kp][r]  (X + X2 after the first step)
-  cd* X2 = X + size_t(kp) * r;              // [kp][r]
-  cd* G = X2 + size_t(kp) * r;              // [r][r]
-  cd* J = G;                                // [we][we]
-  cd* Tm = G + size_t(gj);                  // [r][r] upper, row-major
-  cd* Ti = Tm + size_t(r) * r;              // [r][r]
-  cd* M = Ti + size_t(r) * r;               // [we][we] column-major
+  // T and T^-1 take X2's space once X2 has been added into X when they fit there (2r <= kp):
+  // 2 KB less per problem at k = 24, r = 8, so that four problems share a CU's LDS, not three
+  const bool t_in_x2 = 2 * r <= kp;
+  cd* X = reinterpret_cast<cd*>(smem_raw);        // [kp][r]  (X + X2 after the first step)
+  cd* X2 = X + size_t(kp) * r;                    // [kp][r]
+  cd* G = X2 + size_t(kp) * r;                    // [r][r]
+  cd* J = G;                                      // [we][we]
+  cd* Tm = t_in_x2 ? X2 : G + size_t(gj);         // [r][r] upper, row-major
+  cd* Ti = Tm + size_t(r) * r;                    // [r][r]
+  cd* M = t_in_x2 ? G + size_t(gj) : Ti + size_t(r) * r;  // [we][we] column-major
   double* s = reinterpret_cast<double*>(M + size_t(we) * we);  // [we]
   double* pn = s + we;                      // [r]
   int* keep = reinterpret_cast<int*>(pn + r);  // [r]
@@ -322,11 +325,21 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
       cd v = G[e];
       for (int aa = 0; aa < kp; ++aa) v -= cmul_conj(X2[aa * r + i], X2[aa * r + l]);
       G[e] = v;
-      Tm[e] = {0, 0};
-      Ti[e] = {0, 0};
+      if (!t_in_x2) {
+        Tm[e] = {0, 0};
+        Ti[e] = {0, 0};
+      }
     }
     __syncthreads();
     for (int e = lane; e < kp * r; e += TW) X[e] += X2[e];
+    if (t_in_x2) {  // X2 is dead once every lane has added it: clear T and T^-1 in its place
+      __syncthreads();
+      for (int e = lane; e < r * r; e += TW) {
+        Tm[e] = {0, 0};
+        Ti[e] = {0, 0};
+      }
+      __syncthreads();
+    }
     // Cholesky with dropping: G2 = T^dag T
     for (int jj = 0; jj < r; ++jj) {
       if (lane == 0) {
@@ -560,8 +573,9 @@ size_t gram_lds(int kp, int r) {
 }
 size_t small_lds(int kp, int r) {
   const int w = kp + r, we = w + (w & 1);
-  const size_t n = 2 * size_t(kp) * r + std::max(size_t(r) * r, size_t(we) * we) + 2 * size_t(r) * r +
-                   size_t(we) * we;
+  // X, X2, G / J, T and T^-1 (inside X2 when 2r <= kp), M: the layout of k_isvd_small
+  const size_t tt = (2 * r <= kp) ? 0 : 2 * size_t(r) * r;
+  const size_t n = 2 * size_t(kp) * r + std::max(size_t(r) * r, size_t(we) * we) + tt + size_t(we) * we;
   return n * sizeof(cd) + (we + r) * sizeof(double) + (r + we) * sizeof(int);
 }
 size_t rotate_lds(int kp, int r, int kn) {
