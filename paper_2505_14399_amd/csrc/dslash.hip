@@ -463,13 +463,13 @@ __global__ __launch_bounds__(kBlock) void k_dslash_t(const S* __restrict__ U, co
       if constexpr (CLOV) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-          stc(out, sp_idx<false>(rhs0 + r, k, site, V), acc[r][k]);
+          stc_stream(out, sp_idx<false>(rhs0 + r, k, site, V), acc[r][k]);
           psi[r][k] = nxt[k];
         }
       } else {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-          stc(out, sp_idx<false>(rhs0 + r, k, site, V), diag * psi[r][k] + acc[r][k]);
+          stc_stream(out, sp_idx<false>(rhs0 + r, k, site, V), diag * psi[r][k] + acc[r][k]);
           psi[r][k] = nxt[k];
         }
       }
@@ -922,7 +922,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_eo(const S* __restrict__ Ue, con
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int k = 0; k < 12; ++k) stc(out, sp_idx<false>(rhs + r, k, i, Vh), w[r][k]);
+    for (int k = 0; k < 12; ++k) stc_stream(out, sp_idx<false>(rhs + r, k, i, Vh), w[r][k]);
 }
 
 // Rows I0 .. I0+2 of one chirality of the even-odd epilogue: x holds sgn H in (+ y with YM = 1)

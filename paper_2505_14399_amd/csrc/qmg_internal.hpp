@@ -143,6 +143,22 @@ __device__ inline void stc(S* p, T i, cplx<U> v) {
   p[i] = StoreTraits<S>::st(cplx<C>{C(v.re), C(v.im)});
 }
 
+// The same store with the non-temporal hint: for outputs a kernel streams out and never reads
+// back, so that the inputs it re-reads (a stencil's neighbour spinors) keep the cache (the
+// t-walking stencil at 32^3 x 64 FP32: 8 rhs 1541 -> 1475 us, 12 rhs 2314 -> 2193 us per launch)
+template <int B> struct NtWord;
+template <> struct NtWord<4> { typedef unsigned int T; };
+template <> struct NtWord<8> { typedef unsigned long long T; };
+template <> struct NtWord<16> { typedef unsigned long long T __attribute__((ext_vector_type(2))); };
+template <class S, class T, class U>
+__device__ inline void stc_stream(S* p, T i, cplx<U> v) {
+  using C = ctype<S>;
+  const S sv = StoreTraits<S>::st(cplx<C>{C(v.re), C(v.im)});
+  typename NtWord<sizeof(S)>::T w;
+  __builtin_memcpy(&w, &sv, sizeof(S));
+  __builtin_nontemporal_store(w, reinterpret_cast<typename NtWord<sizeof(S)>::T*>(p + i));
+}
+
 // Wavefront sums through DPP row operations (gfx9 family: quad permutations and row rotations
 // within each 16-lane row, then the row broadcasts of lanes 15 and 31), a few cycles per step
 // instead of an LDS-crossbar shuffle.  The additions happen in a fixed order, so every call
