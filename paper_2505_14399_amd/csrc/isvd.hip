@@ -414,15 +414,17 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
             ga.re += __shfl_xor(ga.re, off, 64);  // lpp divides 64
             ga.im += __shfl_xor(ga.im, off, 64);  // lpp divides 64
           }
-          const double g = sqrt(norm2(ga));
-          if (al > 0.0 && be > 0.0 && g > 1e-300) {
-            const double rel = g / sqrt(al * be);
-            offmax = fmax(offmax, rel);
-            if (rel > kJacobiTol) {
-              const double zeta = (be - al) / (2.0 * g);
+          // the test and the rotation in squared quantities and reciprocal square roots: four
+          // dependent FP64 square roots and divisions per round instead of eight
+          const double g2 = norm2(ga), ab = al * be;
+          if (al > 0.0 && be > 0.0 && g2 > 1e-300) {
+            offmax = fmax(offmax, g2 / ab);  // squared relative off-diagonal
+            if (g2 > kJacobiTol * kJacobiTol * ab) {
+              const double ig = rsqrt(g2);  // 1 / |<m_p, m_q>|
+              const double zeta = 0.5 * (be - al) * ig;
               const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-              const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
-              const cd e = {ga.re / g, -ga.im / g};  // exp(-i theta)
+              const double cs = rsqrt(1.0 + tt * tt), sn = tt * cs;
+              const cd e = {ga.re * ig, -ga.im * ig};  // exp(-i theta)
               cd* Jp = J + size_t(pp) * we;
               cd* Jq = J + size_t(qq) * we;
               for (int row = gl; row < we; row += lpp) {
@@ -443,7 +445,7 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
       __syncthreads();
       for (int q = 0; q < TW / 64; ++q) offmax = fmax(offmax, wmax[q]);
       __syncthreads();
-      if (offmax <= kJacobiTol) break;
+      if (offmax <= kJacobiTol * kJacobiTol) break;
     }
     // singular values = column norms of M, sorted descending (stable)
     for (int c = lane; c < we; c += TW) {
