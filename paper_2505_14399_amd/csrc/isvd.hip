@@ -273,6 +273,20 @@ __global__ __launch_bounds__(T) void k_isvd_gram_mfma(const double2* __restrict_
 
 // ---------------------------------------------------------------------------------------
 // small dense part: one wavefront per problem
+// Sum over the lpp lanes of a pair's group (lpp a power of two, groups aligned, every lane of
+// a group active): DPP quad permutations and row mirrors within a 16-lane row, a few cycles per
+// step instead of an LDS-crossbar shuffle, then shuffles across rows.  Each step adds the
+// partner's partial as the butterfly lane ^ off would (the partials are uniform within the
+// half already summed), so the bits are those of the butterfly.
+__device__ inline double pair_sum(double v, int lpp) {
+  if (lpp >= 2) v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  if (lpp >= 4) v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  if (lpp >= 8) v += dpp_move<0x141, 0xF>(v);  // row_half_mirror: the other quad of 8 lanes
+  if (lpp >= 16) v += dpp_move<0x140, 0xF>(v); // row_mirror: the other half of 16 lanes
+  for (int off = 16; off < lpp; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 constexpr int TW = 128;  // two wavefronts per small problem
 
 __device__ inline int rr_pos(int i, int t, int w) {  // round-robin tournament position
@@ -408,12 +422,10 @@ __global__ __launch_bounds__(TW) void k_isvd_small(const double2* __restrict__ s
             be += norm2(v);
             ga += cmul_conj(u, v);
           }
-          for (int off = 1; off < lpp; off <<= 1) {
-            al += __shfl_xor(al, off, 64);  // lpp divides 64
-            be += __shfl_xor(be, off, 64);  // lpp divides 64
-            ga.re += __shfl_xor(ga.re, off, 64);  // lpp divides 64
-            ga.im += __shfl_xor(ga.im, off, 64);  // lpp divides 64
-          }
+          al = pair_sum(al, lpp);
+          be = pair_sum(be, lpp);
+          ga.re = pair_sum(ga.re, lpp);
+          ga.im = pair_sum(ga.im, lpp);
           // the test and the rotation in squared quantities and reciprocal square roots: four
           // dependent FP64 square roots and divisions per round instead of eight
           const double g2 = norm2(ga), ab = al * be;
