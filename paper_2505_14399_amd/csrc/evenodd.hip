@@ -205,21 +205,9 @@ __global__ void k_su3_row_defect(const double2* __restrict__ U, int V, unsigned 
   atomicMax(out, bits);
 }
 
-// native spinors [rhs][12][V] (storage S) -> half fields of each parity, and back (added)
-template <class S>
-__global__ void k_eo_split(const S* __restrict__ full, S* __restrict__ even, S* __restrict__ odd, EoGeom g,
-                           size_t n) {
-  const size_t q = size_t(blockIdx.x) * 256 + threadIdx.x;
-  if (q >= n) return;
-  const int site = int(q % g.V);
-  const size_t rk = q / g.V;  // rhs * 12 + component
-  const int Vh = g.V >> 1;
-  S* dst = site_parity(site, g) ? odd : even;
-  dst[rk * Vh + (site >> 1)] = full[q];
-}
-
-// half fields of r - t (native spinors r, t): the difference rounded to the storage type once,
-// as a subtraction pass followed by a split would
+// native spinors [rhs][12][V] (storage S) <-> half fields of each parity.  Split: the half fields
+// of r - t, the difference rounded to the storage type once (as a subtraction pass followed by a
+// split would); merge: full += the two halves.
 template <class S>
 __global__ void k_eo_split_sub(const S* __restrict__ r, const S* __restrict__ t, S* __restrict__ even,
                                S* __restrict__ odd, EoGeom g, size_t n) {
@@ -513,19 +501,6 @@ double launch_su3_row_defect(const Geom& g, const void* U64, hipStream_t st) {
   double d;
   std::memcpy(&d, &bits, sizeof(d));
   return d;
-}
-
-void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even, void* odd, int nrhs, hipStream_t st) {
-  const size_t n = size_t(12) * g.V * nrhs;
-  dispatch_eo(prec, [&](auto tag) {
-    using S = decltype(tag);
-    {
-      TimedLaunch tl_("eo_layout/split", st, 2.0 * double(n) * sizeof(S), 0.0);
-      launch(k_eo_split<S>, dim3(nblk(n)), dim3(256), 0, st, static_cast<const S*>(full), static_cast<S*>(even),
-             static_cast<S*>(odd), eo_geom(g), n);
-    }
-  });
-  QMG_LAUNCH_CHECK();
 }
 
 void launch_eo_split_sub(qmg_prec prec, const Geom& g, const void* r, const void* t, void* even, void* odd, int nrhs,

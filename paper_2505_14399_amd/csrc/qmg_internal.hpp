@@ -378,8 +378,7 @@ void launch_eo_gauge_from_native(const Geom& g, const void* U64, void* out, qmg_
                                  int ne = 9);
 // largest |third row - conj(row0 x row1)| over the native FP64 gauge field (synchronises)
 double launch_su3_row_defect(const Geom& g, const void* U64, hipStream_t st);
-// native spinors [rhs][12][V] in prec -> half fields of each parity; full += the two halves
-void launch_eo_split(qmg_prec prec, const Geom& g, const void* full, void* even, void* odd, int nrhs, hipStream_t st);
+// native spinors [rhs][12][V] in prec: full += the two half fields of each parity
 void launch_eo_merge_add(qmg_prec prec, const Geom& g, const void* even, const void* odd, void* full, int nrhs,
                          hipStream_t st);
 // half fields of r - t, rounded once to the storage type
